@@ -1,0 +1,194 @@
+/*
+ * pbit.h — C ABI of the MI355X p-bit Ising-machine sweep library (libpbit.so).
+ *
+ * The library runs the simulated probabilistic-computing sweep of
+ * "Probabilistic Computing Optimization of Complex Spin-Glass Topologies"
+ * (arXiv 2510.23419) on one gfx950 GPU:
+ *
+ *   - the problem is a quadratic Ising Hamiltonian over N +-1 spins with
+ *     symmetric couplings J (Sec. 1.1.1, Eq. 1), read here as
+ *         E(m) = - sum_{bonds (i,j)} J_ij m_i m_j - sum_i h_i m_i ;
+ *   - a p-bit sees the local field I_i = sum_j J_ij m_j + h_i (Sec. 1.2.1,
+ *     Eq. 3) and resets to m_i = sgn(tanh(beta I_i) - u), u uniform on (-1, 1)
+ *     (Sec. 1.2.1, Eq. 2, read with tanh and the annealing beta of Sec. 1.3.1);
+ *   - spins of one update group (colour class) are updated together
+ *     (Sec. 1.2.2); a sweep visits colour 0 then colour 1;
+ *   - beta follows a caller-given schedule, one value per sweep (Sec. 1.3.1),
+ *     over many independent replicas (Sec. 1.3.3).
+ *
+ * Two problem kinds are supported, both two-coloured:
+ *   PBIT_EA3D      periodic 3D Edwards-Anderson cube (Sec. 2), checkerboard
+ *                  colouring (x + y + z) mod 2; every side even and >= 2;
+ *   PBIT_BICLIQUE  complete bipartite K_{na,nb} (Sec. 3), side A colour 0.
+ *
+ * Determinism.  Every result is a pure function of (problem, beta schedule,
+ * sweep range, replica range, seed, initial spins).  Randomness is
+ * Philox4x32-10 with key (seed mod 2^32, seed >> 32) and counter (spin id,
+ * absolute sweep index, global replica >> 2, domain); word (global replica & 3)
+ * of the block belongs to the replica.  Domain 0 draws the updates; domain 1
+ * (sweep 0) draws random initial spins: +1 if the word is below 2^31, else -1.
+ * The decision uses the uint32 minority threshold
+ *     Tm(beta, a) = ceil(ldexp(1 / (1 + exp((2 beta) a)), 32) - 0.5),  a = |I|,
+ * evaluated in IEEE binary64 on the host; with s = sign(I) (+1 for I >= 0)
+ * and x = ~w if I >= 0 else w, the new spin is -s if x < Tm and s otherwise.
+ * Hence results do not depend on launch shapes, tile sizes or batching.
+ *
+ * Layouts at this boundary.
+ *   EA site id      i = x + Lx * (y + Ly * z)
+ *   EA couplings    int8 J[3][N]: J[d][i] is the bond (i, i + e_d), periodic
+ *                   (d = 0, 1, 2 for x, y, z); with a side of 2 the two bonds
+ *                   between a pair are distinct
+ *   biclique sites  side A: 0..na-1, side B: na..na+nb-1
+ *   biclique J      int8 J[na][nb] row-major, J[a][b] joins a and na + b
+ *   fields          int8 h[N] or NULL (all zero)
+ *   spins           int8 +-1, [replica][site]
+ *   couplings must be in {-1, 0, +1} and fields in {-1, 0, +1}.
+ *
+ * Errors.  Every entry point returns PBIT_OK (0), PBIT_PENDING (1, poll
+ * only) or a negative PBIT_E_* code, and never throws.  A failing call leaves
+ * caller buffers and library state as they were, except PBIT_E_DEVICE, which
+ * poisons the context (every later call on it returns PBIT_E_DEVICE).
+ * pbit_last_error() returns a message for the calling thread's last failure.
+ *
+ * Ownership.  Input pointers are borrowed for the duration of the call; the
+ * library copies what it keeps.  Output buffers are caller-allocated.
+ * Problems and jobs belong to their context until unloaded / polled to
+ * completion or until pbit_destroy.  A context may be used from several
+ * threads; calls are serialised internally.
+ */
+#ifndef PBIT_H
+#define PBIT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    PBIT_OK = 0,
+    PBIT_PENDING = 1,
+    PBIT_E_ARG = -1,         /* bad pointer, size, kind or option */
+    PBIT_E_COLOURING = -2,   /* odd EA side or improper colouring */
+    PBIT_E_RANGE = -3,       /* J or h outside {-1,0,1}, beta negative / NaN / inf */
+    PBIT_E_NOMEM = -4,       /* the context's HBM budget (or the device) is exhausted */
+    PBIT_E_BUSY = -5,        /* the serving queue is full */
+    PBIT_E_HANDLE = -6,      /* unknown, stale or foreign problem / job handle */
+    PBIT_E_DEVICE = -7,      /* HIP error; the context is poisoned */
+    PBIT_E_UNSUPPORTED = -8  /* valid request this build does not handle */
+};
+
+enum { PBIT_EA3D = 1, PBIT_BICLIQUE = 2 };
+
+typedef struct pbit_ctx pbit_ctx;
+
+/* Create a context on HIP device `device`.  `hbm_budget_bytes` caps the device
+ * memory the context may hold at once (problems, spins, tables, scratch);
+ * 0 means "no cap beyond the device".  Writes the context to *out. */
+int pbit_create(pbit_ctx **out, int device, uint64_t hbm_budget_bytes);
+
+/* Destroy a context, its problems and pending jobs.  NULL is ignored. */
+void pbit_destroy(pbit_ctx *ctx);
+
+/* Message for the calling thread's last failing call ("" if none). */
+const char *pbit_last_error(void);
+
+/* Device memory currently held by the context, in bytes. */
+uint64_t pbit_bytes_in_use(const pbit_ctx *ctx);
+
+/* ---- problems (Sec. 1.1.1 Eq. 1; Sec. 2; Sec. 3) ------------------------ */
+
+typedef struct {
+    int32_t kind;           /* PBIT_EA3D or PBIT_BICLIQUE */
+    int32_t dims[3];        /* EA: Lx, Ly, Lz (even, >= 2).  BICLIQUE: na, nb (>= 1), dims[2] ignored */
+    const int8_t *J;        /* EA: [3][N].  BICLIQUE: [na][nb] */
+    const int8_t *h;        /* [N] or NULL */
+} pbit_problem_desc;
+
+/* Validate and upload a problem; writes an opaque handle to *problem_out.
+ * Errors: E_ARG, E_COLOURING (odd or zero EA side), E_RANGE, E_NOMEM, E_DEVICE. */
+int pbit_load_problem(pbit_ctx *ctx, const pbit_problem_desc *desc, uint64_t *problem_out);
+
+/* Release a problem's device memory.  E_BUSY while a job still uses it. */
+int pbit_unload_problem(pbit_ctx *ctx, uint64_t problem);
+
+/* Number of spins N of a loaded problem, or a negative error code. */
+int64_t pbit_problem_spins(pbit_ctx *ctx, uint64_t problem);
+
+/* ---- annealing (Sec. 1.3.1 classical annealing; Sec. 1.3.3 replicas) ---- */
+
+typedef struct {
+    const double *beta;       /* [n_sweeps]: beta[s] is used for sweep sweep_offset + s; finite, >= 0 */
+    int32_t n_sweeps;         /* >= 0 */
+    int32_t sweep_offset;     /* >= 0: absolute index of the first sweep (resume) */
+    int32_t n_replicas;       /* >= 1 */
+    int32_t replica_offset;   /* >= 0, multiple of 4: global index of replica 0 (slicing) */
+    uint64_t seed;
+    const int8_t *init_spins; /* host [R][N] +-1, or NULL for the Philox random start */
+    int32_t trace_every;      /* 0: no trace; k > 0: record every replica's energy after
+                                 sweeps k, 2k, ... (n_sweeps / k snapshots) */
+    int32_t has_target;       /* nonzero: stop after the first checked sweep with min_r E_r <= target */
+    int64_t target_energy;
+} pbit_anneal_desc;
+
+typedef struct {
+    int8_t *spins;            /* caller [R][N] or NULL: final spins */
+    int64_t *energies;        /* caller [R] or NULL: final energies */
+    int64_t best_energy;      /* out: min_r E_r */
+    int32_t best_replica;     /* out: lowest local replica index reaching best_energy */
+    int32_t sweeps_done;      /* out: sweeps run (n_sweeps unless the target stopped it) */
+    int64_t *energy_trace;    /* caller [trace_cap][R] or NULL */
+    int32_t trace_cap;        /* rows available in energy_trace */
+    int32_t trace_len;        /* out: rows written */
+    int8_t *spin_trace;       /* caller [trace_cap][R][N] or NULL: spins at each traced sweep */
+} pbit_result;
+
+/* Run the anneal and wait for it.  When has_target is set the target is
+ * tested after every traced sweep (every sweep if trace_every is 0) and the
+ * run stops after the first sweep that meets it.
+ * Errors: E_ARG, E_RANGE (beta), E_HANDLE, E_NOMEM, E_DEVICE. */
+int pbit_anneal(pbit_ctx *ctx, uint64_t problem, const pbit_anneal_desc *desc, pbit_result *result);
+
+/* Device-memory variant: spins and energies live in device memory the caller
+ * owns (e.g. torch tensors) and the work runs on `hip_stream` (a hipStream_t,
+ * NULL for the context's own stream).  d_spins is int8 [R][N]: read as the
+ * initial spins when `spins_in` is nonzero (desc->init_spins must then be
+ * NULL), and always overwritten with the final spins.  d_energies is int64
+ * [R] or NULL.  Returns after the work on the stream has finished.  Traces and
+ * targets are not available here (E_ARG if requested). */
+int pbit_anneal_dev(pbit_ctx *ctx, uint64_t problem, const pbit_anneal_desc *desc,
+                    void *d_spins, int32_t spins_in, void *d_energies, void *hip_stream);
+
+/* Energies of R host configurations [R][N] into out[R] (computed on the GPU). */
+int pbit_energy(pbit_ctx *ctx, uint64_t problem, const int8_t *spins, int32_t R, int64_t *out);
+
+/* ---- serving (BASELINE configs: continuous batching of anneal jobs) ----- */
+
+/* Queue an anneal job.  The descriptor, beta and init spins are copied.  The
+ * job is admitted to the GPU when its device memory fits the context's budget;
+ * jobs that arrive while others run are batched with them.  Writes a job id.
+ * Errors: E_ARG, E_RANGE, E_HANDLE, E_BUSY (queue full), E_NOMEM (the job can
+ * never fit the budget), E_UNSUPPORTED. */
+int pbit_submit(pbit_ctx *ctx, uint64_t problem, const pbit_anneal_desc *desc, uint64_t *job_out);
+
+/* PBIT_PENDING while the job runs; PBIT_OK once it is done, after filling
+ * `result` (same fields as pbit_anneal); the job id is then retired. */
+int pbit_poll(pbit_ctx *ctx, uint64_t job, pbit_result *result);
+
+/* Drive queued work without waiting (also done inside pbit_poll). */
+int pbit_progress(pbit_ctx *ctx);
+
+/* ---- host-side helpers (no GPU needed) ---------------------------------- */
+
+/* The uint32 minority-threshold table Tm[s][a], s < S, a <= A, as the library
+ * builds it on the host for the device (see the decision rule above). */
+int pbit_threshold_table(const double *beta, int32_t S, int32_t A, uint32_t *out);
+
+/* Library version string. */
+const char *pbit_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PBIT_H */

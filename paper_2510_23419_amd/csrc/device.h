@@ -1,0 +1,62 @@
+// device.h — device-side building blocks of the p-bit sweep for gfx950.
+//
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) keyed by the anneal seed,
+// and the integer heat-bath decision of the p-bit law m = sgn(tanh(beta I) - u)
+// (paper Sec. 1.2.1, Eq. 2) through a per-sweep uint32 minority-threshold row.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pbit {
+
+// Philox4x32-10 block function.  The key words are wave-uniform in every
+// caller, so the key schedule runs on the scalar unit; each round is two
+// 32x32->64 products (v_mad_u64_u32) and two three-way XORs.
+struct Block4 {
+    uint32_t w[4];
+};
+
+__device__ __forceinline__ Block4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                         uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t p = (uint64_t)c0 * 0xD2511F53u;
+        const uint64_t q = (uint64_t)c2 * 0xCD9E8D57u;
+        const uint32_t n0 = (uint32_t)(q >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)q;
+        c3 = (uint32_t)p;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    Block4 b;
+    b.w[0] = c0; b.w[1] = c1; b.w[2] = c2; b.w[3] = c3;
+    return b;
+}
+
+// Counter domains.
+constexpr uint32_t kDomainSweep = 0;
+constexpr uint32_t kDomainInit = 1;
+
+// Heat-bath decision for field I, minority threshold T = Tm(beta, |I|) and
+// uniform word w: -s if x < T else s, with s = sign(I) (+1 at I = 0) and
+// x = ~w for I >= 0, w for I < 0.
+__device__ __forceinline__ int8_t decide(int32_t I, uint32_t T, uint32_t w)
+{
+    const bool pos = I >= 0;
+    const uint32_t x = pos ? ~w : w;
+    const bool minority = x < T;
+    return (pos != minority) ? (int8_t)1 : (int8_t)-1;
+}
+
+// Initial spin from a domain-1 word.
+__device__ __forceinline__ int8_t init_spin(uint32_t w)
+{
+    return w < 0x80000000u ? (int8_t)1 : (int8_t)-1;
+}
+
+}  // namespace pbit

@@ -1,0 +1,62 @@
+// internal.h — declarations shared by the host runtime and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pbit {
+
+// Per-site coupling code of a periodic cube.  Directions d = 0..5 are
+// +x, -x, +y, -y, +z, -z.  Bit d: J != 0 on that bond; bit 6 + d: J == -1;
+// bits 16..23: nnz(J) + h as a signed byte, so that the local field is
+//   I = (nnz + h) - 2 * #{d : J_d m_d = -1}.
+constexpr int kCodeFlipShift = 6;
+constexpr int kCodeBaseShift = 16;
+
+struct EaView {
+    int Lx, Ly, Lz;
+    int64_t N;
+    const uint32_t *code;  // [N]
+    const int8_t *J;       // [3][N] as given (for from-scratch energies)
+    const int8_t *h;       // [N] or null
+};
+
+struct BqView {
+    int na, nb;      // real side sizes
+    int na_p, nb_p;  // padded to kBqPad (extra couplings and spins are zero)
+    const int8_t *J;   // [na_p][nb_p]
+    const int8_t *JT;  // [nb_p][na_p]
+    const int8_t *hA;  // [na_p]
+    const int8_t *hB;  // [nb_p]
+};
+
+constexpr int kBqPad = 64;    // site padding of biclique sides (MFMA K and N tiles)
+constexpr int kBqRPad = 64;   // replica padding of biclique spin matrices (MFMA M tile)
+constexpr int kEaRPad = 16;   // replica padding of the cube spin matrix (one dwordx4 per thread)
+constexpr int kMaxTableWidth = 8192;  // threshold-row entries a biclique kernel stages in LDS (32 KiB)
+
+struct Key {
+    uint32_t k0, k1;
+};
+
+// ---- EA launchers; spins are device [N][Rp] (replica fastest) ------------
+hipError_t ea_init(const EaView &p, int8_t *spins, int Rp, uint32_t rq0, Key key, hipStream_t st);
+hipError_t ea_from_rows(const EaView &p, const int8_t *src_rn, int R, int8_t *spins, int Rp, hipStream_t st);
+hipError_t ea_to_rows(const EaView &p, const int8_t *spins, int Rp, int8_t *dst_rn, int R, hipStream_t st);
+hipError_t ea_halfsweep(const EaView &p, int8_t *spins, int Rp, int colour, const uint32_t *trow, int width,
+                        uint32_t sweep, uint32_t rq0, Key key, hipStream_t st);
+hipError_t ea_energy(const EaView &p, const int8_t *spins, int Rp, int R, int32_t *E, hipStream_t st);
+
+// ---- biclique launchers; spins are device MA [Rp][na_p], MB [Rp][nb_p] -----
+hipError_t bq_init(const BqView &p, int8_t *MA, int8_t *MB, int R, uint32_t rq0, Key key, hipStream_t st);
+hipError_t bq_from_rows(const BqView &p, const int8_t *src_rn, int R, int8_t *MA, int8_t *MB, hipStream_t st);
+hipError_t bq_to_rows(const BqView &p, const int8_t *MA, const int8_t *MB, int8_t *dst_rn, int R, hipStream_t st);
+hipError_t bq_halfsweep(const BqView &p, int side, int8_t *MA, int8_t *MB, int R, int Rp, const uint32_t *trow,
+                        int width, uint32_t sweep, uint32_t rq0, Key key, hipStream_t st);
+hipError_t bq_energy(const BqView &p, const int8_t *MA, const int8_t *MB, int R, int Rp, int32_t *E, hipStream_t st);
+
+// ---- misc ---------------------------------------------------------------
+hipError_t fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
+hipError_t widen_i32_i64(const int32_t *src, int64_t *dst, int64_t n, hipStream_t st);
+
+}  // namespace pbit

@@ -1,0 +1,694 @@
+// runtime.cpp — host side of libpbit: contexts, problem upload and validation,
+// the FP64 threshold table, device-memory budget, and the anneal driver that
+// enqueues the HIP kernels.  Every entry point is extern "C", returns a status
+// code and never lets an exception cross the boundary.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pbit.h"
+#include "internal.h"
+#include "runtime_internal.h"
+
+using namespace pbit;
+
+// ---------------------------------------------------------------- errors
+
+static thread_local std::string g_last_error;
+
+namespace pbit {
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int device_fail(pbit_ctx *ctx, hipError_t e, const char *where)
+{
+    ctx->poisoned = true;
+    return fail(PBIT_E_DEVICE, "%s: HIP error %d (%s); context poisoned", where, (int)e, hipGetErrorString(e));
+}
+
+}  // namespace pbit
+
+extern "C" const char *pbit_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" const char *pbit_version(void) { return "pbit-mi355x 0.1 (gfx950)"; }
+
+// ---------------------------------------------------------------- threshold table
+
+namespace pbit {
+
+// Tm(beta, a): the minority probability 1 / (1 + exp(2 beta a)) of the p-bit
+// law (Sec. 1.2.1, Eq. 2 read with tanh and beta), scaled to 2^32 and rounded
+// half-down, in IEEE binary64.
+uint32_t minority_threshold(double beta, int a)
+{
+    const double q = 1.0 / (1.0 + std::exp((2.0 * beta) * (double)a));
+    return (uint32_t)std::ceil(std::ldexp(q, 32) - 0.5);
+}
+
+// Width of the per-sweep rows actually needed: |I| never exceeds amax, and
+// beyond the first a at which every row is 0 all entries are 0 (Tm is
+// non-increasing in a), so the kernel clamps |I| to width - 1.
+int table_width(const double *beta, int S, int amax)
+{
+    int need = 0;
+    for (int s = 0; s < S && need < amax; ++s) {
+        int a = 0;
+        while (a <= amax && minority_threshold(beta[s], a) != 0u) ++a;
+        need = std::max(need, std::min(a, amax));
+    }
+    return need + 1;
+}
+
+void build_table(const double *beta, int S, int width, uint32_t *out)
+{
+    for (int s = 0; s < S; ++s)
+        for (int a = 0; a < width; ++a) out[(size_t)s * width + a] = minority_threshold(beta[s], a);
+}
+
+}  // namespace pbit
+
+extern "C" int pbit_threshold_table(const double *beta, int32_t S, int32_t A, uint32_t *out)
+{
+    if (S < 0 || A < 0 || (S > 0 && (!beta || !out))) return fail(PBIT_E_ARG, "pbit_threshold_table: bad arguments");
+    for (int s = 0; s < S; ++s)
+        if (!(beta[s] >= 0.0) || std::isinf(beta[s]))
+            return fail(PBIT_E_RANGE, "pbit_threshold_table: beta[%d] must be finite and >= 0", s);
+    build_table(beta, S, A + 1, out);
+    return PBIT_OK;
+}
+
+// ---------------------------------------------------------------- device memory
+
+namespace pbit {
+
+static std::atomic<uint32_t> g_ctx_serial{1};
+
+int dev_alloc(pbit_ctx *ctx, size_t bytes, void **out)
+{
+    *out = nullptr;
+    if (bytes == 0) return PBIT_OK;
+    if (ctx->budget && ctx->in_use + bytes > ctx->budget)
+        return fail(PBIT_E_NOMEM, "device budget exhausted: %llu in use + %llu requested > %llu",
+                    (unsigned long long)ctx->in_use, (unsigned long long)bytes, (unsigned long long)ctx->budget);
+    hipError_t e = hipMalloc(out, bytes);
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        *out = nullptr;
+        return fail(PBIT_E_NOMEM, "hipMalloc of %llu bytes failed: out of device memory", (unsigned long long)bytes);
+    }
+    if (e != hipSuccess) return device_fail(ctx, e, "hipMalloc");
+    ctx->in_use += bytes;
+    ctx->sizes[*out] = bytes;
+    return PBIT_OK;
+}
+
+void dev_free(pbit_ctx *ctx, void *p)
+{
+    if (!p) return;
+    auto it = ctx->sizes.find(p);
+    if (it != ctx->sizes.end()) {
+        ctx->in_use -= it->second;
+        ctx->sizes.erase(it);
+    }
+    (void)hipFree(p);
+}
+
+int scratch(pbit_ctx *ctx, Slot slot, size_t bytes, void **out)
+{
+    Scratch &s = ctx->scratch[(int)slot];
+    if (s.bytes >= bytes && s.ptr) {
+        *out = s.ptr;
+        return PBIT_OK;
+    }
+    if (s.ptr) {
+        hipError_t e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) return device_fail(ctx, e, "hipStreamSynchronize");
+        dev_free(ctx, s.ptr);
+        s.ptr = nullptr;
+        s.bytes = 0;
+    }
+    size_t want = std::max(bytes, (size_t)256);
+    int rc = dev_alloc(ctx, want, &s.ptr);
+    if (rc != PBIT_OK) return rc;
+    s.bytes = want;
+    *out = s.ptr;
+    return PBIT_OK;
+}
+
+void release_scratch(pbit_ctx *ctx)
+{
+    for (auto &s : ctx->scratch) {
+        dev_free(ctx, s.ptr);
+        s.ptr = nullptr;
+        s.bytes = 0;
+    }
+}
+
+}  // namespace pbit
+
+// ---------------------------------------------------------------- context
+
+extern "C" int pbit_create(pbit_ctx **out, int device, uint64_t hbm_budget_bytes)
+{
+    if (!out) return fail(PBIT_E_ARG, "pbit_create: out is NULL");
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count <= 0) {
+        (void)hipGetLastError();
+        return fail(PBIT_E_DEVICE, "pbit_create: no HIP device available (%s)", hipGetErrorString(e));
+    }
+    if (device < 0 || device >= count) return fail(PBIT_E_ARG, "pbit_create: device %d out of range [0, %d)", device, count);
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return fail(PBIT_E_DEVICE, "pbit_create: hipSetDevice failed (%s)", hipGetErrorString(e));
+    pbit_ctx *ctx = new (std::nothrow) pbit_ctx();
+    if (!ctx) return fail(PBIT_E_NOMEM, "pbit_create: host allocation failed");
+    ctx->device = device;
+    ctx->budget = hbm_budget_bytes;
+    ctx->serial = g_ctx_serial.fetch_add(1);
+    e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete ctx;
+        return fail(PBIT_E_DEVICE, "pbit_create: hipStreamCreate failed (%s)", hipGetErrorString(e));
+    }
+    *out = ctx;
+    return PBIT_OK;
+}
+
+namespace pbit {
+void free_problem(pbit_ctx *ctx, Problem &p)
+{
+    for (void *q : p.allocs) dev_free(ctx, q);
+    p.allocs.clear();
+}
+}  // namespace pbit
+
+extern "C" void pbit_destroy(pbit_ctx *ctx)
+{
+    if (!ctx) return;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        (void)hipSetDevice(ctx->device);
+        (void)hipStreamSynchronize(ctx->stream);
+        serve_shutdown(ctx);
+        for (auto &kv : ctx->problems) free_problem(ctx, kv.second);
+        ctx->problems.clear();
+        release_scratch(ctx);
+        (void)hipStreamDestroy(ctx->stream);
+    }
+    delete ctx;
+}
+
+extern "C" uint64_t pbit_bytes_in_use(const pbit_ctx *ctx) { return ctx ? ctx->in_use : 0; }
+
+// ---------------------------------------------------------------- problems
+
+namespace pbit {
+
+static bool in_unit_range(const int8_t *v, size_t n)
+{
+    for (size_t k = 0; k < n; ++k)
+        if (v[k] < -1 || v[k] > 1) return false;
+    return true;
+}
+
+static int upload(pbit_ctx *ctx, Problem &p, const void *host, size_t bytes, void **dev)
+{
+    int rc = dev_alloc(ctx, bytes, dev);
+    if (rc != PBIT_OK) return rc;
+    p.allocs.push_back(*dev);
+    hipError_t e = hipMemcpy(*dev, host, bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return device_fail(ctx, e, "hipMemcpy (problem upload)");
+    return PBIT_OK;
+}
+
+static int load_ea(pbit_ctx *ctx, const pbit_problem_desc *d, Problem &p)
+{
+    const int Lx = d->dims[0], Ly = d->dims[1], Lz = d->dims[2];
+    if (Lx < 1 || Ly < 1 || Lz < 1) return fail(PBIT_E_ARG, "EA dims must be positive (got %d %d %d)", Lx, Ly, Lz);
+    if ((Lx | Ly | Lz) & 1)
+        return fail(PBIT_E_COLOURING, "EA sides must be even for a two-colour checkerboard (got %d %d %d)", Lx, Ly, Lz);
+    const int64_t N = (int64_t)Lx * Ly * Lz;
+    if (N > (int64_t)1 << 28) return fail(PBIT_E_UNSUPPORTED, "EA lattice of %lld sites is too large", (long long)N);
+    if (!d->J) return fail(PBIT_E_ARG, "EA couplings are NULL");
+    if (!in_unit_range(d->J, (size_t)(3 * N))) return fail(PBIT_E_RANGE, "EA couplings must be in {-1, 0, +1}");
+    if (d->h && !in_unit_range(d->h, (size_t)N)) return fail(PBIT_E_RANGE, "fields must be in {-1, 0, +1}");
+
+    std::vector<uint32_t> code((size_t)N);
+    int amax = 0;
+    const int64_t plane = (int64_t)Lx * Ly;
+    for (int z = 0; z < Lz; ++z)
+        for (int y = 0; y < Ly; ++y)
+            for (int x = 0; x < Lx; ++x) {
+                const int64_t i = x + (int64_t)Lx * y + plane * z;
+                const int64_t xm = (x == 0 ? Lx - 1 : x - 1) + (int64_t)Lx * y + plane * z;
+                const int64_t ym = x + (int64_t)Lx * (y == 0 ? Ly - 1 : y - 1) + plane * z;
+                const int64_t zm = x + (int64_t)Lx * y + plane * (z == 0 ? Lz - 1 : z - 1);
+                const int8_t Jd[6] = {d->J[i], d->J[xm], d->J[N + i], d->J[N + ym], d->J[2 * N + i], d->J[2 * N + zm]};
+                uint32_t c = 0;
+                int nnz = 0;
+                for (int k = 0; k < 6; ++k) {
+                    if (Jd[k] != 0) {
+                        c |= 1u << k;
+                        ++nnz;
+                    }
+                    if (Jd[k] < 0) c |= 1u << (kCodeFlipShift + k);
+                }
+                const int hv = d->h ? d->h[i] : 0;
+                c |= (uint32_t)(uint8_t)(int8_t)(nnz + hv) << kCodeBaseShift;
+                code[(size_t)i] = c;
+                amax = std::max(amax, nnz + std::abs(hv));
+            }
+    void *dc = nullptr, *dJ = nullptr, *dh = nullptr;
+    int rc = upload(ctx, p, code.data(), sizeof(uint32_t) * (size_t)N, &dc);
+    if (rc == PBIT_OK) rc = upload(ctx, p, d->J, (size_t)(3 * N), &dJ);
+    if (rc == PBIT_OK && d->h) rc = upload(ctx, p, d->h, (size_t)N, &dh);
+    if (rc != PBIT_OK) return rc;
+    p.kind = PBIT_EA3D;
+    p.N = N;
+    p.amax = amax;
+    p.ea = EaView{Lx, Ly, Lz, N, (const uint32_t *)dc, (const int8_t *)dJ, (const int8_t *)dh};
+    return PBIT_OK;
+}
+
+static int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+static int load_biclique(pbit_ctx *ctx, const pbit_problem_desc *d, Problem &p)
+{
+    const int na = d->dims[0], nb = d->dims[1];
+    if (na < 1 || nb < 1) return fail(PBIT_E_ARG, "biclique sides must be >= 1 (got %d %d)", na, nb);
+    if ((int64_t)na * nb > ((int64_t)1 << 30))
+        return fail(PBIT_E_UNSUPPORTED, "biclique with %d x %d couplings is too large", na, nb);
+    if (!d->J) return fail(PBIT_E_ARG, "biclique couplings are NULL");
+    if (!in_unit_range(d->J, (size_t)na * nb)) return fail(PBIT_E_RANGE, "biclique couplings must be in {-1, 0, +1}");
+    if (d->h && !in_unit_range(d->h, (size_t)na + nb)) return fail(PBIT_E_RANGE, "fields must be in {-1, 0, +1}");
+    const int na_p = round_up(na, kBqPad), nb_p = round_up(nb, kBqPad);
+    std::vector<int8_t> J((size_t)na_p * nb_p, 0), JT((size_t)nb_p * na_p, 0), hA(na_p, 0), hB(nb_p, 0);
+    std::vector<int> rowsum(na, 0), colsum(nb, 0);
+    for (int a = 0; a < na; ++a)
+        for (int b = 0; b < nb; ++b) {
+            const int8_t v = d->J[(size_t)a * nb + b];
+            J[(size_t)a * nb_p + b] = v;
+            JT[(size_t)b * na_p + a] = v;
+            rowsum[a] += std::abs(v);
+            colsum[b] += std::abs(v);
+        }
+    int amax = 0;
+    for (int a = 0; a < na; ++a) {
+        hA[a] = d->h ? d->h[a] : 0;
+        amax = std::max(amax, rowsum[a] + std::abs(hA[a]));
+    }
+    for (int b = 0; b < nb; ++b) {
+        hB[b] = d->h ? d->h[na + b] : 0;
+        amax = std::max(amax, colsum[b] + std::abs(hB[b]));
+    }
+    void *dJ = nullptr, *dJT = nullptr, *dhA = nullptr, *dhB = nullptr;
+    int rc = upload(ctx, p, J.data(), J.size(), &dJ);
+    if (rc == PBIT_OK) rc = upload(ctx, p, JT.data(), JT.size(), &dJT);
+    if (rc == PBIT_OK) rc = upload(ctx, p, hA.data(), hA.size(), &dhA);
+    if (rc == PBIT_OK) rc = upload(ctx, p, hB.data(), hB.size(), &dhB);
+    if (rc != PBIT_OK) return rc;
+    p.kind = PBIT_BICLIQUE;
+    p.N = (int64_t)na + nb;
+    p.amax = amax;
+    p.bq = BqView{na, nb, na_p, nb_p, (const int8_t *)dJ, (const int8_t *)dJT, (const int8_t *)dhA,
+                  (const int8_t *)dhB};
+    return PBIT_OK;
+}
+
+Problem *find_problem(pbit_ctx *ctx, uint64_t handle)
+{
+    auto it = ctx->problems.find(handle);
+    return it == ctx->problems.end() ? nullptr : &it->second;
+}
+
+}  // namespace pbit
+
+#define PBIT_ENTER(ctx)                                                                     \
+    if (!(ctx)) return fail(PBIT_E_ARG, "%s: context is NULL", __func__);                   \
+    std::lock_guard<std::mutex> lock_((ctx)->mu);                                           \
+    if ((ctx)->poisoned) return fail(PBIT_E_DEVICE, "%s: context is poisoned", __func__);   \
+    {                                                                                       \
+        hipError_t se_ = hipSetDevice((ctx)->device);                                       \
+        if (se_ != hipSuccess) return device_fail((ctx), se_, "hipSetDevice");              \
+    }
+
+extern "C" int pbit_load_problem(pbit_ctx *ctx, const pbit_problem_desc *desc, uint64_t *problem_out)
+{
+    try {
+        PBIT_ENTER(ctx);
+        if (!desc || !problem_out) return fail(PBIT_E_ARG, "pbit_load_problem: NULL argument");
+        Problem p;
+        int rc;
+        if (desc->kind == PBIT_EA3D)
+            rc = load_ea(ctx, desc, p);
+        else if (desc->kind == PBIT_BICLIQUE)
+            rc = load_biclique(ctx, desc, p);
+        else
+            rc = fail(PBIT_E_ARG, "pbit_load_problem: unknown kind %d", desc->kind);
+        if (rc != PBIT_OK) {
+            free_problem(ctx, p);
+            return rc;
+        }
+        const uint64_t h = ((uint64_t)ctx->serial << 40) | (++ctx->next_handle);
+        ctx->problems.emplace(h, std::move(p));
+        *problem_out = h;
+        return PBIT_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(PBIT_E_NOMEM, "pbit_load_problem: host allocation failed");
+    } catch (...) {
+        return fail(PBIT_E_ARG, "pbit_load_problem: internal error");
+    }
+}
+
+extern "C" int pbit_unload_problem(pbit_ctx *ctx, uint64_t problem)
+{
+    PBIT_ENTER(ctx);
+    Problem *p = find_problem(ctx, problem);
+    if (!p) return fail(PBIT_E_HANDLE, "pbit_unload_problem: unknown problem handle");
+    if (p->jobs > 0) return fail(PBIT_E_BUSY, "pbit_unload_problem: %d job(s) still use the problem", p->jobs);
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return device_fail(ctx, e, "hipStreamSynchronize");
+    free_problem(ctx, *p);
+    ctx->problems.erase(problem);
+    return PBIT_OK;
+}
+
+extern "C" int64_t pbit_problem_spins(pbit_ctx *ctx, uint64_t problem)
+{
+    PBIT_ENTER(ctx);
+    Problem *p = find_problem(ctx, problem);
+    if (!p) return fail(PBIT_E_HANDLE, "pbit_problem_spins: unknown problem handle");
+    return p->N;
+}
+
+// ---------------------------------------------------------------- anneal
+
+namespace pbit {
+
+int check_desc(const pbit_anneal_desc *d, const char *who)
+{
+    if (!d) return fail(PBIT_E_ARG, "%s: descriptor is NULL", who);
+    if (d->n_sweeps < 0 || d->sweep_offset < 0) return fail(PBIT_E_ARG, "%s: sweep count and offset must be >= 0", who);
+    if ((int64_t)d->sweep_offset + d->n_sweeps > (int64_t)UINT32_MAX)
+        return fail(PBIT_E_ARG, "%s: sweep index exceeds 32 bits", who);
+    if (d->n_replicas < 1) return fail(PBIT_E_ARG, "%s: n_replicas must be >= 1", who);
+    if (d->replica_offset < 0 || d->replica_offset % 4 != 0)
+        return fail(PBIT_E_ARG, "%s: replica_offset must be a non-negative multiple of 4", who);
+    if (d->n_sweeps > 0 && !d->beta) return fail(PBIT_E_ARG, "%s: beta is NULL", who);
+    if (d->trace_every < 0) return fail(PBIT_E_ARG, "%s: trace_every must be >= 0", who);
+    for (int s = 0; s < d->n_sweeps; ++s)
+        if (!(d->beta[s] >= 0.0) || std::isinf(d->beta[s]))
+            return fail(PBIT_E_RANGE, "%s: beta[%d] must be finite and >= 0", who, s);
+    return PBIT_OK;
+}
+
+static int spins_in_range(const int8_t *s, size_t n)
+{
+    for (size_t k = 0; k < n; ++k)
+        if (s[k] != 1 && s[k] != -1) return 0;
+    return 1;
+}
+
+// State of one anneal on the device, in the kernels' own layouts.
+struct DevState {
+    int R = 0, Rp = 0;
+    int8_t *spins = nullptr;  // EA: [N][Rp]
+    int8_t *MA = nullptr, *MB = nullptr;  // biclique
+    uint32_t *table = nullptr;
+    int width = 1;
+    int32_t *E32 = nullptr;
+    int8_t *stage = nullptr;  // [R][N] host-layout staging
+};
+
+static int prepare(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, hipStream_t st, DevState &ds,
+                   const void *dev_init)
+{
+    const int R = d->n_replicas;
+    ds.R = R;
+    void *v = nullptr;
+    int rc;
+    if (P.kind == PBIT_EA3D) {
+        ds.Rp = round_up(R, kEaRPad);
+        rc = scratch(ctx, Slot::Spins, (size_t)P.N * ds.Rp, &v);
+        if (rc) return rc;
+        ds.spins = (int8_t *)v;
+    } else {
+        ds.Rp = round_up(R, kBqRPad);
+        const size_t a = (size_t)ds.Rp * P.bq.na_p, b = (size_t)ds.Rp * P.bq.nb_p;
+        rc = scratch(ctx, Slot::Spins, a + b, &v);
+        if (rc) return rc;
+        ds.MA = (int8_t *)v;
+        ds.MB = ds.MA + a;
+        hipError_t e = hipMemsetAsync(ds.MA, 0, a + b, st);
+        if (e != hipSuccess) return device_fail(ctx, e, "hipMemsetAsync");
+    }
+    rc = scratch(ctx, Slot::E32, sizeof(int32_t) * (size_t)ds.Rp, &v);
+    if (rc) return rc;
+    ds.E32 = (int32_t *)v;
+
+    // threshold table for this call's sweeps (built on the host in FP64)
+    const int S = d->n_sweeps;
+    ds.width = S > 0 ? table_width(d->beta, S, P.amax) : 1;
+    if (ds.width > kMaxTableWidth)
+        return fail(PBIT_E_UNSUPPORTED, "threshold rows of %d entries exceed the %d the kernels stage in LDS "
+                    "(raise the smallest beta)", ds.width, kMaxTableWidth);
+    ctx->host_table.resize((size_t)std::max(S, 1) * ds.width);
+    if (S > 0) build_table(d->beta, S, ds.width, ctx->host_table.data());
+    rc = scratch(ctx, Slot::Table, sizeof(uint32_t) * ctx->host_table.size(), &v);
+    if (rc) return rc;
+    ds.table = (uint32_t *)v;
+    hipError_t e = hipMemcpyAsync(ds.table, ctx->host_table.data(), sizeof(uint32_t) * ctx->host_table.size(),
+                                  hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return device_fail(ctx, e, "hipMemcpyAsync (table)");
+
+    const Key key{(uint32_t)d->seed, (uint32_t)(d->seed >> 32)};
+    const uint32_t rq0 = (uint32_t)d->replica_offset >> 2;
+    const int8_t *init_rows = (const int8_t *)dev_init;
+    if (d->init_spins) {
+        rc = scratch(ctx, Slot::Stage, (size_t)R * P.N, &v);
+        if (rc) return rc;
+        ds.stage = (int8_t *)v;
+        e = hipMemcpyAsync(ds.stage, d->init_spins, (size_t)R * P.N, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return device_fail(ctx, e, "hipMemcpyAsync (init spins)");
+        init_rows = ds.stage;
+    }
+    if (init_rows)
+        e = P.kind == PBIT_EA3D ? ea_from_rows(P.ea, init_rows, R, ds.spins, ds.Rp, st)
+                                : bq_from_rows(P.bq, init_rows, R, ds.MA, ds.MB, st);
+    else
+        e = P.kind == PBIT_EA3D ? ea_init(P.ea, ds.spins, ds.Rp, rq0, key, st)
+                                : bq_init(P.bq, ds.MA, ds.MB, R, rq0, key, st);
+    if (e != hipSuccess) return device_fail(ctx, e, "spin initialisation launch");
+    return PBIT_OK;
+}
+
+static hipError_t sweep(const Problem &P, DevState &ds, int s, uint32_t t, uint32_t rq0, Key key, hipStream_t st)
+{
+    const uint32_t *row = ds.table + (size_t)s * ds.width;
+    hipError_t e = hipSuccess;
+    for (int c = 0; c < 2 && e == hipSuccess; ++c) {
+        if (P.kind == PBIT_EA3D)
+            e = ea_halfsweep(P.ea, ds.spins, ds.Rp, c, row, ds.width, t, rq0, key, st);
+        else
+            e = bq_halfsweep(P.bq, c, ds.MA, ds.MB, ds.R, ds.Rp, row, ds.width, t, rq0, key, st);
+    }
+    return e;
+}
+
+static hipError_t energies(const Problem &P, DevState &ds, hipStream_t st)
+{
+    return P.kind == PBIT_EA3D ? ea_energy(P.ea, ds.spins, ds.Rp, ds.R, ds.E32, st)
+                               : bq_energy(P.bq, ds.MA, ds.MB, ds.R, ds.Rp, ds.E32, st);
+}
+
+static hipError_t to_rows(const Problem &P, DevState &ds, int8_t *dst, hipStream_t st)
+{
+    return P.kind == PBIT_EA3D ? ea_to_rows(P.ea, ds.spins, ds.Rp, dst, ds.R, st)
+                               : bq_to_rows(P.bq, ds.MA, ds.MB, dst, ds.R, st);
+}
+
+static int fetch_energies(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStream_t st, std::vector<int32_t> &out)
+{
+    hipError_t e = energies(P, ds, st);
+    if (e == hipSuccess) {
+        out.resize(ds.R);
+        e = hipMemcpyAsync(out.data(), ds.E32, sizeof(int32_t) * ds.R, hipMemcpyDeviceToHost, st);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return device_fail(ctx, e, "energy evaluation");
+    return PBIT_OK;
+}
+
+int run_blocking(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, pbit_result *res)
+{
+    const hipStream_t st = ctx->stream;
+    DevState ds;
+    int rc = prepare(ctx, P, d, st, ds, nullptr);
+    if (rc) return rc;
+    const Key key{(uint32_t)d->seed, (uint32_t)(d->seed >> 32)};
+    const uint32_t rq0 = (uint32_t)d->replica_offset >> 2;
+    const int check = d->has_target ? (d->trace_every > 0 ? d->trace_every : 1) : d->trace_every;
+    std::vector<int32_t> e32;
+    int done = 0, trace_len = 0;
+    bool hit = false;
+    for (int s = 0; s < d->n_sweeps && !hit; ++s) {
+        hipError_t e = sweep(P, ds, s, (uint32_t)(d->sweep_offset + s), rq0, key, st);
+        if (e != hipSuccess) return device_fail(ctx, e, "sweep launch");
+        done = s + 1;
+        if (check > 0 && done % check == 0) {
+            rc = fetch_energies(ctx, P, ds, st, e32);
+            if (rc) return rc;
+            if (d->trace_every > 0 && done % d->trace_every == 0 && trace_len < res->trace_cap) {
+                if (res->energy_trace)
+                    for (int r = 0; r < ds.R; ++r) res->energy_trace[(size_t)trace_len * ds.R + r] = e32[r];
+                if (res->spin_trace) {
+                    void *v = nullptr;
+                    rc = scratch(ctx, Slot::Stage, (size_t)ds.R * P.N, &v);
+                    if (rc) return rc;
+                    e = to_rows(P, ds, (int8_t *)v, st);
+                    if (e == hipSuccess)
+                        e = hipMemcpyAsync(res->spin_trace + (size_t)trace_len * ds.R * P.N, v, (size_t)ds.R * P.N,
+                                           hipMemcpyDeviceToHost, st);
+                    if (e == hipSuccess) e = hipStreamSynchronize(st);
+                    if (e != hipSuccess) return device_fail(ctx, e, "spin trace");
+                }
+                ++trace_len;
+            }
+            if (d->has_target && *std::min_element(e32.begin(), e32.end()) <= d->target_energy) hit = true;
+        }
+    }
+    rc = fetch_energies(ctx, P, ds, st, e32);
+    if (rc) return rc;
+    if (res->spins) {
+        void *v = nullptr;
+        rc = scratch(ctx, Slot::Stage, (size_t)ds.R * P.N, &v);
+        if (rc) return rc;
+        hipError_t e = to_rows(P, ds, (int8_t *)v, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(res->spins, v, (size_t)ds.R * P.N, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return device_fail(ctx, e, "spin readback");
+    }
+    int best = 0;
+    for (int r = 0; r < ds.R; ++r) {
+        if (res->energies) res->energies[r] = e32[r];
+        if (e32[r] < e32[best]) best = r;
+    }
+    res->best_energy = e32[best];
+    res->best_replica = best;
+    res->sweeps_done = done;
+    res->trace_len = trace_len;
+    return PBIT_OK;
+}
+
+int run_device(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, int8_t *d_spins, bool spins_in,
+               int64_t *d_energies, hipStream_t st)
+{
+    DevState ds;
+    int rc = prepare(ctx, P, d, st, ds, spins_in ? d_spins : nullptr);
+    if (rc) return rc;
+    const Key key{(uint32_t)d->seed, (uint32_t)(d->seed >> 32)};
+    const uint32_t rq0 = (uint32_t)d->replica_offset >> 2;
+    for (int s = 0; s < d->n_sweeps; ++s) {
+        hipError_t e = sweep(P, ds, s, (uint32_t)(d->sweep_offset + s), rq0, key, st);
+        if (e != hipSuccess) return device_fail(ctx, e, "sweep launch");
+    }
+    hipError_t e = to_rows(P, ds, d_spins, st);
+    if (e == hipSuccess && d_energies) {
+        e = energies(P, ds, st);
+        if (e == hipSuccess) e = widen_i32_i64(ds.E32, d_energies, ds.R, st);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return device_fail(ctx, e, "anneal (device buffers)");
+    return PBIT_OK;
+}
+
+}  // namespace pbit
+
+extern "C" int pbit_anneal(pbit_ctx *ctx, uint64_t problem, const pbit_anneal_desc *desc, pbit_result *result)
+{
+    try {
+        PBIT_ENTER(ctx);
+        int rc = check_desc(desc, "pbit_anneal");
+        if (rc) return rc;
+        if (!result) return fail(PBIT_E_ARG, "pbit_anneal: result is NULL");
+        Problem *P = find_problem(ctx, problem);
+        if (!P) return fail(PBIT_E_HANDLE, "pbit_anneal: unknown problem handle");
+        if (result->trace_cap < 0) return fail(PBIT_E_ARG, "pbit_anneal: trace_cap must be >= 0");
+        if (desc->init_spins && !spins_in_range(desc->init_spins, (size_t)desc->n_replicas * P->N))
+            return fail(PBIT_E_RANGE, "pbit_anneal: init_spins must be +-1");
+        return run_blocking(ctx, *P, desc, result);
+    } catch (const std::bad_alloc &) {
+        return fail(PBIT_E_NOMEM, "pbit_anneal: host allocation failed");
+    } catch (...) {
+        return fail(PBIT_E_ARG, "pbit_anneal: internal error");
+    }
+}
+
+extern "C" int pbit_anneal_dev(pbit_ctx *ctx, uint64_t problem, const pbit_anneal_desc *desc, void *d_spins,
+                               int32_t spins_in, void *d_energies, void *hip_stream)
+{
+    try {
+        PBIT_ENTER(ctx);
+        int rc = check_desc(desc, "pbit_anneal_dev");
+        if (rc) return rc;
+        if (!d_spins) return fail(PBIT_E_ARG, "pbit_anneal_dev: d_spins is NULL");
+        if (desc->init_spins) return fail(PBIT_E_ARG, "pbit_anneal_dev: pass initial spins in d_spins (spins_in)");
+        if (desc->trace_every || desc->has_target)
+            return fail(PBIT_E_ARG, "pbit_anneal_dev: traces and targets need pbit_anneal");
+        Problem *P = find_problem(ctx, problem);
+        if (!P) return fail(PBIT_E_HANDLE, "pbit_anneal_dev: unknown problem handle");
+        hipStream_t st = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+        return run_device(ctx, *P, desc, (int8_t *)d_spins, spins_in != 0, (int64_t *)d_energies, st);
+    } catch (const std::bad_alloc &) {
+        return fail(PBIT_E_NOMEM, "pbit_anneal_dev: host allocation failed");
+    } catch (...) {
+        return fail(PBIT_E_ARG, "pbit_anneal_dev: internal error");
+    }
+}
+
+extern "C" int pbit_energy(pbit_ctx *ctx, uint64_t problem, const int8_t *spins, int32_t R, int64_t *out)
+{
+    try {
+        PBIT_ENTER(ctx);
+        if (!spins || !out || R < 1) return fail(PBIT_E_ARG, "pbit_energy: bad arguments");
+        Problem *P = find_problem(ctx, problem);
+        if (!P) return fail(PBIT_E_HANDLE, "pbit_energy: unknown problem handle");
+        if (!spins_in_range(spins, (size_t)R * P->N)) return fail(PBIT_E_RANGE, "pbit_energy: spins must be +-1");
+        pbit_anneal_desc d{};
+        d.n_replicas = R;
+        d.init_spins = spins;
+        DevState ds;
+        int rc = prepare(ctx, *P, &d, ctx->stream, ds, nullptr);
+        if (rc) return rc;
+        std::vector<int32_t> e32;
+        rc = fetch_energies(ctx, *P, ds, ctx->stream, e32);
+        if (rc) return rc;
+        for (int r = 0; r < R; ++r) out[r] = e32[r];
+        return PBIT_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(PBIT_E_NOMEM, "pbit_energy: host allocation failed");
+    } catch (...) {
+        return fail(PBIT_E_ARG, "pbit_energy: internal error");
+    }
+}

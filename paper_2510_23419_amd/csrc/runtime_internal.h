@@ -1,0 +1,67 @@
+// runtime_internal.h — host-side state of a libpbit context.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "../../include/pbit.h"
+#include "internal.h"
+
+namespace pbit {
+
+struct Problem {
+    int kind = 0;
+    int64_t N = 0;
+    int amax = 0;  // largest possible |I|
+    EaView ea{};
+    BqView bq{};
+    std::vector<void *> allocs;
+    int jobs = 0;  // serving jobs that still reference the problem
+};
+
+enum class Slot : int { Spins = 0, Table, E32, Stage, Count };
+
+struct Scratch {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct ServeState;
+
+}  // namespace pbit
+
+struct pbit_ctx {
+    std::mutex mu;
+    int device = 0;
+    uint32_t serial = 0;
+    uint64_t budget = 0;
+    uint64_t in_use = 0;
+    bool poisoned = false;
+    hipStream_t stream = nullptr;
+    uint64_t next_handle = 0;
+    std::map<uint64_t, pbit::Problem> problems;
+    std::map<void *, size_t> sizes;
+    std::array<pbit::Scratch, (int)pbit::Slot::Count> scratch{};
+    std::vector<uint32_t> host_table;
+    pbit::ServeState *serve = nullptr;
+};
+
+namespace pbit {
+
+int fail(int code, const char *fmt, ...);
+int device_fail(pbit_ctx *ctx, hipError_t e, const char *where);
+int dev_alloc(pbit_ctx *ctx, size_t bytes, void **out);
+void dev_free(pbit_ctx *ctx, void *p);
+int scratch(pbit_ctx *ctx, Slot slot, size_t bytes, void **out);
+Problem *find_problem(pbit_ctx *ctx, uint64_t handle);
+int check_desc(const pbit_anneal_desc *d, const char *who);
+uint32_t minority_threshold(double beta, int a);
+int table_width(const double *beta, int S, int amax);
+void build_table(const double *beta, int S, int width, uint32_t *out);
+void serve_shutdown(pbit_ctx *ctx);
+
+}  // namespace pbit

@@ -1,0 +1,309 @@
+"""ctypes binding of libpbit (the MI355X p-bit sweep library).
+
+Argument marshalling only: every step of the sweep runs in the HIP kernels of
+libpbit.so.  The functions keep the C names; see ``include/pbit.h`` for the
+meaning of every argument, the layouts and the error codes.  If the library is
+not built, loading fails with an error; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+from pathlib import Path
+
+import numpy as np
+
+_PKG = Path(__file__).resolve().parent
+LIB_PATH = _PKG / "libpbit.so"
+
+PBIT_OK = 0
+PBIT_PENDING = 1
+PBIT_E_ARG = -1
+PBIT_E_COLOURING = -2
+PBIT_E_RANGE = -3
+PBIT_E_NOMEM = -4
+PBIT_E_BUSY = -5
+PBIT_E_HANDLE = -6
+PBIT_E_DEVICE = -7
+PBIT_E_UNSUPPORTED = -8
+
+PBIT_EA3D = 1
+PBIT_BICLIQUE = 2
+
+EXPORTS = ("pbit_create", "pbit_destroy", "pbit_last_error", "pbit_bytes_in_use", "pbit_load_problem",
+           "pbit_unload_problem", "pbit_problem_spins", "pbit_anneal", "pbit_anneal_dev", "pbit_energy",
+           "pbit_submit", "pbit_poll", "pbit_progress", "pbit_threshold_table", "pbit_version")
+
+
+class PbitError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__("%s (code %d)" % (message, code))
+        self.code = code
+
+
+class ProblemDesc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("dims", ctypes.c_int32 * 3),
+                ("J", ctypes.c_void_p), ("h", ctypes.c_void_p)]
+
+
+class AnnealDesc(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_void_p), ("n_sweeps", ctypes.c_int32), ("sweep_offset", ctypes.c_int32),
+                ("n_replicas", ctypes.c_int32), ("replica_offset", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("init_spins", ctypes.c_void_p), ("trace_every", ctypes.c_int32), ("has_target", ctypes.c_int32),
+                ("target_energy", ctypes.c_int64)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("spins", ctypes.c_void_p), ("energies", ctypes.c_void_p), ("best_energy", ctypes.c_int64),
+                ("best_replica", ctypes.c_int32), ("sweeps_done", ctypes.c_int32),
+                ("energy_trace", ctypes.c_void_p), ("trace_cap", ctypes.c_int32), ("trace_len", ctypes.c_int32),
+                ("spin_trace", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libpbit.so (built in-tree by ``__graft_entry__.build()``)."""
+    global _lib
+    if _lib is None:
+        if not LIB_PATH.exists():
+            raise RuntimeError("libpbit.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        L = ctypes.CDLL(str(LIB_PATH))
+        P, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+        sig = {
+            "pbit_create": ([ctypes.POINTER(P), ctypes.c_int, u64], ctypes.c_int),
+            "pbit_destroy": ([P], None),
+            "pbit_last_error": ([], ctypes.c_char_p),
+            "pbit_bytes_in_use": ([P], u64),
+            "pbit_load_problem": ([P, ctypes.POINTER(ProblemDesc), ctypes.POINTER(u64)], ctypes.c_int),
+            "pbit_unload_problem": ([P, u64], ctypes.c_int),
+            "pbit_problem_spins": ([P, u64], i64),
+            "pbit_anneal": ([P, u64, ctypes.POINTER(AnnealDesc), ctypes.POINTER(Result)], ctypes.c_int),
+            "pbit_anneal_dev": ([P, u64, ctypes.POINTER(AnnealDesc), P, i32, P, P], ctypes.c_int),
+            "pbit_energy": ([P, u64, P, i32, P], ctypes.c_int),
+            "pbit_submit": ([P, u64, ctypes.POINTER(AnnealDesc), ctypes.POINTER(u64)], ctypes.c_int),
+            "pbit_poll": ([P, u64, ctypes.POINTER(Result)], ctypes.c_int),
+            "pbit_progress": ([P], ctypes.c_int),
+            "pbit_threshold_table": ([P, i32, i32, P], ctypes.c_int),
+            "pbit_version": ([], ctypes.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise PbitError(rc, lib().pbit_last_error().decode())
+    return rc
+
+
+def _ptr(a):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+# ---------------------------------------------------------------- C-named calls
+
+def pbit_version() -> str:
+    return lib().pbit_version().decode()
+
+
+def pbit_create(device: int = 0, hbm_budget_bytes: int = 0) -> ctypes.c_void_p:
+    ctx = ctypes.c_void_p()
+    _check(lib().pbit_create(ctypes.byref(ctx), int(device), int(hbm_budget_bytes)))
+    return ctx
+
+
+def pbit_destroy(ctx) -> None:
+    lib().pbit_destroy(ctx)
+
+
+def pbit_bytes_in_use(ctx) -> int:
+    return int(lib().pbit_bytes_in_use(ctx))
+
+
+def _problem_desc(kind, dims, J, h):
+    J = np.ascontiguousarray(J, dtype=np.int8)
+    h = None if h is None else np.ascontiguousarray(h, dtype=np.int8)
+    d = ProblemDesc()
+    d.kind = int(kind)
+    dd = list(dims) + [0] * (3 - len(dims))
+    for k in range(3):
+        d.dims[k] = int(dd[k])
+    d.J = J.ctypes.data
+    d.h = None if h is None else h.ctypes.data
+    return d, (J, h)
+
+
+def pbit_load_problem(ctx, kind: int, dims, J, h=None) -> int:
+    d, keep = _problem_desc(kind, dims, J, h)
+    out = ctypes.c_uint64()
+    _check(lib().pbit_load_problem(ctx, ctypes.byref(d), ctypes.byref(out)))
+    del keep
+    return int(out.value)
+
+
+def load_instance(ctx, inst) -> int:
+    """Load a problem dict as produced by the synthetic generators."""
+    kind = PBIT_EA3D if inst["kind"] == "ea3d" else PBIT_BICLIQUE
+    return pbit_load_problem(ctx, kind, inst["dims"], inst["J"], inst.get("h"))
+
+
+def pbit_unload_problem(ctx, problem: int) -> None:
+    _check(lib().pbit_unload_problem(ctx, int(problem)))
+
+
+def pbit_problem_spins(ctx, problem: int) -> int:
+    return int(_check(lib().pbit_problem_spins(ctx, int(problem))))
+
+
+def _anneal_desc(beta, n_replicas, seed, sweep_offset=0, replica_offset=0, init_spins=None, trace_every=0,
+                 target=None):
+    beta = np.ascontiguousarray(beta, dtype=np.float64).reshape(-1)
+    init = None if init_spins is None else np.ascontiguousarray(init_spins, dtype=np.int8)
+    d = AnnealDesc()
+    d.beta = beta.ctypes.data if beta.size else None
+    d.n_sweeps = beta.size
+    d.sweep_offset = int(sweep_offset)
+    d.n_replicas = int(n_replicas)
+    d.replica_offset = int(replica_offset)
+    d.seed = int(seed) & (2**64 - 1)
+    d.init_spins = None if init is None else init.ctypes.data
+    d.trace_every = int(trace_every)
+    d.has_target = 0 if target is None else 1
+    d.target_energy = 0 if target is None else int(target)
+    return d, (beta, init)
+
+
+class AnnealOutput:
+    def __init__(self, spins, energies, best_energy, best_replica, sweeps_done, energy_trace, spin_trace):
+        self.spins = spins
+        self.energies = energies
+        self.best_energy = best_energy
+        self.best_replica = best_replica
+        self.sweeps_done = sweeps_done
+        self.energy_trace = energy_trace
+        self.spin_trace = spin_trace
+
+
+def _result_buffers(R, N, S, trace_every, want_spins, trace_spins):
+    spins = np.zeros((R, N), np.int8) if want_spins else None
+    energies = np.zeros(R, np.int64)
+    cap = S // trace_every if trace_every > 0 else 0
+    etrace = np.zeros((cap, R), np.int64) if cap else None
+    strace = np.zeros((cap, R, N), np.int8) if (cap and trace_spins) else None
+    res = Result()
+    res.spins = None if spins is None else spins.ctypes.data
+    res.energies = energies.ctypes.data
+    res.energy_trace = None if etrace is None else etrace.ctypes.data
+    res.trace_cap = cap
+    res.spin_trace = None if strace is None else strace.ctypes.data
+    return res, spins, energies, etrace, strace
+
+
+def _output(res, spins, energies, etrace, strace):
+    n = res.trace_len
+    return AnnealOutput(spins, energies, int(res.best_energy), int(res.best_replica), int(res.sweeps_done),
+                        None if etrace is None else etrace[:n], None if strace is None else strace[:n])
+
+
+def pbit_anneal(ctx, problem: int, beta, n_replicas: int, seed: int, sweep_offset: int = 0, replica_offset: int = 0,
+                init_spins=None, trace_every: int = 0, target=None, want_spins: bool = True,
+                trace_spins: bool = False) -> AnnealOutput:
+    N = pbit_problem_spins(ctx, problem)
+    d, keep = _anneal_desc(beta, n_replicas, seed, sweep_offset, replica_offset, init_spins, trace_every, target)
+    res, spins, energies, etrace, strace = _result_buffers(int(n_replicas), N, d.n_sweeps, int(trace_every),
+                                                           want_spins, trace_spins)
+    _check(lib().pbit_anneal(ctx, int(problem), ctypes.byref(d), ctypes.byref(res)))
+    del keep
+    return _output(res, spins, energies, etrace, strace)
+
+
+def pbit_anneal_dev(ctx, problem: int, beta, n_replicas: int, seed: int, d_spins, spins_in: bool = False,
+                    d_energies=None, stream=None, sweep_offset: int = 0, replica_offset: int = 0) -> None:
+    """Device-buffer anneal.  ``d_spins`` (int8 [R][N]) and ``d_energies``
+    (int64 [R]) are torch CUDA tensors; the work runs on ``stream`` (a torch
+    stream, default: torch's current stream) and is finished on return."""
+    import torch
+
+    N = pbit_problem_spins(ctx, problem)
+    R = int(n_replicas)
+    if d_spins.dtype != torch.int8 or not d_spins.is_cuda or not d_spins.is_contiguous() or d_spins.numel() != R * N:
+        raise ValueError("d_spins must be a contiguous int8 CUDA tensor of R*N elements")
+    if d_energies is not None and (d_energies.dtype != torch.int64 or not d_energies.is_cuda
+                                   or d_energies.numel() != R):
+        raise ValueError("d_energies must be an int64 CUDA tensor of R elements")
+    st = stream if stream is not None else torch.cuda.current_stream(d_spins.device)
+    d, keep = _anneal_desc(beta, R, seed, sweep_offset, replica_offset)
+    _check(lib().pbit_anneal_dev(ctx, int(problem), ctypes.byref(d), ctypes.c_void_p(d_spins.data_ptr()),
+                                 1 if spins_in else 0,
+                                 None if d_energies is None else ctypes.c_void_p(d_energies.data_ptr()),
+                                 ctypes.c_void_p(st.cuda_stream)))
+    del keep
+
+
+def pbit_energy(ctx, problem: int, spins) -> np.ndarray:
+    s = np.ascontiguousarray(spins, dtype=np.int8)
+    N = pbit_problem_spins(ctx, problem)
+    s = s.reshape(-1, N)
+    out = np.zeros(s.shape[0], np.int64)
+    _check(lib().pbit_energy(ctx, int(problem), _ptr(s), s.shape[0], _ptr(out)))
+    return out
+
+
+def pbit_threshold_table(beta, A: int) -> np.ndarray:
+    beta = np.ascontiguousarray(beta, dtype=np.float64).reshape(-1)
+    out = np.zeros((beta.size, int(A) + 1), np.uint32)
+    _check(lib().pbit_threshold_table(_ptr(beta), beta.size, int(A), _ptr(out)))
+    return out
+
+
+def pbit_submit(ctx, problem: int, beta, n_replicas: int, seed: int, sweep_offset: int = 0, replica_offset: int = 0,
+                init_spins=None, trace_every: int = 0, target=None) -> int:
+    d, keep = _anneal_desc(beta, n_replicas, seed, sweep_offset, replica_offset, init_spins, trace_every, target)
+    out = ctypes.c_uint64()
+    _check(lib().pbit_submit(ctx, int(problem), ctypes.byref(d), ctypes.byref(out)))
+    del keep
+    return int(out.value)
+
+
+def pbit_poll(ctx, job: int, n_replicas: int, n_spins: int, n_sweeps: int = 0, trace_every: int = 0,
+              want_spins: bool = True):
+    """Returns None while the job is pending, else an AnnealOutput."""
+    res, spins, energies, etrace, strace = _result_buffers(int(n_replicas), int(n_spins), int(n_sweeps),
+                                                           int(trace_every), want_spins, False)
+    rc = _check(lib().pbit_poll(ctx, int(job), ctypes.byref(res)))
+    if rc == PBIT_PENDING:
+        return None
+    return _output(res, spins, energies, etrace, strace)
+
+
+def pbit_progress(ctx) -> None:
+    _check(lib().pbit_progress(ctx))
+
+
+class Context:
+    """Owns one libpbit context; closes it on exit."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        self.ctx = pbit_create(device, hbm_budget_bytes)
+
+    def close(self):
+        if self.ctx:
+            pbit_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

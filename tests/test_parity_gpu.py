@@ -1,0 +1,280 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle: bit-exact
+spins and energies, every replica after every sweep on the small cases, and
+sampled replicas at several sweep counts at the full benchmark sizes."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import oracle
+from paper_2510_23419_amd import pbit
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def graph_of(inst):
+    if inst["kind"] == "ea3d":
+        return oracle.ea_graph(inst["dims"], inst["J"], inst["h"])
+    return oracle.biclique_graph(*inst["dims"], inst["J"], inst["h"])
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = pbit.Context(0)
+    yield c.ctx
+    c.close()
+
+
+def _ea_with_zeros(dims, seed):
+    inst = synth.ea_instance(dims, seed=seed, field="uniform3")
+    rng = np.random.default_rng(seed + 1)
+    inst["J"] = (inst["J"] * (rng.random(inst["J"].shape) < 0.8)).astype(np.int8)  # some J = 0
+    return inst
+
+
+# ---------------------------------------------------------------- energies
+
+@pytest.mark.parametrize("dims", [(2, 2, 2), (4, 6, 2), (6, 6, 6), (10, 8, 6)])
+@pytest.mark.parametrize("R", [1, 17, 64])
+def test_ea_energy_matches_oracle(ctx, dims, R):
+    inst = _ea_with_zeros(dims, seed=sum(dims) + R)
+    prob = pbit.load_instance(ctx, inst)
+    spins = synth.random_spins(R, int(np.prod(dims)), seed=R)
+    _say("ea energy %s R=%d" % (dims, R))
+    assert np.array_equal(pbit.pbit_energy(ctx, prob, spins), oracle.energy(graph_of(inst), spins))
+    pbit.pbit_unload_problem(ctx, prob)
+
+
+@pytest.mark.parametrize("na,nb", [(1, 1), (3, 5), (64, 64), (65, 63), (7, 130), (200, 129)])
+@pytest.mark.parametrize("R", [1, 63, 65, 130])
+def test_biclique_energy_matches_oracle(ctx, na, nb, R):
+    inst = synth.biclique_instance(na, seed=na * 7 + nb, nb=nb)
+    prob = pbit.load_instance(ctx, inst)
+    spins = synth.random_spins(R, na + nb, seed=R + na)
+    _say("biclique energy %dx%d R=%d" % (na, nb, R))
+    assert np.array_equal(pbit.pbit_energy(ctx, prob, spins), oracle.energy(graph_of(inst), spins))
+    pbit.pbit_unload_problem(ctx, prob)
+
+
+# ---------------------------------------------------------------- every sweep
+
+def _every_sweep(ctx, inst, beta, R, seed, init=None):
+    prob = pbit.load_instance(ctx, inst)
+    got = pbit.pbit_anneal(ctx, prob, beta, R, seed, init_spins=init, trace_every=1, trace_spins=True)
+    ref = oracle.anneal(graph_of(inst), beta, R, seed, init_spins=init, trace_every=1, trace_spins=True)
+    pbit.pbit_unload_problem(ctx, prob)
+    assert got.spin_trace.shape == ref.spin_trace.shape
+    for s in range(len(beta)):
+        if not np.array_equal(got.spin_trace[s], ref.spin_trace[s]):
+            bad = np.argwhere(got.spin_trace[s] != ref.spin_trace[s])
+            raise AssertionError("first mismatch after sweep %d at (replica, site) %s" % (s + 1, bad[0]))
+    assert np.array_equal(got.energy_trace, ref.energy_trace)
+    assert np.array_equal(got.spins, ref.spins)
+    assert np.array_equal(got.energies, ref.energies)
+    assert got.best_energy == ref.energies.min()
+    assert got.best_replica == int(np.argmin(ref.energies))
+    return got
+
+
+def test_ea_L6_every_replica_every_sweep(ctx):
+    """EA L=6 (216 spins), +-1 couplings, h = 0, 64 replicas from random starts,
+    beta linear 0.1 -> 3.0 over 1000 sweeps, seed 1."""
+    inst = synth.ea_instance(6, seed=1)
+    _say("ea L=6 R=64 S=1000 every sweep")
+    _every_sweep(ctx, inst, synth.beta_linear(0.1, 3.0, 1000), 64, seed=1)
+
+
+@pytest.mark.parametrize("dims,R", [((2, 2, 2), 5), ((4, 6, 2), 33), ((10, 8, 6), 20)])
+def test_ea_ragged_with_fields_and_zero_couplings(ctx, dims, R):
+    inst = _ea_with_zeros(dims, seed=3 * R)
+    _say("ea ragged %s R=%d" % (dims, R))
+    _every_sweep(ctx, inst, synth.beta_geometric(0.1, 5.0, 40), R, seed=0xDEADBEEFCAFE)
+
+
+@pytest.mark.parametrize("na,nb,R", [(40, 40, 70), (7, 130, 3), (130, 66, 129), (1, 1, 1)])
+def test_biclique_every_replica_every_sweep(ctx, na, nb, R):
+    inst = synth.biclique_instance(na, seed=na + nb, nb=nb)
+    _say("biclique %dx%d R=%d every sweep" % (na, nb, R))
+    _every_sweep(ctx, inst, synth.beta_linear(0.05, 2.0, 30), R, seed=5)
+
+
+def test_given_initial_spins(ctx):
+    inst = synth.ea_instance(4, seed=2, field="uniform3")
+    init = synth.random_spins(9, 64, seed=9)
+    _every_sweep(ctx, inst, synth.beta_linear(0.5, 1.0, 10), 9, seed=2, init=init)
+    binst = synth.biclique_instance(20, seed=3)
+    _every_sweep(ctx, binst, synth.beta_linear(0.5, 1.0, 10), 9, seed=2, init=synth.random_spins(9, 40, seed=1))
+
+
+def test_zero_sweeps_returns_the_random_start(ctx):
+    for inst in (synth.ea_instance(4, seed=5), synth.biclique_instance(33, seed=5)):
+        prob = pbit.load_instance(ctx, inst)
+        got = pbit.pbit_anneal(ctx, prob, np.zeros(0), 12, seed=77)
+        ref = oracle.anneal(graph_of(inst), np.zeros(0), 12, seed=77)
+        assert np.array_equal(got.spins, ref.spins) and np.array_equal(got.energies, ref.energies)
+        pbit.pbit_unload_problem(ctx, prob)
+
+
+# ---------------------------------------------------------------- mechanics
+
+@pytest.mark.parametrize("make", [lambda: synth.ea_instance(8, seed=4, field="uniform3"),
+                                  lambda: synth.biclique_instance(100, seed=4)])
+def test_resume_split_and_replica_slices(ctx, make):
+    inst = make()
+    prob = pbit.load_instance(ctx, inst)
+    beta = synth.beta_linear(0.1, 3.0, 60)
+    full = pbit.pbit_anneal(ctx, prob, beta, 24, seed=3)
+    a = pbit.pbit_anneal(ctx, prob, beta[:25], 24, seed=3)
+    b = pbit.pbit_anneal(ctx, prob, beta[25:], 24, seed=3, sweep_offset=25, init_spins=a.spins)
+    assert np.array_equal(full.spins, b.spins) and np.array_equal(full.energies, b.energies)
+    for off, cnt in ((0, 4), (8, 12), (20, 4), (4, 1)):
+        part = pbit.pbit_anneal(ctx, prob, beta, cnt, seed=3, replica_offset=off)
+        assert np.array_equal(full.spins[off:off + cnt], part.spins)
+    ref = oracle.anneal(graph_of(inst), beta, 24, seed=3)
+    assert np.array_equal(full.spins, ref.spins)
+    pbit.pbit_unload_problem(ctx, prob)
+
+
+def test_two_runs_are_identical(ctx):
+    inst = synth.ea_instance(16, seed=16)
+    prob = pbit.load_instance(ctx, inst)
+    beta = synth.beta_geometric(0.1, 5.0, 50)
+    a = pbit.pbit_anneal(ctx, prob, beta, 256, seed=1)
+    b = pbit.pbit_anneal(ctx, prob, beta, 256, seed=1)
+    assert np.array_equal(a.spins, b.spins)
+    pbit.pbit_unload_problem(ctx, prob)
+
+
+def test_target_stops_at_first_reaching_sweep(ctx):
+    inst = synth.ea_instance(6, seed=11)
+    beta = synth.beta_linear(0.1, 3.0, 300)
+    ref = oracle.anneal(graph_of(inst), beta, 16, seed=4, trace_every=1)
+    mins = ref.energy_trace.min(axis=1)
+    target = int(mins[150])
+    first = int(np.argmax(mins <= target)) + 1
+    prob = pbit.load_instance(ctx, inst)
+    got = pbit.pbit_anneal(ctx, prob, beta, 16, seed=4, target=target)
+    assert got.sweeps_done == first
+    assert got.best_energy <= target
+    pre = oracle.anneal(graph_of(inst), beta[:first], 16, seed=4)
+    assert np.array_equal(got.spins, pre.spins)
+    pbit.pbit_unload_problem(ctx, prob)
+
+
+def test_anneal_dev_matches_blocking(ctx):
+    import torch
+
+    for inst in (synth.ea_instance(8, seed=6), synth.biclique_instance(96, seed=6)):
+        prob = pbit.load_instance(ctx, inst)
+        N = pbit.pbit_problem_spins(ctx, prob)
+        beta = synth.beta_linear(0.1, 2.0, 20)
+        ref = pbit.pbit_anneal(ctx, prob, beta, 40, seed=9)
+        d_spins = torch.zeros((40, N), dtype=torch.int8, device="cuda:0")
+        d_e = torch.zeros(40, dtype=torch.int64, device="cuda:0")
+        pbit.pbit_anneal_dev(ctx, prob, beta, 40, 9, d_spins, d_energies=d_e)
+        assert np.array_equal(d_spins.cpu().numpy(), ref.spins)
+        assert np.array_equal(d_e.cpu().numpy(), ref.energies)
+        # spins_in: continue from the device spins
+        beta2 = synth.beta_linear(2.0, 3.0, 5)
+        pbit.pbit_anneal_dev(ctx, prob, beta2, 40, 9, d_spins, spins_in=True, d_energies=d_e, sweep_offset=20)
+        ref2 = pbit.pbit_anneal(ctx, prob, beta2, 40, 9, sweep_offset=20, init_spins=ref.spins)
+        assert np.array_equal(d_spins.cpu().numpy(), ref2.spins)
+        pbit.pbit_unload_problem(ctx, prob)
+
+
+# ---------------------------------------------------------------- errors
+
+def test_errors_leave_state_untouched(ctx):
+    with pytest.raises(pbit.PbitError) as ei:
+        pbit.load_instance(ctx, synth.ea_instance((5, 4, 4), seed=1))
+    assert ei.value.code == pbit.PBIT_E_COLOURING
+    bad = synth.ea_instance(4, seed=1)
+    bad["J"][1, 3] = 2
+    with pytest.raises(pbit.PbitError) as ei:
+        pbit.load_instance(ctx, bad)
+    assert ei.value.code == pbit.PBIT_E_RANGE
+    prob = pbit.load_instance(ctx, synth.ea_instance(4, seed=1))
+    with pytest.raises(pbit.PbitError) as ei:
+        pbit.pbit_anneal(ctx, prob, [0.5, np.nan], 4, seed=1)
+    assert ei.value.code == pbit.PBIT_E_RANGE
+    with pytest.raises(pbit.PbitError) as ei:
+        pbit.pbit_anneal(ctx, prob, [0.5], 4, seed=1, replica_offset=2)
+    assert ei.value.code == pbit.PBIT_E_ARG
+    bad_init = synth.random_spins(2, 64, seed=1)
+    bad_init[1, 5] = 0
+    with pytest.raises(pbit.PbitError) as ei:
+        pbit.pbit_anneal(ctx, prob, [0.5], 2, seed=1, init_spins=bad_init)
+    assert ei.value.code == pbit.PBIT_E_RANGE
+    pbit.pbit_unload_problem(ctx, prob)
+    with pytest.raises(pbit.PbitError) as ei:
+        pbit.pbit_anneal(ctx, prob, [0.5], 4, seed=1)
+    assert ei.value.code == pbit.PBIT_E_HANDLE
+    # the context still works
+    prob = pbit.load_instance(ctx, synth.ea_instance(4, seed=1))
+    assert pbit.pbit_anneal(ctx, prob, [0.5], 4, seed=1).spins.shape == (4, 64)
+    pbit.pbit_unload_problem(ctx, prob)
+
+
+def test_budget_is_enforced():
+    with pbit.Context(0, hbm_budget_bytes=200_000) as c:
+        prob = pbit.load_instance(c.ctx, synth.ea_instance(8, seed=1))  # ~3.6 KB of couplings
+        with pytest.raises(pbit.PbitError) as ei:
+            pbit.pbit_anneal(c.ctx, prob, [0.5], 4096, seed=1)  # 2 MB of spins
+        assert ei.value.code == pbit.PBIT_E_NOMEM
+        assert pbit.pbit_anneal(c.ctx, prob, [0.5], 16, seed=1).spins.shape == (16, 512)
+        assert pbit.pbit_bytes_in_use(c.ctx) <= 200_000
+
+
+# ---------------------------------------------------------------- full sizes, sampled
+
+def _sample_groups(R, rng, extra=2):
+    groups = {0, R // 4 - 1}
+    while len(groups) < 2 + extra:
+        groups.add(int(rng.integers(0, R // 4)))
+    return sorted(groups)
+
+
+def _check_sampled(ctx, inst, beta, R, seed, prefixes, full_groups, rng):
+    prob = pbit.load_instance(ctx, inst)
+    g = graph_of(inst)
+    for S in prefixes:
+        _say("  %s dims=%s R=%d prefix S=%d" % (inst["kind"], inst["dims"], R, S))
+        got = pbit.pbit_anneal(ctx, prob, beta[:S], R, seed)
+        groups = _sample_groups(R, rng) if S < len(beta) else full_groups
+        for gidx in groups:
+            ref = oracle.anneal(g, beta[:S], 4, seed, replica_offset=4 * gidx)
+            assert np.array_equal(got.spins[4 * gidx:4 * gidx + 4], ref.spins), (S, gidx)
+            assert np.array_equal(got.energies[4 * gidx:4 * gidx + 4], ref.energies), (S, gidx)
+    pbit.pbit_unload_problem(ctx, prob)
+
+
+def test_ea_L16_full_size_sampled(ctx):
+    """L=16 cube, 4096 replicas, beta geometric 0.1 -> 5.0 over 10^4 sweeps."""
+    inst = synth.ea_instance(16, seed=16)
+    beta = synth.beta_geometric(0.1, 5.0, 10_000)
+    rng = np.random.default_rng(16)
+    _check_sampled(ctx, inst, beta, 4096, 1, [1, 2, 10, 100, 1000, 10_000], [1023], rng)
+
+
+def test_ea_L32_full_size_sampled(ctx):
+    """L=32 cube, 4096 replicas, beta geometric 0.1 -> 5.0 over 10^4 sweeps."""
+    inst = synth.ea_instance(32, seed=32)
+    beta = synth.beta_geometric(0.1, 5.0, 10_000)
+    rng = np.random.default_rng(32)
+    _check_sampled(ctx, inst, beta, 4096, 1, [1, 2, 10, 100], [], rng)
+
+
+@pytest.mark.parametrize("n,prefixes", [(512, [1, 2, 10, 100, 2000]), (1024, [1, 2, 10, 100]),
+                                        (2048, [1, 2, 10]), (4096, [1, 2])])
+def test_biclique_full_size_sampled(ctx, n, prefixes):
+    """K_{n,n}, 1024 replicas, beta linear 0.05 -> 2.0 over 2000 sweeps."""
+    inst = synth.biclique_instance(n, seed=n)
+    beta = synth.beta_linear(0.05, 2.0, 2000)
+    rng = np.random.default_rng(n)
+    _check_sampled(ctx, inst, beta, 1024, 1, prefixes, [0], rng)
