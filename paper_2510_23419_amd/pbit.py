@@ -68,6 +68,10 @@ def lib() -> ctypes.CDLL:
     if _lib is None:
         if not LIB_PATH.exists():
             raise RuntimeError("libpbit.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        # torch ships its own HIP runtime under the same soname; loading torch
+        # first makes libpbit bind to that one copy, so that one process holds
+        # a single HIP runtime and torch's memory and streams are valid here.
+        import torch  # noqa: F401
         L = ctypes.CDLL(str(LIB_PATH))
         P, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
         sig = {
