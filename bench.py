@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""Benchmark of the p-bit sweep on one MI355X.
+
+One step is one whole anneal of the workload: threshold table (host, FP64),
+random start, every half-sweep of the beta schedule, final energies, all on
+device buffers that are resident before the timed region starts.
+
+Default workload: 3D Edwards-Anderson periodic cube L=32 (32,768 spins),
+J iid +-1, h = 0, 4,096 replicas, beta geometric 0.1 -> 5.0 over 10,000 sweeps,
+seed 1.  Other workloads (``--workload``) are the smaller cube and the biclique
+sizes, printed in the same format.
+
+Prints one JSON line with the throughput in p-bit updates per second (one
+update = one spin of one replica in one sweep), the roofline of the dominant
+kernel (its algorithmic bytes or int8 ops per launch over its mean launch time,
+measured with HIP events on the stream the kernels run on), and the CPU
+oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+INT8_MFMA_PEAK_TOPS = 5000.0   # MI355X dense int8 MFMA, published (TOP/s)
+
+WORKLOADS = {
+    "ea32": dict(kind="ea3d", L=32, R=4096, S=10_000, b0=0.1, b1=5.0, sched="geometric", inst_seed=32),
+    "ea16": dict(kind="ea3d", L=16, R=4096, S=10_000, b0=0.1, b1=5.0, sched="geometric", inst_seed=16),
+    "bq512": dict(kind="biclique", n=512, R=1024, S=2000, b0=0.05, b1=2.0, sched="linear", inst_seed=512),
+    "bq1024": dict(kind="biclique", n=1024, R=1024, S=2000, b0=0.05, b1=2.0, sched="linear", inst_seed=1024),
+    "bq2048": dict(kind="biclique", n=2048, R=1024, S=2000, b0=0.05, b1=2.0, sched="linear", inst_seed=2048),
+    "bq4096": dict(kind="biclique", n=4096, R=1024, S=2000, b0=0.05, b1=2.0, sched="linear", inst_seed=4096),
+}
+
+
+def describe(w):
+    if w["kind"] == "ea3d":
+        return ("3D Edwards-Anderson periodic cube L=%d (%d spins), J iid +-1, h=0, checkerboard, %d replicas, "
+                "beta %s %.2g->%.2g over %d sweeps, seed 1" % (w["L"], w["L"] ** 3, w["R"], w["sched"], w["b0"],
+                                                               w["b1"], w["S"]))
+    return ("biclique K_{%d,%d}, J iid +-1, h uniform {-1,0,1}, %d replicas, beta %s %.2g->%.2g over %d sweeps, "
+            "seed 1" % (w["n"], w["n"], w["R"], w["sched"], w["b0"], w["b1"], w["S"]))
+
+
+def make_instance(w):
+    import synth
+    if w["kind"] == "ea3d":
+        inst = synth.ea_instance(w["L"], seed=w["inst_seed"])
+    else:
+        inst = synth.biclique_instance(w["n"], seed=w["inst_seed"])
+    if w["sched"] == "geometric":
+        beta = synth.beta_geometric(w["b0"], w["b1"], w["S"])
+    else:
+        beta = synth.beta_linear(w["b0"], w["b1"], w["S"])
+    return inst, beta
+
+
+def cpu_baseline(w, inst, beta, budget_s):
+    """The oracle as it stands, single-threaded, on a bounded sample: the first
+    sweeps of the same schedule for a few replicas, sized to ~budget_s."""
+    from oracle import oracle
+    g = oracle.ea_graph(inst["dims"], inst["J"], inst["h"]) if w["kind"] == "ea3d" else \
+        oracle.biclique_graph(*inst["dims"], inst["J"], inst["h"])
+    N = g.n
+    # calibrate on a tiny run, then size the sample
+    t0 = time.perf_counter()
+    oracle.anneal(g, beta[:2], 4, seed=1)
+    rate = 2 * 4 * N / max(time.perf_counter() - t0, 1e-6)
+    R = 8
+    S = int(max(2, min(len(beta), budget_s * rate / (R * N))))
+    t0 = time.perf_counter()
+    oracle.anneal(g, beta[:S], R, seed=1)
+    dt = time.perf_counter() - t0
+    return {"value": R * N * S / dt, "unit": "p-bit updates/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d of %d sweeps, replicas 0-%d of %d, single-threaded C oracle (%s); %.1f s"
+                      % (S, len(beta), R - 1, w["R"], platform.processor() or platform.machine(), dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="ea32", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="oracle sample budget (0 = skip)")
+    ap.add_argument("--profile-every", type=int, default=8, help="bracket every k-th half-sweep with HIP events")
+    ap.add_argument("--sweeps", type=int, default=0, help="run only the first k sweeps of the schedule (profiling)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-sized int8 tensor 5 times (reference kernel for HBM counters)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only; run it with --gpus 1 (the path would shard replicas "
+              "across GPUs with no exchange, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2510_23419_amd import pbit
+
+    if args.calibrate_copy:
+        nbytes = args.calibrate_copy << 20
+        a = torch.ones(nbytes, dtype=torch.int8, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": nbytes, "copies": 5}))
+        return
+
+    w = WORKLOADS[args.workload]
+    inst, beta = make_instance(w)
+    if args.sweeps > 0:
+        beta = beta[:args.sweeps]
+    R = w["R"]
+    dev = torch.device("cuda:0")
+    ctx = pbit.Context(0)
+    prob = pbit.load_instance(ctx.ctx, inst)
+    N = pbit.pbit_problem_spins(ctx.ctx, prob)
+    d_spins = torch.empty((R, N), dtype=torch.int8, device=dev)
+    d_energy = torch.empty(R, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    for _ in range(args.warmup):
+        pbit.pbit_anneal_dev(ctx.ctx, prob, beta, R, 1, d_spins, d_energies=d_energy, stream=stream)
+    torch.cuda.synchronize()
+
+    kind = pbit.PBIT_EA3D if w["kind"] == "ea3d" else pbit.PBIT_BICLIQUE
+    pbit.pbit_profile_enable(ctx.ctx, args.profile_every)
+    pbit.pbit_profile_read(ctx.ctx, kind, reset=True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        pbit.pbit_anneal_dev(ctx.ctx, prob, beta, R, 1, d_spins, d_energies=d_energy, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    dev_ms = ev0.elapsed_time(ev1)
+    kern_ms, launches = pbit.pbit_profile_read(ctx.ctx, kind, reset=True)
+    pbit.pbit_profile_enable(ctx.ctx, 0)
+    best = int(d_energy.min().item())
+
+    S = len(beta)
+    updates = N * R * S * args.steps
+    ms_per_step = wall * 1e3 / args.steps
+    value = updates / wall
+
+    # roofline of the half-sweep kernel
+    avg_ms = kern_ms / max(launches, 1)
+    if w["kind"] == "ea3d":
+        # per launch: N/2 x R updates, each reads its share of the other colour's
+        # spins once (1 B) and writes its own spin (1 B); couplings ~0 B at R=4096
+        alg_bytes = N * R + 4 * (N // 2)
+        roof = {"bound": "hbm", "achieved": alg_bytes / (avg_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "traffic": None, "kernel": "k_ea_halfsweep",
+                "alg_bytes_per_launch": alg_bytes, "avg_launch_us": avg_ms * 1e3, "launches_timed": launches}
+    else:
+        n = w["n"]
+        alg_ops = 2 * n * n * R  # one side's fields: n x n couplings times n x R spins
+        roof = {"bound": "mfma", "achieved": alg_ops / (avg_ms * 1e-3) / 1e12, "peak": INT8_MFMA_PEAK_TOPS,
+                "unit": "TOP/s", "traffic": None, "kernel": "k_bq_halfsweep",
+                "alg_ops_per_launch": alg_ops, "avg_launch_us": avg_ms * 1e3, "launches_timed": launches}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+
+    cpu = None
+    if args.cpu_seconds > 0:
+        cpu = cpu_baseline(w, inst, beta, args.cpu_seconds)
+
+    out = {
+        "metric": "p-bit updates/s/GPU",
+        "value": value,
+        "unit": "p-bit updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8",
+        "data": "synthetic",
+        "config": {"workload": describe(w), "spins": N, "replicas": R, "sweeps": S,
+                   "anneals_per_s": args.steps / wall, "device_ms_per_step": dev_ms / args.steps,
+                   "best_energy": best},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    pbit.pbit_unload_problem(ctx.ctx, prob)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -178,6 +178,18 @@ int pbit_poll(pbit_ctx *ctx, uint64_t job, pbit_result *result);
 /* Drive queued work without waiting (also done inside pbit_poll). */
 int pbit_progress(pbit_ctx *ctx);
 
+/* ---- profiling -------------------------------------------------------------- */
+
+/* Bracket every `every`-th half-sweep launch (0 = off) with a pair of HIP
+ * events recorded on the stream the launch runs on, so that the device time of
+ * the sweep kernels can be read back without an external profiler. */
+int pbit_profile_enable(pbit_ctx *ctx, int32_t every);
+
+/* Device time and number of the bracketed half-sweep launches of problem kind
+ * `kind` (PBIT_EA3D or PBIT_BICLIQUE) since the last reset; `reset` nonzero
+ * clears the counters after reading. */
+int pbit_profile_read(pbit_ctx *ctx, int32_t kind, double *total_ms, int64_t *launches, int32_t reset);
+
 /* ---- host-side helpers (no GPU needed) ---------------------------------- */
 
 /* The uint32 minority-threshold table Tm[s][a], s < S, a <= A, as the library

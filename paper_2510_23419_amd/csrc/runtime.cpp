@@ -214,6 +214,7 @@ extern "C" void pbit_destroy(pbit_ctx *ctx)
         for (auto &kv : ctx->problems) free_problem(ctx, kv.second);
         ctx->problems.clear();
         release_scratch(ctx);
+        prof_release(ctx);
         (void)hipStreamDestroy(ctx->stream);
     }
     delete ctx;
@@ -503,15 +504,22 @@ static int prepare(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, h
     return PBIT_OK;
 }
 
-static hipError_t sweep(const Problem &P, DevState &ds, int s, uint32_t t, uint32_t rq0, Key key, hipStream_t st)
+static hipError_t sweep(pbit_ctx *ctx, const Problem &P, DevState &ds, int s, uint32_t t, uint32_t rq0, Key key,
+                        hipStream_t st)
 {
     const uint32_t *row = ds.table + (size_t)s * ds.width;
     hipError_t e = hipSuccess;
     for (int c = 0; c < 2 && e == hipSuccess; ++c) {
+        int slot = -1;
+        if (ctx->prof_every > 0 && (2 * s + c) % ctx->prof_every == 0) {
+            e = prof_begin(ctx, P.kind, st, &slot);
+            if (e != hipSuccess) return e;
+        }
         if (P.kind == PBIT_EA3D)
             e = ea_halfsweep(P.ea, ds.spins, ds.Rp, c, row, ds.width, t, rq0, key, st);
         else
             e = bq_halfsweep(P.bq, c, ds.MA, ds.MB, ds.R, ds.Rp, row, ds.width, t, rq0, key, st);
+        if (e == hipSuccess) e = prof_end(ctx, slot, st);
     }
     return e;
 }
@@ -536,6 +544,7 @@ static int fetch_energies(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStre
         e = hipMemcpyAsync(out.data(), ds.E32, sizeof(int32_t) * ds.R, hipMemcpyDeviceToHost, st);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = prof_harvest(ctx);
     if (e != hipSuccess) return device_fail(ctx, e, "energy evaluation");
     return PBIT_OK;
 }
@@ -553,7 +562,7 @@ int run_blocking(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, pbi
     int done = 0, trace_len = 0;
     bool hit = false;
     for (int s = 0; s < d->n_sweeps && !hit; ++s) {
-        hipError_t e = sweep(P, ds, s, (uint32_t)(d->sweep_offset + s), rq0, key, st);
+        hipError_t e = sweep(ctx, P, ds, s, (uint32_t)(d->sweep_offset + s), rq0, key, st);
         if (e != hipSuccess) return device_fail(ctx, e, "sweep launch");
         done = s + 1;
         if (check > 0 && done % check == 0) {
@@ -610,7 +619,7 @@ int run_device(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, int8_
     const Key key{(uint32_t)d->seed, (uint32_t)(d->seed >> 32)};
     const uint32_t rq0 = (uint32_t)d->replica_offset >> 2;
     for (int s = 0; s < d->n_sweeps; ++s) {
-        hipError_t e = sweep(P, ds, s, (uint32_t)(d->sweep_offset + s), rq0, key, st);
+        hipError_t e = sweep(ctx, P, ds, s, (uint32_t)(d->sweep_offset + s), rq0, key, st);
         if (e != hipSuccess) return device_fail(ctx, e, "sweep launch");
     }
     hipError_t e = to_rows(P, ds, d_spins, st);
@@ -619,6 +628,7 @@ int run_device(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, int8_
         if (e == hipSuccess) e = widen_i32_i64(ds.E32, d_energies, ds.R, st);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = prof_harvest(ctx);
     if (e != hipSuccess) return device_fail(ctx, e, "anneal (device buffers)");
     return PBIT_OK;
 }
@@ -691,4 +701,78 @@ extern "C" int pbit_energy(pbit_ctx *ctx, uint64_t problem, const int8_t *spins,
     } catch (...) {
         return fail(PBIT_E_ARG, "pbit_energy: internal error");
     }
+}
+
+// ---------------------------------------------------------------- profiling
+
+namespace pbit {
+
+hipError_t prof_begin(pbit_ctx *ctx, int kind, hipStream_t st, int *slot)
+{
+    *slot = -1;
+    const size_t need = ctx->prof_used + 2;
+    while (ctx->prof_pool.size() < need) {
+        hipEvent_t ev;
+        hipError_t e = hipEventCreate(&ev);
+        if (e != hipSuccess) return e;
+        ctx->prof_pool.push_back(ev);
+    }
+    const int k = (int)ctx->prof_used;
+    ctx->prof_used += 2;
+    ctx->prof_kind.push_back(kind);
+    *slot = k;
+    return hipEventRecord(ctx->prof_pool[k], st);
+}
+
+hipError_t prof_end(pbit_ctx *ctx, int slot, hipStream_t st)
+{
+    return slot < 0 ? hipSuccess : hipEventRecord(ctx->prof_pool[slot + 1], st);
+}
+
+// Called after the stream has been synchronised: fold the pending pairs in.
+hipError_t prof_harvest(pbit_ctx *ctx)
+{
+    for (size_t k = 0; k < ctx->prof_kind.size(); ++k) {
+        float ms = 0.f;
+        hipError_t e = hipEventElapsedTime(&ms, ctx->prof_pool[2 * k], ctx->prof_pool[2 * k + 1]);
+        if (e != hipSuccess) return e;
+        const int kind = ctx->prof_kind[k] == PBIT_EA3D ? 1 : 2;
+        ctx->prof_ms[kind] += ms;
+        ctx->prof_count[kind] += 1;
+    }
+    ctx->prof_kind.clear();
+    ctx->prof_used = 0;
+    return hipSuccess;
+}
+
+void prof_release(pbit_ctx *ctx)
+{
+    for (hipEvent_t ev : ctx->prof_pool) (void)hipEventDestroy(ev);
+    ctx->prof_pool.clear();
+    ctx->prof_kind.clear();
+    ctx->prof_used = 0;
+}
+
+}  // namespace pbit
+
+extern "C" int pbit_profile_enable(pbit_ctx *ctx, int32_t every)
+{
+    PBIT_ENTER(ctx);
+    if (every < 0) return fail(PBIT_E_ARG, "pbit_profile_enable: every must be >= 0");
+    ctx->prof_every = every;
+    return PBIT_OK;
+}
+
+extern "C" int pbit_profile_read(pbit_ctx *ctx, int32_t kind, double *total_ms, int64_t *launches, int32_t reset)
+{
+    PBIT_ENTER(ctx);
+    if (kind != PBIT_EA3D && kind != PBIT_BICLIQUE) return fail(PBIT_E_ARG, "pbit_profile_read: unknown kind %d", kind);
+    const int k = kind == PBIT_EA3D ? 1 : 2;
+    if (total_ms) *total_ms = ctx->prof_ms[k];
+    if (launches) *launches = ctx->prof_count[k];
+    if (reset) {
+        ctx->prof_ms[k] = 0;
+        ctx->prof_count[k] = 0;
+    }
+    return PBIT_OK;
 }

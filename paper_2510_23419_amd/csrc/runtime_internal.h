@@ -48,6 +48,13 @@ struct pbit_ctx {
     std::array<pbit::Scratch, (int)pbit::Slot::Count> scratch{};
     std::vector<uint32_t> host_table;
     pbit::ServeState *serve = nullptr;
+    // profiling: event pairs around sampled half-sweep launches
+    int prof_every = 0;
+    std::vector<hipEvent_t> prof_pool;
+    size_t prof_used = 0;
+    std::vector<int> prof_kind;  // kind of each pending pair
+    double prof_ms[3] = {0, 0, 0};
+    int64_t prof_count[3] = {0, 0, 0};
 };
 
 namespace pbit {
@@ -63,5 +70,9 @@ uint32_t minority_threshold(double beta, int a);
 int table_width(const double *beta, int S, int amax);
 void build_table(const double *beta, int S, int width, uint32_t *out);
 void serve_shutdown(pbit_ctx *ctx);
+hipError_t prof_begin(pbit_ctx *ctx, int kind, hipStream_t st, int *slot);
+hipError_t prof_end(pbit_ctx *ctx, int slot, hipStream_t st);
+hipError_t prof_harvest(pbit_ctx *ctx);
+void prof_release(pbit_ctx *ctx);
 
 }  // namespace pbit

@@ -31,7 +31,8 @@ PBIT_BICLIQUE = 2
 
 EXPORTS = ("pbit_create", "pbit_destroy", "pbit_last_error", "pbit_bytes_in_use", "pbit_load_problem",
            "pbit_unload_problem", "pbit_problem_spins", "pbit_anneal", "pbit_anneal_dev", "pbit_energy",
-           "pbit_submit", "pbit_poll", "pbit_progress", "pbit_threshold_table", "pbit_version")
+           "pbit_submit", "pbit_poll", "pbit_progress", "pbit_threshold_table", "pbit_version",
+           "pbit_profile_enable", "pbit_profile_read")
 
 
 class PbitError(RuntimeError):
@@ -90,6 +91,8 @@ def lib() -> ctypes.CDLL:
             "pbit_progress": ([P], ctypes.c_int),
             "pbit_threshold_table": ([P, i32, i32, P], ctypes.c_int),
             "pbit_version": ([], ctypes.c_char_p),
+            "pbit_profile_enable": ([P, i32], ctypes.c_int),
+            "pbit_profile_read": ([P, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), i32], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -256,6 +259,18 @@ def pbit_energy(ctx, problem: int, spins) -> np.ndarray:
     out = np.zeros(s.shape[0], np.int64)
     _check(lib().pbit_energy(ctx, int(problem), _ptr(s), s.shape[0], _ptr(out)))
     return out
+
+
+def pbit_profile_enable(ctx, every: int) -> None:
+    _check(lib().pbit_profile_enable(ctx, int(every)))
+
+
+def pbit_profile_read(ctx, kind: int, reset: bool = False):
+    """(device milliseconds, launches) of the bracketed half-sweep launches of a problem kind."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(lib().pbit_profile_read(ctx, int(kind), ctypes.byref(ms), ctypes.byref(n), 1 if reset else 0))
+    return float(ms.value), int(n.value)
 
 
 def pbit_threshold_table(beta, A: int) -> np.ndarray:
