@@ -24,8 +24,9 @@ __device__ __forceinline__ Block4 philox(uint32_t c0, uint32_t c1, uint32_t c2, 
     for (int round = 0; round < 10; ++round) {
         const uint64_t p = (uint64_t)c0 * 0xD2511F53u;
         const uint64_t q = (uint64_t)c2 * 0xCD9E8D57u;
-        const uint32_t n0 = (uint32_t)(q >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p >> 32) ^ c3 ^ k1;
+        // three-input XORs as single v_bitop3_b32 (truth table 0x96 = a ^ b ^ c)
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(q >> 32), c1, k0, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p >> 32), c3, k1, 0x96);
         c1 = (uint32_t)q;
         c3 = (uint32_t)p;
         c0 = n0;

@@ -82,64 +82,95 @@ __device__ __forceinline__ uint32_t neg2(uint32_t m, uint32_t keep, uint32_t fli
     return (m & keep) ^ flip;
 }
 
-// One checkerboard half-sweep: every site of `colour`, 16 replicas per thread.
+// Decision table of one half-sweep, indexed by I + kFieldOff: the minority
+// threshold Tm(beta_t, |I|), the mask that turns w into x (~0 for I >= 0),
+// and the spin bytes taken on a minority and on a majority outcome.
+constexpr int kFieldOff = 7;  // |I| <= 6 + |h| <= 7 on the cube
+constexpr int kFieldSlots = 2 * kFieldOff + 1;
+
+__device__ __forceinline__ void build_field_table(uint4 *tab, const uint32_t *__restrict__ trow, int width, int tid)
+{
+    if (tid < kFieldSlots) {
+        const int I = tid - kFieldOff;
+        const int a = min(I >= 0 ? I : -I, width - 1);
+        const bool pos = I >= 0;
+        tab[tid] = make_uint4(trow[a], pos ? 0xFFFFFFFFu : 0u, pos ? 0xFFu : 0x01u, pos ? 0x01u : 0xFFu);
+    }
+}
+
+// One checkerboard half-sweep.  Block (cbw, spb): x threads walk 16-replica
+// chunks, y threads walk the sites of one lattice row (y, z) = (blockIdx.y,
+// blockIdx.z).  blockIdx.x = chunk-block * nsl + slab: with nsl = 8 the slab
+// index equals the XCD a workgroup is dispatched to, so each XCD's L2 serves
+// one replica slab of the whole lattice and neighbour rows are reused there.
 __global__ __launch_bounds__(kThreads) void k_ea_halfsweep(int8_t *__restrict__ spins,
                                                            const uint32_t *__restrict__ code,
                                                            const uint32_t *__restrict__ trow, int width, int Lx,
-                                                           int Ly, int Lz, int Rp, int colour, uint32_t sweep,
-                                                           uint32_t rq0, uint32_t k0, uint32_t k1)
+                                                           int Ly, int Lz, int Rp, int colour, int nsl, int cs,
+                                                           uint32_t sweep, uint32_t rq0, uint32_t k0, uint32_t k1)
 {
-    __shared__ uint32_t T[16];
-    if (threadIdx.x < width && threadIdx.x < 16) T[threadIdx.x] = trow[threadIdx.x];
+    __shared__ uint4 tab[kFieldSlots];
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+    build_field_table(tab, trow, width, tid);
     __syncthreads();
 
-    const int chunks = Rp / 16;
-    const int64_t half = (int64_t)Lx * Ly * Lz / 2;
-    const int64_t gid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (gid >= half * chunks) return;
-    const int q = (int)(gid % chunks);
-    const int64_t j = gid / chunks;
+    const int slab = blockIdx.x % nsl;
+    const int qs = (blockIdx.x / nsl) * blockDim.x + threadIdx.x;
+    const int q = slab * cs + qs;
+    if (qs >= cs || 16 * q >= Rp) return;
+    const int y = blockIdx.y, z = blockIdx.z;
+    const uint32_t rowR = (uint32_t)Lx * (uint32_t)Rp;                 // bytes per lattice row
+    const uint32_t planeR = rowR * (uint32_t)Ly;                        // bytes per plane
+    const uint32_t base = (uint32_t)y * rowR + (uint32_t)z * planeR + 16u * (uint32_t)q;
+    const uint32_t yp = (y + 1 == Ly ? 0u : (uint32_t)(y + 1)) * rowR + (uint32_t)z * planeR + 16u * (uint32_t)q;
+    const uint32_t ym = (y == 0 ? (uint32_t)(Ly - 1) : (uint32_t)(y - 1)) * rowR + (uint32_t)z * planeR + 16u * (uint32_t)q;
+    const uint32_t zp = (uint32_t)y * rowR + (z + 1 == Lz ? 0u : (uint32_t)(z + 1)) * planeR + 16u * (uint32_t)q;
+    const uint32_t zm = (uint32_t)y * rowR + (z == 0 ? (uint32_t)(Lz - 1) : (uint32_t)(z - 1)) * planeR + 16u * (uint32_t)q;
+    const uint32_t siteRow = (uint32_t)Lx * ((uint32_t)y + (uint32_t)Ly * (uint32_t)z);
     const int hx = Lx / 2;
-    const int kx = (int)(j % hx);
-    const int64_t row = j / hx;
-    const int y = (int)(row % Ly);
-    const int z = (int)(row / Ly);
-    const int x = 2 * kx + ((colour + y + z) & 1);
-    const int64_t plane = (int64_t)Lx * Ly;
-    const int64_t i = x + (int64_t)Lx * y + plane * z;
-    const int64_t nb[6] = {
-        wrap_inc(x, Lx) + (int64_t)Lx * y + plane * z, wrap_dec(x, Lx) + (int64_t)Lx * y + plane * z,
-        x + (int64_t)Lx * wrap_inc(y, Ly) + plane * z, x + (int64_t)Lx * wrap_dec(y, Ly) + plane * z,
-        x + (int64_t)Lx * y + plane * wrap_inc(z, Lz), x + (int64_t)Lx * y + plane * wrap_dec(z, Lz)};
+    const int par = (colour + y + z) & 1;
+    const uint32_t rg4 = rq0 + 4u * (uint32_t)q;  // Philox counter word 2 of this chunk's first group
 
-    const uint32_t c = code[i];
-    const int base = (int)(int8_t)(c >> kCodeBaseShift);
-    uint32_t cnt[4] = {0u, 0u, 0u, 0u};
+    for (int kx = threadIdx.y; kx < hx; kx += blockDim.y) {
+        const int x = 2 * kx + par;
+        const uint32_t xR = (uint32_t)x * (uint32_t)Rp;
+        const uint32_t xpR = (x + 1 == Lx ? 0u : (uint32_t)(x + 1)) * (uint32_t)Rp;
+        const uint32_t xmR = (x == 0 ? (uint32_t)(Lx - 1) : (uint32_t)(x - 1)) * (uint32_t)Rp;
+        const uint32_t offs[6] = {base + xpR, base + xmR, yp + xR, ym + xR, zp + xR, zm + xR};
+        const uint32_t i = siteRow + (uint32_t)x;
+        const uint32_t c = code[i];
+        uint32_t cnt[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-    for (int d = 0; d < 6; ++d) {
-        const uint4 v = *reinterpret_cast<const uint4 *>(spins + (size_t)nb[d] * Rp + 16 * q);
-        const uint32_t keep = ((c >> d) & 1u) * 0x02020202u;
-        const uint32_t flip = ((c >> (kCodeFlipShift + d)) & 1u) * 0x02020202u;
-        cnt[0] += neg2(v.x, keep, flip);
-        cnt[1] += neg2(v.y, keep, flip);
-        cnt[2] += neg2(v.z, keep, flip);
-        cnt[3] += neg2(v.w, keep, flip);
-    }
-    const int top = width - 1;
-    uint32_t out[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const Block4 b = philox((uint32_t)i, sweep, rq0 + 4u * (uint32_t)q + (uint32_t)k, kDomainSweep, k0, k1);
-        uint32_t packed = 0;
-#pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            const int I = base - (int)((cnt[k] >> (8 * p)) & 0xFFu);
-            const int a = min(I >= 0 ? I : -I, top);
-            packed |= (uint32_t)(uint8_t)decide(I, T[a], b.w[p]) << (8 * p);
+        for (int d = 0; d < 6; ++d) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(spins + offs[d]);
+            const uint32_t keep = ((c >> d) & 1u) * 0x02020202u;
+            const uint32_t flip = ((c >> (kCodeFlipShift + d)) & 1u) * 0x02020202u;
+            cnt[0] += neg2(v.x, keep, flip);
+            cnt[1] += neg2(v.y, keep, flip);
+            cnt[2] += neg2(v.z, keep, flip);
+            cnt[3] += neg2(v.w, keep, flip);
         }
-        out[k] = packed;
+        // LDS byte address of the entry for I = base_i (no negative products)
+        const int entry0 = ((int)(int8_t)(c >> kCodeBaseShift) + kFieldOff) * (int)sizeof(uint4);
+        const char *tbase = reinterpret_cast<const char *>(tab);
+        uint32_t out[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const Block4 b = philox(i, sweep, rg4 + (uint32_t)k, kDomainSweep, k0, k1);
+            // bytes of cnt are c2 <= 12, so cnt * 16 keeps each 16 c2 <= 192 in its own byte
+            const uint32_t off16 = cnt[k] << 4;
+            uint32_t packed = 0;
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const int o = (int)((off16 >> (8 * p)) & 0xFFu);  // 16 c2, with I = base_i - c2
+                const uint4 e = *reinterpret_cast<const uint4 *>(tbase + entry0 - o);
+                const uint32_t xw = b.w[p] ^ e.y;
+                packed |= (xw < e.x ? e.z : e.w) << (8 * p);
+            }
+            out[k] = packed;
+        }
+        *reinterpret_cast<uint4 *>(spins + base + xR) = make_uint4(out[0], out[1], out[2], out[3]);
     }
-    *reinterpret_cast<uint4 *>(spins + (size_t)i * Rp + 16 * q) = make_uint4(out[0], out[1], out[2], out[3]);
 }
 
 // From-scratch energy: E[r] += -sum over a chunk of sites of (bond + field)
@@ -198,10 +229,19 @@ hipError_t ea_to_rows(const EaView &p, const int8_t *spins, int Rp, int8_t *dst_
 hipError_t ea_halfsweep(const EaView &p, int8_t *spins, int Rp, int colour, const uint32_t *trow, int width,
                         uint32_t sweep, uint32_t rq0, Key key, hipStream_t st)
 {
-    if (width < 1 || width > 16 || Rp % 16 != 0) return hipErrorInvalidValue;
-    const int64_t work = p.N / 2 * (Rp / 16);
-    hipLaunchKernelGGL(k_ea_halfsweep, dim3(blocks_for(work)), dim3(kThreads), 0, st, spins, p.code, trow, width, p.Lx,
-                       p.Ly, p.Lz, Rp, colour, sweep, rq0, key.k0, key.k1);
+    if (width < 1 || width > kFieldOff + 1 || Rp % 16 != 0) return hipErrorInvalidValue;
+    if ((uint64_t)p.N * (uint64_t)Rp >= ((uint64_t)1 << 32)) return hipErrorInvalidValue;  // 32-bit byte offsets
+    if (p.Ly > 65535 || p.Lz > 65535) return hipErrorInvalidValue;                      // grid y / z limits
+    const int C = Rp / 16;              // 16-replica chunks
+    const int nsl = C >= 8 ? 8 : 1;     // replica slabs, one per XCD when there are enough chunks
+    const int cs = (C + nsl - 1) / nsl; // chunks per slab
+    int cbw = 1;
+    while (cbw < cs && cbw < 64) cbw *= 2;
+    const int spb = kThreads / cbw;
+    const int ncb = (cs + cbw - 1) / cbw;
+    dim3 grid((unsigned)(nsl * ncb), (unsigned)p.Ly, (unsigned)p.Lz), block((unsigned)cbw, (unsigned)spb);
+    hipLaunchKernelGGL(k_ea_halfsweep, grid, block, 0, st, spins, p.code, trow, width, p.Lx, p.Ly, p.Lz, Rp, colour,
+                       nsl, cs, sweep, rq0, key.k0, key.k1);
     return hipGetLastError();
 }
 
