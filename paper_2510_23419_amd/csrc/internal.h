@@ -30,10 +30,12 @@ struct BqView {
     const int8_t *hB;  // [nb_p]
 };
 
-constexpr int kBqPad = 64;    // site padding of biclique sides (MFMA K and N tiles)
-constexpr int kBqRPad = 64;   // replica padding of biclique spin matrices (MFMA M tile)
+constexpr int kBqPad = 64;       // site padding of small biclique sides (MFMA K and N tiles)
+constexpr int kBqPadLarge = 128; // site padding of sides with at least kBqLargeSide sites
+constexpr int kBqLargeSide = 512;
+constexpr int kBqRPad = 128;     // replica padding of biclique spin matrices (MFMA M tile)
 constexpr int kEaRPad = 16;   // replica padding of the cube spin matrix (one dwordx4 per thread)
-constexpr int kMaxTableWidth = 8192;  // threshold-row entries a biclique kernel stages in LDS (32 KiB)
+constexpr int kMaxTableWidth = 4096;  // threshold-row entries a biclique kernel stages in LDS (16 KiB)
 
 struct Key {
     uint32_t k0, k1;

@@ -303,7 +303,8 @@ static int load_biclique(pbit_ctx *ctx, const pbit_problem_desc *d, Problem &p)
     if (!d->J) return fail(PBIT_E_ARG, "biclique couplings are NULL");
     if (!in_unit_range(d->J, (size_t)na * nb)) return fail(PBIT_E_RANGE, "biclique couplings must be in {-1, 0, +1}");
     if (d->h && !in_unit_range(d->h, (size_t)na + nb)) return fail(PBIT_E_RANGE, "fields must be in {-1, 0, +1}");
-    const int na_p = round_up(na, kBqPad), nb_p = round_up(nb, kBqPad);
+    const int pad = std::min(na, nb) >= kBqLargeSide ? kBqPadLarge : kBqPad;
+    const int na_p = round_up(na, pad), nb_p = round_up(nb, pad);
     std::vector<int8_t> J((size_t)na_p * nb_p, 0), JT((size_t)nb_p * na_p, 0), hA(na_p, 0), hB(nb_p, 0);
     std::vector<int> rowsum(na, 0), colsum(nb, 0);
     for (int a = 0; a < na; ++a)

@@ -104,6 +104,15 @@ def test_biclique_every_replica_every_sweep(ctx, na, nb, R):
     _every_sweep(ctx, inst, synth.beta_linear(0.05, 2.0, 30), R, seed=5)
 
 
+@pytest.mark.parametrize("na,nb,R", [(600, 520, 200), (512, 1024, 130)])
+def test_biclique_large_tiles_ragged(ctx, na, nb, R):
+    """Sides of 512 or more sites take the 128 x 128 LDS-tiled kernel; ragged
+    sites and replicas exercise its padding."""
+    inst = synth.biclique_instance(na, seed=na + 3 * nb, nb=nb)
+    _say("biclique large tiles %dx%d R=%d" % (na, nb, R))
+    _every_sweep(ctx, inst, synth.beta_linear(0.05, 2.0, 8), R, seed=12)
+
+
 def test_given_initial_spins(ctx):
     inst = synth.ea_instance(4, seed=2, field="uniform3")
     init = synth.random_spins(9, 64, seed=9)
