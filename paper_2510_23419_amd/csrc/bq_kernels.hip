@@ -138,58 +138,93 @@ __global__ __launch_bounds__(kThreads) void k_bq_halfsweep(const int8_t *__restr
 
 // Large-tile half-sweep for sides padded to 128: each workgroup owns a
 // 128-replica x 128-site tile of the field matrix and runs the whole K loop
-// through LDS (64-byte K stages, double-buffered, one barrier per stage).
+// through LDS (KT-byte K stages, double-buffered, one barrier per stage).
 // Four waves each hold a 64 x 64 sub-tile as 2 x 2 MFMA accumulators, so each
-// operand fragment read from LDS feeds two MFMAs.  Global loads run kDepth
+// operand fragment read from LDS feeds two MFMAs.  Global loads run DEPTH
 // stages ahead through a ring of registers, and the 16 Philox blocks each lane
-// needs for its epilogue are computed during the first K stages, where they
+// needs for its epilogue are drawn during the first K stages, where they
 // overlap the matrix cores instead of following them.  Workgroups are placed so
 // that each XCD works on one band of sites: its L2 then holds that band's rows
 // of J once while the spins of the other side stream through it.
-constexpr int kT = 128;                 // tile edge (replicas and sites)
-constexpr int kKT = 64;                 // K bytes per LDS stage
-constexpr int kPitch = kKT + 16;        // padded LDS row pitch
-constexpr int kStage = kT * kPitch;     // bytes per operand per stage
-constexpr int kT128Lds = 4 * kStage;    // A and B, two stages each
-constexpr int kDepth = 4;               // K stages in flight in registers
-constexpr int kPhiloxStages = 8;        // stages that also compute Philox (2 blocks each)
+constexpr int kT = 128;  // tile edge (replicas and sites)
 
-struct Stage {
-    uint4 a0, a1, b0, b1;
+template <int KT>
+struct TileGeom {
+    static constexpr int pitch = KT + 16;          // padded LDS row pitch
+    static constexpr int stage = kT * pitch;       // bytes per operand per stage
+    static constexpr int lds = 4 * stage;          // A and B, two stages each
+    static constexpr int chunks = KT / 16;         // 16-byte chunks per row
+    static constexpr int rows_per_pass = kThreads / chunks;
+    static constexpr int passes = kT / rows_per_pass;
 };
 
-__device__ __forceinline__ Stage load_stage(const int8_t *ga, const int8_t *gb, size_t half, int kt)
+// A stage's staging registers as one native vector (4 ints per 16-byte chunk:
+// A chunks first, then B chunks), so that the ring stays in VGPRs.
+typedef int v32i __attribute__((ext_vector_type(32)));
+template <int KT>
+struct StageVec;
+template <>
+struct StageVec<64> {
+    typedef v16i type;
+};
+template <>
+struct StageVec<128> {
+    typedef v32i type;
+};
+
+template <int KT>
+struct Stage {
+    typename StageVec<KT>::type v;
+};
+
+template <int KT>
+__device__ __forceinline__ Stage<KT> load_stage(const int8_t *ga, const int8_t *gb, size_t pass_stride, int kt)
 {
-    const size_t k = (size_t)kt * kKT;
-    Stage r;
-    r.a0 = *reinterpret_cast<const uint4 *>(ga + k);
-    r.a1 = *reinterpret_cast<const uint4 *>(ga + half + k);
-    r.b0 = *reinterpret_cast<const uint4 *>(gb + k);
-    r.b1 = *reinterpret_cast<const uint4 *>(gb + half + k);
+    constexpr int P = TileGeom<KT>::passes;
+    const size_t k = (size_t)kt * KT;
+    Stage<KT> r;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const v4i a = *reinterpret_cast<const v4i *>(ga + p * pass_stride + k);
+        const v4i b = *reinterpret_cast<const v4i *>(gb + p * pass_stride + k);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            r.v[4 * p + e] = a[e];
+            r.v[4 * (P + p) + e] = b[e];
+        }
+    }
     return r;
 }
 
-__device__ __forceinline__ void store_stage(const Stage &r, int8_t *As, int8_t *Bs, int buf, int st0, int st1)
+template <int KT>
+__device__ __forceinline__ void store_stage(const Stage<KT> &r, int8_t *As, int8_t *Bs, int buf, int st)
 {
-    *reinterpret_cast<uint4 *>(As + buf + st0) = r.a0;
-    *reinterpret_cast<uint4 *>(As + buf + st1) = r.a1;
-    *reinterpret_cast<uint4 *>(Bs + buf + st0) = r.b0;
-    *reinterpret_cast<uint4 *>(Bs + buf + st1) = r.b1;
+    using G = TileGeom<KT>;
+    constexpr int P = G::passes;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const v4i a = {r.v[4 * p], r.v[4 * p + 1], r.v[4 * p + 2], r.v[4 * p + 3]};
+        const v4i b = {r.v[4 * (P + p)], r.v[4 * (P + p) + 1], r.v[4 * (P + p) + 2], r.v[4 * (P + p) + 3]};
+        *reinterpret_cast<v4i *>(As + buf + st + p * G::rows_per_pass * G::pitch) = a;
+        *reinterpret_cast<v4i *>(Bs + buf + st + p * G::rows_per_pass * G::pitch) = b;
+    }
 }
 
 struct Acc4 {
     v16i c00, c01, c10, c11;
 };
 
+template <int KT>
 __device__ __forceinline__ void mma_stage(Acc4 &c, const int8_t *As, const int8_t *Bs, int buf, int ra_off, int rb_off)
 {
+    constexpr int pitch = TileGeom<KT>::pitch;
 #pragma unroll
-    for (int sub = 0; sub < 2; ++sub) {
+    for (int sub = 0; sub < KT / 32; ++sub) {
         const int ko = buf + 32 * sub;
         const v4i a0 = *reinterpret_cast<const v4i *>(As + ko + ra_off);
-        const v4i a1 = *reinterpret_cast<const v4i *>(As + ko + ra_off + 32 * kPitch);
+        const v4i a1 = *reinterpret_cast<const v4i *>(As + ko + ra_off + 32 * pitch);
         const v4i b0 = *reinterpret_cast<const v4i *>(Bs + ko + rb_off);
-        const v4i b1 = *reinterpret_cast<const v4i *>(Bs + ko + rb_off + 32 * kPitch);
+        const v4i b1 = *reinterpret_cast<const v4i *>(Bs + ko + rb_off + 32 * pitch);
         c.c00 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, b0, c.c00, 0, 0, 0);
         c.c01 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, b1, c.c01, 0, 0, 0);
         c.c10 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, b0, c.c10, 0, 0, 0);
@@ -197,15 +232,21 @@ __device__ __forceinline__ void mma_stage(Acc4 &c, const int8_t *As, const int8_
     }
 }
 
-__global__ __launch_bounds__(kThreads, 1) void k_bq_halfsweep_t128(
+template <int KT, int DEPTH>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_bq_halfsweep_t128(
     const int8_t *__restrict__ Mo, const int8_t *__restrict__ Jx, const int8_t *__restrict__ hs,
     int8_t *__restrict__ Ms, const uint32_t *__restrict__ trow, int width, int Ns, int Ns_p, int Ko, int R,
     int tiles_s, int xcd_bands, uint32_t site_base, uint32_t sweep, uint32_t rq0, uint32_t k0, uint32_t k1)
 {
+    using G = TileGeom<KT>;
+    constexpr int kPhxPerStage = KT / 32;            // Philox blocks drawn per K stage
+    constexpr int kPhxStages = 16 / kPhxPerStage;    // stages that carry the 16 draws
+    static_assert(kPhxStages % DEPTH == 0, "ring index must restart at 0 after the Philox stages");
+
     extern __shared__ uint4 smem[];
     int8_t *As = reinterpret_cast<int8_t *>(smem);
-    int8_t *Bs = As + 2 * kStage;
-    uint32_t *T = reinterpret_cast<uint32_t *>(As + kT128Lds);
+    int8_t *Bs = As + 2 * G::stage;
+    uint32_t *T = reinterpret_cast<uint32_t *>(As + G::lds);
     for (int a = threadIdx.x; a < width; a += kThreads) T[a] = trow[a];
 
     int ts, tr;
@@ -220,93 +261,75 @@ __global__ __launch_bounds__(kThreads, 1) void k_bq_halfsweep_t128(
     }
     const int r0 = tr * kT, s0 = ts * kT;
 
-    // global -> LDS staging: thread t moves 16 bytes of rows t/4 and t/4 + 64
-    const int lrow = threadIdx.x >> 2, lcol = 16 * (threadIdx.x & 3);
+    // global -> LDS staging: thread t moves 16 bytes of row t / chunks (+ k * rows_per_pass)
+    const int lrow = threadIdx.x / G::chunks, lcol = 16 * (threadIdx.x % G::chunks);
     const int8_t *ga = Mo + (size_t)(r0 + lrow) * Ko + lcol;
     const int8_t *gb = Jx + (size_t)(s0 + lrow) * Ko + lcol;
-    const size_t half = (size_t)64 * Ko;
-    const int st0 = lrow * kPitch + lcol, st1 = (lrow + 64) * kPitch + lcol;
-    const int nk = Ko / kKT;
-
-    static_assert(kDepth == 4, "the register ring below is written out for four stages");
-    // ring: stage s lives in g[s % 4] until it is written to LDS.  Loads past the
-    // last stage re-read the last stage (clamped index) instead of branching, so
-    // the ring stays in registers.
+    const size_t pass_stride = (size_t)G::rows_per_pass * Ko;
+    const int st = lrow * G::pitch + lcol;
+    const int nk = Ko / KT;
     const int last = nk - 1;
-    Stage g0 = load_stage(ga, gb, half, 0);
-    Stage g1 = load_stage(ga, gb, half, min(1, last));
-    Stage g2 = load_stage(ga, gb, half, min(2, last));
-    Stage g3 = load_stage(ga, gb, half, min(3, last));
-    store_stage(g0, As, Bs, 0, st0, st1);
-    g0 = load_stage(ga, gb, half, min(kDepth, last));
+
+    // ring: stage s lives in g[s % DEPTH] until it is written to LDS.  Loads past
+    // the last stage re-read the last stage (clamped index) instead of branching,
+    // so the ring stays in registers.
+    Stage<KT> g[DEPTH];
+#pragma unroll
+    for (int u = 0; u < DEPTH; ++u) g[u] = load_stage<KT>(ga, gb, pass_stride, min(u, last));
+    store_stage<KT>(g[0], As, Bs, 0, st);
+    g[0] = load_stage<KT>(ga, gb, pass_stride, min(DEPTH, last));
     __syncthreads();
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wr = wave >> 1, wc = wave & 1;
     const int ln = lane & 31, kg = lane >> 5;
-    const int ra_off = (wr * 64 + ln) * kPitch + 16 * kg;
-    const int rb_off = (wc * 64 + ln) * kPitch + 16 * kg;
+    const int ra_off = (wr * 64 + ln) * G::pitch + 16 * kg;
+    const int rb_off = (wc * 64 + ln) * G::pitch + 16 * kg;
     Acc4 acc;
     acc.c00 = acc.c01 = acc.c10 = acc.c11 = v16i{0};
 
-// one K stage: MFMAs on stage KT, hand stage KT + 1 (held in NEXT) to LDS, refill NEXT
-#define PBIT_BQ_STEP(KT, NEXT)                                                            \
-    do {                                                                                   \
-        const int kt_ = (KT);                                                              \
-        mma_stage(acc, As, Bs, (kt_ & 1) * kStage, ra_off, rb_off);                        \
-        if (kt_ + 1 < nk) store_stage(NEXT, As, Bs, ((kt_ + 1) & 1) * kStage, st0, st1);   \
-        NEXT = load_stage(ga, gb, half, min(kt_ + 1 + kDepth, last));                      \
-        __syncthreads();                                                                   \
+// one K stage: MFMAs on stage KT_, hand stage KT_ + 1 (held in NEXT) to LDS, refill NEXT
+#define PBIT_BQ_STEP(KT_, NEXT)                                                               \
+    do {                                                                                       \
+        const int kt_ = (KT_);                                                                 \
+        mma_stage<KT>(acc, As, Bs, (kt_ & 1) * G::stage, ra_off, rb_off);                      \
+        if (kt_ + 1 < nk) store_stage<KT>(NEXT, As, Bs, ((kt_ + 1) & 1) * G::stage, st);       \
+        NEXT = load_stage<KT>(ga, gb, pass_stride, min(kt_ + 1 + DEPTH, last));                \
+        __syncthreads();                                                                       \
     } while (0)
 
     // Philox words of this lane's 16 (site, replica group) pairs: block index
     // (bj * 2 + bi) * 4 + q covers site column bj and replica rows bi, q.
-    // Two blocks are drawn after each of the first kPhiloxStages K stages.
     uint32_t words[16][4];
-#define PBIT_BQ_PHILOX(U)                                                                            \
-    do {                                                                                              \
-        _Pragma("unroll") for (int v = 0; v < 2; ++v) {                                               \
-            const int blk = 2 * (U) + v;                                                              \
-            const int bj = blk >> 3, bi = (blk >> 2) & 1, q = blk & 3;                                \
-            const int site = s0 + wc * 64 + bj * 32 + ln;                                             \
-            const int r4 = r0 + wr * 64 + bi * 32 + 8 * q + 4 * kg;                                   \
-            const Block4 b =                                                                          \
-                philox(site_base + (uint32_t)site, sweep, rq0 + (uint32_t)(r4 >> 2), kDomainSweep, k0, k1); \
-            uint32_t w0 = b.w[0], w1 = b.w[1], w2 = b.w[2], w3 = b.w[3];                              \
-            /* pin the draws here, between the MFMAs, instead of letting them sink to the epilogue */ \
-            asm volatile("" : "+v"(w0), "+v"(w1), "+v"(w2), "+v"(w3));                                \
-            words[blk][0] = w0; words[blk][1] = w1; words[blk][2] = w2; words[blk][3] = w3;           \
-        }                                                                                             \
-    } while (0)
-
-    static_assert(kPhiloxStages == 2 * kDepth, "two ring turns carry the Philox draws");
-    PBIT_BQ_STEP(0, g1); PBIT_BQ_PHILOX(0);
-    if (1 < nk) PBIT_BQ_STEP(1, g2);
-    PBIT_BQ_PHILOX(1);
-    if (2 < nk) PBIT_BQ_STEP(2, g3);
-    PBIT_BQ_PHILOX(2);
-    if (3 < nk) PBIT_BQ_STEP(3, g0);
-    PBIT_BQ_PHILOX(3);
-    if (4 < nk) PBIT_BQ_STEP(4, g1);
-    PBIT_BQ_PHILOX(4);
-    if (5 < nk) PBIT_BQ_STEP(5, g2);
-    PBIT_BQ_PHILOX(5);
-    if (6 < nk) PBIT_BQ_STEP(6, g3);
-    PBIT_BQ_PHILOX(6);
-    if (7 < nk) PBIT_BQ_STEP(7, g0);
-    PBIT_BQ_PHILOX(7);
-    int kt = kPhiloxStages;
-    for (; kt + kDepth <= nk; kt += kDepth) {
-        PBIT_BQ_STEP(kt, g1);
-        PBIT_BQ_STEP(kt + 1, g2);
-        PBIT_BQ_STEP(kt + 2, g3);
-        PBIT_BQ_STEP(kt + 3, g0);
+#pragma unroll
+    for (int u = 0; u < kPhxStages; ++u) {
+        if (u < nk) PBIT_BQ_STEP(u, g[(u + 1) % DEPTH]);
+#pragma unroll
+        for (int v = 0; v < kPhxPerStage; ++v) {
+            const int blk = kPhxPerStage * u + v;
+            const int bj = blk >> 3, bi = (blk >> 2) & 1, q = blk & 3;
+            const int site = s0 + wc * 64 + bj * 32 + ln;
+            const int r4 = r0 + wr * 64 + bi * 32 + 8 * q + 4 * kg;
+            const Block4 b =
+                philox(site_base + (uint32_t)site, sweep, rq0 + (uint32_t)(r4 >> 2), kDomainSweep, k0, k1);
+            uint32_t w0 = b.w[0], w1 = b.w[1], w2 = b.w[2], w3 = b.w[3];
+            // pin the draws here, between the MFMAs, instead of letting them sink to the epilogue
+            asm volatile("" : "+v"(w0), "+v"(w1), "+v"(w2), "+v"(w3));
+            words[blk][0] = w0;
+            words[blk][1] = w1;
+            words[blk][2] = w2;
+            words[blk][3] = w3;
+        }
     }
-    if (kt < nk) PBIT_BQ_STEP(kt, g1);
-    if (kt + 1 < nk) PBIT_BQ_STEP(kt + 1, g2);
-    if (kt + 2 < nk) PBIT_BQ_STEP(kt + 2, g3);
+    int kt = kPhxStages;
+    for (; kt + DEPTH <= nk; kt += DEPTH) {
+#pragma unroll
+        for (int u = 0; u < DEPTH; ++u) PBIT_BQ_STEP(kt + u, g[(u + 1) % DEPTH]);
+    }
+#pragma unroll
+    for (int u = 0; u + 1 < DEPTH; ++u)
+        if (kt + u < nk) PBIT_BQ_STEP(kt + u, g[(u + 1) % DEPTH]);
 #undef PBIT_BQ_STEP
-#undef PBIT_BQ_PHILOX
 
     // epilogue: decision for each accumulator element.  Every decision is taken
     // unconditionally (padding sites have h = 0 and padding replicas are never
@@ -388,7 +411,7 @@ hipError_t bq_to_rows(const BqView &p, const int8_t *MA, const int8_t *MB, int8_
 }
 
 hipError_t bq_halfsweep(const BqView &p, int side, int8_t *MA, int8_t *MB, int R, int Rp, const uint32_t *trow,
-                        int width, uint32_t sweep, uint32_t rq0, Key key, hipStream_t st)
+                        int width, uint32_t sweep, uint32_t rq0, Key key, hipStream_t st, BqVariant variant)
 {
     if (Rp % kTileR != 0 || p.na_p % kTileS != 0 || p.nb_p % kTileS != 0 || width < 1 || width > kMaxTableWidth)
         return hipErrorInvalidValue;
@@ -400,12 +423,39 @@ hipError_t bq_halfsweep(const BqView &p, int side, int8_t *MA, int8_t *MB, int R
     int8_t *Ms = A ? MA : MB;
     const int Ns = A ? p.na : p.nb;
     const uint32_t site_base = A ? 0u : (uint32_t)p.na;
-    if (Ns_p % kT == 0 && Ko % kKT == 0 && Rp % kT == 0) {
+    static const hipError_t lds_attr = [] {
+        // the 128-byte-stage variants stage more than the default 64 KiB of LDS
+        const int max_lds = TileGeom<128>::lds + (int)sizeof(uint32_t) * kMaxTableWidth;
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bq_halfsweep_t128<128, 2>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bq_halfsweep_t128<128, 4>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+        return e;
+    }();
+    if (lds_attr != hipSuccess) return lds_attr;
+    if (variant != BqVariant::Small && Ns_p % kT == 0 && Ko % 128 == 0 && Rp % kT == 0) {
         const int tiles_s = Ns_p / kT, tiles_r = Rp / kT;
-        const size_t lds = kT128Lds + sizeof(uint32_t) * (size_t)width;
-        hipLaunchKernelGGL(k_bq_halfsweep_t128, dim3((unsigned)(tiles_s * tiles_r)), dim3(kThreads), lds, st, Mo, Jx,
-                           hs, Ms, trow, width, Ns, Ns_p, Ko, R, tiles_s, tiles_s % 8 == 0 ? 1 : 0, site_base, sweep,
-                           rq0, key.k0, key.k1);
+        const dim3 grid((unsigned)(tiles_s * tiles_r));
+        const int bands = tiles_s % 8 == 0 ? 1 : 0;
+        const size_t tab = sizeof(uint32_t) * (size_t)width;
+        switch (variant) {
+        case BqVariant::K64D4:
+            hipLaunchKernelGGL((k_bq_halfsweep_t128<64, 4>), grid, dim3(kThreads), TileGeom<64>::lds + tab, st, Mo,
+                               Jx, hs, Ms, trow, width, Ns, Ns_p, Ko, R, tiles_s, bands, site_base, sweep, rq0,
+                               key.k0, key.k1);
+            break;
+        case BqVariant::K128D2:
+            hipLaunchKernelGGL((k_bq_halfsweep_t128<128, 2>), grid, dim3(kThreads), TileGeom<128>::lds + tab, st,
+                               Mo, Jx, hs, Ms, trow, width, Ns, Ns_p, Ko, R, tiles_s, bands, site_base, sweep, rq0,
+                               key.k0, key.k1);
+            break;
+        default:
+            hipLaunchKernelGGL((k_bq_halfsweep_t128<128, 4>), grid, dim3(kThreads), TileGeom<128>::lds + tab, st,
+                               Mo, Jx, hs, Ms, trow, width, Ns, Ns_p, Ko, R, tiles_s, bands, site_base, sweep, rq0,
+                               key.k0, key.k1);
+            break;
+        }
         return hipGetLastError();
     }
     dim3 grid((unsigned)(Ns_p / kTileS), (unsigned)(Rp / kTileR));

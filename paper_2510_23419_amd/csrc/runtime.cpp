@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -185,6 +186,10 @@ extern "C" int pbit_create(pbit_ctx **out, int device, uint64_t hbm_budget_bytes
     if (!ctx) return fail(PBIT_E_NOMEM, "pbit_create: host allocation failed");
     ctx->device = device;
     ctx->budget = hbm_budget_bytes;
+    if (const char *v = std::getenv("PBIT_BQ_VARIANT")) {  // tuning override: 1..4 (see BqVariant)
+        const int k = std::atoi(v);
+        if (k >= 1 && k <= 4) ctx->bq_forced = (BqVariant)k;
+    }
     ctx->serial = g_ctx_serial.fetch_add(1);
     e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
@@ -441,7 +446,61 @@ struct DevState {
     int width = 1;
     int32_t *E32 = nullptr;
     int8_t *stage = nullptr;  // [R][N] host-layout staging
+    BqVariant variant = BqVariant::Auto;
 };
+
+// Pick the biclique kernel variant for this shape: the forced one, a cached
+// choice, or the fastest of the candidates timed here on the (not yet
+// initialised) spin buffers, whose contents do not affect the timing.
+static int tune_biclique(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStream_t st)
+{
+    if (ctx->bq_forced != BqVariant::Auto) {
+        ds.variant = ctx->bq_forced;
+        return PBIT_OK;
+    }
+    const std::array<int, 3> shape{P.bq.na_p, P.bq.nb_p, ds.Rp};
+    auto it = ctx->bq_tuned.find(shape);
+    if (it != ctx->bq_tuned.end()) {
+        ds.variant = it->second;
+        return PBIT_OK;
+    }
+    const bool large = P.bq.na_p % 128 == 0 && P.bq.nb_p % 128 == 0;
+    if (!large) {
+        ds.variant = BqVariant::Small;
+        ctx->bq_tuned[shape] = ds.variant;
+        return PBIT_OK;
+    }
+    const BqVariant cand[] = {BqVariant::K64D4, BqVariant::K128D2, BqVariant::K128D4, BqVariant::Small};
+    hipEvent_t e0, e1;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) return device_fail(ctx, e, "hipEventCreate (tuning)");
+    const Key key{0u, 0u};
+    float best_ms = 0.f;
+    BqVariant best = BqVariant::K128D4;
+    for (BqVariant v : cand) {
+        float ms = 0.f;
+        for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // first pass warms up
+            e = hipEventRecord(e0, st);
+            for (int k = 0; k < 4 && e == hipSuccess; ++k)
+                e = bq_halfsweep(P.bq, k & 1, ds.MA, ds.MB, ds.R, ds.Rp, ds.table, ds.width, 0u, 0u, key, st, v);
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        }
+        if (e != hipSuccess) break;
+        if (v == cand[0] || ms < best_ms) {
+            best_ms = ms;
+            best = v;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return device_fail(ctx, e, "biclique kernel tuning");
+    ds.variant = best;
+    ctx->bq_tuned[shape] = best;
+    return PBIT_OK;
+}
 
 static int prepare(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, hipStream_t st, DevState &ds,
                    const void *dev_init)
@@ -484,6 +543,11 @@ static int prepare(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, h
                                   hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return device_fail(ctx, e, "hipMemcpyAsync (table)");
 
+    if (P.kind == PBIT_BICLIQUE && d->n_sweeps > 0) {
+        rc = tune_biclique(ctx, P, ds, st);
+        if (rc) return rc;
+    }
+
     const Key key{(uint32_t)d->seed, (uint32_t)(d->seed >> 32)};
     const uint32_t rq0 = (uint32_t)d->replica_offset >> 2;
     const int8_t *init_rows = (const int8_t *)dev_init;
@@ -519,7 +583,7 @@ static hipError_t sweep(pbit_ctx *ctx, const Problem &P, DevState &ds, int s, ui
         if (P.kind == PBIT_EA3D)
             e = ea_halfsweep(P.ea, ds.spins, ds.Rp, c, row, ds.width, t, rq0, key, st);
         else
-            e = bq_halfsweep(P.bq, c, ds.MA, ds.MB, ds.R, ds.Rp, row, ds.width, t, rq0, key, st);
+            e = bq_halfsweep(P.bq, c, ds.MA, ds.MB, ds.R, ds.Rp, row, ds.width, t, rq0, key, st, ds.variant);
         if (e == hipSuccess) e = prof_end(ctx, slot, st);
     }
     return e;

@@ -55,6 +55,9 @@ struct pbit_ctx {
     std::vector<int> prof_kind;  // kind of each pending pair
     double prof_ms[3] = {0, 0, 0};
     int64_t prof_count[3] = {0, 0, 0};
+    // biclique kernel variant: forced (PBIT_BQ_VARIANT) or autotuned per shape
+    pbit::BqVariant bq_forced = pbit::BqVariant::Auto;
+    std::map<std::array<int, 3>, pbit::BqVariant> bq_tuned;  // (na_p, nb_p, Rp) -> fastest
 };
 
 namespace pbit {
