@@ -83,6 +83,26 @@ def cpu_baseline(w, inst, beta, budget_s):
                       % (S, len(beta), R - 1, w["R"], platform.processor() or platform.machine(), dt)}
 
 
+def measured_traffic(workload):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter
+    reads for a plain copy), or None if the kernel sources changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(workload)
+    if not rec:
+        return None
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec["sha256"]:
+        return None
+    return float(rec["traffic_bytes_per_launch"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -170,6 +190,8 @@ def main():
                 "unit": "TOP/s", "traffic": None, "kernel": "k_bq_halfsweep",
                 "alg_ops_per_launch": alg_ops, "avg_launch_us": avg_ms * 1e3, "launches_timed": launches}
     roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = measured_traffic(args.workload)
+    roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
 
     cpu = None
     if args.cpu_seconds > 0:
