@@ -162,21 +162,53 @@ int pbit_anneal_dev(pbit_ctx *ctx, uint64_t problem, const pbit_anneal_desc *des
 /* Energies of R host configurations [R][N] into out[R] (computed on the GPU). */
 int pbit_energy(pbit_ctx *ctx, uint64_t problem, const int8_t *spins, int32_t R, int64_t *out);
 
-/* ---- serving (BASELINE configs: continuous batching of anneal jobs) ----- */
+/* ---- batched anneals (Sec. 1.3.3: many independent runs) ------------------ */
 
-/* Queue an anneal job.  The descriptor, beta and init spins are copied.  The
- * job is admitted to the GPU when its device memory fits the context's budget;
- * jobs that arrive while others run are batched with them.  Writes a job id.
+/* Many independent jobs share persistent kernels: each job is cut into replica
+ * tiles (4 replicas of a whole cube, or 32/64 replicas of both sides of a
+ * biclique) that never need each other, and every workgroup keeps taking
+ * (job, tile, sweep range) items from a device queue with its tile's spins held
+ * in LDS.  Results are identical to pbit_anneal for the same job, whatever it is
+ * batched with.  Batched jobs need a cube of at most 32,768 sites or a biclique
+ * with na_p + nb_p <= 4,096 padded sites (E_UNSUPPORTED otherwise).  When a job
+ * has a target or a trace, its energies are checked every trace_every sweeps,
+ * or every PBIT_CHECK_SWEEPS sweeps when trace_every is 0, and a target stops
+ * the job after the first checked sweep that meets it. */
+#define PBIT_CHECK_SWEEPS 100
+
+typedef struct {
+    uint64_t problem;
+    const pbit_anneal_desc *desc;
+    pbit_result *result;      /* filled as by pbit_anneal (spin_trace is not supported) */
+} pbit_batch_job;
+
+/* Run all jobs and wait for them. */
+int pbit_anneal_batch(pbit_ctx *ctx, const pbit_batch_job *jobs, int32_t n_jobs);
+
+/* ---- serving: continuous batching of anneal jobs ------------------------- */
+
+/* Queue an anneal job.  The descriptor, beta and init spins are copied.  A job
+ * is admitted to the GPU when its device memory fits the context's budget and
+ * fewer than max_jobs jobs are running; jobs that arrive while others run join
+ * the next round of the persistent kernels, so their work overlaps on the
+ * device.  The device state of an admitted job (couplings, spins, RNG
+ * counters, thresholds) stays resident until it completes.  Writes a job id.
  * Errors: E_ARG, E_RANGE, E_HANDLE, E_BUSY (queue full), E_NOMEM (the job can
- * never fit the budget), E_UNSUPPORTED. */
+ * never fit the budget), E_UNSUPPORTED (shape not batchable). */
 int pbit_submit(pbit_ctx *ctx, uint64_t problem, const pbit_anneal_desc *desc, uint64_t *job_out);
 
-/* PBIT_PENDING while the job runs; PBIT_OK once it is done, after filling
- * `result` (same fields as pbit_anneal); the job id is then retired. */
+/* PBIT_PENDING while the job is queued or running; PBIT_OK once it is done,
+ * after filling `result` (same fields as pbit_anneal; spin_trace not
+ * supported); the job id is then retired.  E_HANDLE for unknown ids. */
 int pbit_poll(pbit_ctx *ctx, uint64_t job, pbit_result *result);
 
-/* Drive queued work without waiting (also done inside pbit_poll). */
+/* Drive the scheduler without waiting: harvest a finished round, admit queued
+ * jobs, launch the next round.  Also done inside pbit_poll. */
 int pbit_progress(pbit_ctx *ctx);
+
+/* Scheduler limits of a context: queue capacity, concurrently running jobs and
+ * sweeps per round (0 keeps the current value). */
+int pbit_serve_config(pbit_ctx *ctx, int32_t max_queue, int32_t max_running, int32_t round_sweeps);
 
 /* ---- profiling -------------------------------------------------------------- */
 

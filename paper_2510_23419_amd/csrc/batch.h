@@ -1,0 +1,59 @@
+// batch.h — device descriptors of the persistent batched sweep (many jobs in
+// one launch).  A job is one anneal (problem, schedule, replicas, seed).  It is
+// cut into replica tiles that never need each other: a cube tile is 4 replicas
+// of the whole lattice, a biclique tile is 32 or 64 replicas of both sides.
+// A work item advances one tile over a range of sweeps; a persistent kernel
+// pulls items from a queue until the queue is empty.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pbit {
+
+struct EaJobDev {
+    const uint32_t *code;   // [N] site codes (see internal.h)
+    const uint32_t *table;  // [S][width] thresholds, row s = local sweep s
+    int8_t *state;          // [tiles][N][4]: spins of a tile, replica fastest
+    int32_t *energy;        // [tiles * 4]: energies after the tile's last item
+    int Lx, Ly, Lz, width;
+    uint32_t sweep0;        // absolute index of local sweep 0
+    uint32_t rq0;           // global replica group of tile 0 (replica_offset / 4)
+    uint32_t k0, k1;        // Philox key
+};
+
+struct BqJobDev {
+    const int8_t *J, *JT;   // [na_p][nb_p], [nb_p][na_p]
+    const int8_t *hA, *hB;  // [na_p], [nb_p]
+    const uint32_t *table;  // [S][width]
+    int8_t *state;          // [tiles][RS][na_p + nb_p]: row r = side A then side B
+    int32_t *energy;        // [tiles * RS]
+    int na, nb, na_p, nb_p, width;
+    uint32_t sweep0, rq0, k0, k1;
+};
+
+struct WorkItem {
+    int32_t job;      // index into the job array of the item's kind
+    int32_t tile;
+    int32_t s_begin;  // local sweeps [s_begin, s_end)
+    int32_t s_end;
+    int32_t init;     // 1: draw the tile's random start before the first sweep
+    int32_t pad[3];
+};
+
+constexpr int kEaTileThreads = 512;
+constexpr int kBqTileThreads = 256;
+
+// Launch a persistent kernel over `n_items` items; `counter` (device int,
+// zeroed by the caller) hands out item indices.
+hipError_t ea_tiles(const EaJobDev *jobs, const WorkItem *items, const int32_t *n_items, int32_t *counter,
+                    int grid, size_t lds_bytes, hipStream_t st);
+hipError_t bq_tiles(const BqJobDev *jobs, const WorkItem *items, const int32_t *n_items, int32_t *counter,
+                    int rs, int grid, size_t lds_bytes, hipStream_t st);
+
+// LDS a tile kernel needs for the given job shape.
+size_t ea_tile_lds(int64_t N);
+size_t bq_tile_lds(int rs, int na_p, int nb_p, int width);
+hipError_t tiles_set_lds_limit();
+
+}  // namespace pbit

@@ -1,0 +1,362 @@
+// batch_kernels.hip — persistent batched sweep for many independent jobs.
+//
+// Each workgroup repeatedly takes a work item (job, replica tile, sweep range)
+// from a device queue and runs it with the tile's spins held in LDS, so the
+// half-sweeps of a tile need only workgroup barriers, never a grid-wide one:
+// replicas are independent runs (paper Sec. 1.3.3), and inside a tile the two
+// update groups alternate (Sec. 1.2.2).  Jobs of uneven sizes therefore share
+// one launch.  The arithmetic, the Philox counters and the decision rule are
+// the same as in the per-instance kernels, so a job's result does not depend on
+// which items it was batched with.
+#include "batch.h"
+#include "device.h"
+#include "internal.h"
+
+namespace pbit {
+
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+// q = n / d and r = n % d for 0 <= n < 2^22 and 1 <= d < 2^10 from a float
+// reciprocal: the estimate is within one of the quotient and is corrected.
+__device__ __forceinline__ int div_small(int n, int d, float inv, int &r)
+{
+    int q = (int)((float)n * inv);
+    int rr = n - q * d;
+    if (rr < 0) {
+        q -= 1;
+        rr += d;
+    } else if (rr >= d) {
+        q += 1;
+        rr -= d;
+    }
+    r = rr;
+    return q;
+}
+
+__device__ __forceinline__ int take_item(int32_t *counter, int *slot)
+{
+    if (threadIdx.x == 0) *slot = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(*slot);
+    __syncthreads();
+    return it;
+}
+
+// ---------------------------------------------------------------- cube tiles
+
+constexpr int kFieldOff = 7;
+constexpr int kFieldSlots = 2 * kFieldOff + 1;
+
+__device__ __forceinline__ uint32_t neg2(uint32_t m, uint32_t keep, uint32_t flip) { return (m & keep) ^ flip; }
+
+// Spins of one 4-replica tile of the whole lattice live in LDS as one dword
+// per site (byte p = replica p, +1 = 0x01, -1 = 0xFF).
+__global__ __launch_bounds__(kEaTileThreads) void k_ea_tiles(const EaJobDev *__restrict__ jobs,
+                                                             const WorkItem *__restrict__ items,
+                                                             const int32_t *__restrict__ n_items_p,
+                                                             int32_t *__restrict__ counter)
+{
+    extern __shared__ uint32_t sp[];
+    __shared__ uint4 dtab[kFieldSlots];
+    __shared__ int32_t eacc[4];
+    __shared__ int slot;
+    const int tid = threadIdx.x;
+    const int n_items = *n_items_p;
+
+    for (;;) {
+        const int it = take_item(counter, &slot);
+        if (it >= n_items) break;
+        const WorkItem w = items[it];
+        const EaJobDev jb = jobs[w.job];
+        const int Lx = jb.Lx, Ly = jb.Ly, Lz = jb.Lz;
+        const int plane = Lx * Ly, N = plane * Lz, half = N / 2, hx = Lx / 2;
+        const float inv_hx = 1.0f / (float)hx, inv_Ly = 1.0f / (float)Ly, inv_Lx = 1.0f / (float)Lx;
+        const uint32_t rg = jb.rq0 + (uint32_t)w.tile;
+        uint32_t *gst = reinterpret_cast<uint32_t *>(jb.state) + (size_t)w.tile * N;
+
+        if (w.init) {
+            for (int i = tid; i < N; i += kEaTileThreads) {
+                const Block4 b = philox((uint32_t)i, 0u, rg, kDomainInit, jb.k0, jb.k1);
+                uint32_t packed = 0;
+#pragma unroll
+                for (int p = 0; p < 4; ++p) packed |= (uint32_t)(uint8_t)init_spin(b.w[p]) << (8 * p);
+                sp[i] = packed;
+            }
+        } else {
+            for (int i = tid; i < N; i += kEaTileThreads) sp[i] = gst[i];
+        }
+
+        for (int s = w.s_begin; s < w.s_end; ++s) {
+            __syncthreads();
+            if (tid < kFieldSlots) {
+                const uint32_t *trow = jb.table + (size_t)s * jb.width;
+                const int I = tid - kFieldOff;
+                const int a = min(I >= 0 ? I : -I, jb.width - 1);
+                const bool pos = I >= 0;
+                dtab[tid] = make_uint4(trow[a], pos ? 0xFFFFFFFFu : 0u, pos ? 0xFFu : 0x01u, pos ? 0x01u : 0xFFu);
+            }
+            __syncthreads();
+            const uint32_t t = jb.sweep0 + (uint32_t)s;
+            for (int c = 0; c < 2; ++c) {
+                for (int j = tid; j < half; j += kEaTileThreads) {
+                    int kx, y;
+                    const int row = div_small(j, hx, inv_hx, kx);
+                    const int z = div_small(row, Ly, inv_Ly, y);
+                    const int x = 2 * kx + ((c + y + z) & 1);
+                    const int i = x + Lx * y + plane * z;
+                    const int nb[6] = {x + 1 == Lx ? i - x : i + 1,
+                                       x == 0 ? i + Lx - 1 : i - 1,
+                                       y + 1 == Ly ? i - y * Lx : i + Lx,
+                                       y == 0 ? i + (Ly - 1) * Lx : i - Lx,
+                                       z + 1 == Lz ? i - z * plane : i + plane,
+                                       z == 0 ? i + (Lz - 1) * plane : i - plane};
+                    const uint32_t code = jb.code[i];
+                    uint32_t cnt = 0;
+#pragma unroll
+                    for (int d = 0; d < 6; ++d)
+                        cnt += neg2(sp[nb[d]], ((code >> d) & 1u) * 0x02020202u,
+                                    ((code >> (kCodeFlipShift + d)) & 1u) * 0x02020202u);
+                    const Block4 b = philox((uint32_t)i, t, rg, kDomainSweep, jb.k0, jb.k1);
+                    const int entry0 = ((int)(int8_t)(code >> kCodeBaseShift) + kFieldOff) * (int)sizeof(uint4);
+                    const uint32_t off16 = cnt << 4;  // bytes of cnt are <= 12
+                    const char *tb = reinterpret_cast<const char *>(dtab);
+                    uint32_t packed = 0;
+#pragma unroll
+                    for (int p = 0; p < 4; ++p) {
+                        const uint4 e = *reinterpret_cast<const uint4 *>(tb + entry0 - (int)((off16 >> (8 * p)) & 0xFFu));
+                        packed |= ((b.w[p] ^ e.y) < e.x ? e.z : e.w) << (8 * p);
+                    }
+                    sp[i] = packed;
+                }
+                __syncthreads();
+            }
+        }
+
+        // energies of the 4 replicas: every bond has exactly one colour-1 end,
+        // so E = -sum_{i in colour 1} m_i sum_j J_ij m_j - sum_i h_i m_i
+        if (tid < 4) eacc[tid] = 0;
+        __syncthreads();
+        int32_t e[4] = {0, 0, 0, 0};
+        for (int i = tid; i < N; i += kEaTileThreads) {
+            int x, y;
+            const int row = div_small(i, Lx, inv_Lx, x);
+            const int z = div_small(row, Ly, inv_Ly, y);
+            const uint32_t code = jb.code[i];
+            const int nnz = __builtin_popcount(code & 63u);
+            const int hv = (int)(int8_t)(code >> kCodeBaseShift) - nnz;
+            const uint32_t mi = sp[i];
+            int bondsum[4] = {0, 0, 0, 0};
+            if ((x + y + z) & 1) {
+                const int nb[6] = {x + 1 == Lx ? i - x : i + 1,
+                                   x == 0 ? i + Lx - 1 : i - 1,
+                                   y + 1 == Ly ? i - y * Lx : i + Lx,
+                                   y == 0 ? i + (Ly - 1) * Lx : i - Lx,
+                                   z + 1 == Lz ? i - z * plane : i + plane,
+                                   z == 0 ? i + (Lz - 1) * plane : i - plane};
+                uint32_t cnt = 0;
+#pragma unroll
+                for (int d = 0; d < 6; ++d)
+                    cnt += neg2(sp[nb[d]], ((code >> d) & 1u) * 0x02020202u,
+                                ((code >> (kCodeFlipShift + d)) & 1u) * 0x02020202u);
+#pragma unroll
+                for (int p = 0; p < 4; ++p) bondsum[p] = nnz - (int)((cnt >> (8 * p)) & 0xFFu);
+            }
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const int m = (int)(int8_t)(mi >> (8 * p));
+                e[p] -= m * (bondsum[p] + hv);
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            int v = e[p];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if ((tid & 63) == 0) atomicAdd(&eacc[p], v);
+        }
+        __syncthreads();
+        if (tid < 4) jb.energy[4 * w.tile + tid] = eacc[tid];
+        for (int i = tid; i < N; i += kEaTileThreads) gst[i] = sp[i];
+    }
+}
+
+// ---------------------------------------------------------------- biclique tiles
+
+// A tile holds RB x 32 replicas of both sides in LDS, one row per replica:
+// side A in columns [0, na_p), side B in [na_p, na_p + nb_p), padding zero.
+// Each half-sweep is an MFMA product of the LDS spin rows with the couplings
+// streamed from global memory (L2-resident, shared by all tiles of the job),
+// followed by the decision epilogue writing the new side into LDS.
+template <int RB>
+__global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__restrict__ jobs,
+                                                             const WorkItem *__restrict__ items,
+                                                             const int32_t *__restrict__ n_items_p,
+                                                             int32_t *__restrict__ counter)
+{
+    constexpr int RS = 32 * RB;
+    extern __shared__ uint4 dyn[];
+    __shared__ int32_t eacc[RS];
+    __shared__ int slot;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6, ln = lane & 31, kg = lane >> 5;
+    const int n_items = *n_items_p;
+
+    for (;;) {
+        const int it = take_item(counter, &slot);
+        if (it >= n_items) break;
+        const WorkItem w = items[it];
+        const BqJobDev jb = jobs[w.job];
+        const int na = jb.na, nb = jb.nb, na_p = jb.na_p, nb_p = jb.nb_p;
+        const int P = na_p + nb_p, pitch = P + 16;
+        int8_t *sp = reinterpret_cast<int8_t *>(dyn);
+        uint32_t *T = reinterpret_cast<uint32_t *>(sp + (size_t)RS * pitch);
+        int8_t *gst = jb.state + (size_t)w.tile * RS * P;
+        const uint32_t rg0 = jb.rq0 + (uint32_t)(w.tile * (RS / 4));
+
+        if (w.init) {
+            for (int k = tid; k < RS * pitch / 16; k += kBqTileThreads) dyn[k] = make_uint4(0, 0, 0, 0);
+            __syncthreads();
+            const int N = na + nb;
+            for (int k = tid; k < N * (RS / 4); k += kBqTileThreads) {
+                const int g = k % (RS / 4), i = k / (RS / 4);
+                const Block4 b = philox((uint32_t)i, 0u, rg0 + (uint32_t)g, kDomainInit, jb.k0, jb.k1);
+                const int col = i < na ? i : na_p + (i - na);
+#pragma unroll
+                for (int p = 0; p < 4; ++p) sp[(4 * g + p) * pitch + col] = init_spin(b.w[p]);
+            }
+        } else {
+            for (int k = tid; k < RS * (P / 16); k += kBqTileThreads) {
+                const int r = k / (P / 16), c16 = k % (P / 16);
+                *reinterpret_cast<uint4 *>(sp + r * pitch + 16 * c16) =
+                    *reinterpret_cast<const uint4 *>(gst + (size_t)r * P + 16 * c16);
+            }
+        }
+        if (tid < RS) eacc[tid] = 0;
+
+        for (int s = w.s_begin; s < w.s_end; ++s) {
+            __syncthreads();
+            const uint32_t *trow = jb.table + (size_t)s * jb.width;
+            for (int a = tid; a < jb.width; a += kBqTileThreads) T[a] = trow[a];
+            __syncthreads();
+            const uint32_t t = jb.sweep0 + (uint32_t)s;
+            const int top = jb.width - 1;
+            const bool last = s + 1 == w.s_end;
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                const int ns_p = side == 0 ? na_p : nb_p;
+                const int ns = side == 0 ? na : nb;
+                const int ko = side == 0 ? nb_p : na_p;
+                const int in_col = side == 0 ? na_p : 0;   // columns of the other side (A operand)
+                const int out_col = side == 0 ? 0 : na_p;  // columns of this side
+                const int8_t *Jx = side == 0 ? jb.J : jb.JT;
+                const int8_t *hs = side == 0 ? jb.hA : jb.hB;
+                const uint32_t site_base = side == 0 ? 0u : (uint32_t)na;
+                for (int blk = wave; blk < ns_p / 32; blk += kBqTileThreads / 64) {
+                    const int site = blk * 32 + ln;
+                    const int8_t *brow = Jx + (size_t)site * ko + 16 * kg;
+                    v16i acc[RB];
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb) acc[rb] = v16i{0};
+                    for (int k = 0; k < ko; k += 64) {
+                        const v4i b0 = *reinterpret_cast<const v4i *>(brow + k);
+                        const v4i b1 = *reinterpret_cast<const v4i *>(brow + k + 32);
+#pragma unroll
+                        for (int rb = 0; rb < RB; ++rb) {
+                            const int8_t *arow = sp + (rb * 32 + ln) * pitch + in_col + 16 * kg + k;
+                            acc[rb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(*reinterpret_cast<const v4i *>(arow),
+                                                                            b0, acc[rb], 0, 0, 0);
+                            acc[rb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                                *reinterpret_cast<const v4i *>(arow + 32), b1, acc[rb], 0, 0, 0);
+                        }
+                    }
+                    const int hval = hs[site];  // site < ns_p: padded fields are zero
+                    const bool site_ok = site < ns;
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int r4 = rb * 32 + 8 * q + 4 * kg;  // first replica of the group in the tile
+                            const Block4 b = philox(site_base + (uint32_t)site, t, rg0 + (uint32_t)(r4 >> 2),
+                                                    kDomainSweep, jb.k0, jb.k1);
+#pragma unroll
+                            for (int p = 0; p < 4; ++p) {
+                                const int I = acc[rb][4 * q + p] + hval;
+                                const int a = min(I >= 0 ? I : -I, top);
+                                const int8_t m = decide(I, T[a], b.w[p]);
+                                if (site_ok) {
+                                    sp[(r4 + p) * pitch + out_col + site] = m;
+                                    // energy after the last side-B update: E = -sum_b m_b I_b - sum_a h_a m_a
+                                    if (side == 1 && last) atomicAdd(&eacc[r4 + p], -(int)m * I);
+                                }
+                            }
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+
+        // field part of side A, then the energies and the spins go back to global memory
+        for (int k = tid; k < RS * na; k += kBqTileThreads) {
+            const int r = k / na, a = k % na;
+            const int v = (int)jb.hA[a] * (int)sp[r * pitch + a];
+            if (v != 0) atomicAdd(&eacc[r], -v);
+        }
+        __syncthreads();
+        if (tid < RS) jb.energy[w.tile * RS + tid] = eacc[tid];
+        for (int k = tid; k < RS * (P / 16); k += kBqTileThreads) {
+            const int r = k / (P / 16), c16 = k % (P / 16);
+            *reinterpret_cast<uint4 *>(gst + (size_t)r * P + 16 * c16) =
+                *reinterpret_cast<const uint4 *>(sp + r * pitch + 16 * c16);
+        }
+    }
+}
+
+}  // namespace
+
+size_t ea_tile_lds(int64_t N) { return (size_t)N * sizeof(uint32_t); }
+
+size_t bq_tile_lds(int rs, int na_p, int nb_p, int width)
+{
+    return (size_t)rs * (size_t)(na_p + nb_p + 16) + sizeof(uint32_t) * (size_t)width;
+}
+
+hipError_t tiles_set_lds_limit()
+{
+    const int max_lds = 160 * 1024 - 4096;  // leave room for the static shared variables
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ea_tiles),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bq_tiles<1>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bq_tiles<2>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+    return e;
+}
+
+hipError_t ea_tiles(const EaJobDev *jobs, const WorkItem *items, const int32_t *n_items, int32_t *counter, int grid,
+                    size_t lds_bytes, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_ea_tiles, dim3((unsigned)grid), dim3(kEaTileThreads), lds_bytes, st, jobs, items, n_items,
+                       counter);
+    return hipGetLastError();
+}
+
+hipError_t bq_tiles(const BqJobDev *jobs, const WorkItem *items, const int32_t *n_items, int32_t *counter, int rs,
+                    int grid, size_t lds_bytes, hipStream_t st)
+{
+    if (rs == 64)
+        hipLaunchKernelGGL(k_bq_tiles<2>, dim3((unsigned)grid), dim3(kBqTileThreads), lds_bytes, st, jobs, items,
+                           n_items, counter);
+    else if (rs == 32)
+        hipLaunchKernelGGL(k_bq_tiles<1>, dim3((unsigned)grid), dim3(kBqTileThreads), lds_bytes, st, jobs, items,
+                           n_items, counter);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace pbit

@@ -430,7 +430,7 @@ int check_desc(const pbit_anneal_desc *d, const char *who)
     return PBIT_OK;
 }
 
-static int spins_in_range(const int8_t *s, size_t n)
+int spins_in_range(const int8_t *s, size_t n)
 {
     for (size_t k = 0; k < n; ++k)
         if (s[k] != 1 && s[k] != -1) return 0;

@@ -1,26 +1,587 @@
-// serve.cpp — job submission and polling (continuous batching of anneal jobs).
+// serve.cpp — batched anneals and the serving scheduler (continuous batching).
+//
+// Jobs are cut into replica tiles; a round advances every running job by one
+// chunk of sweeps with one persistent kernel per tile kind (cube tiles, and
+// biclique tiles of 64 or 32 replicas), each on its own stream so the kinds
+// overlap on the device.  Between rounds the scheduler harvests energies
+// (traces, targets), retires finished jobs, and admits queued ones when their
+// device memory fits the context's budget.  A job's arithmetic and random
+// counters do not depend on the round it runs in, so results are the same
+// alone and in any mix.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <new>
+#include <vector>
+
+#include "batch.h"
 #include "runtime_internal.h"
 
 using namespace pbit;
 
 namespace pbit {
-void serve_shutdown(pbit_ctx *) {}
-}  // namespace pbit
 
-extern "C" int pbit_submit(pbit_ctx *ctx, uint64_t, const pbit_anneal_desc *, uint64_t *)
+int spins_in_range(const int8_t *s, size_t n);  // runtime.cpp
+
+namespace {
+
+constexpr int kMaxLdsTile = 160 * 1024 - 4096;
+
+struct BJob {
+    uint64_t id = 0;
+    uint64_t problem = 0;
+    Problem *P = nullptr;
+    pbit_anneal_desc d{};
+    std::vector<double> beta;
+    std::vector<int8_t> init;
+    int kind = 0, N = 0, R = 0, S = 0;
+    int rs = 4, tiles = 0, width = 1, chunk = 1;
+    // device memory (released when the job finishes)
+    void *d_table = nullptr, *d_state = nullptr, *d_energy = nullptr;
+    size_t bytes = 0;
+    bool admitted = false, started = false, finished = false;
+    int s_done = 0, sweeps_done = 0;
+    std::vector<int32_t> energy;  // latest per-replica energies
+    std::vector<int64_t> etrace;  // [trace_len][R]
+    int trace_len = 0, trace_cap = 0;
+    std::vector<int8_t> spins;    // final spins [R][N] (host), kept until polled
+    bool want_spins = true;
+    pbit_result *user = nullptr;  // batch API: result filled at completion
+};
+
+}  // namespace
+
+struct ServeState {
+    std::deque<BJob *> queue;
+    std::vector<BJob *> running;
+    std::map<uint64_t, std::unique_ptr<BJob>> jobs;
+    uint64_t next_id = 1;
+    int max_queue = 4096, max_running = 1024, round_sweeps = 500;
+    hipStream_t st[3] = {nullptr, nullptr, nullptr};  // cube tiles, 64-replica and 32-replica biclique tiles
+    hipEvent_t fork = nullptr, join[3] = {nullptr, nullptr, nullptr};
+    bool in_flight = false;
+    std::vector<BJob *> round_jobs;
+    std::vector<int> round_end;
+    // device work lists (grown on demand)
+    void *d_ea_jobs = nullptr, *d_bq_jobs[2] = {nullptr, nullptr}, *d_items[3] = {nullptr, nullptr, nullptr};
+    size_t cap_ea_jobs = 0, cap_bq_jobs[2] = {0, 0}, cap_items[3] = {0, 0, 0};
+    int32_t *d_meta = nullptr;  // counters[3], n_items[3]
+    bool lds_ready = false;
+};
+
+static int grow(pbit_ctx *ctx, void **p, size_t *cap, size_t need)
 {
-    if (!ctx) return fail(PBIT_E_ARG, "pbit_submit: context is NULL");
-    return fail(PBIT_E_UNSUPPORTED, "pbit_submit: serving is not built yet");
+    if (*cap >= need && *p) return PBIT_OK;
+    if (*p) {
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return device_fail(ctx, e, "hipDeviceSynchronize");
+        dev_free(ctx, *p);
+        *p = nullptr;
+        *cap = 0;
+    }
+    size_t want = std::max(need, (size_t)4096);
+    int rc = dev_alloc(ctx, want, p);
+    if (rc) return rc;
+    *cap = want;
+    return PBIT_OK;
 }
 
-extern "C" int pbit_poll(pbit_ctx *ctx, uint64_t, pbit_result *)
+static int serve_init(pbit_ctx *ctx)
 {
-    if (!ctx) return fail(PBIT_E_ARG, "pbit_poll: context is NULL");
-    return fail(PBIT_E_HANDLE, "pbit_poll: unknown job");
+    if (ctx->serve) return PBIT_OK;
+    std::unique_ptr<ServeState> s(new (std::nothrow) ServeState());
+    if (!s) return fail(PBIT_E_NOMEM, "serving state: host allocation failed");
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipStreamCreateWithFlags(&s->st[k], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->fork, hipEventDisableTiming);
+    for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&s->join[k], hipEventDisableTiming);
+    if (e != hipSuccess) return device_fail(ctx, e, "serving streams");
+    void *meta = nullptr;
+    int rc = dev_alloc(ctx, 64, &meta);
+    if (rc) return rc;
+    s->d_meta = (int32_t *)meta;
+    ctx->serve = s.release();
+    return PBIT_OK;
+}
+
+void serve_shutdown(pbit_ctx *ctx)
+{
+    ServeState *s = ctx->serve;
+    if (!s) return;
+    (void)hipDeviceSynchronize();
+    for (auto &kv : s->jobs) {
+        BJob *j = kv.second.get();
+        dev_free(ctx, j->d_table);
+        dev_free(ctx, j->d_state);
+        dev_free(ctx, j->d_energy);
+        if (j->P) j->P->jobs--;
+    }
+    dev_free(ctx, s->d_ea_jobs);
+    for (int k = 0; k < 2; ++k) dev_free(ctx, s->d_bq_jobs[k]);
+    for (int k = 0; k < 3; ++k) dev_free(ctx, s->d_items[k]);
+    dev_free(ctx, s->d_meta);
+    for (int k = 0; k < 3; ++k) {
+        if (s->st[k]) (void)hipStreamDestroy(s->st[k]);
+        if (s->join[k]) (void)hipEventDestroy(s->join[k]);
+    }
+    if (s->fork) (void)hipEventDestroy(s->fork);
+    delete s;
+    ctx->serve = nullptr;
+}
+
+// ---------------------------------------------------------------- job set-up
+
+static int plan_job(pbit_ctx *ctx, BJob &j)
+{
+    const Problem &P = *j.P;
+    j.kind = P.kind;
+    j.N = (int)P.N;
+    j.R = j.d.n_replicas;
+    j.S = j.d.n_sweeps;
+    j.width = j.S > 0 ? table_width(j.beta.data(), j.S, P.amax) : 1;
+    if (j.width > kMaxTableWidth) return fail(PBIT_E_UNSUPPORTED, "threshold rows of %d entries are too wide", j.width);
+    if (P.kind == PBIT_EA3D) {
+        if (ea_tile_lds(P.N) > (size_t)kMaxLdsTile || P.ea.Lx > 1024 || P.ea.Ly > 1024)
+            return fail(PBIT_E_UNSUPPORTED, "cube of %lld sites is too large for a batched tile", (long long)P.N);
+        j.rs = 4;
+    } else {
+        const int na_p = P.bq.na_p, nb_p = P.bq.nb_p;
+        if (j.R >= 64 && bq_tile_lds(64, na_p, nb_p, j.width) <= (size_t)kMaxLdsTile)
+            j.rs = 64;
+        else if (bq_tile_lds(32, na_p, nb_p, j.width) <= (size_t)kMaxLdsTile)
+            j.rs = 32;
+        else
+            return fail(PBIT_E_UNSUPPORTED, "biclique %d x %d is too large for a batched tile", P.bq.na, P.bq.nb);
+    }
+    j.tiles = (j.R + j.rs - 1) / j.rs;
+    const size_t tile_bytes = P.kind == PBIT_EA3D ? (size_t)4 * j.N : (size_t)j.rs * (P.bq.na_p + P.bq.nb_p);
+    j.bytes = sizeof(uint32_t) * (size_t)std::max(j.S, 1) * j.width + (size_t)j.tiles * tile_bytes +
+              sizeof(int32_t) * (size_t)j.tiles * j.rs;
+    const bool check = j.d.has_target || j.d.trace_every > 0;
+    j.chunk = check ? (j.d.trace_every > 0 ? j.d.trace_every : PBIT_CHECK_SWEEPS) : std::max(j.S, 1);
+    j.trace_cap = j.d.trace_every > 0 ? j.S / j.d.trace_every : 0;
+    (void)ctx;
+    return PBIT_OK;
+}
+
+// [R][N] host rows <-> tile layout
+static void rows_to_tiles(const BJob &j, const int8_t *rows, std::vector<int8_t> &tiles_out)
+{
+    const Problem &P = *j.P;
+    if (P.kind == PBIT_EA3D) {
+        tiles_out.assign((size_t)j.tiles * 4 * j.N, 1);
+        for (int r = 0; r < j.R; ++r)
+            for (int i = 0; i < j.N; ++i) tiles_out[((size_t)(r / 4) * j.N + i) * 4 + (r % 4)] = rows[(size_t)r * j.N + i];
+    } else {
+        const int Pw = P.bq.na_p + P.bq.nb_p;
+        tiles_out.assign((size_t)j.tiles * j.rs * Pw, 0);
+        for (int r = 0; r < j.R; ++r)
+            for (int i = 0; i < j.N; ++i) {
+                const int col = i < P.bq.na ? i : P.bq.na_p + (i - P.bq.na);
+                tiles_out[((size_t)(r / j.rs) * j.rs + (r % j.rs)) * Pw + col] = rows[(size_t)r * j.N + i];
+            }
+    }
+}
+
+static void tiles_to_rows(const BJob &j, const int8_t *tl, int8_t *rows)
+{
+    const Problem &P = *j.P;
+    if (P.kind == PBIT_EA3D) {
+        for (int r = 0; r < j.R; ++r)
+            for (int i = 0; i < j.N; ++i) rows[(size_t)r * j.N + i] = tl[((size_t)(r / 4) * j.N + i) * 4 + (r % 4)];
+    } else {
+        const int Pw = P.bq.na_p + P.bq.nb_p;
+        for (int r = 0; r < j.R; ++r)
+            for (int i = 0; i < j.N; ++i) {
+                const int col = i < P.bq.na ? i : P.bq.na_p + (i - P.bq.na);
+                rows[(size_t)r * j.N + i] = tl[((size_t)(r / j.rs) * j.rs + (r % j.rs)) * Pw + col];
+            }
+    }
+}
+
+static int admit(pbit_ctx *ctx, BJob &j)
+{
+    int rc = dev_alloc(ctx, sizeof(uint32_t) * (size_t)std::max(j.S, 1) * j.width, &j.d_table);
+    const size_t tile_bytes =
+        j.kind == PBIT_EA3D ? (size_t)4 * j.N : (size_t)j.rs * (j.P->bq.na_p + j.P->bq.nb_p);
+    if (rc == PBIT_OK) rc = dev_alloc(ctx, (size_t)j.tiles * tile_bytes, &j.d_state);
+    if (rc == PBIT_OK) rc = dev_alloc(ctx, sizeof(int32_t) * (size_t)j.tiles * j.rs, &j.d_energy);
+    if (rc != PBIT_OK) {
+        dev_free(ctx, j.d_table);
+        dev_free(ctx, j.d_state);
+        dev_free(ctx, j.d_energy);
+        j.d_table = j.d_state = j.d_energy = nullptr;
+        return rc;
+    }
+    std::vector<uint32_t> tab((size_t)std::max(j.S, 1) * j.width, 0u);
+    if (j.S > 0) build_table(j.beta.data(), j.S, j.width, tab.data());
+    hipError_t e = hipMemcpy(j.d_table, tab.data(), sizeof(uint32_t) * tab.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !j.init.empty()) {
+        std::vector<int8_t> tl;
+        rows_to_tiles(j, j.init.data(), tl);
+        e = hipMemcpy(j.d_state, tl.data(), tl.size(), hipMemcpyHostToDevice);
+        j.started = true;
+    }
+    if (e != hipSuccess) return device_fail(ctx, e, "job upload");
+    j.admitted = true;
+    j.energy.assign(j.R, 0);
+    return PBIT_OK;
+}
+
+static void release(pbit_ctx *ctx, BJob &j)
+{
+    dev_free(ctx, j.d_table);
+    dev_free(ctx, j.d_state);
+    dev_free(ctx, j.d_energy);
+    j.d_table = j.d_state = j.d_energy = nullptr;
+    if (j.P) {
+        j.P->jobs--;
+        j.P = nullptr;
+    }
+}
+
+// ---------------------------------------------------------------- rounds
+
+static int launch_round(pbit_ctx *ctx, ServeState &s)
+{
+    s.round_jobs.clear();
+    s.round_end.clear();
+    std::vector<EaJobDev> ea;
+    std::vector<BqJobDev> bq[2];
+    std::vector<WorkItem> items[3];
+    std::vector<double> cost[3];
+    size_t lds[3] = {0, 0, 0};
+    for (BJob *j : s.running) {
+        if (j->finished) continue;
+        const int s0 = j->s_done;
+        const int s1 = std::min(j->S, s0 + j->chunk);
+        if (s1 <= s0) continue;
+        s.round_jobs.push_back(j);
+        s.round_end.push_back(s1);
+        const Key key{(uint32_t)j->d.seed, (uint32_t)(j->d.seed >> 32)};
+        if (j->kind == PBIT_EA3D) {
+            const EaView &v = j->P->ea;
+            EaJobDev jd{v.code, (const uint32_t *)j->d_table, (int8_t *)j->d_state, (int32_t *)j->d_energy,
+                        v.Lx, v.Ly, v.Lz, j->width, (uint32_t)j->d.sweep_offset,
+                        (uint32_t)j->d.replica_offset >> 2, key.k0, key.k1};
+            const int idx = (int)ea.size();
+            ea.push_back(jd);
+            for (int t = 0; t < j->tiles; ++t) {
+                items[0].push_back(WorkItem{idx, t, s0, s1, j->started ? 0 : 1, {0, 0, 0}});
+                cost[0].push_back((double)(s1 - s0) * j->N);
+            }
+            lds[0] = std::max(lds[0], ea_tile_lds(j->N));
+        } else {
+            const BqView &v = j->P->bq;
+            const int k = j->rs == 64 ? 1 : 2;
+            BqJobDev jd{v.J, v.JT, v.hA, v.hB, (const uint32_t *)j->d_table, (int8_t *)j->d_state,
+                        (int32_t *)j->d_energy, v.na, v.nb, v.na_p, v.nb_p, j->width,
+                        (uint32_t)j->d.sweep_offset, (uint32_t)j->d.replica_offset >> 2, key.k0, key.k1};
+            const int idx = (int)bq[k - 1].size();
+            bq[k - 1].push_back(jd);
+            for (int t = 0; t < j->tiles; ++t) {
+                items[k].push_back(WorkItem{idx, t, s0, s1, j->started ? 0 : 1, {0, 0, 0}});
+                cost[k].push_back((double)(s1 - s0) * (double)v.na_p * v.nb_p * j->rs);
+            }
+            lds[k] = std::max(lds[k], bq_tile_lds(j->rs, v.na_p, v.nb_p, j->width));
+        }
+    }
+    if (s.round_jobs.empty()) return PBIT_OK;
+
+    // longest items first, so that the persistent workgroups finish together
+    for (int k = 0; k < 3; ++k) {
+        std::vector<size_t> ord(items[k].size());
+        for (size_t q = 0; q < ord.size(); ++q) ord[q] = q;
+        std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return cost[k][a] > cost[k][b]; });
+        std::vector<WorkItem> sorted(items[k].size());
+        for (size_t q = 0; q < ord.size(); ++q) sorted[q] = items[k][ord[q]];
+        items[k].swap(sorted);
+    }
+    int rc = grow(ctx, &s.d_ea_jobs, &s.cap_ea_jobs, sizeof(EaJobDev) * std::max<size_t>(ea.size(), 1));
+    for (int k = 0; k < 2 && rc == PBIT_OK; ++k)
+        rc = grow(ctx, &s.d_bq_jobs[k], &s.cap_bq_jobs[k], sizeof(BqJobDev) * std::max<size_t>(bq[k].size(), 1));
+    for (int k = 0; k < 3 && rc == PBIT_OK; ++k)
+        rc = grow(ctx, &s.d_items[k], &s.cap_items[k], sizeof(WorkItem) * std::max<size_t>(items[k].size(), 1));
+    if (rc) return rc;
+    if (!s.lds_ready) {
+        hipError_t e = tiles_set_lds_limit();
+        if (e != hipSuccess) return device_fail(ctx, e, "tile LDS limit");
+        s.lds_ready = true;
+    }
+    int32_t meta[6] = {0, 0, 0, (int32_t)items[0].size(), (int32_t)items[1].size(), (int32_t)items[2].size()};
+    hipError_t e = hipMemcpy(s.d_meta, meta, sizeof meta, hipMemcpyHostToDevice);
+    if (e == hipSuccess && !ea.empty())
+        e = hipMemcpy(s.d_ea_jobs, ea.data(), sizeof(EaJobDev) * ea.size(), hipMemcpyHostToDevice);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k)
+        if (!bq[k].empty()) e = hipMemcpy(s.d_bq_jobs[k], bq[k].data(), sizeof(BqJobDev) * bq[k].size(), hipMemcpyHostToDevice);
+    for (int k = 0; k < 3 && e == hipSuccess; ++k)
+        if (!items[k].empty()) e = hipMemcpy(s.d_items[k], items[k].data(), sizeof(WorkItem) * items[k].size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return device_fail(ctx, e, "round upload");
+
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, ctx->device);
+    if (e != hipSuccess) return device_fail(ctx, e, "hipGetDeviceProperties");
+    const int cus = prop.multiProcessorCount;
+    for (int k = 0; k < 3; ++k) {
+        if (items[k].empty()) continue;
+        const size_t per_cu_lds = std::max<size_t>(lds[k] + 2048, 1);
+        const int per_cu = std::max(1, std::min(4, (int)((160 * 1024) / per_cu_lds)));
+        const int grid = std::max(1, std::min((int)items[k].size(), cus * per_cu));
+        if (k == 0)
+            e = ea_tiles((const EaJobDev *)s.d_ea_jobs, (const WorkItem *)s.d_items[0], s.d_meta + 3, s.d_meta + 0,
+                         grid, lds[0], s.st[0]);
+        else
+            e = bq_tiles((const BqJobDev *)s.d_bq_jobs[k - 1], (const WorkItem *)s.d_items[k], s.d_meta + 3 + k,
+                         s.d_meta + k, k == 1 ? 64 : 32, grid, lds[k], s.st[k]);
+        if (e == hipSuccess) e = hipEventRecord(s.join[k], s.st[k]);
+        if (e != hipSuccess) return device_fail(ctx, e, "tile kernel launch");
+    }
+    s.in_flight = true;
+    return PBIT_OK;
+}
+
+static bool round_done(ServeState &s)
+{
+    for (int k = 0; k < 3; ++k)
+        if (hipEventQuery(s.join[k]) == hipErrorNotReady) return false;
+    return true;
+}
+
+static int harvest(pbit_ctx *ctx, ServeState &s)
+{
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipStreamSynchronize(s.st[k]);
+    if (e != hipSuccess) return device_fail(ctx, e, "round");
+    s.in_flight = false;
+    std::vector<int32_t> tile_e;
+    for (size_t q = 0; q < s.round_jobs.size(); ++q) {
+        BJob &j = *s.round_jobs[q];
+        j.s_done = s.round_end[q];
+        j.started = true;
+        tile_e.resize((size_t)j.tiles * j.rs);
+        e = hipMemcpy(tile_e.data(), j.d_energy, sizeof(int32_t) * tile_e.size(), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return device_fail(ctx, e, "energy readback");
+        for (int r = 0; r < j.R; ++r) j.energy[r] = tile_e[r];
+        if (j.d.trace_every > 0 && j.s_done % j.d.trace_every == 0 && j.trace_len < j.trace_cap) {
+            for (int r = 0; r < j.R; ++r) j.etrace.push_back(j.energy[r]);
+            ++j.trace_len;
+        }
+        const bool hit = j.d.has_target && *std::min_element(j.energy.begin(), j.energy.end()) <= j.d.target_energy;
+        if (hit || j.s_done >= j.S) {
+            j.finished = true;
+            j.sweeps_done = j.s_done;
+            if (j.want_spins) {
+                const size_t tile_bytes =
+                    j.kind == PBIT_EA3D ? (size_t)4 * j.N : (size_t)j.rs * (j.P->bq.na_p + j.P->bq.nb_p);
+                std::vector<int8_t> tl((size_t)j.tiles * tile_bytes);
+                e = hipMemcpy(tl.data(), j.d_state, tl.size(), hipMemcpyDeviceToHost);
+                if (e != hipSuccess) return device_fail(ctx, e, "spin readback");
+                j.spins.resize((size_t)j.R * j.N);
+                tiles_to_rows(j, tl.data(), j.spins.data());
+            }
+            release(ctx, j);
+        }
+    }
+    s.running.erase(std::remove_if(s.running.begin(), s.running.end(), [](BJob *j) { return j->finished; }),
+                    s.running.end());
+    return PBIT_OK;
+}
+
+// One scheduling step.  With wait = true it blocks until the round it launched
+// (or the one in flight) has been harvested.
+static int step(pbit_ctx *ctx, ServeState &s, bool wait)
+{
+    if (s.in_flight) {
+        if (!wait && !round_done(s)) return PBIT_OK;
+        int rc = harvest(ctx, s);
+        if (rc) return rc;
+    }
+    while (!s.queue.empty() && (int)s.running.size() < s.max_running) {
+        BJob *j = s.queue.front();
+        if (ctx->budget && ctx->in_use + j->bytes > ctx->budget) break;
+        int rc = admit(ctx, *j);
+        if (rc == PBIT_E_NOMEM) break;  // wait for running jobs to free memory
+        if (rc) return rc;
+        s.queue.pop_front();
+        s.running.push_back(j);
+    }
+    int rc = launch_round(ctx, s);
+    if (rc) return rc;
+    if (wait && s.in_flight) return harvest(ctx, s);
+    return PBIT_OK;
+}
+
+static int new_job(pbit_ctx *ctx, ServeState &s, uint64_t problem, const pbit_anneal_desc *desc, BJob **out)
+{
+    int rc = check_desc(desc, "pbit_submit");
+    if (rc) return rc;
+    Problem *P = find_problem(ctx, problem);
+    if (!P) return fail(PBIT_E_HANDLE, "pbit_submit: unknown problem handle");
+    if (desc->init_spins && !spins_in_range(desc->init_spins, (size_t)desc->n_replicas * P->N))
+        return fail(PBIT_E_RANGE, "pbit_submit: init_spins must be +-1");
+    if (desc->n_sweeps < 1) return fail(PBIT_E_ARG, "pbit_submit: a job needs at least one sweep");
+    std::unique_ptr<BJob> j(new (std::nothrow) BJob());
+    if (!j) return fail(PBIT_E_NOMEM, "pbit_submit: host allocation failed");
+    j->d = *desc;
+    j->beta.assign(desc->beta, desc->beta + desc->n_sweeps);
+    j->d.beta = j->beta.data();
+    if (desc->init_spins) j->init.assign(desc->init_spins, desc->init_spins + (size_t)desc->n_replicas * P->N);
+    j->d.init_spins = nullptr;
+    j->P = P;
+    j->problem = problem;
+    rc = plan_job(ctx, *j);
+    if (rc) return rc;
+    if (ctx->budget && j->bytes + 65536 > ctx->budget)
+        return fail(PBIT_E_NOMEM, "job needs %llu bytes of device memory, more than the budget",
+                    (unsigned long long)j->bytes);
+    j->id = ((uint64_t)ctx->serial << 40) | (s.next_id++);
+    P->jobs++;
+    s.queue.push_back(j.get());
+    *out = j.get();
+    s.jobs[j->id] = std::move(j);
+    return PBIT_OK;
+}
+
+static void fill_result(const BJob &j, pbit_result *res)
+{
+    if (res->spins && !j.spins.empty()) std::memcpy(res->spins, j.spins.data(), j.spins.size());
+    int best = 0;
+    for (int r = 0; r < j.R; ++r) {
+        if (res->energies) res->energies[r] = j.energy[r];
+        if (j.energy[r] < j.energy[best]) best = r;
+    }
+    res->best_energy = j.energy[best];
+    res->best_replica = best;
+    res->sweeps_done = j.sweeps_done;
+    const int n = std::min(j.trace_len, std::max(res->trace_cap, 0));
+    if (res->energy_trace)
+        for (int k = 0; k < n; ++k)
+            for (int r = 0; r < j.R; ++r) res->energy_trace[(size_t)k * j.R + r] = j.etrace[(size_t)k * j.R + r];
+    res->trace_len = res->energy_trace ? n : 0;
+}
+
+}  // namespace pbit
+
+#define PBIT_SERVE_ENTER(ctx)                                                                \
+    if (!(ctx)) return fail(PBIT_E_ARG, "%s: context is NULL", __func__);                    \
+    std::lock_guard<std::mutex> lock_((ctx)->mu);                                            \
+    if ((ctx)->poisoned) return fail(PBIT_E_DEVICE, "%s: context is poisoned", __func__);    \
+    {                                                                                        \
+        hipError_t se_ = hipSetDevice((ctx)->device);                                        \
+        if (se_ != hipSuccess) return device_fail((ctx), se_, "hipSetDevice");               \
+    }                                                                                        \
+    {                                                                                        \
+        int ir_ = serve_init(ctx);                                                           \
+        if (ir_) return ir_;                                                                 \
+    }
+
+extern "C" int pbit_submit(pbit_ctx *ctx, uint64_t problem, const pbit_anneal_desc *desc, uint64_t *job_out)
+{
+    try {
+        PBIT_SERVE_ENTER(ctx);
+        if (!job_out) return fail(PBIT_E_ARG, "pbit_submit: job_out is NULL");
+        ServeState &s = *ctx->serve;
+        if ((int)s.queue.size() >= s.max_queue) return fail(PBIT_E_BUSY, "pbit_submit: queue full (%d jobs)", s.max_queue);
+        BJob *j = nullptr;
+        int rc = new_job(ctx, s, problem, desc, &j);
+        if (rc) return rc;
+        // jobs without checks advance round_sweeps at a time, so that jobs arriving
+        // later join the running ones at the next round
+        if (!j->d.has_target && j->d.trace_every == 0) j->chunk = std::min(j->chunk, s.round_sweeps);
+        *job_out = j->id;
+        return step(ctx, s, false);
+    } catch (const std::bad_alloc &) {
+        return fail(PBIT_E_NOMEM, "pbit_submit: host allocation failed");
+    } catch (...) {
+        return fail(PBIT_E_ARG, "pbit_submit: internal error");
+    }
+}
+
+extern "C" int pbit_poll(pbit_ctx *ctx, uint64_t job, pbit_result *result)
+{
+    try {
+        PBIT_SERVE_ENTER(ctx);
+        ServeState &s = *ctx->serve;
+        auto it = s.jobs.find(job);
+        if (it == s.jobs.end()) return fail(PBIT_E_HANDLE, "pbit_poll: unknown job");
+        int rc = step(ctx, s, false);
+        if (rc) return rc;
+        BJob &j = *it->second;
+        if (!j.finished) return PBIT_PENDING;
+        if (result) fill_result(j, result);
+        s.jobs.erase(it);
+        return PBIT_OK;
+    } catch (...) {
+        return fail(PBIT_E_ARG, "pbit_poll: internal error");
+    }
 }
 
 extern "C" int pbit_progress(pbit_ctx *ctx)
 {
-    if (!ctx) return fail(PBIT_E_ARG, "pbit_progress: context is NULL");
+    try {
+        PBIT_SERVE_ENTER(ctx);
+        return step(ctx, *ctx->serve, false);
+    } catch (...) {
+        return fail(PBIT_E_ARG, "pbit_progress: internal error");
+    }
+}
+
+extern "C" int pbit_serve_config(pbit_ctx *ctx, int32_t max_queue, int32_t max_running, int32_t round_sweeps)
+{
+    PBIT_SERVE_ENTER(ctx);
+    if (max_queue < 0 || max_running < 0 || round_sweeps < 0) return fail(PBIT_E_ARG, "pbit_serve_config: negative limit");
+    ServeState &s = *ctx->serve;
+    if (max_queue) s.max_queue = max_queue;
+    if (max_running) s.max_running = max_running;
+    if (round_sweeps) s.round_sweeps = round_sweeps;
     return PBIT_OK;
+}
+
+extern "C" int pbit_anneal_batch(pbit_ctx *ctx, const pbit_batch_job *jobs, int32_t n_jobs)
+{
+    try {
+        PBIT_SERVE_ENTER(ctx);
+        if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return fail(PBIT_E_ARG, "pbit_anneal_batch: bad job list");
+        ServeState &s = *ctx->serve;
+        std::vector<BJob *> mine;
+        for (int k = 0; k < n_jobs; ++k) {
+            if (!jobs[k].result) return fail(PBIT_E_ARG, "pbit_anneal_batch: job %d has no result", k);
+            if (jobs[k].result->spin_trace) return fail(PBIT_E_ARG, "pbit_anneal_batch: spin traces are not supported");
+        }
+        for (int k = 0; k < n_jobs; ++k) {
+            BJob *j = nullptr;
+            int rc = new_job(ctx, s, jobs[k].problem, jobs[k].desc, &j);
+            if (rc) {
+                // withdraw the jobs queued by this call
+                for (BJob *m : mine) {
+                    s.queue.erase(std::remove(s.queue.begin(), s.queue.end(), m), s.queue.end());
+                    if (m->P) m->P->jobs--;
+                    s.jobs.erase(m->id);
+                }
+                return rc;
+            }
+            j->want_spins = jobs[k].result->spins != nullptr;
+            j->user = jobs[k].result;
+            mine.push_back(j);
+        }
+        for (;;) {
+            bool all = true;
+            for (BJob *m : mine) all = all && m->finished;
+            if (all) break;
+            int rc = step(ctx, s, true);
+            if (rc) return rc;
+        }
+        for (BJob *m : mine) {
+            fill_result(*m, m->user);
+            s.jobs.erase(m->id);
+        }
+        return PBIT_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(PBIT_E_NOMEM, "pbit_anneal_batch: host allocation failed");
+    } catch (...) {
+        return fail(PBIT_E_ARG, "pbit_anneal_batch: internal error");
+    }
 }

@@ -28,11 +28,12 @@ PBIT_E_UNSUPPORTED = -8
 
 PBIT_EA3D = 1
 PBIT_BICLIQUE = 2
+PBIT_CHECK_SWEEPS = 100
 
 EXPORTS = ("pbit_create", "pbit_destroy", "pbit_last_error", "pbit_bytes_in_use", "pbit_load_problem",
            "pbit_unload_problem", "pbit_problem_spins", "pbit_anneal", "pbit_anneal_dev", "pbit_energy",
            "pbit_submit", "pbit_poll", "pbit_progress", "pbit_threshold_table", "pbit_version",
-           "pbit_profile_enable", "pbit_profile_read")
+           "pbit_profile_enable", "pbit_profile_read", "pbit_anneal_batch", "pbit_serve_config")
 
 
 class PbitError(RuntimeError):
@@ -53,11 +54,16 @@ class AnnealDesc(ctypes.Structure):
                 ("target_energy", ctypes.c_int64)]
 
 
-class Result(ctypes.Structure):
+class Result(ctypes.Structure):  # noqa: E302
     _fields_ = [("spins", ctypes.c_void_p), ("energies", ctypes.c_void_p), ("best_energy", ctypes.c_int64),
                 ("best_replica", ctypes.c_int32), ("sweeps_done", ctypes.c_int32),
                 ("energy_trace", ctypes.c_void_p), ("trace_cap", ctypes.c_int32), ("trace_len", ctypes.c_int32),
                 ("spin_trace", ctypes.c_void_p)]
+
+
+class BatchJob(ctypes.Structure):
+    _fields_ = [("problem", ctypes.c_uint64), ("desc", ctypes.POINTER(AnnealDesc)),
+                ("result", ctypes.POINTER(Result))]
 
 
 _lib = None
@@ -93,6 +99,8 @@ def lib() -> ctypes.CDLL:
             "pbit_version": ([], ctypes.c_char_p),
             "pbit_profile_enable": ([P, i32], ctypes.c_int),
             "pbit_profile_read": ([P, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), i32], ctypes.c_int),
+            "pbit_anneal_batch": ([P, ctypes.POINTER(BatchJob), i32], ctypes.c_int),
+            "pbit_serve_config": ([P, i32, i32, i32], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -302,6 +310,36 @@ def pbit_poll(ctx, job: int, n_replicas: int, n_spins: int, n_sweeps: int = 0, t
 
 def pbit_progress(ctx) -> None:
     _check(lib().pbit_progress(ctx))
+
+
+def pbit_serve_config(ctx, max_queue: int = 0, max_running: int = 0, round_sweeps: int = 0) -> None:
+    _check(lib().pbit_serve_config(ctx, int(max_queue), int(max_running), int(round_sweeps)))
+
+
+def pbit_anneal_batch(ctx, jobs, want_spins: bool = True):
+    """Run many jobs in the persistent batched kernels.  ``jobs`` is a list of
+    dicts with keys problem, beta, n_replicas, seed and optionally
+    sweep_offset, replica_offset, init_spins, trace_every, target.  Returns one
+    AnnealOutput per job."""
+    n = len(jobs)
+    arr = (BatchJob * max(n, 1))()
+    keep, outs = [], []
+    for k, jb in enumerate(jobs):
+        N = pbit_problem_spins(ctx, jb["problem"])
+        d, kd = _anneal_desc(jb["beta"], jb["n_replicas"], jb["seed"], jb.get("sweep_offset", 0),
+                             jb.get("replica_offset", 0), jb.get("init_spins"), jb.get("trace_every", 0),
+                             jb.get("target"))
+        S = len(np.asarray(jb["beta"]).reshape(-1))
+        res, spins, energies, etrace, strace = _result_buffers(int(jb["n_replicas"]), N, S,
+                                                               int(jb.get("trace_every", 0)), want_spins, False)
+        keep.append((d, kd, res))
+        outs.append((res, spins, energies, etrace, strace))
+        arr[k].problem = int(jb["problem"])
+        arr[k].desc = ctypes.pointer(d)
+        arr[k].result = ctypes.pointer(res)
+    _check(lib().pbit_anneal_batch(ctx, arr, n))
+    del keep
+    return [_output(*o) for o in outs]
 
 
 class Context:
