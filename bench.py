@@ -103,12 +103,141 @@ def measured_traffic(workload):
     return float(rec["traffic_bytes_per_launch"])
 
 
+def mixed_bag_bench(args, pbit, torch):
+    """Mixed bag: 256 jobs (128 cubes, L in {8..24}; 128 bicliques, n in
+    [64, 1024]; 32..512 replicas; 1000..5000 sweeps) in the persistent batched
+    kernels, against the plain per-instance sweep (one job after another)."""
+    import synth
+    bag = synth.mixed_bag(seed=args.bag_seed, n_instances=args.bag_size)
+    ctx = pbit.Context(0)
+    probs = [pbit.load_instance(ctx.ctx, j["instance"]) for j in bag]
+    jobs = [dict(problem=p, beta=j["beta"], n_replicas=j["replicas"], seed=j["seed"]) for p, j in zip(probs, bag)]
+    updates = sum(pbit.pbit_problem_spins(ctx.ctx, p) * j["replicas"] * len(j["beta"]) for p, j in zip(probs, bag))
+    # batched: one call, all jobs
+    pbit.pbit_anneal_batch(ctx.ctx, jobs[:4], want_spins=False)  # warm-up (code objects, LDS limits)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = pbit.pbit_anneal_batch(ctx.ctx, jobs, want_spins=False)
+    t_batch = time.perf_counter() - t0
+    # plain per-instance sweep on the same jobs (device buffers, one job at a time)
+    plain_idx = list(range(0, len(bag), max(1, len(bag) // args.plain_jobs)))[:args.plain_jobs]
+    t_plain = 0.0
+    plain_best = {}
+    for k in plain_idx:
+        j = bag[k]
+        N = pbit.pbit_problem_spins(ctx.ctx, probs[k])
+        d = torch.empty((j["replicas"], N), dtype=torch.int8, device="cuda:0")
+        e = torch.empty(j["replicas"], dtype=torch.int64, device="cuda:0")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pbit.pbit_anneal_dev(ctx.ctx, probs[k], j["beta"], j["replicas"], j["seed"], d, d_energies=e)
+        torch.cuda.synchronize()
+        t_plain += time.perf_counter() - t0
+        plain_best[k] = int(e.min().item())
+    same = all(plain_best[k] == outs[k].best_energy for k in plain_idx)
+    plain_per_job = t_plain / len(plain_idx)
+    res = {
+        "metric": "anneals/s (mixed bag, batched persistent kernels)",
+        "value": len(bag) / t_batch,
+        "unit": "anneals/s",
+        "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": t_batch * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int8", "data": "synthetic",
+        "config": {"workload": "mixed bag of %d jobs: 128 EA cubes L in {8,...,24}, 128 bicliques n in [64,1024], "
+                               "replicas 32..512, sweeps 1000..5000, bag seed %d" % (len(bag), args.bag_seed),
+                   "updates_per_s": updates / t_batch,
+                   "plain_per_instance_anneals_per_s": 1.0 / plain_per_job,
+                   "plain_jobs_timed": len(plain_idx),
+                   "speedup_vs_plain": plain_per_job * len(bag) / t_batch,
+                   "plain_and_batched_best_energies_equal": same},
+    }
+    print(json.dumps(res), flush=True)
+    ctx.close()
+
+
+def serve_pool(n, seed):
+    """Serving instances: as the mixed bag, widened to cubes L <= 32 and bicliques n <= 2048."""
+    import synth
+    return synth.mixed_bag(seed=seed, n_instances=n, ea_sides=tuple(range(8, 33, 2)), n_range=(64, 2048))
+
+
+def serve_bench(args, pbit, torch):
+    """Poisson arrivals of anneal jobs with a target energy (the best of 64
+    replicas of the same schedule plus 1 %), served by continuous batching."""
+    import numpy as np
+    import synth
+    pool = serve_pool(args.pool, seed=11)
+    ctx = pbit.Context(0)
+    probs = [pbit.load_instance(ctx.ctx, j["instance"]) for j in pool]
+    Ns = [pbit.pbit_problem_spins(ctx.ctx, p) for p in probs]
+    # reference: best of 64 replicas on the GPU path (bit-identical to the oracle)
+    refs = pbit.pbit_anneal_batch(ctx.ctx, [dict(problem=p, beta=j["beta"], n_replicas=64, seed=7777)
+                                            for p, j in zip(probs, pool)], want_spins=False)
+    e_ref = [r.best_energy for r in refs]
+    targets = [e + int(abs(e) * 0.01) for e in e_ref]
+    arrivals = synth.poisson_arrivals(args.rate, args.duration, seed=int(args.rate))
+    rng = np.random.default_rng(int(args.rate) + 1)
+    which = rng.integers(0, len(pool), size=len(arrivals))
+    pending = {}
+    lat, residual, reached = [], [], 0
+    rejected = 0
+    t0 = time.perf_counter()
+    k = 0
+    while k < len(arrivals) or pending:
+        now = time.perf_counter() - t0
+        while k < len(arrivals) and arrivals[k] <= now:
+            q = int(which[k])
+            j = pool[q]
+            try:
+                jid = pbit.pbit_submit(ctx.ctx, probs[q], j["beta"], j["replicas"], seed=k + 1, target=targets[q])
+                pending[jid] = (arrivals[k], q, j)
+            except pbit.PbitError as e:
+                if e.code != pbit.PBIT_E_BUSY:
+                    raise
+                rejected += 1
+            k += 1
+        for jid in list(pending):
+            t_arr, q, j = pending[jid]
+            out = pbit.pbit_poll(ctx.ctx, jid, j["replicas"], Ns[q], len(j["beta"]), want_spins=False)
+            if out is not None:
+                lat.append(time.perf_counter() - t0 - t_arr)
+                residual.append((out.best_energy - e_ref[q]) / abs(e_ref[q]))
+                reached += int(out.best_energy <= targets[q])
+                del pending[jid]
+        if not pending and k < len(arrivals):
+            time.sleep(max(0.0, min(arrivals[k] - (time.perf_counter() - t0), 0.01)))
+    makespan = time.perf_counter() - t0
+    lat_ms = np.asarray(lat) * 1e3
+    res = {
+        "metric": "anneals/s at <= 1% residual energy (Poisson serving, continuous batching)",
+        "value": len(lat) / makespan,
+        "unit": "anneals/s",
+        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": makespan * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int8", "data": "synthetic",
+        "config": {"workload": "Poisson arrivals at %.0f jobs/s for %.0f s; jobs from a pool of %d instances "
+                               "(EA cubes L <= 32, bicliques n <= 2048, 32..512 replicas, 1000..5000 sweeps); "
+                               "target = best of 64 replicas + 1 %%" % (args.rate, args.duration, len(pool)),
+                   "offered": int(len(arrivals)), "rejected_busy": rejected, "completed": len(lat),
+                   "reached_target": reached,
+                   "p50_latency_ms": float(np.percentile(lat_ms, 50)) if len(lat) else None,
+                   "p99_latency_ms": float(np.percentile(lat_ms, 99)) if len(lat) else None,
+                   "mean_residual": float(np.mean(residual)) if residual else None},
+    }
+    print(json.dumps(res), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="ea32", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="ea32", choices=sorted(WORKLOADS) + ["mixed", "serve"])
+    ap.add_argument("--bag-size", type=int, default=256)
+    ap.add_argument("--bag-seed", type=int, default=0)
+    ap.add_argument("--plain-jobs", type=int, default=32, help="jobs of the bag timed through the per-instance path")
+    ap.add_argument("--rate", type=float, default=200.0, help="serve: Poisson arrival rate (jobs/s)")
+    ap.add_argument("--duration", type=float, default=20.0, help="serve: arrival window (s)")
+    ap.add_argument("--pool", type=int, default=64, help="serve: distinct instances jobs are drawn from")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="oracle sample budget (0 = skip)")
     ap.add_argument("--profile-every", type=int, default=8, help="bracket every k-th half-sweep with HIP events")
     ap.add_argument("--sweeps", type=int, default=0, help="run only the first k sweeps of the schedule (profiling)")
@@ -132,6 +261,13 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": nbytes, "copies": 5}))
+        return
+
+    if args.workload == "mixed":
+        mixed_bag_bench(args, pbit, torch)
+        return
+    if args.workload == "serve":
+        serve_bench(args, pbit, torch)
         return
 
     w = WORKLOADS[args.workload]

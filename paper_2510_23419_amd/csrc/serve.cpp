@@ -47,8 +47,6 @@ struct BJob {
     std::vector<int32_t> energy;  // latest per-replica energies
     std::vector<int64_t> etrace;  // [trace_len][R]
     int trace_len = 0, trace_cap = 0;
-    std::vector<int8_t> spins;    // final spins [R][N] (host), kept until polled
-    bool want_spins = true;
     pbit_result *user = nullptr;  // batch API: result filled at completion
 };
 
@@ -371,18 +369,9 @@ static int harvest(pbit_ctx *ctx, ServeState &s)
         }
         const bool hit = j.d.has_target && *std::min_element(j.energy.begin(), j.energy.end()) <= j.d.target_energy;
         if (hit || j.s_done >= j.S) {
+            // the job's device state stays until it is polled (spins are read back only if asked for)
             j.finished = true;
             j.sweeps_done = j.s_done;
-            if (j.want_spins) {
-                const size_t tile_bytes =
-                    j.kind == PBIT_EA3D ? (size_t)4 * j.N : (size_t)j.rs * (j.P->bq.na_p + j.P->bq.nb_p);
-                std::vector<int8_t> tl((size_t)j.tiles * tile_bytes);
-                e = hipMemcpy(tl.data(), j.d_state, tl.size(), hipMemcpyDeviceToHost);
-                if (e != hipSuccess) return device_fail(ctx, e, "spin readback");
-                j.spins.resize((size_t)j.R * j.N);
-                tiles_to_rows(j, tl.data(), j.spins.data());
-            }
-            release(ctx, j);
         }
     }
     s.running.erase(std::remove_if(s.running.begin(), s.running.end(), [](BJob *j) { return j->finished; }),
@@ -445,9 +434,18 @@ static int new_job(pbit_ctx *ctx, ServeState &s, uint64_t problem, const pbit_an
     return PBIT_OK;
 }
 
-static void fill_result(const BJob &j, pbit_result *res)
+// Copy a finished job's results out and release its device memory.
+static int fill_result(pbit_ctx *ctx, BJob &j, pbit_result *res)
 {
-    if (res->spins && !j.spins.empty()) std::memcpy(res->spins, j.spins.data(), j.spins.size());
+    if (res && res->spins && j.d_state) {
+        const size_t tile_bytes = j.kind == PBIT_EA3D ? (size_t)4 * j.N : (size_t)j.rs * (j.P->bq.na_p + j.P->bq.nb_p);
+        std::vector<int8_t> tl((size_t)j.tiles * tile_bytes);
+        hipError_t e = hipMemcpy(tl.data(), j.d_state, tl.size(), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return device_fail(ctx, e, "spin readback");
+        tiles_to_rows(j, tl.data(), res->spins);
+    }
+    release(ctx, j);
+    if (!res) return PBIT_OK;
     int best = 0;
     for (int r = 0; r < j.R; ++r) {
         if (res->energies) res->energies[r] = j.energy[r];
@@ -461,6 +459,7 @@ static void fill_result(const BJob &j, pbit_result *res)
         for (int k = 0; k < n; ++k)
             for (int r = 0; r < j.R; ++r) res->energy_trace[(size_t)k * j.R + r] = j.etrace[(size_t)k * j.R + r];
     res->trace_len = res->energy_trace ? n : 0;
+    return PBIT_OK;
 }
 
 }  // namespace pbit
@@ -511,9 +510,9 @@ extern "C" int pbit_poll(pbit_ctx *ctx, uint64_t job, pbit_result *result)
         if (rc) return rc;
         BJob &j = *it->second;
         if (!j.finished) return PBIT_PENDING;
-        if (result) fill_result(j, result);
+        rc = fill_result(ctx, j, result);
         s.jobs.erase(it);
-        return PBIT_OK;
+        return rc;
     } catch (...) {
         return fail(PBIT_E_ARG, "pbit_poll: internal error");
     }
@@ -563,7 +562,6 @@ extern "C" int pbit_anneal_batch(pbit_ctx *ctx, const pbit_batch_job *jobs, int3
                 }
                 return rc;
             }
-            j->want_spins = jobs[k].result->spins != nullptr;
             j->user = jobs[k].result;
             mine.push_back(j);
         }
@@ -574,11 +572,13 @@ extern "C" int pbit_anneal_batch(pbit_ctx *ctx, const pbit_batch_job *jobs, int3
             int rc = step(ctx, s, true);
             if (rc) return rc;
         }
+        int frc = PBIT_OK;
         for (BJob *m : mine) {
-            fill_result(*m, m->user);
+            const int rc = fill_result(ctx, *m, m->user);
+            if (rc && frc == PBIT_OK) frc = rc;
             s.jobs.erase(m->id);
         }
-        return PBIT_OK;
+        return frc;
     } catch (const std::bad_alloc &) {
         return fail(PBIT_E_NOMEM, "pbit_anneal_batch: host allocation failed");
     } catch (...) {
