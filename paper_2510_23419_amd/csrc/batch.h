@@ -42,7 +42,7 @@ struct WorkItem {
 };
 
 constexpr int kEaTileThreads = 512;
-constexpr int kBqTileThreads = 256;
+constexpr int kBqTileThreads = 512;
 
 // Launch a persistent kernel over `n_items` items; `counter` (device int,
 // zeroed by the caller) hands out item indices.

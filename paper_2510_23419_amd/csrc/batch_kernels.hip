@@ -189,6 +189,23 @@ __global__ __launch_bounds__(kEaTileThreads) void k_ea_tiles(const EaJobDev *__r
 // Each half-sweep is an MFMA product of the LDS spin rows with the couplings
 // streamed from global memory (L2-resident, shared by all tiles of the job),
 // followed by the decision epilogue writing the new side into LDS.
+constexpr int kRing = 4;  // K-units of J fragments in flight per site block
+
+// 4 x 4 byte transpose across a quad of lanes: lane u holds bytes M[u][0..3]
+// and receives M[0..3][u].  Two exchanges (partners u ^ 1, then u ^ 2), each a
+// DPP quad permutation and one byte permute.
+__device__ __forceinline__ uint32_t quad_transpose(uint32_t d, int u)
+{
+    // v_perm_b32 selects bytes of {src0:src1} as a 64-bit value: selector byte
+    // values 0..3 pick src1 bytes, 4..7 pick src0 bytes
+    const uint32_t t = (uint32_t)__builtin_amdgcn_mov_dpp((int)d, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+    // even u: (d0, t0, d2, t2); odd u: (t1, d1, t3, d3); here src0 = t, src1 = d
+    const uint32_t d1 = __builtin_amdgcn_perm(t, d, (u & 1) ? 0x03070105u : 0x06020400u);
+    const uint32_t t2 = (uint32_t)__builtin_amdgcn_mov_dpp((int)d1, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+    // u < 2: (d1_0, d1_1, t2_0, t2_1); u >= 2: (t2_2, t2_3, d1_2, d1_3)
+    return __builtin_amdgcn_perm(t2, d1, (u & 2) ? 0x03020706u : 0x05040100u);
+}
+
 template <int RB>
 __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__restrict__ jobs,
                                                              const WorkItem *__restrict__ items,
@@ -253,26 +270,43 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
                 const int8_t *Jx = side == 0 ? jb.J : jb.JT;
                 const int8_t *hs = side == 0 ? jb.hA : jb.hB;
                 const uint32_t site_base = side == 0 ? 0u : (uint32_t)na;
+                // one 32-site block per wave at a time; its J fragments stream from
+                // global memory through a ring kRing K-units (32 bytes) ahead
+                const int nku = ko / 32;
                 for (int blk = wave; blk < ns_p / 32; blk += kBqTileThreads / 64) {
                     const int site = blk * 32 + ln;
-                    const int8_t *brow = Jx + (size_t)site * ko + 16 * kg;
+                    const int8_t *br = Jx + (size_t)site * ko + 16 * kg;
+                    v4i ring[kRing];
+#pragma unroll
+                    for (int u = 0; u < kRing; ++u) ring[u] = *reinterpret_cast<const v4i *>(br + 32 * min(u, nku - 1));
                     v16i acc[RB];
 #pragma unroll
                     for (int rb = 0; rb < RB; ++rb) acc[rb] = v16i{0};
-                    for (int k = 0; k < ko; k += 64) {
-                        const v4i b0 = *reinterpret_cast<const v4i *>(brow + k);
-                        const v4i b1 = *reinterpret_cast<const v4i *>(brow + k + 32);
+                    const int8_t *abase = sp + ln * pitch + in_col + 16 * kg;
+                    for (int kb = 0; kb < nku; kb += kRing) {
 #pragma unroll
-                        for (int rb = 0; rb < RB; ++rb) {
-                            const int8_t *arow = sp + (rb * 32 + ln) * pitch + in_col + 16 * kg + k;
-                            acc[rb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(*reinterpret_cast<const v4i *>(arow),
-                                                                            b0, acc[rb], 0, 0, 0);
-                            acc[rb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
-                                *reinterpret_cast<const v4i *>(arow + 32), b1, acc[rb], 0, 0, 0);
+                        for (int u = 0; u < kRing; ++u) {
+                            const int ku = kb + u;
+                            if (ku < nku) {
+                                const v4i b = ring[u];
+                                ring[u] = *reinterpret_cast<const v4i *>(br + 32 * min(ku + kRing, nku - 1));
+#pragma unroll
+                                for (int rb = 0; rb < RB; ++rb) {
+                                    const v4i a = *reinterpret_cast<const v4i *>(abase + rb * 32 * pitch + 32 * ku);
+                                    acc[rb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, acc[rb], 0, 0, 0);
+                                }
+                            }
                         }
                     }
+                    // decisions; the four replicas of a group are packed into one dword,
+                    // then transposed across the lane quad (sites s..s+3) so that each
+                    // lane writes four consecutive sites of one replica row.  Padding
+                    // sites may take any value: their couplings and fields are zero
+                    // and they are never returned.
                     const int hval = hs[site];  // site < ns_p: padded fields are zero
                     const bool site_ok = site < ns;
+                    const int u4 = ln & 3;
+                    const int quad_col = out_col + site - u4;
 #pragma unroll
                     for (int rb = 0; rb < RB; ++rb) {
 #pragma unroll
@@ -280,17 +314,17 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
                             const int r4 = rb * 32 + 8 * q + 4 * kg;  // first replica of the group in the tile
                             const Block4 b = philox(site_base + (uint32_t)site, t, rg0 + (uint32_t)(r4 >> 2),
                                                     kDomainSweep, jb.k0, jb.k1);
+                            uint32_t packed = 0;
 #pragma unroll
                             for (int p = 0; p < 4; ++p) {
                                 const int I = acc[rb][4 * q + p] + hval;
                                 const int a = min(I >= 0 ? I : -I, top);
                                 const int8_t m = decide(I, T[a], b.w[p]);
-                                if (site_ok) {
-                                    sp[(r4 + p) * pitch + out_col + site] = m;
-                                    // energy after the last side-B update: E = -sum_b m_b I_b - sum_a h_a m_a
-                                    if (side == 1 && last) atomicAdd(&eacc[r4 + p], -(int)m * I);
-                                }
+                                packed |= (uint32_t)(uint8_t)m << (8 * p);
+                                // energy after the last side-B update: E = -sum_b m_b I_b - sum_a h_a m_a
+                                if (side == 1 && last && site_ok) atomicAdd(&eacc[r4 + p], -(int)m * I);
                             }
+                            *reinterpret_cast<uint32_t *>(sp + (r4 + u4) * pitch + quad_col) = quad_transpose(packed, u4);
                         }
                     }
                 }
