@@ -16,10 +16,14 @@
  *   - beta follows a caller-given schedule, one value per sweep (Sec. 1.3.1),
  *     over many independent replicas (Sec. 1.3.3).
  *
- * Two problem kinds are supported, both two-coloured:
+ * Three problem kinds are supported:
  *   PBIT_EA3D      periodic 3D Edwards-Anderson cube (Sec. 2), checkerboard
  *                  colouring (x + y + z) mod 2; every side even and >= 2;
- *   PBIT_BICLIQUE  complete bipartite K_{na,nb} (Sec. 3), side A colour 0.
+ *   PBIT_BICLIQUE  complete bipartite K_{na,nb} (Sec. 3), side A colour 0;
+ *   PBIT_GRAPH     any sparse graph given as a bond list, with k update groups
+ *                  from a caller colouring or the greedy colouring of Sec. 1.2.2
+ *                  (odd cubes and general QUBOs, Sec. 4.2); a sweep visits the
+ *                  colour classes in ascending order.
  *
  * Determinism.  Every result is a pure function of (problem, beta schedule,
  * sweep range, replica range, seed, initial spins).  Randomness is
@@ -78,7 +82,7 @@ enum {
     PBIT_E_UNSUPPORTED = -8  /* valid request this build does not handle */
 };
 
-enum { PBIT_EA3D = 1, PBIT_BICLIQUE = 2 };
+enum { PBIT_EA3D = 1, PBIT_BICLIQUE = 2, PBIT_GRAPH = 3 };
 
 typedef struct pbit_ctx pbit_ctx;
 
@@ -108,6 +112,31 @@ typedef struct {
 /* Validate and upload a problem; writes an opaque handle to *problem_out.
  * Errors: E_ARG, E_COLOURING (odd or zero EA side), E_RANGE, E_NOMEM, E_DEVICE. */
 int pbit_load_problem(pbit_ctx *ctx, const pbit_problem_desc *desc, uint64_t *problem_out);
+
+/* A general sparse graph (Sec. 1.2.2, Sec. 4.2).  Bond b joins bond_i[b] and
+ * bond_j[b] (distinct, in [0, n_spins)) with coupling bond_J[b]; several bonds
+ * may join the same pair and then add up.  colour[n_spins] (values below
+ * n_colours) must be a proper colouring, or NULL for the greedy colouring:
+ * vertices in ascending order each take the smallest colour none of their
+ * already coloured neighbours has (at most max degree + 1 colours).  Every
+ * vertex may have at most 127 bonds (E_UNSUPPORTED otherwise). */
+typedef struct {
+    int32_t n_spins;
+    int32_t n_bonds;
+    const int32_t *bond_i;
+    const int32_t *bond_j;
+    const int8_t *bond_J;   /* in {-1, 0, +1} */
+    const int8_t *h;        /* [n_spins] or NULL */
+    const uint8_t *colour;  /* [n_spins] or NULL */
+    int32_t n_colours;      /* with colour: number of classes (1..255) */
+} pbit_graph_desc;
+
+/* Validate and upload a general graph; errors as pbit_load_problem. */
+int pbit_load_graph(pbit_ctx *ctx, const pbit_graph_desc *desc, uint64_t *problem_out);
+
+/* The colouring a problem's sweep uses: colour_out[N] (or NULL) and the
+ * number of colour classes. */
+int pbit_problem_colouring(pbit_ctx *ctx, uint64_t problem, uint8_t *colour_out, int32_t *n_colours_out);
 
 /* Release a problem's device memory.  E_BUSY while a job still uses it. */
 int pbit_unload_problem(pbit_ctx *ctx, uint64_t problem);
@@ -227,6 +256,11 @@ int pbit_profile_read(pbit_ctx *ctx, int32_t kind, double *total_ms, int64_t *la
 /* The uint32 minority-threshold table Tm[s][a], s < S, a <= A, as the library
  * builds it on the host for the device (see the decision rule above). */
 int pbit_threshold_table(const double *beta, int32_t S, int32_t A, uint32_t *out);
+
+/* The greedy colouring pbit_load_graph uses when no colouring is given
+ * (host only).  Writes colour[n] and the number of colours. */
+int pbit_greedy_colouring(int32_t n, int32_t n_bonds, const int32_t *bond_i, const int32_t *bond_j, uint8_t *colour,
+                          int32_t *n_colours);
 
 /* Library version string. */
 const char *pbit_version(void);

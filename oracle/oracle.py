@@ -162,6 +162,33 @@ def biclique_graph(na, nb, J, h=None) -> Graph:
     return Graph(na + nb, a_idx.reshape(-1), na + b_idx.reshape(-1), J.reshape(-1), h, colour, 2)
 
 
+def graph_from_bonds(n, bond_i, bond_j, bond_J, h=None, colour=None, n_colours=None) -> Graph:
+    """General graph; without a colouring, the greedy colouring of the paper
+    (Sec. 1.2.2): vertices in ascending order, smallest free colour."""
+    if colour is None:
+        colour, n_colours = greedy_colouring(n, bond_i, bond_j)
+    return Graph(n, bond_i, bond_j, bond_J, h, colour, n_colours)
+
+
+def greedy_colouring(n, bond_i, bond_j):
+    """Colour vertices 0..n-1 in order, each with the smallest colour not used
+    by an already coloured neighbour.  Returns (colour[n], number of colours)."""
+    nbrs = [[] for _ in range(n)]
+    for a, b in zip(np.asarray(bond_i).tolist(), np.asarray(bond_j).tolist()):
+        nbrs[a].append(b)
+        nbrs[b].append(a)
+    colour = np.zeros(n, np.uint8)
+    used = 0
+    for v in range(n):
+        taken = {int(colour[u]) for u in nbrs[v] if u < v}
+        c = 0
+        while c in taken:
+            c += 1
+        colour[v] = c
+        used = max(used, c + 1)
+    return colour, used
+
+
 # ---------------------------------------------------------------- energy / anneal
 
 def energy(g: Graph, spins) -> np.ndarray:

@@ -1,0 +1,115 @@
+// graph_kernels.hip — general sparse graphs with k update groups (paper Sec. 1.2.2
+// greedy colouring; Sec. 4.2 general QUBOs; odd cubes need more than two groups).
+//
+// Spins use the cube's layout, int8 [N][Rp] with replicas fastest, and one
+// launch updates one colour class: a thread takes one site of the class and 16
+// replicas, gathers its neighbours' 16-byte replica rows through the CSR
+// adjacency, and counts negative products bytewise (degree <= 127 keeps the
+// byte sums below 256).  Classes are visited in ascending colour order.
+#include "device.h"
+#include "internal.h"
+
+namespace pbit {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kMaxOff = kGraphMaxDegree + 1;          // |I| <= degree + |h|
+constexpr int kSlots = 2 * kMaxOff + 1;
+
+__global__ __launch_bounds__(kThreads) void k_graph_halfsweep(int8_t *__restrict__ spins,
+                                                              const int32_t *__restrict__ class_sites, int n_class,
+                                                              const int32_t *__restrict__ adj_start,
+                                                              const int32_t *__restrict__ adj_site,
+                                                              const uint8_t *__restrict__ adj_code,
+                                                              const int16_t *__restrict__ base,
+                                                              const uint32_t *__restrict__ trow, int width, int Rp,
+                                                              uint32_t sweep, uint32_t rq0, uint32_t k0, uint32_t k1)
+{
+    // decision table over I in [-kMaxOff, kMaxOff]: threshold, xor mask, minority and majority byte
+    __shared__ uint4 tab[kSlots];
+    for (int k = threadIdx.x; k < kSlots; k += kThreads) {
+        const int I = k - kMaxOff;
+        const int a = min(I >= 0 ? I : -I, width - 1);
+        const bool pos = I >= 0;
+        tab[k] = make_uint4(trow[a], pos ? 0xFFFFFFFFu : 0u, pos ? 0xFFu : 0x01u, pos ? 0x01u : 0xFFu);
+    }
+    __syncthreads();
+    const int chunks = Rp / 16;
+    const int64_t gid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (gid >= (int64_t)n_class * chunks) return;
+    const int q = (int)(gid % chunks);
+    const int i = class_sites[gid / chunks];
+    uint32_t cnt[4] = {0u, 0u, 0u, 0u};
+    for (int e = adj_start[i]; e < adj_start[i + 1]; ++e) {
+        const uint8_t c = adj_code[e];  // bit 0: J != 0, bit 1: J == -1
+        const uint32_t keep = (c & 1u) * 0x02020202u, flip = ((c >> 1) & 1u) * 0x02020202u;
+        const uint4 v = *reinterpret_cast<const uint4 *>(spins + (size_t)adj_site[e] * Rp + 16 * q);
+        cnt[0] += (v.x & keep) ^ flip;
+        cnt[1] += (v.y & keep) ^ flip;
+        cnt[2] += (v.z & keep) ^ flip;
+        cnt[3] += (v.w & keep) ^ flip;
+    }
+    const int b0 = (int)base[i] + kMaxOff;  // table index for I = nnz + h (no negative products)
+    uint32_t out[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const Block4 b = philox((uint32_t)i, sweep, rq0 + 4u * (uint32_t)q + (uint32_t)k, kDomainSweep, k0, k1);
+        uint32_t packed = 0;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const uint4 e = tab[b0 - (int)((cnt[k] >> (8 * p)) & 0xFFu)];  // I = base - c2
+            packed |= ((b.w[p] ^ e.y) < e.x ? e.z : e.w) << (8 * p);
+        }
+        out[k] = packed;
+    }
+    *reinterpret_cast<uint4 *>(spins + (size_t)i * Rp + 16 * q) = make_uint4(out[0], out[1], out[2], out[3]);
+}
+
+// E[r] += -sum over a chunk of bonds of J m_i m_j, plus -h_i m_i for a chunk of sites
+__global__ __launch_bounds__(kThreads) void k_graph_energy(const int8_t *__restrict__ spins,
+                                                           const int32_t *__restrict__ bi,
+                                                           const int32_t *__restrict__ bj,
+                                                           const int8_t *__restrict__ bJ, int n_bonds,
+                                                           const int8_t *__restrict__ h, int n, int Rp, int R,
+                                                           int chunk, int32_t *__restrict__ E)
+{
+    const int r = blockIdx.x * kThreads + threadIdx.x;
+    if (r >= R) return;
+    const int64_t b0 = (int64_t)blockIdx.y * chunk;
+    int32_t e = 0;
+    for (int64_t b = b0; b < b0 + chunk && b < n_bonds; ++b)
+        e -= bJ[b] * spins[(size_t)bi[b] * Rp + r] * spins[(size_t)bj[b] * Rp + r];
+    if (h)
+        for (int64_t i = b0; i < b0 + chunk && i < n; ++i) e -= h[i] * spins[(size_t)i * Rp + r];
+    atomicAdd(E + r, e);
+}
+
+}  // namespace
+
+hipError_t graph_halfsweep(const GraphView &g, int colour, int8_t *spins, int Rp, const uint32_t *trow, int width,
+                           uint32_t sweep, uint32_t rq0, Key key, hipStream_t st)
+{
+    if (width < 1 || width > kMaxOff + 1 || Rp % 16 != 0) return hipErrorInvalidValue;
+    const int n_class = g.class_start[colour + 1] - g.class_start[colour];
+    if (n_class == 0) return hipSuccess;
+    const int64_t work = (int64_t)n_class * (Rp / 16);
+    hipLaunchKernelGGL(k_graph_halfsweep, dim3((unsigned)((work + kThreads - 1) / kThreads)), dim3(kThreads), 0, st,
+                       spins, g.class_sites + g.class_start[colour], n_class, g.adj_start, g.adj_site, g.adj_code,
+                       g.base, trow, width, Rp, sweep, rq0, key.k0, key.k1);
+    return hipGetLastError();
+}
+
+hipError_t graph_energy(const GraphView &g, const int8_t *spins, int Rp, int R, int32_t *E, hipStream_t st)
+{
+    hipError_t e = fill_i32(E, R, 0, st);
+    if (e != hipSuccess) return e;
+    const int64_t items = g.n_bonds > g.n ? g.n_bonds : g.n;
+    const int chunk = (int)((items + 65534) / 65535 > 256 ? (items + 65534) / 65535 : 256);
+    dim3 grid((unsigned)((R + kThreads - 1) / kThreads), (unsigned)((items + chunk - 1) / chunk));
+    hipLaunchKernelGGL(k_graph_energy, grid, dim3(kThreads), 0, st, spins, g.bi, g.bj, g.bJ, g.n_bonds, g.h, g.n,
+                       Rp, R, chunk, E);
+    return hipGetLastError();
+}
+
+}  // namespace pbit

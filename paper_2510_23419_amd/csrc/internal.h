@@ -21,6 +21,22 @@ struct EaView {
     const int8_t *h;       // [N] or null
 };
 
+// General sparse graph with k colour classes (greedy colouring by default).
+constexpr int kGraphMaxDegree = 127;  // bytewise counts of negative products stay below 256
+
+struct GraphView {
+    int n, n_bonds, n_colours, max_degree;
+    const int32_t *class_start;  // host [n_colours + 1]: class c is class_sites[class_start[c] .. class_start[c+1])
+    const int32_t *class_sites;  // device [n]: sites grouped by colour, ascending inside a class
+    const int32_t *adj_start;    // device [n + 1] CSR offsets
+    const int32_t *adj_site;     // device [2 n_bonds] neighbours
+    const uint8_t *adj_code;     // device [2 n_bonds]: bit 0 J != 0, bit 1 J == -1
+    const int16_t *base;         // device [n]: nnz(J) + h, in [-1, kGraphMaxDegree + 1]
+    const int32_t *bi, *bj;      // device bond list
+    const int8_t *bJ;
+    const int8_t *h;             // device [n] or null
+};
+
 struct BqView {
     int na, nb;      // real side sizes
     int na_p, nb_p;  // padded to kBqPad (extra couplings and spins are zero)
@@ -60,6 +76,11 @@ hipError_t bq_to_rows(const BqView &p, const int8_t *MA, const int8_t *MB, int8_
 hipError_t bq_halfsweep(const BqView &p, int side, int8_t *MA, int8_t *MB, int R, int Rp, const uint32_t *trow,
                         int width, uint32_t sweep, uint32_t rq0, Key key, hipStream_t st, BqVariant variant);
 hipError_t bq_energy(const BqView &p, const int8_t *MA, const int8_t *MB, int R, int Rp, int32_t *E, hipStream_t st);
+
+// ---- general graphs; spins are device [N][Rp] like the cube ----------------
+hipError_t graph_halfsweep(const GraphView &g, int colour, int8_t *spins, int Rp, const uint32_t *trow, int width,
+                           uint32_t sweep, uint32_t rq0, Key key, hipStream_t st);
+hipError_t graph_energy(const GraphView &g, const int8_t *spins, int Rp, int R, int32_t *E, hipStream_t st);
 
 // ---- misc ---------------------------------------------------------------
 hipError_t fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);

@@ -343,6 +343,129 @@ static int load_biclique(pbit_ctx *ctx, const pbit_problem_desc *d, Problem &p)
     return PBIT_OK;
 }
 
+// Greedy colouring (Sec. 1.2.2): vertices in ascending order take the
+// smallest colour none of their already coloured neighbours has.
+int greedy_colouring(int n, int n_bonds, const int32_t *bi, const int32_t *bj, uint8_t *colour, int *n_colours)
+{
+    std::vector<int32_t> start((size_t)n + 1, 0), nbr((size_t)2 * n_bonds);
+    for (int b = 0; b < n_bonds; ++b) {
+        ++start[(size_t)bi[b] + 1];
+        ++start[(size_t)bj[b] + 1];
+    }
+    for (int i = 0; i < n; ++i) start[(size_t)i + 1] += start[i];
+    std::vector<int32_t> fill(start.begin(), start.end() - 1);
+    for (int b = 0; b < n_bonds; ++b) {
+        nbr[(size_t)fill[bi[b]]++] = bj[b];
+        nbr[(size_t)fill[bj[b]]++] = bi[b];
+    }
+    std::vector<int> seen(257, -1);
+    int used = 0;
+    for (int v = 0; v < n; ++v) {
+        for (int e = start[v]; e < start[(size_t)v + 1]; ++e) {
+            const int u = nbr[(size_t)e];
+            if (u < v) seen[colour[u]] = v;
+        }
+        int c = 0;
+        while (seen[c] == v) ++c;
+        if (c > 255) return fail(PBIT_E_UNSUPPORTED, "greedy colouring needs more than 256 colours");
+        colour[v] = (uint8_t)c;
+        used = std::max(used, c + 1);
+    }
+    *n_colours = n > 0 ? used : 0;
+    return PBIT_OK;
+}
+
+static int load_graph(pbit_ctx *ctx, const pbit_graph_desc *d, Problem &p)
+{
+    const int n = d->n_spins, nb = d->n_bonds;
+    if (n < 1 || nb < 0 || (nb > 0 && (!d->bond_i || !d->bond_j || !d->bond_J)))
+        return fail(PBIT_E_ARG, "graph: need n_spins >= 1 and bond arrays");
+    if ((int64_t)n * 16 > ((int64_t)1 << 31)) return fail(PBIT_E_UNSUPPORTED, "graph of %d spins is too large", n);
+    for (int b = 0; b < nb; ++b) {
+        if (d->bond_i[b] < 0 || d->bond_i[b] >= n || d->bond_j[b] < 0 || d->bond_j[b] >= n)
+            return fail(PBIT_E_ARG, "graph: bond %d joins a vertex outside [0, %d)", b, n);
+        if (d->bond_i[b] == d->bond_j[b]) return fail(PBIT_E_ARG, "graph: bond %d is a self-loop", b);
+    }
+    if (nb > 0 && !in_unit_range(d->bond_J, (size_t)nb)) return fail(PBIT_E_RANGE, "graph couplings must be in {-1, 0, +1}");
+    if (d->h && !in_unit_range(d->h, (size_t)n)) return fail(PBIT_E_RANGE, "fields must be in {-1, 0, +1}");
+    std::vector<int32_t> deg((size_t)n, 0);
+    for (int b = 0; b < nb; ++b) {
+        ++deg[d->bond_i[b]];
+        ++deg[d->bond_j[b]];
+    }
+    const int maxdeg = n > 0 ? *std::max_element(deg.begin(), deg.end()) : 0;
+    if (maxdeg > kGraphMaxDegree)
+        return fail(PBIT_E_UNSUPPORTED, "graph: a vertex has %d bonds (at most %d)", maxdeg, kGraphMaxDegree);
+    p.colour.assign((size_t)n, 0);
+    int ncol = 0;
+    if (d->colour) {
+        if (d->n_colours < 1 || d->n_colours > 255) return fail(PBIT_E_ARG, "graph: n_colours must be 1..255");
+        for (int i = 0; i < n; ++i)
+            if (d->colour[i] >= d->n_colours) return fail(PBIT_E_COLOURING, "graph: colour of vertex %d out of range", i);
+        for (int b = 0; b < nb; ++b)
+            if (d->colour[d->bond_i[b]] == d->colour[d->bond_j[b]])
+                return fail(PBIT_E_COLOURING, "graph: bond %d joins two vertices of colour %d", b, d->colour[d->bond_i[b]]);
+        std::copy(d->colour, d->colour + n, p.colour.begin());
+        ncol = d->n_colours;
+    } else {
+        int rc = greedy_colouring(n, nb, d->bond_i, d->bond_j, p.colour.data(), &ncol);
+        if (rc) return rc;
+    }
+    // CSR adjacency, per-site base = nnz + h, colour classes
+    std::vector<int32_t> start((size_t)n + 1, 0);
+    for (int i = 0; i < n; ++i) start[(size_t)i + 1] = start[i] + deg[i];
+    std::vector<int32_t> site((size_t)2 * nb);
+    std::vector<uint8_t> code((size_t)2 * nb);
+    std::vector<int32_t> fill(start.begin(), start.end() - 1);
+    std::vector<int16_t> base((size_t)n, 0);
+    int amax = 0;
+    for (int b = 0; b < nb; ++b) {
+        const int8_t J = d->bond_J[b];
+        const uint8_t c = (uint8_t)((J != 0 ? 1 : 0) | (J < 0 ? 2 : 0));
+        const int i = d->bond_i[b], j = d->bond_j[b];
+        site[(size_t)fill[i]] = j;
+        code[(size_t)fill[i]++] = c;
+        site[(size_t)fill[j]] = i;
+        code[(size_t)fill[j]++] = c;
+        if (J != 0) {
+            ++base[i];
+            ++base[j];
+        }
+    }
+    for (int i = 0; i < n; ++i) {
+        const int hv = d->h ? d->h[i] : 0;
+        amax = std::max(amax, base[i] + std::abs(hv));
+        base[i] = (int16_t)(base[i] + hv);
+    }
+    p.class_start.assign((size_t)ncol + 1, 0);
+    for (int i = 0; i < n; ++i) ++p.class_start[(size_t)p.colour[i] + 1];
+    for (int c = 0; c < ncol; ++c) p.class_start[(size_t)c + 1] += p.class_start[c];
+    std::vector<int32_t> cls((size_t)n), cfill(p.class_start.begin(), p.class_start.end() - 1);
+    for (int i = 0; i < n; ++i) cls[(size_t)cfill[p.colour[i]]++] = i;
+
+    void *dcls = nullptr, *dst = nullptr, *dsite = nullptr, *dcode = nullptr, *dbase = nullptr, *dbi = nullptr,
+         *dbj = nullptr, *dbJ = nullptr, *dh = nullptr;
+    int rc = upload(ctx, p, cls.data(), sizeof(int32_t) * cls.size(), &dcls);
+    if (rc == PBIT_OK) rc = upload(ctx, p, start.data(), sizeof(int32_t) * start.size(), &dst);
+    if (rc == PBIT_OK && nb > 0) rc = upload(ctx, p, site.data(), sizeof(int32_t) * site.size(), &dsite);
+    if (rc == PBIT_OK && nb > 0) rc = upload(ctx, p, code.data(), code.size(), &dcode);
+    if (rc == PBIT_OK) rc = upload(ctx, p, base.data(), sizeof(int16_t) * base.size(), &dbase);
+    if (rc == PBIT_OK && nb > 0) rc = upload(ctx, p, d->bond_i, sizeof(int32_t) * (size_t)nb, &dbi);
+    if (rc == PBIT_OK && nb > 0) rc = upload(ctx, p, d->bond_j, sizeof(int32_t) * (size_t)nb, &dbj);
+    if (rc == PBIT_OK && nb > 0) rc = upload(ctx, p, d->bond_J, (size_t)nb, &dbJ);
+    if (rc == PBIT_OK && d->h) rc = upload(ctx, p, d->h, (size_t)n, &dh);
+    if (rc != PBIT_OK) return rc;
+    p.kind = PBIT_GRAPH;
+    p.N = n;
+    p.amax = amax;
+    p.graph = GraphView{n, nb, ncol, maxdeg, p.class_start.data(), (const int32_t *)dcls, (const int32_t *)dst,
+                        (const int32_t *)dsite, (const uint8_t *)dcode, (const int16_t *)dbase, (const int32_t *)dbi,
+                        (const int32_t *)dbj, (const int8_t *)dbJ, (const int8_t *)dh};
+    // the cube's layout kernels (init, transposes) are reused with N = n
+    p.ea = EaView{0, 0, 0, (int64_t)n, nullptr, nullptr, nullptr};
+    return PBIT_OK;
+}
+
 Problem *find_problem(pbit_ctx *ctx, uint64_t handle)
 {
     auto it = ctx->problems.find(handle);
@@ -385,6 +508,71 @@ extern "C" int pbit_load_problem(pbit_ctx *ctx, const pbit_problem_desc *desc, u
         return fail(PBIT_E_NOMEM, "pbit_load_problem: host allocation failed");
     } catch (...) {
         return fail(PBIT_E_ARG, "pbit_load_problem: internal error");
+    }
+}
+
+extern "C" int pbit_load_graph(pbit_ctx *ctx, const pbit_graph_desc *desc, uint64_t *problem_out)
+{
+    try {
+        PBIT_ENTER(ctx);
+        if (!desc || !problem_out) return fail(PBIT_E_ARG, "pbit_load_graph: NULL argument");
+        Problem p;
+        int rc = load_graph(ctx, desc, p);
+        if (rc != PBIT_OK) {
+            free_problem(ctx, p);
+            return rc;
+        }
+        const uint64_t h = ((uint64_t)ctx->serial << 40) | (++ctx->next_handle);
+        auto it = ctx->problems.emplace(h, std::move(p)).first;
+        it->second.graph.class_start = it->second.class_start.data();  // the vector moved
+        *problem_out = h;
+        return PBIT_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(PBIT_E_NOMEM, "pbit_load_graph: host allocation failed");
+    } catch (...) {
+        return fail(PBIT_E_ARG, "pbit_load_graph: internal error");
+    }
+}
+
+extern "C" int pbit_problem_colouring(pbit_ctx *ctx, uint64_t problem, uint8_t *colour_out, int32_t *n_colours_out)
+{
+    PBIT_ENTER(ctx);
+    Problem *P = find_problem(ctx, problem);
+    if (!P) return fail(PBIT_E_HANDLE, "pbit_problem_colouring: unknown problem handle");
+    int ncol = 2;
+    if (P->kind == PBIT_GRAPH) {
+        ncol = P->graph.n_colours;
+        if (colour_out) std::copy(P->colour.begin(), P->colour.end(), colour_out);
+    } else if (colour_out) {
+        if (P->kind == PBIT_EA3D) {
+            const EaView &v = P->ea;
+            for (int64_t i = 0; i < P->N; ++i) {
+                const int64_t x = i % v.Lx, y = (i / v.Lx) % v.Ly, z = i / ((int64_t)v.Lx * v.Ly);
+                colour_out[i] = (uint8_t)((x + y + z) & 1);
+            }
+        } else {
+            for (int64_t i = 0; i < P->N; ++i) colour_out[i] = i < P->bq.na ? 0 : 1;
+        }
+    }
+    if (n_colours_out) *n_colours_out = ncol;
+    return PBIT_OK;
+}
+
+extern "C" int pbit_greedy_colouring(int32_t n, int32_t n_bonds, const int32_t *bond_i, const int32_t *bond_j,
+                                     uint8_t *colour, int32_t *n_colours)
+{
+    try {
+        if (n < 0 || n_bonds < 0 || !colour || !n_colours || (n_bonds > 0 && (!bond_i || !bond_j)))
+            return fail(PBIT_E_ARG, "pbit_greedy_colouring: bad arguments");
+        for (int b = 0; b < n_bonds; ++b)
+            if (bond_i[b] < 0 || bond_i[b] >= n || bond_j[b] < 0 || bond_j[b] >= n || bond_i[b] == bond_j[b])
+                return fail(PBIT_E_ARG, "pbit_greedy_colouring: bad bond %d", b);
+        int nc = 0;
+        int rc = greedy_colouring(n, n_bonds, bond_i, bond_j, colour, &nc);
+        *n_colours = nc;
+        return rc;
+    } catch (...) {
+        return fail(PBIT_E_NOMEM, "pbit_greedy_colouring: host allocation failed");
     }
 }
 
@@ -509,7 +697,7 @@ static int prepare(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, h
     ds.R = R;
     void *v = nullptr;
     int rc;
-    if (P.kind == PBIT_EA3D) {
+    if (P.kind == PBIT_EA3D || P.kind == PBIT_GRAPH) {
         ds.Rp = round_up(R, kEaRPad);
         rc = scratch(ctx, Slot::Spins, (size_t)P.N * ds.Rp, &v);
         if (rc) return rc;
@@ -559,12 +747,12 @@ static int prepare(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, h
         if (e != hipSuccess) return device_fail(ctx, e, "hipMemcpyAsync (init spins)");
         init_rows = ds.stage;
     }
+    const bool rowlayout = P.kind != PBIT_BICLIQUE;  // cube and graph share the [N][Rp] layout
     if (init_rows)
-        e = P.kind == PBIT_EA3D ? ea_from_rows(P.ea, init_rows, R, ds.spins, ds.Rp, st)
-                                : bq_from_rows(P.bq, init_rows, R, ds.MA, ds.MB, st);
+        e = rowlayout ? ea_from_rows(P.ea, init_rows, R, ds.spins, ds.Rp, st)
+                      : bq_from_rows(P.bq, init_rows, R, ds.MA, ds.MB, st);
     else
-        e = P.kind == PBIT_EA3D ? ea_init(P.ea, ds.spins, ds.Rp, rq0, key, st)
-                                : bq_init(P.bq, ds.MA, ds.MB, R, rq0, key, st);
+        e = rowlayout ? ea_init(P.ea, ds.spins, ds.Rp, rq0, key, st) : bq_init(P.bq, ds.MA, ds.MB, R, rq0, key, st);
     if (e != hipSuccess) return device_fail(ctx, e, "spin initialisation launch");
     return PBIT_OK;
 }
@@ -574,14 +762,17 @@ static hipError_t sweep(pbit_ctx *ctx, const Problem &P, DevState &ds, int s, ui
 {
     const uint32_t *row = ds.table + (size_t)s * ds.width;
     hipError_t e = hipSuccess;
-    for (int c = 0; c < 2 && e == hipSuccess; ++c) {
+    const int ncol = P.kind == PBIT_GRAPH ? P.graph.n_colours : 2;
+    for (int c = 0; c < ncol && e == hipSuccess; ++c) {
         int slot = -1;
-        if (ctx->prof_every > 0 && (2 * s + c) % ctx->prof_every == 0) {
+        if (ctx->prof_every > 0 && (ncol * s + c) % ctx->prof_every == 0) {
             e = prof_begin(ctx, P.kind, st, &slot);
             if (e != hipSuccess) return e;
         }
         if (P.kind == PBIT_EA3D)
             e = ea_halfsweep(P.ea, ds.spins, ds.Rp, c, row, ds.width, t, rq0, key, st);
+        else if (P.kind == PBIT_GRAPH)
+            e = graph_halfsweep(P.graph, c, ds.spins, ds.Rp, row, ds.width, t, rq0, key, st);
         else
             e = bq_halfsweep(P.bq, c, ds.MA, ds.MB, ds.R, ds.Rp, row, ds.width, t, rq0, key, st, ds.variant);
         if (e == hipSuccess) e = prof_end(ctx, slot, st);
@@ -591,14 +782,15 @@ static hipError_t sweep(pbit_ctx *ctx, const Problem &P, DevState &ds, int s, ui
 
 static hipError_t energies(const Problem &P, DevState &ds, hipStream_t st)
 {
+    if (P.kind == PBIT_GRAPH) return graph_energy(P.graph, ds.spins, ds.Rp, ds.R, ds.E32, st);
     return P.kind == PBIT_EA3D ? ea_energy(P.ea, ds.spins, ds.Rp, ds.R, ds.E32, st)
                                : bq_energy(P.bq, ds.MA, ds.MB, ds.R, ds.Rp, ds.E32, st);
 }
 
 static hipError_t to_rows(const Problem &P, DevState &ds, int8_t *dst, hipStream_t st)
 {
-    return P.kind == PBIT_EA3D ? ea_to_rows(P.ea, ds.spins, ds.Rp, dst, ds.R, st)
-                               : bq_to_rows(P.bq, ds.MA, ds.MB, dst, ds.R, st);
+    return P.kind != PBIT_BICLIQUE ? ea_to_rows(P.ea, ds.spins, ds.Rp, dst, ds.R, st)
+                                   : bq_to_rows(P.bq, ds.MA, ds.MB, dst, ds.R, st);
 }
 
 static int fetch_energies(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStream_t st, std::vector<int32_t> &out)

@@ -19,6 +19,9 @@ struct Problem {
     int amax = 0;  // largest possible |I|
     EaView ea{};
     BqView bq{};
+    GraphView graph{};
+    std::vector<int32_t> class_start;  // host copy behind graph.class_start
+    std::vector<uint8_t> colour;       // colouring used (graph problems)
     std::vector<void *> allocs;
     int jobs = 0;  // serving jobs that still reference the problem
 };
@@ -73,6 +76,8 @@ uint32_t minority_threshold(double beta, int a);
 int table_width(const double *beta, int S, int amax);
 void build_table(const double *beta, int S, int width, uint32_t *out);
 void serve_shutdown(pbit_ctx *ctx);
+int spins_in_range(const int8_t *s, size_t n);
+int greedy_colouring(int n, int n_bonds, const int32_t *bi, const int32_t *bj, uint8_t *colour, int *n_colours);
 hipError_t prof_begin(pbit_ctx *ctx, int kind, hipStream_t st, int *slot);
 hipError_t prof_end(pbit_ctx *ctx, int slot, hipStream_t st);
 hipError_t prof_harvest(pbit_ctx *ctx);

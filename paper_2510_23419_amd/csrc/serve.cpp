@@ -141,6 +141,7 @@ static int plan_job(pbit_ctx *ctx, BJob &j)
     j.S = j.d.n_sweeps;
     j.width = j.S > 0 ? table_width(j.beta.data(), j.S, P.amax) : 1;
     if (j.width > kMaxTableWidth) return fail(PBIT_E_UNSUPPORTED, "threshold rows of %d entries are too wide", j.width);
+    if (P.kind == PBIT_GRAPH) return fail(PBIT_E_UNSUPPORTED, "general graphs run through pbit_anneal only");
     if (P.kind == PBIT_EA3D) {
         if (ea_tile_lds(P.N) > (size_t)kMaxLdsTile || P.ea.Lx > 1024 || P.ea.Ly > 1024)
             return fail(PBIT_E_UNSUPPORTED, "cube of %lld sites is too large for a batched tile", (long long)P.N);

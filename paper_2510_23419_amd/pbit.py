@@ -28,12 +28,14 @@ PBIT_E_UNSUPPORTED = -8
 
 PBIT_EA3D = 1
 PBIT_BICLIQUE = 2
+PBIT_GRAPH = 3
 PBIT_CHECK_SWEEPS = 100
 
 EXPORTS = ("pbit_create", "pbit_destroy", "pbit_last_error", "pbit_bytes_in_use", "pbit_load_problem",
            "pbit_unload_problem", "pbit_problem_spins", "pbit_anneal", "pbit_anneal_dev", "pbit_energy",
            "pbit_submit", "pbit_poll", "pbit_progress", "pbit_threshold_table", "pbit_version",
-           "pbit_profile_enable", "pbit_profile_read", "pbit_anneal_batch", "pbit_serve_config")
+           "pbit_profile_enable", "pbit_profile_read", "pbit_anneal_batch", "pbit_serve_config",
+           "pbit_load_graph", "pbit_problem_colouring", "pbit_greedy_colouring")
 
 
 class PbitError(RuntimeError):
@@ -59,6 +61,12 @@ class Result(ctypes.Structure):  # noqa: E302
                 ("best_replica", ctypes.c_int32), ("sweeps_done", ctypes.c_int32),
                 ("energy_trace", ctypes.c_void_p), ("trace_cap", ctypes.c_int32), ("trace_len", ctypes.c_int32),
                 ("spin_trace", ctypes.c_void_p)]
+
+
+class GraphDesc(ctypes.Structure):
+    _fields_ = [("n_spins", ctypes.c_int32), ("n_bonds", ctypes.c_int32), ("bond_i", ctypes.c_void_p),
+                ("bond_j", ctypes.c_void_p), ("bond_J", ctypes.c_void_p), ("h", ctypes.c_void_p),
+                ("colour", ctypes.c_void_p), ("n_colours", ctypes.c_int32)]
 
 
 class BatchJob(ctypes.Structure):
@@ -101,6 +109,9 @@ def lib() -> ctypes.CDLL:
             "pbit_profile_read": ([P, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), i32], ctypes.c_int),
             "pbit_anneal_batch": ([P, ctypes.POINTER(BatchJob), i32], ctypes.c_int),
             "pbit_serve_config": ([P, i32, i32, i32], ctypes.c_int),
+            "pbit_load_graph": ([P, ctypes.POINTER(GraphDesc), ctypes.POINTER(u64)], ctypes.c_int),
+            "pbit_problem_colouring": ([P, u64, P, ctypes.POINTER(i32)], ctypes.c_int),
+            "pbit_greedy_colouring": ([i32, i32, P, P, P, ctypes.POINTER(i32)], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -161,8 +172,45 @@ def pbit_load_problem(ctx, kind: int, dims, J, h=None) -> int:
     return int(out.value)
 
 
+def pbit_load_graph(ctx, n_spins: int, bond_i, bond_j, bond_J, h=None, colour=None, n_colours: int = 0) -> int:
+    bi = np.ascontiguousarray(bond_i, dtype=np.int32)
+    bj = np.ascontiguousarray(bond_j, dtype=np.int32)
+    bJ = np.ascontiguousarray(bond_J, dtype=np.int8)
+    hh = None if h is None else np.ascontiguousarray(h, dtype=np.int8)
+    col = None if colour is None else np.ascontiguousarray(colour, dtype=np.uint8)
+    d = GraphDesc(int(n_spins), int(bi.size), bi.ctypes.data if bi.size else None, bj.ctypes.data if bj.size else None,
+                  bJ.ctypes.data if bJ.size else None, None if hh is None else hh.ctypes.data,
+                  None if col is None else col.ctypes.data, int(n_colours))
+    out = ctypes.c_uint64()
+    _check(lib().pbit_load_graph(ctx, ctypes.byref(d), ctypes.byref(out)))
+    del bi, bj, bJ, hh, col
+    return int(out.value)
+
+
+def pbit_problem_colouring(ctx, problem: int):
+    """(colour[N] uint8, number of colours) of a loaded problem."""
+    N = pbit_problem_spins(ctx, problem)
+    col = np.zeros(N, np.uint8)
+    nc = ctypes.c_int32()
+    _check(lib().pbit_problem_colouring(ctx, int(problem), _ptr(col), ctypes.byref(nc)))
+    return col, int(nc.value)
+
+
+def pbit_greedy_colouring(n: int, bond_i, bond_j):
+    bi = np.ascontiguousarray(bond_i, dtype=np.int32)
+    bj = np.ascontiguousarray(bond_j, dtype=np.int32)
+    col = np.zeros(int(n), np.uint8)
+    nc = ctypes.c_int32()
+    _check(lib().pbit_greedy_colouring(int(n), int(bi.size), _ptr(bi) if bi.size else None,
+                                       _ptr(bj) if bj.size else None, _ptr(col), ctypes.byref(nc)))
+    return col, int(nc.value)
+
+
 def load_instance(ctx, inst) -> int:
     """Load a problem dict as produced by the synthetic generators."""
+    if inst["kind"] == "graph":
+        return pbit_load_graph(ctx, inst["n"], inst["bond_i"], inst["bond_j"], inst["bond_J"], inst.get("h"),
+                               inst.get("colour"), inst.get("n_colours", 0))
     kind = PBIT_EA3D if inst["kind"] == "ea3d" else PBIT_BICLIQUE
     return pbit_load_problem(ctx, kind, inst["dims"], inst["J"], inst.get("h"))
 

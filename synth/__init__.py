@@ -118,3 +118,38 @@ def poisson_arrivals(rate: float, duration: float, seed: int) -> np.ndarray:
             break
         times.append(t)
     return np.asarray(times, dtype=np.float64)
+
+
+def ea_bond_list(inst):
+    """The cube as a general bond list: bond (i, i + e_d) with J[d][i], in the
+    order d-major over sites (the graph form of ea_instance; works for odd sides)."""
+    Lx, Ly, Lz = inst["dims"]
+    N = Lx * Ly * Lz
+    i = np.arange(N)
+    x, y, z = i % Lx, (i // Lx) % Ly, i // (Lx * Ly)
+    nbrs = [((x + 1) % Lx) + Lx * (y + Ly * z), x + Lx * (((y + 1) % Ly) + Ly * z), x + Lx * (y + Ly * ((z + 1) % Lz))]
+    bi = np.concatenate([i, i, i]).astype(np.int32)
+    bj = np.concatenate(nbrs).astype(np.int32)
+    bJ = np.asarray(inst["J"], np.int8).reshape(3, N).reshape(-1)
+    return {"kind": "graph", "n": N, "bond_i": bi, "bond_j": bj, "bond_J": bJ, "h": inst.get("h")}
+
+
+def random_sparse_graph(n: int, degree: int, seed: int, field: str = "uniform3", zero_frac: float = 0.0):
+    """Random simple graph of mean degree about `degree`: each vertex draws
+    `degree // 2` uniform partners (repeats and self-pairs dropped), couplings
+    iid +-1 (a fraction `zero_frac` set to 0), fields uniform in {-1, 0, +1}."""
+    rng = np.random.default_rng(seed)
+    pairs = set()
+    for i in range(n):
+        for _ in range(max(1, degree // 2)):
+            j = int(rng.integers(0, n))
+            if j != i:
+                pairs.add((min(i, j), max(i, j)))
+    pairs = sorted(pairs)
+    bi = np.array([p[0] for p in pairs], np.int32)
+    bj = np.array([p[1] for p in pairs], np.int32)
+    bJ = np.where(rng.random(len(pairs)) < 0.5, 1, -1).astype(np.int8)
+    if zero_frac > 0:
+        bJ[rng.random(len(pairs)) < zero_frac] = 0
+    h = rng.integers(-1, 2, size=n).astype(np.int8) if field == "uniform3" else None
+    return {"kind": "graph", "n": n, "bond_i": bi, "bond_j": bj, "bond_J": bJ, "h": h}
