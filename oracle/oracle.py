@@ -231,3 +231,50 @@ def anneal(g: Graph, beta, n_replicas: int, seed: int, sweep_offset: int = 0, re
     if rc != ORACLE_OK:
         raise RuntimeError("oracle_anneal failed: %d" % rc)
     return AnnealResult(spins, energies, e_trace, s_trace)
+
+
+# ---------------------------------------------------------------- Algorithm 1
+
+def alg1_minimal_budget(pc, G: float, i_start: int, i_step: int, t: int, p: float, p_succ: float,
+                        beta_i: float, beta_f: float, i_max: int):
+    """Algorithm 1 (Sec. 1.3.3) in the paper's order: for budget i, run the t
+    trials one at a time, count those whose energy v exceeds theta = p G,
+    leave the trial loop as soon as the count exceeds m_max, and return the
+    first i whose count stays within m_max; otherwise try i + i_step.
+
+    ``pc(i, beta, j)`` is the solver: the final energy of trial j annealed
+    over the schedule ``beta`` of i sweeps.  Readings: the budget counts
+    sweeps; the linear schedule runs beta_i to beta_f with both ends
+    included; the search gives up (returns None) past ``i_max``.
+    Returns (i_min, [(i, fails counted, trials run) ...])."""
+    theta = p * G
+    m_max = int(np.floor(t * (1.0 - p_succ) + 0.5))
+    history = []
+    i = i_start
+    while i <= i_max:
+        if i == 1:
+            beta = np.array([beta_i], np.float64)
+        else:
+            beta = np.array([beta_i + (beta_f - beta_i) * k / (i - 1) for k in range(i)], np.float64)
+        m = 0
+        ran = 0
+        for j in range(t):
+            v = pc(i, beta, j)
+            ran += 1
+            if v > theta:
+                m += 1
+                if m > m_max:
+                    break
+        history.append((i, m, ran))
+        if m <= m_max:
+            return i, history
+        i += i_step
+    return None, history
+
+
+def alg1_trial(g: Graph, seed_of):
+    """The solver of Algorithm 1 on the oracle: trial j is replica j of the
+    anneal seeded by ``seed_of(i)``."""
+    def pc(i, beta, j):
+        return int(anneal(g, beta, 1, seed_of(i), replica_offset=j).energies[0])
+    return pc
