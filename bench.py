@@ -311,7 +311,7 @@ def main():
     value = updates / wall
 
     # roofline of the half-sweep kernel
-    avg_ms = kern_ms / max(launches, 1)
+    avg_ms = kern_ms / launches if launches else float("inf")
     if w["kind"] == "ea3d":
         # per launch: N/2 x R updates, each reads its share of the other colour's
         # spins once (1 B) and writes its own spin (1 B); couplings ~0 B at R=4096
@@ -325,7 +325,9 @@ def main():
         roof = {"bound": "mfma", "achieved": alg_ops / (avg_ms * 1e-3) / 1e12, "peak": INT8_MFMA_PEAK_TOPS,
                 "unit": "TOP/s", "traffic": None, "kernel": "k_bq_halfsweep",
                 "alg_ops_per_launch": alg_ops, "avg_launch_us": avg_ms * 1e3, "launches_timed": launches}
-    roof["frac"] = roof["achieved"] / roof["peak"]
+    if launches == 0:  # launch timing switched off (--profile-every 0)
+        roof["achieved"] = None
+    roof["frac"] = None if roof["achieved"] is None else roof["achieved"] / roof["peak"]
     roof["traffic"] = measured_traffic(args.workload)
     roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
 

@@ -73,103 +73,126 @@ __global__ __launch_bounds__(kThreads) void k_ea_transpose(const int8_t *__restr
     }
 }
 
-// Count of negative products J_d m_d, times 2, for the four replicas held in
-// the bytes of one dword: spin bytes are +1 (0x01) or -1 (0xFF), so bit 1 of a
-// byte is set exactly for -1; masking keeps nonzero couplings and the XOR
-// flips the sign of J = -1 bonds.  Byte sums stay <= 12.
-__device__ __forceinline__ uint32_t neg2(uint32_t m, uint32_t keep, uint32_t flip)
-{
-    return (m & keep) ^ flip;
-}
-
-// Decision table of one half-sweep, indexed by I + kFieldOff: the minority
-// threshold Tm(beta_t, |I|), the mask that turns w into x (~0 for I >= 0),
-// and the spin bytes taken on a minority and on a majority outcome.
 constexpr int kFieldOff = 7;  // |I| <= 6 + |h| <= 7 on the cube
 constexpr int kFieldSlots = 2 * kFieldOff + 1;
+static_assert(sizeof(EaRow) == kFieldSlots * sizeof(uint64_t), "one decision word per field value");
 
-__device__ __forceinline__ void build_field_table(uint4 *tab, const uint32_t *__restrict__ trow, int width, int tid)
-{
-    if (tid < kFieldSlots) {
-        const int I = tid - kFieldOff;
-        const int a = min(I >= 0 ? I : -I, width - 1);
-        const bool pos = I >= 0;
-        tab[tid] = make_uint4(trow[a], pos ? 0xFFFFFFFFu : 0u, pos ? 0xFFu : 0x01u, pos ? 0x01u : 0xFFu);
-    }
-}
+// Sign mask of bit k of c: 0 or 0xFFFFFFFF.
+__device__ __forceinline__ uint32_t bit_mask(uint32_t c, int k) { return (uint32_t)((int32_t)(c << (31 - k)) >> 31); }
 
 // One checkerboard half-sweep.  Block (cbw, spb): x threads walk 16-replica
-// chunks, y threads walk the sites of one lattice row (y, z) = (blockIdx.y,
-// blockIdx.z).  blockIdx.x = chunk-block * nsl + slab: with nsl = 8 the slab
-// index equals the XCD a workgroup is dispatched to, so each XCD's L2 serves
-// one replica slab of the whole lattice and neighbour rows are reused there.
+// chunks, y threads walk the sites of a lattice row; a block covers `ny`
+// consecutive rows (y0 .. y0 + ny - 1, z) with y0 = blockIdx.y * ny and
+// z = blockIdx.z.  blockIdx.x = chunk-block * nsl + slab: with nsl = 8 the
+// slab index equals the XCD a workgroup is dispatched to, so each XCD's L2
+// serves one replica slab of the whole lattice and neighbour rows are reused
+// there.
+//
+// Decision: the table in LDS holds, for every field value I, the 64-bit word
+// S(I) = Tm for I >= 0 and 2^32 - Tm for I < 0 (EaRow); the heat-bath rule
+// (new spin -1 when ~w < Tm for I >= 0, and when w >= Tm for I < 0) is then
+// exactly "bit 32 of w + S(I) is set", one v_mad_u64_u32 per update (`one`
+// is 1, passed in so that w * one + S is issued as that instruction).
+//
+// Field, bytewise for four replicas per dword: spin bytes are +1 = 0x01 and
+// -1 = 0xFF, so bit 4 of a byte is set exactly for -1, and
+// ~(m ^ F) & K (F = all ones for J = -1, K = 0x10 per byte for J != 0) has
+// bit 4 set exactly where J m = +1.  Six such terms plus the site's base byte
+// give 8 (I + 7) in every byte (at most 112): the LDS byte address of the
+// replica's table entry.
+template <bool DENSE, bool EARLY_RNG>
 __global__ __launch_bounds__(kThreads) void k_ea_halfsweep(int8_t *__restrict__ spins,
-                                                           const uint32_t *__restrict__ code,
-                                                           const uint32_t *__restrict__ trow, int width, int Lx,
-                                                           int Ly, int Lz, int Rp, int colour, int nsl, int cs,
-                                                           uint32_t sweep, uint32_t rq0, uint32_t k0, uint32_t k1)
+                                                           const uint32_t *__restrict__ code, EaRow row, int Lx,
+                                                           int Ly, int Lz, int Rp, int colour, int lg_nsl, int cs,
+                                                           int ny, uint32_t sweep, uint32_t rq0, uint32_t k0,
+                                                           uint32_t k1, uint32_t one)
 {
-    __shared__ uint4 tab[kFieldSlots];
+    __shared__ uint64_t tab[kFieldSlots];  // the kernel's only LDS object, so it starts at address 0
     const int tid = threadIdx.x + blockDim.x * threadIdx.y;
-    build_field_table(tab, trow, width, tid);
+    if (tid < kFieldSlots) {
+        uint64_t v = row.s[0];
+#pragma unroll
+        for (int e = 1; e < kFieldSlots; ++e) v = tid == e ? row.s[e] : v;
+        tab[tid] = v;
+    }
     __syncthreads();
 
-    const int slab = blockIdx.x % nsl;
-    const int qs = (blockIdx.x / nsl) * blockDim.x + threadIdx.x;
+    const int slab = blockIdx.x & ((1 << lg_nsl) - 1);
+    const int qs = (blockIdx.x >> lg_nsl) * blockDim.x + threadIdx.x;
     const int q = slab * cs + qs;
     if (qs >= cs || 16 * q >= Rp) return;
-    const int y = blockIdx.y, z = blockIdx.z;
-    const uint32_t rowR = (uint32_t)Lx * (uint32_t)Rp;                 // bytes per lattice row
-    const uint32_t planeR = rowR * (uint32_t)Ly;                        // bytes per plane
-    const uint32_t base = (uint32_t)y * rowR + (uint32_t)z * planeR + 16u * (uint32_t)q;
-    const uint32_t yp = (y + 1 == Ly ? 0u : (uint32_t)(y + 1)) * rowR + (uint32_t)z * planeR + 16u * (uint32_t)q;
-    const uint32_t ym = (y == 0 ? (uint32_t)(Ly - 1) : (uint32_t)(y - 1)) * rowR + (uint32_t)z * planeR + 16u * (uint32_t)q;
-    const uint32_t zp = (uint32_t)y * rowR + (z + 1 == Lz ? 0u : (uint32_t)(z + 1)) * planeR + 16u * (uint32_t)q;
-    const uint32_t zm = (uint32_t)y * rowR + (z == 0 ? (uint32_t)(Lz - 1) : (uint32_t)(z - 1)) * planeR + 16u * (uint32_t)q;
-    const uint32_t siteRow = (uint32_t)Lx * ((uint32_t)y + (uint32_t)Ly * (uint32_t)z);
+    const int z = blockIdx.z;
+    const uint32_t rowR = (uint32_t)Lx * (uint32_t)Rp;  // bytes per lattice row
+    const uint32_t planeR = rowR * (uint32_t)Ly;         // bytes per plane
+    const uint32_t q16 = 16u * (uint32_t)q;
+    const uint32_t zR = (uint32_t)z * planeR + q16;
+    const uint32_t zpR = (z + 1 == Lz ? 0u : (uint32_t)(z + 1)) * planeR + q16;
+    const uint32_t zmR = (z == 0 ? (uint32_t)(Lz - 1) : (uint32_t)(z - 1)) * planeR + q16;
     const int hx = Lx / 2;
-    const int par = (colour + y + z) & 1;
     const uint32_t rg4 = rq0 + 4u * (uint32_t)q;  // Philox counter word 2 of this chunk's first group
+    const char *tbase = reinterpret_cast<const char *>(tab);
 
-    for (int kx = threadIdx.y; kx < hx; kx += blockDim.y) {
-        const int x = 2 * kx + par;
-        const uint32_t xR = (uint32_t)x * (uint32_t)Rp;
-        const uint32_t xpR = (x + 1 == Lx ? 0u : (uint32_t)(x + 1)) * (uint32_t)Rp;
-        const uint32_t xmR = (x == 0 ? (uint32_t)(Lx - 1) : (uint32_t)(x - 1)) * (uint32_t)Rp;
-        const uint32_t offs[6] = {base + xpR, base + xmR, yp + xR, ym + xR, zp + xR, zm + xR};
-        const uint32_t i = siteRow + (uint32_t)x;
-        const uint32_t c = code[i];
-        uint32_t cnt[4] = {0u, 0u, 0u, 0u};
+    for (int yy = 0; yy < ny; ++yy) {
+        const int y = blockIdx.y * ny + yy;
+        const uint32_t yR = (uint32_t)y * rowR;
+        const uint32_t base = yR + zR;
+        const uint32_t yp = (y + 1 == Ly ? 0u : (uint32_t)(y + 1)) * rowR + zR;
+        const uint32_t ym = (y == 0 ? (uint32_t)(Ly - 1) : (uint32_t)(y - 1)) * rowR + zR;
+        const uint32_t zp = yR + zpR, zm = yR + zmR;
+        const uint32_t siteRow = (uint32_t)Lx * ((uint32_t)y + (uint32_t)Ly * (uint32_t)z);
+        const int par = (colour + y + z) & 1;
+
+        for (int kx = threadIdx.y; kx < hx; kx += blockDim.y) {
+            const int x = 2 * kx + par;
+            const uint32_t xR = (uint32_t)x * (uint32_t)Rp;
+            const uint32_t xpR = (x + 1 == Lx ? 0u : (uint32_t)(x + 1)) * (uint32_t)Rp;
+            const uint32_t xmR = (x == 0 ? (uint32_t)(Lx - 1) : (uint32_t)(x - 1)) * (uint32_t)Rp;
+            const uint32_t offs[6] = {base + xpR, base + xmR, yp + xR, ym + xR, zp + xR, zm + xR};
+            const uint32_t i = siteRow + (uint32_t)x;
+            const uint32_t c = code[i];
+            uint4 v[6];
 #pragma unroll
-        for (int d = 0; d < 6; ++d) {
-            const uint4 v = *reinterpret_cast<const uint4 *>(spins + offs[d]);
-            const uint32_t keep = ((c >> d) & 1u) * 0x02020202u;
-            const uint32_t flip = ((c >> (kCodeFlipShift + d)) & 1u) * 0x02020202u;
-            cnt[0] += neg2(v.x, keep, flip);
-            cnt[1] += neg2(v.y, keep, flip);
-            cnt[2] += neg2(v.z, keep, flip);
-            cnt[3] += neg2(v.w, keep, flip);
-        }
-        // LDS byte address of the entry for I = base_i (no negative products)
-        const int entry0 = ((int)(int8_t)(c >> kCodeBaseShift) + kFieldOff) * (int)sizeof(uint4);
-        const char *tbase = reinterpret_cast<const char *>(tab);
-        uint32_t out[4];
+            for (int d = 0; d < 6; ++d) v[d] = *reinterpret_cast<const uint4 *>(spins + offs[d]);
+            // the random words do not depend on the loads; EARLY_RNG draws them while the loads
+            // are in flight (the scheduling barriers keep the compiler from sinking them)
+            Block4 b[4];
+            if (EARLY_RNG) {
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const Block4 b = philox(i, sweep, rg4 + (uint32_t)k, kDomainSweep, k0, k1);
-            // bytes of cnt are c2 <= 12, so cnt * 16 keeps each 16 c2 <= 192 in its own byte
-            const uint32_t off16 = cnt[k] << 4;
-            uint32_t packed = 0;
-#pragma unroll
-            for (int p = 0; p < 4; ++p) {
-                const int o = (int)((off16 >> (8 * p)) & 0xFFu);  // 16 c2, with I = base_i - c2
-                const uint4 e = *reinterpret_cast<const uint4 *>(tbase + entry0 - o);
-                const uint32_t xw = b.w[p] ^ e.y;
-                packed |= (xw < e.x ? e.z : e.w) << (8 * p);
+                for (int k = 0; k < 4; ++k) b[k] = philox(i, sweep, rg4 + (uint32_t)k, kDomainSweep, k0, k1);
+                __builtin_amdgcn_sched_barrier(0);
             }
-            out[k] = packed;
+            uint32_t t[6][4];
+#pragma unroll
+            for (int d = 0; d < 6; ++d) {
+                const uint32_t F = bit_mask(c, kCodeFlipShift + d);
+                const uint32_t K = DENSE ? 0x10101010u : (bit_mask(c, d) & 0x10101010u);
+                // truth table 0x82: ~(a ^ b) & c
+                t[d][0] = __builtin_amdgcn_bitop3_b32(v[d].x, F, K, 0x82);
+                t[d][1] = __builtin_amdgcn_bitop3_b32(v[d].y, F, K, 0x82);
+                t[d][2] = __builtin_amdgcn_bitop3_b32(v[d].z, F, K, 0x82);
+                t[d][3] = __builtin_amdgcn_bitop3_b32(v[d].w, F, K, 0x82);
+            }
+            const uint32_t pos8 = __builtin_amdgcn_perm(0u, c, 0x03030303u);  // bits 24..31 in every byte
+            uint32_t out[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (!EARLY_RNG) b[k] = philox(i, sweep, rg4 + (uint32_t)k, kDomainSweep, k0, k1);
+                const uint32_t idx = (t[0][k] + t[1][k] + t[2][k]) + (t[3][k] + t[4][k] + t[5][k]) + pos8;
+                uint32_t sgn[4];  // 1: the replica's new spin is -1
+#pragma unroll
+                for (int p = 0; p < 4; ++p) {
+                    const uint64_t S = *static_cast<const uint64_t *>(
+                        __builtin_assume_aligned(tbase + ((idx >> (8 * p)) & 0xFFu), 8));
+                    sgn[p] = (uint32_t)(((uint64_t)b[k].w[p] * one + S) >> 32);
+                }
+                // gather the four low bytes, then map 0 -> 0x01 and 1 -> 0xFF
+                const uint32_t lo = __builtin_amdgcn_perm(sgn[1], sgn[0], 0x0C0C0400u);
+                const uint32_t hi = __builtin_amdgcn_perm(sgn[3], sgn[2], 0x0C0C0400u);
+                out[k] = __builtin_amdgcn_perm(0u, 0xFF01u, __builtin_amdgcn_perm(hi, lo, 0x05040100u));
+            }
+            *reinterpret_cast<uint4 *>(spins + base + xR) = make_uint4(out[0], out[1], out[2], out[3]);
         }
-        *reinterpret_cast<uint4 *>(spins + base + xR) = make_uint4(out[0], out[1], out[2], out[3]);
     }
 }
 
@@ -226,22 +249,43 @@ hipError_t ea_to_rows(const EaView &p, const int8_t *spins, int Rp, int8_t *dst_
     return hipGetLastError();
 }
 
-hipError_t ea_halfsweep(const EaView &p, int8_t *spins, int Rp, int colour, const uint32_t *trow, int width,
-                        uint32_t sweep, uint32_t rq0, Key key, hipStream_t st)
+EaRow ea_row(const uint32_t *trow, int width)
 {
-    if (width < 1 || width > kFieldOff + 1 || Rp % 16 != 0) return hipErrorInvalidValue;
+    EaRow r;
+    for (int e = 0; e < kFieldSlots; ++e) {
+        const int I = e - kFieldOff;
+        const uint32_t T = trow[std::min(I >= 0 ? I : -I, width - 1)];
+        r.s[e] = I >= 0 ? (uint64_t)T : ((uint64_t)1 << 32) - T;
+    }
+    return r;
+}
+
+hipError_t ea_halfsweep(const EaView &p, int8_t *spins, int Rp, int colour, const EaRow &row, uint32_t sweep,
+                        uint32_t rq0, Key key, hipStream_t st, int ny, bool early_rng)
+{
+    if (Rp % 16 != 0) return hipErrorInvalidValue;
     if ((uint64_t)p.N * (uint64_t)Rp >= ((uint64_t)1 << 32)) return hipErrorInvalidValue;  // 32-bit byte offsets
-    if (p.Ly > 65535 || p.Lz > 65535) return hipErrorInvalidValue;                      // grid y / z limits
-    const int C = Rp / 16;              // 16-replica chunks
-    const int nsl = C >= 8 ? 8 : 1;     // replica slabs, one per XCD when there are enough chunks
-    const int cs = (C + nsl - 1) / nsl; // chunks per slab
+    if (p.Lz > 65535) return hipErrorInvalidValue;                                       // grid z limit
+    if (ny <= 0) ny = p.Ly % 2 == 0 ? 2 : 1;  // two rows per workgroup measured best at L = 16 and 32
+    if (p.Ly % ny != 0 || p.Ly / ny > 65535) return hipErrorInvalidValue;
+    const int C = Rp / 16;                   // 16-replica chunks
+    const int lg_nsl = C >= 8 ? 3 : 0;       // 8 replica slabs, one per XCD, when there are enough chunks
+    const int nsl = 1 << lg_nsl;
+    const int cs = (C + nsl - 1) / nsl;      // chunks per slab
     int cbw = 1;
     while (cbw < cs && cbw < 64) cbw *= 2;
     const int spb = kThreads / cbw;
     const int ncb = (cs + cbw - 1) / cbw;
-    dim3 grid((unsigned)(nsl * ncb), (unsigned)p.Ly, (unsigned)p.Lz), block((unsigned)cbw, (unsigned)spb);
-    hipLaunchKernelGGL(k_ea_halfsweep, grid, block, 0, st, spins, p.code, trow, width, p.Lx, p.Ly, p.Lz, Rp, colour,
-                       nsl, cs, sweep, rq0, key.k0, key.k1);
+    dim3 grid((unsigned)(nsl * ncb), (unsigned)(p.Ly / ny), (unsigned)p.Lz), block((unsigned)cbw, (unsigned)spb);
+#define PBIT_EA_LAUNCH(D, E)                                                                                     \
+    hipLaunchKernelGGL((k_ea_halfsweep<D, E>), grid, block, 0, st, spins, p.code, row, p.Lx, p.Ly, p.Lz, Rp, colour, \
+                       lg_nsl, cs, ny, sweep, rq0, key.k0, key.k1, 1u)
+    if (p.dense) {
+        if (early_rng) PBIT_EA_LAUNCH(true, true); else PBIT_EA_LAUNCH(true, false);
+    } else {
+        if (early_rng) PBIT_EA_LAUNCH(false, true); else PBIT_EA_LAUNCH(false, false);
+    }
+#undef PBIT_EA_LAUNCH
     return hipGetLastError();
 }
 

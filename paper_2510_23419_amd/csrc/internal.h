@@ -9,9 +9,12 @@ namespace pbit {
 // Per-site coupling code of a periodic cube.  Directions d = 0..5 are
 // +x, -x, +y, -y, +z, -z.  Bit d: J != 0 on that bond; bit 6 + d: J == -1;
 // bits 16..23: nnz(J) + h as a signed byte, so that the local field is
-//   I = (nnz + h) - 2 * #{d : J_d m_d = -1}.
+//   I = (nnz + h) - 2 * #{d : J_d m_d = -1};
+// bits 24..31: 8 (7 - nnz(J) + h), so that
+//   8 (I + 7) = 16 #{d : J_d m_d = +1} + bits 24..31.
 constexpr int kCodeFlipShift = 6;
 constexpr int kCodeBaseShift = 16;
+constexpr int kCodePosShift = 24;
 
 struct EaView {
     int Lx, Ly, Lz;
@@ -19,6 +22,7 @@ struct EaView {
     const uint32_t *code;  // [N]
     const int8_t *J;       // [3][N] as given (for from-scratch energies)
     const int8_t *h;       // [N] or null
+    bool dense;            // every coupling is nonzero
 };
 
 // General sparse graph with k colour classes (greedy colouring by default).
@@ -61,8 +65,15 @@ struct Key {
 hipError_t ea_init(const EaView &p, int8_t *spins, int Rp, uint32_t rq0, Key key, hipStream_t st);
 hipError_t ea_from_rows(const EaView &p, const int8_t *src_rn, int R, int8_t *spins, int Rp, hipStream_t st);
 hipError_t ea_to_rows(const EaView &p, const int8_t *spins, int Rp, int8_t *dst_rn, int R, hipStream_t st);
-hipError_t ea_halfsweep(const EaView &p, int8_t *spins, int Rp, int colour, const uint32_t *trow, int width,
-                        uint32_t sweep, uint32_t rq0, Key key, hipStream_t st);
+// Decision words of one sweep for the cube: S(I) for I = -7 .. 7 (Tm for
+// I >= 0, 2^32 - Tm for I < 0), passed to the half-sweep by value.
+struct EaRow {
+    uint64_t s[15];
+};
+EaRow ea_row(const uint32_t *host_trow, int width);
+// ny: lattice rows per workgroup (0 = choose); early_rng: draw the random words before the field
+hipError_t ea_halfsweep(const EaView &p, int8_t *spins, int Rp, int colour, const EaRow &row, uint32_t sweep,
+                        uint32_t rq0, Key key, hipStream_t st, int ny = 0, bool early_rng = true);
 hipError_t ea_energy(const EaView &p, const int8_t *spins, int Rp, int R, int32_t *E, hipStream_t st);
 
 // ---- biclique launchers; spins are device MA [Rp][na_p], MB [Rp][nb_p] -----

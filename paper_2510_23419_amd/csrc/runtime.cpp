@@ -262,6 +262,7 @@ static int load_ea(pbit_ctx *ctx, const pbit_problem_desc *d, Problem &p)
 
     std::vector<uint32_t> code((size_t)N);
     int amax = 0;
+    bool dense = true;
     const int64_t plane = (int64_t)Lx * Ly;
     for (int z = 0; z < Lz; ++z)
         for (int y = 0; y < Ly; ++y)
@@ -282,6 +283,8 @@ static int load_ea(pbit_ctx *ctx, const pbit_problem_desc *d, Problem &p)
                 }
                 const int hv = d->h ? d->h[i] : 0;
                 c |= (uint32_t)(uint8_t)(int8_t)(nnz + hv) << kCodeBaseShift;
+                c |= (uint32_t)(8 * (7 - nnz + hv)) << kCodePosShift;  // in [0, 64]
+                dense = dense && nnz == 6;
                 code[(size_t)i] = c;
                 amax = std::max(amax, nnz + std::abs(hv));
             }
@@ -293,7 +296,7 @@ static int load_ea(pbit_ctx *ctx, const pbit_problem_desc *d, Problem &p)
     p.kind = PBIT_EA3D;
     p.N = N;
     p.amax = amax;
-    p.ea = EaView{Lx, Ly, Lz, N, (const uint32_t *)dc, (const int8_t *)dJ, (const int8_t *)dh};
+    p.ea = EaView{Lx, Ly, Lz, N, (const uint32_t *)dc, (const int8_t *)dJ, (const int8_t *)dh, dense};
     return PBIT_OK;
 }
 
@@ -462,7 +465,7 @@ static int load_graph(pbit_ctx *ctx, const pbit_graph_desc *d, Problem &p)
                         (const int32_t *)dsite, (const uint8_t *)dcode, (const int16_t *)dbase, (const int32_t *)dbi,
                         (const int32_t *)dbj, (const int8_t *)dbJ, (const int8_t *)dh};
     // the cube's layout kernels (init, transposes) are reused with N = n
-    p.ea = EaView{0, 0, 0, (int64_t)n, nullptr, nullptr, nullptr};
+    p.ea = EaView{0, 0, 0, (int64_t)n, nullptr, nullptr, nullptr, false};
     return PBIT_OK;
 }
 
@@ -763,6 +766,8 @@ static hipError_t sweep(pbit_ctx *ctx, const Problem &P, DevState &ds, int s, ui
     const uint32_t *row = ds.table + (size_t)s * ds.width;
     hipError_t e = hipSuccess;
     const int ncol = P.kind == PBIT_GRAPH ? P.graph.n_colours : 2;
+    EaRow earow;
+    if (P.kind == PBIT_EA3D) earow = ea_row(ctx->host_table.data() + (size_t)s * ds.width, ds.width);
     for (int c = 0; c < ncol && e == hipSuccess; ++c) {
         int slot = -1;
         if (ctx->prof_every > 0 && (ncol * s + c) % ctx->prof_every == 0) {
@@ -770,7 +775,7 @@ static hipError_t sweep(pbit_ctx *ctx, const Problem &P, DevState &ds, int s, ui
             if (e != hipSuccess) return e;
         }
         if (P.kind == PBIT_EA3D)
-            e = ea_halfsweep(P.ea, ds.spins, ds.Rp, c, row, ds.width, t, rq0, key, st);
+            e = ea_halfsweep(P.ea, ds.spins, ds.Rp, c, earow, t, rq0, key, st);
         else if (P.kind == PBIT_GRAPH)
             e = graph_halfsweep(P.graph, c, ds.spins, ds.Rp, row, ds.width, t, rq0, key, st);
         else
