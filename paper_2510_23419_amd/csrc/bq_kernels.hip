@@ -28,6 +28,21 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr int kThreads = 256;
 constexpr int kTileR = 64;  // replicas per workgroup tile
+
+// 4 x 4 byte transpose across a lane quad: lane u of the quad holds byte p of
+// its dword for replica p; afterwards lane u holds, in byte v, the byte u of
+// quad lane v (four consecutive sites of replica u).
+__device__ __forceinline__ uint32_t quad_transpose(uint32_t d, int u)
+{
+    // v_perm_b32 selects bytes of {src0:src1} as a 64-bit value: selector byte
+    // values 0..3 pick src1 bytes, 4..7 pick src0 bytes
+    const uint32_t t = (uint32_t)__builtin_amdgcn_mov_dpp((int)d, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+    // even u: (d0, t0, d2, t2); odd u: (t1, d1, t3, d3); here src0 = t, src1 = d
+    const uint32_t d1 = __builtin_amdgcn_perm(t, d, (u & 1) ? 0x03070105u : 0x06020400u);
+    const uint32_t t2 = (uint32_t)__builtin_amdgcn_mov_dpp((int)d1, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+    // u < 2: (d1_0, d1_1, t2_0, t2_1); u >= 2: (t2_2, t2_3, d1_2, d1_3)
+    return __builtin_amdgcn_perm(t2, d1, (u & 2) ? 0x03020706u : 0x05040100u);
+}
 constexpr int kTileS = 64;  // sites per workgroup tile
 
 __global__ __launch_bounds__(kThreads) void k_bq_init(int8_t *__restrict__ MA, int8_t *__restrict__ MB, int na, int nb,
@@ -366,6 +381,212 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
     }
 }
 
+// ---------------------------------------------------------------- DMA-staged 128 x 128 tiles
+//
+// The same 128-replica x 128-site tile, with operands staged by the gfx950
+// global-to-LDS DMA (global_load_lds_dwordx4: each lane's 16 bytes land at
+// LDS base + 16 * lane) into a ring of NS stages of KT K-bytes, so that many
+// stages are in flight without occupying registers.  A stage holds 128 rows of
+// A (replicas) then 128 rows of B (sites), KT bytes per row (KT = 128: whole
+// cache lines); chunk c (K bytes 16c .. 16c + 15) of row r sits at position
+// c ^ swz(r), which keeps the 16-byte fragment reads of 8 or 16 consecutive
+// rows on distinct banks.  One barrier per stage both publishes stage t + 1
+// and frees the slot of stage t - 1 for stage t + NS - 1.
+template <int CH>
+__device__ __forceinline__ int swz(int r)
+{
+    return CH == 8 ? ((r ^ (r >> 3)) & 7) : (((r >> 1) ^ (r >> 3)) & 3);
+}
+
+// s_waitcnt vmcnt(n) (expcnt and lgkmcnt not waited for)
+template <int N>
+__device__ __forceinline__ void wait_vm()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt is a 6-bit field");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+template <int KT, int NS>
+struct DmaGeom {
+    static constexpr int CH = KT / 16;              // 16-byte chunks per row
+    static constexpr int op = kT * KT;              // bytes of one operand per stage
+    static constexpr int stage = 2 * op;
+    static constexpr int per_wave = CH / 2;         // DMA instructions per operand per wave and stage
+    static constexpr int subs = KT / 32;            // MFMA K steps per stage
+    static constexpr int ahead = 2 * per_wave * (NS - 2);  // loads allowed in flight after a stage lands
+    static constexpr int lds = NS * stage;
+    static_assert(ahead < 64, "vmcnt is a 6-bit field");
+};
+
+template <int KT, int NS>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_bq_halfsweep_dma(
+    const int8_t *__restrict__ Mo, const int8_t *__restrict__ Jx, const int8_t *__restrict__ hs,
+    int8_t *__restrict__ Ms, const uint32_t *__restrict__ trow, int width, int Ns_p, int Ko, int tiles_s,
+    int xcd_bands, uint32_t site_base, uint32_t sweep, uint32_t rq0, uint32_t k0, uint32_t k1)
+{
+    using G = DmaGeom<KT, NS>;
+    constexpr int CH = G::CH;
+    constexpr int kPhxPerStage = G::subs;            // Philox blocks drawn per stage
+    constexpr int kPhxStages = 16 / kPhxPerStage;
+
+    extern __shared__ uint4 smem[];
+    int8_t *ring = reinterpret_cast<int8_t *>(smem);
+    uint32_t *T = reinterpret_cast<uint32_t *>(ring + G::lds);
+    for (int a = threadIdx.x; a < width; a += kThreads) T[a] = trow[a];
+
+    int ts, tr;
+    if (xcd_bands) {  // tiles_s % 8 == 0: XCD (= block id mod 8) owns tiles_s / 8 site tiles
+        const int per = tiles_s / 8;
+        const int slot = (int)blockIdx.x / 8;
+        ts = ((int)blockIdx.x % 8) * per + slot % per;
+        tr = slot / per;
+    } else {
+        ts = (int)blockIdx.x % tiles_s;
+        tr = (int)blockIdx.x / tiles_s;
+    }
+    const int r0 = tr * kT, s0 = ts * kT;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+
+    // DMA sources: wave w fills slots 64 (per_wave w + j) + lane (j < per_wave) of each operand
+    // (fixed array bounds: the lambdas below capture these arrays by reference)
+    const int8_t *srcA[4], *srcB[4];
+    static_assert(G::per_wave <= 4 && G::subs <= 4, "fixed array bounds");
+#pragma unroll
+    for (int j = 0; j < G::per_wave; ++j) {
+        const int S = 64 * (G::per_wave * wave + j) + lane;
+        const int r = S / CH, c = (S % CH) ^ swz<CH>(S / CH);
+        srcA[j] = Mo + (size_t)(r0 + r) * Ko + 16 * c;
+        srcB[j] = Jx + (size_t)(s0 + r) * Ko + 16 * c;
+    }
+    const int nk = Ko / KT;
+    auto issue = [&](int t) {
+        int8_t *dA = ring + (t % NS) * G::stage + 1024 * G::per_wave * wave;
+        int8_t *dB = dA + G::op;
+        const size_t k = (size_t)t * KT;
+#pragma unroll
+        for (int j = 0; j < G::per_wave; ++j) __builtin_amdgcn_global_load_lds(srcA[j] + k, dA + 1024 * j, 16, 0, 0);
+#pragma unroll
+        for (int j = 0; j < G::per_wave; ++j) __builtin_amdgcn_global_load_lds(srcB[j] + k, dB + 1024 * j, 16, 0, 0);
+    };
+    // the threshold row's loads are waited for before any DMA is counted
+    wait_vm<0>();
+    for (int t = 0; t < NS - 1 && t < nk; ++t) issue(t);
+
+    const int wr = wave >> 1, wc = wave & 1;
+    const int ln = lane & 31, kg = lane >> 5;
+    // fragment rows of this lane: A rows wr*64 + {0, 32} + ln, B rows wc*64 + {0, 32} + ln
+    int offA[2][4], offB[2][4];  // [row block][K step]
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int sub = 0; sub < G::subs; ++sub) {
+            const int ra = wr * 64 + 32 * b + ln, rb = wc * 64 + 32 * b + ln;
+            offA[b][sub] = KT * ra + 16 * ((2 * sub + kg) ^ swz<CH>(ra));
+            offB[b][sub] = G::op + KT * rb + 16 * ((2 * sub + kg) ^ swz<CH>(rb));
+        }
+    Acc4 acc;
+    acc.c00 = acc.c01 = acc.c10 = acc.c11 = v16i{0};
+    uint32_t words[16][4];
+
+    // fragments of stage t from LDS and their MFMAs; the MFMAs keep executing
+    // while the wave goes on to the barrier and the next stage's reads
+    auto compute = [&](int t) {
+        const int8_t *st = ring + (t % NS) * G::stage;
+#pragma unroll
+        for (int sub = 0; sub < G::subs; ++sub) {
+            const v4i a0 = *reinterpret_cast<const v4i *>(st + offA[0][sub]);
+            const v4i a1 = *reinterpret_cast<const v4i *>(st + offA[1][sub]);
+            const v4i b0 = *reinterpret_cast<const v4i *>(st + offB[0][sub]);
+            const v4i b1 = *reinterpret_cast<const v4i *>(st + offB[1][sub]);
+            acc.c00 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, b0, acc.c00, 0, 0, 0);
+            acc.c01 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, b1, acc.c01, 0, 0, 0);
+            acc.c10 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, b0, acc.c10, 0, 0, 0);
+            acc.c11 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, b1, acc.c11, 0, 0, 0);
+        }
+    };
+    auto draw = [&](int blk) {
+        // block (bj * 2 + bi) * 4 + q covers site column bj and replica rows bi, q
+        const int bj = blk >> 3, bi = (blk >> 2) & 1, q = blk & 3;
+        const int site = s0 + wc * 64 + bj * 32 + ln;
+        const int r4 = r0 + wr * 64 + bi * 32 + 8 * q + 4 * kg;
+        const Block4 b = philox(site_base + (uint32_t)site, sweep, rq0 + (uint32_t)(r4 >> 2), kDomainSweep, k0, k1);
+        words[blk][0] = b.w[0];
+        words[blk][1] = b.w[1];
+        words[blk][2] = b.w[2];
+        words[blk][3] = b.w[3];
+    };
+
+    // stage 0 landed in every wave (later stages may still be in flight)
+    if (nk >= NS - 1) wait_vm<G::ahead>(); else wait_vm<0>();
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");  // LDS written by the DMA: no read may move above here
+
+    // first stages: the Philox draws ride along with the MFMAs
+    int t = 0;
+#pragma unroll
+    for (int u = 0; u < kPhxStages; ++u) {
+        if (t < nk) {
+            if (t + NS - 1 < nk) issue(t + NS - 1);
+            compute(t);
+#pragma unroll
+            for (int v = 0; v < kPhxPerStage; ++v) draw(kPhxPerStage * u + v);
+            if (t + NS - 1 < nk) wait_vm<G::ahead>(); else wait_vm<0>();
+            __builtin_amdgcn_s_barrier();
+            asm volatile("" ::: "memory");
+            ++t;
+        } else {
+#pragma unroll
+            for (int v = 0; v < kPhxPerStage; ++v) draw(kPhxPerStage * u + v);
+        }
+    }
+    // steady state: every stage after this one still has NS - 2 successors in flight
+    for (; t + NS - 1 < nk; ++t) {
+        issue(t + NS - 1);
+        compute(t);
+        wait_vm<G::ahead>();
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+    }
+    // tail: nothing left to issue
+    for (; t < nk; ++t) {
+        compute(t);
+        wait_vm<0>();
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+    }
+
+    // epilogue: four replicas of a group are packed into one dword, then
+    // transposed across the lane quad (sites s .. s + 3) so that each lane
+    // stores four consecutive sites of one replica row.  Every store lands
+    // inside the padded [Rp][Ns_p] array; padding sites and replicas take
+    // values that nothing reads (their couplings and fields are zero).
+    const int top = width - 1;
+    const int u4 = ln & 3;
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+        const int site = s0 + wc * 64 + bj * 32 + ln;
+        const int hval = hs[site];  // site < Ns_p: padded fields are zero
+        const int quad_col = site - u4;
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi) {
+            const v16i &c = bi == 0 ? (bj == 0 ? acc.c00 : acc.c01) : (bj == 0 ? acc.c10 : acc.c11);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int blk = (bj * 2 + bi) * 4 + q;
+                uint32_t packed = 0;
+#pragma unroll
+                for (int p = 0; p < 4; ++p) {
+                    const int I = c[4 * q + p] + hval;
+                    const int a = min(I >= 0 ? I : -I, top);
+                    packed |= (uint32_t)(uint8_t)decide(I, T[a], words[blk][p]) << (8 * p);
+                }
+                const int r4 = r0 + wr * 64 + bi * 32 + 8 * q + 4 * kg;
+                *reinterpret_cast<uint32_t *>(Ms + (size_t)(r4 + u4) * Ns_p + quad_col) = quad_transpose(packed, u4);
+            }
+        }
+    }
+}
+
 // Field part of the energy: E[r] -= sum_i h_i m_i over both sides.
 __global__ __launch_bounds__(kThreads) void k_bq_field_energy(const int8_t *__restrict__ MA,
                                                               const int8_t *__restrict__ MB,
@@ -431,6 +652,15 @@ hipError_t bq_halfsweep(const BqView &p, int side, int8_t *MA, int8_t *MB, int R
         if (e == hipSuccess)
             e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bq_halfsweep_t128<128, 4>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+        // the DMA rings plus the threshold row
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bq_halfsweep_dma<64, 8>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    DmaGeom<64, 8>::lds + (int)sizeof(uint32_t) * kMaxTableWidth);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bq_halfsweep_dma<128, 4>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    DmaGeom<128, 4>::lds + (int)sizeof(uint32_t) * kMaxTableWidth);
         return e;
     }();
     if (lds_attr != hipSuccess) return lds_attr;
@@ -440,6 +670,16 @@ hipError_t bq_halfsweep(const BqView &p, int side, int8_t *MA, int8_t *MB, int R
         const int bands = tiles_s % 8 == 0 ? 1 : 0;
         const size_t tab = sizeof(uint32_t) * (size_t)width;
         switch (variant) {
+        case BqVariant::Dma64:
+            hipLaunchKernelGGL((k_bq_halfsweep_dma<64, 8>), grid, dim3(kThreads), (DmaGeom<64, 8>::lds + tab), st, Mo,
+                               Jx, hs, Ms, trow, width, Ns_p, Ko, tiles_s, bands, site_base, sweep, rq0, key.k0,
+                               key.k1);
+            break;
+        case BqVariant::Dma128:
+            hipLaunchKernelGGL((k_bq_halfsweep_dma<128, 4>), grid, dim3(kThreads), (DmaGeom<128, 4>::lds + tab), st, Mo,
+                               Jx, hs, Ms, trow, width, Ns_p, Ko, tiles_s, bands, site_base, sweep, rq0, key.k0,
+                               key.k1);
+            break;
         case BqVariant::K64D4:
             hipLaunchKernelGGL((k_bq_halfsweep_t128<64, 4>), grid, dim3(kThreads), TileGeom<64>::lds + tab, st, Mo,
                                Jx, hs, Ms, trow, width, Ns, Ns_p, Ko, R, tiles_s, bands, site_base, sweep, rq0,

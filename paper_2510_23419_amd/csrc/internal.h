@@ -80,7 +80,7 @@ hipError_t ea_energy(const EaView &p, const int8_t *spins, int Rp, int R, int32_
 // Kernel variants of a biclique half-sweep.  Small: 64 x 64 tiles straight from
 // global memory; the others: 128 x 128 LDS-tiled with K stages of 64 or 128
 // bytes and 2 or 4 stages of register prefetch (needs sides padded to 128).
-enum class BqVariant : int { Auto = 0, Small = 1, K64D4 = 2, K128D2 = 3, K128D4 = 4 };
+enum class BqVariant : int { Auto = 0, Small = 1, K64D4 = 2, K128D2 = 3, K128D4 = 4, Dma64 = 5, Dma128 = 6 };
 hipError_t bq_init(const BqView &p, int8_t *MA, int8_t *MB, int R, uint32_t rq0, Key key, hipStream_t st);
 hipError_t bq_from_rows(const BqView &p, const int8_t *src_rn, int R, int8_t *MA, int8_t *MB, hipStream_t st);
 hipError_t bq_to_rows(const BqView &p, const int8_t *MA, const int8_t *MB, int8_t *dst_rn, int R, hipStream_t st);

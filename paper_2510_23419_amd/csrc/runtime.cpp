@@ -186,9 +186,9 @@ extern "C" int pbit_create(pbit_ctx **out, int device, uint64_t hbm_budget_bytes
     if (!ctx) return fail(PBIT_E_NOMEM, "pbit_create: host allocation failed");
     ctx->device = device;
     ctx->budget = hbm_budget_bytes;
-    if (const char *v = std::getenv("PBIT_BQ_VARIANT")) {  // tuning override: 1..4 (see BqVariant)
+    if (const char *v = std::getenv("PBIT_BQ_VARIANT")) {  // tuning override: 1..6 (see BqVariant)
         const int k = std::atoi(v);
-        if (k >= 1 && k <= 4) ctx->bq_forced = (BqVariant)k;
+        if (k >= 1 && k <= 6) ctx->bq_forced = (BqVariant)k;
     }
     ctx->serial = g_ctx_serial.fetch_add(1);
     e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
@@ -661,7 +661,8 @@ static int tune_biclique(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStrea
         ctx->bq_tuned[shape] = ds.variant;
         return PBIT_OK;
     }
-    const BqVariant cand[] = {BqVariant::K64D4, BqVariant::K128D2, BqVariant::K128D4, BqVariant::Small};
+    const BqVariant cand[] = {BqVariant::K64D4, BqVariant::K128D2, BqVariant::K128D4, BqVariant::Dma64,
+                              BqVariant::Dma128, BqVariant::Small};
     hipEvent_t e0, e1;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
