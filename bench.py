@@ -29,6 +29,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 INT8_MFMA_PEAK_TOPS = 5000.0   # MI355X dense int8 MFMA, published (TOP/s)
+VALU_PEAK_TLANEOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 32-bit vector lane-ops/s: CUs x SIMDs x lanes x clock
 
 WORKLOADS = {
     "ea32": dict(kind="ea3d", L=32, R=4096, S=10_000, b0=0.1, b1=5.0, sched="geometric", inst_seed=32),
@@ -83,10 +84,10 @@ def cpu_baseline(w, inst, beta, budget_s):
                       % (S, len(beta), R - 1, w["R"], platform.processor() or platform.machine(), dt)}
 
 
-def measured_traffic(workload):
-    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
-    counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter
-    reads for a plain copy), or None if the kernel sources changed since."""
+def profile_record(workload):
+    """The committed rocprofv3 counter summary of the dominant kernel for this
+    workload (profiles/traffic.json), or None if the kernel sources changed
+    since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
@@ -100,7 +101,14 @@ def measured_traffic(workload):
             h.update(f.read())
     if h.hexdigest() != rec["sha256"]:
         return None
-    return float(rec["traffic_bytes_per_launch"])
+    return rec
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch (FETCH_SIZE and WRITE_SIZE, each scaled by what the
+    counter reads for a plain copy), or None."""
+    rec = profile_record(workload)
+    return None if rec is None else float(rec["traffic_bytes_per_launch"])
 
 
 def mixed_bag_bench(args, pbit, torch):
@@ -239,7 +247,8 @@ def main():
     ap.add_argument("--duration", type=float, default=20.0, help="serve: arrival window (s)")
     ap.add_argument("--pool", type=int, default=64, help="serve: distinct instances jobs are drawn from")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="oracle sample budget (0 = skip)")
-    ap.add_argument("--profile-every", type=int, default=8, help="bracket every k-th half-sweep with HIP events")
+    ap.add_argument("--profile-every", type=int, default=32,
+                    help="time a window of 8 consecutive half-sweeps with HIP events every k launches (0 = off)")
     ap.add_argument("--sweeps", type=int, default=0, help="run only the first k sweeps of the schedule (profiling)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized int8 tensor 5 times (reference kernel for HBM counters)")
@@ -329,6 +338,16 @@ def main():
         roof["achieved"] = None
     roof["frac"] = None if roof["achieved"] is None else roof["achieved"] / roof["peak"]
     roof["traffic"] = measured_traffic(args.workload)
+    rec = profile_record(args.workload)
+    if rec and rec.get("valu_insts_per_dispatch") and launches:
+        # vector ALU issue: wave instructions x 64 lanes per launch over the measured
+        # launch time, against 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+        lane_ops = float(rec["valu_insts_per_dispatch"]) * 64
+        achieved = lane_ops / (avg_ms * 1e-3) / 1e12
+        roof["valu"] = {"lane_ops_per_launch": lane_ops, "achieved": achieved, "peak": VALU_PEAK_TLANEOPS,
+                        "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK_TLANEOPS}
+        if w["kind"] == "ea3d":
+            roof["valu"]["lane_ops_per_update"] = lane_ops / (N * R / 2)  # a half-sweep updates N/2 sites
     roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
 
     cpu = None

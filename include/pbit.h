@@ -241,9 +241,11 @@ int pbit_serve_config(pbit_ctx *ctx, int32_t max_queue, int32_t max_running, int
 
 /* ---- profiling -------------------------------------------------------------- */
 
-/* Bracket every `every`-th half-sweep launch (0 = off) with a pair of HIP
- * events recorded on the stream the launch runs on, so that the device time of
- * the sweep kernels can be read back without an external profiler. */
+/* Time the sweep kernels without an external profiler (0 = off): a window of
+ * min(8, every) consecutive half-sweep launches, starting at every `every`-th
+ * launch of an anneal, is bracketed by one pair of HIP events recorded on the
+ * stream the launches run on; pbit_profile_read returns the summed device time
+ * of the windows and the number of launches inside them. */
 int pbit_profile_enable(pbit_ctx *ctx, int32_t every);
 
 /* Device time and number of the bracketed half-sweep launches of problem kind

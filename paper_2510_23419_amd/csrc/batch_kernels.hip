@@ -10,7 +10,7 @@
 // which items it was batched with.
 #include "batch.h"
 #include "device.h"
-#include "internal.h"
+#include "bq.h"
 
 namespace pbit {
 

@@ -17,7 +17,7 @@
 // aligned groups of four replicas of one site: exactly the four words of one
 // Philox block per group.
 #include "device.h"
-#include "internal.h"
+#include "bq.h"
 
 namespace pbit {
 

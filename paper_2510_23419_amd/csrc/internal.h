@@ -41,21 +41,7 @@ struct GraphView {
     const int8_t *h;             // device [n] or null
 };
 
-struct BqView {
-    int na, nb;      // real side sizes
-    int na_p, nb_p;  // padded to kBqPad (extra couplings and spins are zero)
-    const int8_t *J;   // [na_p][nb_p]
-    const int8_t *JT;  // [nb_p][na_p]
-    const int8_t *hA;  // [na_p]
-    const int8_t *hB;  // [nb_p]
-};
-
-constexpr int kBqPad = 64;       // site padding of small biclique sides (MFMA K and N tiles)
-constexpr int kBqPadLarge = 128; // site padding of sides with at least kBqLargeSide sites
-constexpr int kBqLargeSide = 512;
-constexpr int kBqRPad = 128;     // replica padding of biclique spin matrices (MFMA M tile)
 constexpr int kEaRPad = 16;   // replica padding of the cube spin matrix (one dwordx4 per thread)
-constexpr int kMaxTableWidth = 4096;  // threshold-row entries a biclique kernel stages in LDS (16 KiB)
 
 struct Key {
     uint32_t k0, k1;
@@ -75,18 +61,6 @@ EaRow ea_row(const uint32_t *host_trow, int width);
 hipError_t ea_halfsweep(const EaView &p, int8_t *spins, int Rp, int colour, const EaRow &row, uint32_t sweep,
                         uint32_t rq0, Key key, hipStream_t st, int ny = 0, bool early_rng = true);
 hipError_t ea_energy(const EaView &p, const int8_t *spins, int Rp, int R, int32_t *E, hipStream_t st);
-
-// ---- biclique launchers; spins are device MA [Rp][na_p], MB [Rp][nb_p] -----
-// Kernel variants of a biclique half-sweep.  Small: 64 x 64 tiles straight from
-// global memory; the others: 128 x 128 LDS-tiled with K stages of 64 or 128
-// bytes and 2 or 4 stages of register prefetch (needs sides padded to 128).
-enum class BqVariant : int { Auto = 0, Small = 1, K64D4 = 2, K128D2 = 3, K128D4 = 4, Dma64 = 5, Dma128 = 6 };
-hipError_t bq_init(const BqView &p, int8_t *MA, int8_t *MB, int R, uint32_t rq0, Key key, hipStream_t st);
-hipError_t bq_from_rows(const BqView &p, const int8_t *src_rn, int R, int8_t *MA, int8_t *MB, hipStream_t st);
-hipError_t bq_to_rows(const BqView &p, const int8_t *MA, const int8_t *MB, int8_t *dst_rn, int R, hipStream_t st);
-hipError_t bq_halfsweep(const BqView &p, int side, int8_t *MA, int8_t *MB, int R, int Rp, const uint32_t *trow,
-                        int width, uint32_t sweep, uint32_t rq0, Key key, hipStream_t st, BqVariant variant);
-hipError_t bq_energy(const BqView &p, const int8_t *MA, const int8_t *MB, int R, int Rp, int32_t *E, hipStream_t st);
 
 // ---- general graphs; spins are device [N][Rp] like the cube ----------------
 hipError_t graph_halfsweep(const GraphView &g, int colour, int8_t *spins, int Rp, const uint32_t *trow, int width,

@@ -770,9 +770,8 @@ static hipError_t sweep(pbit_ctx *ctx, const Problem &P, DevState &ds, int s, ui
     EaRow earow;
     if (P.kind == PBIT_EA3D) earow = ea_row(ctx->host_table.data() + (size_t)s * ds.width, ds.width);
     for (int c = 0; c < ncol && e == hipSuccess; ++c) {
-        int slot = -1;
-        if (ctx->prof_every > 0 && (ncol * s + c) % ctx->prof_every == 0) {
-            e = prof_begin(ctx, P.kind, st, &slot);
+        if (ctx->prof_every > 0 && ctx->prof_open < 0 && (ncol * s + c) % ctx->prof_every == 0) {
+            e = prof_begin(ctx, P.kind, st);
             if (e != hipSuccess) return e;
         }
         if (P.kind == PBIT_EA3D)
@@ -781,7 +780,7 @@ static hipError_t sweep(pbit_ctx *ctx, const Problem &P, DevState &ds, int s, ui
             e = graph_halfsweep(P.graph, c, ds.spins, ds.Rp, row, ds.width, t, rq0, key, st);
         else
             e = bq_halfsweep(P.bq, c, ds.MA, ds.MB, ds.R, ds.Rp, row, ds.width, t, rq0, key, st, ds.variant);
-        if (e == hipSuccess) e = prof_end(ctx, slot, st);
+        if (e == hipSuccess) e = prof_count_launch(ctx, st);
     }
     return e;
 }
@@ -801,7 +800,8 @@ static hipError_t to_rows(const Problem &P, DevState &ds, int8_t *dst, hipStream
 
 static int fetch_energies(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStream_t st, std::vector<int32_t> &out)
 {
-    hipError_t e = energies(P, ds, st);
+    hipError_t e = prof_close(ctx, st);  // a timing window covers sweep launches only
+    if (e == hipSuccess) e = energies(P, ds, st);
     if (e == hipSuccess) {
         out.resize(ds.R);
         e = hipMemcpyAsync(out.data(), ds.E32, sizeof(int32_t) * ds.R, hipMemcpyDeviceToHost, st);
@@ -885,7 +885,8 @@ int run_device(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, int8_
         hipError_t e = sweep(ctx, P, ds, s, (uint32_t)(d->sweep_offset + s), rq0, key, st);
         if (e != hipSuccess) return device_fail(ctx, e, "sweep launch");
     }
-    hipError_t e = to_rows(P, ds, d_spins, st);
+    hipError_t e = prof_close(ctx, st);  // a timing window covers sweep launches only
+    if (e == hipSuccess) e = to_rows(P, ds, d_spins, st);
     if (e == hipSuccess && d_energies) {
         e = energies(P, ds, st);
         if (e == hipSuccess) e = widen_i32_i64(ds.E32, d_energies, ds.R, st);
@@ -970,9 +971,12 @@ extern "C" int pbit_energy(pbit_ctx *ctx, uint64_t problem, const int8_t *spins,
 
 namespace pbit {
 
-hipError_t prof_begin(pbit_ctx *ctx, int kind, hipStream_t st, int *slot)
+// A window of up to kProfWindow consecutive half-sweep launches is bracketed by
+// one pair of events, so that the events' own cost is shared by the window.
+constexpr int kProfWindow = 8;
+
+hipError_t prof_begin(pbit_ctx *ctx, int kind, hipStream_t st)
 {
-    *slot = -1;
     const size_t need = ctx->prof_used + 2;
     while (ctx->prof_pool.size() < need) {
         hipEvent_t ev;
@@ -983,16 +987,29 @@ hipError_t prof_begin(pbit_ctx *ctx, int kind, hipStream_t st, int *slot)
     const int k = (int)ctx->prof_used;
     ctx->prof_used += 2;
     ctx->prof_kind.push_back(kind);
-    *slot = k;
+    ctx->prof_launches.push_back(0);
+    ctx->prof_open = k;
     return hipEventRecord(ctx->prof_pool[k], st);
 }
 
-hipError_t prof_end(pbit_ctx *ctx, int slot, hipStream_t st)
+hipError_t prof_count_launch(pbit_ctx *ctx, hipStream_t st)
 {
-    return slot < 0 ? hipSuccess : hipEventRecord(ctx->prof_pool[slot + 1], st);
+    if (ctx->prof_open < 0) return hipSuccess;
+    const int w = std::min(kProfWindow, ctx->prof_every);
+    if (++ctx->prof_launches.back() < w) return hipSuccess;
+    const int k = ctx->prof_open;
+    ctx->prof_open = -1;
+    return hipEventRecord(ctx->prof_pool[k + 1], st);
 }
 
-// Called after the stream has been synchronised: fold the pending pairs in.
+hipError_t prof_close(pbit_ctx *ctx, hipStream_t st)
+{
+    if (ctx->prof_open < 0) return hipSuccess;
+    const int k = ctx->prof_open;
+    ctx->prof_open = -1;
+    return hipEventRecord(ctx->prof_pool[k + 1], st);
+}
+
 hipError_t prof_harvest(pbit_ctx *ctx)
 {
     for (size_t k = 0; k < ctx->prof_kind.size(); ++k) {
@@ -1001,9 +1018,10 @@ hipError_t prof_harvest(pbit_ctx *ctx)
         if (e != hipSuccess) return e;
         const int kind = ctx->prof_kind[k] == PBIT_EA3D ? 1 : 2;
         ctx->prof_ms[kind] += ms;
-        ctx->prof_count[kind] += 1;
+        ctx->prof_count[kind] += ctx->prof_launches[k];
     }
     ctx->prof_kind.clear();
+    ctx->prof_launches.clear();
     ctx->prof_used = 0;
     return hipSuccess;
 }
@@ -1013,7 +1031,9 @@ void prof_release(pbit_ctx *ctx)
     for (hipEvent_t ev : ctx->prof_pool) (void)hipEventDestroy(ev);
     ctx->prof_pool.clear();
     ctx->prof_kind.clear();
+    ctx->prof_launches.clear();
     ctx->prof_used = 0;
+    ctx->prof_open = -1;
 }
 
 }  // namespace pbit

@@ -9,7 +9,7 @@
 #include <vector>
 
 #include "../../include/pbit.h"
-#include "internal.h"
+#include "bq.h"
 
 namespace pbit {
 
@@ -55,7 +55,9 @@ struct pbit_ctx {
     int prof_every = 0;
     std::vector<hipEvent_t> prof_pool;
     size_t prof_used = 0;
-    std::vector<int> prof_kind;  // kind of each pending pair
+    std::vector<int> prof_kind;      // kind of each pending pair
+    std::vector<int> prof_launches;  // launches inside each pending pair
+    int prof_open = -1;              // pool index of the pair whose end is not recorded yet
     double prof_ms[3] = {0, 0, 0};
     int64_t prof_count[3] = {0, 0, 0};
     // biclique kernel variant: forced (PBIT_BQ_VARIANT) or autotuned per shape
@@ -78,8 +80,9 @@ void build_table(const double *beta, int S, int width, uint32_t *out);
 void serve_shutdown(pbit_ctx *ctx);
 int spins_in_range(const int8_t *s, size_t n);
 int greedy_colouring(int n, int n_bonds, const int32_t *bi, const int32_t *bj, uint8_t *colour, int *n_colours);
-hipError_t prof_begin(pbit_ctx *ctx, int kind, hipStream_t st, int *slot);
-hipError_t prof_end(pbit_ctx *ctx, int slot, hipStream_t st);
+hipError_t prof_begin(pbit_ctx *ctx, int kind, hipStream_t st);
+hipError_t prof_count_launch(pbit_ctx *ctx, hipStream_t st);
+hipError_t prof_close(pbit_ctx *ctx, hipStream_t st);
 hipError_t prof_harvest(pbit_ctx *ctx);
 void prof_release(pbit_ctx *ctx);
 
