@@ -587,6 +587,267 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
     }
 }
 
+// ---------------------------------------------------------------- fp4 operands
+//
+// On bicliques whose sides are both padded to 128, spins and couplings are
+// also held as 4-bit floats (e2m1: +1 = 0x2, -1 = 0xA, 0 = 0x0), two per byte
+// with the lower site in the low nibble.  Products of these values and their
+// sums (|F| <= n < 2^24) are exact in the fp32 accumulators of the f8f6f4 MFMA,
+// so the fields are the same integers as with int8 operands, while a byte of
+// operand now carries two multiply-adds and the MFMA rate doubles.  The half-
+// sweep is the DMA-staged tile above with 32-byte K steps of 64 values.
+__device__ __forceinline__ uint32_t fp4_code(int m) { return m > 0 ? 0x2u : (m < 0 ? 0xAu : 0x0u); }
+__device__ __forceinline__ int8_t fp4_value(uint32_t nib) { return nib == 0 ? (int8_t)0 : ((nib & 8u) ? (int8_t)-1 : (int8_t)1); }
+
+// Random start: thread (site pair, replica group) writes one byte in each of four rows.
+__global__ __launch_bounds__(kThreads) void k_bq4_init(uint8_t *__restrict__ MA4, uint8_t *__restrict__ MB4, int na,
+                                                       int nb, int na_p, int nb_p, int R, uint32_t rq0, uint32_t k0,
+                                                       uint32_t k1)
+{
+    const int groups = (R + 3) / 4;
+    const int pa = na_p / 2, pb = nb_p / 2;
+    const int64_t gid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (gid >= (int64_t)(pa + pb) * groups) return;
+    const int g = (int)(gid % groups);
+    const int pi = (int)(gid / groups);
+    const bool A = pi < pa;
+    const int s0 = 2 * (A ? pi : pi - pa), n = A ? na : nb;
+    const uint32_t i0 = (uint32_t)(A ? s0 : na + s0);
+    uint8_t *dst = A ? MA4 + pi : MB4 + (pi - pa);
+    const int rowbytes = A ? pa : pb;
+    const Block4 b0 = philox(i0, 0u, rq0 + (uint32_t)g, kDomainInit, k0, k1);
+    const Block4 b1 = philox(i0 + 1u, 0u, rq0 + (uint32_t)g, kDomainInit, k0, k1);
+    for (int p = 0; p < 4; ++p) {
+        const int r = 4 * g + p;
+        if (r >= R) break;
+        const uint32_t lo = s0 < n ? fp4_code(init_spin(b0.w[p])) : 0u;
+        const uint32_t hi = s0 + 1 < n ? fp4_code(init_spin(b1.w[p])) : 0u;
+        dst[(size_t)r * rowbytes] = (uint8_t)(lo | (hi << 4));
+    }
+}
+
+// [R][na + nb] int8 rows <-> packed sides; thread (replica, site pair of the real sites)
+template <bool TO_DEVICE>
+__global__ __launch_bounds__(kThreads) void k_bq4_copy(int8_t *__restrict__ rows, uint8_t *__restrict__ MA4,
+                                                       uint8_t *__restrict__ MB4, int na, int nb, int na_p, int nb_p,
+                                                       int R)
+{
+    const int qa = (na + 1) / 2, qb = (nb + 1) / 2;
+    const int64_t gid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (gid >= (int64_t)R * (qa + qb)) return;
+    const int r = (int)(gid / (qa + qb));
+    const int pi = (int)(gid % (qa + qb));
+    const bool A = pi < qa;
+    const int s0 = 2 * (A ? pi : pi - qa), n = A ? na : nb;
+    int8_t *row = rows + (size_t)r * (na + nb) + (A ? 0 : na);
+    uint8_t *byte = A ? MA4 + (size_t)r * (na_p / 2) + pi : MB4 + (size_t)r * (nb_p / 2) + (pi - qa);
+    if (TO_DEVICE) {
+        const uint32_t lo = fp4_code(row[s0]);
+        const uint32_t hi = s0 + 1 < n ? fp4_code(row[s0 + 1]) : 0u;
+        *byte = (uint8_t)(lo | (hi << 4));
+    } else {
+        const uint32_t v = *byte;
+        row[s0] = fp4_value(v & 15u);
+        if (s0 + 1 < n) row[s0 + 1] = fp4_value(v >> 4);
+    }
+}
+
+// packed sides -> int8 sides (all padded rows and columns), for the energy kernels
+__global__ __launch_bounds__(kThreads) void k_bq4_unpack(const uint8_t *__restrict__ MA4,
+                                                         const uint8_t *__restrict__ MB4, int8_t *__restrict__ MA,
+                                                         int8_t *__restrict__ MB, int na_p, int nb_p, int Rp)
+{
+    const int pa = na_p / 2, pb = nb_p / 2;
+    const int64_t gid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const int64_t na4 = (int64_t)Rp * pa;
+    if (gid >= na4 + (int64_t)Rp * pb) return;
+    const bool A = gid < na4;
+    const int64_t k = A ? gid : gid - na4;
+    const uint32_t v = A ? MA4[k] : MB4[k];
+    int8_t *dst = (A ? MA : MB) + 2 * k;  // byte k of a packed row is sites 2k, 2k + 1 of the same row
+    dst[0] = fp4_value(v & 15u);
+    dst[1] = fp4_value(v >> 4);
+}
+
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+struct AccF4 {
+    v16f c00, c01, c10, c11;
+};
+
+// fp4 MFMA with unit block scales (E8M0 127): format 4 (e2m1) for both operands;
+// the 16 bytes of a fragment are the low half of the 32-byte operand.
+__device__ __forceinline__ v16f mfma_fp4(v4i a, v4i b, v16f c)
+{
+    const v8i a8 = {a[0], a[1], a[2], a[3], 0, 0, 0, 0};
+    const v8i b8 = {b[0], b[1], b[2], b[3], 0, 0, 0, 0};
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a8, b8, c, 4, 4, 0, 127, 0, 127);
+}
+
+template <int KT, int NS>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_bq_halfsweep_fp4(
+    const uint8_t *__restrict__ Mo, const uint8_t *__restrict__ Jx, const int8_t *__restrict__ hs,
+    uint8_t *__restrict__ Ms, const uint32_t *__restrict__ trow, int width, int Ns_p, int Ko, int tiles_s,
+    int xcd_bands, uint32_t site_base, uint32_t sweep, uint32_t rq0, uint32_t k0, uint32_t k1)
+{
+    // Ko: bytes per operand row (two K values per byte); Ms rows hold Ns_p / 2 bytes
+    using G = DmaGeom<KT, NS>;
+    constexpr int CH = G::CH;
+    constexpr int kPhxPerStage = G::subs;
+    constexpr int kPhxStages = 16 / kPhxPerStage;
+
+    extern __shared__ uint4 smem[];
+    int8_t *ring = reinterpret_cast<int8_t *>(smem);
+    uint32_t *T = reinterpret_cast<uint32_t *>(ring + G::lds);
+    for (int a = threadIdx.x; a < width; a += kThreads) T[a] = trow[a];
+
+    int ts, tr;
+    if (xcd_bands) {  // tiles_s % 8 == 0: XCD (= block id mod 8) owns tiles_s / 8 site tiles
+        const int per = tiles_s / 8;
+        const int slot = (int)blockIdx.x / 8;
+        ts = ((int)blockIdx.x % 8) * per + slot % per;
+        tr = slot / per;
+    } else {
+        ts = (int)blockIdx.x % tiles_s;
+        tr = (int)blockIdx.x / tiles_s;
+    }
+    const int r0 = tr * kT, s0 = ts * kT;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+
+    // DMA sources (fixed array bounds: the lambdas below capture these arrays by reference)
+    const uint8_t *srcA[4], *srcB[4];
+    static_assert(G::per_wave <= 4 && G::subs <= 4, "fixed array bounds");
+#pragma unroll
+    for (int j = 0; j < G::per_wave; ++j) {
+        const int S = 64 * (G::per_wave * wave + j) + lane;
+        const int r = S / CH, c = (S % CH) ^ swz<CH>(S / CH);
+        srcA[j] = Mo + (size_t)(r0 + r) * Ko + 16 * c;
+        srcB[j] = Jx + (size_t)(s0 + r) * Ko + 16 * c;
+    }
+    const int nk = Ko / KT;
+    auto issue = [&](int t) {
+        int8_t *dA = ring + (t % NS) * G::stage + 1024 * G::per_wave * wave;
+        int8_t *dB = dA + G::op;
+        const size_t k = (size_t)t * KT;
+#pragma unroll
+        for (int j = 0; j < G::per_wave; ++j) __builtin_amdgcn_global_load_lds(srcA[j] + k, dA + 1024 * j, 16, 0, 0);
+#pragma unroll
+        for (int j = 0; j < G::per_wave; ++j) __builtin_amdgcn_global_load_lds(srcB[j] + k, dB + 1024 * j, 16, 0, 0);
+    };
+    wait_vm<0>();  // the threshold row's loads, before any DMA is counted
+    for (int t = 0; t < NS - 1 && t < nk; ++t) issue(t);
+
+    const int wr = wave >> 1, wc = wave & 1;
+    const int ln = lane & 31, kg = lane >> 5;
+    int offA[2][4], offB[2][4];  // [row block][K step]
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int sub = 0; sub < G::subs; ++sub) {
+            const int ra = wr * 64 + 32 * b + ln, rb = wc * 64 + 32 * b + ln;
+            offA[b][sub] = KT * ra + 16 * ((2 * sub + kg) ^ swz<CH>(ra));
+            offB[b][sub] = G::op + KT * rb + 16 * ((2 * sub + kg) ^ swz<CH>(rb));
+        }
+    AccF4 acc;
+    acc.c00 = acc.c01 = acc.c10 = acc.c11 = v16f{0.f};
+    uint32_t words[16][4];
+
+    auto compute = [&](int t) {
+        const int8_t *st = ring + (t % NS) * G::stage;
+#pragma unroll
+        for (int sub = 0; sub < G::subs; ++sub) {
+            const v4i a0 = *reinterpret_cast<const v4i *>(st + offA[0][sub]);
+            const v4i a1 = *reinterpret_cast<const v4i *>(st + offA[1][sub]);
+            const v4i b0 = *reinterpret_cast<const v4i *>(st + offB[0][sub]);
+            const v4i b1 = *reinterpret_cast<const v4i *>(st + offB[1][sub]);
+            acc.c00 = mfma_fp4(a0, b0, acc.c00);
+            acc.c01 = mfma_fp4(a0, b1, acc.c01);
+            acc.c10 = mfma_fp4(a1, b0, acc.c10);
+            acc.c11 = mfma_fp4(a1, b1, acc.c11);
+        }
+    };
+    auto draw = [&](int blk) {
+        // block (bj * 2 + bi) * 4 + q covers site column bj and replica rows bi, q
+        const int bj = blk >> 3, bi = (blk >> 2) & 1, q = blk & 3;
+        const int site = s0 + wc * 64 + bj * 32 + ln;
+        const int r4 = r0 + wr * 64 + bi * 32 + 8 * q + 4 * kg;
+        const Block4 b = philox(site_base + (uint32_t)site, sweep, rq0 + (uint32_t)(r4 >> 2), kDomainSweep, k0, k1);
+        words[blk][0] = b.w[0];
+        words[blk][1] = b.w[1];
+        words[blk][2] = b.w[2];
+        words[blk][3] = b.w[3];
+    };
+
+    if (nk >= NS - 1) wait_vm<G::ahead>(); else wait_vm<0>();
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");  // LDS written by the DMA: no read may move above here
+
+    int t = 0;
+#pragma unroll
+    for (int u = 0; u < kPhxStages; ++u) {
+        if (t < nk) {
+            if (t + NS - 1 < nk) issue(t + NS - 1);
+            compute(t);
+#pragma unroll
+            for (int v = 0; v < kPhxPerStage; ++v) draw(kPhxPerStage * u + v);
+            if (t + NS - 1 < nk) wait_vm<G::ahead>(); else wait_vm<0>();
+            __builtin_amdgcn_s_barrier();
+            asm volatile("" ::: "memory");
+            ++t;
+        } else {
+#pragma unroll
+            for (int v = 0; v < kPhxPerStage; ++v) draw(kPhxPerStage * u + v);
+        }
+    }
+    for (; t + NS - 1 < nk; ++t) {
+        issue(t + NS - 1);
+        compute(t);
+        wait_vm<G::ahead>();
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+    }
+    for (; t < nk; ++t) {
+        compute(t);
+        wait_vm<0>();
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+    }
+
+    // epilogue: the fp4 codes of a group's four replicas are packed one per byte,
+    // transposed across the lane quad (sites s .. s + 3), and squeezed to four
+    // nibbles: each lane stores two bytes (four sites) of one replica row.
+    const int top = width - 1;
+    const int u4 = ln & 3;
+    const int rowbytes = Ns_p / 2;
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+        const int site = s0 + wc * 64 + bj * 32 + ln;
+        const int hval = hs[site];  // site < Ns_p: padded fields are zero
+        const int quad_col = site - u4;
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi) {
+            const v16f &c = bi == 0 ? (bj == 0 ? acc.c00 : acc.c01) : (bj == 0 ? acc.c10 : acc.c11);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int blk = (bj * 2 + bi) * 4 + q;
+                uint32_t packed = 0;
+#pragma unroll
+                for (int p = 0; p < 4; ++p) {
+                    const int I = (int)c[4 * q + p] + hval;  // an exact integer
+                    const int a = min(I >= 0 ? I : -I, top);
+                    packed |= fp4_code(decide(I, T[a], words[blk][p])) << (8 * p);
+                }
+                const uint32_t x = quad_transpose(packed, u4);      // four sites, one byte each
+                const uint32_t y = x | (x >> 4);                     // bytes 0 and 2: site pairs
+                const uint32_t nib = __builtin_amdgcn_perm(0u, y, 0x0C0C0200u);
+                const int r4 = r0 + wr * 64 + bi * 32 + 8 * q + 4 * kg;
+                *reinterpret_cast<uint16_t *>(Ms + (size_t)(r4 + u4) * rowbytes + quad_col / 2) = (uint16_t)nib;
+            }
+        }
+    }
+}
+
 // Field part of the energy: E[r] -= sum_i h_i m_i over both sides.
 __global__ __launch_bounds__(kThreads) void k_bq_field_energy(const int8_t *__restrict__ MA,
                                                               const int8_t *__restrict__ MB,
@@ -702,6 +963,75 @@ hipError_t bq_halfsweep(const BqView &p, int side, int8_t *MA, int8_t *MB, int R
     const size_t lds = sizeof(uint32_t) * (size_t)width;
     hipLaunchKernelGGL(k_bq_halfsweep<false>, grid, dim3(kThreads), lds, st, Mo, Jx, hs, Ms, trow, width, Ns, Ns_p,
                        Ko, R, site_base, sweep, rq0, key.k0, key.k1, (int32_t *)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t bq4_init(const BqView &p, uint8_t *MA4, uint8_t *MB4, int R, uint32_t rq0, Key key, hipStream_t st)
+{
+    const int64_t work = (int64_t)(p.na_p / 2 + p.nb_p / 2) * ((R + 3) / 4);
+    hipLaunchKernelGGL(k_bq4_init, dim3(blocks_for(work)), dim3(kThreads), 0, st, MA4, MB4, p.na, p.nb, p.na_p, p.nb_p,
+                       R, rq0, key.k0, key.k1);
+    return hipGetLastError();
+}
+
+hipError_t bq4_from_rows(const BqView &p, const int8_t *src_rn, int R, uint8_t *MA4, uint8_t *MB4, hipStream_t st)
+{
+    const int64_t work = (int64_t)R * ((p.na + 1) / 2 + (p.nb + 1) / 2);
+    hipLaunchKernelGGL(k_bq4_copy<true>, dim3(blocks_for(work)), dim3(kThreads), 0, st, const_cast<int8_t *>(src_rn),
+                       MA4, MB4, p.na, p.nb, p.na_p, p.nb_p, R);
+    return hipGetLastError();
+}
+
+hipError_t bq4_to_rows(const BqView &p, const uint8_t *MA4, const uint8_t *MB4, int8_t *dst_rn, int R, hipStream_t st)
+{
+    const int64_t work = (int64_t)R * ((p.na + 1) / 2 + (p.nb + 1) / 2);
+    hipLaunchKernelGGL(k_bq4_copy<false>, dim3(blocks_for(work)), dim3(kThreads), 0, st, dst_rn,
+                       const_cast<uint8_t *>(MA4), const_cast<uint8_t *>(MB4), p.na, p.nb, p.na_p, p.nb_p, R);
+    return hipGetLastError();
+}
+
+hipError_t bq4_unpack(const BqView &p, const uint8_t *MA4, const uint8_t *MB4, int8_t *MA, int8_t *MB, int Rp,
+                      hipStream_t st)
+{
+    const int64_t work = (int64_t)Rp * (p.na_p / 2 + p.nb_p / 2);
+    hipLaunchKernelGGL(k_bq4_unpack, dim3(blocks_for(work)), dim3(kThreads), 0, st, MA4, MB4, MA, MB, p.na_p, p.nb_p,
+                       Rp);
+    return hipGetLastError();
+}
+
+hipError_t bq4_halfsweep(const BqView &p, int side, uint8_t *MA4, uint8_t *MB4, int Rp, const uint32_t *trow,
+                         int width, uint32_t sweep, uint32_t rq0, Key key, hipStream_t st)
+{
+    if (!p.J4 || p.na_p % kT != 0 || p.nb_p % kT != 0 || Rp % kT != 0 || width < 1 || width > kMaxTableWidth)
+        return hipErrorInvalidValue;
+    static const hipError_t lds_attr = [] {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bq_halfsweep_fp4<128, 4>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           DmaGeom<128, 4>::lds + (int)sizeof(uint32_t) * kMaxTableWidth);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bq_halfsweep_fp4<64, 8>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    DmaGeom<64, 8>::lds + (int)sizeof(uint32_t) * kMaxTableWidth);
+        return e;
+    }();
+    if (lds_attr != hipSuccess) return lds_attr;
+    const bool A = side == 0;
+    const int Ns_p = A ? p.na_p : p.nb_p, Ko = (A ? p.nb_p : p.na_p) / 2;
+    const uint8_t *Mo = A ? MB4 : MA4;
+    const uint8_t *Jx = A ? p.J4 : p.JT4;
+    const int8_t *hs = A ? p.hA : p.hB;
+    uint8_t *Ms = A ? MA4 : MB4;
+    const uint32_t site_base = A ? 0u : (uint32_t)p.na;
+    const int tiles_s = Ns_p / kT, tiles_r = Rp / kT;
+    const dim3 grid((unsigned)(tiles_s * tiles_r));
+    const int bands = tiles_s % 8 == 0 ? 1 : 0;
+    const size_t tab = sizeof(uint32_t) * (size_t)width;
+    if (Ko % 128 == 0)
+        hipLaunchKernelGGL((k_bq_halfsweep_fp4<128, 4>), grid, dim3(kThreads), (DmaGeom<128, 4>::lds + tab), st, Mo,
+                           Jx, hs, Ms, trow, width, Ns_p, Ko, tiles_s, bands, site_base, sweep, rq0, key.k0, key.k1);
+    else
+        hipLaunchKernelGGL((k_bq_halfsweep_fp4<64, 8>), grid, dim3(kThreads), (DmaGeom<64, 8>::lds + tab), st, Mo, Jx,
+                           hs, Ms, trow, width, Ns_p, Ko, tiles_s, bands, site_base, sweep, rq0, key.k0, key.k1);
     return hipGetLastError();
 }
 

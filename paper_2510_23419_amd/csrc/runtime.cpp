@@ -186,9 +186,9 @@ extern "C" int pbit_create(pbit_ctx **out, int device, uint64_t hbm_budget_bytes
     if (!ctx) return fail(PBIT_E_NOMEM, "pbit_create: host allocation failed");
     ctx->device = device;
     ctx->budget = hbm_budget_bytes;
-    if (const char *v = std::getenv("PBIT_BQ_VARIANT")) {  // tuning override: 1..6 (see BqVariant)
+    if (const char *v = std::getenv("PBIT_BQ_VARIANT")) {  // tuning override: 1..7 (see BqVariant)
         const int k = std::atoi(v);
-        if (k >= 1 && k <= 6) ctx->bq_forced = (BqVariant)k;
+        if (k >= 1 && k <= 7) ctx->bq_forced = (BqVariant)k;
     }
     ctx->serial = g_ctx_serial.fetch_add(1);
     e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
@@ -332,17 +332,31 @@ static int load_biclique(pbit_ctx *ctx, const pbit_problem_desc *d, Problem &p)
         hB[b] = d->h ? d->h[na + b] : 0;
         amax = std::max(amax, colsum[b] + std::abs(hB[b]));
     }
-    void *dJ = nullptr, *dJT = nullptr, *dhA = nullptr, *dhB = nullptr;
+    void *dJ = nullptr, *dJT = nullptr, *dhA = nullptr, *dhB = nullptr, *dJ4 = nullptr, *dJT4 = nullptr;
     int rc = upload(ctx, p, J.data(), J.size(), &dJ);
     if (rc == PBIT_OK) rc = upload(ctx, p, JT.data(), JT.size(), &dJT);
     if (rc == PBIT_OK) rc = upload(ctx, p, hA.data(), hA.size(), &dhA);
     if (rc == PBIT_OK) rc = upload(ctx, p, hB.data(), hB.size(), &dhB);
+    if (rc == PBIT_OK && pad == kBqPadLarge) {
+        // packed 4-bit float couplings for the fp4 half-sweep: +1 = 0x2, -1 = 0xA, 0 = 0x0
+        auto code = [](int8_t v) { return (uint8_t)(v > 0 ? 0x2 : (v < 0 ? 0xA : 0x0)); };
+        auto pack = [&](const std::vector<int8_t> &M, int rows, int cols, std::vector<uint8_t> &out) {
+            out.assign((size_t)rows * cols / 2, 0);
+            for (size_t k = 0; k < out.size(); ++k)
+                out[k] = (uint8_t)(code(M[2 * k]) | (code(M[2 * k + 1]) << 4));  // rows have even length
+        };
+        std::vector<uint8_t> J4, JT4;
+        pack(J, na_p, nb_p, J4);
+        pack(JT, nb_p, na_p, JT4);
+        rc = upload(ctx, p, J4.data(), J4.size(), &dJ4);
+        if (rc == PBIT_OK) rc = upload(ctx, p, JT4.data(), JT4.size(), &dJT4);
+    }
     if (rc != PBIT_OK) return rc;
     p.kind = PBIT_BICLIQUE;
     p.N = (int64_t)na + nb;
     p.amax = amax;
     p.bq = BqView{na, nb, na_p, nb_p, (const int8_t *)dJ, (const int8_t *)dJT, (const int8_t *)dhA,
-                  (const int8_t *)dhB};
+                  (const int8_t *)dhB, (const uint8_t *)dJ4, (const uint8_t *)dJT4};
     return PBIT_OK;
 }
 
@@ -632,7 +646,9 @@ int spins_in_range(const int8_t *s, size_t n)
 struct DevState {
     int R = 0, Rp = 0;
     int8_t *spins = nullptr;  // EA: [N][Rp]
-    int8_t *MA = nullptr, *MB = nullptr;  // biclique
+    int8_t *MA = nullptr, *MB = nullptr;  // biclique (int8 spins; energy staging when fp4)
+    bool fp4 = false;                     // biclique spins held as packed 4-bit floats
+    uint8_t *MA4 = nullptr, *MB4 = nullptr;
     uint32_t *table = nullptr;
     int width = 1;
     int32_t *E32 = nullptr;
@@ -709,12 +725,28 @@ static int prepare(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, h
     } else {
         ds.Rp = round_up(R, kBqRPad);
         const size_t a = (size_t)ds.Rp * P.bq.na_p, b = (size_t)ds.Rp * P.bq.nb_p;
-        rc = scratch(ctx, Slot::Spins, a + b, &v);
-        if (rc) return rc;
-        ds.MA = (int8_t *)v;
-        ds.MB = ds.MA + a;
-        hipError_t e = hipMemsetAsync(ds.MA, 0, a + b, st);
-        if (e != hipSuccess) return device_fail(ctx, e, "hipMemsetAsync");
+        // packed 4-bit operands whenever the problem has them, unless an int8 kernel is forced
+        ds.fp4 = P.bq.J4 && (ctx->bq_forced == BqVariant::Auto || ctx->bq_forced == BqVariant::Fp4);
+        if (ds.fp4) {
+            rc = scratch(ctx, Slot::Spins, (a + b) / 2, &v);
+            if (rc) return rc;
+            ds.MA4 = (uint8_t *)v;
+            ds.MB4 = ds.MA4 + a / 2;
+            hipError_t e = hipMemsetAsync(ds.MA4, 0, (a + b) / 2, st);
+            if (e != hipSuccess) return device_fail(ctx, e, "hipMemsetAsync");
+            rc = scratch(ctx, Slot::Aux, a + b, &v);  // int8 copies for the energy kernels
+            if (rc) return rc;
+            ds.MA = (int8_t *)v;
+            ds.MB = ds.MA + a;
+            ds.variant = BqVariant::Fp4;
+        } else {
+            rc = scratch(ctx, Slot::Spins, a + b, &v);
+            if (rc) return rc;
+            ds.MA = (int8_t *)v;
+            ds.MB = ds.MA + a;
+            hipError_t e = hipMemsetAsync(ds.MA, 0, a + b, st);
+            if (e != hipSuccess) return device_fail(ctx, e, "hipMemsetAsync");
+        }
     }
     rc = scratch(ctx, Slot::E32, sizeof(int32_t) * (size_t)ds.Rp, &v);
     if (rc) return rc;
@@ -735,7 +767,7 @@ static int prepare(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, h
                                   hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return device_fail(ctx, e, "hipMemcpyAsync (table)");
 
-    if (P.kind == PBIT_BICLIQUE && d->n_sweeps > 0) {
+    if (P.kind == PBIT_BICLIQUE && !ds.fp4 && d->n_sweeps > 0) {
         rc = tune_biclique(ctx, P, ds, st);
         if (rc) return rc;
     }
@@ -752,11 +784,14 @@ static int prepare(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, h
         init_rows = ds.stage;
     }
     const bool rowlayout = P.kind != PBIT_BICLIQUE;  // cube and graph share the [N][Rp] layout
-    if (init_rows)
-        e = rowlayout ? ea_from_rows(P.ea, init_rows, R, ds.spins, ds.Rp, st)
-                      : bq_from_rows(P.bq, init_rows, R, ds.MA, ds.MB, st);
+    if (rowlayout)
+        e = init_rows ? ea_from_rows(P.ea, init_rows, R, ds.spins, ds.Rp, st)
+                      : ea_init(P.ea, ds.spins, ds.Rp, rq0, key, st);
+    else if (ds.fp4)
+        e = init_rows ? bq4_from_rows(P.bq, init_rows, R, ds.MA4, ds.MB4, st)
+                      : bq4_init(P.bq, ds.MA4, ds.MB4, R, rq0, key, st);
     else
-        e = rowlayout ? ea_init(P.ea, ds.spins, ds.Rp, rq0, key, st) : bq_init(P.bq, ds.MA, ds.MB, R, rq0, key, st);
+        e = init_rows ? bq_from_rows(P.bq, init_rows, R, ds.MA, ds.MB, st) : bq_init(P.bq, ds.MA, ds.MB, R, rq0, key, st);
     if (e != hipSuccess) return device_fail(ctx, e, "spin initialisation launch");
     return PBIT_OK;
 }
@@ -778,6 +813,8 @@ static hipError_t sweep(pbit_ctx *ctx, const Problem &P, DevState &ds, int s, ui
             e = ea_halfsweep(P.ea, ds.spins, ds.Rp, c, earow, t, rq0, key, st);
         else if (P.kind == PBIT_GRAPH)
             e = graph_halfsweep(P.graph, c, ds.spins, ds.Rp, row, ds.width, t, rq0, key, st);
+        else if (ds.fp4)
+            e = bq4_halfsweep(P.bq, c, ds.MA4, ds.MB4, ds.Rp, row, ds.width, t, rq0, key, st);
         else
             e = bq_halfsweep(P.bq, c, ds.MA, ds.MB, ds.R, ds.Rp, row, ds.width, t, rq0, key, st, ds.variant);
         if (e == hipSuccess) e = prof_count_launch(ctx, st);
@@ -788,14 +825,18 @@ static hipError_t sweep(pbit_ctx *ctx, const Problem &P, DevState &ds, int s, ui
 static hipError_t energies(const Problem &P, DevState &ds, hipStream_t st)
 {
     if (P.kind == PBIT_GRAPH) return graph_energy(P.graph, ds.spins, ds.Rp, ds.R, ds.E32, st);
-    return P.kind == PBIT_EA3D ? ea_energy(P.ea, ds.spins, ds.Rp, ds.R, ds.E32, st)
-                               : bq_energy(P.bq, ds.MA, ds.MB, ds.R, ds.Rp, ds.E32, st);
+    if (P.kind == PBIT_EA3D) return ea_energy(P.ea, ds.spins, ds.Rp, ds.R, ds.E32, st);
+    if (ds.fp4) {
+        hipError_t e = bq4_unpack(P.bq, ds.MA4, ds.MB4, ds.MA, ds.MB, ds.Rp, st);
+        if (e != hipSuccess) return e;
+    }
+    return bq_energy(P.bq, ds.MA, ds.MB, ds.R, ds.Rp, ds.E32, st);
 }
 
 static hipError_t to_rows(const Problem &P, DevState &ds, int8_t *dst, hipStream_t st)
 {
-    return P.kind != PBIT_BICLIQUE ? ea_to_rows(P.ea, ds.spins, ds.Rp, dst, ds.R, st)
-                                   : bq_to_rows(P.bq, ds.MA, ds.MB, dst, ds.R, st);
+    if (P.kind != PBIT_BICLIQUE) return ea_to_rows(P.ea, ds.spins, ds.Rp, dst, ds.R, st);
+    return ds.fp4 ? bq4_to_rows(P.bq, ds.MA4, ds.MB4, dst, ds.R, st) : bq_to_rows(P.bq, ds.MA, ds.MB, dst, ds.R, st);
 }
 
 static int fetch_energies(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStream_t st, std::vector<int32_t> &out)

@@ -26,7 +26,7 @@ struct Problem {
     int jobs = 0;  // serving jobs that still reference the problem
 };
 
-enum class Slot : int { Spins = 0, Table, E32, Stage, Count };
+enum class Slot : int { Spins = 0, Table, E32, Stage, Aux, Count };
 
 struct Scratch {
     void *ptr = nullptr;
