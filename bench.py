@@ -29,6 +29,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 INT8_MFMA_PEAK_TOPS = 5000.0   # MI355X dense int8 MFMA, published (TOP/s)
+FP4_MFMA_PEAK_TOPS = 10100.0   # MI355X dense fp4 MFMA, published (TOP/s)
 VALU_PEAK_TLANEOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 32-bit vector lane-ops/s: CUs x SIMDs x lanes x clock
 
 WORKLOADS = {
@@ -331,8 +332,12 @@ def main():
     else:
         n = w["n"]
         alg_ops = 2 * n * n * R  # one side's fields: n x n couplings times n x R spins
-        roof = {"bound": "mfma", "achieved": alg_ops / (avg_ms * 1e-3) / 1e12, "peak": INT8_MFMA_PEAK_TOPS,
-                "unit": "TOP/s", "traffic": None, "kernel": "k_bq_halfsweep",
+        # sides of 512 or more run on packed 4-bit float operands (the fp4 MFMA) unless
+        # an int8 kernel is forced; the roofline takes the peak of the dtype that ran
+        fp4 = n >= 512 and os.environ.get("PBIT_BQ_VARIANT", "0") in ("", "0", "7")
+        roof = {"bound": "mfma", "achieved": alg_ops / (avg_ms * 1e-3) / 1e12,
+                "peak": FP4_MFMA_PEAK_TOPS if fp4 else INT8_MFMA_PEAK_TOPS, "unit": "TOP/s", "traffic": None,
+                "kernel": "k_bq_halfsweep_fp4" if fp4 else "k_bq_halfsweep", "operands": "fp4" if fp4 else "int8",
                 "alg_ops_per_launch": alg_ops, "avg_launch_us": avg_ms * 1e3, "launches_timed": launches}
     if launches == 0:  # launch timing switched off (--profile-every 0)
         roof["achieved"] = None
@@ -365,7 +370,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int8",
+        "dtype": roof.get("operands", "int8"),
         "data": "synthetic",
         "config": {"workload": describe(w), "spins": N, "replicas": R, "sweeps": S,
                    "anneals_per_s": args.steps / wall, "device_ms_per_step": dev_ms / args.steps,
