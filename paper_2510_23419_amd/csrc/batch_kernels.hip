@@ -52,19 +52,29 @@ constexpr int kFieldSlots = 2 * kFieldOff + 1;
 
 __device__ __forceinline__ uint32_t neg2(uint32_t m, uint32_t keep, uint32_t flip) { return (m & keep) ^ flip; }
 
+// Sign mask of bit k of c: 0 or 0xFFFFFFFF.
+__device__ __forceinline__ uint32_t bit_mask(uint32_t c, int k) { return (uint32_t)((int32_t)(c << (31 - k)) >> 31); }
+
 // Spins of one 4-replica tile of the whole lattice live in LDS as one dword
-// per site (byte p = replica p, +1 = 0x01, -1 = 0xFF).
+// per site (byte p = replica p, +1 = 0x01, -1 = 0xFF).  The field and the
+// decision use the cube stencil's arithmetic: bit 4 of a spin byte marks -1,
+// one bitop3 per neighbour gives 0x10 per byte where J m = +1, and the sum
+// with the site's base byte is 8 (I + 7), the LDS byte offset of the word
+// S(I) (Tm for I >= 0, 2^32 - Tm for I < 0) whose sum with the random word
+// carries into bit 32 exactly when the new spin is -1.  `one` is 1 (passed in
+// so that w * one + S is a single v_mad_u64_u32).
 __global__ __launch_bounds__(kEaTileThreads) void k_ea_tiles(const EaJobDev *__restrict__ jobs,
                                                              const WorkItem *__restrict__ items,
                                                              const int32_t *__restrict__ n_items_p,
-                                                             int32_t *__restrict__ counter)
+                                                             int32_t *__restrict__ counter, uint32_t one)
 {
     extern __shared__ uint32_t sp[];
-    __shared__ uint4 dtab[kFieldSlots];
+    __shared__ uint64_t stab[kFieldSlots];
     __shared__ int32_t eacc[4];
     __shared__ int slot;
     const int tid = threadIdx.x;
     const int n_items = *n_items_p;
+    const char *tb = reinterpret_cast<const char *>(stab);
 
     for (;;) {
         const int it = take_item(counter, &slot);
@@ -94,9 +104,8 @@ __global__ __launch_bounds__(kEaTileThreads) void k_ea_tiles(const EaJobDev *__r
             if (tid < kFieldSlots) {
                 const uint32_t *trow = jb.table + (size_t)s * jb.width;
                 const int I = tid - kFieldOff;
-                const int a = min(I >= 0 ? I : -I, jb.width - 1);
-                const bool pos = I >= 0;
-                dtab[tid] = make_uint4(trow[a], pos ? 0xFFFFFFFFu : 0u, pos ? 0xFFu : 0x01u, pos ? 0x01u : 0xFFu);
+                const uint32_t T = trow[min(I >= 0 ? I : -I, jb.width - 1)];
+                stab[tid] = I >= 0 ? (uint64_t)T : ((uint64_t)1 << 32) - T;
             }
             __syncthreads();
             const uint32_t t = jb.sweep0 + (uint32_t)s;
@@ -114,22 +123,24 @@ __global__ __launch_bounds__(kEaTileThreads) void k_ea_tiles(const EaJobDev *__r
                                        z + 1 == Lz ? i - z * plane : i + plane,
                                        z == 0 ? i + (Lz - 1) * plane : i - plane};
                     const uint32_t code = jb.code[i];
-                    uint32_t cnt = 0;
-#pragma unroll
-                    for (int d = 0; d < 6; ++d)
-                        cnt += neg2(sp[nb[d]], ((code >> d) & 1u) * 0x02020202u,
-                                    ((code >> (kCodeFlipShift + d)) & 1u) * 0x02020202u);
                     const Block4 b = philox((uint32_t)i, t, rg, kDomainSweep, jb.k0, jb.k1);
-                    const int entry0 = ((int)(int8_t)(code >> kCodeBaseShift) + kFieldOff) * (int)sizeof(uint4);
-                    const uint32_t off16 = cnt << 4;  // bytes of cnt are <= 12
-                    const char *tb = reinterpret_cast<const char *>(dtab);
-                    uint32_t packed = 0;
+                    uint32_t idx = __builtin_amdgcn_perm(0u, code, 0x03030303u);  // base byte in every byte
+#pragma unroll
+                    for (int d = 0; d < 6; ++d) {
+                        const uint32_t F = bit_mask(code, kCodeFlipShift + d);
+                        const uint32_t K = bit_mask(code, d) & 0x10101010u;
+                        idx += __builtin_amdgcn_bitop3_b32(sp[nb[d]], F, K, 0x82);  // ~(a ^ b) & c
+                    }
+                    uint32_t sgn[4];  // 1: the replica's new spin is -1
 #pragma unroll
                     for (int p = 0; p < 4; ++p) {
-                        const uint4 e = *reinterpret_cast<const uint4 *>(tb + entry0 - (int)((off16 >> (8 * p)) & 0xFFu));
-                        packed |= ((b.w[p] ^ e.y) < e.x ? e.z : e.w) << (8 * p);
+                        const uint64_t S = *static_cast<const uint64_t *>(
+                            __builtin_assume_aligned(tb + ((idx >> (8 * p)) & 0xFFu), 8));
+                        sgn[p] = (uint32_t)(((uint64_t)b.w[p] * one + S) >> 32);
                     }
-                    sp[i] = packed;
+                    const uint32_t lo = __builtin_amdgcn_perm(sgn[1], sgn[0], 0x0C0C0400u);
+                    const uint32_t hi = __builtin_amdgcn_perm(sgn[3], sgn[2], 0x0C0C0400u);
+                    sp[i] = __builtin_amdgcn_perm(0u, 0xFF01u, __builtin_amdgcn_perm(hi, lo, 0x05040100u));
                 }
                 __syncthreads();
             }
@@ -375,7 +386,7 @@ hipError_t ea_tiles(const EaJobDev *jobs, const WorkItem *items, const int32_t *
                     size_t lds_bytes, hipStream_t st)
 {
     hipLaunchKernelGGL(k_ea_tiles, dim3((unsigned)grid), dim3(kEaTileThreads), lds_bytes, st, jobs, items, n_items,
-                       counter);
+                       counter, 1u);
     return hipGetLastError();
 }
 
