@@ -1,7 +1,7 @@
 // batch.h — device descriptors of the persistent batched sweep (many jobs in
 // one launch).  A job is one anneal (problem, schedule, replicas, seed).  It is
 // cut into replica tiles that never need each other: a cube tile is 4 replicas
-// of the whole lattice, a biclique tile is 32 or 64 replicas of both sides.
+// of the whole lattice, a biclique tile is 32, 64 or 128 replicas of both sides.
 // A work item advances one tile over a range of sweeps; a persistent kernel
 // pulls items from a queue until the queue is empty.
 #pragma once
@@ -23,10 +23,10 @@ struct EaJobDev {
 };
 
 struct BqJobDev {
-    const int8_t *J, *JT;   // [na_p][nb_p], [nb_p][na_p]
-    const int8_t *hA, *hB;  // [na_p], [nb_p]
-    const uint32_t *table;  // [S][width]
-    int8_t *state;          // [tiles][RS][na_p + nb_p]: row r = side A then side B
+    const uint8_t *J4, *JT4;  // packed 4-bit float couplings [na_p][nb_p / 2], [nb_p][na_p / 2]
+    const int8_t *hA, *hB;    // [na_p], [nb_p]
+    const uint32_t *table;    // [S][width]
+    uint8_t *state;           // [tiles][RS][(na_p + nb_p) / 2]: packed spins, row r = side A then side B
     int32_t *energy;        // [tiles * RS]
     int na, nb, na_p, nb_p, width;
     uint32_t sweep0, rq0, k0, k1;

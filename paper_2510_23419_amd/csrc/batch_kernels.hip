@@ -217,6 +217,31 @@ __device__ __forceinline__ uint32_t quad_transpose(uint32_t d, int u)
     return __builtin_amdgcn_perm(t2, d1, (u & 2) ? 0x03020706u : 0x05040100u);
 }
 
+__device__ __forceinline__ uint32_t fp4_code(int m) { return m > 0 ? 0x2u : (m < 0 ? 0xAu : 0x0u); }
+__device__ __forceinline__ int fp4_value(uint32_t nib) { return nib == 0 ? 0 : ((nib & 8u) ? -1 : 1); }
+
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+// fp4 MFMA with unit block scales (E8M0 127), e2m1 for both operands; the 16
+// bytes of a fragment are the low half of the 32-byte operand
+__device__ __forceinline__ v16f mfma_fp4(v4i a, v4i b, v16f c)
+{
+    const v8i a8 = {a[0], a[1], a[2], a[3], 0, 0, 0, 0};
+    const v8i b8 = {b[0], b[1], b[2], b[3], 0, 0, 0, 0};
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a8, b8, c, 4, 4, 0, 127, 0, 127);
+}
+
+// A tile holds RB x 32 replicas of both sides in LDS as packed 4-bit floats
+// (e2m1: +1 = 0x2, -1 = 0xA, 0 = 0x0; two sites per byte, lower site in the
+// low nibble), one row per replica: side A in bytes [0, na_p / 2), side B in
+// [na_p / 2, (na_p + nb_p) / 2).  Each half-sweep is an fp4 MFMA product of
+// the LDS rows with the packed couplings streamed from global memory (L2-
+// resident, shared by all tiles of the job) — exact, as every value is -1, 0
+// or +1 and every partial sum an integer below 2^24 — followed by the decision
+// epilogue writing the new side into LDS.  A byte of J carries two multiply-
+// adds and each J fragment feeds RB MFMAs, so larger tiles stream fewer bytes
+// per replica.
 template <int RB>
 __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__restrict__ jobs,
                                                              const WorkItem *__restrict__ items,
@@ -237,28 +262,37 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
         const WorkItem w = items[it];
         const BqJobDev jb = jobs[w.job];
         const int na = jb.na, nb = jb.nb, na_p = jb.na_p, nb_p = jb.nb_p;
-        const int P = na_p + nb_p, pitch = P + 16;
-        int8_t *sp = reinterpret_cast<int8_t *>(dyn);
+        const int pa = na_p / 2, pb = nb_p / 2;
+        const int P4 = pa + pb, pitch = P4 + 16;
+        uint8_t *sp = reinterpret_cast<uint8_t *>(dyn);
         uint32_t *T = reinterpret_cast<uint32_t *>(sp + (size_t)RS * pitch);
-        int8_t *gst = jb.state + (size_t)w.tile * RS * P;
+        uint8_t *gst = jb.state + (size_t)w.tile * RS * P4;
         const uint32_t rg0 = jb.rq0 + (uint32_t)(w.tile * (RS / 4));
 
         if (w.init) {
             for (int k = tid; k < RS * pitch / 16; k += kBqTileThreads) dyn[k] = make_uint4(0, 0, 0, 0);
             __syncthreads();
-            const int N = na + nb;
-            for (int k = tid; k < N * (RS / 4); k += kBqTileThreads) {
-                const int g = k % (RS / 4), i = k / (RS / 4);
-                const Block4 b = philox((uint32_t)i, 0u, rg0 + (uint32_t)g, kDomainInit, jb.k0, jb.k1);
-                const int col = i < na ? i : na_p + (i - na);
+            // thread (site pair, replica group): one byte in each of four rows
+            for (int k = tid; k < (pa + pb) * (RS / 4); k += kBqTileThreads) {
+                const int g = k % (RS / 4), pi = k / (RS / 4);
+                const bool A = pi < pa;
+                const int s0 = 2 * (A ? pi : pi - pa), n = A ? na : nb;
+                if (s0 >= n) continue;
+                const uint32_t i0 = (uint32_t)(A ? s0 : na + s0);
+                const Block4 b0 = philox(i0, 0u, rg0 + (uint32_t)g, kDomainInit, jb.k0, jb.k1);
+                const Block4 b1 = philox(i0 + 1u, 0u, rg0 + (uint32_t)g, kDomainInit, jb.k0, jb.k1);
 #pragma unroll
-                for (int p = 0; p < 4; ++p) sp[(4 * g + p) * pitch + col] = init_spin(b.w[p]);
+                for (int p = 0; p < 4; ++p) {
+                    const uint32_t lo = fp4_code(init_spin(b0.w[p]));
+                    const uint32_t hi = s0 + 1 < n ? fp4_code(init_spin(b1.w[p])) : 0u;
+                    sp[(4 * g + p) * pitch + pi] = (uint8_t)(lo | (hi << 4));
+                }
             }
         } else {
-            for (int k = tid; k < RS * (P / 16); k += kBqTileThreads) {
-                const int r = k / (P / 16), c16 = k % (P / 16);
+            for (int k = tid; k < RS * (P4 / 16); k += kBqTileThreads) {
+                const int r = k / (P4 / 16), c16 = k % (P4 / 16);
                 *reinterpret_cast<uint4 *>(sp + r * pitch + 16 * c16) =
-                    *reinterpret_cast<const uint4 *>(gst + (size_t)r * P + 16 * c16);
+                    *reinterpret_cast<const uint4 *>(gst + (size_t)r * P4 + 16 * c16);
             }
         }
         if (tid < RS) eacc[tid] = 0;
@@ -275,49 +309,62 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
             for (int side = 0; side < 2; ++side) {
                 const int ns_p = side == 0 ? na_p : nb_p;
                 const int ns = side == 0 ? na : nb;
-                const int ko = side == 0 ? nb_p : na_p;
-                const int in_col = side == 0 ? na_p : 0;   // columns of the other side (A operand)
-                const int out_col = side == 0 ? 0 : na_p;  // columns of this side
-                const int8_t *Jx = side == 0 ? jb.J : jb.JT;
+                const int ko = side == 0 ? pb : pa;         // bytes per coupling row (the other side, packed)
+                const int in_col = side == 0 ? pa : 0;      // bytes of the other side (A operand)
+                const int out_col = side == 0 ? 0 : pa;     // bytes of this side
+                const uint8_t *Jx = side == 0 ? jb.J4 : jb.JT4;
                 const int8_t *hs = side == 0 ? jb.hA : jb.hB;
                 const uint32_t site_base = side == 0 ? 0u : (uint32_t)na;
-                // one 32-site block per wave at a time; its J fragments stream from
-                // global memory through a ring kRing K-units (32 bytes) ahead
+                // one 32-site block per wave at a time; its coupling fragments stream
+                // from global memory through a ring kRing K-units (32 bytes) ahead.
+                // Past the end of a block the ring fills with the first units of the
+                // wave's next block, so that they arrive during this block's epilogue.
                 const int nku = ko / 32;
-                for (int blk = wave; blk < ns_p / 32; blk += kBqTileThreads / 64) {
+                constexpr int kStep = kBqTileThreads / 64;
+                const int nblk = ns_p / 32;
+                v4i ring[kRing];
+                if (wave < nblk) {
+                    const uint8_t *br0 = Jx + (size_t)(wave * 32 + ln) * ko + 16 * kg;
+#pragma unroll
+                    for (int u = 0; u < kRing; ++u) ring[u] = *reinterpret_cast<const v4i *>(br0 + 32 * min(u, nku - 1));
+                }
+                for (int blk = wave; blk < nblk; blk += kStep) {
                     const int site = blk * 32 + ln;
-                    const int8_t *br = Jx + (size_t)site * ko + 16 * kg;
-                    v4i ring[kRing];
+                    const uint8_t *br = Jx + (size_t)site * ko + 16 * kg;
+                    // the next block of this wave, or this one again when there is none
+                    const uint8_t *bn = blk + kStep < nblk ? br + (size_t)kStep * 32 * ko : br;
+                    v16f acc[RB];
 #pragma unroll
-                    for (int u = 0; u < kRing; ++u) ring[u] = *reinterpret_cast<const v4i *>(br + 32 * min(u, nku - 1));
-                    v16i acc[RB];
-#pragma unroll
-                    for (int rb = 0; rb < RB; ++rb) acc[rb] = v16i{0};
-                    const int8_t *abase = sp + ln * pitch + in_col + 16 * kg;
+                    for (int rb = 0; rb < RB; ++rb) acc[rb] = v16f{0.f};
+                    const uint8_t *abase = sp + ln * pitch + in_col + 16 * kg;
                     for (int kb = 0; kb < nku; kb += kRing) {
 #pragma unroll
                         for (int u = 0; u < kRing; ++u) {
                             const int ku = kb + u;
                             if (ku < nku) {
                                 const v4i b = ring[u];
-                                ring[u] = *reinterpret_cast<const v4i *>(br + 32 * min(ku + kRing, nku - 1));
+                                // slot u takes unit ku + kRing of this block, or, after this
+                                // block's last unit of its residue class, unit u of the next block
+                                const int kn = ku + kRing;
+                                ring[u] = *reinterpret_cast<const v4i *>(kn < nku ? br + 32 * kn
+                                                                                : bn + 32 * min(u, nku - 1));
 #pragma unroll
                                 for (int rb = 0; rb < RB; ++rb) {
                                     const v4i a = *reinterpret_cast<const v4i *>(abase + rb * 32 * pitch + 32 * ku);
-                                    acc[rb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, acc[rb], 0, 0, 0);
+                                    acc[rb] = mfma_fp4(a, b, acc[rb]);
                                 }
                             }
                         }
                     }
-                    // decisions; the four replicas of a group are packed into one dword,
-                    // then transposed across the lane quad (sites s..s+3) so that each
-                    // lane writes four consecutive sites of one replica row.  Padding
-                    // sites may take any value: their couplings and fields are zero
-                    // and they are never returned.
+                    // decisions: the fp4 codes of a group's four replicas, one per byte,
+                    // transposed across the lane quad (sites s .. s + 3) and squeezed to
+                    // nibbles, so that each lane writes two bytes of one replica row.
+                    // Padding sites may take any value: their couplings and fields are
+                    // zero and they are never returned.
                     const int hval = hs[site];  // site < ns_p: padded fields are zero
                     const bool site_ok = site < ns;
                     const int u4 = ln & 3;
-                    const int quad_col = out_col + site - u4;
+                    const int quad_col = out_col + (site - u4) / 2;
 #pragma unroll
                     for (int rb = 0; rb < RB; ++rb) {
 #pragma unroll
@@ -328,14 +375,17 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
                             uint32_t packed = 0;
 #pragma unroll
                             for (int p = 0; p < 4; ++p) {
-                                const int I = acc[rb][4 * q + p] + hval;
+                                const int I = (int)acc[rb][4 * q + p] + hval;  // an exact integer
                                 const int a = min(I >= 0 ? I : -I, top);
                                 const int8_t m = decide(I, T[a], b.w[p]);
-                                packed |= (uint32_t)(uint8_t)m << (8 * p);
+                                packed |= fp4_code(m) << (8 * p);
                                 // energy after the last side-B update: E = -sum_b m_b I_b - sum_a h_a m_a
                                 if (side == 1 && last && site_ok) atomicAdd(&eacc[r4 + p], -(int)m * I);
                             }
-                            *reinterpret_cast<uint32_t *>(sp + (r4 + u4) * pitch + quad_col) = quad_transpose(packed, u4);
+                            const uint32_t x = quad_transpose(packed, u4);  // four sites, one byte each
+                            const uint32_t y = x | (x >> 4);                 // bytes 0 and 2: site pairs
+                            *reinterpret_cast<uint16_t *>(sp + (r4 + u4) * pitch + quad_col) =
+                                (uint16_t)__builtin_amdgcn_perm(0u, y, 0x0C0C0200u);
                         }
                     }
                 }
@@ -346,14 +396,14 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
         // field part of side A, then the energies and the spins go back to global memory
         for (int k = tid; k < RS * na; k += kBqTileThreads) {
             const int r = k / na, a = k % na;
-            const int v = (int)jb.hA[a] * (int)sp[r * pitch + a];
+            const int v = (int)jb.hA[a] * fp4_value((sp[r * pitch + a / 2] >> (4 * (a & 1))) & 15u);
             if (v != 0) atomicAdd(&eacc[r], -v);
         }
         __syncthreads();
         if (tid < RS) jb.energy[w.tile * RS + tid] = eacc[tid];
-        for (int k = tid; k < RS * (P / 16); k += kBqTileThreads) {
-            const int r = k / (P / 16), c16 = k % (P / 16);
-            *reinterpret_cast<uint4 *>(gst + (size_t)r * P + 16 * c16) =
+        for (int k = tid; k < RS * (P4 / 16); k += kBqTileThreads) {
+            const int r = k / (P4 / 16), c16 = k % (P4 / 16);
+            *reinterpret_cast<uint4 *>(gst + (size_t)r * P4 + 16 * c16) =
                 *reinterpret_cast<const uint4 *>(sp + r * pitch + 16 * c16);
         }
     }
@@ -365,7 +415,7 @@ size_t ea_tile_lds(int64_t N) { return (size_t)N * sizeof(uint32_t); }
 
 size_t bq_tile_lds(int rs, int na_p, int nb_p, int width)
 {
-    return (size_t)rs * (size_t)(na_p + nb_p + 16) + sizeof(uint32_t) * (size_t)width;
+    return (size_t)rs * (size_t)((na_p + nb_p) / 2 + 16) + sizeof(uint32_t) * (size_t)width;
 }
 
 hipError_t tiles_set_lds_limit()
@@ -378,6 +428,9 @@ hipError_t tiles_set_lds_limit()
                                 hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
     if (e == hipSuccess)
         e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bq_tiles<2>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bq_tiles<4>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
     return e;
 }
@@ -393,7 +446,10 @@ hipError_t ea_tiles(const EaJobDev *jobs, const WorkItem *items, const int32_t *
 hipError_t bq_tiles(const BqJobDev *jobs, const WorkItem *items, const int32_t *n_items, int32_t *counter, int rs,
                     int grid, size_t lds_bytes, hipStream_t st)
 {
-    if (rs == 64)
+    if (rs == 128)
+        hipLaunchKernelGGL(k_bq_tiles<4>, dim3((unsigned)grid), dim3(kBqTileThreads), lds_bytes, st, jobs, items,
+                           n_items, counter);
+    else if (rs == 64)
         hipLaunchKernelGGL(k_bq_tiles<2>, dim3((unsigned)grid), dim3(kBqTileThreads), lds_bytes, st, jobs, items,
                            n_items, counter);
     else if (rs == 32)

@@ -14,9 +14,10 @@ struct BqView {
     const int8_t *hA;  // [na_p]
     const int8_t *hB;  // [nb_p]
     // the couplings as packed 4-bit floats (two per byte, lower index in the low
-    // nibble), present when both sides are padded to 128: [na_p][nb_p / 2], [nb_p][na_p / 2]
+    // nibble): [na_p][nb_p / 2], [nb_p][na_p / 2]
     const uint8_t *J4;
     const uint8_t *JT4;
+    bool fp4_sweep;  // both sides padded to 128: the per-instance half-sweep runs on fp4 operands
 };
 
 constexpr int kBqPad = 64;       // site padding of small biclique sides (MFMA K and N tiles)

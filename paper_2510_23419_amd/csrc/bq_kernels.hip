@@ -1002,7 +1002,8 @@ hipError_t bq4_unpack(const BqView &p, const uint8_t *MA4, const uint8_t *MB4, i
 hipError_t bq4_halfsweep(const BqView &p, int side, uint8_t *MA4, uint8_t *MB4, int Rp, const uint32_t *trow,
                          int width, uint32_t sweep, uint32_t rq0, Key key, hipStream_t st)
 {
-    if (!p.J4 || p.na_p % kT != 0 || p.nb_p % kT != 0 || Rp % kT != 0 || width < 1 || width > kMaxTableWidth)
+    if (!p.J4 || !p.fp4_sweep || p.na_p % kT != 0 || p.nb_p % kT != 0 || Rp % kT != 0 || width < 1 ||
+        width > kMaxTableWidth)
         return hipErrorInvalidValue;
     static const hipError_t lds_attr = [] {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bq_halfsweep_fp4<128, 4>),

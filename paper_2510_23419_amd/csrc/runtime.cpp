@@ -337,8 +337,9 @@ static int load_biclique(pbit_ctx *ctx, const pbit_problem_desc *d, Problem &p)
     if (rc == PBIT_OK) rc = upload(ctx, p, JT.data(), JT.size(), &dJT);
     if (rc == PBIT_OK) rc = upload(ctx, p, hA.data(), hA.size(), &dhA);
     if (rc == PBIT_OK) rc = upload(ctx, p, hB.data(), hB.size(), &dhB);
-    if (rc == PBIT_OK && pad == kBqPadLarge) {
-        // packed 4-bit float couplings for the fp4 half-sweep: +1 = 0x2, -1 = 0xA, 0 = 0x0
+    if (rc == PBIT_OK) {
+        // packed 4-bit float couplings (the batched tiles, and the half-sweep of large sides):
+        // +1 = 0x2, -1 = 0xA, 0 = 0x0
         auto code = [](int8_t v) { return (uint8_t)(v > 0 ? 0x2 : (v < 0 ? 0xA : 0x0)); };
         auto pack = [&](const std::vector<int8_t> &M, int rows, int cols, std::vector<uint8_t> &out) {
             out.assign((size_t)rows * cols / 2, 0);
@@ -356,7 +357,7 @@ static int load_biclique(pbit_ctx *ctx, const pbit_problem_desc *d, Problem &p)
     p.N = (int64_t)na + nb;
     p.amax = amax;
     p.bq = BqView{na, nb, na_p, nb_p, (const int8_t *)dJ, (const int8_t *)dJT, (const int8_t *)dhA,
-                  (const int8_t *)dhB, (const uint8_t *)dJ4, (const uint8_t *)dJT4};
+                  (const int8_t *)dhB, (const uint8_t *)dJ4, (const uint8_t *)dJT4, pad == kBqPadLarge};
     return PBIT_OK;
 }
 
@@ -726,7 +727,7 @@ static int prepare(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, h
         ds.Rp = round_up(R, kBqRPad);
         const size_t a = (size_t)ds.Rp * P.bq.na_p, b = (size_t)ds.Rp * P.bq.nb_p;
         // packed 4-bit operands whenever the problem has them, unless an int8 kernel is forced
-        ds.fp4 = P.bq.J4 && (ctx->bq_forced == BqVariant::Auto || ctx->bq_forced == BqVariant::Fp4);
+        ds.fp4 = P.bq.fp4_sweep && (ctx->bq_forced == BqVariant::Auto || ctx->bq_forced == BqVariant::Fp4);
         if (ds.fp4) {
             rc = scratch(ctx, Slot::Spins, (a + b) / 2, &v);
             if (rc) return rc;

@@ -29,6 +29,9 @@ int spins_in_range(const int8_t *s, size_t n);  // runtime.cpp
 namespace {
 
 constexpr int kMaxLdsTile = 160 * 1024 - 4096;
+constexpr int kKinds = 4;  // tile kinds: cube tiles; 128-, 64- and 32-replica biclique tiles
+inline int kind_of_rs(int rs) { return rs == 128 ? 1 : (rs == 64 ? 2 : 3); }
+inline int rs_of_kind(int k) { return k == 1 ? 128 : (k == 2 ? 64 : 32); }
 
 struct BJob {
     uint64_t id = 0;
@@ -58,15 +61,17 @@ struct ServeState {
     std::map<uint64_t, std::unique_ptr<BJob>> jobs;
     uint64_t next_id = 1;
     int max_queue = 4096, max_running = 1024, round_sweeps = 500;
-    hipStream_t st[3] = {nullptr, nullptr, nullptr};  // cube tiles, 64-replica and 32-replica biclique tiles
-    hipEvent_t fork = nullptr, join[3] = {nullptr, nullptr, nullptr};
+    // one stream per tile kind: cube tiles, then 128-, 64- and 32-replica biclique tiles
+    hipStream_t st[kKinds] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[kKinds] = {nullptr, nullptr, nullptr, nullptr};
     bool in_flight = false;
     std::vector<BJob *> round_jobs;
     std::vector<int> round_end;
     // device work lists (grown on demand)
-    void *d_ea_jobs = nullptr, *d_bq_jobs[2] = {nullptr, nullptr}, *d_items[3] = {nullptr, nullptr, nullptr};
-    size_t cap_ea_jobs = 0, cap_bq_jobs[2] = {0, 0}, cap_items[3] = {0, 0, 0};
-    int32_t *d_meta = nullptr;  // counters[3], n_items[3]
+    void *d_ea_jobs = nullptr, *d_bq_jobs[kKinds - 1] = {nullptr, nullptr, nullptr};
+    void *d_items[kKinds] = {nullptr, nullptr, nullptr, nullptr};
+    size_t cap_ea_jobs = 0, cap_bq_jobs[kKinds - 1] = {0, 0, 0}, cap_items[kKinds] = {0, 0, 0, 0};
+    int32_t *d_meta = nullptr;  // counters[kKinds], n_items[kKinds]
     bool lds_ready = false;
 };
 
@@ -93,9 +98,9 @@ static int serve_init(pbit_ctx *ctx)
     std::unique_ptr<ServeState> s(new (std::nothrow) ServeState());
     if (!s) return fail(PBIT_E_NOMEM, "serving state: host allocation failed");
     hipError_t e = hipSuccess;
-    for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipStreamCreateWithFlags(&s->st[k], hipStreamNonBlocking);
+    for (int k = 0; k < kKinds && e == hipSuccess; ++k) e = hipStreamCreateWithFlags(&s->st[k], hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->fork, hipEventDisableTiming);
-    for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&s->join[k], hipEventDisableTiming);
+    for (int k = 0; k < kKinds && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&s->join[k], hipEventDisableTiming);
     if (e != hipSuccess) return device_fail(ctx, e, "serving streams");
     void *meta = nullptr;
     int rc = dev_alloc(ctx, 64, &meta);
@@ -118,10 +123,10 @@ void serve_shutdown(pbit_ctx *ctx)
         if (j->P) j->P->jobs--;
     }
     dev_free(ctx, s->d_ea_jobs);
-    for (int k = 0; k < 2; ++k) dev_free(ctx, s->d_bq_jobs[k]);
-    for (int k = 0; k < 3; ++k) dev_free(ctx, s->d_items[k]);
+    for (int k = 0; k < kKinds - 1; ++k) dev_free(ctx, s->d_bq_jobs[k]);
+    for (int k = 0; k < kKinds; ++k) dev_free(ctx, s->d_items[k]);
     dev_free(ctx, s->d_meta);
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < kKinds; ++k) {
         if (s->st[k]) (void)hipStreamDestroy(s->st[k]);
         if (s->join[k]) (void)hipEventDestroy(s->join[k]);
     }
@@ -147,16 +152,20 @@ static int plan_job(pbit_ctx *ctx, BJob &j)
             return fail(PBIT_E_UNSUPPORTED, "cube of %lld sites is too large for a batched tile", (long long)P.N);
         j.rs = 4;
     } else {
+        // the largest tile the replicas fill and the LDS holds: larger tiles stream
+        // fewer coupling bytes per replica
         const int na_p = P.bq.na_p, nb_p = P.bq.nb_p;
-        if (j.R >= 64 && bq_tile_lds(64, na_p, nb_p, j.width) <= (size_t)kMaxLdsTile)
-            j.rs = 64;
-        else if (bq_tile_lds(32, na_p, nb_p, j.width) <= (size_t)kMaxLdsTile)
-            j.rs = 32;
-        else
+        j.rs = 0;
+        for (int rs : {128, 64, 32})
+            if ((j.R >= rs || rs == 32) && bq_tile_lds(rs, na_p, nb_p, j.width) <= (size_t)kMaxLdsTile) {
+                j.rs = rs;
+                break;
+            }
+        if (j.rs == 0)
             return fail(PBIT_E_UNSUPPORTED, "biclique %d x %d is too large for a batched tile", P.bq.na, P.bq.nb);
     }
     j.tiles = (j.R + j.rs - 1) / j.rs;
-    const size_t tile_bytes = P.kind == PBIT_EA3D ? (size_t)4 * j.N : (size_t)j.rs * (P.bq.na_p + P.bq.nb_p);
+    const size_t tile_bytes = P.kind == PBIT_EA3D ? (size_t)4 * j.N : (size_t)j.rs * (P.bq.na_p + P.bq.nb_p) / 2;
     j.bytes = sizeof(uint32_t) * (size_t)std::max(j.S, 1) * j.width + (size_t)j.tiles * tile_bytes +
               sizeof(int32_t) * (size_t)j.tiles * j.rs;
     const bool check = j.d.has_target || j.d.trace_every > 0;
@@ -175,12 +184,14 @@ static void rows_to_tiles(const BJob &j, const int8_t *rows, std::vector<int8_t>
         for (int r = 0; r < j.R; ++r)
             for (int i = 0; i < j.N; ++i) tiles_out[((size_t)(r / 4) * j.N + i) * 4 + (r % 4)] = rows[(size_t)r * j.N + i];
     } else {
-        const int Pw = P.bq.na_p + P.bq.nb_p;
+        // packed 4-bit floats: +1 = 0x2, -1 = 0xA, two sites per byte, lower site in the low nibble
+        const int Pw = (P.bq.na_p + P.bq.nb_p) / 2;
         tiles_out.assign((size_t)j.tiles * j.rs * Pw, 0);
         for (int r = 0; r < j.R; ++r)
             for (int i = 0; i < j.N; ++i) {
                 const int col = i < P.bq.na ? i : P.bq.na_p + (i - P.bq.na);
-                tiles_out[((size_t)(r / j.rs) * j.rs + (r % j.rs)) * Pw + col] = rows[(size_t)r * j.N + i];
+                const uint8_t code = rows[(size_t)r * j.N + i] > 0 ? 0x2 : 0xA;
+                tiles_out[((size_t)(r / j.rs) * j.rs + (r % j.rs)) * Pw + col / 2] |= (uint8_t)(code << (4 * (col & 1)));
             }
     }
 }
@@ -192,11 +203,13 @@ static void tiles_to_rows(const BJob &j, const int8_t *tl, int8_t *rows)
         for (int r = 0; r < j.R; ++r)
             for (int i = 0; i < j.N; ++i) rows[(size_t)r * j.N + i] = tl[((size_t)(r / 4) * j.N + i) * 4 + (r % 4)];
     } else {
-        const int Pw = P.bq.na_p + P.bq.nb_p;
+        const int Pw = (P.bq.na_p + P.bq.nb_p) / 2;
         for (int r = 0; r < j.R; ++r)
             for (int i = 0; i < j.N; ++i) {
                 const int col = i < P.bq.na ? i : P.bq.na_p + (i - P.bq.na);
-                rows[(size_t)r * j.N + i] = tl[((size_t)(r / j.rs) * j.rs + (r % j.rs)) * Pw + col];
+                const uint8_t v = (uint8_t)tl[((size_t)(r / j.rs) * j.rs + (r % j.rs)) * Pw + col / 2];
+                const int nib = (v >> (4 * (col & 1))) & 15;
+                rows[(size_t)r * j.N + i] = nib == 0 ? 0 : ((nib & 8) ? -1 : 1);
             }
     }
 }
@@ -205,7 +218,7 @@ static int admit(pbit_ctx *ctx, BJob &j)
 {
     int rc = dev_alloc(ctx, sizeof(uint32_t) * (size_t)std::max(j.S, 1) * j.width, &j.d_table);
     const size_t tile_bytes =
-        j.kind == PBIT_EA3D ? (size_t)4 * j.N : (size_t)j.rs * (j.P->bq.na_p + j.P->bq.nb_p);
+        j.kind == PBIT_EA3D ? (size_t)4 * j.N : (size_t)j.rs * (j.P->bq.na_p + j.P->bq.nb_p) / 2;
     if (rc == PBIT_OK) rc = dev_alloc(ctx, (size_t)j.tiles * tile_bytes, &j.d_state);
     if (rc == PBIT_OK) rc = dev_alloc(ctx, sizeof(int32_t) * (size_t)j.tiles * j.rs, &j.d_energy);
     if (rc != PBIT_OK) {
@@ -249,10 +262,10 @@ static int launch_round(pbit_ctx *ctx, ServeState &s)
     s.round_jobs.clear();
     s.round_end.clear();
     std::vector<EaJobDev> ea;
-    std::vector<BqJobDev> bq[2];
-    std::vector<WorkItem> items[3];
-    std::vector<double> cost[3];
-    size_t lds[3] = {0, 0, 0};
+    std::vector<BqJobDev> bq[kKinds - 1];
+    std::vector<WorkItem> items[kKinds];
+    std::vector<double> cost[kKinds];
+    size_t lds[kKinds] = {0, 0, 0, 0};
     for (BJob *j : s.running) {
         if (j->finished) continue;
         const int s0 = j->s_done;
@@ -275,8 +288,8 @@ static int launch_round(pbit_ctx *ctx, ServeState &s)
             lds[0] = std::max(lds[0], ea_tile_lds(j->N));
         } else {
             const BqView &v = j->P->bq;
-            const int k = j->rs == 64 ? 1 : 2;
-            BqJobDev jd{v.J, v.JT, v.hA, v.hB, (const uint32_t *)j->d_table, (int8_t *)j->d_state,
+            const int k = kind_of_rs(j->rs);
+            BqJobDev jd{v.J4, v.JT4, v.hA, v.hB, (const uint32_t *)j->d_table, (uint8_t *)j->d_state,
                         (int32_t *)j->d_energy, v.na, v.nb, v.na_p, v.nb_p, j->width,
                         (uint32_t)j->d.sweep_offset, (uint32_t)j->d.replica_offset >> 2, key.k0, key.k1};
             const int idx = (int)bq[k - 1].size();
@@ -291,7 +304,7 @@ static int launch_round(pbit_ctx *ctx, ServeState &s)
     if (s.round_jobs.empty()) return PBIT_OK;
 
     // longest items first, so that the persistent workgroups finish together
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < kKinds; ++k) {
         std::vector<size_t> ord(items[k].size());
         for (size_t q = 0; q < ord.size(); ++q) ord[q] = q;
         std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return cost[k][a] > cost[k][b]; });
@@ -300,9 +313,9 @@ static int launch_round(pbit_ctx *ctx, ServeState &s)
         items[k].swap(sorted);
     }
     int rc = grow(ctx, &s.d_ea_jobs, &s.cap_ea_jobs, sizeof(EaJobDev) * std::max<size_t>(ea.size(), 1));
-    for (int k = 0; k < 2 && rc == PBIT_OK; ++k)
+    for (int k = 0; k < kKinds - 1 && rc == PBIT_OK; ++k)
         rc = grow(ctx, &s.d_bq_jobs[k], &s.cap_bq_jobs[k], sizeof(BqJobDev) * std::max<size_t>(bq[k].size(), 1));
-    for (int k = 0; k < 3 && rc == PBIT_OK; ++k)
+    for (int k = 0; k < kKinds && rc == PBIT_OK; ++k)
         rc = grow(ctx, &s.d_items[k], &s.cap_items[k], sizeof(WorkItem) * std::max<size_t>(items[k].size(), 1));
     if (rc) return rc;
     if (!s.lds_ready) {
@@ -310,13 +323,14 @@ static int launch_round(pbit_ctx *ctx, ServeState &s)
         if (e != hipSuccess) return device_fail(ctx, e, "tile LDS limit");
         s.lds_ready = true;
     }
-    int32_t meta[6] = {0, 0, 0, (int32_t)items[0].size(), (int32_t)items[1].size(), (int32_t)items[2].size()};
+    int32_t meta[2 * kKinds] = {0};
+    for (int k = 0; k < kKinds; ++k) meta[kKinds + k] = (int32_t)items[k].size();
     hipError_t e = hipMemcpy(s.d_meta, meta, sizeof meta, hipMemcpyHostToDevice);
     if (e == hipSuccess && !ea.empty())
         e = hipMemcpy(s.d_ea_jobs, ea.data(), sizeof(EaJobDev) * ea.size(), hipMemcpyHostToDevice);
-    for (int k = 0; k < 2 && e == hipSuccess; ++k)
+    for (int k = 0; k < kKinds - 1 && e == hipSuccess; ++k)
         if (!bq[k].empty()) e = hipMemcpy(s.d_bq_jobs[k], bq[k].data(), sizeof(BqJobDev) * bq[k].size(), hipMemcpyHostToDevice);
-    for (int k = 0; k < 3 && e == hipSuccess; ++k)
+    for (int k = 0; k < kKinds && e == hipSuccess; ++k)
         if (!items[k].empty()) e = hipMemcpy(s.d_items[k], items[k].data(), sizeof(WorkItem) * items[k].size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return device_fail(ctx, e, "round upload");
 
@@ -324,17 +338,17 @@ static int launch_round(pbit_ctx *ctx, ServeState &s)
     e = hipGetDeviceProperties(&prop, ctx->device);
     if (e != hipSuccess) return device_fail(ctx, e, "hipGetDeviceProperties");
     const int cus = prop.multiProcessorCount;
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < kKinds; ++k) {
         if (items[k].empty()) continue;
         const size_t per_cu_lds = std::max<size_t>(lds[k] + 2048, 1);
         const int per_cu = std::max(1, std::min(4, (int)((160 * 1024) / per_cu_lds)));
         const int grid = std::max(1, std::min((int)items[k].size(), cus * per_cu));
         if (k == 0)
-            e = ea_tiles((const EaJobDev *)s.d_ea_jobs, (const WorkItem *)s.d_items[0], s.d_meta + 3, s.d_meta + 0,
-                         grid, lds[0], s.st[0]);
+            e = ea_tiles((const EaJobDev *)s.d_ea_jobs, (const WorkItem *)s.d_items[0], s.d_meta + kKinds,
+                         s.d_meta + 0, grid, lds[0], s.st[0]);
         else
-            e = bq_tiles((const BqJobDev *)s.d_bq_jobs[k - 1], (const WorkItem *)s.d_items[k], s.d_meta + 3 + k,
-                         s.d_meta + k, k == 1 ? 64 : 32, grid, lds[k], s.st[k]);
+            e = bq_tiles((const BqJobDev *)s.d_bq_jobs[k - 1], (const WorkItem *)s.d_items[k], s.d_meta + kKinds + k,
+                         s.d_meta + k, rs_of_kind(k), grid, lds[k], s.st[k]);
         if (e == hipSuccess) e = hipEventRecord(s.join[k], s.st[k]);
         if (e != hipSuccess) return device_fail(ctx, e, "tile kernel launch");
     }
@@ -344,7 +358,7 @@ static int launch_round(pbit_ctx *ctx, ServeState &s)
 
 static bool round_done(ServeState &s)
 {
-    for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < kKinds; ++k)
         if (hipEventQuery(s.join[k]) == hipErrorNotReady) return false;
     return true;
 }
@@ -352,7 +366,7 @@ static bool round_done(ServeState &s)
 static int harvest(pbit_ctx *ctx, ServeState &s)
 {
     hipError_t e = hipSuccess;
-    for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipStreamSynchronize(s.st[k]);
+    for (int k = 0; k < kKinds && e == hipSuccess; ++k) e = hipStreamSynchronize(s.st[k]);
     if (e != hipSuccess) return device_fail(ctx, e, "round");
     s.in_flight = false;
     std::vector<int32_t> tile_e;
@@ -439,7 +453,8 @@ static int new_job(pbit_ctx *ctx, ServeState &s, uint64_t problem, const pbit_an
 static int fill_result(pbit_ctx *ctx, BJob &j, pbit_result *res)
 {
     if (res && res->spins && j.d_state) {
-        const size_t tile_bytes = j.kind == PBIT_EA3D ? (size_t)4 * j.N : (size_t)j.rs * (j.P->bq.na_p + j.P->bq.nb_p);
+        const size_t tile_bytes =
+            j.kind == PBIT_EA3D ? (size_t)4 * j.N : (size_t)j.rs * (j.P->bq.na_p + j.P->bq.nb_p) / 2;
         std::vector<int8_t> tl((size_t)j.tiles * tile_bytes);
         hipError_t e = hipMemcpy(tl.data(), j.d_state, tl.size(), hipMemcpyDeviceToHost);
         if (e != hipSuccess) return device_fail(ctx, e, "spin readback");
