@@ -246,7 +246,7 @@ template <int RB>
 __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__restrict__ jobs,
                                                              const WorkItem *__restrict__ items,
                                                              const int32_t *__restrict__ n_items_p,
-                                                             int32_t *__restrict__ counter)
+                                                             int32_t *__restrict__ counter, uint32_t one)
 {
     constexpr int RS = 32 * RB;
     extern __shared__ uint4 dyn[];
@@ -265,7 +265,10 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
         const int pa = na_p / 2, pb = nb_p / 2;
         const int P4 = pa + pb, pitch = P4 + 16;
         uint8_t *sp = reinterpret_cast<uint8_t *>(dyn);
-        uint32_t *T = reinterpret_cast<uint32_t *>(sp + (size_t)RS * pitch);
+        // decision words of the sweep: S(I) = Tm(|I|) for I >= 0, 2^32 - Tm(|I|) for I < 0,
+        // I in [-top, top] (RS * pitch is a multiple of 16, so the words are aligned)
+        uint64_t *Sw = reinterpret_cast<uint64_t *>(sp + (size_t)RS * pitch);
+        const char *Sb = reinterpret_cast<const char *>(Sw);
         uint8_t *gst = jb.state + (size_t)w.tile * RS * P4;
         const uint32_t rg0 = jb.rq0 + (uint32_t)(w.tile * (RS / 4));
 
@@ -300,10 +303,14 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
         for (int s = w.s_begin; s < w.s_end; ++s) {
             __syncthreads();
             const uint32_t *trow = jb.table + (size_t)s * jb.width;
-            for (int a = tid; a < jb.width; a += kBqTileThreads) T[a] = trow[a];
+            const int top = jb.width - 1;
+            for (int e = tid; e <= 2 * top; e += kBqTileThreads) {
+                const int I = e - top;
+                const uint32_t Tm = trow[I >= 0 ? I : -I];
+                Sw[e] = I >= 0 ? (uint64_t)Tm : ((uint64_t)1 << 32) - Tm;
+            }
             __syncthreads();
             const uint32_t t = jb.sweep0 + (uint32_t)s;
-            const int top = jb.width - 1;
             const bool last = s + 1 == w.s_end;
 #pragma unroll
             for (int side = 0; side < 2; ++side) {
@@ -363,6 +370,8 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
                     // zero and they are never returned.
                     const int hval = hs[site];  // site < ns_p: padded fields are zero
                     const bool site_ok = site < ns;
+                    const int flo = -top - hval, fhi = top - hval;  // F range whose F + h is in [-top, top]
+                    const int base8 = 8 * (hval + top);
                     const int u4 = ln & 3;
                     const int quad_col = out_col + (site - u4) / 2;
 #pragma unroll
@@ -372,16 +381,23 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
                             const int r4 = rb * 32 + 8 * q + 4 * kg;  // first replica of the group in the tile
                             const Block4 b = philox(site_base + (uint32_t)site, t, rg0 + (uint32_t)(r4 >> 2),
                                                     kDomainSweep, jb.k0, jb.k1);
-                            uint32_t packed = 0;
+                            uint32_t sgn[4];  // 1: the replica's new spin is -1
 #pragma unroll
                             for (int p = 0; p < 4; ++p) {
-                                const int I = (int)acc[rb][4 * q + p] + hval;  // an exact integer
-                                const int a = min(I >= 0 ? I : -I, top);
-                                const int8_t m = decide(I, T[a], b.w[p]);
-                                packed |= fp4_code(m) << (8 * p);
+                                const int F = (int)acc[rb][4 * q + p];  // an exact integer
+                                const int Fc = min(max(F, flo), fhi);
+                                const uint64_t S = *static_cast<const uint64_t *>(
+                                    __builtin_assume_aligned(Sb + 8 * Fc + base8, 8));
+                                sgn[p] = (uint32_t)(((uint64_t)b.w[p] * one + S) >> 32);
                                 // energy after the last side-B update: E = -sum_b m_b I_b - sum_a h_a m_a
-                                if (side == 1 && last && site_ok) atomicAdd(&eacc[r4 + p], -(int)m * I);
+                                if (side == 1 && last && site_ok)
+                                    atomicAdd(&eacc[r4 + p], (sgn[p] ? 1 : -1) * (F + hval));
                             }
+                            const uint32_t lo = __builtin_amdgcn_perm(sgn[1], sgn[0], 0x0C0C0400u);
+                            const uint32_t hi = __builtin_amdgcn_perm(sgn[3], sgn[2], 0x0C0C0400u);
+                            // sign bit 0 -> +1 = 0x2, 1 -> -1 = 0xA
+                            const uint32_t packed =
+                                __builtin_amdgcn_perm(0u, 0x0A02u, __builtin_amdgcn_perm(hi, lo, 0x05040100u));
                             const uint32_t x = quad_transpose(packed, u4);  // four sites, one byte each
                             const uint32_t y = x | (x >> 4);                 // bytes 0 and 2: site pairs
                             *reinterpret_cast<uint16_t *>(sp + (r4 + u4) * pitch + quad_col) =
@@ -415,7 +431,8 @@ size_t ea_tile_lds(int64_t N) { return (size_t)N * sizeof(uint32_t); }
 
 size_t bq_tile_lds(int rs, int na_p, int nb_p, int width)
 {
-    return (size_t)rs * (size_t)((na_p + nb_p) / 2 + 16) + sizeof(uint32_t) * (size_t)width;
+    // packed spin rows, then one 64-bit decision word per field value in [-(width - 1), width - 1]
+    return (size_t)rs * (size_t)((na_p + nb_p) / 2 + 16) + sizeof(uint64_t) * (size_t)(2 * width - 1);
 }
 
 hipError_t tiles_set_lds_limit()
@@ -448,13 +465,13 @@ hipError_t bq_tiles(const BqJobDev *jobs, const WorkItem *items, const int32_t *
 {
     if (rs == 128)
         hipLaunchKernelGGL(k_bq_tiles<4>, dim3((unsigned)grid), dim3(kBqTileThreads), lds_bytes, st, jobs, items,
-                           n_items, counter);
+                           n_items, counter, 1u);
     else if (rs == 64)
         hipLaunchKernelGGL(k_bq_tiles<2>, dim3((unsigned)grid), dim3(kBqTileThreads), lds_bytes, st, jobs, items,
-                           n_items, counter);
+                           n_items, counter, 1u);
     else if (rs == 32)
         hipLaunchKernelGGL(k_bq_tiles<1>, dim3((unsigned)grid), dim3(kBqTileThreads), lds_bytes, st, jobs, items,
-                           n_items, counter);
+                           n_items, counter, 1u);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

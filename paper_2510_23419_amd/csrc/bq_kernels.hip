@@ -689,7 +689,7 @@ template <int KT, int NS>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_bq_halfsweep_fp4(
     const uint8_t *__restrict__ Mo, const uint8_t *__restrict__ Jx, const int8_t *__restrict__ hs,
     uint8_t *__restrict__ Ms, const uint32_t *__restrict__ trow, int width, int Ns_p, int Ko, int tiles_s,
-    int xcd_bands, uint32_t site_base, uint32_t sweep, uint32_t rq0, uint32_t k0, uint32_t k1)
+    int xcd_bands, uint32_t site_base, uint32_t sweep, uint32_t rq0, uint32_t k0, uint32_t k1, uint32_t one)
 {
     // Ko: bytes per operand row (two K values per byte); Ms rows hold Ns_p / 2 bytes
     using G = DmaGeom<KT, NS>;
@@ -814,16 +814,31 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         asm volatile("" ::: "memory");
     }
 
-    // epilogue: the fp4 codes of a group's four replicas are packed one per byte,
-    // transposed across the lane quad (sites s .. s + 3), and squeezed to four
-    // nibbles: each lane stores two bytes (four sites) of one replica row.
+    // decision words in the LDS the ring no longer needs: S(I) = Tm(|I|) for I >= 0 and
+    // 2^32 - Tm(|I|) for I < 0, I in [-top, top]; the new spin is -1 exactly when the
+    // sum of the random word and S(I) carries into bit 32 (|I| >= top shares Tm(top))
     const int top = width - 1;
+    uint64_t *Sw = reinterpret_cast<uint64_t *>(ring);
+    for (int e = threadIdx.x; e <= 2 * top; e += kThreads) {
+        const int I = e - top;
+        const uint32_t Tm = T[I >= 0 ? I : -I];
+        Sw[e] = I >= 0 ? (uint64_t)Tm : ((uint64_t)1 << 32) - Tm;
+    }
+    __syncthreads();
+    const char *Sb = reinterpret_cast<const char *>(Sw);
+
+    // epilogue: the field F of a replica and site indexes S(F + h) (clamped to
+    // [-top, top]); the sign bits of a group's four replicas become fp4 codes, one
+    // per byte, transposed across the lane quad (sites s .. s + 3) and squeezed to
+    // nibbles: each lane stores two bytes (four sites) of one replica row.
     const int u4 = ln & 3;
     const int rowbytes = Ns_p / 2;
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) {
         const int site = s0 + wc * 64 + bj * 32 + ln;
         const int hval = hs[site];  // site < Ns_p: padded fields are zero
+        const int flo = -top - hval, fhi = top - hval;  // F range whose F + h is in [-top, top]
+        const int base8 = 8 * (hval + top);
         const int quad_col = site - u4;
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi) {
@@ -831,13 +846,18 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int blk = (bj * 2 + bi) * 4 + q;
-                uint32_t packed = 0;
+                uint32_t sgn[4];
 #pragma unroll
                 for (int p = 0; p < 4; ++p) {
-                    const int I = (int)c[4 * q + p] + hval;  // an exact integer
-                    const int a = min(I >= 0 ? I : -I, top);
-                    packed |= fp4_code(decide(I, T[a], words[blk][p])) << (8 * p);
+                    const int F = (int)c[4 * q + p];  // an exact integer
+                    const int Fc = min(max(F, flo), fhi);
+                    const uint64_t S = *static_cast<const uint64_t *>(__builtin_assume_aligned(Sb + 8 * Fc + base8, 8));
+                    sgn[p] = (uint32_t)(((uint64_t)words[blk][p] * one + S) >> 32);
                 }
+                const uint32_t lo = __builtin_amdgcn_perm(sgn[1], sgn[0], 0x0C0C0400u);
+                const uint32_t hi = __builtin_amdgcn_perm(sgn[3], sgn[2], 0x0C0C0400u);
+                // sign bit 0 -> +1 = 0x2, 1 -> -1 = 0xA
+                const uint32_t packed = __builtin_amdgcn_perm(0u, 0x0A02u, __builtin_amdgcn_perm(hi, lo, 0x05040100u));
                 const uint32_t x = quad_transpose(packed, u4);      // four sites, one byte each
                 const uint32_t y = x | (x >> 4);                     // bytes 0 and 2: site pairs
                 const uint32_t nib = __builtin_amdgcn_perm(0u, y, 0x0C0C0200u);
@@ -1029,10 +1049,11 @@ hipError_t bq4_halfsweep(const BqView &p, int side, uint8_t *MA4, uint8_t *MB4, 
     const size_t tab = sizeof(uint32_t) * (size_t)width;
     if (Ko % 128 == 0)
         hipLaunchKernelGGL((k_bq_halfsweep_fp4<128, 4>), grid, dim3(kThreads), (DmaGeom<128, 4>::lds + tab), st, Mo,
-                           Jx, hs, Ms, trow, width, Ns_p, Ko, tiles_s, bands, site_base, sweep, rq0, key.k0, key.k1);
+                           Jx, hs, Ms, trow, width, Ns_p, Ko, tiles_s, bands, site_base, sweep, rq0, key.k0, key.k1,
+                           1u);
     else
         hipLaunchKernelGGL((k_bq_halfsweep_fp4<64, 8>), grid, dim3(kThreads), (DmaGeom<64, 8>::lds + tab), st, Mo, Jx,
-                           hs, Ms, trow, width, Ns_p, Ko, tiles_s, bands, site_base, sweep, rq0, key.k0, key.k1);
+                           hs, Ms, trow, width, Ns_p, Ko, tiles_s, bands, site_base, sweep, rq0, key.k0, key.k1, 1u);
     return hipGetLastError();
 }
 

@@ -31,6 +31,7 @@ namespace {
 constexpr int kMaxLdsTile = 160 * 1024 - 4096;
 constexpr int kKinds = 4;  // tile kinds: cube tiles; 128-, 64- and 32-replica biclique tiles
 inline int kind_of_rs(int rs) { return rs == 128 ? 1 : (rs == 64 ? 2 : 3); }
+constexpr double kItemOps = 1.5e11;  // multiply-adds of one biclique tile over its anneal
 inline int rs_of_kind(int k) { return k == 1 ? 128 : (k == 2 ? 64 : 32); }
 
 struct BJob {
@@ -152,15 +153,18 @@ static int plan_job(pbit_ctx *ctx, BJob &j)
             return fail(PBIT_E_UNSUPPORTED, "cube of %lld sites is too large for a batched tile", (long long)P.N);
         j.rs = 4;
     } else {
-        // the largest tile the replicas fill and the LDS holds: larger tiles stream
-        // fewer coupling bytes per replica
+        // the largest tile that the replicas fill, the LDS holds and whose whole anneal
+        // stays below kItemOps multiply-adds: larger tiles stream fewer coupling bytes
+        // per replica, but a tile is one workgroup for all of its sweeps, so a big job
+        // is cut into more, smaller tiles that run side by side
         const int na_p = P.bq.na_p, nb_p = P.bq.nb_p;
         j.rs = 0;
-        for (int rs : {128, 64, 32})
-            if ((j.R >= rs || rs == 32) && bq_tile_lds(rs, na_p, nb_p, j.width) <= (size_t)kMaxLdsTile) {
-                j.rs = rs;
-                break;
-            }
+        for (int rs : {128, 64, 32}) {
+            if (bq_tile_lds(rs, na_p, nb_p, j.width) > (size_t)kMaxLdsTile) continue;
+            j.rs = rs;  // the smallest that fits, if none passes the tests below
+            const double item = 2.0 * na_p * nb_p * rs * std::max(j.S, 1);
+            if ((j.R >= rs || rs == 32) && item <= kItemOps) break;
+        }
         if (j.rs == 0)
             return fail(PBIT_E_UNSUPPORTED, "biclique %d x %d is too large for a batched tile", P.bq.na, P.bq.nb);
     }
