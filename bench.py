@@ -150,7 +150,7 @@ def mixed_bag_bench(args, pbit, torch):
         "value": len(bag) / t_batch,
         "unit": "anneals/s",
         "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": t_batch * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "int8", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": "int8+fp4", "data": "synthetic",
         "config": {"workload": "mixed bag of %d jobs: 128 EA cubes L in {8,...,24}, 128 bicliques n in [64,1024], "
                                "replicas 32..512, sweeps 1000..5000, bag seed %d" % (len(bag), args.bag_seed),
                    "updates_per_s": updates / t_batch,
@@ -221,7 +221,7 @@ def serve_bench(args, pbit, torch):
         "value": len(lat) / makespan,
         "unit": "anneals/s",
         "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": makespan * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "int8", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": "int8+fp4", "data": "synthetic",
         "config": {"workload": "Poisson arrivals at %.0f jobs/s for %.0f s; jobs from a pool of %d instances "
                                "(EA cubes L <= 32, bicliques n <= 2048, 32..512 replicas, 1000..5000 sweeps); "
                                "target = best of 64 replicas + 1 %%" % (args.rate, args.duration, len(pool)),
