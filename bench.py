@@ -112,6 +112,12 @@ def measured_traffic(workload):
     return None if rec is None else float(rec["traffic_bytes_per_launch"])
 
 
+def _bag_dtype():
+    """Arithmetic of the batched tiles: int8 spins everywhere, biclique fields as
+    int8 MFMA products with int32 sums, or fp4 products (exact) on request."""
+    return "int8 (biclique fields fp4)" if os.environ.get("PBIT_BQ_VARIANT", "") == "7" else "int8"
+
+
 def mixed_bag_bench(args, pbit, torch):
     """Mixed bag: 256 jobs (128 cubes, L in {8..24}; 128 bicliques, n in
     [64, 1024]; 32..512 replicas; 1000..5000 sweeps) in the persistent batched
@@ -150,7 +156,7 @@ def mixed_bag_bench(args, pbit, torch):
         "value": len(bag) / t_batch,
         "unit": "anneals/s",
         "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": t_batch * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "int8+fp4", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": _bag_dtype(), "data": "synthetic",
         "config": {"workload": "mixed bag of %d jobs: 128 EA cubes L in {8,...,24}, 128 bicliques n in [64,1024], "
                                "replicas 32..512, sweeps 1000..5000, bag seed %d" % (len(bag), args.bag_seed),
                    "updates_per_s": updates / t_batch,
@@ -221,7 +227,7 @@ def serve_bench(args, pbit, torch):
         "value": len(lat) / makespan,
         "unit": "anneals/s",
         "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": makespan * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "int8+fp4", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": _bag_dtype(), "data": "synthetic",
         "config": {"workload": "Poisson arrivals at %.0f jobs/s for %.0f s; jobs from a pool of %d instances "
                                "(EA cubes L <= 32, bicliques n <= 2048, 32..512 replicas, 1000..5000 sweeps); "
                                "target = best of 64 replicas + 1 %%" % (args.rate, args.duration, len(pool)),
@@ -332,9 +338,10 @@ def main():
     else:
         n = w["n"]
         alg_ops = 2 * n * n * R  # one side's fields: n x n couplings times n x R spins
-        # sides of 512 or more run on packed 4-bit float operands (the fp4 MFMA) unless
-        # an int8 kernel is forced; the roofline takes the peak of the dtype that ran
-        fp4 = n >= 512 and os.environ.get("PBIT_BQ_VARIANT", "0") in ("", "0", "7")
+        # int8 operands with int32 accumulation by default; with PBIT_BQ_VARIANT=7 sides
+        # of 512 or more run on packed 4-bit float operands (the fp4 MFMA). The roofline
+        # takes the peak of the dtype that ran
+        fp4 = n >= 512 and os.environ.get("PBIT_BQ_VARIANT", "") == "7"
         roof = {"bound": "mfma", "achieved": alg_ops / (avg_ms * 1e-3) / 1e12,
                 "peak": FP4_MFMA_PEAK_TOPS if fp4 else INT8_MFMA_PEAK_TOPS, "unit": "TOP/s", "traffic": None,
                 "kernel": "k_bq_halfsweep_fp4" if fp4 else "k_bq_halfsweep", "operands": "fp4" if fp4 else "int8",

@@ -8,6 +8,8 @@
 // one launch.  The arithmetic, the Philox counters and the decision rule are
 // the same as in the per-instance kernels, so a job's result does not depend on
 // which items it was batched with.
+#include <type_traits>
+
 #include "batch.h"
 #include "device.h"
 #include "bq.h"
@@ -232,23 +234,26 @@ __device__ __forceinline__ v16f mfma_fp4(v4i a, v4i b, v16f c)
     return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a8, b8, c, 4, 4, 0, 127, 0, 127);
 }
 
-// A tile holds RB x 32 replicas of both sides in LDS as packed 4-bit floats
-// (e2m1: +1 = 0x2, -1 = 0xA, 0 = 0x0; two sites per byte, lower site in the
-// low nibble), one row per replica: side A in bytes [0, na_p / 2), side B in
-// [na_p / 2, (na_p + nb_p) / 2).  Each half-sweep is an fp4 MFMA product of
-// the LDS rows with the packed couplings streamed from global memory (L2-
-// resident, shared by all tiles of the job) — exact, as every value is -1, 0
-// or +1 and every partial sum an integer below 2^24 — followed by the decision
-// epilogue writing the new side into LDS.  A byte of J carries two multiply-
-// adds and each J fragment feeds RB MFMAs, so larger tiles stream fewer bytes
-// per replica.
-template <int RB>
+// A tile holds RB x 32 replicas of both sides in LDS, one row per replica:
+// side A first, then side B, zero padding.  With int8 operands (the default)
+// a row holds one byte per site and the half-sweep is the int8 MFMA with int32
+// accumulation; with FP4 operands a row holds packed 4-bit floats (e2m1: +1 =
+// 0x2, -1 = 0xA, 0 = 0x0; two sites per byte, lower site in the low nibble) and
+// the half-sweep is the f8f6f4 MFMA with fp32 accumulation — exact, since every
+// value is -1, 0 or +1 and every partial sum an integer below 2^24 — at half
+// the bytes per multiply-add.  Each half-sweep multiplies the LDS rows by the
+// couplings streamed from global memory (L2-resident, shared by all tiles of
+// the job); each coupling fragment feeds RB MFMAs, so larger tiles stream
+// fewer bytes per replica.  The decision epilogue writes the new side into LDS.
+template <int RB, bool FP4>
 __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__restrict__ jobs,
                                                              const WorkItem *__restrict__ items,
                                                              const int32_t *__restrict__ n_items_p,
                                                              int32_t *__restrict__ counter, uint32_t one)
 {
     constexpr int RS = 32 * RB;
+    constexpr int SH = FP4 ? 1 : 0;  // log2 of sites per byte
+    using Acc = typename std::conditional<FP4, v16f, v16i>::type;
     extern __shared__ uint4 dyn[];
     __shared__ int32_t eacc[RS];
     __shared__ int slot;
@@ -262,40 +267,44 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
         const WorkItem w = items[it];
         const BqJobDev jb = jobs[w.job];
         const int na = jb.na, nb = jb.nb, na_p = jb.na_p, nb_p = jb.nb_p;
-        const int pa = na_p / 2, pb = nb_p / 2;
-        const int P4 = pa + pb, pitch = P4 + 16;
+        const int pa = na_p >> SH, pb = nb_p >> SH;  // bytes of each side in a row
+        const int PR = pa + pb, pitch = PR + 16;
         uint8_t *sp = reinterpret_cast<uint8_t *>(dyn);
         // decision words of the sweep: S(I) = Tm(|I|) for I >= 0, 2^32 - Tm(|I|) for I < 0,
         // I in [-top, top] (RS * pitch is a multiple of 16, so the words are aligned)
         uint64_t *Sw = reinterpret_cast<uint64_t *>(sp + (size_t)RS * pitch);
         const char *Sb = reinterpret_cast<const char *>(Sw);
-        uint8_t *gst = jb.state + (size_t)w.tile * RS * P4;
+        uint8_t *gst = jb.state + (size_t)w.tile * RS * PR;
         const uint32_t rg0 = jb.rq0 + (uint32_t)(w.tile * (RS / 4));
 
         if (w.init) {
             for (int k = tid; k < RS * pitch / 16; k += kBqTileThreads) dyn[k] = make_uint4(0, 0, 0, 0);
             __syncthreads();
-            // thread (site pair, replica group): one byte in each of four rows
-            for (int k = tid; k < (pa + pb) * (RS / 4); k += kBqTileThreads) {
+            // thread (byte column, replica group): one byte in each of four rows
+            for (int k = tid; k < PR * (RS / 4); k += kBqTileThreads) {
                 const int g = k % (RS / 4), pi = k / (RS / 4);
                 const bool A = pi < pa;
-                const int s0 = 2 * (A ? pi : pi - pa), n = A ? na : nb;
+                const int s0 = (A ? pi : pi - pa) << SH, n = A ? na : nb;
                 if (s0 >= n) continue;
                 const uint32_t i0 = (uint32_t)(A ? s0 : na + s0);
                 const Block4 b0 = philox(i0, 0u, rg0 + (uint32_t)g, kDomainInit, jb.k0, jb.k1);
-                const Block4 b1 = philox(i0 + 1u, 0u, rg0 + (uint32_t)g, kDomainInit, jb.k0, jb.k1);
+                Block4 b1 = b0;
+                if (FP4 && s0 + 1 < n) b1 = philox(i0 + 1u, 0u, rg0 + (uint32_t)g, kDomainInit, jb.k0, jb.k1);
 #pragma unroll
                 for (int p = 0; p < 4; ++p) {
-                    const uint32_t lo = fp4_code(init_spin(b0.w[p]));
-                    const uint32_t hi = s0 + 1 < n ? fp4_code(init_spin(b1.w[p])) : 0u;
-                    sp[(4 * g + p) * pitch + pi] = (uint8_t)(lo | (hi << 4));
+                    uint32_t byte;
+                    if (FP4)
+                        byte = fp4_code(init_spin(b0.w[p])) | (s0 + 1 < n ? fp4_code(init_spin(b1.w[p])) << 4 : 0u);
+                    else
+                        byte = (uint32_t)(uint8_t)init_spin(b0.w[p]);
+                    sp[(4 * g + p) * pitch + pi] = (uint8_t)byte;
                 }
             }
         } else {
-            for (int k = tid; k < RS * (P4 / 16); k += kBqTileThreads) {
-                const int r = k / (P4 / 16), c16 = k % (P4 / 16);
+            for (int k = tid; k < RS * (PR / 16); k += kBqTileThreads) {
+                const int r = k / (PR / 16), c16 = k % (PR / 16);
                 *reinterpret_cast<uint4 *>(sp + r * pitch + 16 * c16) =
-                    *reinterpret_cast<const uint4 *>(gst + (size_t)r * P4 + 16 * c16);
+                    *reinterpret_cast<const uint4 *>(gst + (size_t)r * PR + 16 * c16);
             }
         }
         if (tid < RS) eacc[tid] = 0;
@@ -316,10 +325,11 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
             for (int side = 0; side < 2; ++side) {
                 const int ns_p = side == 0 ? na_p : nb_p;
                 const int ns = side == 0 ? na : nb;
-                const int ko = side == 0 ? pb : pa;         // bytes per coupling row (the other side, packed)
+                const int ko = side == 0 ? pb : pa;         // bytes per coupling row (the other side)
                 const int in_col = side == 0 ? pa : 0;      // bytes of the other side (A operand)
                 const int out_col = side == 0 ? 0 : pa;     // bytes of this side
-                const uint8_t *Jx = side == 0 ? jb.J4 : jb.JT4;
+                const uint8_t *Jx = FP4 ? (side == 0 ? jb.J4 : jb.JT4)
+                                        : reinterpret_cast<const uint8_t *>(side == 0 ? jb.J : jb.JT);
                 const int8_t *hs = side == 0 ? jb.hA : jb.hB;
                 const uint32_t site_base = side == 0 ? 0u : (uint32_t)na;
                 // one 32-site block per wave at a time; its coupling fragments stream
@@ -340,9 +350,9 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
                     const uint8_t *br = Jx + (size_t)site * ko + 16 * kg;
                     // the next block of this wave, or this one again when there is none
                     const uint8_t *bn = blk + kStep < nblk ? br + (size_t)kStep * 32 * ko : br;
-                    v16f acc[RB];
+                    Acc acc[RB];
 #pragma unroll
-                    for (int rb = 0; rb < RB; ++rb) acc[rb] = v16f{0.f};
+                    for (int rb = 0; rb < RB; ++rb) acc[rb] = Acc{0};
                     const uint8_t *abase = sp + ln * pitch + in_col + 16 * kg;
                     for (int kb = 0; kb < nku; kb += kRing) {
 #pragma unroll
@@ -358,14 +368,19 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
 #pragma unroll
                                 for (int rb = 0; rb < RB; ++rb) {
                                     const v4i a = *reinterpret_cast<const v4i *>(abase + rb * 32 * pitch + 32 * ku);
-                                    acc[rb] = mfma_fp4(a, b, acc[rb]);
+                                    if constexpr (FP4)
+                                        acc[rb] = mfma_fp4(a, b, acc[rb]);
+                                    else
+                                        acc[rb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, acc[rb], 0, 0, 0);
                                 }
                             }
                         }
                     }
-                    // decisions: the fp4 codes of a group's four replicas, one per byte,
-                    // transposed across the lane quad (sites s .. s + 3) and squeezed to
-                    // nibbles, so that each lane writes two bytes of one replica row.
+                    // decisions: the field F of a replica and site indexes S(F + h)
+                    // (clamped to [-top, top]); the sign bits of a group's four
+                    // replicas become spin codes, one per byte, transposed across the
+                    // lane quad (sites s .. s + 3) so that each lane writes four
+                    // consecutive sites of one replica row (two nibble bytes with FP4).
                     // Padding sites may take any value: their couplings and fields are
                     // zero and they are never returned.
                     const int hval = hs[site];  // site < ns_p: padded fields are zero
@@ -373,7 +388,7 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
                     const int flo = -top - hval, fhi = top - hval;  // F range whose F + h is in [-top, top]
                     const int base8 = 8 * (hval + top);
                     const int u4 = ln & 3;
-                    const int quad_col = out_col + (site - u4) / 2;
+                    const int quad_col = out_col + ((site - u4) >> SH);
 #pragma unroll
                     for (int rb = 0; rb < RB; ++rb) {
 #pragma unroll
@@ -395,13 +410,17 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
                             }
                             const uint32_t lo = __builtin_amdgcn_perm(sgn[1], sgn[0], 0x0C0C0400u);
                             const uint32_t hi = __builtin_amdgcn_perm(sgn[3], sgn[2], 0x0C0C0400u);
-                            // sign bit 0 -> +1 = 0x2, 1 -> -1 = 0xA
-                            const uint32_t packed =
-                                __builtin_amdgcn_perm(0u, 0x0A02u, __builtin_amdgcn_perm(hi, lo, 0x05040100u));
+                            // sign bit 0 -> +1, 1 -> -1: 0x01 / 0xFF bytes, or 0x2 / 0xA codes
+                            const uint32_t packed = __builtin_amdgcn_perm(0u, FP4 ? 0x0A02u : 0xFF01u,
+                                                                          __builtin_amdgcn_perm(hi, lo, 0x05040100u));
                             const uint32_t x = quad_transpose(packed, u4);  // four sites, one byte each
-                            const uint32_t y = x | (x >> 4);                 // bytes 0 and 2: site pairs
-                            *reinterpret_cast<uint16_t *>(sp + (r4 + u4) * pitch + quad_col) =
-                                (uint16_t)__builtin_amdgcn_perm(0u, y, 0x0C0C0200u);
+                            if constexpr (FP4) {
+                                const uint32_t y = x | (x >> 4);  // bytes 0 and 2: site pairs
+                                *reinterpret_cast<uint16_t *>(sp + (r4 + u4) * pitch + quad_col) =
+                                    (uint16_t)__builtin_amdgcn_perm(0u, y, 0x0C0C0200u);
+                            } else {
+                                *reinterpret_cast<uint32_t *>(sp + (r4 + u4) * pitch + quad_col) = x;
+                            }
                         }
                     }
                 }
@@ -412,14 +431,19 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
         // field part of side A, then the energies and the spins go back to global memory
         for (int k = tid; k < RS * na; k += kBqTileThreads) {
             const int r = k / na, a = k % na;
-            const int v = (int)jb.hA[a] * fp4_value((sp[r * pitch + a / 2] >> (4 * (a & 1))) & 15u);
+            int m;
+            if (FP4)
+                m = fp4_value((sp[r * pitch + a / 2] >> (4 * (a & 1))) & 15u);
+            else
+                m = (int)(int8_t)sp[r * pitch + a];
+            const int v = (int)jb.hA[a] * m;
             if (v != 0) atomicAdd(&eacc[r], -v);
         }
         __syncthreads();
         if (tid < RS) jb.energy[w.tile * RS + tid] = eacc[tid];
-        for (int k = tid; k < RS * (P4 / 16); k += kBqTileThreads) {
-            const int r = k / (P4 / 16), c16 = k % (P4 / 16);
-            *reinterpret_cast<uint4 *>(gst + (size_t)r * P4 + 16 * c16) =
+        for (int k = tid; k < RS * (PR / 16); k += kBqTileThreads) {
+            const int r = k / (PR / 16), c16 = k % (PR / 16);
+            *reinterpret_cast<uint4 *>(gst + (size_t)r * PR + 16 * c16) =
                 *reinterpret_cast<const uint4 *>(sp + r * pitch + 16 * c16);
         }
     }
@@ -429,10 +453,11 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
 
 size_t ea_tile_lds(int64_t N) { return (size_t)N * sizeof(uint32_t); }
 
-size_t bq_tile_lds(int rs, int na_p, int nb_p, int width)
+size_t bq_tile_lds(int rs, int na_p, int nb_p, int width, bool fp4)
 {
-    // packed spin rows, then one 64-bit decision word per field value in [-(width - 1), width - 1]
-    return (size_t)rs * (size_t)((na_p + nb_p) / 2 + 16) + sizeof(uint64_t) * (size_t)(2 * width - 1);
+    // spin rows, then one 64-bit decision word per field value in [-(width - 1), width - 1]
+    const size_t row = (size_t)(fp4 ? (na_p + nb_p) / 2 : na_p + nb_p) + 16;
+    return (size_t)rs * row + sizeof(uint64_t) * (size_t)(2 * width - 1);
 }
 
 hipError_t tiles_set_lds_limit()
@@ -440,15 +465,14 @@ hipError_t tiles_set_lds_limit()
     const int max_lds = 160 * 1024 - 4096;  // leave room for the static shared variables
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ea_tiles),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bq_tiles<1>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bq_tiles<2>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bq_tiles<4>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+    const void *bq_kernels[] = {reinterpret_cast<const void *>(&k_bq_tiles<1, false>),
+                                reinterpret_cast<const void *>(&k_bq_tiles<2, false>),
+                                reinterpret_cast<const void *>(&k_bq_tiles<4, false>),
+                                reinterpret_cast<const void *>(&k_bq_tiles<1, true>),
+                                reinterpret_cast<const void *>(&k_bq_tiles<2, true>),
+                                reinterpret_cast<const void *>(&k_bq_tiles<4, true>)};
+    for (const void *k : bq_kernels)
+        if (e == hipSuccess) e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
     return e;
 }
 
@@ -461,19 +485,21 @@ hipError_t ea_tiles(const EaJobDev *jobs, const WorkItem *items, const int32_t *
 }
 
 hipError_t bq_tiles(const BqJobDev *jobs, const WorkItem *items, const int32_t *n_items, int32_t *counter, int rs,
-                    int grid, size_t lds_bytes, hipStream_t st)
+                    bool fp4, int grid, size_t lds_bytes, hipStream_t st)
 {
-    if (rs == 128)
-        hipLaunchKernelGGL(k_bq_tiles<4>, dim3((unsigned)grid), dim3(kBqTileThreads), lds_bytes, st, jobs, items,
-                           n_items, counter, 1u);
-    else if (rs == 64)
-        hipLaunchKernelGGL(k_bq_tiles<2>, dim3((unsigned)grid), dim3(kBqTileThreads), lds_bytes, st, jobs, items,
-                           n_items, counter, 1u);
-    else if (rs == 32)
-        hipLaunchKernelGGL(k_bq_tiles<1>, dim3((unsigned)grid), dim3(kBqTileThreads), lds_bytes, st, jobs, items,
-                           n_items, counter, 1u);
-    else
+#define PBIT_BQ_TILES(RB, F)                                                                                    \
+    hipLaunchKernelGGL((k_bq_tiles<RB, F>), dim3((unsigned)grid), dim3(kBqTileThreads), lds_bytes, st, jobs, items, \
+                       n_items, counter, 1u)
+    if (rs == 128) {
+        if (fp4) PBIT_BQ_TILES(4, true); else PBIT_BQ_TILES(4, false);
+    } else if (rs == 64) {
+        if (fp4) PBIT_BQ_TILES(2, true); else PBIT_BQ_TILES(2, false);
+    } else if (rs == 32) {
+        if (fp4) PBIT_BQ_TILES(1, true); else PBIT_BQ_TILES(1, false);
+    } else {
         return hipErrorInvalidValue;
+    }
+#undef PBIT_BQ_TILES
     return hipGetLastError();
 }
 

@@ -662,7 +662,7 @@ struct DevState {
 // initialised) spin buffers, whose contents do not affect the timing.
 static int tune_biclique(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStream_t st)
 {
-    if (ctx->bq_forced != BqVariant::Auto) {
+    if (ctx->bq_forced != BqVariant::Auto && ctx->bq_forced != BqVariant::Fp4) {
         ds.variant = ctx->bq_forced;
         return PBIT_OK;
     }
@@ -726,8 +726,8 @@ static int prepare(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, h
     } else {
         ds.Rp = round_up(R, kBqRPad);
         const size_t a = (size_t)ds.Rp * P.bq.na_p, b = (size_t)ds.Rp * P.bq.nb_p;
-        // packed 4-bit operands whenever the problem has them, unless an int8 kernel is forced
-        ds.fp4 = P.bq.fp4_sweep && (ctx->bq_forced == BqVariant::Auto || ctx->bq_forced == BqVariant::Fp4);
+        // int8 operands by default; packed 4-bit float operands on request, for sides padded to 128
+        ds.fp4 = P.bq.fp4_sweep && ctx->bq_forced == BqVariant::Fp4;
         if (ds.fp4) {
             rc = scratch(ctx, Slot::Spins, (a + b) / 2, &v);
             if (rc) return rc;

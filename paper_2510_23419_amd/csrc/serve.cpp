@@ -43,6 +43,7 @@ struct BJob {
     std::vector<int8_t> init;
     int kind = 0, N = 0, R = 0, S = 0;
     int rs = 4, tiles = 0, width = 1, chunk = 1;
+    bool fp4 = false;  // biclique tiles on packed 4-bit float operands (else int8)
     // device memory (released when the job finishes)
     void *d_table = nullptr, *d_state = nullptr, *d_energy = nullptr;
     size_t bytes = 0;
@@ -138,6 +139,14 @@ void serve_shutdown(pbit_ctx *ctx)
 
 // ---------------------------------------------------------------- job set-up
 
+// Bytes of one biclique replica row in a tile: one byte per site, or two sites per byte.
+static int bq_row_bytes(const BJob &j) { return j.fp4 ? (j.P->bq.na_p + j.P->bq.nb_p) / 2 : j.P->bq.na_p + j.P->bq.nb_p; }
+
+static size_t tile_bytes(const BJob &j)
+{
+    return j.kind == PBIT_EA3D ? (size_t)4 * j.N : (size_t)j.rs * bq_row_bytes(j);
+}
+
 static int plan_job(pbit_ctx *ctx, BJob &j)
 {
     const Problem &P = *j.P;
@@ -146,6 +155,7 @@ static int plan_job(pbit_ctx *ctx, BJob &j)
     j.R = j.d.n_replicas;
     j.S = j.d.n_sweeps;
     j.width = j.S > 0 ? table_width(j.beta.data(), j.S, P.amax) : 1;
+    j.fp4 = P.kind == PBIT_BICLIQUE && ctx->bq_forced == BqVariant::Fp4;
     if (j.width > kMaxTableWidth) return fail(PBIT_E_UNSUPPORTED, "threshold rows of %d entries are too wide", j.width);
     if (P.kind == PBIT_GRAPH) return fail(PBIT_E_UNSUPPORTED, "general graphs run through pbit_anneal only");
     if (P.kind == PBIT_EA3D) {
@@ -160,7 +170,7 @@ static int plan_job(pbit_ctx *ctx, BJob &j)
         const int na_p = P.bq.na_p, nb_p = P.bq.nb_p;
         j.rs = 0;
         for (int rs : {128, 64, 32}) {
-            if (bq_tile_lds(rs, na_p, nb_p, j.width) > (size_t)kMaxLdsTile) continue;
+            if (bq_tile_lds(rs, na_p, nb_p, j.width, j.fp4) > (size_t)kMaxLdsTile) continue;
             j.rs = rs;  // the smallest that fits, if none passes the tests below
             const double item = 2.0 * na_p * nb_p * rs * std::max(j.S, 1);
             if ((j.R >= rs || rs == 32) && item <= kItemOps) break;
@@ -169,8 +179,7 @@ static int plan_job(pbit_ctx *ctx, BJob &j)
             return fail(PBIT_E_UNSUPPORTED, "biclique %d x %d is too large for a batched tile", P.bq.na, P.bq.nb);
     }
     j.tiles = (j.R + j.rs - 1) / j.rs;
-    const size_t tile_bytes = P.kind == PBIT_EA3D ? (size_t)4 * j.N : (size_t)j.rs * (P.bq.na_p + P.bq.nb_p) / 2;
-    j.bytes = sizeof(uint32_t) * (size_t)std::max(j.S, 1) * j.width + (size_t)j.tiles * tile_bytes +
+    j.bytes = sizeof(uint32_t) * (size_t)std::max(j.S, 1) * j.width + (size_t)j.tiles * tile_bytes(j) +
               sizeof(int32_t) * (size_t)j.tiles * j.rs;
     const bool check = j.d.has_target || j.d.trace_every > 0;
     j.chunk = check ? (j.d.trace_every > 0 ? j.d.trace_every : PBIT_CHECK_SWEEPS) : std::max(j.S, 1);
@@ -188,14 +197,19 @@ static void rows_to_tiles(const BJob &j, const int8_t *rows, std::vector<int8_t>
         for (int r = 0; r < j.R; ++r)
             for (int i = 0; i < j.N; ++i) tiles_out[((size_t)(r / 4) * j.N + i) * 4 + (r % 4)] = rows[(size_t)r * j.N + i];
     } else {
-        // packed 4-bit floats: +1 = 0x2, -1 = 0xA, two sites per byte, lower site in the low nibble
-        const int Pw = (P.bq.na_p + P.bq.nb_p) / 2;
+        // int8 spins, or packed 4-bit floats: +1 = 0x2, -1 = 0xA, two sites per byte,
+        // lower site in the low nibble
+        const int Pw = bq_row_bytes(j);
         tiles_out.assign((size_t)j.tiles * j.rs * Pw, 0);
         for (int r = 0; r < j.R; ++r)
             for (int i = 0; i < j.N; ++i) {
                 const int col = i < P.bq.na ? i : P.bq.na_p + (i - P.bq.na);
-                const uint8_t code = rows[(size_t)r * j.N + i] > 0 ? 0x2 : 0xA;
-                tiles_out[((size_t)(r / j.rs) * j.rs + (r % j.rs)) * Pw + col / 2] |= (uint8_t)(code << (4 * (col & 1)));
+                const int8_t m = rows[(size_t)r * j.N + i] > 0 ? 1 : -1;
+                const size_t row = (size_t)(r / j.rs) * j.rs + (r % j.rs);
+                if (j.fp4)
+                    tiles_out[row * Pw + col / 2] |= (uint8_t)((m > 0 ? 0x2 : 0xA) << (4 * (col & 1)));
+                else
+                    tiles_out[row * Pw + col] = m;
             }
     }
 }
@@ -207,13 +221,17 @@ static void tiles_to_rows(const BJob &j, const int8_t *tl, int8_t *rows)
         for (int r = 0; r < j.R; ++r)
             for (int i = 0; i < j.N; ++i) rows[(size_t)r * j.N + i] = tl[((size_t)(r / 4) * j.N + i) * 4 + (r % 4)];
     } else {
-        const int Pw = (P.bq.na_p + P.bq.nb_p) / 2;
+        const int Pw = bq_row_bytes(j);
         for (int r = 0; r < j.R; ++r)
             for (int i = 0; i < j.N; ++i) {
                 const int col = i < P.bq.na ? i : P.bq.na_p + (i - P.bq.na);
-                const uint8_t v = (uint8_t)tl[((size_t)(r / j.rs) * j.rs + (r % j.rs)) * Pw + col / 2];
-                const int nib = (v >> (4 * (col & 1))) & 15;
-                rows[(size_t)r * j.N + i] = nib == 0 ? 0 : ((nib & 8) ? -1 : 1);
+                const size_t row = (size_t)(r / j.rs) * j.rs + (r % j.rs);
+                if (j.fp4) {
+                    const int nib = ((uint8_t)tl[row * Pw + col / 2] >> (4 * (col & 1))) & 15;
+                    rows[(size_t)r * j.N + i] = nib == 0 ? 0 : ((nib & 8) ? -1 : 1);
+                } else {
+                    rows[(size_t)r * j.N + i] = tl[row * Pw + col];
+                }
             }
     }
 }
@@ -221,9 +239,7 @@ static void tiles_to_rows(const BJob &j, const int8_t *tl, int8_t *rows)
 static int admit(pbit_ctx *ctx, BJob &j)
 {
     int rc = dev_alloc(ctx, sizeof(uint32_t) * (size_t)std::max(j.S, 1) * j.width, &j.d_table);
-    const size_t tile_bytes =
-        j.kind == PBIT_EA3D ? (size_t)4 * j.N : (size_t)j.rs * (j.P->bq.na_p + j.P->bq.nb_p) / 2;
-    if (rc == PBIT_OK) rc = dev_alloc(ctx, (size_t)j.tiles * tile_bytes, &j.d_state);
+    if (rc == PBIT_OK) rc = dev_alloc(ctx, (size_t)j.tiles * tile_bytes(j), &j.d_state);
     if (rc == PBIT_OK) rc = dev_alloc(ctx, sizeof(int32_t) * (size_t)j.tiles * j.rs, &j.d_energy);
     if (rc != PBIT_OK) {
         dev_free(ctx, j.d_table);
@@ -293,7 +309,7 @@ static int launch_round(pbit_ctx *ctx, ServeState &s)
         } else {
             const BqView &v = j->P->bq;
             const int k = kind_of_rs(j->rs);
-            BqJobDev jd{v.J4, v.JT4, v.hA, v.hB, (const uint32_t *)j->d_table, (uint8_t *)j->d_state,
+            BqJobDev jd{v.J, v.JT, v.J4, v.JT4, v.hA, v.hB, (const uint32_t *)j->d_table, (uint8_t *)j->d_state,
                         (int32_t *)j->d_energy, v.na, v.nb, v.na_p, v.nb_p, j->width,
                         (uint32_t)j->d.sweep_offset, (uint32_t)j->d.replica_offset >> 2, key.k0, key.k1};
             const int idx = (int)bq[k - 1].size();
@@ -302,7 +318,7 @@ static int launch_round(pbit_ctx *ctx, ServeState &s)
                 items[k].push_back(WorkItem{idx, t, s0, s1, j->started ? 0 : 1, {0, 0, 0}});
                 cost[k].push_back((double)(s1 - s0) * (double)v.na_p * v.nb_p * j->rs);
             }
-            lds[k] = std::max(lds[k], bq_tile_lds(j->rs, v.na_p, v.nb_p, j->width));
+            lds[k] = std::max(lds[k], bq_tile_lds(j->rs, v.na_p, v.nb_p, j->width, j->fp4));
         }
     }
     if (s.round_jobs.empty()) return PBIT_OK;
@@ -352,7 +368,7 @@ static int launch_round(pbit_ctx *ctx, ServeState &s)
                          s.d_meta + 0, grid, lds[0], s.st[0]);
         else
             e = bq_tiles((const BqJobDev *)s.d_bq_jobs[k - 1], (const WorkItem *)s.d_items[k], s.d_meta + kKinds + k,
-                         s.d_meta + k, rs_of_kind(k), grid, lds[k], s.st[k]);
+                         s.d_meta + k, rs_of_kind(k), ctx->bq_forced == BqVariant::Fp4, grid, lds[k], s.st[k]);
         if (e == hipSuccess) e = hipEventRecord(s.join[k], s.st[k]);
         if (e != hipSuccess) return device_fail(ctx, e, "tile kernel launch");
     }
@@ -457,9 +473,7 @@ static int new_job(pbit_ctx *ctx, ServeState &s, uint64_t problem, const pbit_an
 static int fill_result(pbit_ctx *ctx, BJob &j, pbit_result *res)
 {
     if (res && res->spins && j.d_state) {
-        const size_t tile_bytes =
-            j.kind == PBIT_EA3D ? (size_t)4 * j.N : (size_t)j.rs * (j.P->bq.na_p + j.P->bq.nb_p) / 2;
-        std::vector<int8_t> tl((size_t)j.tiles * tile_bytes);
+        std::vector<int8_t> tl((size_t)j.tiles * tile_bytes(j));
         hipError_t e = hipMemcpy(tl.data(), j.d_state, tl.size(), hipMemcpyDeviceToHost);
         if (e != hipSuccess) return device_fail(ctx, e, "spin readback");
         tiles_to_rows(j, tl.data(), res->spins);
