@@ -18,6 +18,13 @@ struct BqView {
     const uint8_t *J4;
     const uint8_t *JT4;
     bool fp4_sweep;  // both sides padded to 128: the per-instance half-sweep runs on fp4 operands
+    // for the half-sweep on spin bits (sides padded to 128, else null): the couplings
+    // with the columns of every group of 32 in the order the widened bits take,
+    // [na_p][nb_p] and [nb_p][na_p], and each site's field plus its coupling sum
+    const int8_t *Jb;
+    const int8_t *JTb;
+    const int32_t *hA2;  // [na_p]
+    const int32_t *hB2;  // [nb_p]
 };
 
 constexpr int kBqPad = 64;       // site padding of small biclique sides (MFMA K and N tiles)
@@ -31,9 +38,12 @@ constexpr int kMaxTableWidth = 4096;  // threshold-row entries a biclique kernel
 // global memory; K64D4 .. K128D4: 128 x 128 LDS-tiled with K stages of 64 or
 // 128 bytes and 2 or 4 stages of register prefetch; Dma64, Dma128: 128 x 128
 // with stages of 64 or 128 bytes moved by the global-to-LDS DMA into a ring of
-// 8 or 4 stages; Fp4: the DMA tile on packed 4-bit operands (bq4_*).  All but
-// Small need sides padded to 128.
-enum class BqVariant : int { Auto = 0, Small = 1, K64D4 = 2, K128D2 = 3, K128D4 = 4, Dma64 = 5, Dma128 = 6, Fp4 = 7 };
+// 8 or 4 stages; Fp4: the DMA tile on packed 4-bit operands (bq4_*); Bits: the DMA
+// tile on spins held as bits, widened for the int8 MFMA (bqb_*).  All but Small need
+// sides padded to 128.
+enum class BqVariant : int {
+    Auto = 0, Small = 1, K64D4 = 2, K128D2 = 3, K128D4 = 4, Dma64 = 5, Dma128 = 6, Fp4 = 7, Bits = 8
+};
 hipError_t bq_init(const BqView &p, int8_t *MA, int8_t *MB, int R, uint32_t rq0, Key key, hipStream_t st);
 hipError_t bq_from_rows(const BqView &p, const int8_t *src_rn, int R, int8_t *MA, int8_t *MB, hipStream_t st);
 hipError_t bq_to_rows(const BqView &p, const int8_t *MA, const int8_t *MB, int8_t *dst_rn, int R, hipStream_t st);
@@ -48,6 +58,16 @@ hipError_t bq4_to_rows(const BqView &p, const uint8_t *MA4, const uint8_t *MB4, 
 hipError_t bq4_unpack(const BqView &p, const uint8_t *MA4, const uint8_t *MB4, int8_t *MA, int8_t *MB, int Rp,
                       hipStream_t st);
 hipError_t bq4_halfsweep(const BqView &p, int side, uint8_t *MA4, uint8_t *MB4, int Rp, const uint32_t *trow,
+                         int width, uint32_t sweep, uint32_t rq0, Key key, hipStream_t st);
+
+// ---- the same with spins held as bits (set = -1), 32 sites per word, by blocks of 128 sites:
+// word w of replica r at ((w / 4) Rp + r) 4 + w % 4 of MAb (na_p / 32 words per replica) or MBb
+bool bqb_supported(const BqView &p, int Rp);
+hipError_t bqb_pack(const BqView &p, const int8_t *MA, const int8_t *MB, uint32_t *MAb, uint32_t *MBb, int Rp,
+                    hipStream_t st);
+hipError_t bqb_unpack(const BqView &p, const uint32_t *MAb, const uint32_t *MBb, int8_t *MA, int8_t *MB, int Rp,
+                      hipStream_t st);
+hipError_t bqb_halfsweep(const BqView &p, int side, uint32_t *MAb, uint32_t *MBb, int Rp, const uint32_t *trow,
                          int width, uint32_t sweep, uint32_t rq0, Key key, hipStream_t st);
 
 }  // namespace pbit

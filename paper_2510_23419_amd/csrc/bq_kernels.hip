@@ -21,6 +21,10 @@
 
 namespace pbit {
 
+// v_writelane_b32: lane `lane` of `old` takes the wave-uniform `val` (the
+// compiler's intrinsic, bound by name: hip exposes no builtin for it)
+__device__ int lane_write(int val, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+
 namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
@@ -884,6 +888,281 @@ __global__ __launch_bounds__(kThreads) void k_bq_field_energy(const int8_t *__re
     if ((threadIdx.x & 63) == 0) atomicAdd(E + r, e);
 }
 
+
+// ---------------------------------------------------------------- spins as bits
+//
+// Spins are +-1, so a replica fits one bit per site: bit b of spin word w of a
+// replica is set when site 32 w + b holds -1.  The words of a side are stored
+// by blocks of 128 sites: word w of replica r at ((w / 4) Rp + r) 4 + w % 4, so
+// that the 16 bytes of one block of consecutive replicas are contiguous.
+// With b_k the bit of site k, m_k = 1 - 2 b_k and the field of a site s is
+//     I_s = h_s + sum_k J_sk m_k = (h_s + sum_k J_sk) - 2 sum_k J_sk b_k,
+// whose last sum runs on the int8 MFMA with int32 accumulation, the bits
+// widened to 0 / 1 bytes in registers.  The spins cross from L2 at one eighth
+// of the int8 bytes, which is what bounds the int8 tiles of large bicliques.
+//
+// Widening: lane half g (lanes 32 g .. 32 g + 31) of an MFMA fragment holds 16
+// K bytes, dword j byte i at K position 16 g + 4 j + i.  From a spin word w the
+// dword (w >> (4 g + j)) & 0x01010101 puts bit 8 i + 4 g + j into byte i, so K
+// position p = 16 g + 4 j + i carries site 8 i + 4 g + j of the 32-site word.
+// The couplings are stored with their columns in that order inside every
+// group of 32 (Jb, JTb), so both operands agree on the site of every K byte.
+//
+// Tile: 128 sites x 128 replicas per workgroup, wave w owning replicas
+// 32 w .. 32 w + 31 of the tile and all 128 sites (1 x 4 MFMA blocks), so that
+// each widened spin fragment feeds four MFMAs.  On gfx950 an MFMA holds the
+// wave's VALU issue for about half of its 32 cycles, so the kernel stays on
+// the matrix cores only while the vector work (widening, Philox, decisions)
+// is at most about four instructions per MFMA; this shape keeps it there.
+// Stages of 128 K move by the global-to-LDS DMA into a ring: 128 coupling rows
+// of 128 bytes (chunk c of row r at position c ^ swzb(r)), then the 128
+// replicas' 16 bytes (four spin words) of the K block.
+//
+// Decisions through 64-bit words in LDS, one per clamped field value:
+// S(I) = Tm(|I|) for I >= 0, 2^32 - Tm(|I|) for I < 0; the new spin is -1
+// exactly when w + S(I) carries into bit 32 (the heat-bath rule with the
+// uniform word w), so a lane's decision is one multiply-add and one compare,
+// and a wave's 64 decisions form one ballot mask.
+
+constexpr int kBitsST = 128;  // sites per tile
+constexpr int kBitsRT = 128;  // replicas per tile
+constexpr int kBitsKT = 128;  // K per stage
+constexpr int kBitsNS = 5;    // stages in the ring
+
+struct BitsGeom {
+    static constexpr int jbytes = kBitsST * kBitsKT;     // coupling rows of one stage (16 KiB)
+    static constexpr int bbytes = kBitsRT * kBitsKT / 8; // spin words of one stage (2 KiB)
+    static constexpr int stage = jbytes + bbytes;
+    static constexpr int j_per_wave = jbytes / 1024 / 4; // 16-byte DMA instructions per wave and stage
+    static constexpr int b_per_wave = bbytes / 256 / 4;  // 4-byte DMA instructions per wave and stage
+    static constexpr int per_wave = j_per_wave + b_per_wave;
+    static constexpr int ahead = per_wave * (kBitsNS - 2);
+    static constexpr int ring = kBitsNS * stage;
+    static_assert(ahead < 64, "vmcnt is a 6-bit field");
+    static_assert(j_per_wave * 4 * 1024 == jbytes && b_per_wave * 4 * 256 == bbytes, "whole DMA instructions");
+};
+
+// 0 / 1 bytes of the K bytes that lane half g holds, from one spin word
+__device__ __forceinline__ v4i widen_bits(uint32_t w, int g)
+{
+    const uint32_t x = w >> (4 * g);
+    v4i a;
+    a[0] = (int)(x & 0x01010101u);
+    a[1] = (int)((x >> 1) & 0x01010101u);
+    a[2] = (int)((x >> 2) & 0x01010101u);
+    a[3] = (int)((x >> 3) & 0x01010101u);
+    return a;
+}
+
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_bq_halfsweep_bits(
+    const uint32_t *__restrict__ Mob, const int8_t *__restrict__ Jb, const int32_t *__restrict__ hs2,
+    uint32_t *__restrict__ Msb, const uint32_t *__restrict__ trow, int width, int Ko, int Rp, int tiles_s,
+    int xcd_bands, uint32_t site_base, uint32_t sweep, uint32_t rq0, uint32_t k0, uint32_t k1, uint32_t one)
+{
+    using G = BitsGeom;
+    constexpr int NS = kBitsNS;
+    constexpr int CH = kBitsKT / 16;  // 16-byte chunks per coupling row
+    constexpr int kSubs = kBitsKT / 32;
+
+    extern __shared__ uint4 smem[];
+    int8_t *ring = reinterpret_cast<int8_t *>(smem);
+    uint64_t *Sw = reinterpret_cast<uint64_t *>(ring + G::ring);  // [2 top + 1]
+    const int top = width - 1;
+    for (int e = threadIdx.x; e <= 2 * top; e += kThreads) {
+        const int I = e - top;
+        const uint32_t Tm = trow[I >= 0 ? I : -I];
+        Sw[e] = I >= 0 ? (uint64_t)Tm : ((uint64_t)1 << 32) - Tm;
+    }
+
+    int ts, tr;
+    if (xcd_bands) {  // tiles_s % 8 == 0: XCD (= block id mod 8) owns tiles_s / 8 site tiles
+        const int per = tiles_s / 8;
+        const int slot = (int)blockIdx.x / 8;
+        ts = ((int)blockIdx.x % 8) * per + slot % per;
+        tr = slot / per;
+    } else {
+        ts = (int)blockIdx.x % tiles_s;
+        tr = (int)blockIdx.x / tiles_s;
+    }
+    const int r0 = tr * kBitsRT, s0 = ts * kBitsST;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: address math on the SALU
+
+    // DMA sources: wave w fills coupling slots 64 (j_per_wave w + j) + lane (16 bytes
+    // each) and spin words 64 (b_per_wave w + j) + lane (4 bytes each) of each stage,
+    // from a wave-uniform base plus a 32-bit lane offset.  Row r of a stage keeps
+    // chunk c at position c ^ swzb(r), with a swizzle of r mod 32 only, so that the
+    // four site blocks of a fragment read sit at fixed distances.
+    auto swzb = [](int r) { return (r ^ ((r >> 3) & 3)) & 7; };
+    uint32_t offJl[4], offBl[4];
+    static_assert(G::j_per_wave <= 4 && G::b_per_wave <= 4 && kSubs <= 4, "fixed array bounds");
+#pragma unroll
+    for (int j = 0; j < G::j_per_wave; ++j) {
+        const int S = 64 * (G::j_per_wave * wave + j) + lane;
+        const int r = S / CH, c = (S % CH) ^ swzb(S / CH);
+        offJl[j] = (uint32_t)(r * Ko + 16 * c);
+    }
+#pragma unroll
+    for (int j = 0; j < G::b_per_wave; ++j) offBl[j] = 4u * (uint32_t)(64 * (G::b_per_wave * wave + j) + lane);
+    const int8_t *Jt0 = Jb + (size_t)s0 * Ko;
+    const char *Bt0 = reinterpret_cast<const char *>(Mob + (size_t)r0 * 4);
+    const int nk = Ko / kBitsKT;
+    auto issue = [&](int t) {
+        int8_t *dJ = ring + (t % NS) * G::stage + 1024 * G::j_per_wave * wave;
+        int8_t *dB = ring + (t % NS) * G::stage + G::jbytes + 256 * G::b_per_wave * wave;
+        const int8_t *Jt = Jt0 + (size_t)t * kBitsKT;
+        const char *Bt = Bt0 + (size_t)t * 16 * Rp;
+#pragma unroll
+        for (int j = 0; j < G::j_per_wave; ++j) __builtin_amdgcn_global_load_lds(Jt + offJl[j], dJ + 1024 * j, 16, 0, 0);
+#pragma unroll
+        for (int j = 0; j < G::b_per_wave; ++j) __builtin_amdgcn_global_load_lds(Bt + offBl[j], dB + 256 * j, 4, 0, 0);
+    };
+    wait_vm<0>();  // the threshold row's loads are waited for before any DMA is counted
+    for (int t = 0; t < NS - 1 && t < nk; ++t) issue(t);
+
+    const int ln = lane & 31, kg = lane >> 5;
+    // coupling fragment offsets: rows 32 bj + ln, chunk 2 sub + kg; swzb(32 bj + ln) = swzb(ln)
+    int offJ[4];
+#pragma unroll
+    for (int sub = 0; sub < kSubs; ++sub) offJ[sub] = kBitsKT * ln + 16 * ((2 * sub + kg) ^ swzb(ln));
+    const int offB = G::jbytes + 16 * (32 * wave + ln);  // the spin words of replica row 32 wave + ln
+    v16i acc[4];  // site block bj
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) acc[bj] = v16i{0};
+    uint32_t words[16][4];
+
+    auto compute = [&](int t) {
+        const int8_t *st = ring + (t % NS) * G::stage;
+        // int vector reads, like every LDS read of the ring: with this access type the
+        // compiler adds no wait for all DMA in flight (the stage was waited for, and
+        // published by a barrier, before this call)
+        const v4i w = *reinterpret_cast<const v4i *>(st + offB);
+#pragma unroll
+        for (int sub = 0; sub < kSubs; ++sub) {
+            const int8_t *row = st + offJ[sub];
+            v4i b[4];
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj) b[bj] = *reinterpret_cast<const v4i *>(row + 32 * kBitsKT * bj);
+            const v4i a = widen_bits((uint32_t)w[sub], kg);
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj) acc[bj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b[bj], acc[bj], 0, 0, 0);
+        }
+    };
+    auto draw = [&](int blk) {
+        // block 4 bj + q covers site block bj and replica rows 8 q + 4 kg .. + 3 of the wave
+        const int bj = blk >> 2, q = blk & 3;
+        const int site = s0 + bj * 32 + ln;
+        const int r4 = r0 + 32 * wave + 8 * q + 4 * kg;
+        const Block4 b = philox(site_base + (uint32_t)site, sweep, rq0 + (uint32_t)(r4 >> 2), kDomainSweep, k0, k1);
+        words[blk][0] = b.w[0];
+        words[blk][1] = b.w[1];
+        words[blk][2] = b.w[2];
+        words[blk][3] = b.w[3];
+    };
+
+    if (nk >= NS - 1) wait_vm<G::ahead>(); else wait_vm<0>();
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");  // LDS written by the DMA: no read may move above here
+
+    // the first stages carry the Philox draws, two blocks each
+    constexpr int kPhxPerStage = 2, kPhxStages = 16 / kPhxPerStage;
+    int t = 0;
+#pragma unroll
+    for (int u = 0; u < kPhxStages; ++u) {
+        if (t < nk) {
+            if (t + NS - 1 < nk) issue(t + NS - 1);
+            compute(t);
+#pragma unroll
+            for (int v = 0; v < kPhxPerStage; ++v) draw(kPhxPerStage * u + v);
+            if (t + NS - 1 < nk) wait_vm<G::ahead>(); else wait_vm<0>();
+            __builtin_amdgcn_s_barrier();
+            asm volatile("" ::: "memory");
+            ++t;
+        } else {
+#pragma unroll
+            for (int v = 0; v < kPhxPerStage; ++v) draw(kPhxPerStage * u + v);
+        }
+    }
+    for (; t + NS - 1 < nk; ++t) {
+        issue(t + NS - 1);
+        compute(t);
+        wait_vm<G::ahead>();
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+    }
+    for (; t < nk; ++t) {
+        compute(t);
+        wait_vm<0>();
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+    }
+
+    // epilogue: one ballot per (site block, q, p) gives the new spin bits of 32
+    // sites for two replicas (lane half 0: row 8 q + p of the wave, half 1: row
+    // 8 q + 4 + p); lane L < 32 of out[bj] collects the word of replica row L of
+    // the wave for site block bj.  Padding sites and replicas take bits that
+    // nothing reads (their couplings and fields are zero).
+    const char *Sb = reinterpret_cast<const char *>(Sw);
+    uint32_t out[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) {
+        const int h2 = hs2[s0 + bj * 32 + ln];  // field plus coupling sum; zero at padding sites
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const int I = h2 - 2 * acc[bj][4 * q + p];
+                const int Ic = min(max(I, -top), top);
+                const uint64_t S = *static_cast<const uint64_t *>(__builtin_assume_aligned(Sb + 8 * (Ic + top), 8));
+                const uint64_t m = __ballot((((uint64_t)words[4 * bj + q][p] * one + S) >> 32) != 0);
+                const int L = 8 * q + p;
+                out[bj] = (uint32_t)lane_write((int)(uint32_t)m, L, (int)out[bj]);
+                out[bj] = (uint32_t)lane_write((int)(uint32_t)(m >> 32), L + 4, (int)out[bj]);
+            }
+        }
+    }
+    // the four words of replica row ln: one aligned block of four at site word s0 / 32
+    if (lane < 32)
+        *reinterpret_cast<uint4 *>(Msb + ((size_t)(s0 / kBitsKT) * Rp + r0 + 32 * wave + lane) * 4) =
+            make_uint4(out[0], out[1], out[2], out[3]);
+}
+
+// int8 rows [Rp][cols] <-> spin words by blocks of 128 sites; one thread per word
+template <bool PACK>
+__global__ __launch_bounds__(kThreads) void k_bq_bits(int8_t *__restrict__ M, uint32_t *__restrict__ Mb, int Rp,
+                                                      int cols)
+{
+    const int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const int nw = cols / 32;
+    if (k >= (int64_t)Rp * nw) return;
+    const int r = (int)(k / nw), w = (int)(k % nw);
+    uint4 *row = reinterpret_cast<uint4 *>(M + (size_t)r * cols + 32 * w);
+    uint32_t *word = Mb + ((size_t)(w / 4) * Rp + r) * 4 + w % 4;
+    if (PACK) {
+        const uint4 v0 = row[0], v1 = row[1];
+        const uint32_t d[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+        uint32_t x = 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) x |= ((d[i] >> (8 * b + 7)) & 1u) << (4 * i + b);  // sign bit of the byte
+        *word = x;
+    } else {
+        const uint32_t x = *word;
+        uint32_t d[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const uint32_t y = (x >> (4 * i)) & 0xFu;
+            uint32_t v = 0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) v |= ((y >> b) & 1u ? 0xFFu : 0x01u) << (8 * b);
+            d[i] = v;
+        }
+        row[0] = make_uint4(d[0], d[1], d[2], d[3]);
+        row[1] = make_uint4(d[4], d[5], d[6], d[7]);
+    }
+}
+
 }  // namespace
 
 static inline unsigned blocks_for(int64_t work) { return (unsigned)((work + kThreads - 1) / kThreads); }
@@ -1054,6 +1333,62 @@ hipError_t bq4_halfsweep(const BqView &p, int side, uint8_t *MA4, uint8_t *MB4, 
     else
         hipLaunchKernelGGL((k_bq_halfsweep_fp4<64, 8>), grid, dim3(kThreads), (DmaGeom<64, 8>::lds + tab), st, Mo, Jx,
                            hs, Ms, trow, width, Ns_p, Ko, tiles_s, bands, site_base, sweep, rq0, key.k0, key.k1, 1u);
+    return hipGetLastError();
+}
+
+hipError_t bqb_pack(const BqView &p, const int8_t *MA, const int8_t *MB, uint32_t *MAb, uint32_t *MBb, int Rp,
+                    hipStream_t st)
+{
+    if (p.na_p % kBitsKT || p.nb_p % kBitsKT) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_bq_bits<true>, dim3(blocks_for((int64_t)Rp * p.na_p / 32)), dim3(kThreads), 0, st,
+                       const_cast<int8_t *>(MA), MAb, Rp, p.na_p);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bq_bits<true>, dim3(blocks_for((int64_t)Rp * p.nb_p / 32)), dim3(kThreads), 0, st,
+                       const_cast<int8_t *>(MB), MBb, Rp, p.nb_p);
+    return hipGetLastError();
+}
+
+hipError_t bqb_unpack(const BqView &p, const uint32_t *MAb, const uint32_t *MBb, int8_t *MA, int8_t *MB, int Rp,
+                      hipStream_t st)
+{
+    if (p.na_p % kBitsKT || p.nb_p % kBitsKT) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_bq_bits<false>, dim3(blocks_for((int64_t)Rp * p.na_p / 32)), dim3(kThreads), 0, st, MA,
+                       const_cast<uint32_t *>(MAb), Rp, p.na_p);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bq_bits<false>, dim3(blocks_for((int64_t)Rp * p.nb_p / 32)), dim3(kThreads), 0, st, MB,
+                       const_cast<uint32_t *>(MBb), Rp, p.nb_p);
+    return hipGetLastError();
+}
+
+bool bqb_supported(const BqView &p, int Rp)
+{
+    return p.Jb && p.na_p % kBitsST == 0 && p.nb_p % kBitsST == 0 && p.na_p % kBitsKT == 0 &&
+           p.nb_p % kBitsKT == 0 && Rp % kBitsRT == 0;
+}
+
+hipError_t bqb_halfsweep(const BqView &p, int side, uint32_t *MAb, uint32_t *MBb, int Rp, const uint32_t *trow,
+                         int width, uint32_t sweep, uint32_t rq0, Key key, hipStream_t st)
+{
+    if (!bqb_supported(p, Rp) || width < 1 || width > kMaxTableWidth) return hipErrorInvalidValue;
+    static const hipError_t lds_attr =
+        hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bq_halfsweep_bits),
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            BitsGeom::ring + (int)sizeof(uint64_t) * (2 * kMaxTableWidth - 1));
+    if (lds_attr != hipSuccess) return lds_attr;
+    const bool A = side == 0;
+    const int Ns_p = A ? p.na_p : p.nb_p, Ko = A ? p.nb_p : p.na_p;
+    const uint32_t *Mob = A ? MBb : MAb;
+    const int8_t *Jb = A ? p.Jb : p.JTb;
+    const int32_t *hs2 = A ? p.hA2 : p.hB2;
+    uint32_t *Msb = A ? MAb : MBb;
+    const uint32_t site_base = A ? 0u : (uint32_t)p.na;
+    const int tiles_s = Ns_p / kBitsST, tiles_r = Rp / kBitsRT;
+    const int bands = tiles_s % 8 == 0 ? 1 : 0;
+    hipLaunchKernelGGL(k_bq_halfsweep_bits, dim3((unsigned)(tiles_s * tiles_r)), dim3(kThreads),
+                       (BitsGeom::ring + sizeof(uint64_t) * (size_t)(2 * width - 1)), st, Mob, Jb, hs2, Msb, trow,
+                       width, Ko, Rp, tiles_s, bands, site_base, sweep, rq0, key.k0, key.k1, 1u);
     return hipGetLastError();
 }
 

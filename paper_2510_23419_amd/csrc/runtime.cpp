@@ -186,9 +186,9 @@ extern "C" int pbit_create(pbit_ctx **out, int device, uint64_t hbm_budget_bytes
     if (!ctx) return fail(PBIT_E_NOMEM, "pbit_create: host allocation failed");
     ctx->device = device;
     ctx->budget = hbm_budget_bytes;
-    if (const char *v = std::getenv("PBIT_BQ_VARIANT")) {  // tuning override: 1..7 (see BqVariant)
+    if (const char *v = std::getenv("PBIT_BQ_VARIANT")) {  // tuning override: 1..8 (see BqVariant)
         const int k = std::atoi(v);
-        if (k >= 1 && k <= 7) ctx->bq_forced = (BqVariant)k;
+        if (k >= 1 && k <= 8) ctx->bq_forced = (BqVariant)k;
     }
     ctx->serial = g_ctx_serial.fetch_add(1);
     e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
@@ -352,12 +352,44 @@ static int load_biclique(pbit_ctx *ctx, const pbit_problem_desc *d, Problem &p)
         rc = upload(ctx, p, J4.data(), J4.size(), &dJ4);
         if (rc == PBIT_OK) rc = upload(ctx, p, JT4.data(), JT4.size(), &dJT4);
     }
+    void *dJb = nullptr, *dJTb = nullptr, *dhA2 = nullptr, *dhB2 = nullptr;
+    if (rc == PBIT_OK && pad == kBqPadLarge) {
+        // the half-sweep on spin bits: K byte p = 16 g + 4 j + i of every group of 32
+        // columns holds column 8 i + 4 g + j of the group, and each field carries the
+        // coupling sum of its site
+        auto permute = [](const std::vector<int8_t> &M, int rows, int cols, std::vector<int8_t> &out) {
+            out.assign(M.size(), 0);
+            for (int r = 0; r < rows; ++r)
+                for (int c0 = 0; c0 < cols; c0 += 32)
+                    for (int q = 0; q < 32; ++q) {
+                        const int g = q >> 4, j = (q >> 2) & 3, i = q & 3;
+                        out[(size_t)r * cols + c0 + q] = M[(size_t)r * cols + c0 + 8 * i + 4 * g + j];
+                    }
+        };
+        std::vector<int8_t> Jb, JTb;
+        permute(J, na_p, nb_p, Jb);
+        permute(JT, nb_p, na_p, JTb);
+        std::vector<int32_t> hA2(na_p, 0), hB2(nb_p, 0);
+        for (int a = 0; a < na; ++a) {
+            hA2[a] = hA[a];
+            for (int b = 0; b < nb; ++b) hA2[a] += J[(size_t)a * nb_p + b];
+        }
+        for (int b = 0; b < nb; ++b) {
+            hB2[b] = hB[b];
+            for (int a = 0; a < na; ++a) hB2[b] += JT[(size_t)b * na_p + a];
+        }
+        rc = upload(ctx, p, Jb.data(), Jb.size(), &dJb);
+        if (rc == PBIT_OK) rc = upload(ctx, p, JTb.data(), JTb.size(), &dJTb);
+        if (rc == PBIT_OK) rc = upload(ctx, p, hA2.data(), sizeof(int32_t) * hA2.size(), &dhA2);
+        if (rc == PBIT_OK) rc = upload(ctx, p, hB2.data(), sizeof(int32_t) * hB2.size(), &dhB2);
+    }
     if (rc != PBIT_OK) return rc;
     p.kind = PBIT_BICLIQUE;
     p.N = (int64_t)na + nb;
     p.amax = amax;
     p.bq = BqView{na, nb, na_p, nb_p, (const int8_t *)dJ, (const int8_t *)dJT, (const int8_t *)dhA,
-                  (const int8_t *)dhB, (const uint8_t *)dJ4, (const uint8_t *)dJT4, pad == kBqPadLarge};
+                  (const int8_t *)dhB, (const uint8_t *)dJ4, (const uint8_t *)dJT4, pad == kBqPadLarge,
+                  (const int8_t *)dJb, (const int8_t *)dJTb, (const int32_t *)dhA2, (const int32_t *)dhB2};
     return PBIT_OK;
 }
 
@@ -647,9 +679,11 @@ int spins_in_range(const int8_t *s, size_t n)
 struct DevState {
     int R = 0, Rp = 0;
     int8_t *spins = nullptr;  // EA: [N][Rp]
-    int8_t *MA = nullptr, *MB = nullptr;  // biclique (int8 spins; energy staging when fp4)
+    int8_t *MA = nullptr, *MB = nullptr;  // biclique int8 spins (staging when held packed)
     bool fp4 = false;                     // biclique spins held as packed 4-bit floats
     uint8_t *MA4 = nullptr, *MB4 = nullptr;
+    bool bits = false;                    // biclique spins held as bits
+    uint32_t *MAb = nullptr, *MBb = nullptr;
     uint32_t *table = nullptr;
     int width = 1;
     int32_t *E32 = nullptr;
@@ -663,8 +697,11 @@ struct DevState {
 static int tune_biclique(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStream_t st)
 {
     if (ctx->bq_forced != BqVariant::Auto && ctx->bq_forced != BqVariant::Fp4) {
-        ds.variant = ctx->bq_forced;
-        return PBIT_OK;
+        // a forced kernel the shape cannot take falls back to the tuned choice
+        if (ctx->bq_forced != BqVariant::Bits || ds.MAb) {
+            ds.variant = ctx->bq_forced;
+            return PBIT_OK;
+        }
     }
     const std::array<int, 3> shape{P.bq.na_p, P.bq.nb_p, ds.Rp};
     auto it = ctx->bq_tuned.find(shape);
@@ -679,7 +716,7 @@ static int tune_biclique(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStrea
         return PBIT_OK;
     }
     const BqVariant cand[] = {BqVariant::K64D4, BqVariant::K128D2, BqVariant::K128D4, BqVariant::Dma64,
-                              BqVariant::Dma128, BqVariant::Small};
+                              BqVariant::Dma128, BqVariant::Small, BqVariant::Bits};
     hipEvent_t e0, e1;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
@@ -688,11 +725,14 @@ static int tune_biclique(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStrea
     float best_ms = 0.f;
     BqVariant best = BqVariant::K128D4;
     for (BqVariant v : cand) {
+        if (v == BqVariant::Bits && !ds.MAb) continue;  // no bit copy: the shape cannot take it
         float ms = 0.f;
         for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // first pass warms up
             e = hipEventRecord(e0, st);
             for (int k = 0; k < 4 && e == hipSuccess; ++k)
-                e = bq_halfsweep(P.bq, k & 1, ds.MA, ds.MB, ds.R, ds.Rp, ds.table, ds.width, 0u, 0u, key, st, v);
+                e = v == BqVariant::Bits
+                        ? bqb_halfsweep(P.bq, k & 1, ds.MAb, ds.MBb, ds.Rp, ds.table, ds.width, 0u, 0u, key, st)
+                        : bq_halfsweep(P.bq, k & 1, ds.MA, ds.MB, ds.R, ds.Rp, ds.table, ds.width, 0u, 0u, key, st, v);
             if (e == hipSuccess) e = hipEventRecord(e1, st);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
@@ -724,28 +764,32 @@ static int prepare(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, h
         if (rc) return rc;
         ds.spins = (int8_t *)v;
     } else {
+        // int8 spins, plus a packed copy where a kernel runs on one: packed 4-bit floats on
+        // request, bits where the sides are padded to 128 (the tuner then times the bit kernel)
         ds.Rp = round_up(R, kBqRPad);
         const size_t a = (size_t)ds.Rp * P.bq.na_p, b = (size_t)ds.Rp * P.bq.nb_p;
-        // int8 operands by default; packed 4-bit float operands on request, for sides padded to 128
         ds.fp4 = P.bq.fp4_sweep && ctx->bq_forced == BqVariant::Fp4;
+        rc = scratch(ctx, Slot::Spins, a + b, &v);
+        if (rc) return rc;
+        ds.MA = (int8_t *)v;
+        ds.MB = ds.MA + a;
+        hipError_t e = hipMemsetAsync(ds.MA, 0, a + b, st);
+        if (e != hipSuccess) return device_fail(ctx, e, "hipMemsetAsync");
         if (ds.fp4) {
-            rc = scratch(ctx, Slot::Spins, (a + b) / 2, &v);
+            rc = scratch(ctx, Slot::Aux, (a + b) / 2, &v);
             if (rc) return rc;
             ds.MA4 = (uint8_t *)v;
             ds.MB4 = ds.MA4 + a / 2;
-            hipError_t e = hipMemsetAsync(ds.MA4, 0, (a + b) / 2, st);
+            e = hipMemsetAsync(ds.MA4, 0, (a + b) / 2, st);
             if (e != hipSuccess) return device_fail(ctx, e, "hipMemsetAsync");
-            rc = scratch(ctx, Slot::Aux, a + b, &v);  // int8 copies for the energy kernels
-            if (rc) return rc;
-            ds.MA = (int8_t *)v;
-            ds.MB = ds.MA + a;
             ds.variant = BqVariant::Fp4;
-        } else {
-            rc = scratch(ctx, Slot::Spins, a + b, &v);
+        } else if (bqb_supported(P.bq, ds.Rp) &&
+                   (ctx->bq_forced == BqVariant::Auto || ctx->bq_forced == BqVariant::Bits)) {
+            rc = scratch(ctx, Slot::Aux, (a + b) / 8, &v);
             if (rc) return rc;
-            ds.MA = (int8_t *)v;
-            ds.MB = ds.MA + a;
-            hipError_t e = hipMemsetAsync(ds.MA, 0, a + b, st);
+            ds.MAb = (uint32_t *)v;
+            ds.MBb = ds.MAb + a / 32;
+            e = hipMemsetAsync(ds.MAb, 0, (a + b) / 8, st);
             if (e != hipSuccess) return device_fail(ctx, e, "hipMemsetAsync");
         }
     }
@@ -772,6 +816,7 @@ static int prepare(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, h
         rc = tune_biclique(ctx, P, ds, st);
         if (rc) return rc;
     }
+    ds.bits = P.kind == PBIT_BICLIQUE && ds.variant == BqVariant::Bits;
 
     const Key key{(uint32_t)d->seed, (uint32_t)(d->seed >> 32)};
     const uint32_t rq0 = (uint32_t)d->replica_offset >> 2;
@@ -793,6 +838,7 @@ static int prepare(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, h
                       : bq4_init(P.bq, ds.MA4, ds.MB4, R, rq0, key, st);
     else
         e = init_rows ? bq_from_rows(P.bq, init_rows, R, ds.MA, ds.MB, st) : bq_init(P.bq, ds.MA, ds.MB, R, rq0, key, st);
+    if (e == hipSuccess && ds.bits) e = bqb_pack(P.bq, ds.MA, ds.MB, ds.MAb, ds.MBb, ds.Rp, st);
     if (e != hipSuccess) return device_fail(ctx, e, "spin initialisation launch");
     return PBIT_OK;
 }
@@ -816,6 +862,8 @@ static hipError_t sweep(pbit_ctx *ctx, const Problem &P, DevState &ds, int s, ui
             e = graph_halfsweep(P.graph, c, ds.spins, ds.Rp, row, ds.width, t, rq0, key, st);
         else if (ds.fp4)
             e = bq4_halfsweep(P.bq, c, ds.MA4, ds.MB4, ds.Rp, row, ds.width, t, rq0, key, st);
+        else if (ds.bits)
+            e = bqb_halfsweep(P.bq, c, ds.MAb, ds.MBb, ds.Rp, row, ds.width, t, rq0, key, st);
         else
             e = bq_halfsweep(P.bq, c, ds.MA, ds.MB, ds.R, ds.Rp, row, ds.width, t, rq0, key, st, ds.variant);
         if (e == hipSuccess) e = prof_count_launch(ctx, st);
@@ -827,8 +875,9 @@ static hipError_t energies(const Problem &P, DevState &ds, hipStream_t st)
 {
     if (P.kind == PBIT_GRAPH) return graph_energy(P.graph, ds.spins, ds.Rp, ds.R, ds.E32, st);
     if (P.kind == PBIT_EA3D) return ea_energy(P.ea, ds.spins, ds.Rp, ds.R, ds.E32, st);
-    if (ds.fp4) {
-        hipError_t e = bq4_unpack(P.bq, ds.MA4, ds.MB4, ds.MA, ds.MB, ds.Rp, st);
+    if (ds.fp4 || ds.bits) {
+        hipError_t e = ds.fp4 ? bq4_unpack(P.bq, ds.MA4, ds.MB4, ds.MA, ds.MB, ds.Rp, st)
+                              : bqb_unpack(P.bq, ds.MAb, ds.MBb, ds.MA, ds.MB, ds.Rp, st);
         if (e != hipSuccess) return e;
     }
     return bq_energy(P.bq, ds.MA, ds.MB, ds.R, ds.Rp, ds.E32, st);
@@ -837,7 +886,12 @@ static hipError_t energies(const Problem &P, DevState &ds, hipStream_t st)
 static hipError_t to_rows(const Problem &P, DevState &ds, int8_t *dst, hipStream_t st)
 {
     if (P.kind != PBIT_BICLIQUE) return ea_to_rows(P.ea, ds.spins, ds.Rp, dst, ds.R, st);
-    return ds.fp4 ? bq4_to_rows(P.bq, ds.MA4, ds.MB4, dst, ds.R, st) : bq_to_rows(P.bq, ds.MA, ds.MB, dst, ds.R, st);
+    if (ds.fp4) return bq4_to_rows(P.bq, ds.MA4, ds.MB4, dst, ds.R, st);
+    if (ds.bits) {
+        hipError_t e = bqb_unpack(P.bq, ds.MAb, ds.MBb, ds.MA, ds.MB, ds.Rp, st);
+        if (e != hipSuccess) return e;
+    }
+    return bq_to_rows(P.bq, ds.MA, ds.MB, dst, ds.R, st);
 }
 
 static int fetch_energies(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStream_t st, std::vector<int32_t> &out)
