@@ -898,24 +898,27 @@ __global__ __launch_bounds__(kThreads) void k_bq_field_energy(const int8_t *__re
 // With b_k the bit of site k, m_k = 1 - 2 b_k and the field of a site s is
 //     I_s = h_s + sum_k J_sk m_k = (h_s + sum_k J_sk) - 2 sum_k J_sk b_k,
 // whose last sum runs on the int8 MFMA with int32 accumulation, the bits
-// widened to 0 / 1 bytes in registers.  The spins cross from L2 at one eighth
-// of the int8 bytes, which is what bounds the int8 tiles of large bicliques.
+// widened to bytes in registers.  The spins cross from L2 at one eighth of
+// the int8 bytes, which is what bounds the int8 tiles of large bicliques.
 //
 // Widening: lane half g (lanes 32 g .. 32 g + 31) of an MFMA fragment holds 16
-// K bytes, dword j byte i at K position 16 g + 4 j + i.  From a spin word w the
-// dword (w >> (4 g + j)) & 0x01010101 puts bit 8 i + 4 g + j into byte i, so K
-// position p = 16 g + 4 j + i carries site 8 i + 4 g + j of the 32-site word.
-// The couplings are stored with their columns in that order inside every
-// group of 32 (Jb, JTb), so both operands agree on the site of every K byte.
+// K bytes, dword j byte i at K position 16 g + 4 j + i.  From a spin word w,
+// x = w >> 4 g, the dword x & (0x01010101 << j) holds bit 8 i + 4 g + j of w in
+// byte i, as the value 0 or 2^j: one AND per dword.  The couplings are stored
+// with their columns in that order inside every group of 32 and scaled by
+// 2^(3 - j) (Jb, JTb, values in [-8, 8]), so every product is 8 J b and the
+// accumulator holds 8 sum_k J_sk b_k exactly.
 //
-// Tile: 128 sites x 128 replicas per workgroup, wave w owning replicas
-// 32 w .. 32 w + 31 of the tile and all 128 sites (1 x 4 MFMA blocks), so that
-// each widened spin fragment feeds four MFMAs.  On gfx950 an MFMA holds the
-// wave's VALU issue for about half of its 32 cycles, so the kernel stays on
-// the matrix cores only while the vector work (widening, Philox, decisions)
-// is at most about four instructions per MFMA; this shape keeps it there.
-// Stages of 128 K move by the global-to-LDS DMA into a ring: 128 coupling rows
-// of 128 bytes (chunk c of row r at position c ^ swzb(r)), then the 128
+// Tile: 64 sites x 256 replicas per workgroup, wave w owning replicas
+// 64 w .. 64 w + 63 and all 64 sites (2 x 2 MFMA blocks).  The bytes that
+// reach a CU per multiply-add, 1 / 256 for the couplings plus 1 / 512 for the
+// spin bits, bound these tiles on large bicliques (the L2-to-CU rate of one CU
+// is about 20 bytes per clock); a 64 x 64 block per wave keeps both the
+// vector work (about 2.5 instructions per MFMA: an MFMA holds the wave's VALU
+// issue for about half of its 32 cycles) and the LDS fragment reads (40 KiB per
+// stage) under the matrix-core time of a stage.
+// Stages of 128 K move by the global-to-LDS DMA into a ring: 64 coupling rows
+// of 128 bytes (chunk c of row r at position c ^ swzb(r)), then the 256
 // replicas' 16 bytes (four spin words) of the K block.
 //
 // Decisions through 64-bit words in LDS, one per clamped field value:
@@ -924,54 +927,70 @@ __global__ __launch_bounds__(kThreads) void k_bq_field_energy(const int8_t *__re
 // uniform word w), so a lane's decision is one multiply-add and one compare,
 // and a wave's 64 decisions form one ballot mask.
 
-constexpr int kBitsST = 128;  // sites per tile
-constexpr int kBitsRT = 128;  // replicas per tile
+constexpr int kBitsST = 64;   // sites per tile
+constexpr int kBitsRT = 256;  // replicas per tile
 constexpr int kBitsKT = 128;  // K per stage
-constexpr int kBitsNS = 5;    // stages in the ring
+constexpr int kBitsNS = 8;    // stages in the ring
+constexpr int kBitsWaves = 8; // waves per workgroup: 4 (64 replicas each) or 8 (32 each, two per SIMD)
 
+template <int WAVES>
 struct BitsGeom {
-    static constexpr int jbytes = kBitsST * kBitsKT;     // coupling rows of one stage (16 KiB)
-    static constexpr int bbytes = kBitsRT * kBitsKT / 8; // spin words of one stage (2 KiB)
+    static constexpr int threads = 64 * WAVES;
+    static constexpr int jbytes = kBitsST * kBitsKT;     // coupling rows of one stage (8 KiB)
+    static constexpr int bbytes = kBitsRT * kBitsKT / 8; // spin words of one stage (4 KiB)
     static constexpr int stage = jbytes + bbytes;
-    static constexpr int j_per_wave = jbytes / 1024 / 4; // 16-byte DMA instructions per wave and stage
-    static constexpr int b_per_wave = bbytes / 256 / 4;  // 4-byte DMA instructions per wave and stage
+    static constexpr int j_per_wave = jbytes / 1024 / WAVES;  // 16-byte-lane DMA instructions per wave
+    static constexpr int bsz = WAVES == 4 ? 16 : 4;           // bytes per lane of the spin-word DMA
+    static constexpr int b_per_wave = bbytes / (64 * bsz) / WAVES;
     static constexpr int per_wave = j_per_wave + b_per_wave;
     static constexpr int ahead = per_wave * (kBitsNS - 2);
     static constexpr int ring = kBitsNS * stage;
+    static constexpr int bi = kBitsRT / WAVES / 32;  // 32-replica blocks per wave
     static_assert(ahead < 64, "vmcnt is a 6-bit field");
-    static_assert(j_per_wave * 4 * 1024 == jbytes && b_per_wave * 4 * 256 == bbytes, "whole DMA instructions");
+    static_assert(j_per_wave * WAVES * 1024 == jbytes && b_per_wave * WAVES * 64 * bsz == bbytes,
+                  "whole DMA instructions");
 };
 
-// 0 / 1 bytes of the K bytes that lane half g holds, from one spin word
+// the K bytes that lane half g holds, from one spin word: bit b of a site as
+// b 2^j in dword j
 __device__ __forceinline__ v4i widen_bits(uint32_t w, int g)
 {
     const uint32_t x = w >> (4 * g);
     v4i a;
     a[0] = (int)(x & 0x01010101u);
-    a[1] = (int)((x >> 1) & 0x01010101u);
-    a[2] = (int)((x >> 2) & 0x01010101u);
-    a[3] = (int)((x >> 3) & 0x01010101u);
+    a[1] = (int)(x & 0x02020202u);
+    a[2] = (int)(x & 0x04040404u);
+    a[3] = (int)(x & 0x08080808u);
     return a;
 }
 
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_bq_halfsweep_bits(
-    const uint32_t *__restrict__ Mob, const int8_t *__restrict__ Jb, const int32_t *__restrict__ hs2,
-    uint32_t *__restrict__ Msb, const uint32_t *__restrict__ trow, int width, int Ko, int Rp, int tiles_s,
-    int xcd_bands, uint32_t site_base, uint32_t sweep, uint32_t rq0, uint32_t k0, uint32_t k1, uint32_t one)
+template <int WAVES>
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(WAVES / 4, WAVES / 4))) void
+k_bq_halfsweep_bits(const uint32_t *__restrict__ Mob, const int8_t *__restrict__ Jb, const int32_t *__restrict__ hs2,
+                    uint32_t *__restrict__ Msb, const uint32_t *__restrict__ trow, int width, int Ko, int Rp,
+                    int tiles_s, int xcd_bands, uint32_t site_base, uint32_t sweep, uint32_t rq0, uint32_t k0,
+                    uint32_t k1, uint32_t one)
 {
-    using G = BitsGeom;
+    using G = BitsGeom<WAVES>;
     constexpr int NS = kBitsNS;
     constexpr int CH = kBitsKT / 16;  // 16-byte chunks per coupling row
     constexpr int kSubs = kBitsKT / 32;
+    constexpr int BI = G::bi;         // replica blocks of 32 per wave
+    constexpr int RW = 32 * BI;       // replicas per wave
 
     extern __shared__ uint4 smem[];
     int8_t *ring = reinterpret_cast<int8_t *>(smem);
     uint64_t *Sw = reinterpret_cast<uint64_t *>(ring + G::ring);  // [2 top + 1]
     const int top = width - 1;
-    for (int e = threadIdx.x; e <= 2 * top; e += kThreads) {
-        const int I = e - top;
-        const uint32_t Tm = trow[I >= 0 ? I : -I];
-        Sw[e] = I >= 0 ? (uint64_t)Tm : ((uint64_t)1 << 32) - Tm;
+    // the threshold row goes to registers now and into the LDS decision words after
+    // the K loop, so that its load overlaps the DMA stages instead of preceding them:
+    // thread x holds Tm(x + threads k), k < kTv
+    constexpr int kTv = (kMaxTableWidth + G::threads - 1) / G::threads;
+    uint32_t tv[kTv];
+#pragma unroll
+    for (int k = 0; k < kTv; ++k) {
+        const int x = (int)threadIdx.x + G::threads * k;
+        tv[k] = x <= top ? trow[x] : 0u;
     }
 
     int ts, tr;
@@ -989,10 +1008,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: address math on the SALU
 
     // DMA sources: wave w fills coupling slots 64 (j_per_wave w + j) + lane (16 bytes
-    // each) and spin words 64 (b_per_wave w + j) + lane (4 bytes each) of each stage,
-    // from a wave-uniform base plus a 32-bit lane offset.  Row r of a stage keeps
-    // chunk c at position c ^ swzb(r), with a swizzle of r mod 32 only, so that the
-    // four site blocks of a fragment read sit at fixed distances.
+    // each) and spin-word slots 64 (b_per_wave w + j) + lane (bsz bytes each) of each
+    // stage, from a wave-uniform base plus a 32-bit lane offset.  Row r of a stage keeps
+    // chunk c at position c ^ swzb(r), with a swizzle of r mod 32 only, so that the two
+    // site blocks of a fragment read sit at a fixed distance.
     auto swzb = [](int r) { return (r ^ ((r >> 3) & 3)) & 7; };
     uint32_t offJl[4], offBl[4];
     static_assert(G::j_per_wave <= 4 && G::b_per_wave <= 4 && kSubs <= 4, "fixed array bounds");
@@ -1003,56 +1022,101 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         offJl[j] = (uint32_t)(r * Ko + 16 * c);
     }
 #pragma unroll
-    for (int j = 0; j < G::b_per_wave; ++j) offBl[j] = 4u * (uint32_t)(64 * (G::b_per_wave * wave + j) + lane);
+    for (int j = 0; j < G::b_per_wave; ++j) offBl[j] = (uint32_t)(G::bsz * (64 * (G::b_per_wave * wave + j) + lane));
     const int8_t *Jt0 = Jb + (size_t)s0 * Ko;
     const char *Bt0 = reinterpret_cast<const char *>(Mob + (size_t)r0 * 4);
     const int nk = Ko / kBitsKT;
+    const int ln = lane & 31, kg = lane >> 5;
+    // the fields of this lane's two sites (field plus coupling sum; zero at padding sites),
+    // loaded before the DMA so that the stage waits also cover them
+    const int h2v[2] = {hs2[s0 + ln], hs2[s0 + 32 + ln]};
     auto issue = [&](int t) {
         int8_t *dJ = ring + (t % NS) * G::stage + 1024 * G::j_per_wave * wave;
-        int8_t *dB = ring + (t % NS) * G::stage + G::jbytes + 256 * G::b_per_wave * wave;
+        int8_t *dB = ring + (t % NS) * G::stage + G::jbytes + 64 * G::bsz * G::b_per_wave * wave;
         const int8_t *Jt = Jt0 + (size_t)t * kBitsKT;
         const char *Bt = Bt0 + (size_t)t * 16 * Rp;
 #pragma unroll
         for (int j = 0; j < G::j_per_wave; ++j) __builtin_amdgcn_global_load_lds(Jt + offJl[j], dJ + 1024 * j, 16, 0, 0);
 #pragma unroll
-        for (int j = 0; j < G::b_per_wave; ++j) __builtin_amdgcn_global_load_lds(Bt + offBl[j], dB + 256 * j, 4, 0, 0);
+        for (int j = 0; j < G::b_per_wave; ++j)
+            __builtin_amdgcn_global_load_lds(Bt + offBl[j], dB + 64 * G::bsz * j, G::bsz, 0, 0);
     };
-    wait_vm<0>();  // the threshold row's loads are waited for before any DMA is counted
+    // the threshold row and field loads above are older than every DMA below, so each
+    // wait for a stage also covers them
     for (int t = 0; t < NS - 1 && t < nk; ++t) issue(t);
 
-    const int ln = lane & 31, kg = lane >> 5;
-    // coupling fragment offsets: rows 32 bj + ln, chunk 2 sub + kg; swzb(32 bj + ln) = swzb(ln)
+    // coupling fragment offsets: rows 32 bj + ln, chunk 2 sub + kg; swzb(r) depends on
+    // r mod 32 = ln only, so site block bj = 1 sits 32 rows further
     int offJ[4];
 #pragma unroll
     for (int sub = 0; sub < kSubs; ++sub) offJ[sub] = kBitsKT * ln + 16 * ((2 * sub + kg) ^ swzb(ln));
-    const int offB = G::jbytes + 16 * (32 * wave + ln);  // the spin words of replica row 32 wave + ln
-    v16i acc[4];  // site block bj
+    const int offB = G::jbytes + 16 * (RW * wave + ln);  // spin words of replica rows RW wave + 32 bi + ln
+    v16i acc[BI][2];  // [replica block][site block]
 #pragma unroll
-    for (int bj = 0; bj < 4; ++bj) acc[bj] = v16i{0};
-    uint32_t words[16][4];
+    for (int bi = 0; bi < BI; ++bi) acc[bi][0] = acc[bi][1] = v16i{0};
+    uint32_t words[8 * BI][4];
 
-    auto compute = [&](int t) {
+    // the fragments of one stage in registers: the next stage's are read from LDS
+    // while the MFMAs run on the current one's (a barrier before the reads would
+    // otherwise leave the matrix cores idle for the LDS latency at every stage)
+    struct Frag {
+        v4i w[BI];    // spin words of replica rows 32 bi + ln, one per K step
+        v4i b[4][2];  // coupling fragments [K step][site block]
+    };
+    auto load = [&](int t, Frag &f) {
         const int8_t *st = ring + (t % NS) * G::stage;
         // int vector reads, like every LDS read of the ring: with this access type the
         // compiler adds no wait for all DMA in flight (the stage was waited for, and
         // published by a barrier, before this call)
-        const v4i w = *reinterpret_cast<const v4i *>(st + offB);
 #pragma unroll
-        for (int sub = 0; sub < kSubs; ++sub) {
-            const int8_t *row = st + offJ[sub];
-            v4i b[4];
+        for (int bi = 0; bi < BI; ++bi) f.w[bi] = *reinterpret_cast<const v4i *>(st + offB + 16 * 32 * bi);
 #pragma unroll
-            for (int bj = 0; bj < 4; ++bj) b[bj] = *reinterpret_cast<const v4i *>(row + 32 * kBitsKT * bj);
-            const v4i a = widen_bits((uint32_t)w[sub], kg);
+        for (int sub = 0; sub < kSubs; ++sub)
 #pragma unroll
-            for (int bj = 0; bj < 4; ++bj) acc[bj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b[bj], acc[bj], 0, 0, 0);
+            for (int bj = 0; bj < 2; ++bj)
+                f.b[sub][bj] = *reinterpret_cast<const v4i *>(st + offJ[sub] + 32 * kBitsKT * bj);
+    };
+    auto mfmas = [&](const Frag &f) {
+#pragma unroll
+        for (int sub = 0; sub < kSubs; ++sub)
+#pragma unroll
+            for (int bi = 0; bi < BI; ++bi) {
+                const v4i a = widen_bits((uint32_t)f.w[bi][sub], kg);
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj)
+                    acc[bi][bj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, f.b[sub][bj], acc[bi][bj], 0, 0, 0);
+            }
+    };
+    // an empty statement that takes the fragments as its outputs: called where they are
+    // complete, so that the compiler adds no wait for later reads before the MFMAs that
+    // use them (it emits no instruction)
+    auto settle = [&](Frag &f) {
+        asm volatile("" : "+v"(f.b[0][0]), "+v"(f.b[0][1]), "+v"(f.b[1][0]), "+v"(f.b[1][1]), "+v"(f.b[2][0]),
+                     "+v"(f.b[2][1]), "+v"(f.b[3][0]), "+v"(f.b[3][1]));
+#pragma unroll
+        for (int bi = 0; bi < BI; ++bi) asm volatile("" : "+v"(f.w[bi]));
+    };
+    // stage t: refill the ring, publish stage t + 1 and read its fragments, then the
+    // MFMAs of stage t.  Every wave's reads of stage t are complete (lgkmcnt 0) before
+    // the barrier, so after it no wave reads the slot that the next refill overwrites.
+    auto step = [&](int t, Frag &cur, Frag &nxt) {
+        if (t + NS - 1 < nk) issue(t + NS - 1);
+        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): the current fragments are in registers
+        settle(cur);
+        if (t + 1 < nk) {
+            if (t + NS - 1 < nk) wait_vm<G::ahead>(); else wait_vm<0>();
+            __builtin_amdgcn_s_barrier();
+            asm volatile("" ::: "memory");
+            load(t + 1, nxt);
+            __builtin_amdgcn_sched_barrier(0);  // the reads go out before the MFMAs, not after
         }
+        mfmas(cur);
     };
     auto draw = [&](int blk) {
-        // block 4 bj + q covers site block bj and replica rows 8 q + 4 kg .. + 3 of the wave
-        const int bj = blk >> 2, q = blk & 3;
+        // block (bj BI + bi) 4 + q covers site block bj and replica rows 32 bi + 8 q .. of the wave
+        const int q = blk & 3, bi = (blk >> 2) % BI, bj = (blk >> 2) / BI;
         const int site = s0 + bj * 32 + ln;
-        const int r4 = r0 + 32 * wave + 8 * q + 4 * kg;
+        const int r4 = r0 + RW * wave + bi * 32 + 8 * q + 4 * kg;
         const Block4 b = philox(site_base + (uint32_t)site, sweep, rq0 + (uint32_t)(r4 >> 2), kDomainSweep, k0, k1);
         words[blk][0] = b.w[0];
         words[blk][1] = b.w[1];
@@ -1063,68 +1127,75 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
     if (nk >= NS - 1) wait_vm<G::ahead>(); else wait_vm<0>();
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");  // LDS written by the DMA: no read may move above here
+    Frag fa, fb;
+    load(0, fa);
 
-    // the first stages carry the Philox draws, two blocks each
-    constexpr int kPhxPerStage = 2, kPhxStages = 16 / kPhxPerStage;
+    // the first eight stages carry the Philox draws; stage t computes from fa when t
+    // is even, from fb when odd
+    constexpr int kPhxPerStage = BI, kPhxStages = 8;
     int t = 0;
 #pragma unroll
     for (int u = 0; u < kPhxStages; ++u) {
         if (t < nk) {
-            if (t + NS - 1 < nk) issue(t + NS - 1);
-            compute(t);
-#pragma unroll
-            for (int v = 0; v < kPhxPerStage; ++v) draw(kPhxPerStage * u + v);
-            if (t + NS - 1 < nk) wait_vm<G::ahead>(); else wait_vm<0>();
-            __builtin_amdgcn_s_barrier();
-            asm volatile("" ::: "memory");
+            if (u & 1)
+                step(t, fb, fa);
+            else
+                step(t, fa, fb);
             ++t;
-        } else {
-#pragma unroll
-            for (int v = 0; v < kPhxPerStage; ++v) draw(kPhxPerStage * u + v);
         }
+#pragma unroll
+        for (int v = 0; v < kPhxPerStage; ++v) draw(kPhxPerStage * u + v);
     }
-    for (; t + NS - 1 < nk; ++t) {
-        issue(t + NS - 1);
-        compute(t);
-        wait_vm<G::ahead>();
-        __builtin_amdgcn_s_barrier();
-        asm volatile("" ::: "memory");
+    // kPhxStages is even: stage t computes from fa again
+    for (; t + 1 < nk; t += 2) {
+        step(t, fa, fb);
+        step(t + 1, fb, fa);
     }
-    for (; t < nk; ++t) {
-        compute(t);
-        wait_vm<0>();
-        __builtin_amdgcn_s_barrier();
-        asm volatile("" ::: "memory");
-    }
+    if (t < nk) step(t, fa, fb);
 
-    // epilogue: one ballot per (site block, q, p) gives the new spin bits of 32
-    // sites for two replicas (lane half 0: row 8 q + p of the wave, half 1: row
-    // 8 q + 4 + p); lane L < 32 of out[bj] collects the word of replica row L of
-    // the wave for site block bj.  Padding sites and replicas take bits that
-    // nothing reads (their couplings and fields are zero).
-    const char *Sb = reinterpret_cast<const char *>(Sw);
-    uint32_t out[4] = {0u, 0u, 0u, 0u};
+    // epilogue: one ballot per (site block, replica block, q, p) gives the new
+    // spin bits of 32 sites for two replicas (lane half 0: row 8 q + p of the
+    // block, half 1: row 8 q + 4 + p); lane L of out[bj] collects the word of
+    // replica row L of the wave for site block bj.  Padding sites and replicas
+    // take bits that nothing reads (their couplings and fields are zero).
+    // decision words for I = +-x from Tm(x): Tm for I >= 0, 2^32 - Tm for I < 0; built
+    // here, where no DMA is in flight, so that waiting for the row costs nothing
 #pragma unroll
-    for (int bj = 0; bj < 4; ++bj) {
-        const int h2 = hs2[s0 + bj * 32 + ln];  // field plus coupling sum; zero at padding sites
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-#pragma unroll
-            for (int p = 0; p < 4; ++p) {
-                const int I = h2 - 2 * acc[bj][4 * q + p];
-                const int Ic = min(max(I, -top), top);
-                const uint64_t S = *static_cast<const uint64_t *>(__builtin_assume_aligned(Sb + 8 * (Ic + top), 8));
-                const uint64_t m = __ballot((((uint64_t)words[4 * bj + q][p] * one + S) >> 32) != 0);
-                const int L = 8 * q + p;
-                out[bj] = (uint32_t)lane_write((int)(uint32_t)m, L, (int)out[bj]);
-                out[bj] = (uint32_t)lane_write((int)(uint32_t)(m >> 32), L + 4, (int)out[bj]);
-            }
+    for (int k = 0; k < kTv; ++k) {
+        const int x = (int)threadIdx.x + G::threads * k;
+        if (x <= top) {
+            Sw[top + x] = (uint64_t)tv[k];
+            Sw[top - x] = ((uint64_t)1 << 32) - tv[k];
         }
     }
-    // the four words of replica row ln: one aligned block of four at site word s0 / 32
-    if (lane < 32)
-        *reinterpret_cast<uint4 *>(Msb + ((size_t)(s0 / kBitsKT) * Rp + r0 + 32 * wave + lane) * 4) =
-            make_uint4(out[0], out[1], out[2], out[3]);
+    __syncthreads();
+    const char *Sb = reinterpret_cast<const char *>(Sw);
+    uint32_t out[2] = {0u, 0u};
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+        const int h2 = h2v[bj];
+#pragma unroll
+        for (int bi = 0; bi < BI; ++bi)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int blk = (bj * BI + bi) * 4 + q;
+#pragma unroll
+                for (int p = 0; p < 4; ++p) {
+                    const int I = h2 - (acc[bi][bj][4 * q + p] >> 2);  // the accumulator holds 8 sum J b
+                    const int Ic = min(max(I, -top), top);
+                    const uint64_t S =
+                        *static_cast<const uint64_t *>(__builtin_assume_aligned(Sb + 8 * (Ic + top), 8));
+                    const uint64_t m = __ballot((((uint64_t)words[blk][p] * one + S) >> 32) != 0);
+                    const int L = bi * 32 + 8 * q + p;
+                    out[bj] = (uint32_t)lane_write((int)(uint32_t)m, L, (int)out[bj]);
+                    out[bj] = (uint32_t)lane_write((int)(uint32_t)(m >> 32), L + 4, (int)out[bj]);
+                }
+            }
+    }
+    // words s0 / 32 and + 1 of replica row RW wave + lane: an aligned pair in a block of four
+    if (lane < RW)
+        *reinterpret_cast<uint2 *>(Msb + ((size_t)(s0 / kBitsKT) * Rp + r0 + RW * wave + lane) * 4 + (s0 / 32) % 4) =
+            make_uint2(out[0], out[1]);
 }
 
 // int8 rows [Rp][cols] <-> spin words by blocks of 128 sites; one thread per word
@@ -1371,11 +1442,13 @@ bool bqb_supported(const BqView &p, int Rp)
 hipError_t bqb_halfsweep(const BqView &p, int side, uint32_t *MAb, uint32_t *MBb, int Rp, const uint32_t *trow,
                          int width, uint32_t sweep, uint32_t rq0, Key key, hipStream_t st)
 {
+    constexpr int WAVES = kBitsWaves;
+    using G = BitsGeom<WAVES>;
     if (!bqb_supported(p, Rp) || width < 1 || width > kMaxTableWidth) return hipErrorInvalidValue;
     static const hipError_t lds_attr =
-        hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bq_halfsweep_bits),
+        hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bq_halfsweep_bits<WAVES>),
                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                            BitsGeom::ring + (int)sizeof(uint64_t) * (2 * kMaxTableWidth - 1));
+                            G::ring + (int)sizeof(uint64_t) * (2 * kMaxTableWidth - 1));
     if (lds_attr != hipSuccess) return lds_attr;
     const bool A = side == 0;
     const int Ns_p = A ? p.na_p : p.nb_p, Ko = A ? p.nb_p : p.na_p;
@@ -1386,9 +1459,9 @@ hipError_t bqb_halfsweep(const BqView &p, int side, uint32_t *MAb, uint32_t *MBb
     const uint32_t site_base = A ? 0u : (uint32_t)p.na;
     const int tiles_s = Ns_p / kBitsST, tiles_r = Rp / kBitsRT;
     const int bands = tiles_s % 8 == 0 ? 1 : 0;
-    hipLaunchKernelGGL(k_bq_halfsweep_bits, dim3((unsigned)(tiles_s * tiles_r)), dim3(kThreads),
-                       (BitsGeom::ring + sizeof(uint64_t) * (size_t)(2 * width - 1)), st, Mob, Jb, hs2, Msb, trow,
-                       width, Ko, Rp, tiles_s, bands, site_base, sweep, rq0, key.k0, key.k1, 1u);
+    hipLaunchKernelGGL(k_bq_halfsweep_bits<WAVES>, dim3((unsigned)(tiles_s * tiles_r)), dim3(G::threads),
+                       (G::ring + sizeof(uint64_t) * (size_t)(2 * width - 1)), st, Mob, Jb, hs2, Msb, trow, width, Ko,
+                       Rp, tiles_s, bands, site_base, sweep, rq0, key.k0, key.k1, 1u);
     return hipGetLastError();
 }
 

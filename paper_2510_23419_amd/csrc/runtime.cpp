@@ -355,15 +355,17 @@ static int load_biclique(pbit_ctx *ctx, const pbit_problem_desc *d, Problem &p)
     void *dJb = nullptr, *dJTb = nullptr, *dhA2 = nullptr, *dhB2 = nullptr;
     if (rc == PBIT_OK && pad == kBqPadLarge) {
         // the half-sweep on spin bits: K byte p = 16 g + 4 j + i of every group of 32
-        // columns holds column 8 i + 4 g + j of the group, and each field carries the
-        // coupling sum of its site
+        // columns holds column 8 i + 4 g + j of the group times 2^(3 - j) (the spin
+        // byte it meets holds the bit times 2^j), and each field carries the coupling
+        // sum of its site
         auto permute = [](const std::vector<int8_t> &M, int rows, int cols, std::vector<int8_t> &out) {
             out.assign(M.size(), 0);
             for (int r = 0; r < rows; ++r)
                 for (int c0 = 0; c0 < cols; c0 += 32)
                     for (int q = 0; q < 32; ++q) {
                         const int g = q >> 4, j = (q >> 2) & 3, i = q & 3;
-                        out[(size_t)r * cols + c0 + q] = M[(size_t)r * cols + c0 + 8 * i + 4 * g + j];
+                        out[(size_t)r * cols + c0 + q] =
+                            (int8_t)(M[(size_t)r * cols + c0 + 8 * i + 4 * g + j] * (1 << (3 - j)));
                     }
         };
         std::vector<int8_t> Jb, JTb;
@@ -766,7 +768,9 @@ static int prepare(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, h
     } else {
         // int8 spins, plus a packed copy where a kernel runs on one: packed 4-bit floats on
         // request, bits where the sides are padded to 128 (the tuner then times the bit kernel)
-        ds.Rp = round_up(R, kBqRPad);
+        // the bit kernel's tiles hold 256 replicas: a forced bit kernel pads to that
+        const bool bits_forced = ctx->bq_forced == BqVariant::Bits && P.bq.Jb;
+        ds.Rp = round_up(R, bits_forced ? 256 : kBqRPad);
         const size_t a = (size_t)ds.Rp * P.bq.na_p, b = (size_t)ds.Rp * P.bq.nb_p;
         ds.fp4 = P.bq.fp4_sweep && ctx->bq_forced == BqVariant::Fp4;
         rc = scratch(ctx, Slot::Spins, a + b, &v);
