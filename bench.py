@@ -30,6 +30,9 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 INT8_MFMA_PEAK_TOPS = 5000.0   # MI355X dense int8 MFMA, published (TOP/s)
 FP4_MFMA_PEAK_TOPS = 10100.0   # MI355X dense fp4 MFMA, published (TOP/s)
+# biclique half-sweep kernels by variant number (pbit_profile_variant)
+BQ_KERNELS = {1: "k_bq_halfsweep", 2: "k_bq_halfsweep_t128", 3: "k_bq_halfsweep_t128", 4: "k_bq_halfsweep_t128",
+              5: "k_bq_halfsweep_dma", 6: "k_bq_halfsweep_dma", 7: "k_bq_halfsweep_fp4", 8: "k_bq_halfsweep_bits"}
 VALU_PEAK_TLANEOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 32-bit vector lane-ops/s: CUs x SIMDs x lanes x clock
 
 WORKLOADS = {
@@ -338,13 +341,15 @@ def main():
     else:
         n = w["n"]
         alg_ops = 2 * n * n * R  # one side's fields: n x n couplings times n x R spins
-        # int8 operands with int32 accumulation by default; with PBIT_BQ_VARIANT=7 sides
-        # of 512 or more run on packed 4-bit float operands (the fp4 MFMA). The roofline
-        # takes the peak of the dtype that ran
-        fp4 = n >= 512 and os.environ.get("PBIT_BQ_VARIANT", "") == "7"
+        # the kernel the library ran (autotuned among int8-operand variants unless
+        # PBIT_BQ_VARIANT forces one; 7 = packed 4-bit float operands). The roofline
+        # takes the peak of the operand type that ran
+        variant = pbit.pbit_profile_variant(ctx.ctx)
+        fp4 = variant == 7
         roof = {"bound": "mfma", "achieved": alg_ops / (avg_ms * 1e-3) / 1e12,
                 "peak": FP4_MFMA_PEAK_TOPS if fp4 else INT8_MFMA_PEAK_TOPS, "unit": "TOP/s", "traffic": None,
-                "kernel": "k_bq_halfsweep_fp4" if fp4 else "k_bq_halfsweep", "operands": "fp4" if fp4 else "int8",
+                "kernel": BQ_KERNELS.get(variant, "k_bq_halfsweep"), "variant": variant,
+                "operands": "fp4" if fp4 else "int8",
                 "alg_ops_per_launch": alg_ops, "avg_launch_us": avg_ms * 1e3, "launches_timed": launches}
     if launches == 0:  # launch timing switched off (--profile-every 0)
         roof["achieved"] = None

@@ -253,6 +253,14 @@ int pbit_profile_enable(pbit_ctx *ctx, int32_t every);
  * clears the counters after reading. */
 int pbit_profile_read(pbit_ctx *ctx, int32_t kind, double *total_ms, int64_t *launches, int32_t reset);
 
+/* The biclique half-sweep kernel the latest biclique anneal on this context ran
+ * (0 before any): 1 = 64 x 64 tiles from global memory, 2..4 = LDS-tiled with a
+ * register ring, 5, 6 = LDS-tiled through the global-to-LDS DMA, 7 = packed 4-bit
+ * float operands, 8 = spins held as bits.  The library picks the fastest on the
+ * first anneal of a shape unless PBIT_BQ_VARIANT names one when the context is
+ * created.  *variant is written on success only. */
+int pbit_profile_variant(pbit_ctx *ctx, int32_t *variant);
+
 /* ---- host-side helpers (no GPU needed) ---------------------------------- */
 
 /* The uint32 minority-threshold table Tm[s][a], s < S, a <= A, as the library

@@ -821,6 +821,7 @@ static int prepare(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, h
         if (rc) return rc;
     }
     ds.bits = P.kind == PBIT_BICLIQUE && ds.variant == BqVariant::Bits;
+    if (P.kind == PBIT_BICLIQUE && d->n_sweeps > 0) ctx->bq_last_variant = (int)ds.variant;
 
     const Key key{(uint32_t)d->seed, (uint32_t)(d->seed >> 32)};
     const uint32_t rq0 = (uint32_t)d->replica_offset >> 2;
@@ -1143,6 +1144,14 @@ extern "C" int pbit_profile_enable(pbit_ctx *ctx, int32_t every)
     PBIT_ENTER(ctx);
     if (every < 0) return fail(PBIT_E_ARG, "pbit_profile_enable: every must be >= 0");
     ctx->prof_every = every;
+    return PBIT_OK;
+}
+
+extern "C" int pbit_profile_variant(pbit_ctx *ctx, int32_t *variant)
+{
+    PBIT_ENTER(ctx);
+    if (!variant) return fail(PBIT_E_ARG, "pbit_profile_variant: variant is NULL");
+    *variant = ctx->bq_last_variant;
     return PBIT_OK;
 }
 

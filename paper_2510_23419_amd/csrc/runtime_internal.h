@@ -62,6 +62,7 @@ struct pbit_ctx {
     int64_t prof_count[3] = {0, 0, 0};
     // biclique kernel variant: forced (PBIT_BQ_VARIANT) or autotuned per shape
     pbit::BqVariant bq_forced = pbit::BqVariant::Auto;
+    int bq_last_variant = 0;  // biclique half-sweep variant of the latest biclique anneal (0: none yet)
     std::map<std::array<int, 3>, pbit::BqVariant> bq_tuned;  // (na_p, nb_p, Rp) -> fastest
 };
 

@@ -35,7 +35,7 @@ EXPORTS = ("pbit_create", "pbit_destroy", "pbit_last_error", "pbit_bytes_in_use"
            "pbit_unload_problem", "pbit_problem_spins", "pbit_anneal", "pbit_anneal_dev", "pbit_energy",
            "pbit_submit", "pbit_poll", "pbit_progress", "pbit_threshold_table", "pbit_version",
            "pbit_profile_enable", "pbit_profile_read", "pbit_anneal_batch", "pbit_serve_config",
-           "pbit_load_graph", "pbit_problem_colouring", "pbit_greedy_colouring")
+           "pbit_load_graph", "pbit_problem_colouring", "pbit_greedy_colouring", "pbit_profile_variant")
 
 
 class PbitError(RuntimeError):
@@ -107,6 +107,7 @@ def lib() -> ctypes.CDLL:
             "pbit_version": ([], ctypes.c_char_p),
             "pbit_profile_enable": ([P, i32], ctypes.c_int),
             "pbit_profile_read": ([P, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), i32], ctypes.c_int),
+            "pbit_profile_variant": ([P, ctypes.POINTER(i32)], ctypes.c_int),
             "pbit_anneal_batch": ([P, ctypes.POINTER(BatchJob), i32], ctypes.c_int),
             "pbit_serve_config": ([P, i32, i32, i32], ctypes.c_int),
             "pbit_load_graph": ([P, ctypes.POINTER(GraphDesc), ctypes.POINTER(u64)], ctypes.c_int),
@@ -328,6 +329,12 @@ def pbit_profile_read(ctx, kind: int, reset: bool = False):
     _check(lib().pbit_profile_read(ctx, int(kind), ctypes.byref(ms), ctypes.byref(n), 1 if reset else 0))
     return float(ms.value), int(n.value)
 
+
+def pbit_profile_variant(ctx) -> int:
+    """Biclique half-sweep kernel variant of the latest biclique anneal (0: none yet)."""
+    v = ctypes.c_int32(0)
+    _check(lib().pbit_profile_variant(ctx, ctypes.byref(v)))
+    return int(v.value)
 
 def pbit_threshold_table(beta, A: int) -> np.ndarray:
     beta = np.ascontiguousarray(beta, dtype=np.float64).reshape(-1)

@@ -20,6 +20,8 @@ from tests.test_parity_gpu import _check_sampled, _every_sweep, graph_of
 
 pytestmark = pytest.mark.gpu
 
+_FORCED = {}  # context -> forced variant
+
 
 def _say(msg):
     print(msg, flush=True)
@@ -34,6 +36,7 @@ def vctx(request):
     os.environ["PBIT_BQ_VARIANT"] = request.param
     try:
         c = pbit.Context(0)
+        _FORCED[c.ctx.value] = int(request.param)
     finally:
         if old is None:
             del os.environ["PBIT_BQ_VARIANT"]
@@ -49,6 +52,9 @@ def test_variant_every_replica_every_sweep(vctx, na, nb, R):
     inst = synth.biclique_instance(na, seed=na + 3 * nb, nb=nb)
     _say("forced variant biclique %dx%d R=%d every sweep" % (na, nb, R))
     _every_sweep(vctx, inst, synth.beta_linear(0.05, 2.0, 8), R, seed=12)
+    # the library reports the kernel that ran: the forced one, or the 64 x 64 tiles
+    # that small sides fall back to
+    assert pbit.pbit_profile_variant(vctx) == (_FORCED[vctx.value] if min(na, nb) >= 512 else 1)
 
 
 @pytest.mark.parametrize("n,prefixes", [(1024, [1, 2, 10]), (4096, [1, 2])])
