@@ -909,14 +909,16 @@ __global__ __launch_bounds__(kThreads) void k_bq_field_energy(const int8_t *__re
 // 2^(3 - j) (Jb, JTb, values in [-8, 8]), so every product is 8 J b and the
 // accumulator holds 8 sum_k J_sk b_k exactly.
 //
-// Tile: 64 sites x 256 replicas per workgroup, wave w owning replicas
-// 64 w .. 64 w + 63 and all 64 sites (2 x 2 MFMA blocks).  The bytes that
-// reach a CU per multiply-add, 1 / 256 for the couplings plus 1 / 512 for the
-// spin bits, bound these tiles on large bicliques (the L2-to-CU rate of one CU
-// is about 20 bytes per clock); a 64 x 64 block per wave keeps both the
-// vector work (about 2.5 instructions per MFMA: an MFMA holds the wave's VALU
-// issue for about half of its 32 cycles) and the LDS fragment reads (40 KiB per
-// stage) under the matrix-core time of a stage.
+// Tile: 64 sites x 256 replicas per workgroup.  The bytes that reach a CU per
+// multiply-add, 1 / 256 for the couplings plus 1 / 512 for the spin bits, bound
+// these tiles on large bicliques (the L2-to-CU rate of one CU is about 20 bytes
+// per clock).  Eight waves, two per SIMD so that one wave's waits are covered by
+// the other's MFMAs, each own RW = 32 replicas and all 64 sites (1 x 2 MFMA
+// blocks); with kBitsWaves = 4 the template builds the four-wave form (64
+// replicas, 2 x 2 blocks), about 5 % slower.  Either way the vector work stays
+// near 2.5 instructions per MFMA (an
+// MFMA holds the wave's VALU issue for about half of its 32 cycles) and the LDS
+// fragment reads under the matrix-core time of a stage.
 // Stages of 128 K move by the global-to-LDS DMA into a ring: 64 coupling rows
 // of 128 bytes (chunk c of row r at position c ^ swzb(r)), then the 256
 // replicas' 16 bytes (four spin words) of the K block.
