@@ -234,9 +234,186 @@ __device__ __forceinline__ v16f mfma_fp4(v4i a, v4i b, v16f c)
     return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a8, b8, c, 4, 4, 0, 127, 0, 127);
 }
 
+// v_writelane_b32: lane `lane` of `old` takes the wave-uniform `val` (the
+// compiler's intrinsic, bound by name: hip exposes no builtin for it)
+__device__ int tile_lane_write(int val, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+
+// Biclique tiles with the spins held as bits in LDS: row r holds one bit per site (set = -1), 32 sites per word, side A
+// in words [0, na_p / 32), side B after it, with an odd row pitch so that the 32
+// rows a fragment read touches sit on distinct banks.  A K step of 32 sites is
+// one word per replica, widened in registers to the bytes bit * 2^j (dword j)
+// and multiplied on the int8 MFMA with int32 sums by the couplings stored in
+// the widened-bit column order and scaled by 2^(3 - j) (Jb, JTb): the sum is
+// 8 sum_k J_sk b_k and the field is I = (h + sum_k J) - (acc >> 2), exact.
+// A bit row is an eighth of an int8 row, so 128 replicas fit LDS at any side
+// length and each coupling fragment feeds RB MFMAs: couplings reach the CU at
+// 1 / (32 RB) bytes per multiply-add.  Decisions as in the int8 tiles; the 64
+// decisions of a wave for one (replica group, p) form a ballot mask, and the
+// words of the 32 replicas of a block are written by one lane each.
+template <int RB>
+__global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles_bits(const BqJobDev *__restrict__ jobs,
+                                                                  const WorkItem *__restrict__ items,
+                                                                  const int32_t *__restrict__ n_items_p,
+                                                                  int32_t *__restrict__ counter, uint32_t one)
+{
+    constexpr int RS = 32 * RB;
+    extern __shared__ uint4 dyn[];
+    __shared__ int32_t eacc[RS];
+    __shared__ int slot;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, ln = lane & 31, kg = lane >> 5;
+    const int wave = tid >> 6;
+    const int n_items = *n_items_p;
+
+    for (;;) {
+        const int it = take_item(counter, &slot);
+        if (it >= n_items) break;
+        const WorkItem w = items[it];
+        const BqJobDev jb = jobs[w.job];
+        const int na = jb.na, nb = jb.nb, na_p = jb.na_p, nb_p = jb.nb_p;
+        const int wa = na_p / 32, wb = nb_p / 32;  // spin words of each side in a row
+        const int PW = wa + wb, pitch = PW + 1;    // words per row in global memory / in LDS
+        uint32_t *sw = reinterpret_cast<uint32_t *>(dyn);
+        // decision words after the rows, 8-byte aligned
+        uint64_t *Sw = reinterpret_cast<uint64_t *>(sw + ((RS * pitch + 1) & ~1));
+        const char *Sb = reinterpret_cast<const char *>(Sw);
+        uint32_t *gst = reinterpret_cast<uint32_t *>(jb.state) + (size_t)w.tile * RS * PW;
+        const uint32_t rg0 = jb.rq0 + (uint32_t)(w.tile * (RS / 4));
+
+        if (w.init) {
+            for (int k = tid; k < RS * pitch; k += kBqTileThreads) sw[k] = 0u;
+            __syncthreads();
+            // thread (site, replica group): the four replicas' spins of one site
+            for (int k = tid; k < (na + nb) * (RS / 4); k += kBqTileThreads) {
+                const int g = k % (RS / 4), i = k / (RS / 4);  // site id: A first, then B
+                const int col = i < na ? i : na_p + (i - na);
+                const Block4 b = philox((uint32_t)i, 0u, rg0 + (uint32_t)g, kDomainInit, jb.k0, jb.k1);
+#pragma unroll
+                for (int p = 0; p < 4; ++p)
+                    if (init_spin(b.w[p]) < 0) atomicOr(&sw[(4 * g + p) * pitch + col / 32], 1u << (col % 32));
+            }
+        } else {
+            for (int k = tid; k < RS * PW; k += kBqTileThreads) {
+                const int r = k / PW, c = k % PW;
+                sw[r * pitch + c] = gst[(size_t)r * PW + c];
+            }
+        }
+        if (tid < RS) eacc[tid] = 0;
+
+        for (int s = w.s_begin; s < w.s_end; ++s) {
+            __syncthreads();
+            const uint32_t *trow = jb.table + (size_t)s * jb.width;
+            const int top = jb.width - 1;
+            for (int e = tid; e <= 2 * top; e += kBqTileThreads) {
+                const int I = e - top;
+                const uint32_t Tm = trow[I >= 0 ? I : -I];
+                Sw[e] = I >= 0 ? (uint64_t)Tm : ((uint64_t)1 << 32) - Tm;
+            }
+            __syncthreads();
+            const uint32_t t = jb.sweep0 + (uint32_t)s;
+            const bool last = s + 1 == w.s_end;
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                const int ns_p = side == 0 ? na_p : nb_p;
+                const int ns = side == 0 ? na : nb;
+                const int ko = side == 0 ? nb_p : na_p;  // coupling bytes per row (the other side)
+                const int in_w = side == 0 ? wa : 0;     // word column of the other side
+                const int out_w = side == 0 ? 0 : wa;    // word column of this side
+                const uint8_t *Jx = reinterpret_cast<const uint8_t *>(side == 0 ? jb.Jb : jb.JTb);
+                const int32_t *hs2 = side == 0 ? jb.hA2 : jb.hB2;
+                const uint32_t site_base = side == 0 ? 0u : (uint32_t)na;
+                // one 32-site block per wave at a time; its coupling fragments stream
+                // from global memory through a ring kRing K-units (32 bytes) ahead,
+                // which past the end of a block fills with the wave's next block
+                const int nku = ko / 32;
+                constexpr int kStep = kBqTileThreads / 64;
+                const int nblk = ns_p / 32;
+                v4i ring[kRing];
+                if (wave < nblk) {
+                    const uint8_t *br0 = Jx + (size_t)(wave * 32 + ln) * ko + 16 * kg;
+#pragma unroll
+                    for (int u = 0; u < kRing; ++u) ring[u] = *reinterpret_cast<const v4i *>(br0 + 32 * min(u, nku - 1));
+                }
+                for (int blk = wave; blk < nblk; blk += kStep) {
+                    const int site = blk * 32 + ln;
+                    const uint8_t *br = Jx + (size_t)site * ko + 16 * kg;
+                    const uint8_t *bn = blk + kStep < nblk ? br + (size_t)kStep * 32 * ko : br;
+                    v16i acc[RB];
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb) acc[rb] = v16i{0};
+                    const uint32_t *abase = sw + ln * pitch + in_w;
+                    for (int kb = 0; kb < nku; kb += kRing) {
+#pragma unroll
+                        for (int u = 0; u < kRing; ++u) {
+                            const int ku = kb + u;
+                            if (ku < nku) {
+                                const v4i b = ring[u];
+                                const int kn = ku + kRing;
+                                ring[u] = *reinterpret_cast<const v4i *>(kn < nku ? br + 32 * kn
+                                                                                : bn + 32 * min(u, nku - 1));
+#pragma unroll
+                                for (int rb = 0; rb < RB; ++rb) {
+                                    const uint32_t x = abase[rb * 32 * pitch + ku] >> (4 * kg);
+                                    const v4i a = {(int)(x & 0x01010101u), (int)(x & 0x02020202u),
+                                                   (int)(x & 0x04040404u), (int)(x & 0x08080808u)};
+                                    acc[rb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, acc[rb], 0, 0, 0);
+                                }
+                            }
+                        }
+                    }
+                    // decisions; padding sites take bits that nothing reads (their
+                    // couplings and fields are zero and they are never returned)
+                    const int h2 = hs2[site];  // field plus coupling sum; site < ns_p
+                    const bool site_ok = site < ns;
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb) {
+                        uint32_t outw = 0u;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int r4 = rb * 32 + 8 * q + 4 * kg;  // first replica of the group in the tile
+                            const Block4 b = philox(site_base + (uint32_t)site, t, rg0 + (uint32_t)(r4 >> 2),
+                                                    kDomainSweep, jb.k0, jb.k1);
+#pragma unroll
+                            for (int p = 0; p < 4; ++p) {
+                                const int I = h2 - (acc[rb][4 * q + p] >> 2);  // the accumulator holds 8 sum J b
+                                const int Ic = min(max(I, -top), top);
+                                const uint64_t S = *static_cast<const uint64_t *>(
+                                    __builtin_assume_aligned(Sb + 8 * (Ic + top), 8));
+                                const bool neg = (((uint64_t)b.w[p] * one + S) >> 32) != 0;  // new spin -1
+                                // energy after the last side-B update: E = -sum_b m_b I_b - sum_a h_a m_a
+                                if (side == 1 && last && site_ok) atomicAdd(&eacc[r4 + p], neg ? I : -I);
+                                const uint64_t m = __ballot(neg);
+                                const int L = 8 * q + p;
+                                outw = (uint32_t)tile_lane_write((int)(uint32_t)m, L, (int)outw);
+                                outw = (uint32_t)tile_lane_write((int)(uint32_t)(m >> 32), L + 4, (int)outw);
+                            }
+                        }
+                        if (lane < 32) sw[(rb * 32 + lane) * pitch + out_w + blk] = outw;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+
+        // field part of side A, then the energies and the spins go back to global memory
+        for (int k = tid; k < RS * na; k += kBqTileThreads) {
+            const int r = k / na, a = k % na;
+            const int m = (sw[r * pitch + a / 32] >> (a % 32)) & 1u ? -1 : 1;
+            const int v = (int)jb.hA[a] * m;
+            if (v != 0) atomicAdd(&eacc[r], -v);
+        }
+        __syncthreads();
+        if (tid < RS) jb.energy[w.tile * RS + tid] = eacc[tid];
+        for (int k = tid; k < RS * PW; k += kBqTileThreads) {
+            const int r = k / PW, c = k % PW;
+            gst[(size_t)r * PW + c] = sw[r * pitch + c];
+        }
+    }
+}
+
 // A tile holds RB x 32 replicas of both sides in LDS, one row per replica:
-// side A first, then side B, zero padding.  With int8 operands (the default)
-// a row holds one byte per site and the half-sweep is the int8 MFMA with int32
+// side A first, then side B, zero padding.  With int8 operands a row holds one
+// byte per site and the half-sweep is the int8 MFMA with int32
 // accumulation; with FP4 operands a row holds packed 4-bit floats (e2m1: +1 =
 // 0x2, -1 = 0xA, 0 = 0x0; two sites per byte, lower site in the low nibble) and
 // the half-sweep is the f8f6f4 MFMA with fp32 accumulation — exact, since every
@@ -453,11 +630,15 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
 
 size_t ea_tile_lds(int64_t N) { return (size_t)N * sizeof(uint32_t); }
 
-size_t bq_tile_lds(int rs, int na_p, int nb_p, int width, bool fp4)
+size_t bq_tile_lds(int rs, int na_p, int nb_p, int width, int mode)
 {
     // spin rows, then one 64-bit decision word per field value in [-(width - 1), width - 1]
-    const size_t row = (size_t)(fp4 ? (na_p + nb_p) / 2 : na_p + nb_p) + 16;
-    return (size_t)rs * row + sizeof(uint64_t) * (size_t)(2 * width - 1);
+    size_t rows;
+    if (mode == kTileBits)
+        rows = sizeof(uint32_t) * (size_t)((rs * ((na_p + nb_p) / 32 + 1) + 1) & ~1);
+    else
+        rows = (size_t)rs * ((size_t)(mode == kTileFp4 ? (na_p + nb_p) / 2 : na_p + nb_p) + 16);
+    return rows + sizeof(uint64_t) * (size_t)(2 * width - 1);
 }
 
 hipError_t tiles_set_lds_limit()
@@ -465,7 +646,10 @@ hipError_t tiles_set_lds_limit()
     const int max_lds = 160 * 1024 - 4096;  // leave room for the static shared variables
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ea_tiles),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
-    const void *bq_kernels[] = {reinterpret_cast<const void *>(&k_bq_tiles<1, false>),
+    const void *bq_kernels[] = {reinterpret_cast<const void *>(&k_bq_tiles_bits<1>),
+                                reinterpret_cast<const void *>(&k_bq_tiles_bits<2>),
+                                reinterpret_cast<const void *>(&k_bq_tiles_bits<4>),
+                                reinterpret_cast<const void *>(&k_bq_tiles<1, false>),
                                 reinterpret_cast<const void *>(&k_bq_tiles<2, false>),
                                 reinterpret_cast<const void *>(&k_bq_tiles<4, false>),
                                 reinterpret_cast<const void *>(&k_bq_tiles<1, true>),
@@ -485,19 +669,21 @@ hipError_t ea_tiles(const EaJobDev *jobs, const WorkItem *items, const int32_t *
 }
 
 hipError_t bq_tiles(const BqJobDev *jobs, const WorkItem *items, const int32_t *n_items, int32_t *counter, int rs,
-                    bool fp4, int grid, size_t lds_bytes, hipStream_t st)
+                    int mode, int grid, size_t lds_bytes, hipStream_t st)
 {
-#define PBIT_BQ_TILES(RB, F)                                                                                    \
-    hipLaunchKernelGGL((k_bq_tiles<RB, F>), dim3((unsigned)grid), dim3(kBqTileThreads), lds_bytes, st, jobs, items, \
-                       n_items, counter, 1u)
-    if (rs == 128) {
-        if (fp4) PBIT_BQ_TILES(4, true); else PBIT_BQ_TILES(4, false);
-    } else if (rs == 64) {
-        if (fp4) PBIT_BQ_TILES(2, true); else PBIT_BQ_TILES(2, false);
-    } else if (rs == 32) {
-        if (fp4) PBIT_BQ_TILES(1, true); else PBIT_BQ_TILES(1, false);
+#define PBIT_BQ_TILES(K)                                                                                        \
+    hipLaunchKernelGGL(K, dim3((unsigned)grid), dim3(kBqTileThreads), lds_bytes, st, jobs, items, n_items, counter, 1u)
+    const int rb = rs == 128 ? 4 : rs == 64 ? 2 : rs == 32 ? 1 : 0;
+    if (rb == 0 || mode < kTileInt8 || mode > kTileBits) return hipErrorInvalidValue;
+    if (mode == kTileBits) {
+        if (rb == 4) PBIT_BQ_TILES((k_bq_tiles_bits<4>)); else if (rb == 2) PBIT_BQ_TILES((k_bq_tiles_bits<2>));
+        else PBIT_BQ_TILES((k_bq_tiles_bits<1>));
+    } else if (mode == kTileFp4) {
+        if (rb == 4) PBIT_BQ_TILES((k_bq_tiles<4, true>)); else if (rb == 2) PBIT_BQ_TILES((k_bq_tiles<2, true>));
+        else PBIT_BQ_TILES((k_bq_tiles<1, true>));
     } else {
-        return hipErrorInvalidValue;
+        if (rb == 4) PBIT_BQ_TILES((k_bq_tiles<4, false>)); else if (rb == 2) PBIT_BQ_TILES((k_bq_tiles<2, false>));
+        else PBIT_BQ_TILES((k_bq_tiles<1, false>));
     }
 #undef PBIT_BQ_TILES
     return hipGetLastError();

@@ -18,9 +18,10 @@ struct BqView {
     const uint8_t *J4;
     const uint8_t *JT4;
     bool fp4_sweep;  // both sides padded to 128: the per-instance half-sweep runs on fp4 operands
-    // for the half-sweep on spin bits (sides padded to 128, else null): the couplings
-    // with the columns of every group of 32 in the order the widened bits take,
-    // [na_p][nb_p] and [nb_p][na_p], and each site's field plus its coupling sum
+    // for the kernels on spin bits: the couplings with the columns of every group of
+    // 32 in the order the widened bits take, scaled by 2^(3 - j) for the bit's
+    // position j in its byte lane, [na_p][nb_p] and [nb_p][na_p], and each site's
+    // field plus its coupling sum
     const int8_t *Jb;
     const int8_t *JTb;
     const int32_t *hA2;  // [na_p]

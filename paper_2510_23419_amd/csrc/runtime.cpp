@@ -353,8 +353,8 @@ static int load_biclique(pbit_ctx *ctx, const pbit_problem_desc *d, Problem &p)
         if (rc == PBIT_OK) rc = upload(ctx, p, JT4.data(), JT4.size(), &dJT4);
     }
     void *dJb = nullptr, *dJTb = nullptr, *dhA2 = nullptr, *dhB2 = nullptr;
-    if (rc == PBIT_OK && pad == kBqPadLarge) {
-        // the half-sweep on spin bits: K byte p = 16 g + 4 j + i of every group of 32
+    if (rc == PBIT_OK) {
+        // the kernels on spin bits (per-instance half-sweep and batched tiles): K byte p = 16 g + 4 j + i of every group of 32
         // columns holds column 8 i + 4 g + j of the group times 2^(3 - j) (the spin
         // byte it meets holds the bit times 2^j), and each field carries the coupling
         // sum of its site

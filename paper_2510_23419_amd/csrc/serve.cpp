@@ -43,7 +43,7 @@ struct BJob {
     std::vector<int8_t> init;
     int kind = 0, N = 0, R = 0, S = 0;
     int rs = 4, tiles = 0, width = 1, chunk = 1;
-    bool fp4 = false;  // biclique tiles on packed 4-bit float operands (else int8)
+    int mode = kTileInt8;  // biclique tile operands: int8 rows (default), spin bits or packed 4-bit floats
     // device memory (released when the job finishes)
     void *d_table = nullptr, *d_state = nullptr, *d_energy = nullptr;
     size_t bytes = 0;
@@ -140,7 +140,23 @@ void serve_shutdown(pbit_ctx *ctx)
 // ---------------------------------------------------------------- job set-up
 
 // Bytes of one biclique replica row in a tile: one byte per site, or two sites per byte.
-static int bq_row_bytes(const BJob &j) { return j.fp4 ? (j.P->bq.na_p + j.P->bq.nb_p) / 2 : j.P->bq.na_p + j.P->bq.nb_p; }
+static int bq_row_bytes(const BJob &j)
+{
+    const int n = j.P->bq.na_p + j.P->bq.nb_p;
+    return j.mode == kTileBits ? n / 8 : j.mode == kTileFp4 ? n / 2 : n;
+}
+
+// Operand mode of a context's biclique tiles: int8 rows unless the fp4 or the bit
+// variant is forced.  Bit rows let 128 replicas share each coupling fragment at any
+// side length, but on the bag's sides (n <= 1024) a tile's Philox draws and
+// decisions cost about as much as its MFMAs, and the int8 rows' smaller tiles
+// spread a job over more CUs: measured, int8 rows are the faster default there.
+static int tile_mode(const pbit_ctx *ctx)
+{
+    if (ctx->bq_forced == BqVariant::Fp4) return kTileFp4;
+    if (ctx->bq_forced == BqVariant::Bits) return kTileBits;
+    return kTileInt8;
+}
 
 static size_t tile_bytes(const BJob &j)
 {
@@ -155,7 +171,7 @@ static int plan_job(pbit_ctx *ctx, BJob &j)
     j.R = j.d.n_replicas;
     j.S = j.d.n_sweeps;
     j.width = j.S > 0 ? table_width(j.beta.data(), j.S, P.amax) : 1;
-    j.fp4 = P.kind == PBIT_BICLIQUE && ctx->bq_forced == BqVariant::Fp4;
+    j.mode = tile_mode(ctx);
     if (j.width > kMaxTableWidth) return fail(PBIT_E_UNSUPPORTED, "threshold rows of %d entries are too wide", j.width);
     if (P.kind == PBIT_GRAPH) return fail(PBIT_E_UNSUPPORTED, "general graphs run through pbit_anneal only");
     if (P.kind == PBIT_EA3D) {
@@ -170,7 +186,7 @@ static int plan_job(pbit_ctx *ctx, BJob &j)
         const int na_p = P.bq.na_p, nb_p = P.bq.nb_p;
         j.rs = 0;
         for (int rs : {128, 64, 32}) {
-            if (bq_tile_lds(rs, na_p, nb_p, j.width, j.fp4) > (size_t)kMaxLdsTile) continue;
+            if (bq_tile_lds(rs, na_p, nb_p, j.width, j.mode) > (size_t)kMaxLdsTile) continue;
             j.rs = rs;  // the smallest that fits, if none passes the tests below
             const double item = 2.0 * na_p * nb_p * rs * std::max(j.S, 1);
             if ((j.R >= rs || rs == 32) && item <= kItemOps) break;
@@ -197,8 +213,9 @@ static void rows_to_tiles(const BJob &j, const int8_t *rows, std::vector<int8_t>
         for (int r = 0; r < j.R; ++r)
             for (int i = 0; i < j.N; ++i) tiles_out[((size_t)(r / 4) * j.N + i) * 4 + (r % 4)] = rows[(size_t)r * j.N + i];
     } else {
-        // int8 spins, or packed 4-bit floats: +1 = 0x2, -1 = 0xA, two sites per byte,
-        // lower site in the low nibble
+        // spin bits (set = -1, bit col % 8 of byte col / 8: the little-endian words the
+        // kernel reads), int8 spins, or packed 4-bit floats (+1 = 0x2, -1 = 0xA, two
+        // sites per byte, lower site in the low nibble)
         const int Pw = bq_row_bytes(j);
         tiles_out.assign((size_t)j.tiles * j.rs * Pw, 0);
         for (int r = 0; r < j.R; ++r)
@@ -206,7 +223,9 @@ static void rows_to_tiles(const BJob &j, const int8_t *rows, std::vector<int8_t>
                 const int col = i < P.bq.na ? i : P.bq.na_p + (i - P.bq.na);
                 const int8_t m = rows[(size_t)r * j.N + i] > 0 ? 1 : -1;
                 const size_t row = (size_t)(r / j.rs) * j.rs + (r % j.rs);
-                if (j.fp4)
+                if (j.mode == kTileBits)
+                    tiles_out[row * Pw + col / 8] |= (uint8_t)((m < 0 ? 1 : 0) << (col % 8));
+                else if (j.mode == kTileFp4)
                     tiles_out[row * Pw + col / 2] |= (uint8_t)((m > 0 ? 0x2 : 0xA) << (4 * (col & 1)));
                 else
                     tiles_out[row * Pw + col] = m;
@@ -226,7 +245,9 @@ static void tiles_to_rows(const BJob &j, const int8_t *tl, int8_t *rows)
             for (int i = 0; i < j.N; ++i) {
                 const int col = i < P.bq.na ? i : P.bq.na_p + (i - P.bq.na);
                 const size_t row = (size_t)(r / j.rs) * j.rs + (r % j.rs);
-                if (j.fp4) {
+                if (j.mode == kTileBits) {
+                    rows[(size_t)r * j.N + i] = ((uint8_t)tl[row * Pw + col / 8] >> (col % 8)) & 1 ? -1 : 1;
+                } else if (j.mode == kTileFp4) {
                     const int nib = ((uint8_t)tl[row * Pw + col / 2] >> (4 * (col & 1))) & 15;
                     rows[(size_t)r * j.N + i] = nib == 0 ? 0 : ((nib & 8) ? -1 : 1);
                 } else {
@@ -309,7 +330,7 @@ static int launch_round(pbit_ctx *ctx, ServeState &s)
         } else {
             const BqView &v = j->P->bq;
             const int k = kind_of_rs(j->rs);
-            BqJobDev jd{v.J, v.JT, v.J4, v.JT4, v.hA, v.hB, (const uint32_t *)j->d_table, (uint8_t *)j->d_state,
+            BqJobDev jd{v.J, v.JT, v.J4, v.JT4, v.Jb, v.JTb, v.hA2, v.hB2, v.hA, v.hB, (const uint32_t *)j->d_table, (uint8_t *)j->d_state,
                         (int32_t *)j->d_energy, v.na, v.nb, v.na_p, v.nb_p, j->width,
                         (uint32_t)j->d.sweep_offset, (uint32_t)j->d.replica_offset >> 2, key.k0, key.k1};
             const int idx = (int)bq[k - 1].size();
@@ -318,7 +339,7 @@ static int launch_round(pbit_ctx *ctx, ServeState &s)
                 items[k].push_back(WorkItem{idx, t, s0, s1, j->started ? 0 : 1, {0, 0, 0}});
                 cost[k].push_back((double)(s1 - s0) * (double)v.na_p * v.nb_p * j->rs);
             }
-            lds[k] = std::max(lds[k], bq_tile_lds(j->rs, v.na_p, v.nb_p, j->width, j->fp4));
+            lds[k] = std::max(lds[k], bq_tile_lds(j->rs, v.na_p, v.nb_p, j->width, j->mode));
         }
     }
     if (s.round_jobs.empty()) return PBIT_OK;
@@ -368,7 +389,7 @@ static int launch_round(pbit_ctx *ctx, ServeState &s)
                          s.d_meta + 0, grid, lds[0], s.st[0]);
         else
             e = bq_tiles((const BqJobDev *)s.d_bq_jobs[k - 1], (const WorkItem *)s.d_items[k], s.d_meta + kKinds + k,
-                         s.d_meta + k, rs_of_kind(k), ctx->bq_forced == BqVariant::Fp4, grid, lds[k], s.st[k]);
+                         s.d_meta + k, rs_of_kind(k), tile_mode(ctx), grid, lds[k], s.st[k]);
         if (e == hipSuccess) e = hipEventRecord(s.join[k], s.st[k]);
         if (e != hipSuccess) return device_fail(ctx, e, "tile kernel launch");
     }
