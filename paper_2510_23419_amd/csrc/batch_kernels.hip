@@ -234,10 +234,6 @@ __device__ __forceinline__ v16f mfma_fp4(v4i a, v4i b, v16f c)
     return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a8, b8, c, 4, 4, 0, 127, 0, 127);
 }
 
-// v_writelane_b32: lane `lane` of `old` takes the wave-uniform `val` (the
-// compiler's intrinsic, bound by name: hip exposes no builtin for it)
-__device__ int tile_lane_write(int val, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
-
 // Biclique tiles with the spins held as bits in LDS: row r holds one bit per site (set = -1), 32 sites per word, side A
 // in words [0, na_p / 32), side B after it, with an odd row pitch so that the 32
 // rows a fragment read touches sit on distinct banks.  A K step of 32 sites is
@@ -353,9 +349,7 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles_bits(const BqJobDev
                                                                                 : bn + 32 * min(u, nku - 1));
 #pragma unroll
                                 for (int rb = 0; rb < RB; ++rb) {
-                                    const uint32_t x = abase[rb * 32 * pitch + ku] >> (4 * kg);
-                                    const v4i a = {(int)(x & 0x01010101u), (int)(x & 0x02020202u),
-                                                   (int)(x & 0x04040404u), (int)(x & 0x08080808u)};
+                                    const v4i a = widen_bits(abase[rb * 32 * pitch + ku], kg);
                                     acc[rb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, acc[rb], 0, 0, 0);
                                 }
                             }
@@ -384,8 +378,8 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles_bits(const BqJobDev
                                 if (side == 1 && last && site_ok) atomicAdd(&eacc[r4 + p], neg ? I : -I);
                                 const uint64_t m = __ballot(neg);
                                 const int L = 8 * q + p;
-                                outw = (uint32_t)tile_lane_write((int)(uint32_t)m, L, (int)outw);
-                                outw = (uint32_t)tile_lane_write((int)(uint32_t)(m >> 32), L + 4, (int)outw);
+                                outw = (uint32_t)lane_write((int)(uint32_t)m, L, (int)outw);
+                                outw = (uint32_t)lane_write((int)(uint32_t)(m >> 32), L + 4, (int)outw);
                             }
                         }
                         if (lane < 32) sw[(rb * 32 + lane) * pitch + out_w + blk] = outw;

@@ -21,10 +21,6 @@
 
 namespace pbit {
 
-// v_writelane_b32: lane `lane` of `old` takes the wave-uniform `val` (the
-// compiler's intrinsic, bound by name: hip exposes no builtin for it)
-__device__ int lane_write(int val, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
-
 namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
@@ -952,19 +948,6 @@ struct BitsGeom {
     static_assert(j_per_wave * WAVES * 1024 == jbytes && b_per_wave * WAVES * 64 * bsz == bbytes,
                   "whole DMA instructions");
 };
-
-// the K bytes that lane half g holds, from one spin word: bit b of a site as
-// b 2^j in dword j
-__device__ __forceinline__ v4i widen_bits(uint32_t w, int g)
-{
-    const uint32_t x = w >> (4 * g);
-    v4i a;
-    a[0] = (int)(x & 0x01010101u);
-    a[1] = (int)(x & 0x02020202u);
-    a[2] = (int)(x & 0x04040404u);
-    a[3] = (int)(x & 0x08080808u);
-    return a;
-}
 
 template <int WAVES>
 __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(WAVES / 4, WAVES / 4))) void

@@ -54,6 +54,28 @@ __device__ __forceinline__ int8_t decide(int32_t I, uint32_t T, uint32_t w)
     return (pos != minority) ? (int8_t)1 : (int8_t)-1;
 }
 
+// v_writelane_b32: lane `lane` of `old` takes the wave-uniform `val` (the
+// compiler's intrinsic, bound by name: hip exposes no builtin for it).
+__device__ int lane_write(int val, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+
+typedef int v4i_t __attribute__((ext_vector_type(4)));
+
+// Spin bits widened for the int8 MFMA: the K bytes that lane half g of a 32x32x32
+// fragment holds (dword j byte i = K position 16 g + 4 j + i) from a word w of
+// 32 spin bits (set = -1): byte i of dword j holds bit 8 i + 4 g + j of w as the
+// value 0 or 2^j.  Couplings stored in that site order and scaled by 2^(3 - j)
+// make every product 8 J b.
+__device__ __forceinline__ v4i_t widen_bits(uint32_t w, int g)
+{
+    const uint32_t x = w >> (4 * g);
+    v4i_t a;
+    a[0] = (int)(x & 0x01010101u);
+    a[1] = (int)(x & 0x02020202u);
+    a[2] = (int)(x & 0x04040404u);
+    a[3] = (int)(x & 0x08080808u);
+    return a;
+}
+
 // Initial spin from a domain-1 word.
 __device__ __forceinline__ int8_t init_spin(uint32_t w)
 {
