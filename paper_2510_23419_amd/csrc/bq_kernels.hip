@@ -925,41 +925,44 @@ __global__ __launch_bounds__(kThreads) void k_bq_field_energy(const int8_t *__re
 // uniform word w), so a lane's decision is one multiply-add and one compare,
 // and a wave's 64 decisions form one ballot mask.
 
-constexpr int kBitsST = 64;   // sites per tile
-constexpr int kBitsRT = 256;  // replicas per tile
-constexpr int kBitsKT = 128;  // K per stage
-constexpr int kBitsNS = 8;    // stages in the ring
-constexpr int kBitsWaves = 8; // waves per workgroup: 4 (64 replicas each) or 8 (32 each, two per SIMD)
+constexpr int kBitsST = 64;     // sites per tile
+constexpr int kBitsRT = 256;    // replicas per tile
+constexpr int kBitsBlock = 128; // sites per block of the spin-word layout (four words)
+constexpr int kBitsWaves = 8;   // waves per workgroup: 4 (64 replicas each) or 8 (32 each, two per SIMD)
 
-template <int WAVES>
+// KT: K per stage, 128 (an 8-stage ring) or 256 (a 4-stage ring, half the
+// barriers per launch, for sides that are multiples of 256)
+template <int WAVES, int KT>
 struct BitsGeom {
     static constexpr int threads = 64 * WAVES;
-    static constexpr int jbytes = kBitsST * kBitsKT;     // coupling rows of one stage (8 KiB)
-    static constexpr int bbytes = kBitsRT * kBitsKT / 8; // spin words of one stage (4 KiB)
+    static constexpr int NS = KT == 256 ? 4 : 8;          // stages in the ring
+    static constexpr int jbytes = kBitsST * KT;            // coupling rows of one stage
+    static constexpr int bbytes = kBitsRT * KT / 8;        // spin words of one stage (KT / 128 blocks)
     static constexpr int stage = jbytes + bbytes;
-    static constexpr int j_per_wave = jbytes / 1024 / WAVES;  // 16-byte-lane DMA instructions per wave
-    static constexpr int bsz = WAVES == 4 ? 16 : 4;           // bytes per lane of the spin-word DMA
+    static constexpr int j_per_wave = jbytes / 1024 / WAVES;          // 16-byte-lane DMA instructions per wave
+    static constexpr int bsz = (bbytes / WAVES) % 1024 == 0 ? 16 : 4; // bytes per lane of the spin-word DMA
     static constexpr int b_per_wave = bbytes / (64 * bsz) / WAVES;
     static constexpr int per_wave = j_per_wave + b_per_wave;
-    static constexpr int ahead = per_wave * (kBitsNS - 2);
-    static constexpr int ring = kBitsNS * stage;
+    static constexpr int ahead = per_wave * (NS - 2);
+    static constexpr int ring = NS * stage;
     static constexpr int bi = kBitsRT / WAVES / 32;  // 32-replica blocks per wave
     static_assert(ahead < 64, "vmcnt is a 6-bit field");
     static_assert(j_per_wave * WAVES * 1024 == jbytes && b_per_wave * WAVES * 64 * bsz == bbytes,
                   "whole DMA instructions");
 };
 
-template <int WAVES>
+template <int WAVES, int KT>
 __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(WAVES / 4, WAVES / 4))) void
 k_bq_halfsweep_bits(const uint32_t *__restrict__ Mob, const int8_t *__restrict__ Jb, const int32_t *__restrict__ hs2,
                     uint32_t *__restrict__ Msb, const uint32_t *__restrict__ trow, int width, int Ko, int Rp,
                     int tiles_s, int xcd_bands, uint32_t site_base, uint32_t sweep, uint32_t rq0, uint32_t k0,
                     uint32_t k1, uint32_t one)
 {
-    using G = BitsGeom<WAVES>;
-    constexpr int NS = kBitsNS;
-    constexpr int CH = kBitsKT / 16;  // 16-byte chunks per coupling row
-    constexpr int kSubs = kBitsKT / 32;
+    using G = BitsGeom<WAVES, KT>;
+    constexpr int NS = G::NS;
+    constexpr int CH = KT / 16;       // 16-byte chunks per coupling row
+    constexpr int kSubs = KT / 32;    // K steps per stage
+    constexpr int KB = KT / kBitsBlock;  // spin-word blocks per stage
     constexpr int BI = G::bi;         // replica blocks of 32 per wave
     constexpr int RW = 32 * BI;       // replicas per wave
 
@@ -996,21 +999,28 @@ k_bq_halfsweep_bits(const uint32_t *__restrict__ Mob, const int8_t *__restrict__
     // each) and spin-word slots 64 (b_per_wave w + j) + lane (bsz bytes each) of each
     // stage, from a wave-uniform base plus a 32-bit lane offset.  Row r of a stage keeps
     // chunk c at position c ^ swzb(r), with a swizzle of r mod 32 only, so that the two
-    // site blocks of a fragment read sit at a fixed distance.
-    auto swzb = [](int r) { return (r ^ ((r >> 3) & 3)) & 7; };
+    // site blocks of a fragment read sit at a fixed distance.  Rows of 128 bytes span
+    // half the banks: the swizzle spreads 8 even and 8 odd rows; rows of 256 bytes
+    // span all of them: it spreads 16 rows.
+    auto swzb = [](int r) { return CH == 8 ? ((r ^ ((r >> 3) & 3)) & 7) : (r & 15); };
     uint32_t offJl[4], offBl[4];
-    static_assert(G::j_per_wave <= 4 && G::b_per_wave <= 4 && kSubs <= 4, "fixed array bounds");
+    static_assert(G::j_per_wave <= 4 && G::b_per_wave <= 4 && kSubs <= 8, "fixed array bounds");
 #pragma unroll
     for (int j = 0; j < G::j_per_wave; ++j) {
         const int S = 64 * (G::j_per_wave * wave + j) + lane;
         const int r = S / CH, c = (S % CH) ^ swzb(S / CH);
         offJl[j] = (uint32_t)(r * Ko + 16 * c);
     }
+    // spin words: byte o of a stage's spin area is byte o % 4096 of block o / 4096 of the
+    // stage (its replicas' 16 bytes each, contiguous in the block layout)
 #pragma unroll
-    for (int j = 0; j < G::b_per_wave; ++j) offBl[j] = (uint32_t)(G::bsz * (64 * (G::b_per_wave * wave + j) + lane));
+    for (int j = 0; j < G::b_per_wave; ++j) {
+        const uint32_t o = (uint32_t)(G::bsz * (64 * (G::b_per_wave * wave + j) + lane));
+        offBl[j] = (o / 4096u) * 16u * (uint32_t)Rp + o % 4096u;
+    }
     const int8_t *Jt0 = Jb + (size_t)s0 * Ko;
     const char *Bt0 = reinterpret_cast<const char *>(Mob + (size_t)r0 * 4);
-    const int nk = Ko / kBitsKT;
+    const int nk = Ko / KT;
     const int ln = lane & 31, kg = lane >> 5;
     // the fields of this lane's two sites (field plus coupling sum; zero at padding sites),
     // loaded before the DMA so that the stage waits also cover them
@@ -1018,13 +1028,19 @@ k_bq_halfsweep_bits(const uint32_t *__restrict__ Mob, const int8_t *__restrict__
     auto issue = [&](int t) {
         int8_t *dJ = ring + (t % NS) * G::stage + 1024 * G::j_per_wave * wave;
         int8_t *dB = ring + (t % NS) * G::stage + G::jbytes + 64 * G::bsz * G::b_per_wave * wave;
-        const int8_t *Jt = Jt0 + (size_t)t * kBitsKT;
-        const char *Bt = Bt0 + (size_t)t * 16 * Rp;
+        const int8_t *Jt = Jt0 + (size_t)t * KT;
+        const char *Bt = Bt0 + (size_t)t * KB * 16 * Rp;
 #pragma unroll
         for (int j = 0; j < G::j_per_wave; ++j) __builtin_amdgcn_global_load_lds(Jt + offJl[j], dJ + 1024 * j, 16, 0, 0);
+        // size and LDS step as literals: with a template-dependent LDS offset, the
+        // compiler's host pass rejects the 16-byte form and silently drops the kernel
 #pragma unroll
-        for (int j = 0; j < G::b_per_wave; ++j)
-            __builtin_amdgcn_global_load_lds(Bt + offBl[j], dB + 64 * G::bsz * j, G::bsz, 0, 0);
+        for (int j = 0; j < G::b_per_wave; ++j) {
+            if constexpr (G::bsz == 16)
+                __builtin_amdgcn_global_load_lds(Bt + offBl[j], dB + 1024 * j, 16, 0, 0);
+            else
+                __builtin_amdgcn_global_load_lds(Bt + offBl[j], dB + 256 * j, 4, 0, 0);
+        }
     };
     // the threshold row and field loads above are older than every DMA below, so each
     // wait for a stage also covers them
@@ -1032,9 +1048,9 @@ k_bq_halfsweep_bits(const uint32_t *__restrict__ Mob, const int8_t *__restrict__
 
     // coupling fragment offsets: rows 32 bj + ln, chunk 2 sub + kg; swzb(r) depends on
     // r mod 32 = ln only, so site block bj = 1 sits 32 rows further
-    int offJ[4];
+    int offJ[8];
 #pragma unroll
-    for (int sub = 0; sub < kSubs; ++sub) offJ[sub] = kBitsKT * ln + 16 * ((2 * sub + kg) ^ swzb(ln));
+    for (int sub = 0; sub < kSubs; ++sub) offJ[sub] = KT * ln + 16 * ((2 * sub + kg) ^ swzb(ln));
     const int offB = G::jbytes + 16 * (RW * wave + ln);  // spin words of replica rows RW wave + 32 bi + ln
     v16i acc[BI][2];  // [replica block][site block]
 #pragma unroll
@@ -1045,8 +1061,8 @@ k_bq_halfsweep_bits(const uint32_t *__restrict__ Mob, const int8_t *__restrict__
     // while the MFMAs run on the current one's (a barrier before the reads would
     // otherwise leave the matrix cores idle for the LDS latency at every stage)
     struct Frag {
-        v4i w[BI];    // spin words of replica rows 32 bi + ln, one per K step
-        v4i b[4][2];  // coupling fragments [K step][site block]
+        v4i w[BI][KB];     // spin words of replica rows 32 bi + ln, one per K step of a block
+        v4i b[kSubs][2];   // coupling fragments [K step][site block]
     };
     auto load = [&](int t, Frag &f) {
         const int8_t *st = ring + (t % NS) * G::stage;
@@ -1054,19 +1070,22 @@ k_bq_halfsweep_bits(const uint32_t *__restrict__ Mob, const int8_t *__restrict__
         // compiler adds no wait for all DMA in flight (the stage was waited for, and
         // published by a barrier, before this call)
 #pragma unroll
-        for (int bi = 0; bi < BI; ++bi) f.w[bi] = *reinterpret_cast<const v4i *>(st + offB + 16 * 32 * bi);
+        for (int bi = 0; bi < BI; ++bi)
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb)
+                f.w[bi][kb] = *reinterpret_cast<const v4i *>(st + offB + 4096 * kb + 16 * 32 * bi);
 #pragma unroll
         for (int sub = 0; sub < kSubs; ++sub)
 #pragma unroll
             for (int bj = 0; bj < 2; ++bj)
-                f.b[sub][bj] = *reinterpret_cast<const v4i *>(st + offJ[sub] + 32 * kBitsKT * bj);
+                f.b[sub][bj] = *reinterpret_cast<const v4i *>(st + offJ[sub] + 32 * KT * bj);
     };
     auto mfmas = [&](const Frag &f) {
 #pragma unroll
         for (int sub = 0; sub < kSubs; ++sub)
 #pragma unroll
             for (int bi = 0; bi < BI; ++bi) {
-                const v4i a = widen_bits((uint32_t)f.w[bi][sub], kg);
+                const v4i a = widen_bits((uint32_t)f.w[bi][sub / 4][sub % 4], kg);
 #pragma unroll
                 for (int bj = 0; bj < 2; ++bj)
                     acc[bi][bj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, f.b[sub][bj], acc[bi][bj], 0, 0, 0);
@@ -1076,10 +1095,13 @@ k_bq_halfsweep_bits(const uint32_t *__restrict__ Mob, const int8_t *__restrict__
     // complete, so that the compiler adds no wait for later reads before the MFMAs that
     // use them (it emits no instruction)
     auto settle = [&](Frag &f) {
-        asm volatile("" : "+v"(f.b[0][0]), "+v"(f.b[0][1]), "+v"(f.b[1][0]), "+v"(f.b[1][1]), "+v"(f.b[2][0]),
-                     "+v"(f.b[2][1]), "+v"(f.b[3][0]), "+v"(f.b[3][1]));
 #pragma unroll
-        for (int bi = 0; bi < BI; ++bi) asm volatile("" : "+v"(f.w[bi]));
+        for (int sub = 0; sub < kSubs; sub += 2)
+            asm volatile("" : "+v"(f.b[sub][0]), "+v"(f.b[sub][1]), "+v"(f.b[sub + 1][0]), "+v"(f.b[sub + 1][1]));
+#pragma unroll
+        for (int bi = 0; bi < BI; ++bi)
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) asm volatile("" : "+v"(f.w[bi][kb]));
     };
     // stage t: refill the ring, publish stage t + 1 and read its fragments, then the
     // MFMAs of stage t.  Every wave's reads of stage t are complete (lgkmcnt 0) before
@@ -1179,7 +1201,7 @@ k_bq_halfsweep_bits(const uint32_t *__restrict__ Mob, const int8_t *__restrict__
     }
     // words s0 / 32 and + 1 of replica row RW wave + lane: an aligned pair in a block of four
     if (lane < RW)
-        *reinterpret_cast<uint2 *>(Msb + ((size_t)(s0 / kBitsKT) * Rp + r0 + RW * wave + lane) * 4 + (s0 / 32) % 4) =
+        *reinterpret_cast<uint2 *>(Msb + ((size_t)(s0 / kBitsBlock) * Rp + r0 + RW * wave + lane) * 4 + (s0 / 32) % 4) =
             make_uint2(out[0], out[1]);
 }
 
@@ -1395,7 +1417,7 @@ hipError_t bq4_halfsweep(const BqView &p, int side, uint8_t *MA4, uint8_t *MB4, 
 hipError_t bqb_pack(const BqView &p, const int8_t *MA, const int8_t *MB, uint32_t *MAb, uint32_t *MBb, int Rp,
                     hipStream_t st)
 {
-    if (p.na_p % kBitsKT || p.nb_p % kBitsKT) return hipErrorInvalidValue;
+    if (p.na_p % kBitsBlock || p.nb_p % kBitsBlock) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_bq_bits<true>, dim3(blocks_for((int64_t)Rp * p.na_p / 32)), dim3(kThreads), 0, st,
                        const_cast<int8_t *>(MA), MAb, Rp, p.na_p);
     hipError_t e = hipGetLastError();
@@ -1408,7 +1430,7 @@ hipError_t bqb_pack(const BqView &p, const int8_t *MA, const int8_t *MB, uint32_
 hipError_t bqb_unpack(const BqView &p, const uint32_t *MAb, const uint32_t *MBb, int8_t *MA, int8_t *MB, int Rp,
                       hipStream_t st)
 {
-    if (p.na_p % kBitsKT || p.nb_p % kBitsKT) return hipErrorInvalidValue;
+    if (p.na_p % kBitsBlock || p.nb_p % kBitsBlock) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_bq_bits<false>, dim3(blocks_for((int64_t)Rp * p.na_p / 32)), dim3(kThreads), 0, st, MA,
                        const_cast<uint32_t *>(MAb), Rp, p.na_p);
     hipError_t e = hipGetLastError();
@@ -1420,20 +1442,26 @@ hipError_t bqb_unpack(const BqView &p, const uint32_t *MAb, const uint32_t *MBb,
 
 bool bqb_supported(const BqView &p, int Rp)
 {
-    return p.Jb && p.na_p % kBitsST == 0 && p.nb_p % kBitsST == 0 && p.na_p % kBitsKT == 0 &&
-           p.nb_p % kBitsKT == 0 && Rp % kBitsRT == 0;
+    return p.Jb && p.na_p % kBitsST == 0 && p.nb_p % kBitsST == 0 && p.na_p % kBitsBlock == 0 &&
+           p.nb_p % kBitsBlock == 0 && Rp % kBitsRT == 0;
 }
 
 hipError_t bqb_halfsweep(const BqView &p, int side, uint32_t *MAb, uint32_t *MBb, int Rp, const uint32_t *trow,
                          int width, uint32_t sweep, uint32_t rq0, Key key, hipStream_t st)
 {
     constexpr int WAVES = kBitsWaves;
-    using G = BitsGeom<WAVES>;
+    using G1 = BitsGeom<WAVES, 128>;
+    using G2 = BitsGeom<WAVES, 256>;
     if (!bqb_supported(p, Rp) || width < 1 || width > kMaxTableWidth) return hipErrorInvalidValue;
-    static const hipError_t lds_attr =
-        hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bq_halfsweep_bits<WAVES>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                            G::ring + (int)sizeof(uint64_t) * (2 * kMaxTableWidth - 1));
+    static const hipError_t lds_attr = [] {
+        const int tab = (int)sizeof(uint64_t) * (2 * kMaxTableWidth - 1);
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bq_halfsweep_bits<WAVES, 128>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, G1::ring + tab);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bq_halfsweep_bits<WAVES, 256>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, G2::ring + tab);
+        return e;
+    }();
     if (lds_attr != hipSuccess) return lds_attr;
     const bool A = side == 0;
     const int Ns_p = A ? p.na_p : p.nb_p, Ko = A ? p.nb_p : p.na_p;
@@ -1444,9 +1472,14 @@ hipError_t bqb_halfsweep(const BqView &p, int side, uint32_t *MAb, uint32_t *MBb
     const uint32_t site_base = A ? 0u : (uint32_t)p.na;
     const int tiles_s = Ns_p / kBitsST, tiles_r = Rp / kBitsRT;
     const int bands = tiles_s % 8 == 0 ? 1 : 0;
-    hipLaunchKernelGGL(k_bq_halfsweep_bits<WAVES>, dim3((unsigned)(tiles_s * tiles_r)), dim3(G::threads),
-                       (G::ring + sizeof(uint64_t) * (size_t)(2 * width - 1)), st, Mob, Jb, hs2, Msb, trow, width, Ko,
-                       Rp, tiles_s, bands, site_base, sweep, rq0, key.k0, key.k1, 1u);
+    const size_t tab = sizeof(uint64_t) * (size_t)(2 * width - 1);
+    const dim3 grid((unsigned)(tiles_s * tiles_r));
+    if (Ko % 256 == 0)
+        hipLaunchKernelGGL((k_bq_halfsweep_bits<WAVES, 256>), grid, dim3(G2::threads), G2::ring + tab, st, Mob, Jb, hs2,
+                           Msb, trow, width, Ko, Rp, tiles_s, bands, site_base, sweep, rq0, key.k0, key.k1, 1u);
+    else
+        hipLaunchKernelGGL((k_bq_halfsweep_bits<WAVES, 128>), grid, dim3(G1::threads), G1::ring + tab, st, Mob, Jb, hs2,
+                           Msb, trow, width, Ko, Rp, tiles_s, bands, site_base, sweep, rq0, key.k0, key.k1, 1u);
     return hipGetLastError();
 }
 
