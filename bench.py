@@ -265,7 +265,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only; run it with --gpus 1 (the path would shard replicas "
+        print("bench.py: measures one GPU only; run it with --gpus 1 (the path would shard replicas "
               "across GPUs with no exchange, see the design notes)", file=sys.stderr)
         sys.exit(2)
 

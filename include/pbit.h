@@ -79,7 +79,7 @@ enum {
     PBIT_E_BUSY = -5,        /* the serving queue is full */
     PBIT_E_HANDLE = -6,      /* unknown, stale or foreign problem / job handle */
     PBIT_E_DEVICE = -7,      /* HIP error; the context is poisoned */
-    PBIT_E_UNSUPPORTED = -8  /* valid request this build does not handle */
+    PBIT_E_UNSUPPORTED = -8  /* valid request the library does not handle (e.g. a general graph in a batch) */
 };
 
 enum { PBIT_EA3D = 1, PBIT_BICLIQUE = 2, PBIT_GRAPH = 3 };
