@@ -42,10 +42,17 @@ WORKLOADS = {
     "bq1024": dict(kind="biclique", n=1024, R=1024, S=2000, b0=0.05, b1=2.0, sched="linear", inst_seed=1024),
     "bq2048": dict(kind="biclique", n=2048, R=1024, S=2000, b0=0.05, b1=2.0, sched="linear", inst_seed=2048),
     "bq4096": dict(kind="biclique", n=4096, R=1024, S=2000, b0=0.05, b1=2.0, sched="linear", inst_seed=4096),
+    # general graph with k update groups: the dimerized, rewired cube that stands in for
+    # the paper's hardware-embedded literature lattices (5,488 spins, 5 greedy groups)
+    "dimer14": dict(kind="graph", L=14, R=4096, S=2000, b0=0.1, b1=5.0, sched="geometric", inst_seed=14),
 }
 
 
 def describe(w):
+    if w["kind"] == "graph":
+        return ("dimerized periodic cube L=%d (%d spins in ferromagnetic pairs, cube bonds J iid +-1 between random "
+                "pair members, 10%% rewired), h=0, greedy update groups, %d replicas, beta %s %.2g->%.2g over %d "
+                "sweeps, seed 1" % (w["L"], 2 * w["L"] ** 3, w["R"], w["sched"], w["b0"], w["b1"], w["S"]))
     if w["kind"] == "ea3d":
         return ("3D Edwards-Anderson periodic cube L=%d (%d spins), J iid +-1, h=0, checkerboard, %d replicas, "
                 "beta %s %.2g->%.2g over %d sweeps, seed 1" % (w["L"], w["L"] ** 3, w["R"], w["sched"], w["b0"],
@@ -58,6 +65,8 @@ def make_instance(w):
     import synth
     if w["kind"] == "ea3d":
         inst = synth.ea_instance(w["L"], seed=w["inst_seed"])
+    elif w["kind"] == "graph":
+        inst = synth.dimerized_cube(w["L"], seed=w["inst_seed"])
     else:
         inst = synth.biclique_instance(w["n"], seed=w["inst_seed"])
     if w["sched"] == "geometric":
@@ -67,12 +76,31 @@ def make_instance(w):
     return inst, beta
 
 
+def host_threads():
+    """Host threads for the oracle's all-core leg: the cores this process may run
+    on, at most 16 (one GPU's share of a shared host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
 def cpu_baseline(w, inst, beta, budget_s):
-    """The oracle as it stands, single-threaded, on a bounded sample: the first
-    sweeps of the same schedule for a few replicas, sized to ~budget_s."""
+    """The oracle as it stands on a bounded sample: the first sweeps of the same
+    schedule for 8 replicas, sized to ~budget_s on one core; then the same sample
+    on every host thread at once, thread t taking replicas 8t .. 8t + 7 (replicas
+    are independent and drawn from their global index, so the slices are the
+    corresponding part of one run).  The oracle is a C library called through
+    ctypes, which releases the interpreter lock for the call."""
+    from concurrent.futures import ThreadPoolExecutor
     from oracle import oracle
-    g = oracle.ea_graph(inst["dims"], inst["J"], inst["h"]) if w["kind"] == "ea3d" else \
-        oracle.biclique_graph(*inst["dims"], inst["J"], inst["h"])
+    if w["kind"] == "ea3d":
+        g = oracle.ea_graph(inst["dims"], inst["J"], inst["h"])
+    elif w["kind"] == "graph":
+        g = oracle.graph_from_bonds(inst["n"], inst["bond_i"], inst["bond_j"], inst["bond_J"], inst["h"])
+    else:
+        g = oracle.biclique_graph(*inst["dims"], inst["J"], inst["h"])
     N = g.n
     # calibrate on a tiny run, then size the sample
     t0 = time.perf_counter()
@@ -82,10 +110,43 @@ def cpu_baseline(w, inst, beta, budget_s):
     S = int(max(2, min(len(beta), budget_s * rate / (R * N))))
     t0 = time.perf_counter()
     oracle.anneal(g, beta[:S], R, seed=1)
-    dt = time.perf_counter() - t0
-    return {"value": R * N * S / dt, "unit": "p-bit updates/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d of %d sweeps, replicas 0-%d of %d, single-threaded C oracle (%s); %.1f s"
-                      % (S, len(beta), R - 1, w["R"], platform.processor() or platform.machine(), dt)}
+    dt1 = time.perf_counter() - t0
+    T = host_threads()
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=T) as pool:
+        list(pool.map(lambda t: oracle.anneal(g, beta[:S], R, seed=1, replica_offset=R * t), range(T)))
+    dtT = time.perf_counter() - t0
+    cpu = platform.processor() or platform.machine()
+    return {"value": T * R * N * S / dtT, "unit": "p-bit updates/s", "cores": T, "kind": "oracle",
+            "one_core_value": R * N * S / dt1,
+            "sample": "first %d of %d sweeps of the same schedule, replicas 0-%d of %d on one core (%.1f s), then "
+                      "replicas 0-%d on %d threads at once (%.1f s), C oracle (%s)"
+                      % (S, len(beta), R - 1, w["R"], dt1, T * R - 1, T, dtT, cpu)}
+
+
+def graph_launch_bytes(ctx, prob, inst, R):
+    """Algorithmic bytes per group launch of a general graph, averaged over the
+    groups of one sweep: a group writes its own spin rows (1 byte per update),
+    reads the rows of its sites' neighbours once each (1 byte per replica per
+    distinct neighbour: rows shared by several sites of the group are fetched
+    once when they stay in cache), and reads its adjacency (4-byte neighbour id
+    and 1-byte code per bond end, CSR start, field base and class entry)."""
+    import numpy as np
+    from paper_2510_23419_amd import pbit
+    colour, k = pbit.pbit_problem_colouring(ctx, prob)
+    n = inst["n"]
+    bi = np.asarray(inst["bond_i"], np.int64)
+    bj = np.asarray(inst["bond_j"], np.int64)
+    deg = np.bincount(np.concatenate([bi, bj]), minlength=n)
+    total = 0
+    for c in range(k):
+        in_c = colour == c
+        nbr = np.zeros(n, bool)
+        nbr[bj[in_c[bi]]] = True
+        nbr[bi[in_c[bj]]] = True
+        sites = int(in_c.sum())
+        total += sites * R + int(nbr.sum()) * R + 5 * int(deg[in_c].sum()) + 14 * sites
+    return total / k, k
 
 
 def profile_record(workload):
@@ -306,7 +367,7 @@ def main():
         pbit.pbit_anneal_dev(ctx.ctx, prob, beta, R, 1, d_spins, d_energies=d_energy, stream=stream)
     torch.cuda.synchronize()
 
-    kind = pbit.PBIT_EA3D if w["kind"] == "ea3d" else pbit.PBIT_BICLIQUE
+    kind = {"ea3d": pbit.PBIT_EA3D, "graph": pbit.PBIT_GRAPH}.get(w["kind"], pbit.PBIT_BICLIQUE)
     pbit.pbit_profile_enable(ctx.ctx, args.profile_every)
     pbit.pbit_profile_read(ctx.ctx, kind, reset=True)
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -337,6 +398,11 @@ def main():
         alg_bytes = N * R + 4 * (N // 2)
         roof = {"bound": "hbm", "achieved": alg_bytes / (avg_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "traffic": None, "kernel": "k_ea_halfsweep",
+                "alg_bytes_per_launch": alg_bytes, "avg_launch_us": avg_ms * 1e3, "launches_timed": launches}
+    elif w["kind"] == "graph":
+        alg_bytes, groups = graph_launch_bytes(ctx.ctx, prob, inst, R)
+        roof = {"bound": "hbm", "achieved": alg_bytes / (avg_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "traffic": None, "kernel": "k_graph_halfsweep", "groups": groups,
                 "alg_bytes_per_launch": alg_bytes, "avg_launch_us": avg_ms * 1e3, "launches_timed": launches}
     else:
         n = w["n"]

@@ -249,7 +249,7 @@ int pbit_serve_config(pbit_ctx *ctx, int32_t max_queue, int32_t max_running, int
 int pbit_profile_enable(pbit_ctx *ctx, int32_t every);
 
 /* Device time and number of the bracketed half-sweep launches of problem kind
- * `kind` (PBIT_EA3D or PBIT_BICLIQUE) since the last reset; `reset` nonzero
+ * `kind` (PBIT_EA3D, PBIT_BICLIQUE or PBIT_GRAPH) since the last reset; `reset` nonzero
  * clears the counters after reading. */
 int pbit_profile_read(pbit_ctx *ctx, int32_t kind, double *total_ms, int64_t *launches, int32_t reset);
 

@@ -3,9 +3,18 @@
 //
 // Spins use the cube's layout, int8 [N][Rp] with replicas fastest, and one
 // launch updates one colour class: a thread takes one site of the class and 16
-// replicas, gathers its neighbours' 16-byte replica rows through the CSR
-// adjacency, and counts negative products bytewise (degree <= 127 keeps the
-// byte sums below 256).  Classes are visited in ascending colour order.
+// replicas, gathers its neighbours' 16-byte replica rows through the class-major
+// adjacency, and counts negative products bytewise (degree <= 127 keeps the byte
+// sums below 256).  Classes are visited in ascending colour order.
+//
+// The sweep of a sparse graph is bound by the latency of its gathers, so the
+// adjacency is laid out for few dependent loads: the site's record (id,
+// adjacency range, field base) is one 16-byte load, every adjacency entry one
+// word (neighbour and coupling code), and the rows of four neighbours are in
+// flight at once.  With at least 8 chunks of 16 replicas, blockIdx.x mod 8 (the
+// XCD a workgroup is dispatched to) picks one replica slab, so that an XCD's L2
+// holds its slab of every row and the neighbours a class shares are fetched
+// there once.
 #include "device.h"
 #include "internal.h"
 
@@ -18,14 +27,19 @@ constexpr int kMaxOff = kGraphMaxDegree + 1;          // |I| <= degree + |h|
 constexpr int kSlots = 2 * kMaxOff + 1;
 
 __global__ __launch_bounds__(kThreads) void k_graph_halfsweep(int8_t *__restrict__ spins,
-                                                              const int32_t *__restrict__ class_sites, int n_class,
-                                                              const int32_t *__restrict__ adj_start,
-                                                              const int32_t *__restrict__ adj_site,
-                                                              const uint8_t *__restrict__ adj_code,
-                                                              const int16_t *__restrict__ base,
+                                                              const int4 *__restrict__ meta, int n_class,
+                                                              const uint32_t *__restrict__ adj,
                                                               const uint32_t *__restrict__ trow, int width, int Rp,
-                                                              uint32_t sweep, uint32_t rq0, uint32_t k0, uint32_t k1)
+                                                              int lg_nsl, uint32_t sweep, uint32_t rq0, uint32_t k0,
+                                                              uint32_t k1)
 {
+    const int cs = (Rp / 16) >> lg_nsl;  // chunks of 16 replicas per slab
+    const int slab = (int)blockIdx.x & ((1 << lg_nsl) - 1);
+    const int64_t gid = (int64_t)(blockIdx.x >> lg_nsl) * kThreads + threadIdx.x;  // (site, chunk) inside the slab
+    const bool live = gid < (int64_t)n_class * cs;
+    // the site record first, so that its latency overlaps the table build
+    int4 m = make_int4(0, 0, 0, 0);  // site, first entry, end entry, base = nnz + h
+    if (live) m = meta[gid / cs];
     // decision table over I in [-kMaxOff, kMaxOff]: threshold, xor mask, minority and majority byte
     __shared__ uint4 tab[kSlots];
     for (int k = threadIdx.x; k < kSlots; k += kThreads) {
@@ -35,22 +49,30 @@ __global__ __launch_bounds__(kThreads) void k_graph_halfsweep(int8_t *__restrict
         tab[k] = make_uint4(trow[a], pos ? 0xFFFFFFFFu : 0u, pos ? 0xFFu : 0x01u, pos ? 0x01u : 0xFFu);
     }
     __syncthreads();
-    const int chunks = Rp / 16;
-    const int64_t gid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (gid >= (int64_t)n_class * chunks) return;
-    const int q = (int)(gid % chunks);
-    const int i = class_sites[gid / chunks];
+    if (!live) return;
+    const int q = slab * cs + (int)(gid % cs);
+    const int i = m.x;
     uint32_t cnt[4] = {0u, 0u, 0u, 0u};
-    for (int e = adj_start[i]; e < adj_start[i + 1]; ++e) {
-        const uint8_t c = adj_code[e];  // bit 0: J != 0, bit 1: J == -1
-        const uint32_t keep = (c & 1u) * 0x02020202u, flip = ((c >> 1) & 1u) * 0x02020202u;
-        const uint4 v = *reinterpret_cast<const uint4 *>(spins + (size_t)adj_site[e] * Rp + 16 * q);
-        cnt[0] += (v.x & keep) ^ flip;
-        cnt[1] += (v.y & keep) ^ flip;
-        cnt[2] += (v.z & keep) ^ flip;
-        cnt[3] += (v.w & keep) ^ flip;
+    for (int e = m.y; e < m.z; e += 4) {
+        // four entries, then their four rows; entries past the end read as code 0 (no term)
+        uint32_t w[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) w[k] = e + k < m.z ? adj[e + k] : 0u;
+        uint4 v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            v[k] = e + k < m.z ? *reinterpret_cast<const uint4 *>(spins + (size_t)(w[k] >> 2) * Rp + 16 * q)
+                               : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t keep = (w[k] & 1u) * 0x02020202u, flip = ((w[k] >> 1) & 1u) * 0x02020202u;
+            cnt[0] += (v[k].x & keep) ^ flip;
+            cnt[1] += (v[k].y & keep) ^ flip;
+            cnt[2] += (v[k].z & keep) ^ flip;
+            cnt[3] += (v[k].w & keep) ^ flip;
+        }
     }
-    const int b0 = (int)base[i] + kMaxOff;  // table index for I = nnz + h (no negative products)
+    const int b0 = m.w + kMaxOff;  // table index for I = nnz + h (no negative products)
     uint32_t out[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -58,8 +80,8 @@ __global__ __launch_bounds__(kThreads) void k_graph_halfsweep(int8_t *__restrict
         uint32_t packed = 0;
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
-            const uint4 e = tab[b0 - (int)((cnt[k] >> (8 * p)) & 0xFFu)];  // I = base - c2
-            packed |= ((b.w[p] ^ e.y) < e.x ? e.z : e.w) << (8 * p);
+            const uint4 t = tab[b0 - (int)((cnt[k] >> (8 * p)) & 0xFFu)];  // I = base - c2
+            packed |= ((b.w[p] ^ t.y) < t.x ? t.z : t.w) << (8 * p);
         }
         out[k] = packed;
     }
@@ -93,10 +115,14 @@ hipError_t graph_halfsweep(const GraphView &g, int colour, int8_t *spins, int Rp
     if (width < 1 || width > kMaxOff + 1 || Rp % 16 != 0) return hipErrorInvalidValue;
     const int n_class = g.class_start[colour + 1] - g.class_start[colour];
     if (n_class == 0) return hipSuccess;
-    const int64_t work = (int64_t)n_class * (Rp / 16);
-    hipLaunchKernelGGL(k_graph_halfsweep, dim3((unsigned)((work + kThreads - 1) / kThreads)), dim3(kThreads), 0, st,
-                       spins, g.class_sites + g.class_start[colour], n_class, g.adj_start, g.adj_site, g.adj_code,
-                       g.base, trow, width, Rp, sweep, rq0, key.k0, key.k1);
+    const int chunks = Rp / 16;
+    const int lg_nsl = chunks % 8 == 0 ? 3 : 0;  // 8 replica slabs, one per XCD
+    const int64_t work = (int64_t)n_class * (chunks >> lg_nsl);
+    const int64_t blocks = ((work + kThreads - 1) / kThreads) << lg_nsl;
+    if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_graph_halfsweep, dim3((unsigned)blocks), dim3(kThreads), 0, st, spins,
+                       reinterpret_cast<const int4 *>(g.site_meta) + g.class_start[colour], n_class, g.adj, trow,
+                       width, Rp, lg_nsl, sweep, rq0, key.k0, key.k1);
     return hipGetLastError();
 }
 

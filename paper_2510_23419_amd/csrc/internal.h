@@ -30,12 +30,11 @@ constexpr int kGraphMaxDegree = 127;  // bytewise counts of negative products st
 
 struct GraphView {
     int n, n_bonds, n_colours, max_degree;
-    const int32_t *class_start;  // host [n_colours + 1]: class c is class_sites[class_start[c] .. class_start[c+1])
-    const int32_t *class_sites;  // device [n]: sites grouped by colour, ascending inside a class
-    const int32_t *adj_start;    // device [n + 1] CSR offsets
-    const int32_t *adj_site;     // device [2 n_bonds] neighbours
-    const uint8_t *adj_code;     // device [2 n_bonds]: bit 0 J != 0, bit 1 J == -1
-    const int16_t *base;         // device [n]: nnz(J) + h, in [-1, kGraphMaxDegree + 1]
+    // sites are numbered by position: grouped by colour, ascending inside a class
+    const int32_t *class_start;  // host [n_colours + 1]: class c holds positions class_start[c] .. class_start[c+1]
+    const int32_t *site_meta;    // device [n][4] by position: site id, first and end adjacency entry,
+                                 // nnz(J) + h (in [-1, kGraphMaxDegree + 1])
+    const uint32_t *adj;         // device [2 n_bonds] in position order: neighbour << 2 | bit 0 J != 0, bit 1 J == -1
     const int32_t *bi, *bj;      // device bond list
     const int8_t *bJ;
     const int8_t *h;             // device [n] or null

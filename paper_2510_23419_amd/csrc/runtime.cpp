@@ -463,22 +463,22 @@ static int load_graph(pbit_ctx *ctx, const pbit_graph_desc *d, Problem &p)
         int rc = greedy_colouring(n, nb, d->bond_i, d->bond_j, p.colour.data(), &ncol);
         if (rc) return rc;
     }
-    // CSR adjacency, per-site base = nnz + h, colour classes
+    // colour classes, then per position (class-major, ascending site inside a class) the
+    // site's id, its adjacency range and base = nnz + h, and the adjacency in that order,
+    // each entry one word: a kernel thread reaches its site's whole neighbourhood through
+    // two dependent loads
     std::vector<int32_t> start((size_t)n + 1, 0);
     for (int i = 0; i < n; ++i) start[(size_t)i + 1] = start[i] + deg[i];
-    std::vector<int32_t> site((size_t)2 * nb);
-    std::vector<uint8_t> code((size_t)2 * nb);
+    std::vector<uint32_t> word((size_t)2 * nb);
     std::vector<int32_t> fill(start.begin(), start.end() - 1);
-    std::vector<int16_t> base((size_t)n, 0);
+    std::vector<int32_t> base((size_t)n, 0);
     int amax = 0;
     for (int b = 0; b < nb; ++b) {
         const int8_t J = d->bond_J[b];
-        const uint8_t c = (uint8_t)((J != 0 ? 1 : 0) | (J < 0 ? 2 : 0));
+        const uint32_t c = (J != 0 ? 1u : 0u) | (J < 0 ? 2u : 0u);
         const int i = d->bond_i[b], j = d->bond_j[b];
-        site[(size_t)fill[i]] = j;
-        code[(size_t)fill[i]++] = c;
-        site[(size_t)fill[j]] = i;
-        code[(size_t)fill[j]++] = c;
+        word[(size_t)fill[i]++] = (uint32_t)j << 2 | c;
+        word[(size_t)fill[j]++] = (uint32_t)i << 2 | c;
         if (J != 0) {
             ++base[i];
             ++base[j];
@@ -487,21 +487,28 @@ static int load_graph(pbit_ctx *ctx, const pbit_graph_desc *d, Problem &p)
     for (int i = 0; i < n; ++i) {
         const int hv = d->h ? d->h[i] : 0;
         amax = std::max(amax, base[i] + std::abs(hv));
-        base[i] = (int16_t)(base[i] + hv);
+        base[i] += hv;
     }
     p.class_start.assign((size_t)ncol + 1, 0);
     for (int i = 0; i < n; ++i) ++p.class_start[(size_t)p.colour[i] + 1];
     for (int c = 0; c < ncol; ++c) p.class_start[(size_t)c + 1] += p.class_start[c];
     std::vector<int32_t> cls((size_t)n), cfill(p.class_start.begin(), p.class_start.end() - 1);
     for (int i = 0; i < n; ++i) cls[(size_t)cfill[p.colour[i]]++] = i;
+    std::vector<int32_t> meta((size_t)4 * n);
+    std::vector<uint32_t> adj((size_t)2 * nb);
+    size_t at = 0;
+    for (int j = 0; j < n; ++j) {
+        const int i = cls[(size_t)j];
+        meta[(size_t)4 * j] = i;
+        meta[(size_t)4 * j + 1] = (int32_t)at;
+        for (int e = start[i]; e < start[(size_t)i + 1]; ++e) adj[at++] = word[(size_t)e];
+        meta[(size_t)4 * j + 2] = (int32_t)at;
+        meta[(size_t)4 * j + 3] = base[i];
+    }
 
-    void *dcls = nullptr, *dst = nullptr, *dsite = nullptr, *dcode = nullptr, *dbase = nullptr, *dbi = nullptr,
-         *dbj = nullptr, *dbJ = nullptr, *dh = nullptr;
-    int rc = upload(ctx, p, cls.data(), sizeof(int32_t) * cls.size(), &dcls);
-    if (rc == PBIT_OK) rc = upload(ctx, p, start.data(), sizeof(int32_t) * start.size(), &dst);
-    if (rc == PBIT_OK && nb > 0) rc = upload(ctx, p, site.data(), sizeof(int32_t) * site.size(), &dsite);
-    if (rc == PBIT_OK && nb > 0) rc = upload(ctx, p, code.data(), code.size(), &dcode);
-    if (rc == PBIT_OK) rc = upload(ctx, p, base.data(), sizeof(int16_t) * base.size(), &dbase);
+    void *dmeta = nullptr, *dadj = nullptr, *dbi = nullptr, *dbj = nullptr, *dbJ = nullptr, *dh = nullptr;
+    int rc = upload(ctx, p, meta.data(), sizeof(int32_t) * meta.size(), &dmeta);
+    if (rc == PBIT_OK && nb > 0) rc = upload(ctx, p, adj.data(), sizeof(uint32_t) * adj.size(), &dadj);
     if (rc == PBIT_OK && nb > 0) rc = upload(ctx, p, d->bond_i, sizeof(int32_t) * (size_t)nb, &dbi);
     if (rc == PBIT_OK && nb > 0) rc = upload(ctx, p, d->bond_j, sizeof(int32_t) * (size_t)nb, &dbj);
     if (rc == PBIT_OK && nb > 0) rc = upload(ctx, p, d->bond_J, (size_t)nb, &dbJ);
@@ -510,9 +517,8 @@ static int load_graph(pbit_ctx *ctx, const pbit_graph_desc *d, Problem &p)
     p.kind = PBIT_GRAPH;
     p.N = n;
     p.amax = amax;
-    p.graph = GraphView{n, nb, ncol, maxdeg, p.class_start.data(), (const int32_t *)dcls, (const int32_t *)dst,
-                        (const int32_t *)dsite, (const uint8_t *)dcode, (const int16_t *)dbase, (const int32_t *)dbi,
-                        (const int32_t *)dbj, (const int8_t *)dbJ, (const int8_t *)dh};
+    p.graph = GraphView{n, nb, ncol, maxdeg, p.class_start.data(), (const int32_t *)dmeta, (const uint32_t *)dadj,
+                        (const int32_t *)dbi, (const int32_t *)dbj, (const int8_t *)dbJ, (const int8_t *)dh};
     // the cube's layout kernels (init, transposes) are reused with N = n
     p.ea = EaView{0, 0, 0, (int64_t)n, nullptr, nullptr, nullptr, false};
     return PBIT_OK;
@@ -1117,7 +1123,7 @@ hipError_t prof_harvest(pbit_ctx *ctx)
         float ms = 0.f;
         hipError_t e = hipEventElapsedTime(&ms, ctx->prof_pool[2 * k], ctx->prof_pool[2 * k + 1]);
         if (e != hipSuccess) return e;
-        const int kind = ctx->prof_kind[k] == PBIT_EA3D ? 1 : 2;
+        const int kind = ctx->prof_kind[k];
         ctx->prof_ms[kind] += ms;
         ctx->prof_count[kind] += ctx->prof_launches[k];
     }
@@ -1158,8 +1164,9 @@ extern "C" int pbit_profile_variant(pbit_ctx *ctx, int32_t *variant)
 extern "C" int pbit_profile_read(pbit_ctx *ctx, int32_t kind, double *total_ms, int64_t *launches, int32_t reset)
 {
     PBIT_ENTER(ctx);
-    if (kind != PBIT_EA3D && kind != PBIT_BICLIQUE) return fail(PBIT_E_ARG, "pbit_profile_read: unknown kind %d", kind);
-    const int k = kind == PBIT_EA3D ? 1 : 2;
+    if (kind != PBIT_EA3D && kind != PBIT_BICLIQUE && kind != PBIT_GRAPH)
+        return fail(PBIT_E_ARG, "pbit_profile_read: unknown kind %d", kind);
+    const int k = kind;
     if (total_ms) *total_ms = ctx->prof_ms[k];
     if (launches) *launches = ctx->prof_count[k];
     if (reset) {

@@ -58,8 +58,8 @@ struct pbit_ctx {
     std::vector<int> prof_kind;      // kind of each pending pair
     std::vector<int> prof_launches;  // launches inside each pending pair
     int prof_open = -1;              // pool index of the pair whose end is not recorded yet
-    double prof_ms[3] = {0, 0, 0};
-    int64_t prof_count[3] = {0, 0, 0};
+    double prof_ms[4] = {0, 0, 0, 0};       // by problem kind (PBIT_EA3D, PBIT_BICLIQUE, PBIT_GRAPH)
+    int64_t prof_count[4] = {0, 0, 0, 0};
     // biclique kernel variant: forced (PBIT_BQ_VARIANT) or autotuned per shape
     pbit::BqVariant bq_forced = pbit::BqVariant::Auto;
     int bq_last_variant = 0;  // biclique half-sweep variant of the latest biclique anneal (0: none yet)

@@ -42,6 +42,8 @@ def _graphs():
     yield "cube5", synth.ea_bond_list(synth.ea_instance(5, seed=4))
     for k, (n, d) in enumerate([(50, 4), (300, 6), (1000, 12), (200, 40)]):
         yield "random%d" % k, synth.random_sparse_graph(n, d, seed=k)
+    for L in (3, 7):
+        yield "dimer%d" % L, synth.dimerized_cube(L, seed=L)
 
 
 @pytest.mark.parametrize("name,g", list(_graphs()))
@@ -157,3 +159,24 @@ def test_even_cube_as_a_graph_sweeps_like_the_cube():
     r1 = oracle.anneal(g1, beta, 9, seed=3, trace_every=5)
     r2 = oracle.anneal(g2, beta, 9, seed=3, trace_every=5)
     assert np.array_equal(r1.spins, r2.spins) and np.array_equal(r1.energy_trace, r2.energy_trace)
+
+
+@pytest.mark.parametrize("L", [7, 8, 9, 10, 14])
+def test_dimerized_cubes_need_more_than_two_groups(L):
+    """The stand-ins for the paper's hardware-embedded lattices (Sec. 3, which
+    needed four or five update groups): 2 L^3 spins, every pair bonded
+    ferromagnetically, a simple graph (no self-bonds or repeats), and a greedy
+    colouring with five groups that stays within the degree bound."""
+    g = synth.dimerized_cube(L, seed=L)
+    n, bi, bj, bJ = g["n"], g["bond_i"], g["bond_j"], g["bond_J"]
+    assert n == 2 * L ** 3
+    assert np.all(bi != bj)
+    pairs = set(zip(np.minimum(bi, bj).tolist(), np.maximum(bi, bj).tolist()))
+    assert len(pairs) == bi.size
+    dimer = (bi // 2 == bj // 2)
+    assert int(dimer.sum()) == L ** 3 and np.all(bJ[dimer] == 1)
+    assert set(np.unique(bJ[~dimer]).tolist()) <= {-1, 1}
+    col, nc = pbit.pbit_greedy_colouring(n, bi, bj)
+    deg = np.bincount(np.concatenate([bi, bj]), minlength=n)
+    assert nc == 5 and nc <= deg.max() + 1
+    assert np.all(col[bi] != col[bj])

@@ -66,6 +66,55 @@ def test_random_sparse_graph_every_sweep(ctx, n, deg, R):
     _every_sweep(ctx, g, synth.beta_linear(0.05, 3.0, 30), R, seed=7)
 
 
+@pytest.mark.parametrize("L,R,field", [(3, 5, "uniform3"), (7, 50, "zero"), (7, 33, "uniform3")])
+def test_dimerized_cube_every_sweep(ctx, L, R, field):
+    """The five-group stand-in for the paper's hardware-embedded lattices."""
+    g = synth.dimerized_cube(L, seed=L + R, field=field)
+    _say("dimerized cube L=%d R=%d %s every sweep" % (L, R, field))
+    assert pbit.pbit_greedy_colouring(g["n"], g["bond_i"], g["bond_j"])[1] == (5 if L == 7 else 4)
+    _every_sweep(ctx, g, synth.beta_geometric(0.1, 5.0, 30), R, seed=5)
+
+
+def test_dimerized_cube_benchmark_size_sampled(ctx):
+    """The benchmark's graph workload (L = 14: 5,488 spins, 4,096 replicas, the
+    first 12 sweeps of its schedule) in the launch configuration the benchmark
+    times; replica slices recomputed by the oracle through replica_offset."""
+    g = synth.dimerized_cube(14, seed=14)
+    prob = pbit.load_instance(ctx, g)
+    beta = synth.beta_geometric(0.1, 5.0, 2000)[:12]
+    _say("dimerized cube L=14 R=4096 S=12")
+    got = pbit.pbit_anneal(ctx, prob, beta, 4096, seed=1)
+    og = _oracle_graph(g)
+    for off in (0, 1360, 4092):
+        ref = oracle.anneal(og, beta, 4, seed=1, replica_offset=off)
+        assert np.array_equal(got.spins[off:off + 4], ref.spins), off
+        assert np.array_equal(got.energies[off:off + 4], ref.energies), off
+    pbit.pbit_unload_problem(ctx, prob)
+
+
+def test_profile_windows_count_group_launches(ctx):
+    """pbit_profile_read keeps the half-sweep launches of each problem kind
+    apart: k launches per sweep for a graph of k groups, 2 for a cube."""
+    g = synth.dimerized_cube(3, seed=3)
+    gp = pbit.load_instance(ctx, g)
+    k = pbit.pbit_problem_colouring(ctx, gp)[1]
+    cp = pbit.load_instance(ctx, synth.ea_instance(4, seed=1))
+    pbit.pbit_profile_enable(ctx, 1)
+    for kind in (pbit.PBIT_EA3D, pbit.PBIT_BICLIQUE, pbit.PBIT_GRAPH):
+        pbit.pbit_profile_read(ctx, kind, reset=True)
+    _say("profile windows: graph of %d groups, cube" % k)
+    pbit.pbit_anneal(ctx, gp, synth.beta_linear(0.1, 1.0, 6), 16, seed=1)
+    pbit.pbit_anneal(ctx, cp, synth.beta_linear(0.1, 1.0, 5), 16, seed=1)
+    pbit.pbit_profile_enable(ctx, 0)
+    ms_g, n_g = pbit.pbit_profile_read(ctx, pbit.PBIT_GRAPH, reset=True)
+    ms_c, n_c = pbit.pbit_profile_read(ctx, pbit.PBIT_EA3D, reset=True)
+    ms_b, n_b = pbit.pbit_profile_read(ctx, pbit.PBIT_BICLIQUE, reset=True)
+    assert (n_g, n_c, n_b) == (6 * k, 10, 0)
+    assert ms_g > 0 and ms_c > 0 and ms_b == 0
+    pbit.pbit_unload_problem(ctx, gp)
+    pbit.pbit_unload_problem(ctx, cp)
+
+
 def test_caller_colouring_one_vertex_per_group(ctx):
     """Every vertex its own group: the sequential (Gibbs-order) sweep."""
     g = synth.random_sparse_graph(60, 5, seed=1)
