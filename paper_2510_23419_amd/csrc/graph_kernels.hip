@@ -26,64 +26,80 @@ constexpr int kThreads = 256;
 constexpr int kMaxOff = kGraphMaxDegree + 1;          // |I| <= degree + |h|
 constexpr int kSlots = 2 * kMaxOff + 1;
 
+// Decision: the table holds, for every field value I, the 64-bit word S(I) = Tm
+// for I >= 0 and 2^32 - Tm for I < 0; the new spin is -1 exactly when w + S(I)
+// carries into bit 32 (the heat-bath rule with the uniform word w), one
+// v_mad_u64_u32 per update (`one` is 1, passed in so that the multiply-add is
+// kept as that instruction).
 __global__ __launch_bounds__(kThreads) void k_graph_halfsweep(int8_t *__restrict__ spins,
-                                                              const int4 *__restrict__ meta, int n_class,
+                                                              const int4 *__restrict__ meta, uint32_t n_class,
                                                               const uint32_t *__restrict__ adj,
                                                               const uint32_t *__restrict__ trow, int width, int Rp,
                                                               int lg_nsl, uint32_t sweep, uint32_t rq0, uint32_t k0,
-                                                              uint32_t k1)
+                                                              uint32_t k1, uint32_t one)
 {
-    const int cs = (Rp / 16) >> lg_nsl;  // chunks of 16 replicas per slab
-    const int slab = (int)blockIdx.x & ((1 << lg_nsl) - 1);
-    const int64_t gid = (int64_t)(blockIdx.x >> lg_nsl) * kThreads + threadIdx.x;  // (site, chunk) inside the slab
-    const bool live = gid < (int64_t)n_class * cs;
+    const uint32_t cs = (uint32_t)(Rp / 16) >> lg_nsl;  // chunks of 16 replicas per slab
+    const uint32_t slab = blockIdx.x & ((1u << lg_nsl) - 1u);
+    const uint32_t gid = (blockIdx.x >> lg_nsl) * kThreads + threadIdx.x;  // (site, chunk) inside the slab
+    const bool live = gid < n_class * cs;
+    const uint32_t j = gid / cs;
     // the site record first, so that its latency overlaps the table build
     int4 m = make_int4(0, 0, 0, 0);  // site, first entry, end entry, base = nnz + h
-    if (live) m = meta[gid / cs];
-    // decision table over I in [-kMaxOff, kMaxOff]: threshold, xor mask, minority and majority byte
-    __shared__ uint4 tab[kSlots];
+    if (live) m = meta[j];
+    // decision words by descending field value: entry k is S(I) for I = kMaxOff - k
+    __shared__ uint64_t tab[kSlots];
     for (int k = threadIdx.x; k < kSlots; k += kThreads) {
-        const int I = k - kMaxOff;
-        const int a = min(I >= 0 ? I : -I, width - 1);
-        const bool pos = I >= 0;
-        tab[k] = make_uint4(trow[a], pos ? 0xFFFFFFFFu : 0u, pos ? 0xFFu : 0x01u, pos ? 0x01u : 0xFFu);
+        const int I = kMaxOff - k;
+        const uint32_t T = trow[min(I >= 0 ? I : -I, width - 1)];
+        tab[k] = I >= 0 ? (uint64_t)T : ((uint64_t)1 << 32) - T;
     }
     __syncthreads();
     if (!live) return;
-    const int q = slab * cs + (int)(gid % cs);
+    const uint32_t q = slab * cs + (gid - j * cs);
     const int i = m.x;
+    const int last = m.z - 1;
     uint32_t cnt[4] = {0u, 0u, 0u, 0u};
-    for (int e = m.y; e < m.z; e += 4) {
-        // four entries, then their four rows; entries past the end read as code 0 (no term)
+    for (int e = m.y; e <= last; e += 4) {
+        // four entries, then their four rows; an entry past the end repeats the last one
+        // with its coupling code cleared, so it adds nothing and every load is in range
         uint32_t w[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) w[k] = e + k < m.z ? adj[e + k] : 0u;
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t x = adj[min(e + k, last)];
+            w[k] = e + k <= last ? x : x & ~3u;
+        }
         uint4 v[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-            v[k] = e + k < m.z ? *reinterpret_cast<const uint4 *>(spins + (size_t)(w[k] >> 2) * Rp + 16 * q)
-                               : make_uint4(0u, 0u, 0u, 0u);
+        for (int k = 0; k < 4; ++k) v[k] = *reinterpret_cast<const uint4 *>(spins + (size_t)(w[k] >> 2) * Rp + 16 * q);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const uint32_t keep = (w[k] & 1u) * 0x02020202u, flip = ((w[k] >> 1) & 1u) * 0x02020202u;
+            // 0x02 in every byte where J != 0 (keep) and where J = -1 (flip)
+            const uint32_t keep = (uint32_t)((int32_t)(w[k] << 31) >> 31) & 0x02020202u;
+            const uint32_t flip = (uint32_t)((int32_t)(w[k] << 30) >> 31) & 0x02020202u;
             cnt[0] += (v[k].x & keep) ^ flip;
             cnt[1] += (v[k].y & keep) ^ flip;
             cnt[2] += (v[k].z & keep) ^ flip;
             cnt[3] += (v[k].w & keep) ^ flip;
         }
     }
-    const int b0 = m.w + kMaxOff;  // table index for I = nnz + h (no negative products)
+    // a byte c of cnt (two per negative product) gives I = base - c: table entry
+    // kMaxOff - base + c
+    const char *tb = reinterpret_cast<const char *>(tab) + 8 * (kMaxOff - m.w);
     uint32_t out[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const Block4 b = philox((uint32_t)i, sweep, rq0 + 4u * (uint32_t)q + (uint32_t)k, kDomainSweep, k0, k1);
-        uint32_t packed = 0;
+        const Block4 b = philox((uint32_t)i, sweep, rq0 + 4u * q + (uint32_t)k, kDomainSweep, k0, k1);
+        uint32_t sgn[4];  // 1: the replica's new spin is -1
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
-            const uint4 t = tab[b0 - (int)((cnt[k] >> (8 * p)) & 0xFFu)];  // I = base - c2
-            packed |= ((b.w[p] ^ t.y) < t.x ? t.z : t.w) << (8 * p);
+            const uint32_t c = (cnt[k] >> (8 * p)) & 0xFFu;
+            const uint64_t S = *static_cast<const uint64_t *>(__builtin_assume_aligned(tb + 8 * c, 8));
+            sgn[p] = (uint32_t)(((uint64_t)b.w[p] * one + S) >> 32);
         }
-        out[k] = packed;
+        // gather the four low bytes, then map 0 -> 0x01 and 1 -> 0xFF
+        const uint32_t lo = __builtin_amdgcn_perm(sgn[1], sgn[0], 0x0C0C0400u);
+        const uint32_t hi = __builtin_amdgcn_perm(sgn[3], sgn[2], 0x0C0C0400u);
+        out[k] = __builtin_amdgcn_perm(0u, 0xFF01u, __builtin_amdgcn_perm(hi, lo, 0x05040100u));
     }
     *reinterpret_cast<uint4 *>(spins + (size_t)i * Rp + 16 * q) = make_uint4(out[0], out[1], out[2], out[3]);
 }
@@ -118,11 +134,11 @@ hipError_t graph_halfsweep(const GraphView &g, int colour, int8_t *spins, int Rp
     const int chunks = Rp / 16;
     const int lg_nsl = chunks % 8 == 0 ? 3 : 0;  // 8 replica slabs, one per XCD
     const int64_t work = (int64_t)n_class * (chunks >> lg_nsl);
+    if (work > 0xFFFFFF00LL) return hipErrorInvalidValue;  // 32-bit thread indices
     const int64_t blocks = ((work + kThreads - 1) / kThreads) << lg_nsl;
-    if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_graph_halfsweep, dim3((unsigned)blocks), dim3(kThreads), 0, st, spins,
-                       reinterpret_cast<const int4 *>(g.site_meta) + g.class_start[colour], n_class, g.adj, trow,
-                       width, Rp, lg_nsl, sweep, rq0, key.k0, key.k1);
+                       reinterpret_cast<const int4 *>(g.site_meta) + g.class_start[colour], (uint32_t)n_class, g.adj,
+                       trow, width, Rp, lg_nsl, sweep, rq0, key.k0, key.k1, 1u);
     return hipGetLastError();
 }
 
