@@ -305,12 +305,75 @@ def serve_bench(args, pbit, torch):
     ctx.close()
 
 
+def alg1_bench(args, pbit, torch):
+    """Algorithm 1 (Sec. 1.3.3) on the paper's ladder of cubic lattices N = 2^3 ... 10^3
+    (J iid +-1, h = 0, periodic; odd sides run as general graphs with greedy groups):
+    for each quality p, the smallest sweep budget of a linear 0.35 -> 3.5 schedule at
+    which 18 of 20 trials end at or below p G, each size starting its search at the
+    budget the previous size needed.  G is the best energy of 4096 replicas annealed
+    over 10^4 sweeps (geometric 0.1 -> 5.0).  The i_min of every p is fitted to the
+    anchored logistic of Eq. 4 over N."""
+    import numpy as np
+    import synth
+    from paper_2510_23419_amd import alg1
+    ctx = pbit.Context(0)
+    t0 = time.perf_counter()
+    ladder = []
+    for L in range(2, 11):
+        inst = synth.ea_instance(L, seed=L)
+        prob = pbit.load_instance(ctx.ctx, inst if L % 2 == 0 else synth.ea_bond_list(inst))
+        ref = pbit.pbit_anneal(ctx.ctx, prob, synth.beta_geometric(0.1, 5.0, 10_000), 4096, seed=99, want_spins=False)
+        ladder.append((L, prob, ref.best_energy, pbit.pbit_problem_colouring(ctx.ctx, prob)[1]))
+    t_ref = time.perf_counter() - t0
+    results, fits, updates = [], {}, 0
+    t1 = time.perf_counter()
+    for p in args.alg1_qualities:
+        start, pts = 1, []
+        for L, prob, G, groups in ladder:
+            r = alg1.i_min(ctx.ctx, prob, G, i_start=start, i_step=1, t=20, p=p, p_succ=0.9, seed=1, window=16,
+                           i_max=args.alg1_max)
+            updates += sum(b for b, _ in r.history) * 20 * L ** 3
+            print("alg1: p=%.2f L=%d i_min=%s (%d budgets, %.1f s)" % (p, L, r.i_min, len(r.history),
+                                                                     time.perf_counter() - t1),
+                  file=sys.stderr, flush=True)
+            results.append({"L": L, "N": L ** 3, "groups": groups, "G": G, "p": p, "i_min_sweeps": r.i_min,
+                            "i_min_iterations": None if r.i_min is None else r.i_min * groups,
+                            "budgets_tried": len(r.history)})
+            if r.i_min is not None:
+                start = r.i_min
+                pts.append((L ** 3, r.i_min * groups))
+        if len(pts) >= 4:
+            try:
+                Lf, kf, xc = alg1.fit_anchored_logistic([x for x, _ in pts], [y for _, y in pts])
+                fits[str(p)] = {"L": Lf, "k": kf, "x_c": xc}
+            except Exception as e:  # a ladder the logistic does not fit is reported, not fatal
+                fits[str(p)] = {"error": str(e)[:80]}
+    wall = time.perf_counter() - t1
+    for _, prob, _, _ in ladder:
+        pbit.pbit_unload_problem(ctx.ctx, prob)
+    res = {
+        "metric": "p-bit updates/s inside Algorithm 1 searches (minimum iteration budgets, Sec. 1.3.3)",
+        "value": updates / wall, "unit": "p-bit updates/s",
+        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": wall * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int8", "data": "synthetic",
+        "config": {"workload": "Algorithm 1 on random +-1 cubes L = 2..10 (seed L, h = 0), 20 trials at 90 %% "
+                               "success, qualities %s, linear 0.35 -> 3.5, search window 16 budgets"
+                               % ",".join("%.2f" % q for q in args.alg1_qualities),
+                   "reference_seconds": t_ref, "i_min": results, "logistic_fits": fits},
+    }
+    print(json.dumps(res), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="ea32", choices=sorted(WORKLOADS) + ["mixed", "serve"])
+    ap.add_argument("--workload", default="ea32", choices=sorted(WORKLOADS) + ["mixed", "serve", "alg1"])
+    ap.add_argument("--alg1-qualities", type=float, nargs="+", default=[0.90, 0.95, 0.98],
+                    help="alg1: solution qualities p (pass when E <= p G)")
+    ap.add_argument("--alg1-max", type=int, default=20000, help="alg1: largest sweep budget tried")
     ap.add_argument("--bag-size", type=int, default=256)
     ap.add_argument("--bag-seed", type=int, default=0)
     ap.add_argument("--plain-jobs", type=int, default=32, help="jobs of the bag timed through the per-instance path")
@@ -348,6 +411,9 @@ def main():
         return
     if args.workload == "serve":
         serve_bench(args, pbit, torch)
+        return
+    if args.workload == "alg1":
+        alg1_bench(args, pbit, torch)
         return
 
     w = WORKLOADS[args.workload]

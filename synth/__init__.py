@@ -156,7 +156,7 @@ def random_sparse_graph(n: int, degree: int, seed: int, field: str = "uniform3",
 
 
 def dimerized_cube(L: int, seed: int, rewire: float = 0.1, field: str = "zero"):
-    """Stand-in for the paper's literature lattices (Sec. 3: cubic lattices
+    """Stand-in for the paper's literature lattices (Sec. 2.2: cubic lattices
     dimerized at every site and rewired to a hardware graph, which needed four
     or five update groups): a periodic L^3 cube with iid +-1 bonds whose sites
     are split into ferromagnetic pairs (spins 2 i and 2 i + 1, J = +1); each cube

@@ -163,7 +163,7 @@ def test_even_cube_as_a_graph_sweeps_like_the_cube():
 
 @pytest.mark.parametrize("L", [7, 8, 9, 10, 14])
 def test_dimerized_cubes_need_more_than_two_groups(L):
-    """The stand-ins for the paper's hardware-embedded lattices (Sec. 3, which
+    """The stand-ins for the paper's hardware-embedded lattices (Sec. 2.2, which
     needed four or five update groups): 2 L^3 spins, every pair bonded
     ferromagnetically, a simple graph (no self-bonds or repeats), and a greedy
     colouring with five groups that stays within the degree bound."""
