@@ -384,6 +384,8 @@ def main():
     ap.add_argument("--profile-every", type=int, default=32,
                     help="time a window of 8 consecutive half-sweeps with HIP events every k launches (0 = off)")
     ap.add_argument("--sweeps", type=int, default=0, help="run only the first k sweeps of the schedule (profiling)")
+    ap.add_argument("--trace-points", type=int, default=100,
+                    help="points of the residual-against-sweeps trace, from one untimed anneal (0 = off)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized int8 tensor 5 times (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -499,6 +501,22 @@ def main():
             roof["valu"]["lane_ops_per_update"] = lane_ops / (N * R / 2)  # a half-sweep updates N/2 sites
     roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
 
+    # residual energy against sweeps: one more anneal, outside the timed region, with every
+    # replica's energy recorded every S/100 sweeps; residual of the best and of the mean
+    # replica against the best energy this anneal reaches
+    trace = None
+    if args.trace_points > 0:
+        every = max(1, S // args.trace_points)
+        t0 = time.perf_counter()
+        tr = pbit.pbit_anneal(ctx.ctx, prob, beta, R, 1, trace_every=every, want_spins=False)
+        traced_ms = (time.perf_counter() - t0) * 1e3
+        et = tr.energy_trace.astype(float)
+        ref = float(min(et.min(), tr.best_energy))
+        trace = {"every_sweeps": every, "reference_energy": ref, "traced_anneal_ms": traced_ms,
+                 "sweeps": [every * (k + 1) for k in range(et.shape[0])],
+                 "residual_best": [round((float(r.min()) - ref) / abs(ref), 6) for r in et],
+                 "residual_mean": [round((float(r.mean()) - ref) / abs(ref), 6) for r in et]}
+
     cpu = None
     if args.cpu_seconds > 0:
         cpu = cpu_baseline(w, inst, beta, args.cpu_seconds)
@@ -518,7 +536,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": describe(w), "spins": N, "replicas": R, "sweeps": S,
                    "anneals_per_s": args.steps / wall, "device_ms_per_step": dev_ms / args.steps,
-                   "best_energy": best},
+                   "best_energy": best, "residual_vs_sweeps": trace},
         "roofline": roof,
         "cpu_baseline": cpu,
     }
