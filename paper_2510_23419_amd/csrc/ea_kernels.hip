@@ -196,32 +196,70 @@ __global__ __launch_bounds__(kThreads) void k_ea_halfsweep(int8_t *__restrict__ 
     }
 }
 
-// From-scratch energy: E[r] += -sum over a chunk of sites of (bond + field)
-// terms.  Each bond (i, i + e_d) is visited once, from its lower-end site i.
+// From-scratch energy (Eq. 1 with the field): E[r] = -sum_bonds J m_i m_j - sum_i h_i m_i,
+// each bond (i, i + e_d) visited once, from its lower-end site i.  With d = 1 where two
+// spins differ (bit 1 of the xor of their bytes) and b = 1 where a spin is -1,
+// -J m_i m_j = -J + 2 J d and -h m = -h + 2 h b, so
+//     E[r] = -(sum J + sum h) + 2 (P[r] - Q[r]),
+// P counting the d of bonds with J = +1 and the b of sites with h = +1, Q those with -1.
+// A thread counts P and Q bytewise for 16 replicas over kEnergySites sites (at most
+// 4 kEnergySites per byte); the workgroup (16 site chunks x 16 replica chunks) sums its
+// chunks in LDS and adds one total per replica.
+constexpr int kEnergySites = 32;
+
 __global__ __launch_bounds__(kThreads) void k_ea_energy(const int8_t *__restrict__ spins, const int8_t *__restrict__ J,
                                                         const int8_t *__restrict__ h, int Lx, int Ly, int Lz, int Rp,
-                                                        int R, int64_t chunk, int32_t *__restrict__ E)
+                                                        int R, int32_t *__restrict__ E)
 {
-    const int r = blockIdx.x * kThreads + threadIdx.x;
-    if (r >= R) return;
+    __shared__ int32_t part[16][256 + 1];
+    const int rq = threadIdx.x & 15, sc = threadIdx.x >> 4;
+    const int q = blockIdx.y * 16 + rq;                       // chunk of 16 replicas
     const int64_t N = (int64_t)Lx * Ly * Lz;
     const int64_t plane = (int64_t)Lx * Ly;
-    const int64_t s0 = (int64_t)blockIdx.y * chunk;
-    const int64_t s1 = min(s0 + chunk, N);
-    int32_t e = 0;
-    for (int64_t i = s0; i < s1; ++i) {
-        const int x = (int)(i % Lx);
-        const int y = (int)((i / Lx) % Ly);
-        const int z = (int)(i / plane);
-        const int mi = spins[(size_t)i * Rp + r];
-        const int64_t jx = wrap_inc(x, Lx) + (int64_t)Lx * y + plane * z;
-        const int64_t jy = x + (int64_t)Lx * wrap_inc(y, Ly) + plane * z;
-        const int64_t jz = x + (int64_t)Lx * y + plane * wrap_inc(z, Lz);
-        const int s = J[i] * spins[(size_t)jx * Rp + r] + J[N + i] * spins[(size_t)jy * Rp + r] +
-                      J[2 * N + i] * spins[(size_t)jz * Rp + r] + (h ? h[i] : 0);
-        e -= mi * s;
+    const int64_t s0 = ((int64_t)blockIdx.x * 16 + sc) * kEnergySites;
+    const int64_t s1 = min(s0 + kEnergySites, N);
+    uint32_t P[4] = {0u, 0u, 0u, 0u}, Q[4] = {0u, 0u, 0u, 0u};
+    int32_t base = 0;  // -(sum J + sum h) over the chunk's sites
+    if (16 * q < Rp) {
+        for (int64_t i = s0; i < s1; ++i) {
+            const int x = (int)(i % Lx), y = (int)((i / Lx) % Ly), z = (int)(i / plane);
+            const int64_t nb[3] = {(x + 1 == Lx ? 0 : x + 1) + (int64_t)Lx * y + plane * z,
+                                   x + (int64_t)Lx * (y + 1 == Ly ? 0 : y + 1) + plane * z,
+                                   x + (int64_t)Lx * y + plane * (z + 1 == Lz ? 0 : z + 1)};
+            const uint4 mi = *reinterpret_cast<const uint4 *>(spins + (size_t)i * Rp + 16 * q);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const int j = J[d * N + i];
+                const uint4 mj = *reinterpret_cast<const uint4 *>(spins + (size_t)nb[d] * Rp + 16 * q);
+                const uint32_t mp = j > 0 ? 0x01010101u : 0u, mn = j < 0 ? 0x01010101u : 0u;
+                const uint32_t dx = (mi.x ^ mj.x) >> 1, dy = (mi.y ^ mj.y) >> 1, dz = (mi.z ^ mj.z) >> 1,
+                               dw = (mi.w ^ mj.w) >> 1;
+                P[0] += dx & mp; P[1] += dy & mp; P[2] += dz & mp; P[3] += dw & mp;
+                Q[0] += dx & mn; Q[1] += dy & mn; Q[2] += dz & mn; Q[3] += dw & mn;
+                base -= j;
+            }
+            const int hv = h ? h[i] : 0;
+            const uint32_t mp = hv > 0 ? 0x01010101u : 0u, mn = hv < 0 ? 0x01010101u : 0u;
+            const uint32_t bx = mi.x >> 1, by = mi.y >> 1, bz = mi.z >> 1, bw = mi.w >> 1;
+            P[0] += bx & mp; P[1] += by & mp; P[2] += bz & mp; P[3] += bw & mp;
+            Q[0] += bx & mn; Q[1] += by & mn; Q[2] += bz & mn; Q[3] += bw & mn;
+            base -= hv;
+        }
     }
-    atomicAdd(E + r, e);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+            part[sc][16 * rq + 4 * k + p] =
+                base + 2 * ((int)((P[k] >> (8 * p)) & 0xFFu) - (int)((Q[k] >> (8 * p)) & 0xFFu));
+    __syncthreads();
+    const int r = blockIdx.y * 256 + threadIdx.x;
+    if (r < R) {
+        int32_t e = 0;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) e += part[c][threadIdx.x];
+        atomicAdd(E + r, e);
+    }
 }
 
 }  // namespace
@@ -293,10 +331,12 @@ hipError_t ea_energy(const EaView &p, const int8_t *spins, int Rp, int R, int32_
 {
     hipError_t e = fill_i32(E, R, 0, st);
     if (e != hipSuccess) return e;
-    // 64 sites per block row, more when that would exceed the grid's y limit
-    const int64_t chunk = std::max<int64_t>(64, (p.N + 65534) / 65535);
-    dim3 grid(blocks_for(R), (unsigned)((p.N + chunk - 1) / chunk));
-    hipLaunchKernelGGL(k_ea_energy, grid, dim3(kThreads), 0, st, spins, p.J, p.h, p.Lx, p.Ly, p.Lz, Rp, R, chunk, E);
+    // a workgroup: 256 replicas x 16 chunks of kEnergySites sites
+    const int64_t sites_per_block = 16 * kEnergySites;
+    const int64_t gx = (p.N + sites_per_block - 1) / sites_per_block;
+    if ((Rp + 255) / 256 > 65535) return hipErrorInvalidValue;
+    dim3 grid((unsigned)gx, (unsigned)((Rp + 255) / 256));
+    hipLaunchKernelGGL(k_ea_energy, grid, dim3(kThreads), 0, st, spins, p.J, p.h, p.Lx, p.Ly, p.Lz, Rp, R, E);
     return hipGetLastError();
 }
 
