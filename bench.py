@@ -261,8 +261,13 @@ def serve_bench(args, pbit, torch):
     rejected = 0
     t0 = time.perf_counter()
     k = 0
+    next_note = 10.0
     while k < len(arrivals) or pending:
         now = time.perf_counter() - t0
+        if now >= next_note:  # progress on stderr (stdout carries the one result line)
+            print("serve: %.0f s, %d offered, %d done, %d pending, %d rejected" % (now, k, len(lat), len(pending),
+                                                                                 rejected), file=sys.stderr, flush=True)
+            next_note += 10.0
         while k < len(arrivals) and arrivals[k] <= now:
             q = int(which[k])
             j = pool[q]
@@ -378,7 +383,7 @@ def main():
     ap.add_argument("--bag-seed", type=int, default=0)
     ap.add_argument("--plain-jobs", type=int, default=32, help="jobs of the bag timed through the per-instance path")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: Poisson arrival rate (jobs/s)")
-    ap.add_argument("--duration", type=float, default=20.0, help="serve: arrival window (s)")
+    ap.add_argument("--duration", type=float, default=60.0, help="serve: arrival window (s)")
     ap.add_argument("--pool", type=int, default=64, help="serve: distinct instances jobs are drawn from")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="oracle sample budget (0 = skip)")
     ap.add_argument("--profile-every", type=int, default=32,
