@@ -27,6 +27,7 @@ struct BqJobDev {
     const uint8_t *J4, *JT4;  // packed 4-bit float couplings [na_p][nb_p / 2], [nb_p][na_p / 2]
     const int8_t *Jb, *JTb;   // couplings in the widened-bit column order, scaled (bit tiles)
     const int32_t *hA2, *hB2; // field plus coupling sum per site (bit tiles)
+    const uint32_t *J2, *JT2; // J + 1 as two-bit codes in fragment order (int8 tiles)
     const int8_t *hA, *hB;    // [na_p], [nb_p]
     const uint32_t *table;    // [S][width]
     uint8_t *state;           // [tiles][RS][row]: row r = side A then side B, as int8 (na_p + nb_p

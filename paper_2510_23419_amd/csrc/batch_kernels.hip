@@ -222,6 +222,20 @@ __device__ __forceinline__ uint32_t quad_transpose(uint32_t d, int u)
 __device__ __forceinline__ uint32_t fp4_code(int m) { return m > 0 ? 0x2u : (m < 0 ? 0xAu : 0x0u); }
 __device__ __forceinline__ int fp4_value(uint32_t nib) { return nib == 0 ? 0 : ((nib & 8u) ? -1 : 1); }
 
+// Four dwords of int8 K bytes from one word of two-bit codes: byte i of dword j is
+// the code at bits 2 j, 2 j + 1 of byte i (the value J + 1 in {0, 1, 2}).
+__device__ __forceinline__ v4i widen_codes(uint32_t x)
+{
+    return v4i{(int)(x & 0x03030303u), (int)((x >> 2) & 0x03030303u), (int)((x >> 4) & 0x03030303u),
+               (int)((x >> 6) & 0x03030303u)};
+}
+
+// Sum of the four bytes of x.
+__device__ __forceinline__ int byte_sum(uint32_t x)
+{
+    return (int)((x & 0xFFu) + ((x >> 8) & 0xFFu) + ((x >> 16) & 0xFFu) + (x >> 24));
+}
+
 typedef int v8i __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
@@ -302,7 +316,7 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles_bits(const BqJobDev
             const int top = jb.width - 1;
             for (int e = tid; e <= 2 * top; e += kBqTileThreads) {
                 const int I = e - top;
-                const uint32_t Tm = trow[I >= 0 ? I : -I];
+                const uint32_t Tm = load_global<uint32_t>(trow + (I >= 0 ? I : -I));
                 Sw[e] = I >= 0 ? (uint64_t)Tm : ((uint64_t)1 << 32) - Tm;
             }
             __syncthreads();
@@ -328,7 +342,7 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles_bits(const BqJobDev
                 if (wave < nblk) {
                     const uint8_t *br0 = Jx + (size_t)(wave * 32 + ln) * ko + 16 * kg;
 #pragma unroll
-                    for (int u = 0; u < kRing; ++u) ring[u] = *reinterpret_cast<const v4i *>(br0 + 32 * min(u, nku - 1));
+                    for (int u = 0; u < kRing; ++u) ring[u] = load_global<v4i>(br0 + 32 * min(u, nku - 1));
                 }
                 for (int blk = wave; blk < nblk; blk += kStep) {
                     const int site = blk * 32 + ln;
@@ -345,8 +359,7 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles_bits(const BqJobDev
                             if (ku < nku) {
                                 const v4i b = ring[u];
                                 const int kn = ku + kRing;
-                                ring[u] = *reinterpret_cast<const v4i *>(kn < nku ? br + 32 * kn
-                                                                                : bn + 32 * min(u, nku - 1));
+                                ring[u] = load_global<v4i>(kn < nku ? br + 32 * kn : bn + 32 * min(u, nku - 1));
 #pragma unroll
                                 for (int rb = 0; rb < RB; ++rb) {
                                     const v4i a = widen_bits(abase[rb * 32 * pitch + ku], kg);
@@ -408,7 +421,10 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles_bits(const BqJobDev
 // A tile holds RB x 32 replicas of both sides in LDS, one row per replica:
 // side A first, then side B, zero padding.  With int8 operands a row holds one
 // byte per site and the half-sweep is the int8 MFMA with int32
-// accumulation; with FP4 operands a row holds packed 4-bit floats (e2m1: +1 =
+// accumulation; the couplings stream as two-bit codes of J + 1 (a quarter of
+// the int8 bytes: these tiles are bound by how fast a CU pulls couplings from
+// L2), widened to bytes in registers, and the field is the product minus the
+// replica's sum over the other side's spins; with FP4 operands a row holds packed 4-bit floats (e2m1: +1 =
 // 0x2, -1 = 0xA, 0 = 0x0; two sites per byte, lower site in the low nibble) and
 // the half-sweep is the f8f6f4 MFMA with fp32 accumulation — exact, since every
 // value is -1, 0 or +1 and every partial sum an integer below 2^24 — at half
@@ -427,6 +443,7 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
     using Acc = typename std::conditional<FP4, v16f, v16i>::type;
     extern __shared__ uint4 dyn[];
     __shared__ int32_t eacc[RS];
+    __shared__ int32_t mag[RS];  // int8 codes: sum of the other side's spins per replica
     __shared__ int slot;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6, ln = lane & 31, kg = lane >> 5;
@@ -486,7 +503,7 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
             const int top = jb.width - 1;
             for (int e = tid; e <= 2 * top; e += kBqTileThreads) {
                 const int I = e - top;
-                const uint32_t Tm = trow[I >= 0 ? I : -I];
+                const uint32_t Tm = load_global<uint32_t>(trow + (I >= 0 ? I : -I));
                 Sw[e] = I >= 0 ? (uint64_t)Tm : ((uint64_t)1 << 32) - Tm;
             }
             __syncthreads();
@@ -500,7 +517,7 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
                 const int in_col = side == 0 ? pa : 0;      // bytes of the other side (A operand)
                 const int out_col = side == 0 ? 0 : pa;     // bytes of this side
                 const uint8_t *Jx = FP4 ? (side == 0 ? jb.J4 : jb.JT4)
-                                        : reinterpret_cast<const uint8_t *>(side == 0 ? jb.J : jb.JT);
+                                        : reinterpret_cast<const uint8_t *>(side == 0 ? jb.J2 : jb.JT2);
                 const int8_t *hs = side == 0 ? jb.hA : jb.hB;
                 const uint32_t site_base = side == 0 ? 0u : (uint32_t)na;
                 // one 32-site block per wave at a time; its coupling fragments stream
@@ -510,17 +527,50 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
                 const int nku = ko / 32;
                 constexpr int kStep = kBqTileThreads / 64;
                 const int nblk = ns_p / 32;
-                v4i ring[kRing];
-                if (wave < nblk) {
-                    const uint8_t *br0 = Jx + (size_t)(wave * 32 + ln) * ko + 16 * kg;
+                if constexpr (!FP4) {
+                    // the other side's spin sum per replica, padding sites included (their
+                    // codes are 1): T threads per row, bytewise
+                    // counts of nonzero and of -1 spins (at most 72 per byte for the
+                    // row lengths that fit LDS), then a sum over the T lanes
+                    constexpr int T = kBqTileThreads / RS;
+                    const int r = tid / T, part = tid % T;
+                    const uint4 *row = reinterpret_cast<const uint4 *>(sp + r * pitch + in_col);
+                    uint32_t nz = 0u, neg = 0u;
+#pragma unroll 4
+                    for (int d = part; d < ko / 16; d += T) {
+                        const uint4 x = row[d];
+                        nz += (x.x & 0x01010101u) + (x.y & 0x01010101u) + (x.z & 0x01010101u) + (x.w & 0x01010101u);
+                        neg += ((x.x >> 7) & 0x01010101u) + ((x.y >> 7) & 0x01010101u) + ((x.z >> 7) & 0x01010101u) +
+                               ((x.w >> 7) & 0x01010101u);
+                    }
+                    int v = byte_sum(nz) - 2 * byte_sum(neg);
 #pragma unroll
-                    for (int u = 0; u < kRing; ++u) ring[u] = *reinterpret_cast<const v4i *>(br0 + 32 * min(u, nku - 1));
+                    for (int off = T / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+                    if (part == 0) mag[r] = v;
+                    __syncthreads();
+                }
+                // coupling fragments: [K step][site block] of 16 int8 bytes per lane (FP4:
+                // packed nibbles) or one word of codes per lane, 64 words per K step and block
+                using Frag = typename std::conditional<FP4, v4i, uint32_t>::type;
+                auto frag_ptr = [&](int blk) -> const uint8_t * {
+                    if constexpr (FP4)
+                        return Jx + (size_t)(blk * 32 + ln) * ko + 16 * kg;
+                    else
+                        return Jx + 4 * (((size_t)blk * nku * 2 + kg) * 32 + ln);
+                };
+                constexpr int kUnit = FP4 ? 32 : 256;  // bytes from one K step of a fragment to the next
+                Frag ring[kRing];
+                if (wave < nblk) {
+                    const uint8_t *br0 = frag_ptr(wave);
+#pragma unroll
+                    for (int u = 0; u < kRing; ++u)
+                        ring[u] = load_global<Frag>(br0 + (size_t)kUnit * min(u, nku - 1));
                 }
                 for (int blk = wave; blk < nblk; blk += kStep) {
                     const int site = blk * 32 + ln;
-                    const uint8_t *br = Jx + (size_t)site * ko + 16 * kg;
+                    const uint8_t *br = frag_ptr(blk);
                     // the next block of this wave, or this one again when there is none
-                    const uint8_t *bn = blk + kStep < nblk ? br + (size_t)kStep * 32 * ko : br;
+                    const uint8_t *bn = blk + kStep < nblk ? frag_ptr(blk + kStep) : br;
                     Acc acc[RB];
 #pragma unroll
                     for (int rb = 0; rb < RB; ++rb) acc[rb] = Acc{0};
@@ -530,12 +580,16 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
                         for (int u = 0; u < kRing; ++u) {
                             const int ku = kb + u;
                             if (ku < nku) {
-                                const v4i b = ring[u];
+                                v4i b;
+                                if constexpr (FP4)
+                                    b = ring[u];
+                                else
+                                    b = widen_codes(ring[u]);
                                 // slot u takes unit ku + kRing of this block, or, after this
                                 // block's last unit of its residue class, unit u of the next block
                                 const int kn = ku + kRing;
-                                ring[u] = *reinterpret_cast<const v4i *>(kn < nku ? br + 32 * kn
-                                                                                : bn + 32 * min(u, nku - 1));
+                                ring[u] = load_global<Frag>(kn < nku ? br + (size_t)kUnit * kn
+                                                                     : bn + (size_t)kUnit * min(u, nku - 1));
 #pragma unroll
                                 for (int rb = 0; rb < RB; ++rb) {
                                     const v4i a = *reinterpret_cast<const v4i *>(abase + rb * 32 * pitch + 32 * ku);
@@ -554,7 +608,7 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
                     // consecutive sites of one replica row (two nibble bytes with FP4).
                     // Padding sites may take any value: their couplings and fields are
                     // zero and they are never returned.
-                    const int hval = hs[site];  // site < ns_p: padded fields are zero
+                    const int hval = load_global<int8_t>(hs + site);  // site < ns_p: padded fields are zero
                     const bool site_ok = site < ns;
                     const int flo = -top - hval, fhi = top - hval;  // F range whose F + h is in [-top, top]
                     const int base8 = 8 * (hval + top);
@@ -570,7 +624,9 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
                             uint32_t sgn[4];  // 1: the replica's new spin is -1
 #pragma unroll
                             for (int p = 0; p < 4; ++p) {
-                                const int F = (int)acc[rb][4 * q + p];  // an exact integer
+                                // an exact integer; with codes of J + 1 the product exceeds the
+                                // field by the replica's spin sum over the other side
+                                const int F = FP4 ? (int)acc[rb][4 * q + p] : (int)acc[rb][4 * q + p] - mag[r4 + p];
                                 const int Fc = min(max(F, flo), fhi);
                                 const uint64_t S = *static_cast<const uint64_t *>(
                                     __builtin_assume_aligned(Sb + 8 * Fc + base8, 8));

@@ -58,6 +58,16 @@ __device__ __forceinline__ int8_t decide(int32_t I, uint32_t T, uint32_t w)
 // compiler's intrinsic, bound by name: hip exposes no builtin for it).
 __device__ int lane_write(int val, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
 
+// A load from global memory through a pointer the compiler cannot place (one read
+// out of a job descriptor, say): issued as a global load, counted by vmcnt alone.
+// Through a generic pointer it would be a flat load, which also counts against
+// lgkmcnt, so that every wait for an LDS read would wait for it as well.
+template <typename T>
+__device__ __forceinline__ T load_global(const void *p)
+{
+    return *(const __attribute__((address_space(1))) T *)p;
+}
+
 typedef int v4i_t __attribute__((ext_vector_type(4)));
 
 // Spin bits widened for the int8 MFMA: the K bytes that lane half g of a 32x32x32

@@ -385,13 +385,37 @@ static int load_biclique(pbit_ctx *ctx, const pbit_problem_desc *d, Problem &p)
         if (rc == PBIT_OK) rc = upload(ctx, p, hA2.data(), sizeof(int32_t) * hA2.size(), &dhA2);
         if (rc == PBIT_OK) rc = upload(ctx, p, hB2.data(), sizeof(int32_t) * hB2.size(), &dhB2);
     }
+    void *dJ2 = nullptr, *dJT2 = nullptr;
+    if (rc == PBIT_OK) {
+        // two-bit couplings for the batched int8 tiles: J + 1 in {0, 1, 2}, padding included
+        // (J = 0 there, so the code is 1: the tiles subtract every spin of the other side,
+        // and padding spins take arbitrary values after the first update), 16 per word in
+        // fragment order: word ((blk nku + u) 2 + g) 32 + l holds row 32 blk + l, columns
+        // 32 u + 16 g + 4 j + i, as bits 2 j (low) and 2 j + 1 (high) of byte i
+        auto pack2 = [](const std::vector<int8_t> &M, int rows, int cols, std::vector<uint32_t> &out) {
+            const int nku = cols / 32;
+            out.assign((size_t)rows * cols / 16, 0u);
+            for (int r = 0; r < rows; ++r)
+                for (int c = 0; c < cols; ++c) {
+                    const uint32_t v = (uint32_t)(M[(size_t)r * cols + c] + 1);
+                    const int blk = r / 32, l = r % 32, u = c / 32, g = (c / 16) % 2, j = (c / 4) % 4, i = c % 4;
+                    out[(((size_t)blk * nku + u) * 2 + g) * 32 + l] |= v << (8 * i + 2 * j);
+                }
+        };
+        std::vector<uint32_t> J2, JT2;
+        pack2(J, na_p, nb_p, J2);
+        pack2(JT, nb_p, na_p, JT2);
+        rc = upload(ctx, p, J2.data(), sizeof(uint32_t) * J2.size(), &dJ2);
+        if (rc == PBIT_OK) rc = upload(ctx, p, JT2.data(), sizeof(uint32_t) * JT2.size(), &dJT2);
+    }
     if (rc != PBIT_OK) return rc;
     p.kind = PBIT_BICLIQUE;
     p.N = (int64_t)na + nb;
     p.amax = amax;
     p.bq = BqView{na, nb, na_p, nb_p, (const int8_t *)dJ, (const int8_t *)dJT, (const int8_t *)dhA,
                   (const int8_t *)dhB, (const uint8_t *)dJ4, (const uint8_t *)dJT4, pad == kBqPadLarge,
-                  (const int8_t *)dJb, (const int8_t *)dJTb, (const int32_t *)dhA2, (const int32_t *)dhB2};
+                  (const int8_t *)dJb, (const int8_t *)dJTb, (const int32_t *)dhA2, (const int32_t *)dhB2,
+                  (const uint32_t *)dJ2, (const uint32_t *)dJT2};
     return PBIT_OK;
 }
 

@@ -330,7 +330,8 @@ static int launch_round(pbit_ctx *ctx, ServeState &s)
         } else {
             const BqView &v = j->P->bq;
             const int k = kind_of_rs(j->rs);
-            BqJobDev jd{v.J, v.JT, v.J4, v.JT4, v.Jb, v.JTb, v.hA2, v.hB2, v.hA, v.hB, (const uint32_t *)j->d_table, (uint8_t *)j->d_state,
+            BqJobDev jd{v.J, v.JT, v.J4, v.JT4, v.Jb, v.JTb, v.hA2, v.hB2, v.J2, v.JT2, v.hA, v.hB,
+                        (const uint32_t *)j->d_table, (uint8_t *)j->d_state,
                         (int32_t *)j->d_energy, v.na, v.nb, v.na_p, v.nb_p, j->width,
                         (uint32_t)j->d.sweep_offset, (uint32_t)j->d.replica_offset >> 2, key.k0, key.k1};
             const int idx = (int)bq[k - 1].size();
