@@ -106,25 +106,41 @@ __global__ __launch_bounds__(kEaTileThreads) void k_ea_tiles(const EaJobDev *__r
             if (tid < kFieldSlots) {
                 const uint32_t *trow = jb.table + (size_t)s * jb.width;
                 const int I = tid - kFieldOff;
-                const uint32_t T = trow[min(I >= 0 ? I : -I, jb.width - 1)];
+                const uint32_t T = load_global<uint32_t>(trow + min(I >= 0 ? I : -I, jb.width - 1));
                 stab[tid] = I >= 0 ? (uint64_t)T : ((uint64_t)1 << 32) - T;
             }
             __syncthreads();
             const uint32_t t = jb.sweep0 + (uint32_t)s;
             for (int c = 0; c < 2; ++c) {
-                for (int j = tid; j < half; j += kEaTileThreads) {
-                    int kx, y;
+                // site j of the colour class: lattice coordinates and index
+                auto locate = [&](int j, int &x, int &y, int &z) {
+                    int kx;
                     const int row = div_small(j, hx, inv_hx, kx);
-                    const int z = div_small(row, Ly, inv_Ly, y);
-                    const int x = 2 * kx + ((c + y + z) & 1);
-                    const int i = x + Lx * y + plane * z;
+                    z = div_small(row, Ly, inv_Ly, y);
+                    x = 2 * kx + ((c + y + z) & 1);
+                    return x + Lx * y + plane * z;
+                };
+                // the site code of the next iteration is loaded one iteration ahead (a global
+                // load: the LDS reads of this iteration do not wait for it)
+                int x = 0, y = 0, z = 0, i = 0;
+                uint32_t code = 0u;
+                if (tid < half) {
+                    i = locate(tid, x, y, z);
+                    code = load_global<uint32_t>(jb.code + i);
+                }
+                for (int j = tid; j < half; j += kEaTileThreads) {
+                    int xn = 0, yn = 0, zn = 0, in = 0;
+                    uint32_t code_n = 0u;
+                    if (j + kEaTileThreads < half) {
+                        in = locate(j + kEaTileThreads, xn, yn, zn);
+                        code_n = load_global<uint32_t>(jb.code + in);
+                    }
                     const int nb[6] = {x + 1 == Lx ? i - x : i + 1,
                                        x == 0 ? i + Lx - 1 : i - 1,
                                        y + 1 == Ly ? i - y * Lx : i + Lx,
                                        y == 0 ? i + (Ly - 1) * Lx : i - Lx,
                                        z + 1 == Lz ? i - z * plane : i + plane,
                                        z == 0 ? i + (Lz - 1) * plane : i - plane};
-                    const uint32_t code = jb.code[i];
                     const Block4 b = philox((uint32_t)i, t, rg, kDomainSweep, jb.k0, jb.k1);
                     uint32_t idx = __builtin_amdgcn_perm(0u, code, 0x03030303u);  // base byte in every byte
 #pragma unroll
@@ -143,6 +159,11 @@ __global__ __launch_bounds__(kEaTileThreads) void k_ea_tiles(const EaJobDev *__r
                     const uint32_t lo = __builtin_amdgcn_perm(sgn[1], sgn[0], 0x0C0C0400u);
                     const uint32_t hi = __builtin_amdgcn_perm(sgn[3], sgn[2], 0x0C0C0400u);
                     sp[i] = __builtin_amdgcn_perm(0u, 0xFF01u, __builtin_amdgcn_perm(hi, lo, 0x05040100u));
+                    i = in;
+                    x = xn;
+                    y = yn;
+                    z = zn;
+                    code = code_n;
                 }
                 __syncthreads();
             }
@@ -157,7 +178,7 @@ __global__ __launch_bounds__(kEaTileThreads) void k_ea_tiles(const EaJobDev *__r
             int x, y;
             const int row = div_small(i, Lx, inv_Lx, x);
             const int z = div_small(row, Ly, inv_Ly, y);
-            const uint32_t code = jb.code[i];
+            const uint32_t code = load_global<uint32_t>(jb.code + i);
             const int nnz = __builtin_popcount(code & 63u);
             const int hv = (int)(int8_t)(code >> kCodeBaseShift) - nnz;
             const uint32_t mi = sp[i];
