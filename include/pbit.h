@@ -150,7 +150,7 @@ typedef struct {
     const double *beta;       /* [n_sweeps]: beta[s] is used for sweep sweep_offset + s; finite, >= 0 */
     int32_t n_sweeps;         /* >= 0 */
     int32_t sweep_offset;     /* >= 0: absolute index of the first sweep (resume) */
-    int32_t n_replicas;       /* >= 1 */
+    int32_t n_replicas;       /* 1 .. 2^30 */
     int32_t replica_offset;   /* >= 0, multiple of 4: global index of replica 0 (slicing) */
     uint64_t seed;
     const int8_t *init_spins; /* host [R][N] +-1, or NULL for the Philox random start */

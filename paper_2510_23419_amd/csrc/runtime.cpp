@@ -689,7 +689,8 @@ int check_desc(const pbit_anneal_desc *d, const char *who)
     if (d->n_sweeps < 0 || d->sweep_offset < 0) return fail(PBIT_E_ARG, "%s: sweep count and offset must be >= 0", who);
     if ((int64_t)d->sweep_offset + d->n_sweeps > (int64_t)UINT32_MAX)
         return fail(PBIT_E_ARG, "%s: sweep index exceeds 32 bits", who);
-    if (d->n_replicas < 1) return fail(PBIT_E_ARG, "%s: n_replicas must be >= 1", who);
+    if (d->n_replicas < 1 || d->n_replicas > (1 << 30))
+        return fail(PBIT_E_ARG, "%s: n_replicas must be in [1, 2^30]", who);
     if (d->replica_offset < 0 || d->replica_offset % 4 != 0)
         return fail(PBIT_E_ARG, "%s: replica_offset must be a non-negative multiple of 4", who);
     if (d->n_sweeps > 0 && !d->beta) return fail(PBIT_E_ARG, "%s: beta is NULL", who);
@@ -791,6 +792,10 @@ static int prepare(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, h
     void *v = nullptr;
     int rc;
     if (P.kind == PBIT_EA3D || P.kind == PBIT_GRAPH) {
+        // the stencil and the gather address the spin matrix with 32-bit byte offsets
+        if ((uint64_t)P.N * (((uint64_t)R + kEaRPad - 1) / kEaRPad * kEaRPad) >= ((uint64_t)1 << 32))
+            return fail(PBIT_E_UNSUPPORTED, "%lld spins x %d replicas exceed 4 GiB of int8 spins",
+                        (long long)P.N, R);
         ds.Rp = round_up(R, kEaRPad);
         rc = scratch(ctx, Slot::Spins, (size_t)P.N * ds.Rp, &v);
         if (rc) return rc;

@@ -224,6 +224,12 @@ def test_errors_leave_state_untouched(ctx):
     with pytest.raises(pbit.PbitError) as ei:
         pbit.pbit_anneal(ctx, prob, [0.5], 4, seed=1)
     assert ei.value.code == pbit.PBIT_E_HANDLE
+    # a spin matrix beyond the kernels' 32-bit offsets is refused before anything is allocated
+    big = pbit.load_instance(ctx, synth.ferro_ea(102))  # 1,061,208 spins
+    with pytest.raises(pbit.PbitError) as ei:
+        pbit.pbit_anneal(ctx, big, [0.5], 4096, seed=1)
+    assert ei.value.code == pbit.PBIT_E_UNSUPPORTED
+    pbit.pbit_unload_problem(ctx, big)
     # the context still works
     prob = pbit.load_instance(ctx, synth.ea_instance(4, seed=1))
     assert pbit.pbit_anneal(ctx, prob, [0.5], 4, seed=1).spins.shape == (4, 64)
