@@ -17,6 +17,7 @@ struct EaJobDev {
     int8_t *state;          // [tiles][N][4]: spins of a tile, replica fastest
     int32_t *energy;        // [tiles * 4]: energies after the tile's last item
     int Lx, Ly, Lz, width;
+    int dense;              // 1: every coupling is nonzero
     uint32_t sweep0;        // absolute index of local sweep 0
     uint32_t rq0;           // global replica group of tile 0 (replica_offset / 4)
     uint32_t k0, k1;        // Philox key

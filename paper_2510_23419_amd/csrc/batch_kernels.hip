@@ -111,30 +111,17 @@ __global__ __launch_bounds__(kEaTileThreads) void k_ea_tiles(const EaJobDev *__r
             }
             __syncthreads();
             const uint32_t t = jb.sweep0 + (uint32_t)s;
-            for (int c = 0; c < 2; ++c) {
-                // site j of the colour class: lattice coordinates and index
-                auto locate = [&](int j, int &x, int &y, int &z) {
-                    int kx;
-                    const int row = div_small(j, hx, inv_hx, kx);
-                    z = div_small(row, Ly, inv_Ly, y);
-                    x = 2 * kx + ((c + y + z) & 1);
-                    return x + Lx * y + plane * z;
-                };
-                // the site code of the next iteration is loaded one iteration ahead (a global
-                // load: the LDS reads of this iteration do not wait for it)
-                int x = 0, y = 0, z = 0, i = 0;
-                uint32_t code = 0u;
-                if (tid < half) {
-                    i = locate(tid, x, y, z);
-                    code = load_global<uint32_t>(jb.code + i);
-                }
+            // one colour class: DENSE (every coupling nonzero) drops the per-bond keep masks
+            auto half_sweep = [&](int c, auto dense_tag) {
+                constexpr bool DENSE = decltype(dense_tag)::value;
                 for (int j = tid; j < half; j += kEaTileThreads) {
-                    int xn = 0, yn = 0, zn = 0, in = 0;
-                    uint32_t code_n = 0u;
-                    if (j + kEaTileThreads < half) {
-                        in = locate(j + kEaTileThreads, xn, yn, zn);
-                        code_n = load_global<uint32_t>(jb.code + in);
-                    }
+                    int kx, y;
+                    const int row = div_small(j, hx, inv_hx, kx);
+                    const int z = div_small(row, Ly, inv_Ly, y);
+                    const int x = 2 * kx + ((c + y + z) & 1);
+                    const int i = x + Lx * y + plane * z;
+                    // a global load: the LDS reads below do not wait for it
+                    const uint32_t code = load_global<uint32_t>(jb.code + i);
                     const int nb[6] = {x + 1 == Lx ? i - x : i + 1,
                                        x == 0 ? i + Lx - 1 : i - 1,
                                        y + 1 == Ly ? i - y * Lx : i + Lx,
@@ -146,7 +133,7 @@ __global__ __launch_bounds__(kEaTileThreads) void k_ea_tiles(const EaJobDev *__r
 #pragma unroll
                     for (int d = 0; d < 6; ++d) {
                         const uint32_t F = bit_mask(code, kCodeFlipShift + d);
-                        const uint32_t K = bit_mask(code, d) & 0x10101010u;
+                        const uint32_t K = DENSE ? 0x10101010u : (bit_mask(code, d) & 0x10101010u);
                         idx += __builtin_amdgcn_bitop3_b32(sp[nb[d]], F, K, 0x82);  // ~(a ^ b) & c
                     }
                     uint32_t sgn[4];  // 1: the replica's new spin is -1
@@ -159,12 +146,13 @@ __global__ __launch_bounds__(kEaTileThreads) void k_ea_tiles(const EaJobDev *__r
                     const uint32_t lo = __builtin_amdgcn_perm(sgn[1], sgn[0], 0x0C0C0400u);
                     const uint32_t hi = __builtin_amdgcn_perm(sgn[3], sgn[2], 0x0C0C0400u);
                     sp[i] = __builtin_amdgcn_perm(0u, 0xFF01u, __builtin_amdgcn_perm(hi, lo, 0x05040100u));
-                    i = in;
-                    x = xn;
-                    y = yn;
-                    z = zn;
-                    code = code_n;
                 }
+            };
+            for (int c = 0; c < 2; ++c) {
+                if (jb.dense)
+                    half_sweep(c, std::true_type{});
+                else
+                    half_sweep(c, std::false_type{});
                 __syncthreads();
             }
         }

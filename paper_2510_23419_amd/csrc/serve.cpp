@@ -318,7 +318,7 @@ static int launch_round(pbit_ctx *ctx, ServeState &s)
         if (j->kind == PBIT_EA3D) {
             const EaView &v = j->P->ea;
             EaJobDev jd{v.code, (const uint32_t *)j->d_table, (int8_t *)j->d_state, (int32_t *)j->d_energy,
-                        v.Lx, v.Ly, v.Lz, j->width, (uint32_t)j->d.sweep_offset,
+                        v.Lx, v.Ly, v.Lz, j->width, v.dense ? 1 : 0, (uint32_t)j->d.sweep_offset,
                         (uint32_t)j->d.replica_offset >> 2, key.k0, key.k1};
             const int idx = (int)ea.size();
             ea.push_back(jd);
