@@ -261,6 +261,13 @@ int pbit_profile_read(pbit_ctx *ctx, int32_t kind, double *total_ms, int64_t *la
  * created.  *variant is written on success only. */
 int pbit_profile_variant(pbit_ctx *ctx, int32_t *variant);
 
+/* The cube path of the latest cube anneal on this context (0 before any): 1 = the
+ * streaming stencil, one launch per half-sweep; 2 = the LDS-resident form, the
+ * whole lattice of 16 replicas per workgroup for runs of sweeps, taken for
+ * cubes of at most 8192 sites unless PBIT_EA_STREAM=1 was set when the context
+ * was created.  Both give the same spins.  *path is written on success only. */
+int pbit_profile_ea_path(pbit_ctx *ctx, int32_t *path);
+
 /* ---- host-side helpers (no GPU needed) ---------------------------------- */
 
 /* The uint32 minority-threshold table Tm[s][a], s < S, a <= A, as the library

@@ -196,6 +196,118 @@ __global__ __launch_bounds__(kThreads) void k_ea_halfsweep(int8_t *__restrict__ 
     }
 }
 
+// The half-sweeps of a small cube, resident in LDS (the stencil's LDS-staged
+// form): a workgroup holds 16 replicas (one chunk of the [N][Rp] layout) of the
+// whole lattice, 16 bytes per site, and runs a range of sweeps with workgroup
+// barriers between the half-sweeps, so that no sweep needs a launch or touches
+// HBM.  A thread takes the same sites in every sweep, one at a time with the
+// chunk's 16 replicas, as in the streaming kernel (same field bytes, Philox
+// counters and carry decision), reading the six neighbour rows from LDS; it
+// keeps each site's index, periodic-wrap flags and code in registers.  The
+// decision words of a sweep come from its threshold row, loaded one sweep ahead.
+constexpr int kSlabThreads = 512;
+constexpr int kSlabPer = kEaSlabMaxSites / 2 / kSlabThreads;  // sites of a colour per thread
+
+template <bool DENSE>
+__global__ __launch_bounds__(kSlabThreads) void k_ea_slab(int8_t *__restrict__ spins,
+                                                        const uint32_t *__restrict__ code,
+                                                        const uint32_t *__restrict__ table, int width, int Lx,
+                                                        int Ly, int Lz, int Rp, int s_begin, int s_end,
+                                                        uint32_t sweep0, uint32_t rq0, uint32_t k0, uint32_t k1,
+                                                        uint32_t one)
+{
+    extern __shared__ uint4 rows[];  // [N]: the chunk's 16 replicas of every site
+    __shared__ uint64_t stab[kFieldSlots];
+    const int tid = threadIdx.x;
+    const int q = blockIdx.x;  // chunk of 16 replicas
+    const int plane = Lx * Ly, N = plane * Lz, half = N / 2, hx = Lx / 2;
+    for (int i = tid; i < N; i += kSlabThreads)
+        rows[i] = *reinterpret_cast<const uint4 *>(spins + (size_t)i * Rp + 16 * q);
+    // this thread's sites of each colour: index (low 16 bits) and the wrap flags of
+    // the +x, -x, +y, -y, +z, -z neighbours (bits 16..21), and the site code
+    uint32_t site[2][kSlabPer], cw[2][kSlabPer];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int k = 0; k < kSlabPer; ++k) {
+            const int j = tid + kSlabThreads * k;
+            site[c][k] = 0u;
+            cw[c][k] = 0u;
+            if (j < half) {
+                const int kx = j % hx, row = j / hx;
+                const int y = row % Ly, z = row / Ly;
+                const int x = 2 * kx + ((c + y + z) & 1);
+                const int i = x + Lx * y + plane * z;
+                const uint32_t wrap = (x + 1 == Lx ? 1u : 0u) | (x == 0 ? 2u : 0u) | (y + 1 == Ly ? 4u : 0u) |
+                                      (y == 0 ? 8u : 0u) | (z + 1 == Lz ? 16u : 0u) | (z == 0 ? 32u : 0u);
+                site[c][k] = (uint32_t)i | wrap << 16;
+                cw[c][k] = code[i];
+            }
+        }
+    // neighbour d of site i: i + step[d], or i + step[d] + fix[d] across the boundary
+    const int step[6] = {1, -1, Lx, -Lx, plane, -plane};
+    const int fix[6] = {-Lx, Lx, -plane, plane, -N, N};
+    const uint32_t rg4 = rq0 + 4u * (uint32_t)q;  // Philox counter word 2 of the chunk's first group
+    const char *tb = reinterpret_cast<const char *>(stab);
+    const int tix = min(tid >= kFieldOff ? tid - kFieldOff : kFieldOff - tid, width - 1);  // |I| of entry tid
+    uint32_t tnext = 0u;
+    if (tid < kFieldSlots && s_begin < s_end) tnext = table[(size_t)s_begin * width + tix];
+    for (int s = s_begin; s < s_end; ++s) {
+        __syncthreads();
+        if (tid < kFieldSlots) {
+            stab[tid] = tid >= kFieldOff ? (uint64_t)tnext : ((uint64_t)1 << 32) - tnext;
+            if (s + 1 < s_end) tnext = table[(size_t)(s + 1) * width + tix];
+        }
+        __syncthreads();
+        const uint32_t t = sweep0 + (uint32_t)s;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+#pragma unroll
+            for (int k = 0; k < kSlabPer; ++k) {
+                if (tid + kSlabThreads * k >= half) break;
+                const int i = (int)(site[c][k] & 0xFFFFu);
+                const uint32_t wrap = site[c][k] >> 16, w = cw[c][k];
+                uint4 v[6];
+#pragma unroll
+                for (int d = 0; d < 6; ++d) v[d] = rows[i + step[d] + (((wrap >> d) & 1u) ? fix[d] : 0)];
+                Block4 b[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) b[r] = philox((uint32_t)i, t, rg4 + (uint32_t)r, kDomainSweep, k0, k1);
+                uint32_t tt[6][4];
+#pragma unroll
+                for (int d = 0; d < 6; ++d) {
+                    const uint32_t F = bit_mask(w, kCodeFlipShift + d);
+                    const uint32_t K = DENSE ? 0x10101010u : (bit_mask(w, d) & 0x10101010u);
+                    tt[d][0] = __builtin_amdgcn_bitop3_b32(v[d].x, F, K, 0x82);  // ~(a ^ b) & c
+                    tt[d][1] = __builtin_amdgcn_bitop3_b32(v[d].y, F, K, 0x82);
+                    tt[d][2] = __builtin_amdgcn_bitop3_b32(v[d].z, F, K, 0x82);
+                    tt[d][3] = __builtin_amdgcn_bitop3_b32(v[d].w, F, K, 0x82);
+                }
+                const uint32_t pos8 = __builtin_amdgcn_perm(0u, w, 0x03030303u);  // base byte in every byte
+                uint32_t out[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const uint32_t idx = (tt[0][r] + tt[1][r] + tt[2][r]) + (tt[3][r] + tt[4][r] + tt[5][r]) + pos8;
+                    uint32_t sgn[4];  // 1: the replica's new spin is -1
+#pragma unroll
+                    for (int p = 0; p < 4; ++p) {
+                        const uint64_t S = *static_cast<const uint64_t *>(
+                            __builtin_assume_aligned(tb + ((idx >> (8 * p)) & 0xFFu), 8));
+                        sgn[p] = (uint32_t)(((uint64_t)b[r].w[p] * one + S) >> 32);
+                    }
+                    const uint32_t lo = __builtin_amdgcn_perm(sgn[1], sgn[0], 0x0C0C0400u);
+                    const uint32_t hi = __builtin_amdgcn_perm(sgn[3], sgn[2], 0x0C0C0400u);
+                    out[r] = __builtin_amdgcn_perm(0u, 0xFF01u, __builtin_amdgcn_perm(hi, lo, 0x05040100u));
+                }
+                rows[i] = make_uint4(out[0], out[1], out[2], out[3]);
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = tid; i < N; i += kSlabThreads)
+        *reinterpret_cast<uint4 *>(spins + (size_t)i * Rp + 16 * q) = rows[i];
+}
+
 // From-scratch energy (Eq. 1 with the field): E[r] = -sum_bonds J m_i m_j - sum_i h_i m_i,
 // each bond (i, i + e_d) visited once, from its lower-end site i.  With d = 1 where two
 // spins differ (bit 1 of the xor of their bytes) and b = 1 where a spin is -1,
@@ -324,6 +436,34 @@ hipError_t ea_halfsweep(const EaView &p, int8_t *spins, int Rp, int colour, cons
         if (early_rng) PBIT_EA_LAUNCH(false, true); else PBIT_EA_LAUNCH(false, false);
     }
 #undef PBIT_EA_LAUNCH
+    return hipGetLastError();
+}
+
+bool ea_slab_fits(const EaView &p) { return p.N <= kEaSlabMaxSites; }
+
+hipError_t ea_slab(const EaView &p, int8_t *spins, int Rp, const uint32_t *table, int width, int s_begin, int s_end,
+                   uint32_t sweep0, uint32_t rq0, Key key, hipStream_t st)
+{
+    if (!ea_slab_fits(p) || Rp % 16 != 0 || width < 1 || s_end < s_begin) return hipErrorInvalidValue;
+    if (s_end == s_begin) return hipSuccess;
+    const size_t lds = sizeof(uint4) * (size_t)p.N;
+    static const hipError_t lds_attr = [] {
+        const int bytes = (int)sizeof(uint4) * kEaSlabMaxSites;
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ea_slab<true>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ea_slab<false>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        return e;
+    }();
+    if (lds_attr != hipSuccess) return lds_attr;
+    const dim3 grid((unsigned)(Rp / 16));
+    if (p.dense)
+        hipLaunchKernelGGL((k_ea_slab<true>), grid, dim3(kSlabThreads), lds, st, spins, p.code, table, width, p.Lx, p.Ly,
+                           p.Lz, Rp, s_begin, s_end, sweep0, rq0, key.k0, key.k1, 1u);
+    else
+        hipLaunchKernelGGL((k_ea_slab<false>), grid, dim3(kSlabThreads), lds, st, spins, p.code, table, width, p.Lx,
+                           p.Ly, p.Lz, Rp, s_begin, s_end, sweep0, rq0, key.k0, key.k1, 1u);
     return hipGetLastError();
 }
 

@@ -57,6 +57,12 @@ struct EaRow {
 };
 EaRow ea_row(const uint32_t *host_trow, int width);
 // ny: lattice rows per workgroup (0 = choose); early_rng: draw the random words before the field
+// Sweeps [s_begin, s_end) of a cube of at most kEaSlabMaxSites sites held in LDS,
+// 16 replicas per workgroup; table row s is sweep s, its absolute index sweep0 + s.
+constexpr int kEaSlabMaxSites = 8192;
+bool ea_slab_fits(const EaView &p);
+hipError_t ea_slab(const EaView &p, int8_t *spins, int Rp, const uint32_t *table, int width, int s_begin, int s_end,
+                   uint32_t sweep0, uint32_t rq0, Key key, hipStream_t st);
 hipError_t ea_halfsweep(const EaView &p, int8_t *spins, int Rp, int colour, const EaRow &row, uint32_t sweep,
                         uint32_t rq0, Key key, hipStream_t st, int ny = 0, bool early_rng = true);
 hipError_t ea_energy(const EaView &p, const int8_t *spins, int Rp, int R, int32_t *E, hipStream_t st);

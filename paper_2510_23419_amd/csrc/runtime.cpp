@@ -190,6 +190,7 @@ extern "C" int pbit_create(pbit_ctx **out, int device, uint64_t hbm_budget_bytes
         const int k = std::atoi(v);
         if (k >= 1 && k <= 8) ctx->bq_forced = (BqVariant)k;
     }
+    if (const char *v = std::getenv("PBIT_EA_STREAM")) ctx->ea_stream_forced = std::atoi(v) != 0;
     ctx->serial = g_ctx_serial.fetch_add(1);
     e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
@@ -722,7 +723,10 @@ struct DevState {
     int32_t *E32 = nullptr;
     int8_t *stage = nullptr;  // [R][N] host-layout staging
     BqVariant variant = BqVariant::Auto;
+    bool slab = false;        // cube held in LDS for runs of sweeps (ea_slab)
 };
+
+constexpr int kSlabChunk = 1000;  // sweeps per launch of the LDS-resident cube kernel
 
 // Pick the biclique kernel variant for this shape: the forced one, a cached
 // choice, or the fastest of the candidates timed here on the (not yet
@@ -856,6 +860,8 @@ static int prepare(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, h
         if (rc) return rc;
     }
     ds.bits = P.kind == PBIT_BICLIQUE && ds.variant == BqVariant::Bits;
+    ds.slab = P.kind == PBIT_EA3D && ea_slab_fits(P.ea) && !ctx->ea_stream_forced;
+    if (P.kind == PBIT_EA3D && d->n_sweeps > 0) ctx->ea_last_path = ds.slab ? 2 : 1;
     if (P.kind == PBIT_BICLIQUE && d->n_sweeps > 0) ctx->bq_last_variant = (int)ds.variant;
 
     const Key key{(uint32_t)d->seed, (uint32_t)(d->seed >> 32)};
@@ -911,6 +917,29 @@ static hipError_t sweep(pbit_ctx *ctx, const Problem &P, DevState &ds, int s, ui
     return e;
 }
 
+// Sweeps [s0, s1): one launch of the LDS-resident cube kernel, or a launch per
+// half-sweep.  A timing window brackets the resident launch, counted as its half-sweeps.
+static hipError_t sweeps(pbit_ctx *ctx, const Problem &P, DevState &ds, int s0, int s1, uint32_t sweep0,
+                         uint32_t rq0, Key key, hipStream_t st)
+{
+    if (!ds.slab) {
+        for (int s = s0; s < s1; ++s) {
+            hipError_t e = sweep(ctx, P, ds, s, sweep0 + (uint32_t)s, rq0, key, st);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    hipError_t e = hipSuccess;
+    const bool timed = ctx->prof_every > 0 && ctx->prof_open < 0;
+    if (timed) e = prof_begin(ctx, P.kind, st);
+    if (e == hipSuccess) e = ea_slab(P.ea, ds.spins, ds.Rp, ds.table, ds.width, s0, s1, sweep0, rq0, key, st);
+    if (e == hipSuccess && timed) {
+        ctx->prof_launches.back() += 2 * (s1 - s0);
+        e = prof_close(ctx, st);
+    }
+    return e;
+}
+
 static hipError_t energies(const Problem &P, DevState &ds, hipStream_t st)
 {
     if (P.kind == PBIT_GRAPH) return graph_energy(P.graph, ds.spins, ds.Rp, ds.R, ds.E32, st);
@@ -960,10 +989,14 @@ int run_blocking(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, pbi
     std::vector<int32_t> e32;
     int done = 0, trace_len = 0;
     bool hit = false;
-    for (int s = 0; s < d->n_sweeps && !hit; ++s) {
-        hipError_t e = sweep(ctx, P, ds, s, (uint32_t)(d->sweep_offset + s), rq0, key, st);
+    for (int s = 0; s < d->n_sweeps && !hit;) {
+        // up to the next energy check (every sweep on the per-half-sweep path)
+        int s1 = ds.slab ? std::min(d->n_sweeps, s + kSlabChunk) : s + 1;
+        if (check > 0) s1 = std::min(s1, (s / check + 1) * check);
+        hipError_t e = sweeps(ctx, P, ds, s, s1, (uint32_t)d->sweep_offset, rq0, key, st);
         if (e != hipSuccess) return device_fail(ctx, e, "sweep launch");
-        done = s + 1;
+        s = s1;
+        done = s;
         if (check > 0 && done % check == 0) {
             rc = fetch_energies(ctx, P, ds, st, e32);
             if (rc) return rc;
@@ -1017,9 +1050,11 @@ int run_device(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, int8_
     if (rc) return rc;
     const Key key{(uint32_t)d->seed, (uint32_t)(d->seed >> 32)};
     const uint32_t rq0 = (uint32_t)d->replica_offset >> 2;
-    for (int s = 0; s < d->n_sweeps; ++s) {
-        hipError_t e = sweep(ctx, P, ds, s, (uint32_t)(d->sweep_offset + s), rq0, key, st);
+    for (int s = 0; s < d->n_sweeps;) {
+        const int s1 = ds.slab ? std::min(d->n_sweeps, s + kSlabChunk) : s + 1;
+        hipError_t e = sweeps(ctx, P, ds, s, s1, (uint32_t)d->sweep_offset, rq0, key, st);
         if (e != hipSuccess) return device_fail(ctx, e, "sweep launch");
+        s = s1;
     }
     hipError_t e = prof_close(ctx, st);  // a timing window covers sweep launches only
     if (e == hipSuccess) e = to_rows(P, ds, d_spins, st);
@@ -1187,6 +1222,14 @@ extern "C" int pbit_profile_variant(pbit_ctx *ctx, int32_t *variant)
     PBIT_ENTER(ctx);
     if (!variant) return fail(PBIT_E_ARG, "pbit_profile_variant: variant is NULL");
     *variant = ctx->bq_last_variant;
+    return PBIT_OK;
+}
+
+extern "C" int pbit_profile_ea_path(pbit_ctx *ctx, int32_t *path)
+{
+    PBIT_ENTER(ctx);
+    if (!path) return fail(PBIT_E_ARG, "pbit_profile_ea_path: path is NULL");
+    *path = ctx->ea_last_path;
     return PBIT_OK;
 }
 

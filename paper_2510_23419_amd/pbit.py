@@ -35,7 +35,8 @@ EXPORTS = ("pbit_create", "pbit_destroy", "pbit_last_error", "pbit_bytes_in_use"
            "pbit_unload_problem", "pbit_problem_spins", "pbit_anneal", "pbit_anneal_dev", "pbit_energy",
            "pbit_submit", "pbit_poll", "pbit_progress", "pbit_threshold_table", "pbit_version",
            "pbit_profile_enable", "pbit_profile_read", "pbit_anneal_batch", "pbit_serve_config",
-           "pbit_load_graph", "pbit_problem_colouring", "pbit_greedy_colouring", "pbit_profile_variant")
+           "pbit_load_graph", "pbit_problem_colouring", "pbit_greedy_colouring", "pbit_profile_variant",
+           "pbit_profile_ea_path")
 
 
 class PbitError(RuntimeError):
@@ -108,6 +109,7 @@ def lib() -> ctypes.CDLL:
             "pbit_profile_enable": ([P, i32], ctypes.c_int),
             "pbit_profile_read": ([P, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), i32], ctypes.c_int),
             "pbit_profile_variant": ([P, ctypes.POINTER(i32)], ctypes.c_int),
+            "pbit_profile_ea_path": ([P, ctypes.POINTER(i32)], ctypes.c_int),
             "pbit_anneal_batch": ([P, ctypes.POINTER(BatchJob), i32], ctypes.c_int),
             "pbit_serve_config": ([P, i32, i32, i32], ctypes.c_int),
             "pbit_load_graph": ([P, ctypes.POINTER(GraphDesc), ctypes.POINTER(u64)], ctypes.c_int),
@@ -341,6 +343,13 @@ def pbit_threshold_table(beta, A: int) -> np.ndarray:
     out = np.zeros((beta.size, int(A) + 1), np.uint32)
     _check(lib().pbit_threshold_table(_ptr(beta), beta.size, int(A), _ptr(out)))
     return out
+
+
+def pbit_profile_ea_path(ctx) -> int:
+    """Cube path of the latest cube anneal: 1 streaming stencil, 2 LDS-resident (0: none yet)."""
+    v = ctypes.c_int32(0)
+    _check(lib().pbit_profile_ea_path(ctx, ctypes.byref(v)))
+    return int(v.value)
 
 
 def pbit_submit(ctx, problem: int, beta, n_replicas: int, seed: int, sweep_offset: int = 0, replica_offset: int = 0,

@@ -1,6 +1,7 @@
 """Parity of the HIP path (through the C ABI) with the CPU oracle: bit-exact
 spins and energies, every replica after every sweep on the small cases, and
 sampled replicas at several sweep counts at the full benchmark sizes."""
+import os
 import sys
 
 import numpy as np
@@ -29,6 +30,30 @@ def ctx():
     c = pbit.Context(0)
     yield c.ctx
     c.close()
+
+
+@pytest.fixture(scope="module", params=["lds", "stream"])
+def ectx(request):
+    """A context per cube path: small cubes held in LDS for runs of sweeps (the
+    default), or every cube on the streaming stencil (PBIT_EA_STREAM=1)."""
+    old = os.environ.get("PBIT_EA_STREAM")
+    os.environ["PBIT_EA_STREAM"] = "1" if request.param == "stream" else "0"
+    try:
+        c = pbit.Context(0)
+    finally:
+        if old is None:
+            del os.environ["PBIT_EA_STREAM"]
+        else:
+            os.environ["PBIT_EA_STREAM"] = old
+    c.mode = request.param
+    yield c
+    c.close()
+
+
+def _check_path(c, inst):
+    """The cube path the latest anneal took is the one the context asks for."""
+    small = int(np.prod(inst["dims"])) <= 8192
+    assert pbit.pbit_profile_ea_path(c.ctx) == (2 if c.mode == "lds" and small else 1)
 
 
 def _ea_with_zeros(dims, seed):
@@ -82,19 +107,41 @@ def _every_sweep(ctx, inst, beta, R, seed, init=None):
     return got
 
 
-def test_ea_L6_every_replica_every_sweep(ctx):
+def test_ea_L6_every_replica_every_sweep(ectx):
     """EA L=6 (216 spins), +-1 couplings, h = 0, 64 replicas from random starts,
     beta linear 0.1 -> 3.0 over 1000 sweeps, seed 1."""
     inst = synth.ea_instance(6, seed=1)
-    _say("ea L=6 R=64 S=1000 every sweep")
-    _every_sweep(ctx, inst, synth.beta_linear(0.1, 3.0, 1000), 64, seed=1)
+    _say("ea L=6 R=64 S=1000 every sweep (%s)" % ectx.mode)
+    _every_sweep(ectx.ctx, inst, synth.beta_linear(0.1, 3.0, 1000), 64, seed=1)
+    _check_path(ectx, inst)
 
 
 @pytest.mark.parametrize("dims,R", [((2, 2, 2), 5), ((4, 6, 2), 33), ((10, 8, 6), 20)])
-def test_ea_ragged_with_fields_and_zero_couplings(ctx, dims, R):
+def test_ea_ragged_with_fields_and_zero_couplings(ectx, dims, R):
     inst = _ea_with_zeros(dims, seed=3 * R)
-    _say("ea ragged %s R=%d" % (dims, R))
-    _every_sweep(ctx, inst, synth.beta_geometric(0.1, 5.0, 40), R, seed=0xDEADBEEFCAFE)
+    _say("ea ragged %s R=%d (%s)" % (dims, R, ectx.mode))
+    _every_sweep(ectx.ctx, inst, synth.beta_geometric(0.1, 5.0, 40), R, seed=0xDEADBEEFCAFE)
+    _check_path(ectx, inst)
+
+
+@pytest.mark.parametrize("dims,R,S", [((2, 2, 2), 5, 2500), ((4, 6, 2), 33, 1500), ((20, 20, 20), 40, 30),
+                                      ((10, 8, 6), 4096, 300)])
+def test_ea_runs_of_sweeps(ectx, dims, R, S):
+    """Runs longer than one launch of the LDS-resident kernel, the largest cube it
+    takes, and a cube split over 256 workgroups; fields and zero couplings."""
+    inst = _ea_with_zeros(dims, seed=7 * R + S)
+    prob = pbit.load_instance(ectx.ctx, inst)
+    beta = synth.beta_geometric(0.1, 5.0, S)
+    _say("ea runs %s R=%d S=%d (%s)" % (dims, R, S, ectx.mode))
+    got = pbit.pbit_anneal(ectx.ctx, prob, beta, R, seed=21)
+    _check_path(ectx, inst)
+    g = graph_of(inst)
+    groups = range((R + 3) // 4) if R <= 64 else (0, 511, 1023)
+    for gi in groups:
+        ref = oracle.anneal(g, beta, min(4, R - 4 * gi), 21, replica_offset=4 * gi)
+        assert np.array_equal(got.spins[4 * gi:4 * gi + 4], ref.spins), gi
+        assert np.array_equal(got.energies[4 * gi:4 * gi + 4], ref.energies), gi
+    pbit.pbit_unload_problem(ectx.ctx, prob)
 
 
 @pytest.mark.parametrize("na,nb,R", [(40, 40, 70), (7, 130, 3), (130, 66, 129), (1, 1, 1)])
@@ -150,17 +197,20 @@ def test_resume_split_and_replica_slices(ctx, make):
     pbit.pbit_unload_problem(ctx, prob)
 
 
-def test_two_runs_are_identical(ctx):
+def test_two_runs_are_identical(ectx):
+    ctx = ectx.ctx
     inst = synth.ea_instance(16, seed=16)
     prob = pbit.load_instance(ctx, inst)
     beta = synth.beta_geometric(0.1, 5.0, 50)
     a = pbit.pbit_anneal(ctx, prob, beta, 256, seed=1)
     b = pbit.pbit_anneal(ctx, prob, beta, 256, seed=1)
     assert np.array_equal(a.spins, b.spins)
+    _check_path(ectx, inst)
     pbit.pbit_unload_problem(ctx, prob)
 
 
-def test_target_stops_at_first_reaching_sweep(ctx):
+def test_target_stops_at_first_reaching_sweep(ectx):
+    ctx = ectx.ctx
     inst = synth.ea_instance(6, seed=11)
     beta = synth.beta_linear(0.1, 3.0, 300)
     ref = oracle.anneal(graph_of(inst), beta, 16, seed=4, trace_every=1)
@@ -169,6 +219,7 @@ def test_target_stops_at_first_reaching_sweep(ctx):
     first = int(np.argmax(mins <= target)) + 1
     prob = pbit.load_instance(ctx, inst)
     got = pbit.pbit_anneal(ctx, prob, beta, 16, seed=4, target=target)
+    _check_path(ectx, inst)
     assert got.sweeps_done == first
     assert got.best_energy <= target
     pre = oracle.anneal(graph_of(inst), beta[:first], 16, seed=4)
@@ -176,9 +227,10 @@ def test_target_stops_at_first_reaching_sweep(ctx):
     pbit.pbit_unload_problem(ctx, prob)
 
 
-def test_anneal_dev_matches_blocking(ctx):
+def test_anneal_dev_matches_blocking(ectx):
     import torch
 
+    ctx = ectx.ctx
     for inst in (synth.ea_instance(8, seed=6), synth.biclique_instance(96, seed=6)):
         prob = pbit.load_instance(ctx, inst)
         N = pbit.pbit_problem_spins(ctx, prob)
@@ -269,12 +321,13 @@ def _check_sampled(ctx, inst, beta, R, seed, prefixes, full_groups, rng):
     pbit.pbit_unload_problem(ctx, prob)
 
 
-def test_ea_L16_full_size_sampled(ctx):
+def test_ea_L16_full_size_sampled(ectx):
     """L=16 cube, 4096 replicas, beta geometric 0.1 -> 5.0 over 10^4 sweeps."""
     inst = synth.ea_instance(16, seed=16)
     beta = synth.beta_geometric(0.1, 5.0, 10_000)
     rng = np.random.default_rng(16)
-    _check_sampled(ctx, inst, beta, 4096, 1, [1, 2, 10, 100, 1000, 10_000], [1023], rng)
+    _check_sampled(ectx.ctx, inst, beta, 4096, 1, [1, 2, 10, 100, 1000, 10_000], [1023], rng)
+    _check_path(ectx, inst)
 
 
 def test_ea_L32_full_size_sampled(ctx):
