@@ -465,7 +465,20 @@ def main():
 
     # roofline of the half-sweep kernel
     avg_ms = kern_ms / launches if launches else float("inf")
-    if w["kind"] == "ea3d":
+    ea_path = pbit.pbit_profile_ea_path(ctx.ctx) if w["kind"] == "ea3d" else 0
+    if ea_path == 2:
+        # the cube held in LDS for runs of sweeps: no HBM traffic per half-sweep, so the
+        # vector ALU is the roof; lane-ops per update from the committed counter run
+        rec = profile_record(args.workload)
+        lops = None
+        if rec and rec.get("valu_insts_per_dispatch"):
+            lops = float(rec["valu_insts_per_dispatch"]) * 64 / (N * R * rec["sweeps_per_dispatch"])
+        upd_per_s = (N * R / 2) / (avg_ms * 1e-3)  # updates per second inside the kernel
+        roof = {"bound": "alu", "achieved": None if lops is None else upd_per_s * lops / 1e12,
+                "peak": VALU_PEAK_TLANEOPS, "unit": "Tlane-op/s", "traffic": None, "kernel": "k_ea_slab",
+                "lane_ops_per_update": lops, "updates_per_s_in_kernel": upd_per_s,
+                "avg_halfsweep_us": avg_ms * 1e3, "halfsweeps_timed": launches}
+    elif w["kind"] == "ea3d":
         # per launch: N/2 x R updates, each reads its share of the other colour's
         # spins once (1 B) and writes its own spin (1 B); couplings ~0 B at R=4096
         alg_bytes = N * R + 4 * (N // 2)
@@ -493,9 +506,10 @@ def main():
     if launches == 0:  # launch timing switched off (--profile-every 0)
         roof["achieved"] = None
     roof["frac"] = None if roof["achieved"] is None else roof["achieved"] / roof["peak"]
-    roof["traffic"] = measured_traffic(args.workload)
+    if ea_path != 2:
+        roof["traffic"] = measured_traffic(args.workload)
     rec = profile_record(args.workload)
-    if rec and rec.get("valu_insts_per_dispatch") and launches:
+    if ea_path != 2 and rec and rec.get("valu_insts_per_dispatch") and launches:
         # vector ALU issue: wave instructions x 64 lanes per launch over the measured
         # launch time, against 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
         lane_ops = float(rec["valu_insts_per_dispatch"]) * 64
