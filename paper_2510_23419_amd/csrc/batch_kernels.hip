@@ -21,23 +21,6 @@ namespace {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-// q = n / d and r = n % d for 0 <= n < 2^22 and 1 <= d < 2^10 from a float
-// reciprocal: the estimate is within one of the quotient and is corrected.
-__device__ __forceinline__ int div_small(int n, int d, float inv, int &r)
-{
-    int q = (int)((float)n * inv);
-    int rr = n - q * d;
-    if (rr < 0) {
-        q -= 1;
-        rr += d;
-    } else if (rr >= d) {
-        q += 1;
-        rr -= d;
-    }
-    r = rr;
-    return q;
-}
-
 __device__ __forceinline__ int take_item(int32_t *counter, int *slot)
 {
     if (threadIdx.x == 0) *slot = atomicAdd(counter, 1);

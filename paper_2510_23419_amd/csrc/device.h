@@ -58,6 +58,23 @@ __device__ __forceinline__ int8_t decide(int32_t I, uint32_t T, uint32_t w)
 // compiler's intrinsic, bound by name: hip exposes no builtin for it).
 __device__ int lane_write(int val, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
 
+// q = n / d and r = n % d for 0 <= n < 2^22 and 1 <= d < 2^10 from a float
+// reciprocal: the estimate is within one of the quotient and is corrected.
+__device__ __forceinline__ int div_small(int n, int d, float inv, int &r)
+{
+    int q = (int)((float)n * inv);
+    int rr = n - q * d;
+    if (rr < 0) {
+        q -= 1;
+        rr += d;
+    } else if (rr >= d) {
+        q += 1;
+        rr -= d;
+    }
+    r = rr;
+    return q;
+}
+
 // A load from global memory through a pointer the compiler cannot place (one read
 // out of a job descriptor, say): issued as a global load, counted by vmcnt alone.
 // Through a generic pointer it would be a flat load, which also counts against

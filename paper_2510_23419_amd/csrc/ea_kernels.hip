@@ -200,17 +200,16 @@ __global__ __launch_bounds__(kThreads) void k_ea_halfsweep(int8_t *__restrict__ 
 // form): a workgroup holds 16 replicas (one chunk of the [N][Rp] layout) of the
 // whole lattice, 16 bytes per site, and runs a range of sweeps with workgroup
 // barriers between the half-sweeps, so that no sweep needs a launch or touches
-// HBM.  A thread takes the same sites in every sweep, one at a time with the
-// chunk's 16 replicas, as in the streaming kernel (same field bytes, Philox
-// counters and carry decision), reading the six neighbour rows from LDS; it
-// keeps each site's index, periodic-wrap flags and code in registers.  The
-// decision words of a sweep come from its threshold row, loaded one sweep ahead.
+// HBM.  A thread takes one site at a time with the chunk's 16 replicas, as in
+// the streaming kernel (same field bytes, Philox counters and carry decision),
+// reading the six neighbour rows from LDS; one 8-byte load from the problem's
+// site list gives the site, its periodic-wrap flags and its code.  The decision
+// words of a sweep come from its threshold row, loaded one sweep ahead.
 constexpr int kSlabThreads = 512;
-constexpr int kSlabPer = kEaSlabMaxSites / 2 / kSlabThreads;  // sites of a colour per thread
 
 template <bool DENSE>
 __global__ __launch_bounds__(kSlabThreads) void k_ea_slab(int8_t *__restrict__ spins,
-                                                        const uint32_t *__restrict__ code,
+                                                        const uint2 *__restrict__ sites,
                                                         const uint32_t *__restrict__ table, int width, int Lx,
                                                         int Ly, int Lz, int Rp, int s_begin, int s_end,
                                                         uint32_t sweep0, uint32_t rq0, uint32_t k0, uint32_t k1,
@@ -220,33 +219,12 @@ __global__ __launch_bounds__(kSlabThreads) void k_ea_slab(int8_t *__restrict__ s
     __shared__ uint64_t stab[kFieldSlots];
     const int tid = threadIdx.x;
     const int q = blockIdx.x;  // chunk of 16 replicas
-    const int plane = Lx * Ly, N = plane * Lz, half = N / 2, hx = Lx / 2;
-    for (int i = tid; i < N; i += kSlabThreads)
-        rows[i] = *reinterpret_cast<const uint4 *>(spins + (size_t)i * Rp + 16 * q);
-    // this thread's sites of each colour: index (low 16 bits) and the wrap flags of
-    // the +x, -x, +y, -y, +z, -z neighbours (bits 16..21), and the site code
-    uint32_t site[2][kSlabPer], cw[2][kSlabPer];
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-        for (int k = 0; k < kSlabPer; ++k) {
-            const int j = tid + kSlabThreads * k;
-            site[c][k] = 0u;
-            cw[c][k] = 0u;
-            if (j < half) {
-                const int kx = j % hx, row = j / hx;
-                const int y = row % Ly, z = row / Ly;
-                const int x = 2 * kx + ((c + y + z) & 1);
-                const int i = x + Lx * y + plane * z;
-                const uint32_t wrap = (x + 1 == Lx ? 1u : 0u) | (x == 0 ? 2u : 0u) | (y + 1 == Ly ? 4u : 0u) |
-                                      (y == 0 ? 8u : 0u) | (z + 1 == Lz ? 16u : 0u) | (z == 0 ? 32u : 0u);
-                site[c][k] = (uint32_t)i | wrap << 16;
-                cw[c][k] = code[i];
-            }
-        }
+    const int plane = Lx * Ly, N = plane * Lz, half = N / 2;
     // neighbour d of site i: i + step[d], or i + step[d] + fix[d] across the boundary
     const int step[6] = {1, -1, Lx, -Lx, plane, -plane};
     const int fix[6] = {-Lx, Lx, -plane, plane, -N, N};
+    for (int i = tid; i < N; i += kSlabThreads)
+        rows[i] = *reinterpret_cast<const uint4 *>(spins + (size_t)i * Rp + 16 * q);
     const uint32_t rg4 = rq0 + 4u * (uint32_t)q;  // Philox counter word 2 of the chunk's first group
     const char *tb = reinterpret_cast<const char *>(stab);
     const int tix = min(tid >= kFieldOff ? tid - kFieldOff : kFieldOff - tid, width - 1);  // |I| of entry tid
@@ -260,13 +238,11 @@ __global__ __launch_bounds__(kSlabThreads) void k_ea_slab(int8_t *__restrict__ s
         }
         __syncthreads();
         const uint32_t t = sweep0 + (uint32_t)s;
-#pragma unroll
         for (int c = 0; c < 2; ++c) {
-#pragma unroll
-            for (int k = 0; k < kSlabPer; ++k) {
-                if (tid + kSlabThreads * k >= half) break;
-                const int i = (int)(site[c][k] & 0xFFFFu);
-                const uint32_t wrap = site[c][k] >> 16, w = cw[c][k];
+            for (int j = tid; j < half; j += kSlabThreads) {
+                const uint2 e = sites[c * half + j];
+                const int i = (int)(e.x & 0xFFFFu);
+                const uint32_t wrap = e.x >> 16, w = e.y;
                 uint4 v[6];
 #pragma unroll
                 for (int d = 0; d < 6; ++d) v[d] = rows[i + step[d] + (((wrap >> d) & 1u) ? fix[d] : 0)];
@@ -444,7 +420,8 @@ bool ea_slab_fits(const EaView &p) { return p.N <= kEaSlabMaxSites; }
 hipError_t ea_slab(const EaView &p, int8_t *spins, int Rp, const uint32_t *table, int width, int s_begin, int s_end,
                    uint32_t sweep0, uint32_t rq0, Key key, hipStream_t st)
 {
-    if (!ea_slab_fits(p) || Rp % 16 != 0 || width < 1 || s_end < s_begin) return hipErrorInvalidValue;
+    if (!ea_slab_fits(p) || !p.slab_sites || Rp % 16 != 0 || width < 1 || s_end < s_begin)
+        return hipErrorInvalidValue;
     if (s_end == s_begin) return hipSuccess;
     const size_t lds = sizeof(uint4) * (size_t)p.N;
     static const hipError_t lds_attr = [] {
@@ -459,11 +436,13 @@ hipError_t ea_slab(const EaView &p, int8_t *spins, int Rp, const uint32_t *table
     if (lds_attr != hipSuccess) return lds_attr;
     const dim3 grid((unsigned)(Rp / 16));
     if (p.dense)
-        hipLaunchKernelGGL((k_ea_slab<true>), grid, dim3(kSlabThreads), lds, st, spins, p.code, table, width, p.Lx, p.Ly,
-                           p.Lz, Rp, s_begin, s_end, sweep0, rq0, key.k0, key.k1, 1u);
+        hipLaunchKernelGGL((k_ea_slab<true>), grid, dim3(kSlabThreads), lds, st, spins,
+                           reinterpret_cast<const uint2 *>(p.slab_sites), table, width, p.Lx, p.Ly, p.Lz, Rp, s_begin,
+                           s_end, sweep0, rq0, key.k0, key.k1, 1u);
     else
-        hipLaunchKernelGGL((k_ea_slab<false>), grid, dim3(kSlabThreads), lds, st, spins, p.code, table, width, p.Lx,
-                           p.Ly, p.Lz, Rp, s_begin, s_end, sweep0, rq0, key.k0, key.k1, 1u);
+        hipLaunchKernelGGL((k_ea_slab<false>), grid, dim3(kSlabThreads), lds, st, spins,
+                           reinterpret_cast<const uint2 *>(p.slab_sites), table, width, p.Lx, p.Ly, p.Lz, Rp, s_begin,
+                           s_end, sweep0, rq0, key.k0, key.k1, 1u);
     return hipGetLastError();
 }
 

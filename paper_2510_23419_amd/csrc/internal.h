@@ -23,6 +23,10 @@ struct EaView {
     const int8_t *J;       // [3][N] as given (for from-scratch energies)
     const int8_t *h;       // [N] or null
     bool dense;            // every coupling is nonzero
+    // for lattices the LDS-resident kernel takes: per colour c and class position j
+    // (x = 2 (j mod Lx/2) + parity, row j / (Lx/2)), the pair {site | wrap flags of
+    // the +x, -x, +y, -y, +z, -z neighbours << 16, site code}, [2][N / 2]; else null
+    const uint32_t *slab_sites;
 };
 
 // General sparse graph with k colour classes (greedy colouring by default).

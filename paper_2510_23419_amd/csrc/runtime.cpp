@@ -289,15 +289,34 @@ static int load_ea(pbit_ctx *ctx, const pbit_problem_desc *d, Problem &p)
                 code[(size_t)i] = c;
                 amax = std::max(amax, nnz + std::abs(hv));
             }
-    void *dc = nullptr, *dJ = nullptr, *dh = nullptr;
+    void *dc = nullptr, *dJ = nullptr, *dh = nullptr, *ds = nullptr;
     int rc = upload(ctx, p, code.data(), sizeof(uint32_t) * (size_t)N, &dc);
     if (rc == PBIT_OK) rc = upload(ctx, p, d->J, (size_t)(3 * N), &dJ);
     if (rc == PBIT_OK && d->h) rc = upload(ctx, p, d->h, (size_t)N, &dh);
+    EaView v{Lx, Ly, Lz, N, (const uint32_t *)dc, (const int8_t *)dJ, (const int8_t *)dh, dense, nullptr};
+    if (rc == PBIT_OK && ea_slab_fits(v)) {
+        // the LDS-resident kernel's site list: class position -> site, wrap flags, code
+        const int64_t half = N / 2, hx = Lx / 2;
+        std::vector<uint32_t> sites((size_t)4 * half);
+        for (int c = 0; c < 2; ++c)
+            for (int64_t j = 0; j < half; ++j) {
+                const int kx = (int)(j % hx), row = (int)(j / hx);
+                const int y = row % Ly, z = row / Ly;
+                const int x = 2 * kx + ((c + y + z) & 1);
+                const int64_t i = x + (int64_t)Lx * y + plane * z;
+                const uint32_t wrap = (x + 1 == Lx ? 1u : 0u) | (x == 0 ? 2u : 0u) | (y + 1 == Ly ? 4u : 0u) |
+                                      (y == 0 ? 8u : 0u) | (z + 1 == Lz ? 16u : 0u) | (z == 0 ? 32u : 0u);
+                sites[(size_t)2 * (c * half + j)] = (uint32_t)i | wrap << 16;
+                sites[(size_t)2 * (c * half + j) + 1] = code[(size_t)i];
+            }
+        rc = upload(ctx, p, sites.data(), sizeof(uint32_t) * sites.size(), &ds);
+        v.slab_sites = (const uint32_t *)ds;
+    }
     if (rc != PBIT_OK) return rc;
     p.kind = PBIT_EA3D;
     p.N = N;
     p.amax = amax;
-    p.ea = EaView{Lx, Ly, Lz, N, (const uint32_t *)dc, (const int8_t *)dJ, (const int8_t *)dh, dense};
+    p.ea = v;
     return PBIT_OK;
 }
 
@@ -545,7 +564,7 @@ static int load_graph(pbit_ctx *ctx, const pbit_graph_desc *d, Problem &p)
     p.graph = GraphView{n, nb, ncol, maxdeg, p.class_start.data(), (const int32_t *)dmeta, (const uint32_t *)dadj,
                         (const int32_t *)dbi, (const int32_t *)dbj, (const int8_t *)dbJ, (const int8_t *)dh};
     // the cube's layout kernels (init, transposes) are reused with N = n
-    p.ea = EaView{0, 0, 0, (int64_t)n, nullptr, nullptr, nullptr, false};
+    p.ea = EaView{0, 0, 0, (int64_t)n, nullptr, nullptr, nullptr, false, nullptr};
     return PBIT_OK;
 }
 
@@ -860,7 +879,7 @@ static int prepare(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, h
         if (rc) return rc;
     }
     ds.bits = P.kind == PBIT_BICLIQUE && ds.variant == BqVariant::Bits;
-    ds.slab = P.kind == PBIT_EA3D && ea_slab_fits(P.ea) && !ctx->ea_stream_forced;
+    ds.slab = P.kind == PBIT_EA3D && P.ea.slab_sites && !ctx->ea_stream_forced;
     if (P.kind == PBIT_EA3D && d->n_sweeps > 0) ctx->ea_last_path = ds.slab ? 2 : 1;
     if (P.kind == PBIT_BICLIQUE && d->n_sweeps > 0) ctx->bq_last_variant = (int)ds.variant;
 
