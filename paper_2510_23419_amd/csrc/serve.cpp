@@ -29,7 +29,8 @@ int spins_in_range(const int8_t *s, size_t n);  // runtime.cpp
 namespace {
 
 constexpr int kMaxLdsTile = 160 * 1024 - 4096;
-constexpr int kKinds = 4;  // tile kinds: cube tiles; 128-, 64- and 32-replica biclique tiles
+constexpr int kKinds = 5;  // tile kinds: 4-replica cube tiles; 128-, 64-, 32-replica biclique tiles; 16-replica cube tiles
+constexpr int kKindEa16 = 4;
 inline int kind_of_rs(int rs) { return rs == 128 ? 1 : (rs == 64 ? 2 : 3); }
 constexpr double kItemOps = 1.5e11;  // multiply-adds of one biclique tile over its anneal
 inline int rs_of_kind(int k) { return k == 1 ? 128 : (k == 2 ? 64 : 32); }
@@ -63,16 +64,16 @@ struct ServeState {
     std::map<uint64_t, std::unique_ptr<BJob>> jobs;
     uint64_t next_id = 1;
     int max_queue = 4096, max_running = 1024, round_sweeps = 500;
-    // one stream per tile kind: cube tiles, then 128-, 64- and 32-replica biclique tiles
-    hipStream_t st[kKinds] = {nullptr, nullptr, nullptr, nullptr};
-    hipEvent_t fork = nullptr, join[kKinds] = {nullptr, nullptr, nullptr, nullptr};
+    // one stream per tile kind
+    hipStream_t st[kKinds] = {};
+    hipEvent_t fork = nullptr, join[kKinds] = {};
     bool in_flight = false;
     std::vector<BJob *> round_jobs;
     std::vector<int> round_end;
     // device work lists (grown on demand)
-    void *d_ea_jobs = nullptr, *d_bq_jobs[kKinds - 1] = {nullptr, nullptr, nullptr};
-    void *d_items[kKinds] = {nullptr, nullptr, nullptr, nullptr};
-    size_t cap_ea_jobs = 0, cap_bq_jobs[kKinds - 1] = {0, 0, 0}, cap_items[kKinds] = {0, 0, 0, 0};
+    void *d_ea_jobs = nullptr, *d_bq_jobs[3] = {};  // cube jobs (both cube kinds); biclique jobs per tile kind
+    void *d_items[kKinds] = {};
+    size_t cap_ea_jobs = 0, cap_bq_jobs[3] = {}, cap_items[kKinds] = {};
     int32_t *d_meta = nullptr;  // counters[kKinds], n_items[kKinds]
     bool lds_ready = false;
 };
@@ -125,7 +126,7 @@ void serve_shutdown(pbit_ctx *ctx)
         if (j->P) j->P->jobs--;
     }
     dev_free(ctx, s->d_ea_jobs);
-    for (int k = 0; k < kKinds - 1; ++k) dev_free(ctx, s->d_bq_jobs[k]);
+    for (int k = 0; k < 3; ++k) dev_free(ctx, s->d_bq_jobs[k]);
     for (int k = 0; k < kKinds; ++k) dev_free(ctx, s->d_items[k]);
     dev_free(ctx, s->d_meta);
     for (int k = 0; k < kKinds; ++k) {
@@ -160,7 +161,7 @@ static int tile_mode(const pbit_ctx *ctx)
 
 static size_t tile_bytes(const BJob &j)
 {
-    return j.kind == PBIT_EA3D ? (size_t)4 * j.N : (size_t)j.rs * bq_row_bytes(j);
+    return j.kind == PBIT_EA3D ? (size_t)j.rs * j.N : (size_t)j.rs * bq_row_bytes(j);
 }
 
 static int plan_job(pbit_ctx *ctx, BJob &j)
@@ -175,9 +176,11 @@ static int plan_job(pbit_ctx *ctx, BJob &j)
     if (j.width > kMaxTableWidth) return fail(PBIT_E_UNSUPPORTED, "threshold rows of %d entries are too wide", j.width);
     if (P.kind == PBIT_GRAPH) return fail(PBIT_E_UNSUPPORTED, "general graphs run through pbit_anneal only");
     if (P.kind == PBIT_EA3D) {
-        if (ea_tile_lds(P.N) > (size_t)kMaxLdsTile || P.ea.Lx > 1024 || P.ea.Ly > 1024)
+        if (ea_tile_lds(P.N, 4) > (size_t)kMaxLdsTile || P.ea.Lx > 1024 || P.ea.Ly > 1024)
             return fail(PBIT_E_UNSUPPORTED, "cube of %lld sites is too large for a batched tile", (long long)P.N);
-        j.rs = 4;
+        // 16-replica tiles (one 16-byte row per site) where the lattice has a site list
+        // and the job fills them; 4-replica tiles otherwise
+        j.rs = P.ea.slab_sites && j.R >= 16 && ea_tile_lds(P.N, 16) <= (size_t)kMaxLdsTile ? 16 : 4;
     } else {
         // the largest tile that the replicas fill, the LDS holds and whose whole anneal
         // stays below kItemOps multiply-adds: larger tiles stream fewer coupling bytes
@@ -209,9 +212,10 @@ static void rows_to_tiles(const BJob &j, const int8_t *rows, std::vector<int8_t>
 {
     const Problem &P = *j.P;
     if (P.kind == PBIT_EA3D) {
-        tiles_out.assign((size_t)j.tiles * 4 * j.N, 1);
+        tiles_out.assign((size_t)j.tiles * j.rs * j.N, 1);
         for (int r = 0; r < j.R; ++r)
-            for (int i = 0; i < j.N; ++i) tiles_out[((size_t)(r / 4) * j.N + i) * 4 + (r % 4)] = rows[(size_t)r * j.N + i];
+            for (int i = 0; i < j.N; ++i)
+                tiles_out[((size_t)(r / j.rs) * j.N + i) * j.rs + (r % j.rs)] = rows[(size_t)r * j.N + i];
     } else {
         // spin bits (set = -1, bit col % 8 of byte col / 8: the little-endian words the
         // kernel reads), int8 spins, or packed 4-bit floats (+1 = 0x2, -1 = 0xA, two
@@ -238,7 +242,8 @@ static void tiles_to_rows(const BJob &j, const int8_t *tl, int8_t *rows)
     const Problem &P = *j.P;
     if (P.kind == PBIT_EA3D) {
         for (int r = 0; r < j.R; ++r)
-            for (int i = 0; i < j.N; ++i) rows[(size_t)r * j.N + i] = tl[((size_t)(r / 4) * j.N + i) * 4 + (r % 4)];
+            for (int i = 0; i < j.N; ++i)
+                rows[(size_t)r * j.N + i] = tl[((size_t)(r / j.rs) * j.N + i) * j.rs + (r % j.rs)];
     } else {
         const int Pw = bq_row_bytes(j);
         for (int r = 0; r < j.R; ++r)
@@ -303,10 +308,10 @@ static int launch_round(pbit_ctx *ctx, ServeState &s)
     s.round_jobs.clear();
     s.round_end.clear();
     std::vector<EaJobDev> ea;
-    std::vector<BqJobDev> bq[kKinds - 1];
+    std::vector<BqJobDev> bq[3];
     std::vector<WorkItem> items[kKinds];
     std::vector<double> cost[kKinds];
-    size_t lds[kKinds] = {0, 0, 0, 0};
+    size_t lds[kKinds] = {};
     for (BJob *j : s.running) {
         if (j->finished) continue;
         const int s0 = j->s_done;
@@ -317,16 +322,17 @@ static int launch_round(pbit_ctx *ctx, ServeState &s)
         const Key key{(uint32_t)j->d.seed, (uint32_t)(j->d.seed >> 32)};
         if (j->kind == PBIT_EA3D) {
             const EaView &v = j->P->ea;
-            EaJobDev jd{v.code, (const uint32_t *)j->d_table, (int8_t *)j->d_state, (int32_t *)j->d_energy,
+            EaJobDev jd{v.code, reinterpret_cast<const uint2 *>(v.slab_sites), (const uint32_t *)j->d_table, (int8_t *)j->d_state, (int32_t *)j->d_energy,
                         v.Lx, v.Ly, v.Lz, j->width, v.dense ? 1 : 0, (uint32_t)j->d.sweep_offset,
                         (uint32_t)j->d.replica_offset >> 2, key.k0, key.k1};
             const int idx = (int)ea.size();
             ea.push_back(jd);
+            const int k = j->rs == 16 ? kKindEa16 : 0;
             for (int t = 0; t < j->tiles; ++t) {
-                items[0].push_back(WorkItem{idx, t, s0, s1, j->started ? 0 : 1, {0, 0, 0}});
-                cost[0].push_back((double)(s1 - s0) * j->N);
+                items[k].push_back(WorkItem{idx, t, s0, s1, j->started ? 0 : 1, {0, 0, 0}});
+                cost[k].push_back((double)(s1 - s0) * j->N);
             }
-            lds[0] = std::max(lds[0], ea_tile_lds(j->N));
+            lds[k] = std::max(lds[k], ea_tile_lds(j->N, j->rs));
         } else {
             const BqView &v = j->P->bq;
             const int k = kind_of_rs(j->rs);
@@ -355,7 +361,7 @@ static int launch_round(pbit_ctx *ctx, ServeState &s)
         items[k].swap(sorted);
     }
     int rc = grow(ctx, &s.d_ea_jobs, &s.cap_ea_jobs, sizeof(EaJobDev) * std::max<size_t>(ea.size(), 1));
-    for (int k = 0; k < kKinds - 1 && rc == PBIT_OK; ++k)
+    for (int k = 0; k < 3 && rc == PBIT_OK; ++k)
         rc = grow(ctx, &s.d_bq_jobs[k], &s.cap_bq_jobs[k], sizeof(BqJobDev) * std::max<size_t>(bq[k].size(), 1));
     for (int k = 0; k < kKinds && rc == PBIT_OK; ++k)
         rc = grow(ctx, &s.d_items[k], &s.cap_items[k], sizeof(WorkItem) * std::max<size_t>(items[k].size(), 1));
@@ -370,7 +376,7 @@ static int launch_round(pbit_ctx *ctx, ServeState &s)
     hipError_t e = hipMemcpy(s.d_meta, meta, sizeof meta, hipMemcpyHostToDevice);
     if (e == hipSuccess && !ea.empty())
         e = hipMemcpy(s.d_ea_jobs, ea.data(), sizeof(EaJobDev) * ea.size(), hipMemcpyHostToDevice);
-    for (int k = 0; k < kKinds - 1 && e == hipSuccess; ++k)
+    for (int k = 0; k < 3 && e == hipSuccess; ++k)
         if (!bq[k].empty()) e = hipMemcpy(s.d_bq_jobs[k], bq[k].data(), sizeof(BqJobDev) * bq[k].size(), hipMemcpyHostToDevice);
     for (int k = 0; k < kKinds && e == hipSuccess; ++k)
         if (!items[k].empty()) e = hipMemcpy(s.d_items[k], items[k].data(), sizeof(WorkItem) * items[k].size(), hipMemcpyHostToDevice);
@@ -388,6 +394,9 @@ static int launch_round(pbit_ctx *ctx, ServeState &s)
         if (k == 0)
             e = ea_tiles((const EaJobDev *)s.d_ea_jobs, (const WorkItem *)s.d_items[0], s.d_meta + kKinds,
                          s.d_meta + 0, grid, lds[0], s.st[0]);
+        else if (k == kKindEa16)
+            e = ea_tiles16((const EaJobDev *)s.d_ea_jobs, (const WorkItem *)s.d_items[k], s.d_meta + kKinds + k,
+                           s.d_meta + k, grid, lds[k], s.st[k]);
         else
             e = bq_tiles((const BqJobDev *)s.d_bq_jobs[k - 1], (const WorkItem *)s.d_items[k], s.d_meta + kKinds + k,
                          s.d_meta + k, rs_of_kind(k), tile_mode(ctx), grid, lds[k], s.st[k]);
