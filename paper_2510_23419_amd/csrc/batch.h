@@ -1,7 +1,7 @@
 // batch.h — device descriptors of the persistent batched sweep (many jobs in
 // one launch).  A job is one anneal (problem, schedule, replicas, seed).  It is
-// cut into replica tiles that never need each other: a cube tile is 4 replicas
-// of the whole lattice (16 for lattices of at most kEaSlabMaxSites sites), a
+// cut into replica tiles that never need each other: a cube tile is 4, 8 or 16
+// replicas of the whole lattice (8 and 16 where the lattice has a site list), a
 // biclique tile is 32, 64 or 128 replicas of both sides.
 // A work item advances one tile over a range of sweeps; a persistent kernel
 // pulls items from a queue until the queue is empty.
@@ -14,9 +14,9 @@ namespace pbit {
 
 struct EaJobDev {
     const uint32_t *code;   // [N] site codes (see internal.h)
-    const uint2 *sites;     // 16-replica tiles: [2][N / 2] class position -> {site | wrap flags << 16, code}
+    const uint2 *sites;     // 8- and 16-replica tiles: [2][N / 2] class position -> {site | wrap flags << 16, code}
     const uint32_t *table;  // [S][width] thresholds, row s = local sweep s
-    int8_t *state;          // [tiles][N][rs]: spins of a tile, replica fastest (rs = 4 or 16)
+    int8_t *state;          // [tiles][N][rs]: spins of a tile, replica fastest (rs = 4, 8 or 16)
     int32_t *energy;        // [tiles * rs]: energies after the tile's last item
     int Lx, Ly, Lz, width;
     int dense;              // 1: every coupling is nonzero
@@ -57,16 +57,16 @@ constexpr int kBqTileThreads = 512;
 // zeroed by the caller) hands out item indices.
 hipError_t ea_tiles(const EaJobDev *jobs, const WorkItem *items, const int32_t *n_items, int32_t *counter,
                     int grid, size_t lds_bytes, hipStream_t st);
-// the same with 16 replicas per tile (cubes of at most kEaSlabMaxSites sites, 16 N bytes of LDS)
-hipError_t ea_tiles16(const EaJobDev *jobs, const WorkItem *items, const int32_t *n_items, int32_t *counter,
-                      int grid, size_t lds_bytes, hipStream_t st);
+// the same with rs = 8 or 16 replicas per tile (cubes with a site list, rs N bytes of LDS)
+hipError_t ea_tiles_wide(const EaJobDev *jobs, const WorkItem *items, const int32_t *n_items, int32_t *counter, int rs,
+                         int grid, size_t lds_bytes, hipStream_t st);
 // operand modes of the biclique tiles
 constexpr int kTileInt8 = 0, kTileFp4 = 1, kTileBits = 2;
 hipError_t bq_tiles(const BqJobDev *jobs, const WorkItem *items, const int32_t *n_items, int32_t *counter,
                     int rs, int mode, int grid, size_t lds_bytes, hipStream_t st);
 
 // LDS a tile kernel needs for the given job shape.
-size_t ea_tile_lds(int64_t N, int rs);  // rs = 4 or 16 replicas
+size_t ea_tile_lds(int64_t N, int rs);  // rs = 4, 8 or 16 replicas
 size_t bq_tile_lds(int rs, int na_p, int nb_p, int width, int mode);
 hipError_t tiles_set_lds_limit();
 

@@ -203,19 +203,23 @@ __global__ __launch_bounds__(kEaTileThreads) void k_ea_tiles(const EaJobDev *__r
     }
 }
 
-// A tile of 16 replicas of the whole lattice, one uint4 per site (the layout of
-// the per-instance LDS-resident cube kernel): same field bytes, Philox counters
-// and carry decisions, the site list of the problem for indices, wrap flags and
-// codes.  More replicas per site than the 4-replica tiles, so the per-site work
-// (addresses, codes, neighbour reads) is shared by four times as many updates.
-__global__ __launch_bounds__(kEaTileThreads) void k_ea_tiles16(const EaJobDev *__restrict__ jobs,
-                                                               const WorkItem *__restrict__ items,
-                                                               const int32_t *__restrict__ n_items_p,
-                                                               int32_t *__restrict__ counter, uint32_t one)
+// A tile of 4W replicas (W = 2 or 4) of the whole lattice, W dwords per site (for
+// W = 4 the layout of the per-instance LDS-resident cube kernel): same field bytes,
+// Philox counters and carry decisions, and the problem's site list for indices,
+// wrap flags and codes.  Each site's index, code and neighbour addresses then serve
+// 4W updates instead of 4.
+template <int W>
+__global__ __launch_bounds__(kEaTileThreads) void k_ea_tiles_wide(const EaJobDev *__restrict__ jobs,
+                                                                  const WorkItem *__restrict__ items,
+                                                                  const int32_t *__restrict__ n_items_p,
+                                                                  int32_t *__restrict__ counter, uint32_t one)
 {
-    extern __shared__ uint4 rows[];  // [N]: the tile's 16 replicas of every site
+    typedef uint32_t V __attribute__((ext_vector_type(W)));
+    constexpr int RS = 4 * W;  // replicas in the tile
+    extern __shared__ uint4 tile_rows[];
+    V *rows = reinterpret_cast<V *>(tile_rows);  // [N]: the tile's replicas of every site
     __shared__ uint64_t stab[kFieldSlots];
-    __shared__ int32_t eacc[16];
+    __shared__ int32_t eacc[RS];
     __shared__ int slot;
     const int tid = threadIdx.x;
     const int n_items = *n_items_p;
@@ -228,27 +232,27 @@ __global__ __launch_bounds__(kEaTileThreads) void k_ea_tiles16(const EaJobDev *_
         const EaJobDev jb = jobs[w.job];
         const int Lx = jb.Lx, Ly = jb.Ly, Lz = jb.Lz;
         const int plane = Lx * Ly, N = plane * Lz, half = N / 2;
-        const uint32_t rg4 = jb.rq0 + 4u * (uint32_t)w.tile;  // Philox counter word 2 of the tile's first group
-        uint4 *gst = reinterpret_cast<uint4 *>(jb.state) + (size_t)w.tile * N;
+        const uint32_t rgw = jb.rq0 + (uint32_t)W * (uint32_t)w.tile;  // Philox counter word 2 of the tile's first group
+        V *gst = reinterpret_cast<V *>(jb.state) + (size_t)w.tile * N;
         // neighbour d of site i: i + step[d], or i + step[d] + fix[d] across the boundary
         const int step[6] = {1, -1, Lx, -Lx, plane, -plane};
         const int fix[6] = {-Lx, Lx, -plane, plane, -N, N};
 
         if (w.init) {
             for (int i = tid; i < N; i += kEaTileThreads) {
-                uint32_t d[4];
+                V d;
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const Block4 b = philox((uint32_t)i, 0u, rg4 + (uint32_t)k, kDomainInit, jb.k0, jb.k1);
+                for (int k = 0; k < W; ++k) {
+                    const Block4 b = philox((uint32_t)i, 0u, rgw + (uint32_t)k, kDomainInit, jb.k0, jb.k1);
                     uint32_t packed = 0;
 #pragma unroll
                     for (int p = 0; p < 4; ++p) packed |= (uint32_t)(uint8_t)init_spin(b.w[p]) << (8 * p);
                     d[k] = packed;
                 }
-                rows[i] = make_uint4(d[0], d[1], d[2], d[3]);
+                rows[i] = d;
             }
         } else {
-            for (int i = tid; i < N; i += kEaTileThreads) rows[i] = load_u4(gst + i);
+            for (int i = tid; i < N; i += kEaTileThreads) rows[i] = load_global<V>(gst + i);
         }
 
         for (int s = w.s_begin; s < w.s_end; ++s) {
@@ -267,27 +271,25 @@ __global__ __launch_bounds__(kEaTileThreads) void k_ea_tiles16(const EaJobDev *_
                     const uint2 e = load_u2(jb.sites + (size_t)c * half + j);
                     const int i = (int)(e.x & 0xFFFFu);
                     const uint32_t wrap = e.x >> 16, code = e.y;
-                    uint4 v[6];
+                    V v[6];
 #pragma unroll
                     for (int d = 0; d < 6; ++d) v[d] = rows[i + step[d] + (((wrap >> d) & 1u) ? fix[d] : 0)];
-                    Block4 b[4];
+                    Block4 b[W];
 #pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        b[r] = philox((uint32_t)i, t, rg4 + (uint32_t)r, kDomainSweep, jb.k0, jb.k1);
-                    uint32_t tt[6][4];
+                    for (int r = 0; r < W; ++r)
+                        b[r] = philox((uint32_t)i, t, rgw + (uint32_t)r, kDomainSweep, jb.k0, jb.k1);
+                    uint32_t tt[6][W];
 #pragma unroll
                     for (int d = 0; d < 6; ++d) {
                         const uint32_t F = bit_mask(code, kCodeFlipShift + d);
                         const uint32_t K = DENSE ? 0x10101010u : (bit_mask(code, d) & 0x10101010u);
-                        tt[d][0] = __builtin_amdgcn_bitop3_b32(v[d].x, F, K, 0x82);  // ~(a ^ b) & c
-                        tt[d][1] = __builtin_amdgcn_bitop3_b32(v[d].y, F, K, 0x82);
-                        tt[d][2] = __builtin_amdgcn_bitop3_b32(v[d].z, F, K, 0x82);
-                        tt[d][3] = __builtin_amdgcn_bitop3_b32(v[d].w, F, K, 0x82);
+#pragma unroll
+                        for (int r = 0; r < W; ++r) tt[d][r] = __builtin_amdgcn_bitop3_b32(v[d][r], F, K, 0x82);
                     }
                     const uint32_t pos8 = __builtin_amdgcn_perm(0u, code, 0x03030303u);  // base byte in every byte
-                    uint32_t out[4];
+                    V out;
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
+                    for (int r = 0; r < W; ++r) {
                         const uint32_t idx =
                             (tt[0][r] + tt[1][r] + tt[2][r]) + (tt[3][r] + tt[4][r] + tt[5][r]) + pos8;
                         uint32_t sgn[4];  // 1: the replica's new spin is -1
@@ -301,7 +303,7 @@ __global__ __launch_bounds__(kEaTileThreads) void k_ea_tiles16(const EaJobDev *_
                         const uint32_t hi = __builtin_amdgcn_perm(sgn[3], sgn[2], 0x0C0C0400u);
                         out[r] = __builtin_amdgcn_perm(0u, 0xFF01u, __builtin_amdgcn_perm(hi, lo, 0x05040100u));
                     }
-                    rows[i] = make_uint4(out[0], out[1], out[2], out[3]);
+                    rows[i] = out;
                 }
             };
             for (int c = 0; c < 2; ++c) {
@@ -313,14 +315,14 @@ __global__ __launch_bounds__(kEaTileThreads) void k_ea_tiles16(const EaJobDev *_
             }
         }
 
-        // energies of the 16 replicas: every bond has exactly one end of colour 1 (the
+        // energies of the tile's replicas: every bond has exactly one end of colour 1 (the
         // second half of the site list), so E = -sum_{i in colour 1} m_i sum_j J_ij m_j
         // - sum_i h_i m_i
-        if (tid < 16) eacc[tid] = 0;
+        if (tid < RS) eacc[tid] = 0;
         __syncthreads();
-        int32_t e16[16];
+        int32_t er[RS];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) e16[r] = 0;
+        for (int r = 0; r < RS; ++r) er[r] = 0;
         for (int j = tid; j < N; j += kEaTileThreads) {
             const int c = j < half ? 0 : 1;
             const uint2 e = load_u2(jb.sites + j);  // colour 0 first, then colour 1
@@ -328,38 +330,37 @@ __global__ __launch_bounds__(kEaTileThreads) void k_ea_tiles16(const EaJobDev *_
             const uint32_t wrap = e.x >> 16, code = e.y;
             const int nnz = __builtin_popcount(code & 63u);
             const int hv = (int)(int8_t)(code >> kCodeBaseShift) - nnz;
-            const uint4 mi = rows[i];
-            const uint32_t md[4] = {mi.x, mi.y, mi.z, mi.w};
-            uint32_t cnt[4] = {0u, 0u, 0u, 0u};
+            const V mi = rows[i];
+            uint32_t cnt[W];
+#pragma unroll
+            for (int k = 0; k < W; ++k) cnt[k] = 0u;
             if (c == 1) {
 #pragma unroll
                 for (int d = 0; d < 6; ++d) {
-                    const uint4 v = rows[i + step[d] + (((wrap >> d) & 1u) ? fix[d] : 0)];
+                    const V v = rows[i + step[d] + (((wrap >> d) & 1u) ? fix[d] : 0)];
                     const uint32_t keep = ((code >> d) & 1u) * 0x02020202u;
                     const uint32_t flip = ((code >> (kCodeFlipShift + d)) & 1u) * 0x02020202u;
-                    cnt[0] += neg2(v.x, keep, flip);
-                    cnt[1] += neg2(v.y, keep, flip);
-                    cnt[2] += neg2(v.z, keep, flip);
-                    cnt[3] += neg2(v.w, keep, flip);
+#pragma unroll
+                    for (int k = 0; k < W; ++k) cnt[k] += neg2(v[k], keep, flip);
                 }
             }
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
+            for (int k = 0; k < W; ++k)
 #pragma unroll
                 for (int p = 0; p < 4; ++p) {
-                    const int m = (int)(int8_t)(md[k] >> (8 * p));
+                    const int m = (int)(int8_t)(mi[k] >> (8 * p));
                     const int bonds = c == 1 ? nnz - (int)((cnt[k] >> (8 * p)) & 0xFFu) : 0;
-                    e16[4 * k + p] -= m * (bonds + hv);
+                    er[4 * k + p] -= m * (bonds + hv);
                 }
         }
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            int v = e16[r];
+        for (int r = 0; r < RS; ++r) {
+            int v = er[r];
             for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
             if ((tid & 63) == 0) atomicAdd(&eacc[r], v);
         }
         __syncthreads();
-        if (tid < 16) jb.energy[16 * w.tile + tid] = eacc[tid];
+        if (tid < RS) jb.energy[RS * w.tile + tid] = eacc[tid];
         for (int i = tid; i < N; i += kEaTileThreads) gst[i] = rows[i];
     }
 }
@@ -866,7 +867,10 @@ hipError_t tiles_set_lds_limit()
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ea_tiles),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
     if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ea_tiles16),
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ea_tiles_wide<2>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ea_tiles_wide<4>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
     const void *bq_kernels[] = {reinterpret_cast<const void *>(&k_bq_tiles_bits<1>),
                                 reinterpret_cast<const void *>(&k_bq_tiles_bits<2>),
@@ -890,11 +894,17 @@ hipError_t ea_tiles(const EaJobDev *jobs, const WorkItem *items, const int32_t *
     return hipGetLastError();
 }
 
-hipError_t ea_tiles16(const EaJobDev *jobs, const WorkItem *items, const int32_t *n_items, int32_t *counter, int grid,
-                      size_t lds_bytes, hipStream_t st)
+hipError_t ea_tiles_wide(const EaJobDev *jobs, const WorkItem *items, const int32_t *n_items, int32_t *counter, int rs,
+                         int grid, size_t lds_bytes, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_ea_tiles16, dim3((unsigned)grid), dim3(kEaTileThreads), lds_bytes, st, jobs, items, n_items,
-                       counter, 1u);
+    if (rs == 8)
+        hipLaunchKernelGGL(k_ea_tiles_wide<2>, dim3((unsigned)grid), dim3(kEaTileThreads), lds_bytes, st, jobs, items,
+                           n_items, counter, 1u);
+    else if (rs == 16)
+        hipLaunchKernelGGL(k_ea_tiles_wide<4>, dim3((unsigned)grid), dim3(kEaTileThreads), lds_bytes, st, jobs, items,
+                           n_items, counter, 1u);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

@@ -294,8 +294,8 @@ static int load_ea(pbit_ctx *ctx, const pbit_problem_desc *d, Problem &p)
     if (rc == PBIT_OK) rc = upload(ctx, p, d->J, (size_t)(3 * N), &dJ);
     if (rc == PBIT_OK && d->h) rc = upload(ctx, p, d->h, (size_t)N, &dh);
     EaView v{Lx, Ly, Lz, N, (const uint32_t *)dc, (const int8_t *)dJ, (const int8_t *)dh, dense, nullptr};
-    if (rc == PBIT_OK && ea_slab_fits(v)) {
-        // the LDS-resident kernel's site list: class position -> site, wrap flags, code
+    if (rc == PBIT_OK && N < 65536) {
+        // the LDS-resident kernels' site list: class position -> site, wrap flags, code
         const int64_t half = N / 2, hx = Lx / 2;
         std::vector<uint32_t> sites((size_t)4 * half);
         for (int c = 0; c < 2; ++c)
@@ -310,7 +310,8 @@ static int load_ea(pbit_ctx *ctx, const pbit_problem_desc *d, Problem &p)
                 sites[(size_t)2 * (c * half + j) + 1] = code[(size_t)i];
             }
         rc = upload(ctx, p, sites.data(), sizeof(uint32_t) * sites.size(), &ds);
-        v.slab_sites = (const uint32_t *)ds;
+        p.tile_sites = (const uint32_t *)ds;
+        if (ea_slab_fits(v)) v.slab_sites = (const uint32_t *)ds;
     }
     if (rc != PBIT_OK) return rc;
     p.kind = PBIT_EA3D;

@@ -20,6 +20,7 @@ struct Problem {
     EaView ea{};
     BqView bq{};
     GraphView graph{};
+    const uint32_t *tile_sites = nullptr;  // cube site list for the batched tiles (N < 65536), else null
     std::vector<int32_t> class_start;  // host copy behind graph.class_start
     std::vector<uint8_t> colour;       // colouring used (graph problems)
     std::vector<void *> allocs;
