@@ -78,6 +78,34 @@ def test_batch_equals_single_runs_at_mixed_bag_sizes(ctx):
         pbit.pbit_unload_problem(ctx, p)
 
 
+def test_batch_cube_tile_widths(ctx):
+    """Cube jobs of every tile width: 16-replica tiles (lattices up to 8192 sites
+    with at least 16 replicas), 8-replica tiles (where 16 do not fit the LDS or the
+    job has 8..15 replicas) and 4-replica tiles, each with a ragged last tile, dense
+    and diluted couplings, with and without fields, and non-cubic sides: batched
+    results equal the per-instance path (itself bit-exact with the oracle)."""
+    rng = np.random.default_rng(7)
+    cases = [((20, 20, 20), 20, "zero", 1.0), ((22, 22, 22), 12, "uniform3", 0.9), ((24, 24, 24), 8, "zero", 1.0),
+             ((20, 22, 16), 17, "uniform3", 1.0), ((6, 6, 6), 16, "zero", 0.8), ((20, 20, 20), 5, "uniform3", 0.9),
+             ((2, 2, 2), 33, "uniform3", 1.0), ((26, 26, 26), 9, "zero", 1.0), ((28, 28, 28), 16, "zero", 1.0)]
+    jobs = []
+    for k, (dims, R, field, keep) in enumerate(cases):
+        inst = synth.ea_instance(dims, seed=40 + k, field=field)
+        if keep < 1.0:
+            inst["J"] = (inst["J"] * (rng.random(inst["J"].shape) < keep)).astype(np.int8)
+        jobs.append(dict(inst=inst, R=R, seed=300 + k, beta=synth.beta_geometric(0.2, 3.0, int(rng.integers(20, 45)))))
+    probs = [pbit.load_instance(ctx, j["inst"]) for j in jobs]
+    _say("cube tile widths: %d jobs" % len(jobs))
+    outs = pbit.pbit_anneal_batch(ctx, [dict(problem=p, beta=j["beta"], n_replicas=j["R"], seed=j["seed"])
+                                        for p, j in zip(probs, jobs)])
+    for p, j, o in zip(probs, jobs, outs):
+        single = pbit.pbit_anneal(ctx, p, j["beta"], j["R"], j["seed"])
+        assert np.array_equal(o.spins, single.spins), j["inst"]["dims"]
+        assert np.array_equal(o.energies, single.energies), j["inst"]["dims"]
+        assert o.sweeps_done == len(j["beta"])
+        pbit.pbit_unload_problem(ctx, p)
+
+
 def test_batch_given_spins_offsets_and_traces(ctx):
     inst = synth.ea_instance(6, seed=8, field="uniform3")
     binst = synth.biclique_instance(40, seed=8)
