@@ -1,8 +1,8 @@
 // batch.h — device descriptors of the persistent batched sweep (many jobs in
 // one launch).  A job is one anneal (problem, schedule, replicas, seed).  It is
 // cut into replica tiles that never need each other: a cube tile is 4, 8 or 16
-// replicas of the whole lattice (8 and 16 where the lattice has a site list), a
-// biclique tile is 32, 64 or 128 replicas of both sides.
+// replicas of the whole lattice, a biclique tile is 32, 64 or 128 replicas of
+// both sides.
 // A work item advances one tile over a range of sweeps; a persistent kernel
 // pulls items from a queue until the queue is empty.
 #pragma once
@@ -13,12 +13,12 @@
 namespace pbit {
 
 struct EaJobDev {
-    const uint32_t *code;   // [N] site codes (see internal.h)
-    const uint2 *sites;     // 8- and 16-replica tiles: [2][N / 2] class position -> {site | wrap flags << 16, code}
+    const uint2 *sites;     // [2][N / 2] class position -> {site | wrap flags << 16, code}
     const uint32_t *table;  // [S][width] thresholds, row s = local sweep s
     int8_t *state;          // [tiles][N][rs]: spins of a tile, replica fastest (rs = 4, 8 or 16)
     int32_t *energy;        // [tiles * rs]: energies after the tile's last item
     int Lx, Ly, Lz, width;
+    int rs;                 // replicas per tile: 4, 8 or 16
     int dense;              // 1: every coupling is nonzero
     uint32_t sweep0;        // absolute index of local sweep 0
     uint32_t rq0;           // global replica group of tile 0 (replica_offset / 4)
@@ -57,9 +57,6 @@ constexpr int kBqTileThreads = 512;
 // zeroed by the caller) hands out item indices.
 hipError_t ea_tiles(const EaJobDev *jobs, const WorkItem *items, const int32_t *n_items, int32_t *counter,
                     int grid, size_t lds_bytes, hipStream_t st);
-// the same with rs = 8 or 16 replicas per tile (cubes with a site list, rs N bytes of LDS)
-hipError_t ea_tiles_wide(const EaJobDev *jobs, const WorkItem *items, const int32_t *n_items, int32_t *counter, int rs,
-                         int grid, size_t lds_bytes, hipStream_t st);
 // operand modes of the biclique tiles
 constexpr int kTileInt8 = 0, kTileFp4 = 1, kTileBits = 2;
 hipError_t bq_tiles(const BqJobDev *jobs, const WorkItem *items, const int32_t *n_items, int32_t *counter,

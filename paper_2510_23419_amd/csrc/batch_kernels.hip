@@ -56,312 +56,183 @@ __device__ __forceinline__ uint32_t neg2(uint32_t m, uint32_t keep, uint32_t fli
 // Sign mask of bit k of c: 0 or 0xFFFFFFFF.
 __device__ __forceinline__ uint32_t bit_mask(uint32_t c, int k) { return (uint32_t)((int32_t)(c << (31 - k)) >> 31); }
 
-// Spins of one 4-replica tile of the whole lattice live in LDS as one dword
-// per site (byte p = replica p, +1 = 0x01, -1 = 0xFF).  The field and the
-// decision use the cube stencil's arithmetic: bit 4 of a spin byte marks -1,
-// one bitop3 per neighbour gives 0x10 per byte where J m = +1, and the sum
-// with the site's base byte is 8 (I + 7), the LDS byte offset of the word
-// S(I) (Tm for I >= 0, 2^32 - Tm for I < 0) whose sum with the random word
-// carries into bit 32 exactly when the new spin is -1.  `one` is 1 (passed in
-// so that w * one + S is a single v_mad_u64_u32).
-__global__ __launch_bounds__(kEaTileThreads) void k_ea_tiles(const EaJobDev *__restrict__ jobs,
-                                                             const WorkItem *__restrict__ items,
-                                                             const int32_t *__restrict__ n_items_p,
-                                                             int32_t *__restrict__ counter, uint32_t one)
+// Cube tiles: the spins of 4W replicas (W = 1, 2 or 4) of the whole lattice live in
+// LDS as W dwords per site (byte p of dword k = replica 4k + p, +1 = 0x01, -1 = 0xFF;
+// for W = 4 the layout of the per-instance LDS-resident cube kernel), and the
+// problem's site list gives each class position's site index, wrap flags and code,
+// so that one site's addresses and code serve 4W updates.  The field and the
+// decision use the cube stencil's arithmetic: bit 4 of a spin byte marks -1, one
+// bitop3 per neighbour gives 0x10 per byte where J m = +1, and the sum with the
+// site's base byte is 8 (I + 7), the LDS byte offset of the word S(I) (Tm for
+// I >= 0, 2^32 - Tm for I < 0) whose sum with the random word carries into bit 32
+// exactly when the new spin is -1.  `one` is 1 (passed in so that w * one + S is a
+// single v_mad_u64_u32).
+template <int W>
+__device__ __forceinline__ void ea_tile_item(const WorkItem &w, const EaJobDev &jb, uint4 *tile_rows,
+                                             uint64_t *stab, int32_t *eacc, uint32_t one)
 {
-    extern __shared__ uint32_t sp[];
-    __shared__ uint64_t stab[kFieldSlots];
-    __shared__ int32_t eacc[4];
-    __shared__ int slot;
+    typedef uint32_t V __attribute__((ext_vector_type(W)));
+    constexpr int RS = 4 * W;  // replicas in the tile
+    V *rows = reinterpret_cast<V *>(tile_rows);  // [N]: the tile's replicas of every site
     const int tid = threadIdx.x;
-    const int n_items = *n_items_p;
     const char *tb = reinterpret_cast<const char *>(stab);
+    const int Lx = jb.Lx, Ly = jb.Ly, Lz = jb.Lz;
+    const int plane = Lx * Ly, N = plane * Lz, half = N / 2;
+    const uint32_t rgw = jb.rq0 + (uint32_t)W * (uint32_t)w.tile;  // Philox counter word 2 of the tile's first group
+    V *gst = reinterpret_cast<V *>(jb.state) + (size_t)w.tile * N;
+    // neighbour d of site i: i + step[d], or i + step[d] + fix[d] across the boundary
+    const int step[6] = {1, -1, Lx, -Lx, plane, -plane};
+    const int fix[6] = {-Lx, Lx, -plane, plane, -N, N};
 
-    for (;;) {
-        const int it = take_item(counter, &slot);
-        if (it >= n_items) break;
-        const WorkItem w = items[it];
-        const EaJobDev jb = jobs[w.job];
-        const int Lx = jb.Lx, Ly = jb.Ly, Lz = jb.Lz;
-        const int plane = Lx * Ly, N = plane * Lz, half = N / 2, hx = Lx / 2;
-        const float inv_hx = 1.0f / (float)hx, inv_Ly = 1.0f / (float)Ly, inv_Lx = 1.0f / (float)Lx;
-        const uint32_t rg = jb.rq0 + (uint32_t)w.tile;
-        uint32_t *gst = reinterpret_cast<uint32_t *>(jb.state) + (size_t)w.tile * N;
-
-        if (w.init) {
-            for (int i = tid; i < N; i += kEaTileThreads) {
-                const Block4 b = philox((uint32_t)i, 0u, rg, kDomainInit, jb.k0, jb.k1);
+    if (w.init) {
+        for (int i = tid; i < N; i += kEaTileThreads) {
+            V d;
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                const Block4 b = philox((uint32_t)i, 0u, rgw + (uint32_t)k, kDomainInit, jb.k0, jb.k1);
                 uint32_t packed = 0;
 #pragma unroll
                 for (int p = 0; p < 4; ++p) packed |= (uint32_t)(uint8_t)init_spin(b.w[p]) << (8 * p);
-                sp[i] = packed;
+                d[k] = packed;
             }
-        } else {
-            for (int i = tid; i < N; i += kEaTileThreads) sp[i] = gst[i];
+            rows[i] = d;
         }
+    } else {
+        for (int i = tid; i < N; i += kEaTileThreads) rows[i] = load_global<V>(gst + i);
+    }
 
-        for (int s = w.s_begin; s < w.s_end; ++s) {
-            __syncthreads();
-            if (tid < kFieldSlots) {
-                const uint32_t *trow = jb.table + (size_t)s * jb.width;
-                const int I = tid - kFieldOff;
-                const uint32_t T = load_global<uint32_t>(trow + min(I >= 0 ? I : -I, jb.width - 1));
-                stab[tid] = I >= 0 ? (uint64_t)T : ((uint64_t)1 << 32) - T;
-            }
-            __syncthreads();
-            const uint32_t t = jb.sweep0 + (uint32_t)s;
-            // one colour class: DENSE (every coupling nonzero) drops the per-bond keep masks
-            auto half_sweep = [&](int c, auto dense_tag) {
-                constexpr bool DENSE = decltype(dense_tag)::value;
-                for (int j = tid; j < half; j += kEaTileThreads) {
-                    int kx, y;
-                    const int row = div_small(j, hx, inv_hx, kx);
-                    const int z = div_small(row, Ly, inv_Ly, y);
-                    const int x = 2 * kx + ((c + y + z) & 1);
-                    const int i = x + Lx * y + plane * z;
-                    // a global load: the LDS reads below do not wait for it
-                    const uint32_t code = load_global<uint32_t>(jb.code + i);
-                    const int nb[6] = {x + 1 == Lx ? i - x : i + 1,
-                                       x == 0 ? i + Lx - 1 : i - 1,
-                                       y + 1 == Ly ? i - y * Lx : i + Lx,
-                                       y == 0 ? i + (Ly - 1) * Lx : i - Lx,
-                                       z + 1 == Lz ? i - z * plane : i + plane,
-                                       z == 0 ? i + (Lz - 1) * plane : i - plane};
-                    const Block4 b = philox((uint32_t)i, t, rg, kDomainSweep, jb.k0, jb.k1);
-                    uint32_t idx = __builtin_amdgcn_perm(0u, code, 0x03030303u);  // base byte in every byte
+    for (int s = w.s_begin; s < w.s_end; ++s) {
+        __syncthreads();
+        if (tid < kFieldSlots) {
+            const uint32_t *trow = jb.table + (size_t)s * jb.width;
+            const int I = tid - kFieldOff;
+            const uint32_t T = load_global<uint32_t>(trow + min(I >= 0 ? I : -I, jb.width - 1));
+            stab[tid] = I >= 0 ? (uint64_t)T : ((uint64_t)1 << 32) - T;
+        }
+        __syncthreads();
+        const uint32_t t = jb.sweep0 + (uint32_t)s;
+        auto half_sweep = [&](int c, auto dense_tag) {
+            constexpr bool DENSE = decltype(dense_tag)::value;
+            for (int j = tid; j < half; j += kEaTileThreads) {
+                const uint2 e = load_u2(jb.sites + (size_t)c * half + j);
+                const int i = (int)(e.x & 0xFFFFu);
+                const uint32_t wrap = e.x >> 16, code = e.y;
+                V v[6];
 #pragma unroll
-                    for (int d = 0; d < 6; ++d) {
-                        const uint32_t F = bit_mask(code, kCodeFlipShift + d);
-                        const uint32_t K = DENSE ? 0x10101010u : (bit_mask(code, d) & 0x10101010u);
-                        idx += __builtin_amdgcn_bitop3_b32(sp[nb[d]], F, K, 0x82);  // ~(a ^ b) & c
-                    }
+                for (int d = 0; d < 6; ++d) v[d] = rows[i + step[d] + (((wrap >> d) & 1u) ? fix[d] : 0)];
+                Block4 b[W];
+#pragma unroll
+                for (int r = 0; r < W; ++r)
+                    b[r] = philox((uint32_t)i, t, rgw + (uint32_t)r, kDomainSweep, jb.k0, jb.k1);
+                uint32_t tt[6][W];
+#pragma unroll
+                for (int d = 0; d < 6; ++d) {
+                    const uint32_t F = bit_mask(code, kCodeFlipShift + d);
+                    const uint32_t K = DENSE ? 0x10101010u : (bit_mask(code, d) & 0x10101010u);
+#pragma unroll
+                    for (int r = 0; r < W; ++r) tt[d][r] = __builtin_amdgcn_bitop3_b32(v[d][r], F, K, 0x82);
+                }
+                const uint32_t pos8 = __builtin_amdgcn_perm(0u, code, 0x03030303u);  // base byte in every byte
+                V out;
+#pragma unroll
+                for (int r = 0; r < W; ++r) {
+                    const uint32_t idx =
+                        (tt[0][r] + tt[1][r] + tt[2][r]) + (tt[3][r] + tt[4][r] + tt[5][r]) + pos8;
                     uint32_t sgn[4];  // 1: the replica's new spin is -1
 #pragma unroll
                     for (int p = 0; p < 4; ++p) {
                         const uint64_t S = *static_cast<const uint64_t *>(
                             __builtin_assume_aligned(tb + ((idx >> (8 * p)) & 0xFFu), 8));
-                        sgn[p] = (uint32_t)(((uint64_t)b.w[p] * one + S) >> 32);
+                        sgn[p] = (uint32_t)(((uint64_t)b[r].w[p] * one + S) >> 32);
                     }
                     const uint32_t lo = __builtin_amdgcn_perm(sgn[1], sgn[0], 0x0C0C0400u);
                     const uint32_t hi = __builtin_amdgcn_perm(sgn[3], sgn[2], 0x0C0C0400u);
-                    sp[i] = __builtin_amdgcn_perm(0u, 0xFF01u, __builtin_amdgcn_perm(hi, lo, 0x05040100u));
+                    out[r] = __builtin_amdgcn_perm(0u, 0xFF01u, __builtin_amdgcn_perm(hi, lo, 0x05040100u));
                 }
-            };
-            for (int c = 0; c < 2; ++c) {
-                if (jb.dense)
-                    half_sweep(c, std::true_type{});
-                else
-                    half_sweep(c, std::false_type{});
-                __syncthreads();
+                rows[i] = out;
+            }
+        };
+        for (int c = 0; c < 2; ++c) {
+            if (jb.dense)
+                half_sweep(c, std::true_type{});
+            else
+                half_sweep(c, std::false_type{});
+            __syncthreads();
+        }
+    }
+
+    // energies of the tile's replicas: every bond has exactly one end of colour 1 (the
+    // second half of the site list), so E = -sum_{i in colour 1} m_i sum_j J_ij m_j
+    // - sum_i h_i m_i
+    if (tid < RS) eacc[tid] = 0;
+    __syncthreads();
+    int32_t er[RS];
+#pragma unroll
+    for (int r = 0; r < RS; ++r) er[r] = 0;
+    for (int j = tid; j < N; j += kEaTileThreads) {
+        const int c = j < half ? 0 : 1;
+        const uint2 e = load_u2(jb.sites + j);  // colour 0 first, then colour 1
+        const int i = (int)(e.x & 0xFFFFu);
+        const uint32_t wrap = e.x >> 16, code = e.y;
+        const int nnz = __builtin_popcount(code & 63u);
+        const int hv = (int)(int8_t)(code >> kCodeBaseShift) - nnz;
+        const V mi = rows[i];
+        uint32_t cnt[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k) cnt[k] = 0u;
+        if (c == 1) {
+#pragma unroll
+            for (int d = 0; d < 6; ++d) {
+                const V v = rows[i + step[d] + (((wrap >> d) & 1u) ? fix[d] : 0)];
+                const uint32_t keep = ((code >> d) & 1u) * 0x02020202u;
+                const uint32_t flip = ((code >> (kCodeFlipShift + d)) & 1u) * 0x02020202u;
+#pragma unroll
+                for (int k = 0; k < W; ++k) cnt[k] += neg2(v[k], keep, flip);
             }
         }
-
-        // energies of the 4 replicas: every bond has exactly one colour-1 end,
-        // so E = -sum_{i in colour 1} m_i sum_j J_ij m_j - sum_i h_i m_i
-        if (tid < 4) eacc[tid] = 0;
-        __syncthreads();
-        int32_t e[4] = {0, 0, 0, 0};
-        for (int i = tid; i < N; i += kEaTileThreads) {
-            int x, y;
-            const int row = div_small(i, Lx, inv_Lx, x);
-            const int z = div_small(row, Ly, inv_Ly, y);
-            const uint32_t code = load_global<uint32_t>(jb.code + i);
-            const int nnz = __builtin_popcount(code & 63u);
-            const int hv = (int)(int8_t)(code >> kCodeBaseShift) - nnz;
-            const uint32_t mi = sp[i];
-            int bondsum[4] = {0, 0, 0, 0};
-            if ((x + y + z) & 1) {
-                const int nb[6] = {x + 1 == Lx ? i - x : i + 1,
-                                   x == 0 ? i + Lx - 1 : i - 1,
-                                   y + 1 == Ly ? i - y * Lx : i + Lx,
-                                   y == 0 ? i + (Ly - 1) * Lx : i - Lx,
-                                   z + 1 == Lz ? i - z * plane : i + plane,
-                                   z == 0 ? i + (Lz - 1) * plane : i - plane};
-                uint32_t cnt = 0;
 #pragma unroll
-                for (int d = 0; d < 6; ++d)
-                    cnt += neg2(sp[nb[d]], ((code >> d) & 1u) * 0x02020202u,
-                                ((code >> (kCodeFlipShift + d)) & 1u) * 0x02020202u);
-#pragma unroll
-                for (int p = 0; p < 4; ++p) bondsum[p] = nnz - (int)((cnt >> (8 * p)) & 0xFFu);
-            }
+        for (int k = 0; k < W; ++k)
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
-                const int m = (int)(int8_t)(mi >> (8 * p));
-                e[p] -= m * (bondsum[p] + hv);
+                const int m = (int)(int8_t)(mi[k] >> (8 * p));
+                const int bonds = c == 1 ? nnz - (int)((cnt[k] >> (8 * p)) & 0xFFu) : 0;
+                er[4 * k + p] -= m * (bonds + hv);
             }
-        }
-#pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            int v = e[p];
-            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-            if ((tid & 63) == 0) atomicAdd(&eacc[p], v);
-        }
-        __syncthreads();
-        if (tid < 4) jb.energy[4 * w.tile + tid] = eacc[tid];
-        for (int i = tid; i < N; i += kEaTileThreads) gst[i] = sp[i];
     }
+#pragma unroll
+    for (int r = 0; r < RS; ++r) {
+        int v = er[r];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if ((tid & 63) == 0) atomicAdd(&eacc[r], v);
+    }
+    __syncthreads();
+    if (tid < RS) jb.energy[RS * w.tile + tid] = eacc[tid];
+    for (int i = tid; i < N; i += kEaTileThreads) gst[i] = rows[i];
 }
 
-// A tile of 4W replicas (W = 2 or 4) of the whole lattice, W dwords per site (for
-// W = 4 the layout of the per-instance LDS-resident cube kernel): same field bytes,
-// Philox counters and carry decisions, and the problem's site list for indices,
-// wrap flags and codes.  Each site's index, code and neighbour addresses then serve
-// 4W updates instead of 4.
-template <int W>
-__global__ __launch_bounds__(kEaTileThreads) void k_ea_tiles_wide(const EaJobDev *__restrict__ jobs,
-                                                                  const WorkItem *__restrict__ items,
-                                                                  const int32_t *__restrict__ n_items_p,
-                                                                  int32_t *__restrict__ counter, uint32_t one)
+// Persistent cube-tile kernel: items of any tile width share the launch.
+__global__ __launch_bounds__(kEaTileThreads) void k_ea_tiles(const EaJobDev *__restrict__ jobs,
+                                                             const WorkItem *__restrict__ items,
+                                                             const int32_t *__restrict__ n_items_p,
+                                                             int32_t *__restrict__ counter, uint32_t one)
 {
-    typedef uint32_t V __attribute__((ext_vector_type(W)));
-    constexpr int RS = 4 * W;  // replicas in the tile
     extern __shared__ uint4 tile_rows[];
-    V *rows = reinterpret_cast<V *>(tile_rows);  // [N]: the tile's replicas of every site
     __shared__ uint64_t stab[kFieldSlots];
-    __shared__ int32_t eacc[RS];
+    __shared__ int32_t eacc[16];
     __shared__ int slot;
-    const int tid = threadIdx.x;
     const int n_items = *n_items_p;
-    const char *tb = reinterpret_cast<const char *>(stab);
-
     for (;;) {
         const int it = take_item(counter, &slot);
         if (it >= n_items) break;
         const WorkItem w = items[it];
         const EaJobDev jb = jobs[w.job];
-        const int Lx = jb.Lx, Ly = jb.Ly, Lz = jb.Lz;
-        const int plane = Lx * Ly, N = plane * Lz, half = N / 2;
-        const uint32_t rgw = jb.rq0 + (uint32_t)W * (uint32_t)w.tile;  // Philox counter word 2 of the tile's first group
-        V *gst = reinterpret_cast<V *>(jb.state) + (size_t)w.tile * N;
-        // neighbour d of site i: i + step[d], or i + step[d] + fix[d] across the boundary
-        const int step[6] = {1, -1, Lx, -Lx, plane, -plane};
-        const int fix[6] = {-Lx, Lx, -plane, plane, -N, N};
-
-        if (w.init) {
-            for (int i = tid; i < N; i += kEaTileThreads) {
-                V d;
-#pragma unroll
-                for (int k = 0; k < W; ++k) {
-                    const Block4 b = philox((uint32_t)i, 0u, rgw + (uint32_t)k, kDomainInit, jb.k0, jb.k1);
-                    uint32_t packed = 0;
-#pragma unroll
-                    for (int p = 0; p < 4; ++p) packed |= (uint32_t)(uint8_t)init_spin(b.w[p]) << (8 * p);
-                    d[k] = packed;
-                }
-                rows[i] = d;
-            }
-        } else {
-            for (int i = tid; i < N; i += kEaTileThreads) rows[i] = load_global<V>(gst + i);
-        }
-
-        for (int s = w.s_begin; s < w.s_end; ++s) {
-            __syncthreads();
-            if (tid < kFieldSlots) {
-                const uint32_t *trow = jb.table + (size_t)s * jb.width;
-                const int I = tid - kFieldOff;
-                const uint32_t T = load_global<uint32_t>(trow + min(I >= 0 ? I : -I, jb.width - 1));
-                stab[tid] = I >= 0 ? (uint64_t)T : ((uint64_t)1 << 32) - T;
-            }
-            __syncthreads();
-            const uint32_t t = jb.sweep0 + (uint32_t)s;
-            auto half_sweep = [&](int c, auto dense_tag) {
-                constexpr bool DENSE = decltype(dense_tag)::value;
-                for (int j = tid; j < half; j += kEaTileThreads) {
-                    const uint2 e = load_u2(jb.sites + (size_t)c * half + j);
-                    const int i = (int)(e.x & 0xFFFFu);
-                    const uint32_t wrap = e.x >> 16, code = e.y;
-                    V v[6];
-#pragma unroll
-                    for (int d = 0; d < 6; ++d) v[d] = rows[i + step[d] + (((wrap >> d) & 1u) ? fix[d] : 0)];
-                    Block4 b[W];
-#pragma unroll
-                    for (int r = 0; r < W; ++r)
-                        b[r] = philox((uint32_t)i, t, rgw + (uint32_t)r, kDomainSweep, jb.k0, jb.k1);
-                    uint32_t tt[6][W];
-#pragma unroll
-                    for (int d = 0; d < 6; ++d) {
-                        const uint32_t F = bit_mask(code, kCodeFlipShift + d);
-                        const uint32_t K = DENSE ? 0x10101010u : (bit_mask(code, d) & 0x10101010u);
-#pragma unroll
-                        for (int r = 0; r < W; ++r) tt[d][r] = __builtin_amdgcn_bitop3_b32(v[d][r], F, K, 0x82);
-                    }
-                    const uint32_t pos8 = __builtin_amdgcn_perm(0u, code, 0x03030303u);  // base byte in every byte
-                    V out;
-#pragma unroll
-                    for (int r = 0; r < W; ++r) {
-                        const uint32_t idx =
-                            (tt[0][r] + tt[1][r] + tt[2][r]) + (tt[3][r] + tt[4][r] + tt[5][r]) + pos8;
-                        uint32_t sgn[4];  // 1: the replica's new spin is -1
-#pragma unroll
-                        for (int p = 0; p < 4; ++p) {
-                            const uint64_t S = *static_cast<const uint64_t *>(
-                                __builtin_assume_aligned(tb + ((idx >> (8 * p)) & 0xFFu), 8));
-                            sgn[p] = (uint32_t)(((uint64_t)b[r].w[p] * one + S) >> 32);
-                        }
-                        const uint32_t lo = __builtin_amdgcn_perm(sgn[1], sgn[0], 0x0C0C0400u);
-                        const uint32_t hi = __builtin_amdgcn_perm(sgn[3], sgn[2], 0x0C0C0400u);
-                        out[r] = __builtin_amdgcn_perm(0u, 0xFF01u, __builtin_amdgcn_perm(hi, lo, 0x05040100u));
-                    }
-                    rows[i] = out;
-                }
-            };
-            for (int c = 0; c < 2; ++c) {
-                if (jb.dense)
-                    half_sweep(c, std::true_type{});
-                else
-                    half_sweep(c, std::false_type{});
-                __syncthreads();
-            }
-        }
-
-        // energies of the tile's replicas: every bond has exactly one end of colour 1 (the
-        // second half of the site list), so E = -sum_{i in colour 1} m_i sum_j J_ij m_j
-        // - sum_i h_i m_i
-        if (tid < RS) eacc[tid] = 0;
-        __syncthreads();
-        int32_t er[RS];
-#pragma unroll
-        for (int r = 0; r < RS; ++r) er[r] = 0;
-        for (int j = tid; j < N; j += kEaTileThreads) {
-            const int c = j < half ? 0 : 1;
-            const uint2 e = load_u2(jb.sites + j);  // colour 0 first, then colour 1
-            const int i = (int)(e.x & 0xFFFFu);
-            const uint32_t wrap = e.x >> 16, code = e.y;
-            const int nnz = __builtin_popcount(code & 63u);
-            const int hv = (int)(int8_t)(code >> kCodeBaseShift) - nnz;
-            const V mi = rows[i];
-            uint32_t cnt[W];
-#pragma unroll
-            for (int k = 0; k < W; ++k) cnt[k] = 0u;
-            if (c == 1) {
-#pragma unroll
-                for (int d = 0; d < 6; ++d) {
-                    const V v = rows[i + step[d] + (((wrap >> d) & 1u) ? fix[d] : 0)];
-                    const uint32_t keep = ((code >> d) & 1u) * 0x02020202u;
-                    const uint32_t flip = ((code >> (kCodeFlipShift + d)) & 1u) * 0x02020202u;
-#pragma unroll
-                    for (int k = 0; k < W; ++k) cnt[k] += neg2(v[k], keep, flip);
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < W; ++k)
-#pragma unroll
-                for (int p = 0; p < 4; ++p) {
-                    const int m = (int)(int8_t)(mi[k] >> (8 * p));
-                    const int bonds = c == 1 ? nnz - (int)((cnt[k] >> (8 * p)) & 0xFFu) : 0;
-                    er[4 * k + p] -= m * (bonds + hv);
-                }
-        }
-#pragma unroll
-        for (int r = 0; r < RS; ++r) {
-            int v = er[r];
-            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-            if ((tid & 63) == 0) atomicAdd(&eacc[r], v);
-        }
-        __syncthreads();
-        if (tid < RS) jb.energy[RS * w.tile + tid] = eacc[tid];
-        for (int i = tid; i < N; i += kEaTileThreads) gst[i] = rows[i];
+        if (jb.rs == 16)
+            ea_tile_item<4>(w, jb, tile_rows, stab, eacc, one);
+        else if (jb.rs == 8)
+            ea_tile_item<2>(w, jb, tile_rows, stab, eacc, one);
+        else
+            ea_tile_item<1>(w, jb, tile_rows, stab, eacc, one);
+        __syncthreads();  // the next item's first LDS writes wait for this item's last reads
     }
 }
 
@@ -866,12 +737,7 @@ hipError_t tiles_set_lds_limit()
     const int max_lds = 160 * 1024 - 4096;  // leave room for the static shared variables
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ea_tiles),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ea_tiles_wide<2>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ea_tiles_wide<4>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+
     const void *bq_kernels[] = {reinterpret_cast<const void *>(&k_bq_tiles_bits<1>),
                                 reinterpret_cast<const void *>(&k_bq_tiles_bits<2>),
                                 reinterpret_cast<const void *>(&k_bq_tiles_bits<4>),
@@ -891,20 +757,6 @@ hipError_t ea_tiles(const EaJobDev *jobs, const WorkItem *items, const int32_t *
 {
     hipLaunchKernelGGL(k_ea_tiles, dim3((unsigned)grid), dim3(kEaTileThreads), lds_bytes, st, jobs, items, n_items,
                        counter, 1u);
-    return hipGetLastError();
-}
-
-hipError_t ea_tiles_wide(const EaJobDev *jobs, const WorkItem *items, const int32_t *n_items, int32_t *counter, int rs,
-                         int grid, size_t lds_bytes, hipStream_t st)
-{
-    if (rs == 8)
-        hipLaunchKernelGGL(k_ea_tiles_wide<2>, dim3((unsigned)grid), dim3(kEaTileThreads), lds_bytes, st, jobs, items,
-                           n_items, counter, 1u);
-    else if (rs == 16)
-        hipLaunchKernelGGL(k_ea_tiles_wide<4>, dim3((unsigned)grid), dim3(kEaTileThreads), lds_bytes, st, jobs, items,
-                           n_items, counter, 1u);
-    else
-        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

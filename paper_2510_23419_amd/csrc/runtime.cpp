@@ -16,6 +16,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/pbit.h"
@@ -68,22 +69,46 @@ uint32_t minority_threshold(double beta, int a)
 
 // Width of the per-sweep rows actually needed: |I| never exceeds amax, and
 // beyond the first a at which every row is 0 all entries are 0 (Tm is
-// non-increasing in a), so the kernel clamps |I| to width - 1.
+// non-increasing in a), so the kernel clamps |I| to width - 1.  Tm is also
+// non-increasing in beta for a >= 1 (every step of its evaluation is monotone),
+// so the row of the smallest beta is the last to reach 0.
 int table_width(const double *beta, int S, int amax)
 {
-    int need = 0;
-    for (int s = 0; s < S && need < amax; ++s) {
-        int a = 0;
-        while (a <= amax && minority_threshold(beta[s], a) != 0u) ++a;
-        need = std::max(need, std::min(a, amax));
-    }
-    return need + 1;
+    if (S <= 0) return 1;
+    double bmin = beta[0];
+    for (int s = 1; s < S; ++s) bmin = std::min(bmin, beta[s]);
+    int a = 0;
+    while (a <= amax && minority_threshold(bmin, a) != 0u) ++a;
+    return std::min(a, amax) + 1;
 }
 
+// Rows of the table; large tables (a biclique schedule: thousands of sweeps by
+// hundreds of field values, one exp each) are split over up to 16 host threads.
 void build_table(const double *beta, int S, int width, uint32_t *out)
 {
-    for (int s = 0; s < S; ++s)
-        for (int a = 0; a < width; ++a) out[(size_t)s * width + a] = minority_threshold(beta[s], a);
+    auto rows = [=](int s0, int s1) {
+        for (int s = s0; s < s1; ++s)
+            for (int a = 0; a < width; ++a) out[(size_t)s * width + a] = minority_threshold(beta[s], a);
+    };
+    const size_t cells = (size_t)S * width;
+    const int nt = (int)std::min<size_t>({(size_t)16, (size_t)std::max(1u, std::thread::hardware_concurrency()),
+                                          cells >> 15, (size_t)std::max(S, 1)});
+    if (nt < 2) {
+        rows(0, S);
+        return;
+    }
+    std::vector<std::thread> pool;
+    pool.reserve((size_t)nt - 1);
+    for (int t = 1; t < nt; ++t) {
+        const int s0 = (int)((int64_t)S * t / nt), s1 = (int)((int64_t)S * (t + 1) / nt);
+        try {
+            pool.emplace_back(rows, s0, s1);
+        } catch (...) {
+            rows(s0, s1);  // no thread: this one does the rows
+        }
+    }
+    rows(0, (int)((int64_t)S / nt));
+    for (std::thread &th : pool) th.join();
 }
 
 }  // namespace pbit

@@ -29,9 +29,9 @@ int spins_in_range(const int8_t *s, size_t n);  // runtime.cpp
 namespace {
 
 constexpr int kMaxLdsTile = 160 * 1024 - 4096;
-// tile kinds: 4-replica cube tiles; 128-, 64-, 32-replica biclique tiles; 16- and 8-replica cube tiles
-constexpr int kKinds = 6;
-constexpr int kKindEa16 = 4, kKindEa8 = 5;
+// tile kinds, one persistent launch and one stream each: cube tiles (4, 8 or 16
+// replicas, one launch); 128-, 64- and 32-replica biclique tiles
+constexpr int kKinds = 4;
 inline int kind_of_rs(int rs) { return rs == 128 ? 1 : (rs == 64 ? 2 : 3); }
 constexpr double kItemOps = 1.5e11;  // multiply-adds of one biclique tile over its anneal
 inline int rs_of_kind(int k) { return k == 1 ? 128 : (k == 2 ? 64 : 32); }
@@ -179,11 +179,13 @@ static int plan_job(pbit_ctx *ctx, BJob &j)
     if (P.kind == PBIT_EA3D) {
         if (ea_tile_lds(P.N, 4) > (size_t)kMaxLdsTile || P.ea.Lx > 1024 || P.ea.Ly > 1024)
             return fail(PBIT_E_UNSUPPORTED, "cube of %lld sites is too large for a batched tile", (long long)P.N);
-        // the widest tile (16 or 8 replicas, one 16- or 8-byte row per site) that the job
-        // fills and the LDS holds, where the lattice has a site list; 4 replicas otherwise
+        // the widest tile (16, 8 or 4 replicas: a 16-, 8- or 4-byte row per site) that the
+        // job fills and the LDS holds
+        if (!P.tile_sites)
+            return fail(PBIT_E_UNSUPPORTED, "cube of %lld sites has no site list", (long long)P.N);
         j.rs = 4;
         for (int rs : {16, 8})
-            if (P.tile_sites && j.R >= rs && ea_tile_lds(P.N, rs) <= (size_t)kMaxLdsTile) {
+            if (j.R >= rs && ea_tile_lds(P.N, rs) <= (size_t)kMaxLdsTile) {
                 j.rs = rs;
                 break;
             }
@@ -328,15 +330,18 @@ static int launch_round(pbit_ctx *ctx, ServeState &s)
         const Key key{(uint32_t)j->d.seed, (uint32_t)(j->d.seed >> 32)};
         if (j->kind == PBIT_EA3D) {
             const EaView &v = j->P->ea;
-            EaJobDev jd{v.code, reinterpret_cast<const uint2 *>(j->P->tile_sites), (const uint32_t *)j->d_table, (int8_t *)j->d_state, (int32_t *)j->d_energy,
-                        v.Lx, v.Ly, v.Lz, j->width, v.dense ? 1 : 0, (uint32_t)j->d.sweep_offset,
-                        (uint32_t)j->d.replica_offset >> 2, key.k0, key.k1};
+            EaJobDev jd{reinterpret_cast<const uint2 *>(j->P->tile_sites),
+                        (const uint32_t *)j->d_table,
+                        (int8_t *)j->d_state,
+                        (int32_t *)j->d_energy,
+                        v.Lx, v.Ly, v.Lz, j->width, j->rs, v.dense ? 1 : 0,
+                        (uint32_t)j->d.sweep_offset, (uint32_t)j->d.replica_offset >> 2, key.k0, key.k1};
             const int idx = (int)ea.size();
             ea.push_back(jd);
-            const int k = j->rs == 16 ? kKindEa16 : (j->rs == 8 ? kKindEa8 : 0);
+            const int k = 0;
             for (int t = 0; t < j->tiles; ++t) {
                 items[k].push_back(WorkItem{idx, t, s0, s1, j->started ? 0 : 1, {0, 0, 0}});
-                cost[k].push_back((double)(s1 - s0) * j->N);
+                cost[k].push_back((double)(s1 - s0) * j->N * j->rs);
             }
             lds[k] = std::max(lds[k], ea_tile_lds(j->N, j->rs));
         } else {
@@ -400,9 +405,6 @@ static int launch_round(pbit_ctx *ctx, ServeState &s)
         if (k == 0)
             e = ea_tiles((const EaJobDev *)s.d_ea_jobs, (const WorkItem *)s.d_items[0], s.d_meta + kKinds,
                          s.d_meta + 0, grid, lds[0], s.st[0]);
-        else if (k == kKindEa16 || k == kKindEa8)
-            e = ea_tiles_wide((const EaJobDev *)s.d_ea_jobs, (const WorkItem *)s.d_items[k], s.d_meta + kKinds + k,
-                              s.d_meta + k, k == kKindEa16 ? 16 : 8, grid, lds[k], s.st[k]);
         else
             e = bq_tiles((const BqJobDev *)s.d_bq_jobs[k - 1], (const WorkItem *)s.d_items[k], s.d_meta + kKinds + k,
                          s.d_meta + k, rs_of_kind(k), tile_mode(ctx), grid, lds[k], s.st[k]);
