@@ -42,6 +42,16 @@ def test_threshold_table_equals_oracle_entry_by_entry(beta):
     assert np.array_equal(lib_tab, ref)
 
 
+def test_large_threshold_table_split_over_threads_equals_oracle():
+    """A biclique-sized table (2000 sweeps x 256 field values: built by several
+    host threads, each a band of rows) equals the oracle entry by entry."""
+    beta = np.geomspace(0.05, 2.0, 2000)
+    A = 255
+    lib_tab = pbit.pbit_threshold_table(beta, A)
+    ref = oracle.threshold_table(beta, A)
+    assert np.array_equal(lib_tab, ref)
+
+
 def test_threshold_table_rejects_bad_beta():
     for bad in (np.nan, -0.1, np.inf):
         with pytest.raises(pbit.PbitError) as ei:
