@@ -84,14 +84,15 @@ int table_width(const double *beta, int S, int amax)
 
 // Rows of the table; large tables (a biclique schedule: thousands of sweeps by
 // hundreds of field values, one exp each) are split over up to 16 host threads.
-void build_table(const double *beta, int S, int width, uint32_t *out)
+void build_table(const double *beta, int S, int width, uint32_t *out, int max_threads)
 {
     auto rows = [=](int s0, int s1) {
         for (int s = s0; s < s1; ++s)
             for (int a = 0; a < width; ++a) out[(size_t)s * width + a] = minority_threshold(beta[s], a);
     };
     const size_t cells = (size_t)S * width;
-    const int nt = (int)std::min<size_t>({(size_t)16, (size_t)std::max(1u, std::thread::hardware_concurrency()),
+    const int nt = (int)std::min<size_t>({(size_t)std::max(max_threads, 1), (size_t)16,
+                                          (size_t)std::max(1u, std::thread::hardware_concurrency()),
                                           cells >> 15, (size_t)std::max(S, 1)});
     if (nt < 2) {
         rows(0, S);

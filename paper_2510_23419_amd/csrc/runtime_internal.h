@@ -80,7 +80,7 @@ Problem *find_problem(pbit_ctx *ctx, uint64_t handle);
 int check_desc(const pbit_anneal_desc *d, const char *who);
 uint32_t minority_threshold(double beta, int a);
 int table_width(const double *beta, int S, int amax);
-void build_table(const double *beta, int S, int width, uint32_t *out);
+void build_table(const double *beta, int S, int width, uint32_t *out, int max_threads = 16);
 void serve_shutdown(pbit_ctx *ctx);
 int spins_in_range(const int8_t *s, size_t n);
 int greedy_colouring(int n, int n_bonds, const int32_t *bi, const int32_t *bj, uint8_t *colour, int *n_colours);

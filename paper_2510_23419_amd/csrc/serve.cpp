@@ -11,10 +11,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <deque>
 #include <memory>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "batch.h"
@@ -43,6 +45,7 @@ struct BJob {
     pbit_anneal_desc d{};
     std::vector<double> beta;
     std::vector<int8_t> init;
+    std::vector<uint32_t> table;  // threshold rows built ahead of admission (batch calls), else empty
     int kind = 0, N = 0, R = 0, S = 0;
     int rs = 4, tiles = 0, width = 1, chunk = 1;
     int mode = kTileInt8;  // biclique tile operands: int8 rows (default), spin bits or packed 4-bit floats
@@ -282,8 +285,13 @@ static int admit(pbit_ctx *ctx, BJob &j)
         j.d_table = j.d_state = j.d_energy = nullptr;
         return rc;
     }
-    std::vector<uint32_t> tab((size_t)std::max(j.S, 1) * j.width, 0u);
-    if (j.S > 0) build_table(j.beta.data(), j.S, j.width, tab.data());
+    std::vector<uint32_t> tab;
+    if (j.table.size() == (size_t)std::max(j.S, 1) * j.width) {
+        tab.swap(j.table);
+    } else {
+        tab.assign((size_t)std::max(j.S, 1) * j.width, 0u);
+        if (j.S > 0) build_table(j.beta.data(), j.S, j.width, tab.data());
+    }
     hipError_t e = hipMemcpy(j.d_table, tab.data(), sizeof(uint32_t) * tab.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !j.init.empty()) {
         std::vector<int8_t> tl;
@@ -295,6 +303,45 @@ static int admit(pbit_ctx *ctx, BJob &j)
     j.admitted = true;
     j.energy.assign(j.R, 0);
     return PBIT_OK;
+}
+
+// Threshold tables of a batch's jobs, built side by side on up to 16 host threads (one
+// job per thread at a time) before admission, up to 1 GiB of them; admission builds the
+// rest (and any a thread could not allocate).
+static void prebuild_tables(const std::vector<BJob *> &js)
+{
+    std::vector<BJob *> todo;
+    size_t bytes = 0;
+    for (BJob *j : js) {
+        const size_t b = sizeof(uint32_t) * (size_t)std::max(j->S, 1) * j->width;
+        if (j->S <= 0 || bytes + b > ((size_t)1 << 30)) continue;
+        bytes += b;
+        todo.push_back(j);
+    }
+    std::atomic<size_t> next{0};
+    auto work = [&]() {
+        for (size_t q; (q = next++) < todo.size();) {
+            BJob &j = *todo[q];
+            try {
+                j.table.assign((size_t)j.S * j.width, 0u);
+                build_table(j.beta.data(), j.S, j.width, j.table.data(), 1);
+            } catch (...) {
+                std::vector<uint32_t>().swap(j.table);
+            }
+        }
+    };
+    const int nt = (int)std::min<size_t>({(size_t)16, (size_t)std::max(1u, std::thread::hardware_concurrency()),
+                                          todo.size()});
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nt; ++t) {
+        try {
+            pool.emplace_back(work);
+        } catch (...) {
+            break;
+        }
+    }
+    work();
+    for (std::thread &th : pool) th.join();
 }
 
 static void release(pbit_ctx *ctx, BJob &j)
@@ -638,6 +685,7 @@ extern "C" int pbit_anneal_batch(pbit_ctx *ctx, const pbit_batch_job *jobs, int3
             j->user = jobs[k].result;
             mine.push_back(j);
         }
+        prebuild_tables(mine);
         for (;;) {
             bool all = true;
             for (BJob *m : mine) all = all && m->finished;
