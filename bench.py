@@ -29,10 +29,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 INT8_MFMA_PEAK_TOPS = 5000.0   # MI355X dense int8 MFMA, published (TOP/s)
-FP4_MFMA_PEAK_TOPS = 10100.0   # MI355X dense fp4 MFMA, published (TOP/s)
 # biclique half-sweep kernels by variant number (pbit_profile_variant)
-BQ_KERNELS = {1: "k_bq_halfsweep", 2: "k_bq_halfsweep_t128", 3: "k_bq_halfsweep_t128", 4: "k_bq_halfsweep_t128",
-              5: "k_bq_halfsweep_dma", 6: "k_bq_halfsweep_dma", 7: "k_bq_halfsweep_fp4", 8: "k_bq_halfsweep_bits"}
+BQ_KERNELS = {1: "k_bq_halfsweep", 2: "k_bq_halfsweep_dma", 3: "k_bq_halfsweep_bits"}
 VALU_PEAK_TLANEOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 32-bit vector lane-ops/s: CUs x SIMDs x lanes x clock
 
 WORKLOADS = {
@@ -177,9 +175,9 @@ def measured_traffic(workload):
 
 
 def _bag_dtype():
-    """Arithmetic of the batched tiles: int8 spins everywhere, biclique fields as
-    int8 MFMA products with int32 sums, or fp4 products (exact) on request."""
-    return "int8 (biclique fields fp4)" if os.environ.get("PBIT_BQ_VARIANT", "") == "7" else "int8"
+    """Arithmetic of the batched tiles: int8 spins and couplings, biclique fields as
+    int8 MFMA products with int32 sums."""
+    return "int8"
 
 
 def mixed_bag_bench(args, pbit, torch):
@@ -493,15 +491,11 @@ def main():
     else:
         n = w["n"]
         alg_ops = 2 * n * n * R  # one side's fields: n x n couplings times n x R spins
-        # the kernel the library ran (autotuned among int8-operand variants unless
-        # PBIT_BQ_VARIANT forces one; 7 = packed 4-bit float operands). The roofline
-        # takes the peak of the operand type that ran
+        # the kernel the library ran (autotuned unless PBIT_BQ_VARIANT forces one)
         variant = pbit.pbit_profile_variant(ctx.ctx)
-        fp4 = variant == 7
         roof = {"bound": "mfma", "achieved": alg_ops / (avg_ms * 1e-3) / 1e12,
-                "peak": FP4_MFMA_PEAK_TOPS if fp4 else INT8_MFMA_PEAK_TOPS, "unit": "TOP/s", "traffic": None,
-                "kernel": BQ_KERNELS.get(variant, "k_bq_halfsweep"), "variant": variant,
-                "operands": "fp4" if fp4 else "int8",
+                "peak": INT8_MFMA_PEAK_TOPS, "unit": "TOP/s", "traffic": None,
+                "kernel": BQ_KERNELS.get(variant, "k_bq_halfsweep"), "variant": variant, "operands": "int8",
                 "alg_ops_per_launch": alg_ops, "avg_launch_us": avg_ms * 1e3, "launches_timed": launches}
     if launches == 0:  # launch timing switched off (--profile-every 0)
         roof["achieved"] = None

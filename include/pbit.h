@@ -211,7 +211,9 @@ typedef struct {
     pbit_result *result;      /* filled as by pbit_anneal (spin_trace is not supported) */
 } pbit_batch_job;
 
-/* Run all jobs and wait for them. */
+/* Run all jobs and wait for them.  A job whose device memory does not fit the
+ * budget while no other job runs fails the call with E_NOMEM; the call's other
+ * jobs are then withdrawn (their results may be partly written). */
 int pbit_anneal_batch(pbit_ctx *ctx, const pbit_batch_job *jobs, int32_t n_jobs);
 
 /* ---- serving: continuous batching of anneal jobs ------------------------- */
@@ -228,7 +230,11 @@ int pbit_submit(pbit_ctx *ctx, uint64_t problem, const pbit_anneal_desc *desc, u
 
 /* PBIT_PENDING while the job is queued or running; PBIT_OK once it is done,
  * after filling `result` (same fields as pbit_anneal; spin_trace not
- * supported); the job id is then retired.  E_HANDLE for unknown ids. */
+ * supported); the job id is then retired.  E_HANDLE for unknown ids.  E_NOMEM
+ * (the id is retired, `result` untouched) when the job reached the head of the
+ * queue but its device memory did not fit the budget while no job was running:
+ * memory held by problems, by other calls' scratch or by finished jobs not yet
+ * polled is never freed by the scheduler, so the job cannot wait for it. */
 int pbit_poll(pbit_ctx *ctx, uint64_t job, pbit_result *result);
 
 /* Drive the scheduler without waiting: harvest a finished round, admit queued
@@ -254,11 +260,13 @@ int pbit_profile_enable(pbit_ctx *ctx, int32_t every);
 int pbit_profile_read(pbit_ctx *ctx, int32_t kind, double *total_ms, int64_t *launches, int32_t reset);
 
 /* The biclique half-sweep kernel the latest biclique anneal on this context ran
- * (0 before any): 1 = 64 x 64 tiles from global memory, 2..4 = LDS-tiled with a
- * register ring, 5, 6 = LDS-tiled through the global-to-LDS DMA, 7 = packed 4-bit
- * float operands, 8 = spins held as bits.  The library picks the fastest on the
- * first anneal of a shape unless PBIT_BQ_VARIANT names one when the context is
- * created.  *variant is written on success only. */
+ * (0 before any): 1 = 64 x 64 tiles from global memory (any side), 2 = 128 x 128
+ * tiles staged in LDS by the global-to-LDS DMA (sides padded to 128), 3 = spins
+ * held as bits, 64 x 256 tiles (sides padded to 128, replicas to 256).  The
+ * library times the kernels the shape can take on the first anneal of a shape
+ * and keeps the fastest, unless PBIT_BQ_VARIANT (1..3) names one when the context
+ * is created; a named kernel the shape cannot take falls back to the timed
+ * choice.  All give the same spins.  *variant is written on success only. */
 int pbit_profile_variant(pbit_ctx *ctx, int32_t *variant);
 
 /* The cube path of the latest cube anneal on this context (0 before any): 1 = the

@@ -27,15 +27,13 @@ struct EaJobDev {
 
 struct BqJobDev {
     const int8_t *J, *JT;     // int8 couplings [na_p][nb_p], [nb_p][na_p]
-    const uint8_t *J4, *JT4;  // packed 4-bit float couplings [na_p][nb_p / 2], [nb_p][na_p / 2]
     const int8_t *Jb, *JTb;   // couplings in the widened-bit column order, scaled (bit tiles)
     const int32_t *hA2, *hB2; // field plus coupling sum per site (bit tiles)
     const uint32_t *J2, *JT2; // J + 1 as two-bit codes in fragment order (int8 tiles)
     const int8_t *hA, *hB;    // [na_p], [nb_p]
     const uint32_t *table;    // [S][width]
     uint8_t *state;           // [tiles][RS][row]: row r = side A then side B, as int8 (na_p + nb_p
-                              // bytes, the default), bits ((na_p + nb_p) / 8 bytes) or packed 4-bit
-                              // floats ((na_p + nb_p) / 2 bytes)
+                              // bytes, the default) or bits ((na_p + nb_p) / 8 bytes)
     int32_t *energy;        // [tiles * RS]
     int na, nb, na_p, nb_p, width;
     uint32_t sweep0, rq0, k0, k1;
@@ -58,7 +56,7 @@ constexpr int kBqTileThreads = 512;
 hipError_t ea_tiles(const EaJobDev *jobs, const WorkItem *items, const int32_t *n_items, int32_t *counter,
                     int grid, size_t lds_bytes, hipStream_t st);
 // operand modes of the biclique tiles
-constexpr int kTileInt8 = 0, kTileFp4 = 1, kTileBits = 2;
+constexpr int kTileInt8 = 0, kTileBits = 2;
 hipError_t bq_tiles(const BqJobDev *jobs, const WorkItem *items, const int32_t *n_items, int32_t *counter,
                     int rs, int mode, int grid, size_t lds_bytes, hipStream_t st);
 

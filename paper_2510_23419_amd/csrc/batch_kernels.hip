@@ -260,9 +260,6 @@ __device__ __forceinline__ uint32_t quad_transpose(uint32_t d, int u)
     return __builtin_amdgcn_perm(t2, d1, (u & 2) ? 0x03020706u : 0x05040100u);
 }
 
-__device__ __forceinline__ uint32_t fp4_code(int m) { return m > 0 ? 0x2u : (m < 0 ? 0xAu : 0x0u); }
-__device__ __forceinline__ int fp4_value(uint32_t nib) { return nib == 0 ? 0 : ((nib & 8u) ? -1 : 1); }
-
 // Four dwords of int8 K bytes from one word of two-bit codes: byte i of dword j is
 // the code at bits 2 j, 2 j + 1 of byte i (the value J + 1 in {0, 1, 2}).
 __device__ __forceinline__ v4i widen_codes(uint32_t x)
@@ -275,18 +272,6 @@ __device__ __forceinline__ v4i widen_codes(uint32_t x)
 __device__ __forceinline__ int byte_sum(uint32_t x)
 {
     return (int)((x & 0xFFu) + ((x >> 8) & 0xFFu) + ((x >> 16) & 0xFFu) + (x >> 24));
-}
-
-typedef int v8i __attribute__((ext_vector_type(8)));
-typedef float v16f __attribute__((ext_vector_type(16)));
-
-// fp4 MFMA with unit block scales (E8M0 127), e2m1 for both operands; the 16
-// bytes of a fragment are the low half of the 32-byte operand
-__device__ __forceinline__ v16f mfma_fp4(v4i a, v4i b, v16f c)
-{
-    const v8i a8 = {a[0], a[1], a[2], a[3], 0, 0, 0, 0};
-    const v8i b8 = {b[0], b[1], b[2], b[3], 0, 0, 0, 0};
-    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a8, b8, c, 4, 4, 0, 127, 0, 127);
 }
 
 // Biclique tiles with the spins held as bits in LDS: row r holds one bit per site (set = -1), 32 sites per word, side A
@@ -465,26 +450,20 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles_bits(const BqJobDev
 // accumulation; the couplings stream as two-bit codes of J + 1 (a quarter of
 // the int8 bytes: these tiles are bound by how fast a CU pulls couplings from
 // L2), widened to bytes in registers, and the field is the product minus the
-// replica's sum over the other side's spins; with FP4 operands a row holds packed 4-bit floats (e2m1: +1 =
-// 0x2, -1 = 0xA, 0 = 0x0; two sites per byte, lower site in the low nibble) and
-// the half-sweep is the f8f6f4 MFMA with fp32 accumulation — exact, since every
-// value is -1, 0 or +1 and every partial sum an integer below 2^24 — at half
-// the bytes per multiply-add.  Each half-sweep multiplies the LDS rows by the
+// replica's sum over the other side's spins.  Each half-sweep multiplies the LDS rows by the
 // couplings streamed from global memory (L2-resident, shared by all tiles of
 // the job); each coupling fragment feeds RB MFMAs, so larger tiles stream
 // fewer bytes per replica.  The decision epilogue writes the new side into LDS.
-template <int RB, bool FP4>
+template <int RB>
 __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__restrict__ jobs,
                                                              const WorkItem *__restrict__ items,
                                                              const int32_t *__restrict__ n_items_p,
                                                              int32_t *__restrict__ counter, uint32_t one)
 {
     constexpr int RS = 32 * RB;
-    constexpr int SH = FP4 ? 1 : 0;  // log2 of sites per byte
-    using Acc = typename std::conditional<FP4, v16f, v16i>::type;
     extern __shared__ uint4 dyn[];
     __shared__ int32_t eacc[RS];
-    __shared__ int32_t mag[RS];  // int8 codes: sum of the other side's spins per replica
+    __shared__ int32_t mag[RS];  // sum of the other side's spins per replica
     __shared__ int slot;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6, ln = lane & 31, kg = lane >> 5;
@@ -496,7 +475,7 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
         const WorkItem w = items[it];
         const BqJobDev jb = jobs[w.job];
         const int na = jb.na, nb = jb.nb, na_p = jb.na_p, nb_p = jb.nb_p;
-        const int pa = na_p >> SH, pb = nb_p >> SH;  // bytes of each side in a row
+        const int pa = na_p, pb = nb_p;  // bytes of each side in a row
         const int PR = pa + pb, pitch = PR + 16;
         uint8_t *sp = reinterpret_cast<uint8_t *>(dyn);
         // decision words of the sweep: S(I) = Tm(|I|) for I >= 0, 2^32 - Tm(|I|) for I < 0,
@@ -513,21 +492,12 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
             for (int k = tid; k < PR * (RS / 4); k += kBqTileThreads) {
                 const int g = k % (RS / 4), pi = k / (RS / 4);
                 const bool A = pi < pa;
-                const int s0 = (A ? pi : pi - pa) << SH, n = A ? na : nb;
+                const int s0 = A ? pi : pi - pa, n = A ? na : nb;
                 if (s0 >= n) continue;
                 const uint32_t i0 = (uint32_t)(A ? s0 : na + s0);
                 const Block4 b0 = philox(i0, 0u, rg0 + (uint32_t)g, kDomainInit, jb.k0, jb.k1);
-                Block4 b1 = b0;
-                if (FP4 && s0 + 1 < n) b1 = philox(i0 + 1u, 0u, rg0 + (uint32_t)g, kDomainInit, jb.k0, jb.k1);
 #pragma unroll
-                for (int p = 0; p < 4; ++p) {
-                    uint32_t byte;
-                    if (FP4)
-                        byte = fp4_code(init_spin(b0.w[p])) | (s0 + 1 < n ? fp4_code(init_spin(b1.w[p])) << 4 : 0u);
-                    else
-                        byte = (uint32_t)(uint8_t)init_spin(b0.w[p]);
-                    sp[(4 * g + p) * pitch + pi] = (uint8_t)byte;
-                }
+                for (int p = 0; p < 4; ++p) sp[(4 * g + p) * pitch + pi] = (uint8_t)init_spin(b0.w[p]);
             }
         } else {
             for (int k = tid; k < RS * (PR / 16); k += kBqTileThreads) {
@@ -557,8 +527,7 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
                 const int ko = side == 0 ? pb : pa;         // bytes per coupling row (the other side)
                 const int in_col = side == 0 ? pa : 0;      // bytes of the other side (A operand)
                 const int out_col = side == 0 ? 0 : pa;     // bytes of this side
-                const uint8_t *Jx = FP4 ? (side == 0 ? jb.J4 : jb.JT4)
-                                        : reinterpret_cast<const uint8_t *>(side == 0 ? jb.J2 : jb.JT2);
+                const uint8_t *Jx = reinterpret_cast<const uint8_t *>(side == 0 ? jb.J2 : jb.JT2);
                 const int8_t *hs = side == 0 ? jb.hA : jb.hB;
                 const uint32_t site_base = side == 0 ? 0u : (uint32_t)na;
                 // one 32-site block per wave at a time; its coupling fragments stream
@@ -568,7 +537,7 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
                 const int nku = ko / 32;
                 constexpr int kStep = kBqTileThreads / 64;
                 const int nblk = ns_p / 32;
-                if constexpr (!FP4) {
+                {
                     // the other side's spin sum per replica, padding sites included (their
                     // codes are 1): T threads per row, bytewise
                     // counts of nonzero and of -1 spins (at most 72 per byte for the
@@ -590,16 +559,13 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
                     if (part == 0) mag[r] = v;
                     __syncthreads();
                 }
-                // coupling fragments: [K step][site block] of 16 int8 bytes per lane (FP4:
-                // packed nibbles) or one word of codes per lane, 64 words per K step and block
-                using Frag = typename std::conditional<FP4, v4i, uint32_t>::type;
+                // coupling fragments: [K step][site block] of one word of codes per lane,
+                // 64 words per K step and block
+                using Frag = uint32_t;
                 auto frag_ptr = [&](int blk) -> const uint8_t * {
-                    if constexpr (FP4)
-                        return Jx + (size_t)(blk * 32 + ln) * ko + 16 * kg;
-                    else
-                        return Jx + 4 * (((size_t)blk * nku * 2 + kg) * 32 + ln);
+                    return Jx + 4 * (((size_t)blk * nku * 2 + kg) * 32 + ln);
                 };
-                constexpr int kUnit = FP4 ? 32 : 256;  // bytes from one K step of a fragment to the next
+                constexpr int kUnit = 256;  // bytes from one K step of a fragment to the next
                 Frag ring[kRing];
                 if (wave < nblk) {
                     const uint8_t *br0 = frag_ptr(wave);
@@ -612,20 +578,16 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
                     const uint8_t *br = frag_ptr(blk);
                     // the next block of this wave, or this one again when there is none
                     const uint8_t *bn = blk + kStep < nblk ? frag_ptr(blk + kStep) : br;
-                    Acc acc[RB];
+                    v16i acc[RB];
 #pragma unroll
-                    for (int rb = 0; rb < RB; ++rb) acc[rb] = Acc{0};
+                    for (int rb = 0; rb < RB; ++rb) acc[rb] = v16i{0};
                     const uint8_t *abase = sp + ln * pitch + in_col + 16 * kg;
                     for (int kb = 0; kb < nku; kb += kRing) {
 #pragma unroll
                         for (int u = 0; u < kRing; ++u) {
                             const int ku = kb + u;
                             if (ku < nku) {
-                                v4i b;
-                                if constexpr (FP4)
-                                    b = ring[u];
-                                else
-                                    b = widen_codes(ring[u]);
+                                const v4i b = widen_codes(ring[u]);
                                 // slot u takes unit ku + kRing of this block, or, after this
                                 // block's last unit of its residue class, unit u of the next block
                                 const int kn = ku + kRing;
@@ -634,10 +596,7 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
 #pragma unroll
                                 for (int rb = 0; rb < RB; ++rb) {
                                     const v4i a = *reinterpret_cast<const v4i *>(abase + rb * 32 * pitch + 32 * ku);
-                                    if constexpr (FP4)
-                                        acc[rb] = mfma_fp4(a, b, acc[rb]);
-                                    else
-                                        acc[rb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, acc[rb], 0, 0, 0);
+                                    acc[rb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, acc[rb], 0, 0, 0);
                                 }
                             }
                         }
@@ -646,7 +605,7 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
                     // (clamped to [-top, top]); the sign bits of a group's four
                     // replicas become spin codes, one per byte, transposed across the
                     // lane quad (sites s .. s + 3) so that each lane writes four
-                    // consecutive sites of one replica row (two nibble bytes with FP4).
+                    // consecutive sites of one replica row.
                     // Padding sites may take any value: their couplings and fields are
                     // zero and they are never returned.
                     const int hval = load_global<int8_t>(hs + site);  // site < ns_p: padded fields are zero
@@ -654,7 +613,7 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
                     const int flo = -top - hval, fhi = top - hval;  // F range whose F + h is in [-top, top]
                     const int base8 = 8 * (hval + top);
                     const int u4 = ln & 3;
-                    const int quad_col = out_col + ((site - u4) >> SH);
+                    const int quad_col = out_col + site - u4;
 #pragma unroll
                     for (int rb = 0; rb < RB; ++rb) {
 #pragma unroll
@@ -667,7 +626,7 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
                             for (int p = 0; p < 4; ++p) {
                                 // an exact integer; with codes of J + 1 the product exceeds the
                                 // field by the replica's spin sum over the other side
-                                const int F = FP4 ? (int)acc[rb][4 * q + p] : (int)acc[rb][4 * q + p] - mag[r4 + p];
+                                const int F = (int)acc[rb][4 * q + p] - mag[r4 + p];
                                 const int Fc = min(max(F, flo), fhi);
                                 const uint64_t S = *static_cast<const uint64_t *>(
                                     __builtin_assume_aligned(Sb + 8 * Fc + base8, 8));
@@ -678,17 +637,11 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
                             }
                             const uint32_t lo = __builtin_amdgcn_perm(sgn[1], sgn[0], 0x0C0C0400u);
                             const uint32_t hi = __builtin_amdgcn_perm(sgn[3], sgn[2], 0x0C0C0400u);
-                            // sign bit 0 -> +1, 1 -> -1: 0x01 / 0xFF bytes, or 0x2 / 0xA codes
-                            const uint32_t packed = __builtin_amdgcn_perm(0u, FP4 ? 0x0A02u : 0xFF01u,
+                            // sign bit 0 -> +1, 1 -> -1: 0x01 / 0xFF bytes
+                            const uint32_t packed = __builtin_amdgcn_perm(0u, 0xFF01u,
                                                                           __builtin_amdgcn_perm(hi, lo, 0x05040100u));
                             const uint32_t x = quad_transpose(packed, u4);  // four sites, one byte each
-                            if constexpr (FP4) {
-                                const uint32_t y = x | (x >> 4);  // bytes 0 and 2: site pairs
-                                *reinterpret_cast<uint16_t *>(sp + (r4 + u4) * pitch + quad_col) =
-                                    (uint16_t)__builtin_amdgcn_perm(0u, y, 0x0C0C0200u);
-                            } else {
-                                *reinterpret_cast<uint32_t *>(sp + (r4 + u4) * pitch + quad_col) = x;
-                            }
+                            *reinterpret_cast<uint32_t *>(sp + (r4 + u4) * pitch + quad_col) = x;
                         }
                     }
                 }
@@ -699,11 +652,7 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
         // field part of side A, then the energies and the spins go back to global memory
         for (int k = tid; k < RS * na; k += kBqTileThreads) {
             const int r = k / na, a = k % na;
-            int m;
-            if (FP4)
-                m = fp4_value((sp[r * pitch + a / 2] >> (4 * (a & 1))) & 15u);
-            else
-                m = (int)(int8_t)sp[r * pitch + a];
+            const int m = (int)(int8_t)sp[r * pitch + a];
             const int v = (int)jb.hA[a] * m;
             if (v != 0) atomicAdd(&eacc[r], -v);
         }
@@ -728,7 +677,7 @@ size_t bq_tile_lds(int rs, int na_p, int nb_p, int width, int mode)
     if (mode == kTileBits)
         rows = sizeof(uint32_t) * (size_t)((rs * ((na_p + nb_p) / 32 + 1) + 1) & ~1);
     else
-        rows = (size_t)rs * ((size_t)(mode == kTileFp4 ? (na_p + nb_p) / 2 : na_p + nb_p) + 16);
+        rows = (size_t)rs * ((size_t)(na_p + nb_p) + 16);
     return rows + sizeof(uint64_t) * (size_t)(2 * width - 1);
 }
 
@@ -741,12 +690,8 @@ hipError_t tiles_set_lds_limit()
     const void *bq_kernels[] = {reinterpret_cast<const void *>(&k_bq_tiles_bits<1>),
                                 reinterpret_cast<const void *>(&k_bq_tiles_bits<2>),
                                 reinterpret_cast<const void *>(&k_bq_tiles_bits<4>),
-                                reinterpret_cast<const void *>(&k_bq_tiles<1, false>),
-                                reinterpret_cast<const void *>(&k_bq_tiles<2, false>),
-                                reinterpret_cast<const void *>(&k_bq_tiles<4, false>),
-                                reinterpret_cast<const void *>(&k_bq_tiles<1, true>),
-                                reinterpret_cast<const void *>(&k_bq_tiles<2, true>),
-                                reinterpret_cast<const void *>(&k_bq_tiles<4, true>)};
+                                reinterpret_cast<const void *>(&k_bq_tiles<1>),
+                                reinterpret_cast<const void *>(&k_bq_tiles<2>)};
     for (const void *k : bq_kernels)
         if (e == hipSuccess) e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
     return e;
@@ -766,16 +711,14 @@ hipError_t bq_tiles(const BqJobDev *jobs, const WorkItem *items, const int32_t *
 #define PBIT_BQ_TILES(K)                                                                                        \
     hipLaunchKernelGGL(K, dim3((unsigned)grid), dim3(kBqTileThreads), lds_bytes, st, jobs, items, n_items, counter, 1u)
     const int rb = rs == 128 ? 4 : rs == 64 ? 2 : rs == 32 ? 1 : 0;
-    if (rb == 0 || mode < kTileInt8 || mode > kTileBits) return hipErrorInvalidValue;
+    if (rb == 0 || (mode != kTileInt8 && mode != kTileBits)) return hipErrorInvalidValue;
     if (mode == kTileBits) {
         if (rb == 4) PBIT_BQ_TILES((k_bq_tiles_bits<4>)); else if (rb == 2) PBIT_BQ_TILES((k_bq_tiles_bits<2>));
         else PBIT_BQ_TILES((k_bq_tiles_bits<1>));
-    } else if (mode == kTileFp4) {
-        if (rb == 4) PBIT_BQ_TILES((k_bq_tiles<4, true>)); else if (rb == 2) PBIT_BQ_TILES((k_bq_tiles<2, true>));
-        else PBIT_BQ_TILES((k_bq_tiles<1, true>));
     } else {
-        if (rb == 4) PBIT_BQ_TILES((k_bq_tiles<4, false>)); else if (rb == 2) PBIT_BQ_TILES((k_bq_tiles<2, false>));
-        else PBIT_BQ_TILES((k_bq_tiles<1, false>));
+        // int8 rows come in 32- and 64-replica tiles (a 128-replica int8 tile spills registers)
+        if (rb == 4) return hipErrorInvalidValue;
+        if (rb == 2) PBIT_BQ_TILES((k_bq_tiles<2>)); else PBIT_BQ_TILES((k_bq_tiles<1>));
     }
 #undef PBIT_BQ_TILES
     return hipGetLastError();

@@ -13,11 +13,6 @@ struct BqView {
     const int8_t *JT;  // [nb_p][na_p]
     const int8_t *hA;  // [na_p]
     const int8_t *hB;  // [nb_p]
-    // the couplings as packed 4-bit floats (two per byte, lower index in the low
-    // nibble): [na_p][nb_p / 2], [nb_p][na_p / 2]
-    const uint8_t *J4;
-    const uint8_t *JT4;
-    bool fp4_sweep;  // both sides padded to 128: the per-instance half-sweep runs on fp4 operands
     // for the kernels on spin bits: the couplings with the columns of every group of
     // 32 in the order the widened bits take, scaled by 2^(3 - j) for the bit's
     // position j in its byte lane, [na_p][nb_p] and [nb_p][na_p], and each site's
@@ -40,30 +35,17 @@ constexpr int kMaxTableWidth = 4096;  // threshold-row entries a biclique kernel
 
 // ---- biclique launchers; spins are device MA [Rp][na_p], MB [Rp][nb_p] -----
 // Kernel variants of a biclique half-sweep.  Small: 64 x 64 tiles straight from
-// global memory; K64D4 .. K128D4: 128 x 128 LDS-tiled with K stages of 64 or
-// 128 bytes and 2 or 4 stages of register prefetch; Dma64, Dma128: 128 x 128
-// with stages of 64 or 128 bytes moved by the global-to-LDS DMA into a ring of
-// 8 or 4 stages; Fp4: the DMA tile on packed 4-bit operands (bq4_*); Bits: the DMA
-// tile on spins held as bits, widened for the int8 MFMA (bqb_*).  All but Small need
-// sides padded to 128.
-enum class BqVariant : int {
-    Auto = 0, Small = 1, K64D4 = 2, K128D2 = 3, K128D4 = 4, Dma64 = 5, Dma128 = 6, Fp4 = 7, Bits = 8
-};
+// global memory (any padding); Dma: 128 x 128 tiles with K stages of 128 bytes
+// moved by the global-to-LDS DMA into a ring of 4 stages (sides padded to 128,
+// Rp a multiple of 128); Bits: 64 x 256 tiles on spins held as bits, widened for
+// the int8 MFMA (bqb_*; sides padded to 128, Rp a multiple of 256).
+enum class BqVariant : int { Auto = 0, Small = 1, Dma = 2, Bits = 3 };
 hipError_t bq_init(const BqView &p, int8_t *MA, int8_t *MB, int R, uint32_t rq0, Key key, hipStream_t st);
 hipError_t bq_from_rows(const BqView &p, const int8_t *src_rn, int R, int8_t *MA, int8_t *MB, hipStream_t st);
 hipError_t bq_to_rows(const BqView &p, const int8_t *MA, const int8_t *MB, int8_t *dst_rn, int R, hipStream_t st);
 hipError_t bq_halfsweep(const BqView &p, int side, int8_t *MA, int8_t *MB, int R, int Rp, const uint32_t *trow,
                         int width, uint32_t sweep, uint32_t rq0, Key key, hipStream_t st, BqVariant variant);
 hipError_t bq_energy(const BqView &p, const int8_t *MA, const int8_t *MB, int R, int Rp, int32_t *E, hipStream_t st);
-
-// ---- the same with spins held as packed 4-bit floats: MA4 [Rp][na_p / 2], MB4 [Rp][nb_p / 2]
-hipError_t bq4_init(const BqView &p, uint8_t *MA4, uint8_t *MB4, int R, uint32_t rq0, Key key, hipStream_t st);
-hipError_t bq4_from_rows(const BqView &p, const int8_t *src_rn, int R, uint8_t *MA4, uint8_t *MB4, hipStream_t st);
-hipError_t bq4_to_rows(const BqView &p, const uint8_t *MA4, const uint8_t *MB4, int8_t *dst_rn, int R, hipStream_t st);
-hipError_t bq4_unpack(const BqView &p, const uint8_t *MA4, const uint8_t *MB4, int8_t *MA, int8_t *MB, int Rp,
-                      hipStream_t st);
-hipError_t bq4_halfsweep(const BqView &p, int side, uint8_t *MA4, uint8_t *MB4, int Rp, const uint32_t *trow,
-                         int width, uint32_t sweep, uint32_t rq0, Key key, hipStream_t st);
 
 // ---- the same with spins held as bits (set = -1), 32 sites per word, by blocks of 128 sites:
 // word w of replica r at ((w / 4) Rp + r) 4 + w % 4 of MAb (na_p / 32 words per replica) or MBb

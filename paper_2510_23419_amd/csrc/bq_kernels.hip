@@ -151,235 +151,14 @@ __global__ __launch_bounds__(kThreads) void k_bq_halfsweep(const int8_t *__restr
     }
 }
 
-// Large-tile half-sweep for sides padded to 128: each workgroup owns a
-// 128-replica x 128-site tile of the field matrix and runs the whole K loop
-// through LDS (KT-byte K stages, double-buffered, one barrier per stage).
+// Tile edge of the DMA-staged half-sweep: 128 replicas x 128 sites per workgroup.
 // Four waves each hold a 64 x 64 sub-tile as 2 x 2 MFMA accumulators, so each
-// operand fragment read from LDS feeds two MFMAs.  Global loads run DEPTH
-// stages ahead through a ring of registers, and the 16 Philox blocks each lane
-// needs for its epilogue are drawn during the first K stages, where they
-// overlap the matrix cores instead of following them.  Workgroups are placed so
-// that each XCD works on one band of sites: its L2 then holds that band's rows
-// of J once while the spins of the other side stream through it.
-constexpr int kT = 128;  // tile edge (replicas and sites)
-
-template <int KT>
-struct TileGeom {
-    static constexpr int pitch = KT + 16;          // padded LDS row pitch
-    static constexpr int stage = kT * pitch;       // bytes per operand per stage
-    static constexpr int lds = 4 * stage;          // A and B, two stages each
-    static constexpr int chunks = KT / 16;         // 16-byte chunks per row
-    static constexpr int rows_per_pass = kThreads / chunks;
-    static constexpr int passes = kT / rows_per_pass;
-};
-
-// A stage's staging registers as one native vector (4 ints per 16-byte chunk:
-// A chunks first, then B chunks), so that the ring stays in VGPRs.
-typedef int v32i __attribute__((ext_vector_type(32)));
-template <int KT>
-struct StageVec;
-template <>
-struct StageVec<64> {
-    typedef v16i type;
-};
-template <>
-struct StageVec<128> {
-    typedef v32i type;
-};
-
-template <int KT>
-struct Stage {
-    typename StageVec<KT>::type v;
-};
-
-template <int KT>
-__device__ __forceinline__ Stage<KT> load_stage(const int8_t *ga, const int8_t *gb, size_t pass_stride, int kt)
-{
-    constexpr int P = TileGeom<KT>::passes;
-    const size_t k = (size_t)kt * KT;
-    Stage<KT> r;
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-        const v4i a = *reinterpret_cast<const v4i *>(ga + p * pass_stride + k);
-        const v4i b = *reinterpret_cast<const v4i *>(gb + p * pass_stride + k);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            r.v[4 * p + e] = a[e];
-            r.v[4 * (P + p) + e] = b[e];
-        }
-    }
-    return r;
-}
-
-template <int KT>
-__device__ __forceinline__ void store_stage(const Stage<KT> &r, int8_t *As, int8_t *Bs, int buf, int st)
-{
-    using G = TileGeom<KT>;
-    constexpr int P = G::passes;
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-        const v4i a = {r.v[4 * p], r.v[4 * p + 1], r.v[4 * p + 2], r.v[4 * p + 3]};
-        const v4i b = {r.v[4 * (P + p)], r.v[4 * (P + p) + 1], r.v[4 * (P + p) + 2], r.v[4 * (P + p) + 3]};
-        *reinterpret_cast<v4i *>(As + buf + st + p * G::rows_per_pass * G::pitch) = a;
-        *reinterpret_cast<v4i *>(Bs + buf + st + p * G::rows_per_pass * G::pitch) = b;
-    }
-}
+// operand fragment read from LDS feeds two MFMAs.
+constexpr int kT = 128;
 
 struct Acc4 {
     v16i c00, c01, c10, c11;
 };
-
-template <int KT>
-__device__ __forceinline__ void mma_stage(Acc4 &c, const int8_t *As, const int8_t *Bs, int buf, int ra_off, int rb_off)
-{
-    constexpr int pitch = TileGeom<KT>::pitch;
-#pragma unroll
-    for (int sub = 0; sub < KT / 32; ++sub) {
-        const int ko = buf + 32 * sub;
-        const v4i a0 = *reinterpret_cast<const v4i *>(As + ko + ra_off);
-        const v4i a1 = *reinterpret_cast<const v4i *>(As + ko + ra_off + 32 * pitch);
-        const v4i b0 = *reinterpret_cast<const v4i *>(Bs + ko + rb_off);
-        const v4i b1 = *reinterpret_cast<const v4i *>(Bs + ko + rb_off + 32 * pitch);
-        c.c00 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, b0, c.c00, 0, 0, 0);
-        c.c01 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, b1, c.c01, 0, 0, 0);
-        c.c10 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, b0, c.c10, 0, 0, 0);
-        c.c11 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, b1, c.c11, 0, 0, 0);
-    }
-}
-
-template <int KT, int DEPTH>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_bq_halfsweep_t128(
-    const int8_t *__restrict__ Mo, const int8_t *__restrict__ Jx, const int8_t *__restrict__ hs,
-    int8_t *__restrict__ Ms, const uint32_t *__restrict__ trow, int width, int Ns, int Ns_p, int Ko, int R,
-    int tiles_s, int xcd_bands, uint32_t site_base, uint32_t sweep, uint32_t rq0, uint32_t k0, uint32_t k1)
-{
-    using G = TileGeom<KT>;
-    constexpr int kPhxPerStage = KT / 32;            // Philox blocks drawn per K stage
-    constexpr int kPhxStages = 16 / kPhxPerStage;    // stages that carry the 16 draws
-    static_assert(kPhxStages % DEPTH == 0, "ring index must restart at 0 after the Philox stages");
-
-    extern __shared__ uint4 smem[];
-    int8_t *As = reinterpret_cast<int8_t *>(smem);
-    int8_t *Bs = As + 2 * G::stage;
-    uint32_t *T = reinterpret_cast<uint32_t *>(As + G::lds);
-    for (int a = threadIdx.x; a < width; a += kThreads) T[a] = trow[a];
-
-    int ts, tr;
-    if (xcd_bands) {  // tiles_s % 8 == 0: XCD (= block id mod 8) owns tiles_s / 8 site tiles
-        const int per = tiles_s / 8;
-        const int slot = (int)blockIdx.x / 8;
-        ts = ((int)blockIdx.x % 8) * per + slot % per;
-        tr = slot / per;
-    } else {
-        ts = (int)blockIdx.x % tiles_s;
-        tr = (int)blockIdx.x / tiles_s;
-    }
-    const int r0 = tr * kT, s0 = ts * kT;
-
-    // global -> LDS staging: thread t moves 16 bytes of row t / chunks (+ k * rows_per_pass)
-    const int lrow = threadIdx.x / G::chunks, lcol = 16 * (threadIdx.x % G::chunks);
-    const int8_t *ga = Mo + (size_t)(r0 + lrow) * Ko + lcol;
-    const int8_t *gb = Jx + (size_t)(s0 + lrow) * Ko + lcol;
-    const size_t pass_stride = (size_t)G::rows_per_pass * Ko;
-    const int st = lrow * G::pitch + lcol;
-    const int nk = Ko / KT;
-    const int last = nk - 1;
-
-    // ring: stage s lives in g[s % DEPTH] until it is written to LDS.  Loads past
-    // the last stage re-read the last stage (clamped index) instead of branching,
-    // so the ring stays in registers.
-    Stage<KT> g[DEPTH];
-#pragma unroll
-    for (int u = 0; u < DEPTH; ++u) g[u] = load_stage<KT>(ga, gb, pass_stride, min(u, last));
-    store_stage<KT>(g[0], As, Bs, 0, st);
-    g[0] = load_stage<KT>(ga, gb, pass_stride, min(DEPTH, last));
-    __syncthreads();
-
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wr = wave >> 1, wc = wave & 1;
-    const int ln = lane & 31, kg = lane >> 5;
-    const int ra_off = (wr * 64 + ln) * G::pitch + 16 * kg;
-    const int rb_off = (wc * 64 + ln) * G::pitch + 16 * kg;
-    Acc4 acc;
-    acc.c00 = acc.c01 = acc.c10 = acc.c11 = v16i{0};
-
-// one K stage: MFMAs on stage KT_, hand stage KT_ + 1 (held in NEXT) to LDS, refill NEXT
-#define PBIT_BQ_STEP(KT_, NEXT)                                                               \
-    do {                                                                                       \
-        const int kt_ = (KT_);                                                                 \
-        mma_stage<KT>(acc, As, Bs, (kt_ & 1) * G::stage, ra_off, rb_off);                      \
-        if (kt_ + 1 < nk) store_stage<KT>(NEXT, As, Bs, ((kt_ + 1) & 1) * G::stage, st);       \
-        NEXT = load_stage<KT>(ga, gb, pass_stride, min(kt_ + 1 + DEPTH, last));                \
-        __syncthreads();                                                                       \
-    } while (0)
-
-    // Philox words of this lane's 16 (site, replica group) pairs: block index
-    // (bj * 2 + bi) * 4 + q covers site column bj and replica rows bi, q.
-    uint32_t words[16][4];
-#pragma unroll
-    for (int u = 0; u < kPhxStages; ++u) {
-        if (u < nk) PBIT_BQ_STEP(u, g[(u + 1) % DEPTH]);
-#pragma unroll
-        for (int v = 0; v < kPhxPerStage; ++v) {
-            const int blk = kPhxPerStage * u + v;
-            const int bj = blk >> 3, bi = (blk >> 2) & 1, q = blk & 3;
-            const int site = s0 + wc * 64 + bj * 32 + ln;
-            const int r4 = r0 + wr * 64 + bi * 32 + 8 * q + 4 * kg;
-            const Block4 b =
-                philox(site_base + (uint32_t)site, sweep, rq0 + (uint32_t)(r4 >> 2), kDomainSweep, k0, k1);
-            uint32_t w0 = b.w[0], w1 = b.w[1], w2 = b.w[2], w3 = b.w[3];
-            // pin the draws here, between the MFMAs, instead of letting them sink to the epilogue
-            asm volatile("" : "+v"(w0), "+v"(w1), "+v"(w2), "+v"(w3));
-            words[blk][0] = w0;
-            words[blk][1] = w1;
-            words[blk][2] = w2;
-            words[blk][3] = w3;
-        }
-    }
-    int kt = kPhxStages;
-    for (; kt + DEPTH <= nk; kt += DEPTH) {
-#pragma unroll
-        for (int u = 0; u < DEPTH; ++u) PBIT_BQ_STEP(kt + u, g[(u + 1) % DEPTH]);
-    }
-#pragma unroll
-    for (int u = 0; u + 1 < DEPTH; ++u)
-        if (kt + u < nk) PBIT_BQ_STEP(kt + u, g[(u + 1) % DEPTH]);
-#undef PBIT_BQ_STEP
-
-    // epilogue: decision for each accumulator element.  Every decision is taken
-    // unconditionally (padding sites have h = 0 and padding replicas are never
-    // read back); only the byte store is guarded, so stores stay in flight
-    // together instead of being waited for one by one.
-    const int top = width - 1;
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj) {
-        const int site = s0 + wc * 64 + bj * 32 + ln;
-        const int hval = hs[site];  // site < Ns_p: padded fields are zero
-        const bool site_ok = site < Ns;
-#pragma unroll
-        for (int bi = 0; bi < 2; ++bi) {
-            const v16i &c = bi == 0 ? (bj == 0 ? acc.c00 : acc.c01) : (bj == 0 ? acc.c10 : acc.c11);
-            int8_t m[16];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int blk = (bj * 2 + bi) * 4 + q;
-#pragma unroll
-                for (int p = 0; p < 4; ++p) {
-                    const int I = c[4 * q + p] + hval;
-                    const int a = min(I >= 0 ? I : -I, top);
-                    m[4 * q + p] = decide(I, T[a], words[blk][p]);
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int r4 = r0 + wr * 64 + bi * 32 + 8 * q + 4 * kg;
-#pragma unroll
-                for (int p = 0; p < 4; ++p)
-                    if (site_ok && r4 + p < R) Ms[(size_t)(r4 + p) * Ns_p + site] = m[4 * q + p];
-            }
-        }
-    }
-}
 
 // ---------------------------------------------------------------- DMA-staged 128 x 128 tiles
 //
@@ -582,287 +361,6 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
                 }
                 const int r4 = r0 + wr * 64 + bi * 32 + 8 * q + 4 * kg;
                 *reinterpret_cast<uint32_t *>(Ms + (size_t)(r4 + u4) * Ns_p + quad_col) = quad_transpose(packed, u4);
-            }
-        }
-    }
-}
-
-// ---------------------------------------------------------------- fp4 operands
-//
-// On bicliques whose sides are both padded to 128, spins and couplings are
-// also held as 4-bit floats (e2m1: +1 = 0x2, -1 = 0xA, 0 = 0x0), two per byte
-// with the lower site in the low nibble.  Products of these values and their
-// sums (|F| <= n < 2^24) are exact in the fp32 accumulators of the f8f6f4 MFMA,
-// so the fields are the same integers as with int8 operands, while a byte of
-// operand now carries two multiply-adds and the MFMA rate doubles.  The half-
-// sweep is the DMA-staged tile above with 32-byte K steps of 64 values.
-__device__ __forceinline__ uint32_t fp4_code(int m) { return m > 0 ? 0x2u : (m < 0 ? 0xAu : 0x0u); }
-__device__ __forceinline__ int8_t fp4_value(uint32_t nib) { return nib == 0 ? (int8_t)0 : ((nib & 8u) ? (int8_t)-1 : (int8_t)1); }
-
-// Random start: thread (site pair, replica group) writes one byte in each of four rows.
-__global__ __launch_bounds__(kThreads) void k_bq4_init(uint8_t *__restrict__ MA4, uint8_t *__restrict__ MB4, int na,
-                                                       int nb, int na_p, int nb_p, int R, uint32_t rq0, uint32_t k0,
-                                                       uint32_t k1)
-{
-    const int groups = (R + 3) / 4;
-    const int pa = na_p / 2, pb = nb_p / 2;
-    const int64_t gid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (gid >= (int64_t)(pa + pb) * groups) return;
-    const int g = (int)(gid % groups);
-    const int pi = (int)(gid / groups);
-    const bool A = pi < pa;
-    const int s0 = 2 * (A ? pi : pi - pa), n = A ? na : nb;
-    const uint32_t i0 = (uint32_t)(A ? s0 : na + s0);
-    uint8_t *dst = A ? MA4 + pi : MB4 + (pi - pa);
-    const int rowbytes = A ? pa : pb;
-    const Block4 b0 = philox(i0, 0u, rq0 + (uint32_t)g, kDomainInit, k0, k1);
-    const Block4 b1 = philox(i0 + 1u, 0u, rq0 + (uint32_t)g, kDomainInit, k0, k1);
-    for (int p = 0; p < 4; ++p) {
-        const int r = 4 * g + p;
-        if (r >= R) break;
-        const uint32_t lo = s0 < n ? fp4_code(init_spin(b0.w[p])) : 0u;
-        const uint32_t hi = s0 + 1 < n ? fp4_code(init_spin(b1.w[p])) : 0u;
-        dst[(size_t)r * rowbytes] = (uint8_t)(lo | (hi << 4));
-    }
-}
-
-// [R][na + nb] int8 rows <-> packed sides; thread (replica, site pair of the real sites)
-template <bool TO_DEVICE>
-__global__ __launch_bounds__(kThreads) void k_bq4_copy(int8_t *__restrict__ rows, uint8_t *__restrict__ MA4,
-                                                       uint8_t *__restrict__ MB4, int na, int nb, int na_p, int nb_p,
-                                                       int R)
-{
-    const int qa = (na + 1) / 2, qb = (nb + 1) / 2;
-    const int64_t gid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (gid >= (int64_t)R * (qa + qb)) return;
-    const int r = (int)(gid / (qa + qb));
-    const int pi = (int)(gid % (qa + qb));
-    const bool A = pi < qa;
-    const int s0 = 2 * (A ? pi : pi - qa), n = A ? na : nb;
-    int8_t *row = rows + (size_t)r * (na + nb) + (A ? 0 : na);
-    uint8_t *byte = A ? MA4 + (size_t)r * (na_p / 2) + pi : MB4 + (size_t)r * (nb_p / 2) + (pi - qa);
-    if (TO_DEVICE) {
-        const uint32_t lo = fp4_code(row[s0]);
-        const uint32_t hi = s0 + 1 < n ? fp4_code(row[s0 + 1]) : 0u;
-        *byte = (uint8_t)(lo | (hi << 4));
-    } else {
-        const uint32_t v = *byte;
-        row[s0] = fp4_value(v & 15u);
-        if (s0 + 1 < n) row[s0 + 1] = fp4_value(v >> 4);
-    }
-}
-
-// packed sides -> int8 sides (all padded rows and columns), for the energy kernels
-__global__ __launch_bounds__(kThreads) void k_bq4_unpack(const uint8_t *__restrict__ MA4,
-                                                         const uint8_t *__restrict__ MB4, int8_t *__restrict__ MA,
-                                                         int8_t *__restrict__ MB, int na_p, int nb_p, int Rp)
-{
-    const int pa = na_p / 2, pb = nb_p / 2;
-    const int64_t gid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    const int64_t na4 = (int64_t)Rp * pa;
-    if (gid >= na4 + (int64_t)Rp * pb) return;
-    const bool A = gid < na4;
-    const int64_t k = A ? gid : gid - na4;
-    const uint32_t v = A ? MA4[k] : MB4[k];
-    int8_t *dst = (A ? MA : MB) + 2 * k;  // byte k of a packed row is sites 2k, 2k + 1 of the same row
-    dst[0] = fp4_value(v & 15u);
-    dst[1] = fp4_value(v >> 4);
-}
-
-typedef int v8i __attribute__((ext_vector_type(8)));
-typedef float v16f __attribute__((ext_vector_type(16)));
-
-struct AccF4 {
-    v16f c00, c01, c10, c11;
-};
-
-// fp4 MFMA with unit block scales (E8M0 127): format 4 (e2m1) for both operands;
-// the 16 bytes of a fragment are the low half of the 32-byte operand.
-__device__ __forceinline__ v16f mfma_fp4(v4i a, v4i b, v16f c)
-{
-    const v8i a8 = {a[0], a[1], a[2], a[3], 0, 0, 0, 0};
-    const v8i b8 = {b[0], b[1], b[2], b[3], 0, 0, 0, 0};
-    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a8, b8, c, 4, 4, 0, 127, 0, 127);
-}
-
-template <int KT, int NS>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_bq_halfsweep_fp4(
-    const uint8_t *__restrict__ Mo, const uint8_t *__restrict__ Jx, const int8_t *__restrict__ hs,
-    uint8_t *__restrict__ Ms, const uint32_t *__restrict__ trow, int width, int Ns_p, int Ko, int tiles_s,
-    int xcd_bands, uint32_t site_base, uint32_t sweep, uint32_t rq0, uint32_t k0, uint32_t k1, uint32_t one)
-{
-    // Ko: bytes per operand row (two K values per byte); Ms rows hold Ns_p / 2 bytes
-    using G = DmaGeom<KT, NS>;
-    constexpr int CH = G::CH;
-    constexpr int kPhxPerStage = G::subs;
-    constexpr int kPhxStages = 16 / kPhxPerStage;
-
-    extern __shared__ uint4 smem[];
-    int8_t *ring = reinterpret_cast<int8_t *>(smem);
-    uint32_t *T = reinterpret_cast<uint32_t *>(ring + G::lds);
-    for (int a = threadIdx.x; a < width; a += kThreads) T[a] = trow[a];
-
-    int ts, tr;
-    if (xcd_bands) {  // tiles_s % 8 == 0: XCD (= block id mod 8) owns tiles_s / 8 site tiles
-        const int per = tiles_s / 8;
-        const int slot = (int)blockIdx.x / 8;
-        ts = ((int)blockIdx.x % 8) * per + slot % per;
-        tr = slot / per;
-    } else {
-        ts = (int)blockIdx.x % tiles_s;
-        tr = (int)blockIdx.x / tiles_s;
-    }
-    const int r0 = tr * kT, s0 = ts * kT;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-
-    // DMA sources (fixed array bounds: the lambdas below capture these arrays by reference)
-    const uint8_t *srcA[4], *srcB[4];
-    static_assert(G::per_wave <= 4 && G::subs <= 4, "fixed array bounds");
-#pragma unroll
-    for (int j = 0; j < G::per_wave; ++j) {
-        const int S = 64 * (G::per_wave * wave + j) + lane;
-        const int r = S / CH, c = (S % CH) ^ swz<CH>(S / CH);
-        srcA[j] = Mo + (size_t)(r0 + r) * Ko + 16 * c;
-        srcB[j] = Jx + (size_t)(s0 + r) * Ko + 16 * c;
-    }
-    const int nk = Ko / KT;
-    auto issue = [&](int t) {
-        int8_t *dA = ring + (t % NS) * G::stage + 1024 * G::per_wave * wave;
-        int8_t *dB = dA + G::op;
-        const size_t k = (size_t)t * KT;
-#pragma unroll
-        for (int j = 0; j < G::per_wave; ++j) __builtin_amdgcn_global_load_lds(srcA[j] + k, dA + 1024 * j, 16, 0, 0);
-#pragma unroll
-        for (int j = 0; j < G::per_wave; ++j) __builtin_amdgcn_global_load_lds(srcB[j] + k, dB + 1024 * j, 16, 0, 0);
-    };
-    wait_vm<0>();  // the threshold row's loads, before any DMA is counted
-    for (int t = 0; t < NS - 1 && t < nk; ++t) issue(t);
-
-    const int wr = wave >> 1, wc = wave & 1;
-    const int ln = lane & 31, kg = lane >> 5;
-    int offA[2][4], offB[2][4];  // [row block][K step]
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-        for (int sub = 0; sub < G::subs; ++sub) {
-            const int ra = wr * 64 + 32 * b + ln, rb = wc * 64 + 32 * b + ln;
-            offA[b][sub] = KT * ra + 16 * ((2 * sub + kg) ^ swz<CH>(ra));
-            offB[b][sub] = G::op + KT * rb + 16 * ((2 * sub + kg) ^ swz<CH>(rb));
-        }
-    AccF4 acc;
-    acc.c00 = acc.c01 = acc.c10 = acc.c11 = v16f{0.f};
-    uint32_t words[16][4];
-
-    auto compute = [&](int t) {
-        const int8_t *st = ring + (t % NS) * G::stage;
-#pragma unroll
-        for (int sub = 0; sub < G::subs; ++sub) {
-            const v4i a0 = *reinterpret_cast<const v4i *>(st + offA[0][sub]);
-            const v4i a1 = *reinterpret_cast<const v4i *>(st + offA[1][sub]);
-            const v4i b0 = *reinterpret_cast<const v4i *>(st + offB[0][sub]);
-            const v4i b1 = *reinterpret_cast<const v4i *>(st + offB[1][sub]);
-            acc.c00 = mfma_fp4(a0, b0, acc.c00);
-            acc.c01 = mfma_fp4(a0, b1, acc.c01);
-            acc.c10 = mfma_fp4(a1, b0, acc.c10);
-            acc.c11 = mfma_fp4(a1, b1, acc.c11);
-        }
-    };
-    auto draw = [&](int blk) {
-        // block (bj * 2 + bi) * 4 + q covers site column bj and replica rows bi, q
-        const int bj = blk >> 3, bi = (blk >> 2) & 1, q = blk & 3;
-        const int site = s0 + wc * 64 + bj * 32 + ln;
-        const int r4 = r0 + wr * 64 + bi * 32 + 8 * q + 4 * kg;
-        const Block4 b = philox(site_base + (uint32_t)site, sweep, rq0 + (uint32_t)(r4 >> 2), kDomainSweep, k0, k1);
-        words[blk][0] = b.w[0];
-        words[blk][1] = b.w[1];
-        words[blk][2] = b.w[2];
-        words[blk][3] = b.w[3];
-    };
-
-    if (nk >= NS - 1) wait_vm<G::ahead>(); else wait_vm<0>();
-    __builtin_amdgcn_s_barrier();
-    asm volatile("" ::: "memory");  // LDS written by the DMA: no read may move above here
-
-    int t = 0;
-#pragma unroll
-    for (int u = 0; u < kPhxStages; ++u) {
-        if (t < nk) {
-            if (t + NS - 1 < nk) issue(t + NS - 1);
-            compute(t);
-#pragma unroll
-            for (int v = 0; v < kPhxPerStage; ++v) draw(kPhxPerStage * u + v);
-            if (t + NS - 1 < nk) wait_vm<G::ahead>(); else wait_vm<0>();
-            __builtin_amdgcn_s_barrier();
-            asm volatile("" ::: "memory");
-            ++t;
-        } else {
-#pragma unroll
-            for (int v = 0; v < kPhxPerStage; ++v) draw(kPhxPerStage * u + v);
-        }
-    }
-    for (; t + NS - 1 < nk; ++t) {
-        issue(t + NS - 1);
-        compute(t);
-        wait_vm<G::ahead>();
-        __builtin_amdgcn_s_barrier();
-        asm volatile("" ::: "memory");
-    }
-    for (; t < nk; ++t) {
-        compute(t);
-        wait_vm<0>();
-        __builtin_amdgcn_s_barrier();
-        asm volatile("" ::: "memory");
-    }
-
-    // decision words in the LDS the ring no longer needs: S(I) = Tm(|I|) for I >= 0 and
-    // 2^32 - Tm(|I|) for I < 0, I in [-top, top]; the new spin is -1 exactly when the
-    // sum of the random word and S(I) carries into bit 32 (|I| >= top shares Tm(top))
-    const int top = width - 1;
-    uint64_t *Sw = reinterpret_cast<uint64_t *>(ring);
-    for (int e = threadIdx.x; e <= 2 * top; e += kThreads) {
-        const int I = e - top;
-        const uint32_t Tm = T[I >= 0 ? I : -I];
-        Sw[e] = I >= 0 ? (uint64_t)Tm : ((uint64_t)1 << 32) - Tm;
-    }
-    __syncthreads();
-    const char *Sb = reinterpret_cast<const char *>(Sw);
-
-    // epilogue: the field F of a replica and site indexes S(F + h) (clamped to
-    // [-top, top]); the sign bits of a group's four replicas become fp4 codes, one
-    // per byte, transposed across the lane quad (sites s .. s + 3) and squeezed to
-    // nibbles: each lane stores two bytes (four sites) of one replica row.
-    const int u4 = ln & 3;
-    const int rowbytes = Ns_p / 2;
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj) {
-        const int site = s0 + wc * 64 + bj * 32 + ln;
-        const int hval = hs[site];  // site < Ns_p: padded fields are zero
-        const int flo = -top - hval, fhi = top - hval;  // F range whose F + h is in [-top, top]
-        const int base8 = 8 * (hval + top);
-        const int quad_col = site - u4;
-#pragma unroll
-        for (int bi = 0; bi < 2; ++bi) {
-            const v16f &c = bi == 0 ? (bj == 0 ? acc.c00 : acc.c01) : (bj == 0 ? acc.c10 : acc.c11);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int blk = (bj * 2 + bi) * 4 + q;
-                uint32_t sgn[4];
-#pragma unroll
-                for (int p = 0; p < 4; ++p) {
-                    const int F = (int)c[4 * q + p];  // an exact integer
-                    const int Fc = min(max(F, flo), fhi);
-                    const uint64_t S = *static_cast<const uint64_t *>(__builtin_assume_aligned(Sb + 8 * Fc + base8, 8));
-                    sgn[p] = (uint32_t)(((uint64_t)words[blk][p] * one + S) >> 32);
-                }
-                const uint32_t lo = __builtin_amdgcn_perm(sgn[1], sgn[0], 0x0C0C0400u);
-                const uint32_t hi = __builtin_amdgcn_perm(sgn[3], sgn[2], 0x0C0C0400u);
-                // sign bit 0 -> +1 = 0x2, 1 -> -1 = 0xA
-                const uint32_t packed = __builtin_amdgcn_perm(0u, 0x0A02u, __builtin_amdgcn_perm(hi, lo, 0x05040100u));
-                const uint32_t x = quad_transpose(packed, u4);      // four sites, one byte each
-                const uint32_t y = x | (x >> 4);                     // bytes 0 and 2: site pairs
-                const uint32_t nib = __builtin_amdgcn_perm(0u, y, 0x0C0C0200u);
-                const int r4 = r0 + wr * 64 + bi * 32 + 8 * q + 4 * kg;
-                *reinterpret_cast<uint16_t *>(Ms + (size_t)(r4 + u4) * rowbytes + quad_col / 2) = (uint16_t)nib;
             }
         }
     }
@@ -1283,134 +781,26 @@ hipError_t bq_halfsweep(const BqView &p, int side, int8_t *MA, int8_t *MB, int R
     const int Ns = A ? p.na : p.nb;
     const uint32_t site_base = A ? 0u : (uint32_t)p.na;
     static const hipError_t lds_attr = [] {
-        // the 128-byte-stage variants stage more than the default 64 KiB of LDS
-        const int max_lds = TileGeom<128>::lds + (int)sizeof(uint32_t) * kMaxTableWidth;
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bq_halfsweep_t128<128, 2>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bq_halfsweep_t128<128, 4>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
-        // the DMA rings plus the threshold row
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bq_halfsweep_dma<64, 8>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    DmaGeom<64, 8>::lds + (int)sizeof(uint32_t) * kMaxTableWidth);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bq_halfsweep_dma<128, 4>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    DmaGeom<128, 4>::lds + (int)sizeof(uint32_t) * kMaxTableWidth);
-        return e;
+        // the DMA ring plus the threshold row exceed the default 64 KiB of LDS
+        return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bq_halfsweep_dma<128, 4>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   DmaGeom<128, 4>::lds + (int)sizeof(uint32_t) * kMaxTableWidth);
     }();
     if (lds_attr != hipSuccess) return lds_attr;
-    if (variant != BqVariant::Small && Ns_p % kT == 0 && Ko % 128 == 0 && Rp % kT == 0) {
+    if (variant == BqVariant::Dma) {
+        if (Ns_p % kT != 0 || Ko % 128 != 0 || Rp % kT != 0) return hipErrorInvalidValue;
         const int tiles_s = Ns_p / kT, tiles_r = Rp / kT;
         const dim3 grid((unsigned)(tiles_s * tiles_r));
         const int bands = tiles_s % 8 == 0 ? 1 : 0;
         const size_t tab = sizeof(uint32_t) * (size_t)width;
-        switch (variant) {
-        case BqVariant::Dma64:
-            hipLaunchKernelGGL((k_bq_halfsweep_dma<64, 8>), grid, dim3(kThreads), (DmaGeom<64, 8>::lds + tab), st, Mo,
-                               Jx, hs, Ms, trow, width, Ns_p, Ko, tiles_s, bands, site_base, sweep, rq0, key.k0,
-                               key.k1);
-            break;
-        case BqVariant::Dma128:
-            hipLaunchKernelGGL((k_bq_halfsweep_dma<128, 4>), grid, dim3(kThreads), (DmaGeom<128, 4>::lds + tab), st, Mo,
-                               Jx, hs, Ms, trow, width, Ns_p, Ko, tiles_s, bands, site_base, sweep, rq0, key.k0,
-                               key.k1);
-            break;
-        case BqVariant::K64D4:
-            hipLaunchKernelGGL((k_bq_halfsweep_t128<64, 4>), grid, dim3(kThreads), TileGeom<64>::lds + tab, st, Mo,
-                               Jx, hs, Ms, trow, width, Ns, Ns_p, Ko, R, tiles_s, bands, site_base, sweep, rq0,
-                               key.k0, key.k1);
-            break;
-        case BqVariant::K128D2:
-            hipLaunchKernelGGL((k_bq_halfsweep_t128<128, 2>), grid, dim3(kThreads), TileGeom<128>::lds + tab, st,
-                               Mo, Jx, hs, Ms, trow, width, Ns, Ns_p, Ko, R, tiles_s, bands, site_base, sweep, rq0,
-                               key.k0, key.k1);
-            break;
-        default:
-            hipLaunchKernelGGL((k_bq_halfsweep_t128<128, 4>), grid, dim3(kThreads), TileGeom<128>::lds + tab, st,
-                               Mo, Jx, hs, Ms, trow, width, Ns, Ns_p, Ko, R, tiles_s, bands, site_base, sweep, rq0,
-                               key.k0, key.k1);
-            break;
-        }
+        hipLaunchKernelGGL((k_bq_halfsweep_dma<128, 4>), grid, dim3(kThreads), (DmaGeom<128, 4>::lds + tab), st, Mo, Jx,
+                           hs, Ms, trow, width, Ns_p, Ko, tiles_s, bands, site_base, sweep, rq0, key.k0, key.k1);
         return hipGetLastError();
     }
     dim3 grid((unsigned)(Ns_p / kTileS), (unsigned)(Rp / kTileR));
     const size_t lds = sizeof(uint32_t) * (size_t)width;
     hipLaunchKernelGGL(k_bq_halfsweep<false>, grid, dim3(kThreads), lds, st, Mo, Jx, hs, Ms, trow, width, Ns, Ns_p,
                        Ko, R, site_base, sweep, rq0, key.k0, key.k1, (int32_t *)nullptr);
-    return hipGetLastError();
-}
-
-hipError_t bq4_init(const BqView &p, uint8_t *MA4, uint8_t *MB4, int R, uint32_t rq0, Key key, hipStream_t st)
-{
-    const int64_t work = (int64_t)(p.na_p / 2 + p.nb_p / 2) * ((R + 3) / 4);
-    hipLaunchKernelGGL(k_bq4_init, dim3(blocks_for(work)), dim3(kThreads), 0, st, MA4, MB4, p.na, p.nb, p.na_p, p.nb_p,
-                       R, rq0, key.k0, key.k1);
-    return hipGetLastError();
-}
-
-hipError_t bq4_from_rows(const BqView &p, const int8_t *src_rn, int R, uint8_t *MA4, uint8_t *MB4, hipStream_t st)
-{
-    const int64_t work = (int64_t)R * ((p.na + 1) / 2 + (p.nb + 1) / 2);
-    hipLaunchKernelGGL(k_bq4_copy<true>, dim3(blocks_for(work)), dim3(kThreads), 0, st, const_cast<int8_t *>(src_rn),
-                       MA4, MB4, p.na, p.nb, p.na_p, p.nb_p, R);
-    return hipGetLastError();
-}
-
-hipError_t bq4_to_rows(const BqView &p, const uint8_t *MA4, const uint8_t *MB4, int8_t *dst_rn, int R, hipStream_t st)
-{
-    const int64_t work = (int64_t)R * ((p.na + 1) / 2 + (p.nb + 1) / 2);
-    hipLaunchKernelGGL(k_bq4_copy<false>, dim3(blocks_for(work)), dim3(kThreads), 0, st, dst_rn,
-                       const_cast<uint8_t *>(MA4), const_cast<uint8_t *>(MB4), p.na, p.nb, p.na_p, p.nb_p, R);
-    return hipGetLastError();
-}
-
-hipError_t bq4_unpack(const BqView &p, const uint8_t *MA4, const uint8_t *MB4, int8_t *MA, int8_t *MB, int Rp,
-                      hipStream_t st)
-{
-    const int64_t work = (int64_t)Rp * (p.na_p / 2 + p.nb_p / 2);
-    hipLaunchKernelGGL(k_bq4_unpack, dim3(blocks_for(work)), dim3(kThreads), 0, st, MA4, MB4, MA, MB, p.na_p, p.nb_p,
-                       Rp);
-    return hipGetLastError();
-}
-
-hipError_t bq4_halfsweep(const BqView &p, int side, uint8_t *MA4, uint8_t *MB4, int Rp, const uint32_t *trow,
-                         int width, uint32_t sweep, uint32_t rq0, Key key, hipStream_t st)
-{
-    if (!p.J4 || !p.fp4_sweep || p.na_p % kT != 0 || p.nb_p % kT != 0 || Rp % kT != 0 || width < 1 ||
-        width > kMaxTableWidth)
-        return hipErrorInvalidValue;
-    static const hipError_t lds_attr = [] {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bq_halfsweep_fp4<128, 4>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           DmaGeom<128, 4>::lds + (int)sizeof(uint32_t) * kMaxTableWidth);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bq_halfsweep_fp4<64, 8>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    DmaGeom<64, 8>::lds + (int)sizeof(uint32_t) * kMaxTableWidth);
-        return e;
-    }();
-    if (lds_attr != hipSuccess) return lds_attr;
-    const bool A = side == 0;
-    const int Ns_p = A ? p.na_p : p.nb_p, Ko = (A ? p.nb_p : p.na_p) / 2;
-    const uint8_t *Mo = A ? MB4 : MA4;
-    const uint8_t *Jx = A ? p.J4 : p.JT4;
-    const int8_t *hs = A ? p.hA : p.hB;
-    uint8_t *Ms = A ? MA4 : MB4;
-    const uint32_t site_base = A ? 0u : (uint32_t)p.na;
-    const int tiles_s = Ns_p / kT, tiles_r = Rp / kT;
-    const dim3 grid((unsigned)(tiles_s * tiles_r));
-    const int bands = tiles_s % 8 == 0 ? 1 : 0;
-    const size_t tab = sizeof(uint32_t) * (size_t)width;
-    if (Ko % 128 == 0)
-        hipLaunchKernelGGL((k_bq_halfsweep_fp4<128, 4>), grid, dim3(kThreads), (DmaGeom<128, 4>::lds + tab), st, Mo,
-                           Jx, hs, Ms, trow, width, Ns_p, Ko, tiles_s, bands, site_base, sweep, rq0, key.k0, key.k1,
-                           1u);
-    else
-        hipLaunchKernelGGL((k_bq_halfsweep_fp4<64, 8>), grid, dim3(kThreads), (DmaGeom<64, 8>::lds + tab), st, Mo, Jx,
-                           hs, Ms, trow, width, Ns_p, Ko, tiles_s, bands, site_base, sweep, rq0, key.k0, key.k1, 1u);
     return hipGetLastError();
 }
 

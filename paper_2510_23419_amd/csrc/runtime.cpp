@@ -212,9 +212,9 @@ extern "C" int pbit_create(pbit_ctx **out, int device, uint64_t hbm_budget_bytes
     if (!ctx) return fail(PBIT_E_NOMEM, "pbit_create: host allocation failed");
     ctx->device = device;
     ctx->budget = hbm_budget_bytes;
-    if (const char *v = std::getenv("PBIT_BQ_VARIANT")) {  // tuning override: 1..8 (see BqVariant)
+    if (const char *v = std::getenv("PBIT_BQ_VARIANT")) {  // tuning override: 1..3 (see BqVariant)
         const int k = std::atoi(v);
-        if (k >= 1 && k <= 8) ctx->bq_forced = (BqVariant)k;
+        if (k >= 1 && k <= 3) ctx->bq_forced = (BqVariant)k;
     }
     if (const char *v = std::getenv("PBIT_EA_STREAM")) ctx->ea_stream_forced = std::atoi(v) != 0;
     ctx->serial = g_ctx_serial.fetch_add(1);
@@ -379,26 +379,11 @@ static int load_biclique(pbit_ctx *ctx, const pbit_problem_desc *d, Problem &p)
         hB[b] = d->h ? d->h[na + b] : 0;
         amax = std::max(amax, colsum[b] + std::abs(hB[b]));
     }
-    void *dJ = nullptr, *dJT = nullptr, *dhA = nullptr, *dhB = nullptr, *dJ4 = nullptr, *dJT4 = nullptr;
+    void *dJ = nullptr, *dJT = nullptr, *dhA = nullptr, *dhB = nullptr;
     int rc = upload(ctx, p, J.data(), J.size(), &dJ);
     if (rc == PBIT_OK) rc = upload(ctx, p, JT.data(), JT.size(), &dJT);
     if (rc == PBIT_OK) rc = upload(ctx, p, hA.data(), hA.size(), &dhA);
     if (rc == PBIT_OK) rc = upload(ctx, p, hB.data(), hB.size(), &dhB);
-    if (rc == PBIT_OK) {
-        // packed 4-bit float couplings (the batched tiles, and the half-sweep of large sides):
-        // +1 = 0x2, -1 = 0xA, 0 = 0x0
-        auto code = [](int8_t v) { return (uint8_t)(v > 0 ? 0x2 : (v < 0 ? 0xA : 0x0)); };
-        auto pack = [&](const std::vector<int8_t> &M, int rows, int cols, std::vector<uint8_t> &out) {
-            out.assign((size_t)rows * cols / 2, 0);
-            for (size_t k = 0; k < out.size(); ++k)
-                out[k] = (uint8_t)(code(M[2 * k]) | (code(M[2 * k + 1]) << 4));  // rows have even length
-        };
-        std::vector<uint8_t> J4, JT4;
-        pack(J, na_p, nb_p, J4);
-        pack(JT, nb_p, na_p, JT4);
-        rc = upload(ctx, p, J4.data(), J4.size(), &dJ4);
-        if (rc == PBIT_OK) rc = upload(ctx, p, JT4.data(), JT4.size(), &dJT4);
-    }
     void *dJb = nullptr, *dJTb = nullptr, *dhA2 = nullptr, *dhB2 = nullptr;
     if (rc == PBIT_OK) {
         // the kernels on spin bits (per-instance half-sweep and batched tiles): K byte p = 16 g + 4 j + i of every group of 32
@@ -460,8 +445,7 @@ static int load_biclique(pbit_ctx *ctx, const pbit_problem_desc *d, Problem &p)
     p.N = (int64_t)na + nb;
     p.amax = amax;
     p.bq = BqView{na, nb, na_p, nb_p, (const int8_t *)dJ, (const int8_t *)dJT, (const int8_t *)dhA,
-                  (const int8_t *)dhB, (const uint8_t *)dJ4, (const uint8_t *)dJT4, pad == kBqPadLarge,
-                  (const int8_t *)dJb, (const int8_t *)dJTb, (const int32_t *)dhA2, (const int32_t *)dhB2,
+                  (const int8_t *)dhB, (const int8_t *)dJb, (const int8_t *)dJTb, (const int32_t *)dhA2, (const int32_t *)dhB2,
                   (const uint32_t *)dJ2, (const uint32_t *)dJT2};
     return PBIT_OK;
 }
@@ -759,9 +743,7 @@ int spins_in_range(const int8_t *s, size_t n)
 struct DevState {
     int R = 0, Rp = 0;
     int8_t *spins = nullptr;  // EA: [N][Rp]
-    int8_t *MA = nullptr, *MB = nullptr;  // biclique int8 spins (staging when held packed)
-    bool fp4 = false;                     // biclique spins held as packed 4-bit floats
-    uint8_t *MA4 = nullptr, *MB4 = nullptr;
+    int8_t *MA = nullptr, *MB = nullptr;  // biclique int8 spins (staging when held as bits)
     bool bits = false;                    // biclique spins held as bits
     uint32_t *MAb = nullptr, *MBb = nullptr;
     uint32_t *table = nullptr;
@@ -779,12 +761,13 @@ constexpr int kSlabChunk = 1000;  // sweeps per launch of the LDS-resident cube 
 // initialised) spin buffers, whose contents do not affect the timing.
 static int tune_biclique(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStream_t st)
 {
-    if (ctx->bq_forced != BqVariant::Auto && ctx->bq_forced != BqVariant::Fp4) {
-        // a forced kernel the shape cannot take falls back to the tuned choice
-        if (ctx->bq_forced != BqVariant::Bits || ds.MAb) {
-            ds.variant = ctx->bq_forced;
-            return PBIT_OK;
-        }
+    // the DMA and bit tiles need sides padded to 128 (and the bit tiles a bit copy of
+    // the spins, made where the replicas pad to 256)
+    const bool large = P.bq.na_p % 128 == 0 && P.bq.nb_p % 128 == 0;
+    const BqVariant f = ctx->bq_forced;
+    if (f == BqVariant::Small || (f == BqVariant::Dma && large) || (f == BqVariant::Bits && ds.MAb)) {
+        ds.variant = f;  // a forced kernel the shape cannot take falls back to the tuned choice
+        return PBIT_OK;
     }
     const std::array<int, 3> shape{P.bq.na_p, P.bq.nb_p, ds.Rp};
     auto it = ctx->bq_tuned.find(shape);
@@ -792,21 +775,19 @@ static int tune_biclique(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStrea
         ds.variant = it->second;
         return PBIT_OK;
     }
-    const bool large = P.bq.na_p % 128 == 0 && P.bq.nb_p % 128 == 0;
     if (!large) {
         ds.variant = BqVariant::Small;
         ctx->bq_tuned[shape] = ds.variant;
         return PBIT_OK;
     }
-    const BqVariant cand[] = {BqVariant::K64D4, BqVariant::K128D2, BqVariant::K128D4, BqVariant::Dma64,
-                              BqVariant::Dma128, BqVariant::Small, BqVariant::Bits};
+    const BqVariant cand[] = {BqVariant::Dma, BqVariant::Small, BqVariant::Bits};
     hipEvent_t e0, e1;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     if (e != hipSuccess) return device_fail(ctx, e, "hipEventCreate (tuning)");
     const Key key{0u, 0u};
     float best_ms = 0.f;
-    BqVariant best = BqVariant::K128D4;
+    BqVariant best = BqVariant::Dma;
     for (BqVariant v : cand) {
         if (v == BqVariant::Bits && !ds.MAb) continue;  // no bit copy: the shape cannot take it
         float ms = 0.f;
@@ -851,28 +832,19 @@ static int prepare(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, h
         if (rc) return rc;
         ds.spins = (int8_t *)v;
     } else {
-        // int8 spins, plus a packed copy where a kernel runs on one: packed 4-bit floats on
-        // request, bits where the sides are padded to 128 (the tuner then times the bit kernel)
-        // the bit kernel's tiles hold 256 replicas: a forced bit kernel pads to that
+        // int8 spins, plus a bit copy where the sides are padded to 128 and the replicas to 256
+        // (the tuner then times the bit kernel, whose tiles hold 256 replicas: a forced bit
+        // kernel pads to that)
         const bool bits_forced = ctx->bq_forced == BqVariant::Bits && P.bq.Jb;
         ds.Rp = round_up(R, bits_forced ? 256 : kBqRPad);
         const size_t a = (size_t)ds.Rp * P.bq.na_p, b = (size_t)ds.Rp * P.bq.nb_p;
-        ds.fp4 = P.bq.fp4_sweep && ctx->bq_forced == BqVariant::Fp4;
         rc = scratch(ctx, Slot::Spins, a + b, &v);
         if (rc) return rc;
         ds.MA = (int8_t *)v;
         ds.MB = ds.MA + a;
         hipError_t e = hipMemsetAsync(ds.MA, 0, a + b, st);
         if (e != hipSuccess) return device_fail(ctx, e, "hipMemsetAsync");
-        if (ds.fp4) {
-            rc = scratch(ctx, Slot::Aux, (a + b) / 2, &v);
-            if (rc) return rc;
-            ds.MA4 = (uint8_t *)v;
-            ds.MB4 = ds.MA4 + a / 2;
-            e = hipMemsetAsync(ds.MA4, 0, (a + b) / 2, st);
-            if (e != hipSuccess) return device_fail(ctx, e, "hipMemsetAsync");
-            ds.variant = BqVariant::Fp4;
-        } else if (bqb_supported(P.bq, ds.Rp) &&
+        if (bqb_supported(P.bq, ds.Rp) &&
                    (ctx->bq_forced == BqVariant::Auto || ctx->bq_forced == BqVariant::Bits)) {
             rc = scratch(ctx, Slot::Aux, (a + b) / 8, &v);
             if (rc) return rc;
@@ -901,7 +873,7 @@ static int prepare(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, h
                                   hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return device_fail(ctx, e, "hipMemcpyAsync (table)");
 
-    if (P.kind == PBIT_BICLIQUE && !ds.fp4 && d->n_sweeps > 0) {
+    if (P.kind == PBIT_BICLIQUE && d->n_sweeps > 0) {
         rc = tune_biclique(ctx, P, ds, st);
         if (rc) return rc;
     }
@@ -925,9 +897,6 @@ static int prepare(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, h
     if (rowlayout)
         e = init_rows ? ea_from_rows(P.ea, init_rows, R, ds.spins, ds.Rp, st)
                       : ea_init(P.ea, ds.spins, ds.Rp, rq0, key, st);
-    else if (ds.fp4)
-        e = init_rows ? bq4_from_rows(P.bq, init_rows, R, ds.MA4, ds.MB4, st)
-                      : bq4_init(P.bq, ds.MA4, ds.MB4, R, rq0, key, st);
     else
         e = init_rows ? bq_from_rows(P.bq, init_rows, R, ds.MA, ds.MB, st) : bq_init(P.bq, ds.MA, ds.MB, R, rq0, key, st);
     if (e == hipSuccess && ds.bits) e = bqb_pack(P.bq, ds.MA, ds.MB, ds.MAb, ds.MBb, ds.Rp, st);
@@ -952,8 +921,6 @@ static hipError_t sweep(pbit_ctx *ctx, const Problem &P, DevState &ds, int s, ui
             e = ea_halfsweep(P.ea, ds.spins, ds.Rp, c, earow, t, rq0, key, st);
         else if (P.kind == PBIT_GRAPH)
             e = graph_halfsweep(P.graph, c, ds.spins, ds.Rp, row, ds.width, t, rq0, key, st);
-        else if (ds.fp4)
-            e = bq4_halfsweep(P.bq, c, ds.MA4, ds.MB4, ds.Rp, row, ds.width, t, rq0, key, st);
         else if (ds.bits)
             e = bqb_halfsweep(P.bq, c, ds.MAb, ds.MBb, ds.Rp, row, ds.width, t, rq0, key, st);
         else
@@ -990,9 +957,8 @@ static hipError_t energies(const Problem &P, DevState &ds, hipStream_t st)
 {
     if (P.kind == PBIT_GRAPH) return graph_energy(P.graph, ds.spins, ds.Rp, ds.R, ds.E32, st);
     if (P.kind == PBIT_EA3D) return ea_energy(P.ea, ds.spins, ds.Rp, ds.R, ds.E32, st);
-    if (ds.fp4 || ds.bits) {
-        hipError_t e = ds.fp4 ? bq4_unpack(P.bq, ds.MA4, ds.MB4, ds.MA, ds.MB, ds.Rp, st)
-                              : bqb_unpack(P.bq, ds.MAb, ds.MBb, ds.MA, ds.MB, ds.Rp, st);
+    if (ds.bits) {
+        hipError_t e = bqb_unpack(P.bq, ds.MAb, ds.MBb, ds.MA, ds.MB, ds.Rp, st);
         if (e != hipSuccess) return e;
     }
     return bq_energy(P.bq, ds.MA, ds.MB, ds.R, ds.Rp, ds.E32, st);
@@ -1001,7 +967,6 @@ static hipError_t energies(const Problem &P, DevState &ds, hipStream_t st)
 static hipError_t to_rows(const Problem &P, DevState &ds, int8_t *dst, hipStream_t st)
 {
     if (P.kind != PBIT_BICLIQUE) return ea_to_rows(P.ea, ds.spins, ds.Rp, dst, ds.R, st);
-    if (ds.fp4) return bq4_to_rows(P.bq, ds.MA4, ds.MB4, dst, ds.R, st);
     if (ds.bits) {
         hipError_t e = bqb_unpack(P.bq, ds.MAb, ds.MBb, ds.MA, ds.MB, ds.Rp, st);
         if (e != hipSuccess) return e;

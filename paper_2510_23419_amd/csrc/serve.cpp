@@ -48,11 +48,13 @@ struct BJob {
     std::vector<uint32_t> table;  // threshold rows built ahead of admission (batch calls), else empty
     int kind = 0, N = 0, R = 0, S = 0;
     int rs = 4, tiles = 0, width = 1, chunk = 1;
-    int mode = kTileInt8;  // biclique tile operands: int8 rows (default), spin bits or packed 4-bit floats
+    int mode = kTileInt8;  // biclique tile operands: int8 rows (default) or spin bits
     // device memory (released when the job finishes)
     void *d_table = nullptr, *d_state = nullptr, *d_energy = nullptr;
     size_t bytes = 0;
     bool admitted = false, started = false, finished = false;
+    int status = PBIT_OK;  // PBIT_E_NOMEM: the job could not be admitted while nothing else ran
+    bool filled = false;   // batch API: result copied out and device memory released
     int s_done = 0, sweeps_done = 0;
     std::vector<int32_t> energy;  // latest per-replica energies
     std::vector<int64_t> etrace;  // [trace_len][R]
@@ -144,21 +146,20 @@ void serve_shutdown(pbit_ctx *ctx)
 
 // ---------------------------------------------------------------- job set-up
 
-// Bytes of one biclique replica row in a tile: one byte per site, or two sites per byte.
+// Bytes of one biclique replica row in a tile: one byte per site, or one bit.
 static int bq_row_bytes(const BJob &j)
 {
     const int n = j.P->bq.na_p + j.P->bq.nb_p;
-    return j.mode == kTileBits ? n / 8 : j.mode == kTileFp4 ? n / 2 : n;
+    return j.mode == kTileBits ? n / 8 : n;
 }
 
-// Operand mode of a context's biclique tiles: int8 rows unless the fp4 or the bit
-// variant is forced.  Bit rows let 128 replicas share each coupling fragment at any
+// Operand mode of a context's biclique tiles: int8 rows unless the bit variant is
+// forced.  Bit rows let 128 replicas share each coupling fragment at any
 // side length, but on the bag's sides (n <= 1024) a tile's Philox draws and
 // decisions cost about as much as its MFMAs, and the int8 rows' smaller tiles
 // spread a job over more CUs: measured, int8 rows are the faster default there.
 static int tile_mode(const pbit_ctx *ctx)
 {
-    if (ctx->bq_forced == BqVariant::Fp4) return kTileFp4;
     if (ctx->bq_forced == BqVariant::Bits) return kTileBits;
     return kTileInt8;
 }
@@ -200,6 +201,7 @@ static int plan_job(pbit_ctx *ctx, BJob &j)
         const int na_p = P.bq.na_p, nb_p = P.bq.nb_p;
         j.rs = 0;
         for (int rs : {128, 64, 32}) {
+            if (rs == 128 && j.mode != kTileBits) continue;  // int8 rows: 64 and 32 replicas
             if (bq_tile_lds(rs, na_p, nb_p, j.width, j.mode) > (size_t)kMaxLdsTile) continue;
             j.rs = rs;  // the smallest that fits, if none passes the tests below
             const double item = 2.0 * na_p * nb_p * rs * std::max(j.S, 1);
@@ -229,8 +231,7 @@ static void rows_to_tiles(const BJob &j, const int8_t *rows, std::vector<int8_t>
                 tiles_out[((size_t)(r / j.rs) * j.N + i) * j.rs + (r % j.rs)] = rows[(size_t)r * j.N + i];
     } else {
         // spin bits (set = -1, bit col % 8 of byte col / 8: the little-endian words the
-        // kernel reads), int8 spins, or packed 4-bit floats (+1 = 0x2, -1 = 0xA, two
-        // sites per byte, lower site in the low nibble)
+        // kernel reads) or int8 spins
         const int Pw = bq_row_bytes(j);
         tiles_out.assign((size_t)j.tiles * j.rs * Pw, 0);
         for (int r = 0; r < j.R; ++r)
@@ -240,8 +241,6 @@ static void rows_to_tiles(const BJob &j, const int8_t *rows, std::vector<int8_t>
                 const size_t row = (size_t)(r / j.rs) * j.rs + (r % j.rs);
                 if (j.mode == kTileBits)
                     tiles_out[row * Pw + col / 8] |= (uint8_t)((m < 0 ? 1 : 0) << (col % 8));
-                else if (j.mode == kTileFp4)
-                    tiles_out[row * Pw + col / 2] |= (uint8_t)((m > 0 ? 0x2 : 0xA) << (4 * (col & 1)));
                 else
                     tiles_out[row * Pw + col] = m;
             }
@@ -263,9 +262,6 @@ static void tiles_to_rows(const BJob &j, const int8_t *tl, int8_t *rows)
                 const size_t row = (size_t)(r / j.rs) * j.rs + (r % j.rs);
                 if (j.mode == kTileBits) {
                     rows[(size_t)r * j.N + i] = ((uint8_t)tl[row * Pw + col / 8] >> (col % 8)) & 1 ? -1 : 1;
-                } else if (j.mode == kTileFp4) {
-                    const int nib = ((uint8_t)tl[row * Pw + col / 2] >> (4 * (col & 1))) & 15;
-                    rows[(size_t)r * j.N + i] = nib == 0 ? 0 : ((nib & 8) ? -1 : 1);
                 } else {
                     rows[(size_t)r * j.N + i] = tl[row * Pw + col];
                 }
@@ -394,7 +390,7 @@ static int launch_round(pbit_ctx *ctx, ServeState &s)
         } else {
             const BqView &v = j->P->bq;
             const int k = kind_of_rs(j->rs);
-            BqJobDev jd{v.J, v.JT, v.J4, v.JT4, v.Jb, v.JTb, v.hA2, v.hB2, v.J2, v.JT2, v.hA, v.hB,
+            BqJobDev jd{v.J, v.JT, v.Jb, v.JTb, v.hA2, v.hB2, v.J2, v.JT2, v.hA, v.hB,
                         (const uint32_t *)j->d_table, (uint8_t *)j->d_state,
                         (int32_t *)j->d_energy, v.na, v.nb, v.na_p, v.nb_p, j->width,
                         (uint32_t)j->d.sweep_offset, (uint32_t)j->d.replica_offset >> 2, key.k0, key.k1};
@@ -511,9 +507,22 @@ static int step(pbit_ctx *ctx, ServeState &s, bool wait)
     }
     while (!s.queue.empty() && (int)s.running.size() < s.max_running) {
         BJob *j = s.queue.front();
-        if (ctx->budget && ctx->in_use + j->bytes > ctx->budget) break;
-        int rc = admit(ctx, *j);
-        if (rc == PBIT_E_NOMEM) break;  // wait for running jobs to free memory
+        int rc = ctx->budget && ctx->in_use + j->bytes > ctx->budget
+                     ? fail(PBIT_E_NOMEM, "job %llu needs %llu bytes; %llu of the %llu-byte budget are in use",
+                            (unsigned long long)j->id, (unsigned long long)j->bytes,
+                            (unsigned long long)ctx->in_use, (unsigned long long)ctx->budget)
+                     : admit(ctx, *j);
+        if (rc == PBIT_E_NOMEM) {
+            if (!s.running.empty() || s.in_flight) break;  // running jobs will free memory
+            // nothing the scheduler runs will free memory (it is held by problems, by
+            // other entry points' scratch or by finished jobs not yet polled): the job
+            // fails instead of waiting for ever
+            s.queue.pop_front();
+            j->status = PBIT_E_NOMEM;
+            j->finished = true;
+            release(ctx, *j);
+            continue;
+        }
         if (rc) return rc;
         s.queue.pop_front();
         s.running.push_back(j);
@@ -582,6 +591,25 @@ static int fill_result(pbit_ctx *ctx, BJob &j, pbit_result *res)
     return PBIT_OK;
 }
 
+// Take a failing batch call's jobs out of the scheduler: finish the round in
+// flight (it may use their memory), then drop them from the queue and the running
+// list and release their device memory and problem references.  Their result
+// structs are not touched.
+static void withdraw(pbit_ctx *ctx, ServeState &s, const std::vector<BJob *> &mine)
+{
+    if (s.in_flight) {
+        if (harvest(ctx, s) != PBIT_OK) {
+            for (int k = 0; k < kKinds; ++k) (void)hipStreamSynchronize(s.st[k]);
+            s.in_flight = false;
+        }
+    }
+    for (BJob *m : mine) {
+        s.queue.erase(std::remove(s.queue.begin(), s.queue.end(), m), s.queue.end());
+        s.running.erase(std::remove(s.running.begin(), s.running.end(), m), s.running.end());
+        release(ctx, *m);
+    }
+}
+
 }  // namespace pbit
 
 #define PBIT_SERVE_ENTER(ctx)                                                                \
@@ -630,6 +658,13 @@ extern "C" int pbit_poll(pbit_ctx *ctx, uint64_t job, pbit_result *result)
         if (rc) return rc;
         BJob &j = *it->second;
         if (!j.finished) return PBIT_PENDING;
+        if (j.status != PBIT_OK) {
+            const int st = j.status;
+            const unsigned long long bytes = (unsigned long long)j.bytes;
+            s.jobs.erase(it);
+            return fail(st, "pbit_poll: the job (%llu bytes of device memory) could not be admitted while no "
+                        "other job ran", bytes);
+        }
         rc = fill_result(ctx, j, result);
         s.jobs.erase(it);
         return rc;
@@ -686,19 +721,31 @@ extern "C" int pbit_anneal_batch(pbit_ctx *ctx, const pbit_batch_job *jobs, int3
             mine.push_back(j);
         }
         prebuild_tables(mine);
-        for (;;) {
-            bool all = true;
-            for (BJob *m : mine) all = all && m->finished;
-            if (all) break;
-            int rc = step(ctx, s, true);
-            if (rc) return rc;
-        }
         int frc = PBIT_OK;
-        for (BJob *m : mine) {
-            const int rc = fill_result(ctx, *m, m->user);
-            if (rc && frc == PBIT_OK) frc = rc;
-            s.jobs.erase(m->id);
+        for (;;) {
+            // copy finished jobs out at once: their device memory then serves the jobs
+            // still queued
+            bool all = true;
+            for (BJob *m : mine) {
+                if (m->finished && !m->filled) {
+                    m->filled = true;
+                    const int rc = m->status != PBIT_OK ? m->status : fill_result(ctx, *m, m->user);
+                    if (rc && frc == PBIT_OK) {
+                        frc = rc;
+                        if (m->status != PBIT_OK)
+                            fail(rc, "pbit_anneal_batch: job %d needs %llu bytes of device memory and could not "
+                                 "be admitted while no other job ran", (int)(std::find(mine.begin(), mine.end(), m) -
+                                                                             mine.begin()),
+                                 (unsigned long long)m->bytes);
+                    }
+                }
+                all = all && m->finished;
+            }
+            if (all || frc != PBIT_OK) break;
+            frc = step(ctx, s, true);
         }
+        if (frc != PBIT_OK) withdraw(ctx, s, mine);
+        for (BJob *m : mine) s.jobs.erase(m->id);
         return frc;
     } catch (const std::bad_alloc &) {
         return fail(PBIT_E_NOMEM, "pbit_anneal_batch: host allocation failed");

@@ -62,10 +62,23 @@ def test_batch_matches_oracle(ctx):
         pbit.pbit_unload_problem(ctx, p)
 
 
+def _oracle_groups(inst, beta, R, seed, got, groups):
+    """Replica groups of a result against the oracle run on those replicas alone
+    (replica_offset): the counters use the global replica index, so a slice of
+    four replicas equals the same rows of the whole run."""
+    g = graph_of(inst)
+    for gi in groups:
+        cnt = min(4, R - 4 * gi)
+        ref = oracle.anneal(g, beta, cnt, seed, replica_offset=4 * gi)
+        assert np.array_equal(got.spins[4 * gi:4 * gi + cnt], ref.spins), (inst["dims"], gi)
+        assert np.array_equal(got.energies[4 * gi:4 * gi + cnt], ref.energies), (inst["dims"], gi)
+
+
 def test_batch_equals_single_runs_at_mixed_bag_sizes(ctx):
     """A slice of the mixed bag (cubes L in 8..24, bicliques n in 64..1024,
     uneven replica and sweep counts), shortened to 60..200 sweeps: each job's
-    batched result equals the same job through the per-instance path."""
+    batched result equals the same job through the per-instance path, and its
+    first and last replica groups equal the oracle."""
     bag = synth.mixed_bag(seed=3, n_instances=12, replica_range=(32, 200), sweep_range=(60, 200))
     probs = [pbit.load_instance(ctx, j["instance"]) for j in bag]
     _say("mixed-bag slice of %d jobs" % len(bag))
@@ -75,6 +88,8 @@ def test_batch_equals_single_runs_at_mixed_bag_sizes(ctx):
         single = pbit.pbit_anneal(ctx, p, j["beta"], j["replicas"], j["seed"])
         assert np.array_equal(o.spins, single.spins), j["instance"]["dims"]
         assert np.array_equal(o.energies, single.energies)
+        R = j["replicas"]
+        _oracle_groups(j["instance"], j["beta"], R, j["seed"], o, sorted({0, (R - 1) // 4}))
         pbit.pbit_unload_problem(ctx, p)
 
 
@@ -83,7 +98,8 @@ def test_batch_cube_tile_widths(ctx):
     with at least 16 replicas), 8-replica tiles (where 16 do not fit the LDS or the
     job has 8..15 replicas) and 4-replica tiles, each with a ragged last tile, dense
     and diluted couplings, with and without fields, and non-cubic sides: batched
-    results equal the per-instance path (itself bit-exact with the oracle)."""
+    results equal the per-instance path, and the first replica group and the
+    ragged last one equal the oracle."""
     rng = np.random.default_rng(7)
     cases = [((20, 20, 20), 20, "zero", 1.0), ((22, 22, 22), 12, "uniform3", 0.9), ((24, 24, 24), 8, "zero", 1.0),
              ((20, 22, 16), 17, "uniform3", 1.0), ((6, 6, 6), 16, "zero", 0.8), ((20, 20, 20), 5, "uniform3", 0.9),
@@ -103,6 +119,7 @@ def test_batch_cube_tile_widths(ctx):
         assert np.array_equal(o.spins, single.spins), j["inst"]["dims"]
         assert np.array_equal(o.energies, single.energies), j["inst"]["dims"]
         assert o.sweeps_done == len(j["beta"])
+        _oracle_groups(j["inst"], j["beta"], j["R"], j["seed"], o, sorted({0, (j["R"] - 1) // 4}))
         pbit.pbit_unload_problem(ctx, p)
 
 
@@ -233,3 +250,38 @@ def test_serving_errors(ctx):
         for jid in (a, b):
             while pbit.pbit_poll(c2.ctx, jid, 4, 8, 2000) is None:
                 pass
+
+
+def test_job_that_cannot_fit_fails_instead_of_waiting():
+    """Under a budget that is tight after loading problems and running one
+    pbit_anneal (whose scratch the context keeps), a job that fits the budget by
+    itself but not beside what is already held fails with E_NOMEM, in a batch
+    call and through submit/poll, instead of waiting for ever; the context keeps
+    working afterwards."""
+    budget = 3_000_000
+    with pbit.Context(0, hbm_budget_bytes=budget) as c:
+        inst = synth.ea_instance(20, seed=3)  # 8000 sites
+        p = pbit.load_instance(c.ctx, inst)
+        pbit.pbit_anneal(c.ctx, p, synth.beta_linear(0.1, 1.0, 3), 128, seed=1)  # ~2 MB of kept scratch
+        held = pbit.pbit_bytes_in_use(c.ctx)
+        R = 128  # 16-replica tiles: 8 x 128,000 bytes of tile state
+        assert held + 8000 * R > budget and 8000 * R + 200_000 < budget, held
+        beta = synth.beta_linear(0.1, 1.0, 20)
+        _say("budget stall: %d bytes held of %d" % (held, budget))
+        with pytest.raises(pbit.PbitError) as ei:
+            pbit.pbit_anneal_batch(c.ctx, [dict(problem=p, beta=beta, n_replicas=R, seed=2)])
+        assert ei.value.code == pbit.PBIT_E_NOMEM
+        jid = pbit.pbit_submit(c.ctx, p, beta, R, 2)
+        with pytest.raises(pbit.PbitError) as ei:
+            for _ in range(10_000):
+                if pbit.pbit_poll(c.ctx, jid, R, 8000, len(beta)) is not None:
+                    break
+        assert ei.value.code == pbit.PBIT_E_NOMEM
+        with pytest.raises(pbit.PbitError) as ei:
+            pbit.pbit_poll(c.ctx, jid, R, 8000, len(beta))  # the failed job is retired
+        assert ei.value.code == pbit.PBIT_E_HANDLE
+        # a job that fits still runs, bit-exact, and the problem can be unloaded
+        out = pbit.pbit_anneal_batch(c.ctx, [dict(problem=p, beta=beta, n_replicas=16, seed=2)])[0]
+        ref = oracle.anneal(graph_of(inst), beta, 4, 2)
+        assert np.array_equal(out.spins[:4], ref.spins)
+        pbit.pbit_unload_problem(c.ctx, p)
