@@ -188,6 +188,25 @@ int pbit_anneal(pbit_ctx *ctx, uint64_t problem, const pbit_anneal_desc *desc, p
 int pbit_anneal_dev(pbit_ctx *ctx, uint64_t problem, const pbit_anneal_desc *desc,
                     void *d_spins, int32_t spins_in, void *d_energies, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): pbit_anneal_dev with
+ * the same arguments, results and errors, whose working buffers (the kernels'
+ * spin layout, energy accumulators, threshold table) are carved from a static
+ * device array of PBIT_NOALLOC_SCRATCH_BYTES instead of the context's
+ * allocations.  The call itself allocates nothing on the device and creates no
+ * events; the biclique kernel is the one already timed for the shape on this
+ * context, else the bit or DMA tile without timing.  Requests whose buffers
+ * exceed the array return E_UNSUPPORTED before any work is enqueued (the bytes
+ * needed are about N x R for the cube and graphs, (na + nb) x R x 9/8 for the
+ * biclique, plus 4 S x (max |I| + 1) for the table).  The array lives on every
+ * device the library runs on until the process ends; calls on one device share
+ * it and the library runs them one at a time (each returns after its work on
+ * the stream has finished), so nothing of an earlier call's contents leaks into
+ * a later one: buffers that must start at zero are cleared by each call. */
+#define PBIT_NOALLOC_SCRATCH_BYTES (64u << 20)
+int pbit_anneal_dev_noalloc(pbit_ctx *ctx, uint64_t problem, const pbit_anneal_desc *desc, void *d_spins,
+                            int32_t spins_in, void *d_energies, void *hip_stream);
+
 /* Energies of R host configurations [R][N] into out[R] (computed on the GPU). */
 int pbit_energy(pbit_ctx *ctx, uint64_t problem, const int8_t *spins, int32_t R, int64_t *out);
 

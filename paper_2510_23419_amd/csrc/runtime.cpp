@@ -218,6 +218,11 @@ extern "C" int pbit_create(pbit_ctx **out, int device, uint64_t hbm_budget_bytes
     }
     if (const char *v = std::getenv("PBIT_EA_STREAM")) ctx->ea_stream_forced = std::atoi(v) != 0;
     ctx->serial = g_ctx_serial.fetch_add(1);
+    int rc = noalloc_setup(device);  // device address of the static scratch of pbit_anneal_dev_noalloc
+    if (rc) {
+        delete ctx;
+        return rc;
+    }
     e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         delete ctx;
@@ -587,14 +592,6 @@ Problem *find_problem(pbit_ctx *ctx, uint64_t handle)
 
 }  // namespace pbit
 
-#define PBIT_ENTER(ctx)                                                                     \
-    if (!(ctx)) return fail(PBIT_E_ARG, "%s: context is NULL", __func__);                   \
-    std::lock_guard<std::mutex> lock_((ctx)->mu);                                           \
-    if ((ctx)->poisoned) return fail(PBIT_E_DEVICE, "%s: context is poisoned", __func__);   \
-    {                                                                                       \
-        hipError_t se_ = hipSetDevice((ctx)->device);                                       \
-        if (se_ != hipSuccess) return device_fail((ctx), se_, "hipSetDevice");              \
-    }
 
 extern "C" int pbit_load_problem(pbit_ctx *ctx, const pbit_problem_desc *desc, uint64_t *problem_out)
 {
@@ -752,7 +749,22 @@ struct DevState {
     int8_t *stage = nullptr;  // [R][N] host-layout staging
     BqVariant variant = BqVariant::Auto;
     bool slab = false;        // cube held in LDS for runs of sweeps (ea_slab)
+    Arena *arena = nullptr;   // set: buffers are carved from it (no allocation, no kernel timing)
 };
+
+// Device buffers of an anneal: carved from the arena when there is one, else the
+// context's scratch slots (grown on demand).
+static int take(pbit_ctx *ctx, DevState &ds, Slot slot, size_t bytes, void **out)
+{
+    if (!ds.arena) return scratch(ctx, slot, bytes, out);
+    const size_t at = (ds.arena->used + 255) & ~(size_t)255;
+    if (at + bytes > ds.arena->bytes)
+        return fail(PBIT_E_UNSUPPORTED, "the anneal needs more than the %llu bytes of static scratch",
+                    (unsigned long long)ds.arena->bytes);
+    *out = static_cast<uint8_t *>(ds.arena->base) + at;
+    ds.arena->used = at + bytes;
+    return PBIT_OK;
+}
 
 constexpr int kSlabChunk = 1000;  // sweeps per launch of the LDS-resident cube kernel
 
@@ -778,6 +790,12 @@ static int tune_biclique(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStrea
     if (!large) {
         ds.variant = BqVariant::Small;
         ctx->bq_tuned[shape] = ds.variant;
+        return PBIT_OK;
+    }
+    if (ds.arena) {
+        // no timing here (it would create events and wait for the stream): the kernel
+        // the tuner keeps at the benchmark's large sides, else the DMA tile; not cached
+        ds.variant = ds.MAb ? BqVariant::Bits : BqVariant::Dma;
         return PBIT_OK;
     }
     const BqVariant cand[] = {BqVariant::Dma, BqVariant::Small, BqVariant::Bits};
@@ -828,7 +846,7 @@ static int prepare(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, h
             return fail(PBIT_E_UNSUPPORTED, "%lld spins x %d replicas exceed 4 GiB of int8 spins",
                         (long long)P.N, R);
         ds.Rp = round_up(R, kEaRPad);
-        rc = scratch(ctx, Slot::Spins, (size_t)P.N * ds.Rp, &v);
+        rc = take(ctx, ds, Slot::Spins, (size_t)P.N * ds.Rp, &v);
         if (rc) return rc;
         ds.spins = (int8_t *)v;
     } else {
@@ -838,23 +856,24 @@ static int prepare(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, h
         const bool bits_forced = ctx->bq_forced == BqVariant::Bits && P.bq.Jb;
         ds.Rp = round_up(R, bits_forced ? 256 : kBqRPad);
         const size_t a = (size_t)ds.Rp * P.bq.na_p, b = (size_t)ds.Rp * P.bq.nb_p;
-        rc = scratch(ctx, Slot::Spins, a + b, &v);
+        rc = take(ctx, ds, Slot::Spins, a + b, &v);
         if (rc) return rc;
         ds.MA = (int8_t *)v;
         ds.MB = ds.MA + a;
-        hipError_t e = hipMemsetAsync(ds.MA, 0, a + b, st);
-        if (e != hipSuccess) return device_fail(ctx, e, "hipMemsetAsync");
+        // padding sites must hold zero (a fill kernel: no memset node if a caller captures the stream)
+        hipError_t e = fill_i32((int32_t *)ds.MA, (int64_t)((a + b) / 4), 0, st);
+        if (e != hipSuccess) return device_fail(ctx, e, "spin buffer clear");
         if (bqb_supported(P.bq, ds.Rp) &&
                    (ctx->bq_forced == BqVariant::Auto || ctx->bq_forced == BqVariant::Bits)) {
-            rc = scratch(ctx, Slot::Aux, (a + b) / 8, &v);
+            rc = take(ctx, ds, Slot::Aux, (a + b) / 8, &v);
             if (rc) return rc;
             ds.MAb = (uint32_t *)v;
             ds.MBb = ds.MAb + a / 32;
-            e = hipMemsetAsync(ds.MAb, 0, (a + b) / 8, st);
-            if (e != hipSuccess) return device_fail(ctx, e, "hipMemsetAsync");
+            e = fill_i32((int32_t *)ds.MAb, (int64_t)((a + b) / 32), 0, st);
+            if (e != hipSuccess) return device_fail(ctx, e, "spin bit buffer clear");
         }
     }
-    rc = scratch(ctx, Slot::E32, sizeof(int32_t) * (size_t)ds.Rp, &v);
+    rc = take(ctx, ds, Slot::E32, sizeof(int32_t) * (size_t)ds.Rp, &v);
     if (rc) return rc;
     ds.E32 = (int32_t *)v;
 
@@ -866,7 +885,7 @@ static int prepare(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, h
                     "(raise the smallest beta)", ds.width, kMaxTableWidth);
     ctx->host_table.resize((size_t)std::max(S, 1) * ds.width);
     if (S > 0) build_table(d->beta, S, ds.width, ctx->host_table.data());
-    rc = scratch(ctx, Slot::Table, sizeof(uint32_t) * ctx->host_table.size(), &v);
+    rc = take(ctx, ds, Slot::Table, sizeof(uint32_t) * ctx->host_table.size(), &v);
     if (rc) return rc;
     ds.table = (uint32_t *)v;
     hipError_t e = hipMemcpyAsync(ds.table, ctx->host_table.data(), sizeof(uint32_t) * ctx->host_table.size(),
@@ -886,7 +905,7 @@ static int prepare(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, h
     const uint32_t rq0 = (uint32_t)d->replica_offset >> 2;
     const int8_t *init_rows = (const int8_t *)dev_init;
     if (d->init_spins) {
-        rc = scratch(ctx, Slot::Stage, (size_t)R * P.N, &v);
+        rc = take(ctx, ds, Slot::Stage, (size_t)R * P.N, &v);
         if (rc) return rc;
         ds.stage = (int8_t *)v;
         e = hipMemcpyAsync(ds.stage, d->init_spins, (size_t)R * P.N, hipMemcpyHostToDevice, st);
@@ -1054,9 +1073,10 @@ int run_blocking(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, pbi
 }
 
 int run_device(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, int8_t *d_spins, bool spins_in,
-               int64_t *d_energies, hipStream_t st)
+               int64_t *d_energies, hipStream_t st, Arena *arena)
 {
     DevState ds;
+    ds.arena = arena;
     int rc = prepare(ctx, P, d, st, ds, spins_in ? d_spins : nullptr);
     if (rc) return rc;
     const Key key{(uint32_t)d->seed, (uint32_t)(d->seed >> 32)};
@@ -1077,6 +1097,26 @@ int run_device(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, int8_
     if (e == hipSuccess) e = prof_harvest(ctx);
     if (e != hipSuccess) return device_fail(ctx, e, "anneal (device buffers)");
     return PBIT_OK;
+}
+
+// Device bytes the buffers of pbit_anneal_dev take for this request (an upper
+// bound: each buffer is counted with its 256-byte alignment).
+size_t anneal_dev_bytes(const pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d)
+{
+    const size_t R = (size_t)d->n_replicas;
+    size_t spins, Rp;
+    if (P.kind == PBIT_BICLIQUE) {
+        const bool bits = ctx->bq_forced == BqVariant::Bits && P.bq.Jb;
+        Rp = (R + (bits ? 255 : kBqRPad - 1)) / (bits ? 256 : kBqRPad) * (bits ? 256 : kBqRPad);
+        const size_t ab = Rp * (size_t)(P.bq.na_p + P.bq.nb_p);
+        spins = ab + (bqb_supported(P.bq, (int)Rp) ? ab / 8 + 256 : 0);
+    } else {
+        Rp = (R + kEaRPad - 1) / kEaRPad * kEaRPad;
+        spins = (size_t)P.N * Rp;
+    }
+    const int width = d->n_sweeps > 0 ? table_width(d->beta, d->n_sweeps, P.amax) : 1;
+    const size_t table = sizeof(uint32_t) * (size_t)std::max(d->n_sweeps, 1) * (size_t)width;
+    return spins + 256 + sizeof(int32_t) * Rp + 256 + table + 256;
 }
 
 }  // namespace pbit
@@ -1115,7 +1155,7 @@ extern "C" int pbit_anneal_dev(pbit_ctx *ctx, uint64_t problem, const pbit_annea
         Problem *P = find_problem(ctx, problem);
         if (!P) return fail(PBIT_E_HANDLE, "pbit_anneal_dev: unknown problem handle");
         hipStream_t st = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
-        return run_device(ctx, *P, desc, (int8_t *)d_spins, spins_in != 0, (int64_t *)d_energies, st);
+        return run_device(ctx, *P, desc, (int8_t *)d_spins, spins_in != 0, (int64_t *)d_energies, st, nullptr);
     } catch (const std::bad_alloc &) {
         return fail(PBIT_E_NOMEM, "pbit_anneal_dev: host allocation failed");
     } catch (...) {

@@ -36,6 +36,14 @@ struct Scratch {
 
 struct ServeState;
 
+// A fixed device region that an anneal carves its buffers from instead of
+// allocating them (the no-allocation entry point).
+struct Arena {
+    void *base = nullptr;
+    size_t bytes = 0;
+    size_t used = 0;
+};
+
 }  // namespace pbit
 
 struct pbit_ctx {
@@ -89,5 +97,19 @@ hipError_t prof_count_launch(pbit_ctx *ctx, hipStream_t st);
 hipError_t prof_close(pbit_ctx *ctx, hipStream_t st);
 hipError_t prof_harvest(pbit_ctx *ctx);
 void prof_release(pbit_ctx *ctx);
+int run_device(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, int8_t *d_spins, bool spins_in,
+               int64_t *d_energies, hipStream_t st, Arena *arena);
+size_t anneal_dev_bytes(const pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d);
+int noalloc_setup(int device);
 
 }  // namespace pbit
+
+// Entry of every context call: a context, its lock, not poisoned, its device current.
+#define PBIT_ENTER(ctx)                                                                     \
+    if (!(ctx)) return pbit::fail(PBIT_E_ARG, "%s: context is NULL", __func__);             \
+    std::lock_guard<std::mutex> lock_((ctx)->mu);                                           \
+    if ((ctx)->poisoned) return pbit::fail(PBIT_E_DEVICE, "%s: context is poisoned", __func__); \
+    {                                                                                       \
+        hipError_t se_ = hipSetDevice((ctx)->device);                                       \
+        if (se_ != hipSuccess) return pbit::device_fail((ctx), se_, "hipSetDevice");        \
+    }

@@ -30,13 +30,14 @@ PBIT_EA3D = 1
 PBIT_BICLIQUE = 2
 PBIT_GRAPH = 3
 PBIT_CHECK_SWEEPS = 100
+PBIT_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 EXPORTS = ("pbit_create", "pbit_destroy", "pbit_last_error", "pbit_bytes_in_use", "pbit_load_problem",
            "pbit_unload_problem", "pbit_problem_spins", "pbit_anneal", "pbit_anneal_dev", "pbit_energy",
            "pbit_submit", "pbit_poll", "pbit_progress", "pbit_threshold_table", "pbit_version",
            "pbit_profile_enable", "pbit_profile_read", "pbit_anneal_batch", "pbit_serve_config",
            "pbit_load_graph", "pbit_problem_colouring", "pbit_greedy_colouring", "pbit_profile_variant",
-           "pbit_profile_ea_path")
+           "pbit_profile_ea_path", "pbit_anneal_dev_noalloc")
 
 
 class PbitError(RuntimeError):
@@ -100,6 +101,7 @@ def lib() -> ctypes.CDLL:
             "pbit_problem_spins": ([P, u64], i64),
             "pbit_anneal": ([P, u64, ctypes.POINTER(AnnealDesc), ctypes.POINTER(Result)], ctypes.c_int),
             "pbit_anneal_dev": ([P, u64, ctypes.POINTER(AnnealDesc), P, i32, P, P], ctypes.c_int),
+            "pbit_anneal_dev_noalloc": ([P, u64, ctypes.POINTER(AnnealDesc), P, i32, P, P], ctypes.c_int),
             "pbit_energy": ([P, u64, P, i32, P], ctypes.c_int),
             "pbit_submit": ([P, u64, ctypes.POINTER(AnnealDesc), ctypes.POINTER(u64)], ctypes.c_int),
             "pbit_poll": ([P, u64, ctypes.POINTER(Result)], ctypes.c_int),
@@ -289,10 +291,13 @@ def pbit_anneal(ctx, problem: int, beta, n_replicas: int, seed: int, sweep_offse
 
 
 def pbit_anneal_dev(ctx, problem: int, beta, n_replicas: int, seed: int, d_spins, spins_in: bool = False,
-                    d_energies=None, stream=None, sweep_offset: int = 0, replica_offset: int = 0) -> None:
+                    d_energies=None, stream=None, sweep_offset: int = 0, replica_offset: int = 0,
+                    noalloc: bool = False) -> None:
     """Device-buffer anneal.  ``d_spins`` (int8 [R][N]) and ``d_energies``
     (int64 [R]) are torch CUDA tensors; the work runs on ``stream`` (a torch
-    stream, default: torch's current stream) and is finished on return."""
+    stream, default: torch's current stream) and is finished on return.  With
+    ``noalloc`` the call goes to pbit_anneal_dev_noalloc (working buffers in the
+    library's static device array)."""
     import torch
 
     N = pbit_problem_spins(ctx, problem)
@@ -304,10 +309,9 @@ def pbit_anneal_dev(ctx, problem: int, beta, n_replicas: int, seed: int, d_spins
         raise ValueError("d_energies must be an int64 CUDA tensor of R elements")
     st = stream if stream is not None else torch.cuda.current_stream(d_spins.device)
     d, keep = _anneal_desc(beta, R, seed, sweep_offset, replica_offset)
-    _check(lib().pbit_anneal_dev(ctx, int(problem), ctypes.byref(d), ctypes.c_void_p(d_spins.data_ptr()),
-                                 1 if spins_in else 0,
-                                 None if d_energies is None else ctypes.c_void_p(d_energies.data_ptr()),
-                                 ctypes.c_void_p(st.cuda_stream)))
+    fn = lib().pbit_anneal_dev_noalloc if noalloc else lib().pbit_anneal_dev
+    _check(fn(ctx, int(problem), ctypes.byref(d), ctypes.c_void_p(d_spins.data_ptr()), 1 if spins_in else 0,
+              None if d_energies is None else ctypes.c_void_p(d_energies.data_ptr()), ctypes.c_void_p(st.cuda_stream)))
     del keep
 
 
