@@ -74,6 +74,20 @@ def make_instance(w):
     return inst, beta
 
 
+def cpu_model():
+    """The host CPU's model name and logical CPU count, as the kernel reports them."""
+    name = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return name, os.cpu_count() or 1
+
+
 def host_threads():
     """Host threads for the oracle's all-core leg: the cores this process may run
     on, at most 16 (one GPU's share of a shared host)."""
@@ -114,12 +128,12 @@ def cpu_baseline(w, inst, beta, budget_s):
     with ThreadPoolExecutor(max_workers=T) as pool:
         list(pool.map(lambda t: oracle.anneal(g, beta[:S], R, seed=1, replica_offset=R * t), range(T)))
     dtT = time.perf_counter() - t0
-    cpu = platform.processor() or platform.machine()
+    model, nproc = cpu_model()
     return {"value": T * R * N * S / dtT, "unit": "p-bit updates/s", "cores": T, "kind": "oracle",
-            "one_core_value": R * N * S / dt1,
+            "one_core_value": R * N * S / dt1, "cpu_model": model, "host_nproc": nproc,
             "sample": "first %d of %d sweeps of the same schedule, replicas 0-%d of %d on one core (%.1f s), then "
-                      "replicas 0-%d on %d threads at once (%.1f s), C oracle (%s)"
-                      % (S, len(beta), R - 1, w["R"], dt1, T * R - 1, T, dtT, cpu)}
+                      "replicas 0-%d on %d threads at once (%.1f s); C oracle on %s (%d logical CPUs, %d used)"
+                      % (S, len(beta), R - 1, w["R"], dt1, T * R - 1, T, dtT, model, nproc, T)}
 
 
 def graph_launch_bytes(ctx, prob, inst, R):
@@ -368,12 +382,50 @@ def alg1_bench(args, pbit, torch):
     ctx.close()
 
 
+PROBES = {
+    # name: (probe id, size, reps, metric, unit, peak, unit scale)
+    "philox": (1, 64, 50, "Philox4x32-10 words/s (the sweep's counter layout, no other work)", "words/s", None),
+    "copy": (2, 1 << 30, 20, "device copy bandwidth (bytes read + written per second, 1 GiB each way)", "GB/s",
+             HBM_PEAK_GBS),
+    "mfma": (3, 64, 10, "int8 MFMA throughput (v_mfma_i32_32x32x32_i8 chains, operands in registers)", "TOP/s",
+             INT8_MFMA_PEAK_TOPS),
+}
+
+
+def probe_bench(args, pbit, name):
+    """One of the ceilings the sweep kernels are measured against, timed on its own."""
+    probe, size, reps, metric, unit, peak = PROBES[name]
+    ctx = pbit.Context(0)
+    ms, work = pbit.pbit_probe(ctx.ctx, probe, size, reps)
+    rate = work / (ms * 1e-3)
+    value = rate / 1e9 if unit == "GB/s" else (rate / 1e12 if unit == "TOP/s" else rate)
+    extra = {}
+    if name == "philox":
+        # what the rate caps: one word per p-bit update, 2 algorithmic bytes per stencil update
+        extra = {"updates_per_s_cap": rate, "stencil_hbm_cap_GBs": 2 * rate / 1e9,
+                 "stencil_hbm_cap_frac": 2 * rate / 1e9 / HBM_PEAK_GBS,
+                 "valu_lane_ops_per_word_at_peak": VALU_PEAK_TLANEOPS * 1e12 / rate}
+    res = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": reps, "warmup": 1,
+           "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": {"philox": "u32", "copy": "u8", "mfma": "int8"}[name], "data": "synthetic",
+           "config": dict({"workload": "ceiling probe %s, size %d, %d launches" % (name, size, reps),
+                           "work_per_launch": work}, **extra),
+           "roofline": {"bound": {"philox": "alu", "copy": "hbm", "mfma": "mfma"}[name], "achieved": value,
+                        "peak": peak if peak else VALU_PEAK_TLANEOPS * 1e12 / 10,
+                        "unit": unit if peak else "words/s (10 lane-ops per word)",
+                        "frac": value / peak if peak else rate / (VALU_PEAK_TLANEOPS * 1e12 / 10),
+                        "traffic": None}}
+    print(json.dumps(res), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="ea32", choices=sorted(WORKLOADS) + ["mixed", "serve", "alg1"])
+    ap.add_argument("--workload", default="ea32",
+                    choices=sorted(WORKLOADS) + ["mixed", "serve", "alg1"] + sorted(PROBES))
     ap.add_argument("--alg1-qualities", type=float, nargs="+", default=[0.90, 0.95, 0.98],
                     help="alg1: solution qualities p (pass when E <= p G)")
     ap.add_argument("--alg1-max", type=int, default=20000, help="alg1: largest sweep budget tried")
@@ -419,6 +471,9 @@ def main():
         return
     if args.workload == "alg1":
         alg1_bench(args, pbit, torch)
+        return
+    if args.workload in PROBES:
+        probe_bench(args, pbit, args.workload)
         return
 
     w = WORKLOADS[args.workload]
@@ -516,7 +571,8 @@ def main():
 
     # residual energy against sweeps: one more anneal, outside the timed region, with every
     # replica's energy recorded every S/100 sweeps; residual of the best and of the mean
-    # replica against the best energy this anneal reaches
+    # replica against an independent reference: the best of 64 replicas annealed over the
+    # same schedule with another seed (bit-identical to the oracle's 64 runs by parity)
     trace = None
     if args.trace_points > 0:
         every = max(1, S // args.trace_points)
@@ -524,8 +580,10 @@ def main():
         tr = pbit.pbit_anneal(ctx.ctx, prob, beta, R, 1, trace_every=every, want_spins=False)
         traced_ms = (time.perf_counter() - t0) * 1e3
         et = tr.energy_trace.astype(float)
-        ref = float(min(et.min(), tr.best_energy))
-        trace = {"every_sweeps": every, "reference_energy": ref, "traced_anneal_ms": traced_ms,
+        ref = float(pbit.pbit_anneal(ctx.ctx, prob, beta, 64, 7777, want_spins=False).best_energy)
+        trace = {"every_sweeps": every, "reference_energy": ref,
+                 "reference": "best of 64 replicas, same schedule, seed 7777",
+                 "final_best_energy": float(tr.best_energy), "traced_anneal_ms": traced_ms,
                  "sweeps": [every * (k + 1) for k in range(et.shape[0])],
                  "residual_best": [round((float(r.min()) - ref) / abs(ref), 6) for r in et],
                  "residual_mean": [round((float(r.mean()) - ref) / abs(ref), 6) for r in et]}

@@ -295,6 +295,22 @@ int pbit_profile_variant(pbit_ctx *ctx, int32_t *variant);
  * was created.  Both give the same spins.  *path is written on success only. */
 int pbit_profile_ea_path(pbit_ctx *ctx, int32_t *path);
 
+/* The ceilings the sweep kernels are measured against, each timed as a kernel of
+ * its own over `reps` launches (after one warm-up launch) on the context's
+ * stream.  *ms_per_launch receives the mean launch time and *work_per_launch
+ * the work one launch does:
+ *   PBIT_PROBE_PHILOX  `size` Philox4x32-10 blocks per thread (the counter layout of
+ *                      the sweep), 8 workgroups of 256 threads per CU; work = words drawn;
+ *   PBIT_PROBE_COPY    a device copy of `size` bytes (16 bytes per thread and step);
+ *                      work = bytes read plus bytes written;
+ *   PBIT_PROBE_MFMA    `size` steps of four independent v_mfma_i32_32x32x32_i8 chains
+ *                      per wave, operands in registers, 8 waves per CU; work = int8
+ *                      operations (two per multiply-add).
+ * Uses the context's scratch memory.  Errors: E_ARG, E_NOMEM, E_DEVICE. */
+enum { PBIT_PROBE_PHILOX = 1, PBIT_PROBE_COPY = 2, PBIT_PROBE_MFMA = 3 };
+int pbit_probe(pbit_ctx *ctx, int32_t probe, int64_t size, int32_t reps, double *ms_per_launch,
+               double *work_per_launch);
+
 /* ---- host-side helpers (no GPU needed) ---------------------------------- */
 
 /* The uint32 minority-threshold table Tm[s][a], s < S, a <= A, as the library

@@ -217,6 +217,7 @@ extern "C" int pbit_create(pbit_ctx **out, int device, uint64_t hbm_budget_bytes
         if (k >= 1 && k <= 3) ctx->bq_forced = (BqVariant)k;
     }
     if (const char *v = std::getenv("PBIT_EA_STREAM")) ctx->ea_stream_forced = std::atoi(v) != 0;
+    if (const char *v = std::getenv("PBIT_EA_ROWS")) ctx->ea_rows = std::max(0, std::atoi(v));  // tuning override
     ctx->serial = g_ctx_serial.fetch_add(1);
     int rc = noalloc_setup(device);  // device address of the static scratch of pbit_anneal_dev_noalloc
     if (rc) {
@@ -937,7 +938,7 @@ static hipError_t sweep(pbit_ctx *ctx, const Problem &P, DevState &ds, int s, ui
             if (e != hipSuccess) return e;
         }
         if (P.kind == PBIT_EA3D)
-            e = ea_halfsweep(P.ea, ds.spins, ds.Rp, c, earow, t, rq0, key, st);
+            e = ea_halfsweep(P.ea, ds.spins, ds.Rp, c, earow, t, rq0, key, st, ctx->ea_rows);
         else if (P.kind == PBIT_GRAPH)
             e = graph_halfsweep(P.graph, c, ds.spins, ds.Rp, row, ds.width, t, rq0, key, st);
         else if (ds.bits)

@@ -73,6 +73,7 @@ struct pbit_ctx {
     pbit::BqVariant bq_forced = pbit::BqVariant::Auto;
     int bq_last_variant = 0;  // biclique half-sweep variant of the latest biclique anneal (0: none yet)
     bool ea_stream_forced = false;  // cubes always take the streaming stencil (PBIT_EA_STREAM=1)
+    int ea_rows = 0;                // lattice rows per workgroup of the streaming stencil (PBIT_EA_ROWS; 0 = default)
     int ea_last_path = 0;           // cube path of the latest cube anneal: 1 stream, 2 LDS-resident (0: none)
     std::map<std::array<int, 3>, pbit::BqVariant> bq_tuned;  // (na_p, nb_p, Rp) -> fastest
 };

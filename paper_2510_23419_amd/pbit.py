@@ -31,13 +31,16 @@ PBIT_BICLIQUE = 2
 PBIT_GRAPH = 3
 PBIT_CHECK_SWEEPS = 100
 PBIT_NOALLOC_SCRATCH_BYTES = 64 << 20
+PBIT_PROBE_PHILOX = 1
+PBIT_PROBE_COPY = 2
+PBIT_PROBE_MFMA = 3
 
 EXPORTS = ("pbit_create", "pbit_destroy", "pbit_last_error", "pbit_bytes_in_use", "pbit_load_problem",
            "pbit_unload_problem", "pbit_problem_spins", "pbit_anneal", "pbit_anneal_dev", "pbit_energy",
            "pbit_submit", "pbit_poll", "pbit_progress", "pbit_threshold_table", "pbit_version",
            "pbit_profile_enable", "pbit_profile_read", "pbit_anneal_batch", "pbit_serve_config",
            "pbit_load_graph", "pbit_problem_colouring", "pbit_greedy_colouring", "pbit_profile_variant",
-           "pbit_profile_ea_path", "pbit_anneal_dev_noalloc")
+           "pbit_profile_ea_path", "pbit_anneal_dev_noalloc", "pbit_probe")
 
 
 class PbitError(RuntimeError):
@@ -102,6 +105,8 @@ def lib() -> ctypes.CDLL:
             "pbit_anneal": ([P, u64, ctypes.POINTER(AnnealDesc), ctypes.POINTER(Result)], ctypes.c_int),
             "pbit_anneal_dev": ([P, u64, ctypes.POINTER(AnnealDesc), P, i32, P, P], ctypes.c_int),
             "pbit_anneal_dev_noalloc": ([P, u64, ctypes.POINTER(AnnealDesc), P, i32, P, P], ctypes.c_int),
+            "pbit_probe": ([P, i32, i64, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
+                           ctypes.c_int),
             "pbit_energy": ([P, u64, P, i32, P], ctypes.c_int),
             "pbit_submit": ([P, u64, ctypes.POINTER(AnnealDesc), ctypes.POINTER(u64)], ctypes.c_int),
             "pbit_poll": ([P, u64, ctypes.POINTER(Result)], ctypes.c_int),
@@ -341,6 +346,13 @@ def pbit_profile_variant(ctx) -> int:
     v = ctypes.c_int32(0)
     _check(lib().pbit_profile_variant(ctx, ctypes.byref(v)))
     return int(v.value)
+
+def pbit_probe(ctx, probe: int, size: int, reps: int = 20):
+    """Mean launch time (ms) and work per launch of a ceiling kernel (PBIT_PROBE_*)."""
+    ms, work = ctypes.c_double(), ctypes.c_double()
+    _check(lib().pbit_probe(ctx, int(probe), int(size), int(reps), ctypes.byref(ms), ctypes.byref(work)))
+    return ms.value, work.value
+
 
 def pbit_threshold_table(beta, A: int) -> np.ndarray:
     beta = np.ascontiguousarray(beta, dtype=np.float64).reshape(-1)
