@@ -328,8 +328,7 @@ def alg1_bench(args, pbit, torch):
     for each quality p, the smallest sweep budget of a linear 0.35 -> 3.5 schedule at
     which 18 of 20 trials end at or below p G, each size starting its search at the
     budget the previous size needed.  G is the best energy of 4096 replicas annealed
-    over 10^4 sweeps (geometric 0.1 -> 5.0).  The i_min of every p is fitted to the
-    anchored logistic of Eq. 4 over N."""
+    over 10^4 sweeps (geometric 0.1 -> 5.0)."""
     import numpy as np
     import synth
     from paper_2510_23419_amd import alg1
@@ -342,10 +341,10 @@ def alg1_bench(args, pbit, torch):
         ref = pbit.pbit_anneal(ctx.ctx, prob, synth.beta_geometric(0.1, 5.0, 10_000), 4096, seed=99, want_spins=False)
         ladder.append((L, prob, ref.best_energy, pbit.pbit_problem_colouring(ctx.ctx, prob)[1]))
     t_ref = time.perf_counter() - t0
-    results, fits, updates = [], {}, 0
+    results, updates = [], 0
     t1 = time.perf_counter()
     for p in args.alg1_qualities:
-        start, pts = 1, []
+        start = 1
         for L, prob, G, groups in ladder:
             r = alg1.i_min(ctx.ctx, prob, G, i_start=start, i_step=1, t=20, p=p, p_succ=0.9, seed=1, window=16,
                            i_max=args.alg1_max)
@@ -358,13 +357,6 @@ def alg1_bench(args, pbit, torch):
                             "budgets_tried": len(r.history)})
             if r.i_min is not None:
                 start = r.i_min
-                pts.append((L ** 3, r.i_min * groups))
-        if len(pts) >= 4:
-            try:
-                Lf, kf, xc = alg1.fit_anchored_logistic([x for x, _ in pts], [y for _, y in pts])
-                fits[str(p)] = {"L": Lf, "k": kf, "x_c": xc}
-            except Exception as e:  # a ladder the logistic does not fit is reported, not fatal
-                fits[str(p)] = {"error": str(e)[:80]}
     wall = time.perf_counter() - t1
     for _, prob, _, _ in ladder:
         pbit.pbit_unload_problem(ctx.ctx, prob)
@@ -376,7 +368,7 @@ def alg1_bench(args, pbit, torch):
         "config": {"workload": "Algorithm 1 on random +-1 cubes L = 2..10 (seed L, h = 0), 20 trials at 90 %% "
                                "success, qualities %s, linear 0.35 -> 3.5, search window 16 budgets"
                                % ",".join("%.2f" % q for q in args.alg1_qualities),
-                   "reference_seconds": t_ref, "i_min": results, "logistic_fits": fits},
+                   "reference_seconds": t_ref, "i_min": results},
     }
     print(json.dumps(res), flush=True)
     ctx.close()

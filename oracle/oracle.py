@@ -244,18 +244,17 @@ def alg1_minimal_budget(pc, G: float, i_start: int, i_step: int, t: int, p: floa
 
     ``pc(i, beta, j)`` is the solver: the final energy of trial j annealed
     over the schedule ``beta`` of i sweeps.  Readings: the budget counts
-    sweeps; the linear schedule runs beta_i to beta_f with both ends
-    included; the search gives up (returns None) past ``i_max``.
+    sweeps; the schedule starts at beta_i and grows by the algorithm's step
+    delta_beta = (beta_f - beta_i) / i after every sweep (so its last value is
+    beta_f - delta_beta); the search gives up (returns None) past ``i_max``.
     Returns (i_min, [(i, fails counted, trials run) ...])."""
     theta = p * G
     m_max = int(np.floor(t * (1.0 - p_succ) + 0.5))
     history = []
     i = i_start
     while i <= i_max:
-        if i == 1:
-            beta = np.array([beta_i], np.float64)
-        else:
-            beta = np.array([beta_i + (beta_f - beta_i) * k / (i - 1) for k in range(i)], np.float64)
+        delta_beta = (beta_f - beta_i) / i
+        beta = np.array([beta_i + k * delta_beta for k in range(i)], np.float64)
         m = 0
         ran = 0
         for j in range(t):

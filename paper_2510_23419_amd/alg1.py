@@ -9,8 +9,8 @@ is the ground-truth energy, growing i by a fixed step from i_start.  Here
   replicas of a single anneal with the same linear schedule;
 * the budget counts sweeps (every update group once, beta constant within a
   sweep); the paper's iterations are sweeps times the number of groups;
-* the linear schedule over i sweeps runs from beta_i to beta_f with both ends
-  included;
+* the linear schedule over i sweeps starts at beta_i and grows by the
+  algorithm's step delta_beta = (beta_f - beta_i) / i after every sweep;
 * candidate budgets are tried ``window`` at a time in one batched launch; the
   answer is still the smallest passing budget in ascending order, so it does
   not depend on the window, and each budget's anneal uses a seed that depends
@@ -38,12 +38,12 @@ def max_fails(t: int, p_succ: float) -> int:
 
 
 def linear_schedule(beta_i: float, beta_f: float, sweeps: int) -> np.ndarray:
-    """beta for sweeps 0..sweeps-1, linear from beta_i to beta_f inclusive."""
+    """beta for sweeps k = 0..sweeps-1: beta_i + k delta_beta with Algorithm 1's
+    step delta_beta = (beta_f - beta_i) / sweeps."""
     if sweeps < 1:
         raise ValueError("a schedule needs at least one sweep")
-    if sweeps == 1:
-        return np.array([float(beta_i)])
-    return beta_i + (beta_f - beta_i) * np.arange(sweeps, dtype=np.float64) / (sweeps - 1)
+    delta_beta = (beta_f - beta_i) / sweeps
+    return np.array([beta_i + k * delta_beta for k in range(sweeps)], np.float64)
 
 
 def budget_seed(seed: int, budget: int) -> int:
@@ -155,36 +155,3 @@ def b_cooled(N: int, E, E0):
     """Inverse temperature reachable by digital cooling from b_eff (Sec. 2.2):
     (2 log 2)(|E0| / N) b_eff."""
     return 2.0 * math.log(2.0) * abs(E0) / N * b_eff(N, E, E0)
-
-
-# ---------------------------------------------------------------- fits
-
-def anchored_logistic(x, L, k, xc):
-    """Logistic through the origin with asymptote L (Eq. 4)."""
-    x = np.asarray(x, np.float64)
-    a = math.exp(-k * xc)
-    return L * ((1.0 + a) / (1.0 + np.exp(-k * (x - xc))) - a)
-
-
-def fit_anchored_logistic(x, y, p0=None):
-    """Least-squares (L, k, xc) of the anchored logistic."""
-    from scipy.optimize import curve_fit
-
-    x = np.asarray(x, np.float64)
-    y = np.asarray(y, np.float64)
-    if p0 is None:
-        p0 = (float(y.max()), 4.0 / max(float(np.ptp(x)), 1e-9), float(np.median(x)))
-    popt, _ = curve_fit(anchored_logistic, x, y, p0=p0, maxfev=20000)
-    return tuple(float(v) for v in popt)
-
-
-def fit_power_law(i, b, b_err=None):
-    """b = a i^c by weighted least squares in log space, each point weighted
-    by the inverse variance of log b (sigma_b / b).  Returns (a, c)."""
-    li = np.log(np.asarray(i, np.float64))
-    lb = np.log(np.asarray(b, np.float64))
-    w = np.ones_like(lb) if b_err is None else (np.asarray(b, np.float64) / np.asarray(b_err, np.float64)) ** 2
-    A = np.stack([np.ones_like(li), li], axis=1)
-    sw = np.sqrt(w)
-    coef, *_ = np.linalg.lstsq(A * sw[:, None], lb * sw, rcond=None)
-    return float(math.exp(coef[0])), float(coef[1])

@@ -63,10 +63,21 @@ def test_threshold_is_p_times_G():
         return -89 if (i == 1 and j < 3) else -90
     i, _ = oracle.alg1_minimal_budget(pc, -100.0, 1, 1, 20, 0.9, 0.9, 0.35, 3.5, 10)
     assert i == 2
-    # the schedule: linear, both ends included
-    assert np.array_equal(seen[-1], np.array([0.35, 3.5]))
+    # the schedule: starts at beta_i, step delta_beta = (beta_f - beta_i) / i
+    assert np.array_equal(seen[-1], np.array([0.35, 0.35 + 3.15 / 2]))
     assert np.array_equal(alg1.linear_schedule(0.35, 3.5, 2), seen[-1])
     assert np.array_equal(alg1.linear_schedule(0.35, 3.5, 1), [0.35])
+
+
+@pytest.mark.parametrize("i", [1, 2, 3, 7, 100, 1000])
+def test_schedule_takes_the_algorithms_step(i):
+    """Algorithm 1 steps beta by (beta_f - beta_i) / i per iteration from beta_i:
+    i values, the first beta_i, equal steps, the last one step short of beta_f."""
+    b = alg1.linear_schedule(0.35, 3.5, i)
+    step = (3.5 - 0.35) / i
+    assert b.shape == (i,) and b[0] == 0.35
+    assert np.allclose(np.diff(b), step, rtol=0, atol=1e-12)
+    assert b[-1] == pytest.approx(3.5 - step, abs=1e-12)
 
 
 @pytest.mark.parametrize("window", [1, 2, 3, 8])
@@ -167,28 +178,3 @@ def test_residual_and_success_rate():
         if abs(e - p * E0) < 1e-6:
             continue
         assert (e <= p * E0) == (alg1.residual(e, E0) <= 1 - p)
-
-
-def test_anchored_logistic_closed_forms_and_fit():
-    L, k, xc = 120.0, 0.8, 6.0
-    assert alg1.anchored_logistic(0.0, L, k, xc) == pytest.approx(0.0, abs=1e-12)
-    assert alg1.anchored_logistic(1e4, L, k, xc) == pytest.approx(L)
-    a = math.exp(-k * xc)
-    assert alg1.anchored_logistic(xc, L, k, xc) == pytest.approx(L * ((1 + a) / 2 - a))
-    x = np.arange(1, 15, dtype=np.float64)
-    fit = alg1.fit_anchored_logistic(x, alg1.anchored_logistic(x, L, k, xc), p0=(100.0, 1.0, 5.0))
-    assert np.allclose(fit, (L, k, xc), rtol=1e-5)
-
-
-def test_power_law_fit():
-    i = np.array([10, 30, 100, 300, 1000, 3000], np.float64)
-    b = 7.07 * i ** 0.37
-    a, c = alg1.fit_power_law(i, b)
-    assert a == pytest.approx(7.07) and c == pytest.approx(0.37)
-    # a wild point with a huge error bar barely moves a weighted fit
-    b2 = b.copy()
-    b2[2] *= 5
-    err = np.full(b.size, 0.01) * b
-    err[2] = 1e3 * b2[2]
-    a2, c2 = alg1.fit_power_law(i, b2, err)
-    assert c2 == pytest.approx(0.37, abs=1e-3)
