@@ -28,6 +28,9 @@ MUTANTS = {
     "energy_update_sign": ("e -= (int64_t)(mn - m[i]) * I;", "e += (int64_t)(mn - m[i]) * I;"),
     "energy_bond_sign": ("e -= (int64_t)bJ[b] * m[bi[b]] * m[bj[b]];", "e += (int64_t)bJ[b] * m[bi[b]] * m[bj[b]];"),
     "threshold_rounding": ("ceil(ldexp(q, 32) - 0.5)", "floor(ldexp(q, 31))"),
+    "init_comparison": ("draw(seed, (uint32_t)i, 0u, rg, 1u) < 0x80000000u ? 1 : -1",
+                        "draw(seed, (uint32_t)i, 0u, rg, 1u) >= 0x80000000u ? 1 : -1"),
+    "init_domain": ("draw(seed, (uint32_t)i, 0u, rg, 1u) < 0x80000000u", "draw(seed, (uint32_t)i, 0u, rg, 0u) < 0x80000000u"),
 }
 
 
@@ -54,6 +57,19 @@ def pin_philox_rocrand(exe):
     for c, line in zip(cases, out):
         got = oracle.philox4x32_10(c[1:], [c[0] & 0xFFFFFFFF, c[0] >> 32])
         if tuple(int(v) for v in got) != tuple(int(v) for v in line.split()):
+            return False
+    return True
+
+
+def pin_random_start_rocrand(exe):
+    # the random start: +1 where word r & 3 of rocRAND's block (i, 0, r >> 2, 1) is below 2^31
+    g = oracle.biclique_graph(3, 2, np.ones((3, 2), np.int8), None)
+    got = oracle.anneal(g, np.zeros(0), 8, 77).spins
+    cases = [(77, i, 0, r >> 2, 1) for r in range(8) for i in range(5)]
+    inp = "\n".join(" ".join(map(str, c)) for c in cases) + "\n"
+    out = subprocess.run([str(exe)], input=inp, capture_output=True, text=True, check=True).stdout.split("\n")
+    for (_, i, _, _, _), line, r in zip(cases, out, [r for r in range(8) for _ in range(5)]):
+        if got[r, i] != (1 if int(line.split()[r & 3]) < 2**31 else -1):
             return False
     return True
 
@@ -134,6 +150,7 @@ def rocrand_exe(tmp_path_factory):
 def _all_pins(exe):
     return {
         "philox_rocrand": pin_philox_rocrand(exe),
+        "random_start_rocrand": pin_random_start_rocrand(exe),
         "threshold_closed_form": pin_threshold_closed_form(),
         "energy_dense": pin_energy_dense(),
         "ferro_ground": pin_ferro_ground(),

@@ -55,3 +55,25 @@ def test_philox_words_look_uniform():
     words = np.concatenate([oracle.philox4x32_10([i, 7, 3, 0], [1, 0]) for i in range(4096)])
     assert abs((words >> 31).mean() - 0.5) < 0.02
     assert abs(words.astype(np.float64).mean() / 2**32 - 0.5) < 0.01
+
+
+@pytest.mark.parametrize("kind", ["cube", "biclique"])
+def test_random_start_is_the_domain_one_word_of_rocrand(rocrand_exe, kind):
+    """The oracle's random start, spin by spin, against rocRAND's Philox4x32-10:
+    replica r at spin i is +1 exactly when word r mod 4 of the block at counter
+    (i, 0, global replica >> 2, 1) is below 2^31.  A swapped comparison, a wrong
+    domain or sweep word, or a wrong word index fails here."""
+    g = (oracle.ea_graph((4, 2, 2), np.ones((3, 16), np.int8), None) if kind == "cube"
+         else oracle.biclique_graph(5, 3, np.ones((5, 3), np.int8), None))
+    seed, R, off = 0x123456789AB, 11, 8
+    got = oracle.anneal(g, np.zeros(0), R, seed, replica_offset=off).spins
+    cases = [(seed, i, 0, (off + r) >> 2, 1) for r in range(R) for i in range(g.n)]
+    inp = "\n".join(" ".join(str(v) for v in c) for c in cases) + "\n"
+    out = subprocess.run([str(rocrand_exe)], input=inp, capture_output=True, text=True, check=True).stdout
+    words = [tuple(int(v) for v in line.split()) for line in out.strip().splitlines()]
+    k = 0
+    for r in range(R):
+        for i in range(g.n):
+            w = words[k][(off + r) & 3]
+            assert got[r, i] == (1 if w < 2**31 else -1), (r, i)
+            k += 1
