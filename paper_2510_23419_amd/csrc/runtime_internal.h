@@ -10,6 +10,7 @@
 
 #include "../../include/pbit.h"
 #include "bq.h"
+#include "host.h"
 
 namespace pbit {
 
@@ -80,19 +81,14 @@ struct pbit_ctx {
 
 namespace pbit {
 
-int fail(int code, const char *fmt, ...);
 int device_fail(pbit_ctx *ctx, hipError_t e, const char *where);
 int dev_alloc(pbit_ctx *ctx, size_t bytes, void **out);
 void dev_free(pbit_ctx *ctx, void *p);
 int scratch(pbit_ctx *ctx, Slot slot, size_t bytes, void **out);
 Problem *find_problem(pbit_ctx *ctx, uint64_t handle);
 int check_desc(const pbit_anneal_desc *d, const char *who);
-uint32_t minority_threshold(double beta, int a);
-int table_width(const double *beta, int S, int amax);
-void build_table(const double *beta, int S, int width, uint32_t *out, int max_threads = 16);
 void serve_shutdown(pbit_ctx *ctx);
 int spins_in_range(const int8_t *s, size_t n);
-int greedy_colouring(int n, int n_bonds, const int32_t *bi, const int32_t *bj, uint8_t *colour, int *n_colours);
 hipError_t prof_begin(pbit_ctx *ctx, int kind, hipStream_t st);
 hipError_t prof_count_launch(pbit_ctx *ctx, hipStream_t st);
 hipError_t prof_close(pbit_ctx *ctx, hipStream_t st);
