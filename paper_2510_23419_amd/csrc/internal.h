@@ -79,5 +79,7 @@ hipError_t graph_energy(const GraphView &g, const int8_t *spins, int Rp, int R, 
 // ---- misc ---------------------------------------------------------------
 hipError_t fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
 hipError_t widen_i32_i64(const int32_t *src, int64_t *dst, int64_t n, hipStream_t st);
+// *hit = sweep if min_r E[r] <= target and *hit is still INT32_MAX
+hipError_t check_target(const int32_t *E, int R, int64_t target, int32_t sweep, int32_t *hit, hipStream_t st);
 
 }  // namespace pbit

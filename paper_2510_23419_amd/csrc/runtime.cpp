@@ -871,6 +871,69 @@ static int fetch_energies(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStre
     return PBIT_OK;
 }
 
+// The device state an anneal's next sweep depends on (the spin layout the sweep kernels read).
+static void state_span(const Problem &P, const DevState &ds, void **ptr, size_t *bytes)
+{
+    if (P.kind != PBIT_BICLIQUE) {
+        *ptr = ds.spins;
+        *bytes = (size_t)P.N * ds.Rp;
+    } else {
+        const size_t ab = (size_t)ds.Rp * (P.bq.na_p + P.bq.nb_p);
+        *ptr = ds.bits ? (void *)ds.MAb : (void *)ds.MA;
+        *bytes = ds.bits ? ab / 8 : ab;
+    }
+}
+
+// Sweeps with a target checked after every sweep, without a host round trip per
+// sweep: chunks of sweeps are enqueued with a from-scratch energy pass and an
+// on-device check after each sweep that records the first sweep meeting the
+// target, and the host reads that once per chunk.  The state at the start of a
+// chunk is kept; when a sweep inside the chunk met the target, the state is
+// restored and the chunk re-run up to that sweep, which reproduces it exactly
+// (the random words depend only on spin, sweep and replica).  Returns the
+// sweeps done.
+static int run_to_target(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, DevState &ds, hipStream_t st,
+                         Key key, uint32_t rq0, int *done_out)
+{
+    constexpr int kChunk = 32;
+    void *state = nullptr, *snap = nullptr, *hitp = nullptr;
+    size_t bytes = 0;
+    state_span(P, ds, &state, &bytes);
+    int rc = scratch(ctx, Slot::Snap, bytes, &snap);
+    if (rc == PBIT_OK) rc = scratch(ctx, Slot::Hit, sizeof(int32_t), &hitp);
+    if (rc) return rc;
+    int32_t *hit_dev = (int32_t *)hitp;
+    hipError_t e = fill_i32(hit_dev, 1, INT32_MAX, st);
+    if (e != hipSuccess) return device_fail(ctx, e, "target flag");
+    int done = 0;
+    for (int s0 = 0; s0 < d->n_sweeps;) {
+        const int s1 = std::min(d->n_sweeps, s0 + kChunk);
+        e = hipMemcpyAsync(snap, state, bytes, hipMemcpyDeviceToDevice, st);
+        for (int s = s0; s < s1 && e == hipSuccess; ++s) {
+            e = sweeps(ctx, P, ds, s, s + 1, (uint32_t)d->sweep_offset, rq0, key, st);
+            if (e == hipSuccess) e = prof_close(ctx, st);
+            if (e == hipSuccess) e = energies(P, ds, st);
+            if (e == hipSuccess) e = check_target(ds.E32, ds.R, d->target_energy, s + 1, hit_dev, st);
+        }
+        int32_t hit = INT32_MAX;
+        if (e == hipSuccess) e = hipMemcpyAsync(&hit, hit_dev, sizeof hit, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e == hipSuccess) e = prof_harvest(ctx);
+        if (e != hipSuccess) return device_fail(ctx, e, "sweeps with a target");
+        if (hit != INT32_MAX) {
+            // back to the chunk's start, then forward to the first sweep that met the target
+            e = hipMemcpyAsync(state, snap, bytes, hipMemcpyDeviceToDevice, st);
+            if (e == hipSuccess) e = sweeps(ctx, P, ds, s0, hit, (uint32_t)d->sweep_offset, rq0, key, st);
+            if (e != hipSuccess) return device_fail(ctx, e, "target replay");
+            done = hit;
+            break;
+        }
+        done = s0 = s1;
+    }
+    *done_out = done;
+    return PBIT_OK;
+}
+
 int run_blocking(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, pbit_result *res)
 {
     const hipStream_t st = ctx->stream;
@@ -883,6 +946,11 @@ int run_blocking(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, pbi
     std::vector<int32_t> e32;
     int done = 0, trace_len = 0;
     bool hit = false;
+    if (d->has_target && d->trace_every == 0) {
+        rc = run_to_target(ctx, P, d, ds, st, key, rq0, &done);
+        if (rc) return rc;
+        hit = true;  // the loop below has nothing left to do
+    }
     for (int s = 0; s < d->n_sweeps && !hit;) {
         // up to the next energy check (every sweep on the per-half-sweep path)
         int s1 = ds.slab ? std::min(d->n_sweeps, s + kSlabChunk) : s + 1;

@@ -28,7 +28,7 @@ struct Problem {
     int jobs = 0;  // serving jobs that still reference the problem
 };
 
-enum class Slot : int { Spins = 0, Table, E32, Stage, Aux, Count };
+enum class Slot : int { Spins = 0, Table, E32, Stage, Aux, Snap, Hit, Count };
 
 struct Scratch {
     void *ptr = nullptr;

@@ -21,6 +21,7 @@
 
 #include "batch.h"
 #include "runtime_internal.h"
+#include "serve_sched.h"
 
 using namespace pbit;
 
@@ -38,7 +39,7 @@ inline int kind_of_rs(int rs) { return rs == 128 ? 1 : (rs == 64 ? 2 : 3); }
 constexpr double kItemOps = 1.5e11;  // multiply-adds of one biclique tile over its anneal
 inline int rs_of_kind(int k) { return k == 1 ? 128 : (k == 2 ? 64 : 32); }
 
-struct BJob {
+struct BJob : SchedJob {
     uint64_t id = 0;
     uint64_t problem = 0;
     Problem *P = nullptr;
@@ -52,9 +53,8 @@ struct BJob {
     // device memory (released when the job finishes)
     void *d_table = nullptr, *d_state = nullptr, *d_energy = nullptr;
     size_t bytes = 0;
-    bool admitted = false, started = false, finished = false;
-    int status = PBIT_OK;  // PBIT_E_NOMEM: the job could not be admitted while nothing else ran
-    bool filled = false;   // batch API: result copied out and device memory released
+    bool admitted = false, started = false;
+    bool filled = false;  // batch API: result copied out and device memory released
     int s_done = 0, sweeps_done = 0;
     std::vector<int32_t> energy;  // latest per-replica energies
     std::vector<int64_t> etrace;  // [trace_len][R]
@@ -65,15 +65,13 @@ struct BJob {
 }  // namespace
 
 struct ServeState {
-    std::deque<BJob *> queue;
-    std::vector<BJob *> running;
+    SchedQueues<BJob> q;  // queue, running jobs, round in flight
     std::map<uint64_t, std::unique_ptr<BJob>> jobs;
     uint64_t next_id = 1;
-    int max_queue = 4096, max_running = 1024, round_sweeps = 500;
+    int max_queue = 4096, round_sweeps = 500;
     // one stream per tile kind
     hipStream_t st[kKinds] = {};
     hipEvent_t fork = nullptr, join[kKinds] = {};
-    bool in_flight = false;
     std::vector<BJob *> round_jobs;
     std::vector<int> round_end;
     // device work lists (grown on demand)
@@ -354,8 +352,9 @@ static void release(pbit_ctx *ctx, BJob &j)
 
 // ---------------------------------------------------------------- rounds
 
-static int launch_round(pbit_ctx *ctx, ServeState &s)
+static int launch_round(pbit_ctx *ctx, ServeState &s, const std::vector<BJob *> &running, bool &launched)
 {
+    launched = false;
     s.round_jobs.clear();
     s.round_end.clear();
     std::vector<EaJobDev> ea;
@@ -363,7 +362,7 @@ static int launch_round(pbit_ctx *ctx, ServeState &s)
     std::vector<WorkItem> items[kKinds];
     std::vector<double> cost[kKinds];
     size_t lds[kKinds] = {};
-    for (BJob *j : s.running) {
+    for (BJob *j : running) {
         if (j->finished) continue;
         const int s0 = j->s_done;
         const int s1 = std::min(j->S, s0 + j->chunk);
@@ -454,7 +453,7 @@ static int launch_round(pbit_ctx *ctx, ServeState &s)
         if (e == hipSuccess) e = hipEventRecord(s.join[k], s.st[k]);
         if (e != hipSuccess) return device_fail(ctx, e, "tile kernel launch");
     }
-    s.in_flight = true;
+    launched = true;
     return PBIT_OK;
 }
 
@@ -470,7 +469,6 @@ static int harvest(pbit_ctx *ctx, ServeState &s)
     hipError_t e = hipSuccess;
     for (int k = 0; k < kKinds && e == hipSuccess; ++k) e = hipStreamSynchronize(s.st[k]);
     if (e != hipSuccess) return device_fail(ctx, e, "round");
-    s.in_flight = false;
     std::vector<int32_t> tile_e;
     for (size_t q = 0; q < s.round_jobs.size(); ++q) {
         BJob &j = *s.round_jobs[q];
@@ -491,46 +489,36 @@ static int harvest(pbit_ctx *ctx, ServeState &s)
             j.sweeps_done = j.s_done;
         }
     }
-    s.running.erase(std::remove_if(s.running.begin(), s.running.end(), [](BJob *j) { return j->finished; }),
-                    s.running.end());
     return PBIT_OK;
 }
+
+// The device side of a scheduling step (see serve_sched.h).
+struct ServeDevice {
+    pbit_ctx *ctx;
+    ServeState &s;
+    bool round_done() { return pbit::round_done(s); }
+    int harvest() { return pbit::harvest(ctx, s); }
+    int admit(BJob *j)
+    {
+        if (ctx->budget && ctx->in_use + j->bytes > ctx->budget)
+            return fail(PBIT_E_NOMEM, "job %llu needs %llu bytes; %llu of the %llu-byte budget are in use",
+                        (unsigned long long)j->id, (unsigned long long)j->bytes, (unsigned long long)ctx->in_use,
+                        (unsigned long long)ctx->budget);
+        return pbit::admit(ctx, *j);
+    }
+    void drop(BJob *j) { release(ctx, *j); }
+    int launch_round(const std::vector<BJob *> &running, bool &launched)
+    {
+        return pbit::launch_round(ctx, s, running, launched);
+    }
+};
 
 // One scheduling step.  With wait = true it blocks until the round it launched
 // (or the one in flight) has been harvested.
 static int step(pbit_ctx *ctx, ServeState &s, bool wait)
 {
-    if (s.in_flight) {
-        if (!wait && !round_done(s)) return PBIT_OK;
-        int rc = harvest(ctx, s);
-        if (rc) return rc;
-    }
-    while (!s.queue.empty() && (int)s.running.size() < s.max_running) {
-        BJob *j = s.queue.front();
-        int rc = ctx->budget && ctx->in_use + j->bytes > ctx->budget
-                     ? fail(PBIT_E_NOMEM, "job %llu needs %llu bytes; %llu of the %llu-byte budget are in use",
-                            (unsigned long long)j->id, (unsigned long long)j->bytes,
-                            (unsigned long long)ctx->in_use, (unsigned long long)ctx->budget)
-                     : admit(ctx, *j);
-        if (rc == PBIT_E_NOMEM) {
-            if (!s.running.empty() || s.in_flight) break;  // running jobs will free memory
-            // nothing the scheduler runs will free memory (it is held by problems, by
-            // other entry points' scratch or by finished jobs not yet polled): the job
-            // fails instead of waiting for ever
-            s.queue.pop_front();
-            j->status = PBIT_E_NOMEM;
-            j->finished = true;
-            release(ctx, *j);
-            continue;
-        }
-        if (rc) return rc;
-        s.queue.pop_front();
-        s.running.push_back(j);
-    }
-    int rc = launch_round(ctx, s);
-    if (rc) return rc;
-    if (wait && s.in_flight) return harvest(ctx, s);
-    return PBIT_OK;
+    ServeDevice dev{ctx, s};
+    return sched_step(s.q, dev, wait);
 }
 
 static int new_job(pbit_ctx *ctx, ServeState &s, uint64_t problem, const pbit_anneal_desc *desc, BJob **out)
@@ -558,7 +546,7 @@ static int new_job(pbit_ctx *ctx, ServeState &s, uint64_t problem, const pbit_an
                     (unsigned long long)j->bytes);
     j->id = ((uint64_t)ctx->serial << 40) | (s.next_id++);
     P->jobs++;
-    s.queue.push_back(j.get());
+    s.q.queue.push_back(j.get());
     *out = j.get();
     s.jobs[j->id] = std::move(j);
     return PBIT_OK;
@@ -597,15 +585,16 @@ static int fill_result(pbit_ctx *ctx, BJob &j, pbit_result *res)
 // structs are not touched.
 static void withdraw(pbit_ctx *ctx, ServeState &s, const std::vector<BJob *> &mine)
 {
-    if (s.in_flight) {
-        if (harvest(ctx, s) != PBIT_OK) {
+    if (s.q.in_flight) {
+        if (harvest(ctx, s) != PBIT_OK)
             for (int k = 0; k < kKinds; ++k) (void)hipStreamSynchronize(s.st[k]);
-            s.in_flight = false;
-        }
+        s.q.in_flight = false;
+        s.q.running.erase(std::remove_if(s.q.running.begin(), s.q.running.end(), [](BJob *j) { return j->finished; }),
+                          s.q.running.end());
     }
     for (BJob *m : mine) {
-        s.queue.erase(std::remove(s.queue.begin(), s.queue.end(), m), s.queue.end());
-        s.running.erase(std::remove(s.running.begin(), s.running.end(), m), s.running.end());
+        s.q.queue.erase(std::remove(s.q.queue.begin(), s.q.queue.end(), m), s.q.queue.end());
+        s.q.running.erase(std::remove(s.q.running.begin(), s.q.running.end(), m), s.q.running.end());
         release(ctx, *m);
     }
 }
@@ -631,7 +620,8 @@ extern "C" int pbit_submit(pbit_ctx *ctx, uint64_t problem, const pbit_anneal_de
         PBIT_SERVE_ENTER(ctx);
         if (!job_out) return fail(PBIT_E_ARG, "pbit_submit: job_out is NULL");
         ServeState &s = *ctx->serve;
-        if ((int)s.queue.size() >= s.max_queue) return fail(PBIT_E_BUSY, "pbit_submit: queue full (%d jobs)", s.max_queue);
+        if ((int)s.q.queue.size() >= s.max_queue)
+            return fail(PBIT_E_BUSY, "pbit_submit: queue full (%d jobs)", s.max_queue);
         BJob *j = nullptr;
         int rc = new_job(ctx, s, problem, desc, &j);
         if (rc) return rc;
@@ -689,7 +679,7 @@ extern "C" int pbit_serve_config(pbit_ctx *ctx, int32_t max_queue, int32_t max_r
     if (max_queue < 0 || max_running < 0 || round_sweeps < 0) return fail(PBIT_E_ARG, "pbit_serve_config: negative limit");
     ServeState &s = *ctx->serve;
     if (max_queue) s.max_queue = max_queue;
-    if (max_running) s.max_running = max_running;
+    if (max_running) s.q.max_running = max_running;
     if (round_sweeps) s.round_sweeps = round_sweeps;
     return PBIT_OK;
 }
@@ -711,7 +701,7 @@ extern "C" int pbit_anneal_batch(pbit_ctx *ctx, const pbit_batch_job *jobs, int3
             if (rc) {
                 // withdraw the jobs queued by this call
                 for (BJob *m : mine) {
-                    s.queue.erase(std::remove(s.queue.begin(), s.queue.end(), m), s.queue.end());
+                    s.q.queue.erase(std::remove(s.q.queue.begin(), s.q.queue.end(), m), s.q.queue.end());
                     if (m->P) m->P->jobs--;
                     s.jobs.erase(m->id);
                 }

@@ -227,6 +227,35 @@ def test_target_stops_at_first_reaching_sweep(ectx):
     pbit.pbit_unload_problem(ctx, prob)
 
 
+@pytest.mark.parametrize("make,R,S,k", [
+    (lambda: synth.biclique_instance(512, seed=9), 256, 120, 70),        # bit tiles; hit inside a chunk
+    (lambda: synth.biclique_instance(40, seed=9, nb=33), 12, 100, 31),   # 64 x 64 tiles; hit on a chunk edge
+    (lambda: synth.dimerized_cube(4, seed=4), 16, 90, 40),               # general graph, greedy groups
+    (lambda: synth.ea_instance(24, seed=2), 8, 70, 65)])                 # streaming cube
+def test_target_checked_on_the_device(ctx, make, R, S, k):
+    """With a target and no trace the library checks the target on the device
+    after every sweep and reads the result once per chunk of sweeps: the run
+    still stops after the first sweep that meets the target, with the spins of
+    that sweep; a target never met runs every sweep."""
+    inst = make()
+    g = graph_of(inst) if inst["kind"] != "graph" else oracle.graph_from_bonds(
+        inst["n"], inst["bond_i"], inst["bond_j"], inst["bond_J"], inst["h"])
+    beta = synth.beta_linear(0.05, 3.0, S)
+    ref = oracle.anneal(g, beta, R, seed=6, trace_every=1)
+    mins = ref.energy_trace.min(axis=1)
+    target = int(mins[k - 1])
+    first = int(np.argmax(mins <= target)) + 1
+    prob = pbit.load_instance(ctx, inst)
+    _say("device target check %s R=%d S=%d first=%d" % (inst["kind"], R, S, first))
+    got = pbit.pbit_anneal(ctx, prob, beta, R, seed=6, target=target)
+    assert got.sweeps_done == first
+    pre = oracle.anneal(g, beta[:first], R, seed=6)
+    assert np.array_equal(got.spins, pre.spins) and np.array_equal(got.energies, pre.energies)
+    never = pbit.pbit_anneal(ctx, prob, beta, R, seed=6, target=int(mins.min()) - 1)
+    assert never.sweeps_done == S and np.array_equal(never.spins, ref.spins)
+    pbit.pbit_unload_problem(ctx, prob)
+
+
 def test_anneal_dev_matches_blocking(ectx):
     import torch
 

@@ -29,3 +29,16 @@ def test_host_code_and_oracle_under_asan_ubsan(tmp_path):
     assert r.returncode == 0, r.stdout + r.stderr
     assert "sanitize ok" in r.stdout
     assert "runtime error" not in r.stderr and "AddressSanitizer" not in r.stderr
+
+
+def test_serving_scheduler_policy_with_a_stub_device(tmp_path):
+    """serve_sched.h, the admission and round policy of the serving loop, driven
+    by a host stub of the device (under the sanitizers too)."""
+    if not shutil.which("g++"):
+        pytest.skip("host compiler not available")
+    exe = tmp_path / "sched_stub"
+    subprocess.run(["g++", "-std=c++17", "-I" + str(ROOT / "paper_2510_23419_amd" / "csrc"),
+                    str(ROOT / "tests" / "helpers" / "sched_stub.cpp"), "-o", str(exe)] + SAN, check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "sched ok" in r.stdout
