@@ -288,6 +288,15 @@ int pbit_profile_read(pbit_ctx *ctx, int32_t kind, double *total_ms, int64_t *la
  * choice.  All give the same spins.  *variant is written on success only. */
 int pbit_profile_variant(pbit_ctx *ctx, int32_t *variant);
 
+/* Graph use of pbit_anneal_dev on this context.  With PBIT_GRAPH=1 set when the
+ * context is created, the sweep launches of pbit_anneal_dev are captured into
+ * one HIP graph, instantiated and launched; the executable graph is kept and
+ * replayed by later calls that launch the same kernels with the same arguments
+ * (same problem, schedule, sweep and replica ranges, seed, kernel path and
+ * working buffers).  Results are the same as without the graph.  Writes the
+ * number of captures and of graph launches so far (either pointer may be NULL). */
+int pbit_profile_graph(pbit_ctx *ctx, int64_t *captures, int64_t *launches);
+
 /* The cube path of the latest cube anneal on this context (0 before any): 1 = the
  * streaming stencil, one launch per half-sweep; 2 = the LDS-resident form, the
  * whole lattice of 16 replicas per workgroup for runs of sweeps, taken for

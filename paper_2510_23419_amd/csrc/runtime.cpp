@@ -131,6 +131,7 @@ extern "C" int pbit_create(pbit_ctx **out, int device, uint64_t hbm_budget_bytes
     }
     if (const char *v = std::getenv("PBIT_EA_STREAM")) ctx->ea_stream_forced = std::atoi(v) != 0;
     if (const char *v = std::getenv("PBIT_EA_ROWS")) ctx->ea_rows = std::max(0, std::atoi(v));  // tuning override
+    if (const char *v = std::getenv("PBIT_GRAPH")) ctx->use_graph = std::atoi(v) != 0;
     ctx->serial = g_ctx_serial.fetch_add(1);
     int rc = noalloc_setup(device);  // device address of the static scratch of pbit_anneal_dev_noalloc
     if (rc) {
@@ -166,6 +167,7 @@ extern "C" void pbit_destroy(pbit_ctx *ctx)
         ctx->problems.clear();
         release_scratch(ctx);
         prof_release(ctx);
+        if (ctx->graph_exec) (void)hipGraphExecDestroy((hipGraphExec_t)ctx->graph_exec);
         (void)hipStreamDestroy(ctx->stream);
     }
     delete ctx;
@@ -1004,6 +1006,58 @@ int run_blocking(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, pbi
     return PBIT_OK;
 }
 
+// The sweep launches of pbit_anneal_dev as one HIP graph (PBIT_GRAPH=1 when the
+// context is created): captured from the stream, instantiated and launched.  The
+// executable graph is kept and replayed while the next call would capture the
+// same launches: same problem, schedule, sweeps, replicas, seed, kernel path and
+// device buffers (the sweep kernels take the decision words of the cube and the
+// buffer addresses as launch arguments).
+static uint64_t launch_key(const Problem &P, const pbit_anneal_desc *d, const DevState &ds, hipStream_t st)
+{
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&h](const void *p, size_t n) {
+        const unsigned char *b = (const unsigned char *)p;
+        for (size_t k = 0; k < n; ++k) h = (h ^ b[k]) * 1099511628211ull;
+    };
+    const void *ptrs[] = {&P, ds.spins, ds.MA, ds.MAb, ds.table, ds.E32, (void *)st};
+    mix(ptrs, sizeof ptrs);
+    mix(d->beta, sizeof(double) * (size_t)d->n_sweeps);
+    const int64_t f[] = {d->n_sweeps, d->sweep_offset, d->n_replicas, d->replica_offset, (int64_t)d->seed,
+                         ds.Rp, ds.width, (int64_t)ds.variant, ds.slab, ds.bits};
+    mix(f, sizeof f);
+    return h;
+}
+
+template <class Loop>
+static int graph_sweeps(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, DevState &ds, hipStream_t st,
+                        Loop &loop)
+{
+    const uint64_t key = launch_key(P, d, ds, st);
+    if (!ctx->graph_exec || ctx->graph_key != key) {
+        if (ctx->graph_exec) (void)hipGraphExecDestroy((hipGraphExec_t)ctx->graph_exec);
+        ctx->graph_exec = nullptr;
+        const int prof = ctx->prof_every;
+        ctx->prof_every = 0;  // no event records inside the graph
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+        hipError_t el = e == hipSuccess ? loop() : e;
+        if (e == hipSuccess) e = hipStreamEndCapture(st, &g);
+        ctx->prof_every = prof;
+        if (e == hipSuccess) e = el;
+        hipGraphExec_t x = nullptr;
+        if (e == hipSuccess) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return device_fail(ctx, e, "sweep graph capture");
+        ctx->graph_exec = x;
+        ctx->graph_key = key;
+        ++ctx->graph_captures;
+    }
+    hipError_t e = hipGraphLaunch((hipGraphExec_t)ctx->graph_exec, st);
+    if (e != hipSuccess) return device_fail(ctx, e, "sweep graph launch");
+    ++ctx->graph_launches;
+    return PBIT_OK;
+}
+
 int run_device(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, int8_t *d_spins, bool spins_in,
                int64_t *d_energies, hipStream_t st, Arena *arena)
 {
@@ -1013,11 +1067,21 @@ int run_device(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, int8_
     if (rc) return rc;
     const Key key{(uint32_t)d->seed, (uint32_t)(d->seed >> 32)};
     const uint32_t rq0 = (uint32_t)d->replica_offset >> 2;
-    for (int s = 0; s < d->n_sweeps;) {
-        const int s1 = ds.slab ? std::min(d->n_sweeps, s + kSlabChunk) : s + 1;
-        hipError_t e = sweeps(ctx, P, ds, s, s1, (uint32_t)d->sweep_offset, rq0, key, st);
+    auto loop = [&]() -> hipError_t {
+        for (int s = 0; s < d->n_sweeps;) {
+            const int s1 = ds.slab ? std::min(d->n_sweeps, s + kSlabChunk) : s + 1;
+            hipError_t e = sweeps(ctx, P, ds, s, s1, (uint32_t)d->sweep_offset, rq0, key, st);
+            if (e != hipSuccess) return e;
+            s = s1;
+        }
+        return hipSuccess;
+    };
+    if (ctx->use_graph && !arena && d->n_sweeps > 0) {
+        rc = graph_sweeps(ctx, P, d, ds, st, loop);
+        if (rc) return rc;
+    } else {
+        hipError_t e = loop();
         if (e != hipSuccess) return device_fail(ctx, e, "sweep launch");
-        s = s1;
     }
     hipError_t e = prof_close(ctx, st);  // a timing window covers sweep launches only
     if (e == hipSuccess) e = to_rows(P, ds, d_spins, st);
@@ -1205,6 +1269,14 @@ extern "C" int pbit_profile_variant(pbit_ctx *ctx, int32_t *variant)
     PBIT_ENTER(ctx);
     if (!variant) return fail(PBIT_E_ARG, "pbit_profile_variant: variant is NULL");
     *variant = ctx->bq_last_variant;
+    return PBIT_OK;
+}
+
+extern "C" int pbit_profile_graph(pbit_ctx *ctx, int64_t *captures, int64_t *launches)
+{
+    PBIT_ENTER(ctx);
+    if (captures) *captures = ctx->graph_captures;
+    if (launches) *launches = ctx->graph_launches;
     return PBIT_OK;
 }
 

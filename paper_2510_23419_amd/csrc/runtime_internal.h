@@ -75,6 +75,11 @@ struct pbit_ctx {
     int bq_last_variant = 0;  // biclique half-sweep variant of the latest biclique anneal (0: none yet)
     bool ea_stream_forced = false;  // cubes always take the streaming stencil (PBIT_EA_STREAM=1)
     int ea_rows = 0;                // lattice rows per workgroup of the streaming stencil (PBIT_EA_ROWS; 0 = default)
+    // pbit_anneal_dev's sweep launches as one HIP graph (PBIT_GRAPH=1), kept for replay
+    bool use_graph = false;
+    void *graph_exec = nullptr;  // hipGraphExec_t
+    uint64_t graph_key = 0;
+    int64_t graph_captures = 0, graph_launches = 0;
     int ea_last_path = 0;           // cube path of the latest cube anneal: 1 stream, 2 LDS-resident (0: none)
     std::map<std::array<int, 3>, pbit::BqVariant> bq_tuned;  // (na_p, nb_p, Rp) -> fastest
 };

@@ -40,7 +40,7 @@ EXPORTS = ("pbit_create", "pbit_destroy", "pbit_last_error", "pbit_bytes_in_use"
            "pbit_submit", "pbit_poll", "pbit_progress", "pbit_threshold_table", "pbit_version",
            "pbit_profile_enable", "pbit_profile_read", "pbit_anneal_batch", "pbit_serve_config",
            "pbit_load_graph", "pbit_problem_colouring", "pbit_greedy_colouring", "pbit_profile_variant",
-           "pbit_profile_ea_path", "pbit_anneal_dev_noalloc", "pbit_probe")
+           "pbit_profile_ea_path", "pbit_anneal_dev_noalloc", "pbit_probe", "pbit_profile_graph")
 
 
 class PbitError(RuntimeError):
@@ -117,6 +117,7 @@ def lib() -> ctypes.CDLL:
             "pbit_profile_read": ([P, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), i32], ctypes.c_int),
             "pbit_profile_variant": ([P, ctypes.POINTER(i32)], ctypes.c_int),
             "pbit_profile_ea_path": ([P, ctypes.POINTER(i32)], ctypes.c_int),
+            "pbit_profile_graph": ([P, ctypes.POINTER(i64), ctypes.POINTER(i64)], ctypes.c_int),
             "pbit_anneal_batch": ([P, ctypes.POINTER(BatchJob), i32], ctypes.c_int),
             "pbit_serve_config": ([P, i32, i32, i32], ctypes.c_int),
             "pbit_load_graph": ([P, ctypes.POINTER(GraphDesc), ctypes.POINTER(u64)], ctypes.c_int),
@@ -359,6 +360,13 @@ def pbit_threshold_table(beta, A: int) -> np.ndarray:
     out = np.zeros((beta.size, int(A) + 1), np.uint32)
     _check(lib().pbit_threshold_table(_ptr(beta), beta.size, int(A), _ptr(out)))
     return out
+
+
+def pbit_profile_graph(ctx):
+    """(captures, graph launches) of pbit_anneal_dev's sweep graph on this context."""
+    c, n = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().pbit_profile_graph(ctx, ctypes.byref(c), ctypes.byref(n)))
+    return c.value, n.value
 
 
 def pbit_profile_ea_path(ctx) -> int:
