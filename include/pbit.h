@@ -213,12 +213,14 @@ int pbit_energy(pbit_ctx *ctx, uint64_t problem, const int8_t *spins, int32_t R,
 /* ---- batched anneals (Sec. 1.3.3: many independent runs) ------------------ */
 
 /* Many independent jobs share persistent kernels: each job is cut into replica
- * tiles (4, 8 or 16 replicas of a whole cube, or 32, 64 or 128 replicas of both
- * sides of a biclique) that never need each other, and every workgroup keeps taking
- * (job, tile, sweep range) items from a device queue with its tile's spins held
- * in LDS.  Results are identical to pbit_anneal for the same job, whatever it is
- * batched with.  Batched jobs need a cube of at most 38,912 sites (a 4-replica tile in LDS) or a biclique
- * with na_p + nb_p <= 4,096 padded sites (E_UNSUPPORTED otherwise).  When a job
+ * tiles (4, 8 or 16 replicas of a whole cube or general graph, or 32 or 64
+ * replicas of both sides of a biclique, 128 with spins held as bits) that never
+ * need each other, and every workgroup keeps taking (job, tile, sweep range)
+ * items from a device queue with its tile's spins held in LDS.  Results are
+ * identical to pbit_anneal for the same job, whatever it is batched with.
+ * Batched jobs need a cube or a general graph of at most 38,912 spins (a
+ * 4-replica tile in LDS) or a biclique with na_p + nb_p <= 4,096 padded sites
+ * (E_UNSUPPORTED otherwise).  When a job
  * has a target or a trace, its energies are checked every trace_every sweeps,
  * or every PBIT_CHECK_SWEEPS sweeps when trace_every is 0, and a target stops
  * the job after the first checked sweep that meets it. */

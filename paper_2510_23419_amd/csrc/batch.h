@@ -39,6 +39,20 @@ struct BqJobDev {
     uint32_t sweep0, rq0, k0, k1;
 };
 
+struct GraphJobDev {
+    const int4 *meta;          // [n] by class position: site, first and end adjacency entry, nnz + h
+    const uint32_t *adj;       // adjacency words in position order: neighbour << 2 | J != 0 | (J == -1) << 1
+    const int32_t *class_start;  // [n_colours + 1] class boundaries in position order
+    const int32_t *bi, *bj;    // bond list (for energies)
+    const int8_t *bJ;
+    const int8_t *h;           // [n] or null
+    const uint32_t *table;     // [S][width] thresholds, row s = local sweep s
+    int8_t *state;             // [tiles][n][rs]: spins of a tile, replica fastest (rs = 4, 8 or 16)
+    int32_t *energy;           // [tiles * rs]
+    int n, n_bonds, n_colours, width, rs;
+    uint32_t sweep0, rq0, k0, k1;
+};
+
 struct WorkItem {
     int32_t job;      // index into the job array of the item's kind
     int32_t tile;
@@ -49,6 +63,7 @@ struct WorkItem {
 };
 
 constexpr int kEaTileThreads = 512;
+constexpr int kGraphTileThreads = 512;
 constexpr int kBqTileThreads = 512;
 
 // Launch a persistent kernel over `n_items` items; `counter` (device int,
@@ -60,8 +75,12 @@ constexpr int kTileInt8 = 0, kTileBits = 2;
 hipError_t bq_tiles(const BqJobDev *jobs, const WorkItem *items, const int32_t *n_items, int32_t *counter,
                     int rs, int mode, int grid, size_t lds_bytes, hipStream_t st);
 
+hipError_t graph_tiles(const GraphJobDev *jobs, const WorkItem *items, const int32_t *n_items, int32_t *counter,
+                       int grid, size_t lds_bytes, hipStream_t st);
+
 // LDS a tile kernel needs for the given job shape.
 size_t ea_tile_lds(int64_t N, int rs);  // rs = 4, 8 or 16 replicas
+size_t graph_tile_lds(int64_t N, int rs);
 size_t bq_tile_lds(int rs, int na_p, int nb_p, int width, int mode);
 hipError_t tiles_set_lds_limit();
 

@@ -236,6 +236,166 @@ __global__ __launch_bounds__(kEaTileThreads) void k_ea_tiles(const EaJobDev *__r
     }
 }
 
+// ---------------------------------------------------------------- graph tiles
+
+// General graphs with k update groups (Sec. 1.2.2): the spins of 4W replicas of
+// the whole graph live in LDS as W dwords per site, in the layout of the cube
+// tiles (byte p of dword k = replica 4k + p, +1 = 0x01, -1 = 0xFF).  The classes
+// are swept in ascending colour order with a workgroup barrier between them; a
+// thread takes one site of the class at a time, reads its record and adjacency
+// words from global memory (class-major, as for the per-instance sweep) and its
+// neighbours' rows from LDS, and counts negative products bytewise exactly as
+// the per-instance kernel does (0x02 per negative product, degree <= 127), so
+// that the field, the Philox counters and the carry decision are the same.
+constexpr int kGraphOff = kGraphMaxDegree + 1;  // |I| <= degree + |h|
+constexpr int kGraphSlots = 2 * kGraphOff + 1;
+
+template <int W>
+__device__ __forceinline__ void graph_tile_item(const WorkItem &w, const GraphJobDev &jb, uint4 *tile_rows,
+                                                uint64_t *gtab, int32_t *eacc, uint32_t one)
+{
+    typedef uint32_t V __attribute__((ext_vector_type(W)));
+    constexpr int RS = 4 * W;
+    V *rows = reinterpret_cast<V *>(tile_rows);  // [n]
+    const int tid = threadIdx.x;
+    const int n = jb.n;
+    const uint32_t rgw = jb.rq0 + (uint32_t)W * (uint32_t)w.tile;  // Philox counter word 2 of the tile's first group
+    V *gst = reinterpret_cast<V *>(jb.state) + (size_t)w.tile * n;
+
+    if (w.init) {
+        for (int i = tid; i < n; i += kGraphTileThreads) {
+            V d;
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                const Block4 b = philox((uint32_t)i, 0u, rgw + (uint32_t)k, kDomainInit, jb.k0, jb.k1);
+                uint32_t packed = 0;
+#pragma unroll
+                for (int p = 0; p < 4; ++p) packed |= (uint32_t)(uint8_t)init_spin(b.w[p]) << (8 * p);
+                d[k] = packed;
+            }
+            rows[i] = d;
+        }
+    } else {
+        for (int i = tid; i < n; i += kGraphTileThreads) rows[i] = load_global<V>(gst + i);
+    }
+
+    for (int s = w.s_begin; s < w.s_end; ++s) {
+        __syncthreads();
+        // decision words by descending field value: entry k is S(I) for I = kGraphOff - k
+        const uint32_t *trow = jb.table + (size_t)s * jb.width;
+        for (int k = tid; k < kGraphSlots; k += kGraphTileThreads) {
+            const int I = kGraphOff - k;
+            const uint32_t T = load_global<uint32_t>(trow + min(I >= 0 ? I : -I, jb.width - 1));
+            gtab[k] = I >= 0 ? (uint64_t)T : ((uint64_t)1 << 32) - T;
+        }
+        __syncthreads();
+        const uint32_t t = jb.sweep0 + (uint32_t)s;
+        for (int c = 0; c < jb.n_colours; ++c) {
+            const int p0 = load_global<int32_t>(jb.class_start + c), p1 = load_global<int32_t>(jb.class_start + c + 1);
+            for (int j = p0 + tid; j < p1; j += kGraphTileThreads) {
+                const v4i mv = load_global<v4i>(jb.meta + j);  // site, first entry, end entry, nnz + h
+                const int4 m = make_int4(mv[0], mv[1], mv[2], mv[3]);
+                const int i = m.x;
+                uint32_t cnt[W];
+#pragma unroll
+                for (int k = 0; k < W; ++k) cnt[k] = 0u;
+                for (int e = m.y; e < m.z; ++e) {
+                    const uint32_t a = load_global<uint32_t>(jb.adj + e);
+                    const V v = rows[a >> 2];
+                    // 0x02 in every byte where J != 0 (keep) and where J = -1 (flip)
+                    const uint32_t keep = (uint32_t)((int32_t)(a << 31) >> 31) & 0x02020202u;
+                    const uint32_t flip = (uint32_t)((int32_t)(a << 30) >> 31) & 0x02020202u;
+#pragma unroll
+                    for (int k = 0; k < W; ++k) cnt[k] += neg2(v[k], keep, flip);
+                }
+                // a byte c of cnt (two per negative product) gives I = base - c: entry kGraphOff - base + c
+                const char *tb = reinterpret_cast<const char *>(gtab) + 8 * (kGraphOff - m.w);
+                V out;
+#pragma unroll
+                for (int k = 0; k < W; ++k) {
+                    const Block4 b = philox((uint32_t)i, t, rgw + (uint32_t)k, kDomainSweep, jb.k0, jb.k1);
+                    uint32_t sgn[4];  // 1: the replica's new spin is -1
+#pragma unroll
+                    for (int p = 0; p < 4; ++p) {
+                        const uint32_t cb = (cnt[k] >> (8 * p)) & 0xFFu;
+                        const uint64_t S = *static_cast<const uint64_t *>(__builtin_assume_aligned(tb + 8 * cb, 8));
+                        sgn[p] = (uint32_t)(((uint64_t)b.w[p] * one + S) >> 32);
+                    }
+                    const uint32_t lo = __builtin_amdgcn_perm(sgn[1], sgn[0], 0x0C0C0400u);
+                    const uint32_t hi = __builtin_amdgcn_perm(sgn[3], sgn[2], 0x0C0C0400u);
+                    out[k] = __builtin_amdgcn_perm(0u, 0xFF01u, __builtin_amdgcn_perm(hi, lo, 0x05040100u));
+                }
+                rows[i] = out;
+            }
+            __syncthreads();
+        }
+    }
+
+    // energies from scratch: E = -sum_bonds J m_i m_j - sum_i h_i m_i; a product is -1
+    // where the two bytes differ (bit 1 of their xor)
+    if (tid < RS) eacc[tid] = 0;
+    __syncthreads();
+    int32_t er[RS];
+#pragma unroll
+    for (int r = 0; r < RS; ++r) er[r] = 0;
+    for (int b = tid; b < jb.n_bonds; b += kGraphTileThreads) {
+        const int J = load_global<int8_t>(jb.bJ + b);
+        if (J == 0) continue;
+        const V mi = rows[load_global<int32_t>(jb.bi + b)], mj = rows[load_global<int32_t>(jb.bj + b)];
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            const uint32_t d = ((mi[k] ^ mj[k]) >> 1) & 0x01010101u;
+#pragma unroll
+            for (int p = 0; p < 4; ++p) er[4 * k + p] -= J * (1 - 2 * (int)((d >> (8 * p)) & 1u));
+        }
+    }
+    if (jb.h)
+        for (int i = tid; i < n; i += kGraphTileThreads) {
+            const int hv = load_global<int8_t>(jb.h + i);
+            if (hv == 0) continue;
+            const V mi = rows[i];
+#pragma unroll
+            for (int k = 0; k < W; ++k)
+#pragma unroll
+                for (int p = 0; p < 4; ++p) er[4 * k + p] -= hv * (int)(int8_t)(mi[k] >> (8 * p));
+        }
+#pragma unroll
+    for (int r = 0; r < RS; ++r) {
+        int v = er[r];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if ((tid & 63) == 0) atomicAdd(&eacc[r], v);
+    }
+    __syncthreads();
+    if (tid < RS) jb.energy[RS * w.tile + tid] = eacc[tid];
+    for (int i = tid; i < n; i += kGraphTileThreads) gst[i] = rows[i];
+}
+
+// Persistent graph-tile kernel: items of any tile width share the launch.
+__global__ __launch_bounds__(kGraphTileThreads) void k_graph_tiles(const GraphJobDev *__restrict__ jobs,
+                                                                   const WorkItem *__restrict__ items,
+                                                                   const int32_t *__restrict__ n_items_p,
+                                                                   int32_t *__restrict__ counter, uint32_t one)
+{
+    extern __shared__ uint4 tile_rows[];
+    __shared__ uint64_t gtab[kGraphSlots];
+    __shared__ int32_t eacc[16];
+    __shared__ int slot;
+    const int n_items = *n_items_p;
+    for (;;) {
+        const int it = take_item(counter, &slot);
+        if (it >= n_items) break;
+        const WorkItem w = items[it];
+        const GraphJobDev jb = jobs[w.job];
+        if (jb.rs == 16)
+            graph_tile_item<4>(w, jb, tile_rows, gtab, eacc, one);
+        else if (jb.rs == 8)
+            graph_tile_item<2>(w, jb, tile_rows, gtab, eacc, one);
+        else
+            graph_tile_item<1>(w, jb, tile_rows, gtab, eacc, one);
+        __syncthreads();  // the next item's first LDS writes wait for this item's last reads
+    }
+}
+
 // ---------------------------------------------------------------- biclique tiles
 
 // A tile holds RB x 32 replicas of both sides in LDS, one row per replica:
@@ -670,6 +830,8 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
 
 size_t ea_tile_lds(int64_t N, int rs) { return (size_t)N * rs; }
 
+size_t graph_tile_lds(int64_t N, int rs) { return (size_t)N * rs; }
+
 size_t bq_tile_lds(int rs, int na_p, int nb_p, int width, int mode)
 {
     // spin rows, then one 64-bit decision word per field value in [-(width - 1), width - 1]
@@ -686,6 +848,9 @@ hipError_t tiles_set_lds_limit()
     const int max_lds = 160 * 1024 - 4096;  // leave room for the static shared variables
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ea_tiles),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_graph_tiles),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
 
     const void *bq_kernels[] = {reinterpret_cast<const void *>(&k_bq_tiles_bits<1>),
                                 reinterpret_cast<const void *>(&k_bq_tiles_bits<2>),
@@ -702,6 +867,14 @@ hipError_t ea_tiles(const EaJobDev *jobs, const WorkItem *items, const int32_t *
 {
     hipLaunchKernelGGL(k_ea_tiles, dim3((unsigned)grid), dim3(kEaTileThreads), lds_bytes, st, jobs, items, n_items,
                        counter, 1u);
+    return hipGetLastError();
+}
+
+hipError_t graph_tiles(const GraphJobDev *jobs, const WorkItem *items, const int32_t *n_items, int32_t *counter,
+                       int grid, size_t lds_bytes, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_graph_tiles, dim3((unsigned)grid), dim3(kGraphTileThreads), lds_bytes, st, jobs, items,
+                       n_items, counter, 1u);
     return hipGetLastError();
 }
 

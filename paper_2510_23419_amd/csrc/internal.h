@@ -42,6 +42,7 @@ struct GraphView {
     const int32_t *bi, *bj;      // device bond list
     const int8_t *bJ;
     const int8_t *h;             // device [n] or null
+    const int32_t *class_start_dev;  // device copy of class_start (the batched tiles read it)
 };
 
 constexpr int kEaRPad = 16;   // replica padding of the cube spin matrix (one dwordx4 per thread)

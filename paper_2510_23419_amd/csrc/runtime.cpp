@@ -457,12 +457,15 @@ static int load_graph(pbit_ctx *ctx, const pbit_graph_desc *d, Problem &p)
     if (rc == PBIT_OK && nb > 0) rc = upload(ctx, p, d->bond_j, sizeof(int32_t) * (size_t)nb, &dbj);
     if (rc == PBIT_OK && nb > 0) rc = upload(ctx, p, d->bond_J, (size_t)nb, &dbJ);
     if (rc == PBIT_OK && d->h) rc = upload(ctx, p, d->h, (size_t)n, &dh);
+    void *dcs = nullptr;
+    if (rc == PBIT_OK) rc = upload(ctx, p, p.class_start.data(), sizeof(int32_t) * p.class_start.size(), &dcs);
     if (rc != PBIT_OK) return rc;
     p.kind = PBIT_GRAPH;
     p.N = n;
     p.amax = amax;
     p.graph = GraphView{n, nb, ncol, maxdeg, p.class_start.data(), (const int32_t *)dmeta, (const uint32_t *)dadj,
-                        (const int32_t *)dbi, (const int32_t *)dbj, (const int8_t *)dbJ, (const int8_t *)dh};
+                        (const int32_t *)dbi, (const int32_t *)dbj, (const int8_t *)dbJ, (const int8_t *)dh,
+                        (const int32_t *)dcs};
     // the cube's layout kernels (init, transposes) are reused with N = n
     p.ea = EaView{0, 0, 0, (int64_t)n, nullptr, nullptr, nullptr, false, nullptr};
     return PBIT_OK;

@@ -33,8 +33,10 @@ namespace {
 
 constexpr int kMaxLdsTile = 160 * 1024 - 4096;
 // tile kinds, one persistent launch and one stream each: cube tiles (4, 8 or 16
-// replicas, one launch); 128-, 64- and 32-replica biclique tiles
-constexpr int kKinds = 4;
+// replicas, one launch); 128-, 64- and 32-replica biclique tiles; general-graph
+// tiles (4, 8 or 16 replicas, one launch)
+constexpr int kKinds = 5;
+constexpr int kGraphKind = 4;
 inline int kind_of_rs(int rs) { return rs == 128 ? 1 : (rs == 64 ? 2 : 3); }
 constexpr double kItemOps = 1.5e11;  // multiply-adds of one biclique tile over its anneal
 inline int rs_of_kind(int k) { return k == 1 ? 128 : (k == 2 ? 64 : 32); }
@@ -75,9 +77,9 @@ struct ServeState {
     std::vector<BJob *> round_jobs;
     std::vector<int> round_end;
     // device work lists (grown on demand)
-    void *d_ea_jobs = nullptr, *d_bq_jobs[3] = {};  // cube jobs (both cube kinds); biclique jobs per tile kind
+    void *d_ea_jobs = nullptr, *d_bq_jobs[3] = {}, *d_graph_jobs = nullptr;  // per tile kind
     void *d_items[kKinds] = {};
-    size_t cap_ea_jobs = 0, cap_bq_jobs[3] = {}, cap_items[kKinds] = {};
+    size_t cap_ea_jobs = 0, cap_bq_jobs[3] = {}, cap_graph_jobs = 0, cap_items[kKinds] = {};
     int32_t *d_meta = nullptr;  // counters[kKinds], n_items[kKinds]
     bool lds_ready = false;
 };
@@ -130,6 +132,7 @@ void serve_shutdown(pbit_ctx *ctx)
         if (j->P) j->P->jobs--;
     }
     dev_free(ctx, s->d_ea_jobs);
+    dev_free(ctx, s->d_graph_jobs);
     for (int k = 0; k < 3; ++k) dev_free(ctx, s->d_bq_jobs[k]);
     for (int k = 0; k < kKinds; ++k) dev_free(ctx, s->d_items[k]);
     dev_free(ctx, s->d_meta);
@@ -164,7 +167,7 @@ static int tile_mode(const pbit_ctx *ctx)
 
 static size_t tile_bytes(const BJob &j)
 {
-    return j.kind == PBIT_EA3D ? (size_t)j.rs * j.N : (size_t)j.rs * bq_row_bytes(j);
+    return j.kind != PBIT_BICLIQUE ? (size_t)j.rs * j.N : (size_t)j.rs * bq_row_bytes(j);
 }
 
 static int plan_job(pbit_ctx *ctx, BJob &j)
@@ -177,8 +180,19 @@ static int plan_job(pbit_ctx *ctx, BJob &j)
     j.width = j.S > 0 ? table_width(j.beta.data(), j.S, P.amax) : 1;
     j.mode = tile_mode(ctx);
     if (j.width > kMaxTableWidth) return fail(PBIT_E_UNSUPPORTED, "threshold rows of %d entries are too wide", j.width);
-    if (P.kind == PBIT_GRAPH) return fail(PBIT_E_UNSUPPORTED, "general graphs run through pbit_anneal only");
-    if (P.kind == PBIT_EA3D) {
+    if (P.kind == PBIT_GRAPH) {
+        // the widest tile (16, 8 or 4 replicas of every site) that the job fills and the LDS holds
+        if (graph_tile_lds(P.N, 4) > (size_t)kMaxLdsTile)
+            return fail(PBIT_E_UNSUPPORTED, "graph of %lld spins is too large for a batched tile", (long long)P.N);
+        if (j.width > kGraphMaxDegree + 2)
+            return fail(PBIT_E_UNSUPPORTED, "threshold rows of %d entries are too wide", j.width);
+        j.rs = 4;
+        for (int rs : {16, 8})
+            if (j.R >= rs && graph_tile_lds(P.N, rs) <= (size_t)kMaxLdsTile) {
+                j.rs = rs;
+                break;
+            }
+    } else if (P.kind == PBIT_EA3D) {
         if (ea_tile_lds(P.N, 4) > (size_t)kMaxLdsTile || P.ea.Lx > 1024 || P.ea.Ly > 1024)
             return fail(PBIT_E_UNSUPPORTED, "cube of %lld sites is too large for a batched tile", (long long)P.N);
         // the widest tile (16, 8 or 4 replicas: a 16-, 8- or 4-byte row per site) that the
@@ -222,7 +236,7 @@ static int plan_job(pbit_ctx *ctx, BJob &j)
 static void rows_to_tiles(const BJob &j, const int8_t *rows, std::vector<int8_t> &tiles_out)
 {
     const Problem &P = *j.P;
-    if (P.kind == PBIT_EA3D) {
+    if (P.kind != PBIT_BICLIQUE) {  // cubes and graphs: [tile][site][replica in tile]
         tiles_out.assign((size_t)j.tiles * j.rs * j.N, 1);
         for (int r = 0; r < j.R; ++r)
             for (int i = 0; i < j.N; ++i)
@@ -248,7 +262,7 @@ static void rows_to_tiles(const BJob &j, const int8_t *rows, std::vector<int8_t>
 static void tiles_to_rows(const BJob &j, const int8_t *tl, int8_t *rows)
 {
     const Problem &P = *j.P;
-    if (P.kind == PBIT_EA3D) {
+    if (P.kind != PBIT_BICLIQUE) {
         for (int r = 0; r < j.R; ++r)
             for (int i = 0; i < j.N; ++i)
                 rows[(size_t)r * j.N + i] = tl[((size_t)(r / j.rs) * j.N + i) * j.rs + (r % j.rs)];
@@ -358,6 +372,7 @@ static int launch_round(pbit_ctx *ctx, ServeState &s, const std::vector<BJob *> 
     s.round_jobs.clear();
     s.round_end.clear();
     std::vector<EaJobDev> ea;
+    std::vector<GraphJobDev> gr;
     std::vector<BqJobDev> bq[3];
     std::vector<WorkItem> items[kKinds];
     std::vector<double> cost[kKinds];
@@ -386,6 +401,20 @@ static int launch_round(pbit_ctx *ctx, ServeState &s, const std::vector<BJob *> 
                 cost[k].push_back((double)(s1 - s0) * j->N * j->rs);
             }
             lds[k] = std::max(lds[k], ea_tile_lds(j->N, j->rs));
+        } else if (j->kind == PBIT_GRAPH) {
+            const GraphView &v = j->P->graph;
+            GraphJobDev jd{reinterpret_cast<const int4 *>(v.site_meta), v.adj, v.class_start_dev, v.bi, v.bj, v.bJ,
+                           v.h, (const uint32_t *)j->d_table, (int8_t *)j->d_state, (int32_t *)j->d_energy,
+                           v.n, v.n_bonds, v.n_colours, j->width, j->rs,
+                           (uint32_t)j->d.sweep_offset, (uint32_t)j->d.replica_offset >> 2, key.k0, key.k1};
+            const int idx = (int)gr.size();
+            gr.push_back(jd);
+            const int k = kGraphKind;
+            for (int t = 0; t < j->tiles; ++t) {
+                items[k].push_back(WorkItem{idx, t, s0, s1, j->started ? 0 : 1, {0, 0, 0}});
+                cost[k].push_back((double)(s1 - s0) * ((double)j->N + 2.0 * v.n_bonds) * j->rs);
+            }
+            lds[k] = std::max(lds[k], graph_tile_lds(j->N, j->rs));
         } else {
             const BqView &v = j->P->bq;
             const int k = kind_of_rs(j->rs);
@@ -414,6 +443,8 @@ static int launch_round(pbit_ctx *ctx, ServeState &s, const std::vector<BJob *> 
         items[k].swap(sorted);
     }
     int rc = grow(ctx, &s.d_ea_jobs, &s.cap_ea_jobs, sizeof(EaJobDev) * std::max<size_t>(ea.size(), 1));
+    if (rc == PBIT_OK)
+        rc = grow(ctx, &s.d_graph_jobs, &s.cap_graph_jobs, sizeof(GraphJobDev) * std::max<size_t>(gr.size(), 1));
     for (int k = 0; k < 3 && rc == PBIT_OK; ++k)
         rc = grow(ctx, &s.d_bq_jobs[k], &s.cap_bq_jobs[k], sizeof(BqJobDev) * std::max<size_t>(bq[k].size(), 1));
     for (int k = 0; k < kKinds && rc == PBIT_OK; ++k)
@@ -429,6 +460,8 @@ static int launch_round(pbit_ctx *ctx, ServeState &s, const std::vector<BJob *> 
     hipError_t e = hipMemcpy(s.d_meta, meta, sizeof meta, hipMemcpyHostToDevice);
     if (e == hipSuccess && !ea.empty())
         e = hipMemcpy(s.d_ea_jobs, ea.data(), sizeof(EaJobDev) * ea.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !gr.empty())
+        e = hipMemcpy(s.d_graph_jobs, gr.data(), sizeof(GraphJobDev) * gr.size(), hipMemcpyHostToDevice);
     for (int k = 0; k < 3 && e == hipSuccess; ++k)
         if (!bq[k].empty()) e = hipMemcpy(s.d_bq_jobs[k], bq[k].data(), sizeof(BqJobDev) * bq[k].size(), hipMemcpyHostToDevice);
     for (int k = 0; k < kKinds && e == hipSuccess; ++k)
@@ -447,6 +480,9 @@ static int launch_round(pbit_ctx *ctx, ServeState &s, const std::vector<BJob *> 
         if (k == 0)
             e = ea_tiles((const EaJobDev *)s.d_ea_jobs, (const WorkItem *)s.d_items[0], s.d_meta + kKinds,
                          s.d_meta + 0, grid, lds[0], s.st[0]);
+        else if (k == kGraphKind)
+            e = graph_tiles((const GraphJobDev *)s.d_graph_jobs, (const WorkItem *)s.d_items[k], s.d_meta + kKinds + k,
+                            s.d_meta + k, grid, lds[k], s.st[k]);
         else
             e = bq_tiles((const BqJobDev *)s.d_bq_jobs[k - 1], (const WorkItem *)s.d_items[k], s.d_meta + kKinds + k,
                          s.d_meta + k, rs_of_kind(k), tile_mode(ctx), grid, lds[k], s.st[k]);

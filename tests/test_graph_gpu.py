@@ -211,7 +211,105 @@ def test_graph_errors(ctx):
     assert ei.value.code == pbit.PBIT_E_UNSUPPORTED
     prob = pbit.pbit_load_graph(ctx, 3, bi, bj, J)
     assert pbit.pbit_problem_colouring(ctx, prob)[1] == 3
-    with pytest.raises(pbit.PbitError) as ei:  # the batched engine takes cubes and bicliques only
-        pbit.pbit_anneal_batch(ctx, [dict(problem=prob, beta=[1.0], n_replicas=4, seed=1)])
-    assert ei.value.code == pbit.PBIT_E_UNSUPPORTED
     pbit.pbit_unload_problem(ctx, prob)
+    # a graph whose 4-replica tile does not fit the LDS is refused by the batched engine
+    n = 41000
+    ring_i = np.arange(n, dtype=np.int32)
+    big = pbit.pbit_load_graph(ctx, n, ring_i, (ring_i + 1) % n, np.ones(n, np.int8))
+    with pytest.raises(pbit.PbitError) as ei:
+        pbit.pbit_anneal_batch(ctx, [dict(problem=big, beta=[1.0], n_replicas=4, seed=1)])
+    assert ei.value.code == pbit.PBIT_E_UNSUPPORTED
+    pbit.pbit_unload_problem(ctx, big)
+
+
+def _batched_graphs():
+    """Odd cubes (three or four groups), a dimerized cube (five groups), random
+    graphs with zero couplings and fields, and a caller colouring."""
+    rng = np.random.default_rng(12)
+    jobs = []
+    for k, (dims, R) in enumerate([((3, 3, 3), 5), ((5, 5, 5), 17), ((7, 5, 3), 40), ((3, 4, 6), 16)]):
+        inst = synth.ea_instance(dims, seed=30 + k, field="uniform3")
+        jobs.append(dict(g=_with_zeros(synth.ea_bond_list(inst), 0.15, seed=k), R=R, seed=70 + k,
+                         beta=synth.beta_geometric(0.1, 5.0, int(rng.integers(8, 30)))))
+    jobs.append(dict(g=synth.dimerized_cube(5, seed=5), R=33, seed=80, beta=synth.beta_geometric(0.1, 5.0, 25)))
+    g = synth.random_sparse_graph(300, degree=7, seed=3)
+    jobs.append(dict(g=_with_zeros(g, 0.2, seed=9), R=9, seed=81, beta=synth.beta_linear(0.1, 3.0, 20)))
+    # a caller colouring: the greedy one with the colour ids reversed (groups swept in another order)
+    g = synth.random_sparse_graph(120, degree=5, seed=4, field="zero")
+    colour, nc = pbit.pbit_greedy_colouring(120, g["bond_i"], g["bond_j"])
+    jobs.append(dict(g=g, R=64, seed=82, beta=synth.beta_linear(0.1, 3.0, 12),
+                     colour=(nc - 1 - colour).astype(np.uint8), n_colours=nc))
+    return jobs
+
+
+def test_graphs_in_the_batched_tiles_match_the_oracle(ctx):
+    jobs = _batched_graphs()
+    probs = [pbit.pbit_load_graph(ctx, j["g"]["n"], j["g"]["bond_i"], j["g"]["bond_j"], j["g"]["bond_J"],
+                                  j["g"].get("h"), j.get("colour"), j.get("n_colours", 0)) for j in jobs]
+    # mixed with a cube and a biclique in the same call
+    cube, bq = synth.ea_instance(6, seed=2), synth.biclique_instance(50, seed=2)
+    pc, pq = pbit.load_instance(ctx, cube), pbit.load_instance(ctx, bq)
+    beta = synth.beta_linear(0.1, 3.0, 15)
+    _say("batched graphs: %d jobs with a cube and a biclique" % len(jobs))
+    outs = pbit.pbit_anneal_batch(ctx, [dict(problem=p, beta=j["beta"], n_replicas=j["R"], seed=j["seed"])
+                                        for p, j in zip(probs, jobs)] +
+                                  [dict(problem=pc, beta=beta, n_replicas=20, seed=3),
+                                   dict(problem=pq, beta=beta, n_replicas=40, seed=4)])
+    for p, j, o in zip(probs, jobs, outs):
+        ref = oracle.anneal(_oracle_graph(j["g"], j.get("colour"), j.get("n_colours")), j["beta"], j["R"], j["seed"])
+        assert np.array_equal(o.spins, ref.spins), j["g"]["n"]
+        assert np.array_equal(o.energies, ref.energies), j["g"]["n"]
+        assert o.sweeps_done == len(j["beta"])
+        pbit.pbit_unload_problem(ctx, p)
+    refc = oracle.anneal(oracle.ea_graph(cube["dims"], cube["J"], cube["h"]), beta, 20, 3)
+    refq = oracle.anneal(oracle.biclique_graph(*bq["dims"], bq["J"], bq["h"]), beta, 40, 4)
+    assert np.array_equal(outs[-2].spins, refc.spins) and np.array_equal(outs[-1].spins, refq.spins)
+    pbit.pbit_unload_problem(ctx, pc)
+    pbit.pbit_unload_problem(ctx, pq)
+
+
+def test_graph_tiles_offsets_given_spins_traces_and_target(ctx):
+    g = synth.dimerized_cube(4, seed=7)
+    prob = pbit.load_instance(ctx, g)
+    og = _oracle_graph(g)
+    beta = synth.beta_linear(0.2, 3.0, 300)
+    init = synth.random_spins(11, g["n"], seed=5)
+    ref = oracle.anneal(og, beta, 11, 9, sweep_offset=7, replica_offset=12, init_spins=init, trace_every=50)
+    out = pbit.pbit_anneal_batch(ctx, [dict(problem=prob, beta=beta, n_replicas=11, seed=9, sweep_offset=7,
+                                             replica_offset=12, init_spins=init, trace_every=50)])[0]
+    assert np.array_equal(out.spins, ref.spins) and np.array_equal(out.energy_trace, ref.energy_trace)
+    # a target stops the job after the first checked sweep (every PBIT_CHECK_SWEEPS) that meets it
+    full = oracle.anneal(og, beta, 16, 4, trace_every=pbit.PBIT_CHECK_SWEEPS)
+    mins = full.energy_trace.min(axis=1)
+    target = int(mins[1])
+    first = (int(np.argmax(mins <= target)) + 1) * pbit.PBIT_CHECK_SWEEPS
+    out = pbit.pbit_anneal_batch(ctx, [dict(problem=prob, beta=beta, n_replicas=16, seed=4, target=target)])[0]
+    assert out.sweeps_done == first
+    pre = oracle.anneal(og, beta[:first], 16, 4)
+    assert np.array_equal(out.spins, pre.spins)
+    pbit.pbit_unload_problem(ctx, prob)
+
+
+def test_graph_job_served_alone_and_in_a_mix_is_the_same():
+    jobs = _batched_graphs()[:5]
+    with pbit.Context(0) as c:
+        probs = [pbit.load_instance(c.ctx, dict(j["g"], kind="graph")) for j in jobs]
+        pbit.pbit_serve_config(c.ctx, round_sweeps=5)
+        res_alone, res_mix = {}, {}
+        for k, (p, j) in enumerate(zip(probs, jobs)):
+            jid = pbit.pbit_submit(c.ctx, p, j["beta"], j["R"], j["seed"])
+            while (o := pbit.pbit_poll(c.ctx, jid, j["R"], j["g"]["n"], len(j["beta"]))) is None:
+                pass
+            res_alone[k] = o
+        ids = {k: pbit.pbit_submit(c.ctx, p, j["beta"], j["R"], j["seed"]) for k, (p, j) in enumerate(zip(probs, jobs))}
+        while ids:
+            for k in list(ids):
+                o = pbit.pbit_poll(c.ctx, ids[k], jobs[k]["R"], jobs[k]["g"]["n"], len(jobs[k]["beta"]))
+                if o is not None:
+                    res_mix[k] = o
+                    del ids[k]
+        for k, j in enumerate(jobs):
+            ref = oracle.anneal(_oracle_graph(j["g"]), j["beta"], j["R"], j["seed"])
+            assert np.array_equal(res_alone[k].spins, ref.spins)
+            assert np.array_equal(res_mix[k].spins, ref.spins) and np.array_equal(res_mix[k].energies,
+                                                                                   ref.energies)
