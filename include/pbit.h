@@ -232,6 +232,16 @@ typedef struct {
     pbit_result *result;      /* filled as by pbit_anneal (spin_trace is not supported) */
 } pbit_batch_job;
 
+/* Tile sizes of batched jobs.  Where a job's shape can take more than one tile
+ * size, the library times one tile of each (a couple of the job's sweeps on
+ * scratch memory) when the shape is first seen and no round is in flight, and
+ * keeps the size whose tiles cost the least device time per job; the choice is
+ * cached per (problem kind, sides or spins, threshold width, replicas rounded up
+ * to a power of two, operand mode).  PBIT_TILE_TUNE=0 at context creation keeps
+ * the fixed rule (the widest tile the replicas fill).  Results do not depend on
+ * the tile size.  Writes the number of timings run and of cached shapes. */
+int pbit_profile_tiles(pbit_ctx *ctx, int64_t *tunings, int32_t *shapes);
+
 /* Run all jobs and wait for them.  A job whose device memory does not fit the
  * budget while no other job runs fails the call with E_NOMEM; the call's other
  * jobs are then withdrawn (their results may be partly written). */

@@ -132,6 +132,7 @@ extern "C" int pbit_create(pbit_ctx **out, int device, uint64_t hbm_budget_bytes
     if (const char *v = std::getenv("PBIT_EA_STREAM")) ctx->ea_stream_forced = std::atoi(v) != 0;
     if (const char *v = std::getenv("PBIT_EA_ROWS")) ctx->ea_rows = std::max(0, std::atoi(v));  // tuning override
     if (const char *v = std::getenv("PBIT_GRAPH")) ctx->use_graph = std::atoi(v) != 0;
+    if (const char *v = std::getenv("PBIT_TILE_TUNE")) ctx->tile_tune = std::atoi(v) != 0;
     ctx->serial = g_ctx_serial.fetch_add(1);
     int rc = noalloc_setup(device);  // device address of the static scratch of pbit_anneal_dev_noalloc
     if (rc) {

@@ -77,6 +77,7 @@ struct pbit_ctx {
     int ea_rows = 0;                // lattice rows per workgroup of the streaming stencil (PBIT_EA_ROWS; 0 = default)
     // pbit_anneal_dev's sweep launches as one HIP graph (PBIT_GRAPH=1), kept for replay
     bool use_graph = false;
+    bool tile_tune = true;  // batched tile sizes timed per shape (PBIT_TILE_TUNE=0: the fixed rule)
     void *graph_exec = nullptr;  // hipGraphExec_t
     uint64_t graph_key = 0;
     int64_t graph_captures = 0, graph_launches = 0;

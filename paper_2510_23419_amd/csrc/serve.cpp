@@ -11,9 +11,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <memory>
 #include <new>
 #include <thread>
@@ -82,6 +85,12 @@ struct ServeState {
     size_t cap_ea_jobs = 0, cap_bq_jobs[3] = {}, cap_graph_jobs = 0, cap_items[kKinds] = {};
     int32_t *d_meta = nullptr;  // counters[kKinds], n_items[kKinds]
     bool lds_ready = false;
+    // tile autotuner: (kind, shape, threshold width, replicas rounded to a power of two,
+    // operand mode) -> replicas per tile; the rule picks when PBIT_TILE_TUNE=0 or a round
+    // is in flight (the timing would share the device)
+    std::map<std::array<int, 6>, int> tile_tuned;
+    bool tune = true;
+    int64_t tunings = 0;
 };
 
 static int grow(pbit_ctx *ctx, void **p, size_t *cap, size_t need)
@@ -111,6 +120,7 @@ static int serve_init(pbit_ctx *ctx)
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->fork, hipEventDisableTiming);
     for (int k = 0; k < kKinds && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&s->join[k], hipEventDisableTiming);
     if (e != hipSuccess) return device_fail(ctx, e, "serving streams");
+    s->tune = ctx->tile_tune;
     void *meta = nullptr;
     int rc = dev_alloc(ctx, 64, &meta);
     if (rc) return rc;
@@ -170,7 +180,9 @@ static size_t tile_bytes(const BJob &j)
     return j.kind != PBIT_BICLIQUE ? (size_t)j.rs * j.N : (size_t)j.rs * bq_row_bytes(j);
 }
 
-static int plan_job(pbit_ctx *ctx, BJob &j)
+static int tune_tile(pbit_ctx *ctx, ServeState &s, BJob &j, const std::vector<int> &cands, int *pick);
+
+static int plan_job(pbit_ctx *ctx, ServeState &s, BJob &j)
 {
     const Problem &P = *j.P;
     j.kind = P.kind;
@@ -179,6 +191,7 @@ static int plan_job(pbit_ctx *ctx, BJob &j)
     j.S = j.d.n_sweeps;
     j.width = j.S > 0 ? table_width(j.beta.data(), j.S, P.amax) : 1;
     j.mode = tile_mode(ctx);
+    std::vector<int> cands;  // tile sizes the job can take (the autotuner times them)
     if (j.width > kMaxTableWidth) return fail(PBIT_E_UNSUPPORTED, "threshold rows of %d entries are too wide", j.width);
     if (P.kind == PBIT_GRAPH) {
         // the widest tile (16, 8 or 4 replicas of every site) that the job fills and the LDS holds
@@ -192,6 +205,8 @@ static int plan_job(pbit_ctx *ctx, BJob &j)
                 j.rs = rs;
                 break;
             }
+        for (int rs : {16, 8, 4})
+            if (rs <= std::max(j.R, 4) && graph_tile_lds(P.N, rs) <= (size_t)kMaxLdsTile) cands.push_back(rs);
     } else if (P.kind == PBIT_EA3D) {
         if (ea_tile_lds(P.N, 4) > (size_t)kMaxLdsTile || P.ea.Lx > 1024 || P.ea.Ly > 1024)
             return fail(PBIT_E_UNSUPPORTED, "cube of %lld sites is too large for a batched tile", (long long)P.N);
@@ -205,6 +220,8 @@ static int plan_job(pbit_ctx *ctx, BJob &j)
                 j.rs = rs;
                 break;
             }
+        for (int rs : {16, 8, 4})
+            if (rs <= std::max(j.R, 4) && ea_tile_lds(P.N, rs) <= (size_t)kMaxLdsTile) cands.push_back(rs);
     } else {
         // the largest tile that the replicas fill, the LDS holds and whose whole anneal
         // stays below kItemOps multiply-adds: larger tiles stream fewer coupling bytes
@@ -221,6 +238,26 @@ static int plan_job(pbit_ctx *ctx, BJob &j)
         }
         if (j.rs == 0)
             return fail(PBIT_E_UNSUPPORTED, "biclique %d x %d is too large for a batched tile", P.bq.na, P.bq.nb);
+        for (int rs : {128, 64, 32})
+            if ((rs != 128 || j.mode == kTileBits) && (rs == 32 || rs <= j.R) &&
+                bq_tile_lds(rs, na_p, nb_p, j.width, j.mode) <= (size_t)kMaxLdsTile)
+                cands.push_back(rs);
+    }
+    if (cands.size() > 1 && s.tune && j.S > 0) {
+        int R2 = 1;
+        while (R2 < j.R) R2 *= 2;
+        const std::array<int, 6> key{P.kind, P.kind == PBIT_BICLIQUE ? P.bq.na_p : (int)P.N,
+                                     P.kind == PBIT_BICLIQUE ? P.bq.nb_p : 0, j.width, R2, j.mode};
+        auto it = s.tile_tuned.find(key);
+        if (it != s.tile_tuned.end()) {
+            j.rs = it->second;
+        } else if (!s.q.in_flight) {
+            int pick = j.rs;
+            int rc = tune_tile(ctx, s, j, cands, &pick);
+            if (rc) return rc;
+            j.rs = pick;
+            s.tile_tuned[key] = pick;
+        }
     }
     j.tiles = (j.R + j.rs - 1) / j.rs;
     j.bytes = sizeof(uint32_t) * (size_t)std::max(j.S, 1) * j.width + (size_t)j.tiles * tile_bytes(j) +
@@ -493,6 +530,114 @@ static int launch_round(pbit_ctx *ctx, ServeState &s, const std::vector<BJob *> 
     return PBIT_OK;
 }
 
+// The tile autotuner: one tile of each candidate size runs a couple of the job's
+// sweeps alone on the device (from a random start, on scratch memory), timed with
+// HIP events.  The job's cost with that size is its number of tiles times the tile
+// time over the number of tiles the device holds at once (the device time the job
+// takes from a full batch), and the cheapest size is kept; a smaller size must be
+// at least 2 % cheaper, as larger tiles stream fewer bytes per replica.
+static int tune_tile(pbit_ctx *ctx, ServeState &s, BJob &j, const std::vector<int> &cands, int *pick)
+{
+    const Problem &P = *j.P;
+    constexpr int kSweeps = 2;
+    if (!s.lds_ready) {
+        hipError_t e = tiles_set_lds_limit();
+        if (e != hipSuccess) return device_fail(ctx, e, "tile LDS limit");
+        s.lds_ready = true;
+    }
+    std::vector<uint32_t> tab((size_t)kSweeps * j.width);
+    std::vector<double> beta(kSweeps, j.beta[0]);
+    for (int k = 1; k < kSweeps && k < j.S; ++k) beta[k] = j.beta[k];
+    build_table(beta.data(), kSweeps, j.width, tab.data(), 1);
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDeviceProperties(&prop, ctx->device);
+    if (e != hipSuccess) return device_fail(ctx, e, "hipGetDeviceProperties");
+    const int cus = prop.multiProcessorCount;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) return device_fail(ctx, e, "hipEventCreate (tile tuning)");
+    const hipStream_t st = ctx->stream;
+    double best_t = 0.0;
+    int rc = PBIT_OK;
+    for (int rs : cands) {
+        BJob t = j;  // the job's shape with this tile size
+        t.rs = rs;
+        const size_t state = tile_bytes(t);
+        const size_t lds = P.kind == PBIT_EA3D ? ea_tile_lds(P.N, rs)
+                           : P.kind == PBIT_GRAPH ? graph_tile_lds(P.N, rs)
+                                                  : bq_tile_lds(rs, P.bq.na_p, P.bq.nb_p, j.width, j.mode);
+        // scratch: job descriptor, item, counter and item count, energies, table, state
+        const size_t off_item = 512, off_meta = off_item + 64, off_en = off_meta + 64,
+                     off_tab = off_en + ((sizeof(int32_t) * rs + 255) & ~(size_t)255),
+                     off_state = off_tab + ((sizeof(uint32_t) * tab.size() + 255) & ~(size_t)255);
+        void *buf = nullptr;
+        rc = scratch(ctx, Slot::Stage, off_state + state, &buf);
+        if (rc) break;
+        uint8_t *b = (uint8_t *)buf;
+        const WorkItem item{0, 0, 0, kSweeps, 1, {0, 0, 0}};
+        const int32_t meta[2] = {0, 1};
+        e = hipMemcpy(b + off_tab, tab.data(), sizeof(uint32_t) * tab.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(b + off_item, &item, sizeof item, hipMemcpyHostToDevice);
+        if (e == hipSuccess) {
+            if (P.kind == PBIT_EA3D) {
+                const EaView &v = P.ea;
+                const EaJobDev jd{reinterpret_cast<const uint2 *>(P.tile_sites), (const uint32_t *)(b + off_tab),
+                                  (int8_t *)(b + off_state), (int32_t *)(b + off_en), v.Lx, v.Ly, v.Lz, j.width, rs,
+                                  v.dense ? 1 : 0, 0u, 0u, 0u, 0u};
+                e = hipMemcpy(b, &jd, sizeof jd, hipMemcpyHostToDevice);
+            } else if (P.kind == PBIT_GRAPH) {
+                const GraphView &v = P.graph;
+                const GraphJobDev jd{reinterpret_cast<const int4 *>(v.site_meta), v.adj, v.class_start_dev, v.bi,
+                                     v.bj, v.bJ, v.h, (const uint32_t *)(b + off_tab), (int8_t *)(b + off_state),
+                                     (int32_t *)(b + off_en), v.n, v.n_bonds, v.n_colours, j.width, rs,
+                                     0u, 0u, 0u, 0u};
+                e = hipMemcpy(b, &jd, sizeof jd, hipMemcpyHostToDevice);
+            } else {
+                const BqView &v = P.bq;
+                const BqJobDev jd{v.J, v.JT, v.Jb, v.JTb, v.hA2, v.hB2, v.J2, v.JT2, v.hA, v.hB,
+                                  (const uint32_t *)(b + off_tab), (uint8_t *)(b + off_state),
+                                  (int32_t *)(b + off_en), v.na, v.nb, v.na_p, v.nb_p, j.width, 0u, 0u, 0u, 0u};
+                e = hipMemcpy(b, &jd, sizeof jd, hipMemcpyHostToDevice);
+            }
+        }
+        float ms = 0.f;
+        for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // the first run warms up
+            e = hipMemcpyAsync(b + off_meta, meta, sizeof meta, hipMemcpyHostToDevice, st);
+            if (e == hipSuccess) e = hipEventRecord(e0, st);
+            if (e == hipSuccess) {
+                const WorkItem *it = (const WorkItem *)(b + off_item);
+                int32_t *ctr = (int32_t *)(b + off_meta);
+                if (P.kind == PBIT_EA3D)
+                    e = ea_tiles((const EaJobDev *)b, it, ctr + 1, ctr, 1, lds, st);
+                else if (P.kind == PBIT_GRAPH)
+                    e = graph_tiles((const GraphJobDev *)b, it, ctr + 1, ctr, 1, lds, st);
+                else
+                    e = bq_tiles((const BqJobDev *)b, it, ctr + 1, ctr, rs, j.mode, 1, lds, st);
+            }
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        }
+        if (e != hipSuccess) {
+            rc = device_fail(ctx, e, "tile tuning");
+            break;
+        }
+        // device time the job's tiles take: tiles x tile time over the tiles the device holds at once
+        const int per_cu = std::max(1, std::min(4, (int)((160 * 1024) / (lds + 2048))));
+        const int slots = cus * per_cu, tiles = (j.R + rs - 1) / rs;
+        const double est = (double)tiles * ms / slots;
+        if (rs == cands[0] || est < best_t * 0.98) {
+            best_t = est;
+            *pick = rs;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == PBIT_OK) ++s.tunings;
+    return rc;
+}
+
 static bool round_done(ServeState &s)
 {
     for (int k = 0; k < kKinds; ++k)
@@ -575,7 +720,7 @@ static int new_job(pbit_ctx *ctx, ServeState &s, uint64_t problem, const pbit_an
     j->d.init_spins = nullptr;
     j->P = P;
     j->problem = problem;
-    rc = plan_job(ctx, *j);
+    rc = plan_job(ctx, s, *j);
     if (rc) return rc;
     if (ctx->budget && j->bytes + 65536 > ctx->budget)
         return fail(PBIT_E_NOMEM, "job needs %llu bytes of device memory, more than the budget",
@@ -717,6 +862,14 @@ extern "C" int pbit_serve_config(pbit_ctx *ctx, int32_t max_queue, int32_t max_r
     if (max_queue) s.max_queue = max_queue;
     if (max_running) s.q.max_running = max_running;
     if (round_sweeps) s.round_sweeps = round_sweeps;
+    return PBIT_OK;
+}
+
+extern "C" int pbit_profile_tiles(pbit_ctx *ctx, int64_t *tunings, int32_t *shapes)
+{
+    PBIT_SERVE_ENTER(ctx);
+    if (tunings) *tunings = ctx->serve->tunings;
+    if (shapes) *shapes = (int32_t)ctx->serve->tile_tuned.size();
     return PBIT_OK;
 }
 

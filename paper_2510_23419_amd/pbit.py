@@ -40,7 +40,7 @@ EXPORTS = ("pbit_create", "pbit_destroy", "pbit_last_error", "pbit_bytes_in_use"
            "pbit_submit", "pbit_poll", "pbit_progress", "pbit_threshold_table", "pbit_version",
            "pbit_profile_enable", "pbit_profile_read", "pbit_anneal_batch", "pbit_serve_config",
            "pbit_load_graph", "pbit_problem_colouring", "pbit_greedy_colouring", "pbit_profile_variant",
-           "pbit_profile_ea_path", "pbit_anneal_dev_noalloc", "pbit_probe", "pbit_profile_graph")
+           "pbit_profile_ea_path", "pbit_anneal_dev_noalloc", "pbit_probe", "pbit_profile_graph", "pbit_profile_tiles")
 
 
 class PbitError(RuntimeError):
@@ -118,6 +118,7 @@ def lib() -> ctypes.CDLL:
             "pbit_profile_variant": ([P, ctypes.POINTER(i32)], ctypes.c_int),
             "pbit_profile_ea_path": ([P, ctypes.POINTER(i32)], ctypes.c_int),
             "pbit_profile_graph": ([P, ctypes.POINTER(i64), ctypes.POINTER(i64)], ctypes.c_int),
+            "pbit_profile_tiles": ([P, ctypes.POINTER(i64), ctypes.POINTER(i32)], ctypes.c_int),
             "pbit_anneal_batch": ([P, ctypes.POINTER(BatchJob), i32], ctypes.c_int),
             "pbit_serve_config": ([P, i32, i32, i32], ctypes.c_int),
             "pbit_load_graph": ([P, ctypes.POINTER(GraphDesc), ctypes.POINTER(u64)], ctypes.c_int),
@@ -367,6 +368,13 @@ def pbit_profile_graph(ctx):
     c, n = ctypes.c_int64(), ctypes.c_int64()
     _check(lib().pbit_profile_graph(ctx, ctypes.byref(c), ctypes.byref(n)))
     return c.value, n.value
+
+
+def pbit_profile_tiles(ctx):
+    """(tile timings run, cached tile shapes) of the batched engine on this context."""
+    t, n = ctypes.c_int64(), ctypes.c_int32()
+    _check(lib().pbit_profile_tiles(ctx, ctypes.byref(t), ctypes.byref(n)))
+    return t.value, n.value
 
 
 def pbit_profile_ea_path(ctx) -> int:

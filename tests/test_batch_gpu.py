@@ -285,3 +285,50 @@ def test_job_that_cannot_fit_fails_instead_of_waiting():
         ref = oracle.anneal(graph_of(inst), beta, 4, 2)
         assert np.array_equal(out.spins[:4], ref.spins)
         pbit.pbit_unload_problem(c.ctx, p)
+
+
+def test_tuned_and_fixed_tile_sizes_give_the_same_results():
+    """The tile autotuner times the tile sizes a job's shape can take and caches
+    the choice; whatever it picks, every job equals the fixed rule's result (and
+    the oracle on sampled replicas), and a second batch of the same shapes
+    reuses the cache."""
+    import os
+
+    bag = synth.mixed_bag(seed=8, n_instances=10, replica_range=(20, 300), sweep_range=(20, 60))
+    old = os.environ.get("PBIT_TILE_TUNE")
+    os.environ["PBIT_TILE_TUNE"] = "0"
+    try:
+        fixed = pbit.Context(0)
+    finally:
+        if old is None:
+            del os.environ["PBIT_TILE_TUNE"]
+        else:
+            os.environ["PBIT_TILE_TUNE"] = old
+    tuned = pbit.Context(0)
+    try:
+        outs = {}
+        for name, c in (("fixed", fixed), ("tuned", tuned)):
+            probs = [pbit.load_instance(c.ctx, j["instance"]) for j in bag]
+            _say("tile sizes: %s" % name)
+            outs[name] = pbit.pbit_anneal_batch(c.ctx, [dict(problem=p, beta=j["beta"], n_replicas=j["replicas"],
+                                                             seed=j["seed"]) for p, j in zip(probs, bag)])
+            if name == "tuned":
+                tunings, shapes = pbit.pbit_profile_tiles(c.ctx)
+                assert tunings >= 1 and shapes == tunings
+                again = pbit.pbit_anneal_batch(c.ctx, [dict(problem=p, beta=j["beta"], n_replicas=j["replicas"],
+                                                            seed=j["seed"]) for p, j in zip(probs, bag)])
+                assert pbit.pbit_profile_tiles(c.ctx) == (tunings, shapes)
+                for a, b in zip(again, outs[name]):
+                    assert np.array_equal(a.spins, b.spins)
+            else:
+                assert pbit.pbit_profile_tiles(c.ctx) == (0, 0)
+            for p in probs:
+                pbit.pbit_unload_problem(c.ctx, p)
+        for j, a, b in zip(bag, outs["fixed"], outs["tuned"]):
+            assert np.array_equal(a.spins, b.spins), j["instance"]["dims"]
+            assert np.array_equal(a.energies, b.energies)
+        j = bag[0]
+        _oracle_groups(j["instance"], j["beta"], j["replicas"], j["seed"], outs["tuned"][0], [0])
+    finally:
+        fixed.close()
+        tuned.close()
