@@ -161,16 +161,17 @@ def graph_launch_bytes(ctx, prob, inst, R):
     return total / k, k
 
 
-def profile_record(workload):
+def profile_record(workload, kernel=None):
     """The committed rocprofv3 counter summary of the dominant kernel for this
     workload (profiles/traffic.json), or None if the kernel sources changed
-    since the counters were taken."""
+    since the counters were taken or the record is of another kernel than
+    `kernel`."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path)).get(workload)
-    if not rec:
+    if not rec or (kernel and kernel not in rec["kernel"]):
         return None
     h = hashlib.sha256()
     for src in rec["sources"]:
@@ -181,10 +182,10 @@ def profile_record(workload):
     return rec
 
 
-def measured_traffic(workload):
+def measured_traffic(workload, kernel=None):
     """HBM bytes per launch (FETCH_SIZE and WRITE_SIZE, each scaled by what the
     counter reads for a plain copy), or None."""
-    rec = profile_record(workload)
+    rec = profile_record(workload, kernel)
     return None if rec is None else float(rec["traffic_bytes_per_launch"])
 
 
@@ -522,7 +523,7 @@ def main():
     if ea_path == 2:
         # the cube held in LDS for runs of sweeps: no HBM traffic per half-sweep, so the
         # vector ALU is the roof; lane-ops per update from the committed counter run
-        rec = profile_record(args.workload)
+        rec = profile_record(args.workload, "k_ea_slab")
         lops = None
         if rec and rec.get("valu_insts_per_dispatch"):
             lops = float(rec["valu_insts_per_dispatch"]) * 64 / (N * R * rec["sweeps_per_dispatch"])
@@ -533,10 +534,13 @@ def main():
                 "avg_halfsweep_us": avg_ms * 1e3, "halfsweeps_timed": launches}
     elif w["kind"] == "ea3d":
         # per launch: N/2 x R updates, each reads its share of the other colour's
-        # spins once (1 B) and writes its own spin (1 B); couplings ~0 B at R=4096
+        # spins once (1 B) and writes its own spin (1 B); couplings ~0 B at R=4096.
+        # The same algorithmic bytes for both one-launch-per-half-sweep paths: the
+        # streaming stencil (path 1) and the fields on the matrix cores (path 3)
         alg_bytes = N * R + 4 * (N // 2)
         roof = {"bound": "hbm", "achieved": alg_bytes / (avg_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "traffic": None, "kernel": "k_ea_halfsweep",
+                "unit": "GB/s", "traffic": None, "kernel": "k_eam_halfsweep" if ea_path == 3 else "k_ea_halfsweep",
+                "ea_path": ea_path,
                 "alg_bytes_per_launch": alg_bytes, "avg_launch_us": avg_ms * 1e3, "launches_timed": launches}
     elif w["kind"] == "graph":
         alg_bytes, groups = graph_launch_bytes(ctx.ctx, prob, inst, R)
@@ -556,8 +560,8 @@ def main():
         roof["achieved"] = None
     roof["frac"] = None if roof["achieved"] is None else roof["achieved"] / roof["peak"]
     if ea_path != 2:
-        roof["traffic"] = measured_traffic(args.workload)
-    rec = profile_record(args.workload)
+        roof["traffic"] = measured_traffic(args.workload, roof["kernel"])
+    rec = profile_record(args.workload, roof["kernel"])
     if ea_path != 2 and rec and rec.get("valu_insts_per_dispatch") and launches:
         # vector ALU issue: wave instructions x 64 lanes per launch over the measured
         # launch time, against 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz

@@ -312,8 +312,19 @@ int pbit_profile_graph(pbit_ctx *ctx, int64_t *captures, int64_t *launches);
 /* The cube path of the latest cube anneal on this context (0 before any): 1 = the
  * streaming stencil, one launch per half-sweep; 2 = the LDS-resident form, the
  * whole lattice of 16 replicas per workgroup for runs of sweeps, taken for
- * cubes of at most 8192 sites unless PBIT_EA_STREAM=1 was set when the context
- * was created.  Both give the same spins.  *path is written on success only. */
+ * cubes of at most 8192 sites; 3 = the fields of 32 sites x 32 replicas as int8
+ * MFMAs over blocks of neighbour sites, one launch per half-sweep, possible for
+ * cubes whose colour classes split into tiles of 32 sites with at most 8
+ * neighbour blocks each (every cube with Lx = 32, for one).  By default a cube of
+ * more than 8192 and at most 2^21 sites that allows path 3 takes whichever of
+ * paths 1 and 3 ran faster when the first anneal of that shape and replica count
+ * (rounded up to 128) on this context timed four half-sweeps of each; without
+ * allocation (pbit_anneal_dev_noalloc) there is no timing and path 3 is taken
+ * for at most 1024 replicas.  When the context is created, PBIT_EA_STREAM=1
+ * selects path 1 for every cube, PBIT_EA_MFMA=1 path 3 wherever it can run,
+ * PBIT_EA_MFMA=0 never path 3 and a negative value keeps the default.  All give
+ * the same spins.
+ * *path is written on success only. */
 int pbit_profile_ea_path(pbit_ctx *ctx, int32_t *path);
 
 /* The ceilings the sweep kernels are measured against, each timed as a kernel of

@@ -19,7 +19,7 @@ ROOT = PKG.parent
 BUILD = ROOT / "_build" / "pbit"
 LIB = PKG / "libpbit.so"
 
-SOURCES = ["host.cpp", "runtime.cpp", "serve.cpp", "ea_kernels.hip", "bq_kernels.hip", "batch_kernels.hip", "graph_kernels.hip", "misc_kernels.hip", "noalloc.cpp", "probe_kernels.hip"]
+SOURCES = ["host.cpp", "runtime.cpp", "serve.cpp", "ea_kernels.hip", "ea_mfma.hip", "bq_kernels.hip", "batch_kernels.hip", "graph_kernels.hip", "misc_kernels.hip", "noalloc.cpp", "probe_kernels.hip"]
 
 ARCH = "gfx950"
 FLAGS = [
@@ -37,9 +37,14 @@ def hipcc() -> str:
     return exe
 
 
+# Per-source flags: the matrix-core cube kernel keeps its MFMA accumulators in
+# ordinary VGPRs (no copies out of the accumulation registers before the decisions).
+EXTRA = {"ea_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def _compile(src: str) -> Path:
     obj = BUILD / (src + ".o")
-    cmd = [hipcc(), "-x", "hip", "-c", str(CSRC / src), "-o", str(obj)] + FLAGS
+    cmd = [hipcc(), "-x", "hip", "-c", str(CSRC / src), "-o", str(obj)] + FLAGS + EXTRA.get(src, [])
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed on %s:\n%s\n%s" % (src, r.stdout, r.stderr))

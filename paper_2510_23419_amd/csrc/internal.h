@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace pbit {
 
 // Per-site coupling code of a periodic cube.  Directions d = 0..5 are
@@ -27,7 +29,27 @@ struct EaView {
     // (x = 2 (j mod Lx/2) + parity, row j / (Lx/2)), the pair {site | wrap flags of
     // the +x, -x, +y, -y, +z, -z neighbours << 16, site code}, [2][N / 2]; else null
     const uint32_t *slab_sites;
+    // the matrix-core half-sweep (ea_mfma.hip), where the cube's shape allows it: per
+    // colour and tile of 32 class positions a 16-word record (first coupling fragment,
+    // then the K block starts), per colour and position {site, 8 (h + sum J + 7)}, and
+    // the B fragments (64 lanes x 16 bytes each); null where not built
+    const int32_t *mfma_tiles;
+    const int2 *mfma_pos;
+    const void *mfma_frags;
+    int mfma_nb;       // K blocks per tile
+    int mfma_n_tiles;  // tiles per colour
 };
+
+constexpr int kEaMfmaMaxBlocks = 8;
+struct EaMfmaHost {
+    int nb = 0, n_tiles = 0;
+    std::vector<int32_t> tiles;  // [2][n_tiles][16]
+    std::vector<int32_t> pos;    // [2][N / 2][2]
+    std::vector<int8_t> frags;   // [2][n_tiles][nb][64][16]
+};
+// Builds the tiles of the matrix-core half-sweep; false where the shape does not allow it
+// (N / 2 not a multiple of 32, or a tile whose neighbours span more than kEaMfmaMaxBlocks blocks).
+bool ea_mfma_build(int Lx, int Ly, int Lz, const int8_t *J, const int8_t *h, EaMfmaHost &out);
 
 // General sparse graph with k colour classes (greedy colouring by default).
 constexpr int kGraphMaxDegree = 127;  // bytewise counts of negative products stay below 256
@@ -71,6 +93,16 @@ hipError_t ea_slab(const EaView &p, int8_t *spins, int Rp, const uint32_t *table
 hipError_t ea_halfsweep(const EaView &p, int8_t *spins, int Rp, int colour, const EaRow &row, uint32_t sweep,
                         uint32_t rq0, Key key, hipStream_t st, int ny = 0, bool early_rng = true);
 hipError_t ea_energy(const EaView &p, const int8_t *spins, int Rp, int R, int32_t *E, hipStream_t st);
+
+// ---- the matrix-core cube path: spins as bytes b (1 = -1), tile-major [2][Rp / 32][N / 64][32][32]
+// (colour, replica tile, position tile, replica, position), Rp a multiple of 128
+constexpr int kEaMfmaRPad = 128;
+hipError_t eam_init(const EaView &p, uint8_t *S, int Rp, uint32_t rq0, Key key, hipStream_t st);
+hipError_t eam_from_rows(const EaView &p, const int8_t *src, int R, uint8_t *S, int Rp, hipStream_t st);
+hipError_t eam_to_rows(const EaView &p, const uint8_t *S, int Rp, int8_t *dst, int R, hipStream_t st);
+hipError_t eam_energy(const EaView &p, const uint8_t *S, int Rp, int R, int32_t *E, hipStream_t st);
+hipError_t eam_halfsweep(const EaView &p, uint8_t *S, int Rp, int colour, const EaRow &row, uint32_t sweep,
+                         uint32_t rq0, Key key, hipStream_t st);
 
 // ---- general graphs; spins are device [N][Rp] like the cube ----------------
 hipError_t graph_halfsweep(const GraphView &g, int colour, int8_t *spins, int Rp, const uint32_t *trow, int width,

@@ -133,6 +133,7 @@ extern "C" int pbit_create(pbit_ctx **out, int device, uint64_t hbm_budget_bytes
     if (const char *v = std::getenv("PBIT_EA_ROWS")) ctx->ea_rows = std::max(0, std::atoi(v));  // tuning override
     if (const char *v = std::getenv("PBIT_GRAPH")) ctx->use_graph = std::atoi(v) != 0;
     if (const char *v = std::getenv("PBIT_TILE_TUNE")) ctx->tile_tune = std::atoi(v) != 0;
+    if (const char *v = std::getenv("PBIT_EA_MFMA")) ctx->ea_mfma = std::atoi(v) < 0 ? -1 : (std::atoi(v) ? 1 : 0);
     ctx->serial = g_ctx_serial.fetch_add(1);
     int rc = noalloc_setup(device);  // device address of the static scratch of pbit_anneal_dev_noalloc
     if (rc) {
@@ -241,7 +242,8 @@ static int load_ea(pbit_ctx *ctx, const pbit_problem_desc *d, Problem &p)
     int rc = upload(ctx, p, code.data(), sizeof(uint32_t) * (size_t)N, &dc);
     if (rc == PBIT_OK) rc = upload(ctx, p, d->J, (size_t)(3 * N), &dJ);
     if (rc == PBIT_OK && d->h) rc = upload(ctx, p, d->h, (size_t)N, &dh);
-    EaView v{Lx, Ly, Lz, N, (const uint32_t *)dc, (const int8_t *)dJ, (const int8_t *)dh, dense, nullptr};
+    EaView v{Lx, Ly, Lz, N, (const uint32_t *)dc, (const int8_t *)dJ, (const int8_t *)dh, dense, nullptr,
+             nullptr, nullptr, nullptr, 0, 0};
     if (rc == PBIT_OK && N < 65536) {
         // the LDS-resident kernels' site list: class position -> site, wrap flags, code
         const int64_t half = N / 2, hx = Lx / 2;
@@ -260,6 +262,25 @@ static int load_ea(pbit_ctx *ctx, const pbit_problem_desc *d, Problem &p)
         rc = upload(ctx, p, sites.data(), sizeof(uint32_t) * sites.size(), &ds);
         p.tile_sites = (const uint32_t *)ds;
         if (ea_slab_fits(v)) v.slab_sites = (const uint32_t *)ds;
+    }
+    // the matrix-core half-sweep's tiles (about 160 bytes per site), where the shape
+    // allows them and the path may run: every cube with PBIT_EA_MFMA=1; by default the
+    // cubes too large for the LDS-resident path, up to 2^21 sites
+    const bool mfma_wanted = !ctx->ea_stream_forced && (ctx->ea_mfma == 1 ||
+                             (ctx->ea_mfma != 0 && N > kEaSlabMaxSites && N <= ((int64_t)1 << 21)));
+    if (rc == PBIT_OK && mfma_wanted) {
+        EaMfmaHost mh;
+        if (ea_mfma_build(Lx, Ly, Lz, d->J, d->h, mh)) {
+            void *dt = nullptr, *dp = nullptr, *df = nullptr;
+            rc = upload(ctx, p, mh.tiles.data(), sizeof(int32_t) * mh.tiles.size(), &dt);
+            if (rc == PBIT_OK) rc = upload(ctx, p, mh.pos.data(), sizeof(int32_t) * mh.pos.size(), &dp);
+            if (rc == PBIT_OK) rc = upload(ctx, p, mh.frags.data(), mh.frags.size(), &df);
+            v.mfma_tiles = (const int32_t *)dt;
+            v.mfma_pos = (const int2 *)dp;
+            v.mfma_frags = df;
+            v.mfma_nb = mh.nb;
+            v.mfma_n_tiles = mh.n_tiles;
+        }
     }
     if (rc != PBIT_OK) return rc;
     p.kind = PBIT_EA3D;
@@ -468,7 +489,7 @@ static int load_graph(pbit_ctx *ctx, const pbit_graph_desc *d, Problem &p)
                         (const int32_t *)dbi, (const int32_t *)dbj, (const int8_t *)dbJ, (const int8_t *)dh,
                         (const int32_t *)dcs};
     // the cube's layout kernels (init, transposes) are reused with N = n
-    p.ea = EaView{0, 0, 0, (int64_t)n, nullptr, nullptr, nullptr, false, nullptr};
+    p.ea = EaView{0, 0, 0, (int64_t)n, nullptr, nullptr, nullptr, false, nullptr, nullptr, nullptr, nullptr, 0, 0};
     return PBIT_OK;
 }
 
@@ -619,6 +640,7 @@ struct DevState {
     int8_t *stage = nullptr;  // [R][N] host-layout staging
     BqVariant variant = BqVariant::Auto;
     bool slab = false;        // cube held in LDS for runs of sweeps (ea_slab)
+    bool mfma = false;        // cube fields on the matrix cores (ea_mfma.hip), spins [2][Rp][N / 2]
     Arena *arena = nullptr;   // set: buffers are carved from it (no allocation, no kernel timing)
 };
 
@@ -703,6 +725,48 @@ static int tune_biclique(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStrea
     return PBIT_OK;
 }
 
+// Cube path for a shape that both one-launch-per-half-sweep kernels can take: the
+// streaming stencil or the matrix-core half-sweep, whichever ran faster when timed
+// here (four half-sweeps each, after a warm-up pass) on `spins`, zeroed first (zero
+// bytes are valid +1 spins for both kernels) and at least N x round_up(R, 128)
+// bytes.  The choice is cached per shape and replica count.
+static int tune_cube(pbit_ctx *ctx, const Problem &P, int R, int8_t *spins, hipStream_t st, bool *mfma)
+{
+    const int Rs = round_up(R, kEaRPad), Rm = round_up(R, kEaMfmaRPad);
+    const std::array<int, 4> shape{P.ea.Lx, P.ea.Ly, P.ea.Lz, Rm};
+    auto it = ctx->ea_tuned.find(shape);
+    if (it != ctx->ea_tuned.end()) {
+        *mfma = it->second;
+        return PBIT_OK;
+    }
+    hipError_t e = fill_i32((int32_t *)spins, (int64_t)((size_t)P.N * Rm / 4), 0, st);
+    if (e != hipSuccess) return device_fail(ctx, e, "spin buffer clear (tuning)");
+    hipEvent_t e0, e1;
+    e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) return device_fail(ctx, e, "hipEventCreate (tuning)");
+    EaRow row;
+    for (uint64_t &v : row.s) v = (uint64_t)1 << 31;
+    const Key key{0u, 0u};
+    float ms[2] = {0.f, 0.f};
+    for (int m = 0; m < 2 && e == hipSuccess; ++m)
+        for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // the first pass warms up
+            e = hipEventRecord(e0, st);
+            for (int k = 0; k < 4 && e == hipSuccess; ++k)
+                e = m ? eam_halfsweep(P.ea, (uint8_t *)spins, Rm, k & 1, row, 0u, 0u, key, st)
+                      : ea_halfsweep(P.ea, spins, Rs, k & 1, row, 0u, 0u, key, st, ctx->ea_rows);
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms[m], e0, e1);
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return device_fail(ctx, e, "cube kernel tuning");
+    *mfma = ms[1] < ms[0];
+    ctx->ea_tuned[shape] = *mfma;
+    return PBIT_OK;
+}
+
 static int prepare(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, hipStream_t st, DevState &ds,
                    const void *dev_init)
 {
@@ -715,10 +779,29 @@ static int prepare(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, h
         if ((uint64_t)P.N * (((uint64_t)R + kEaRPad - 1) / kEaRPad * kEaRPad) >= ((uint64_t)1 << 32))
             return fail(PBIT_E_UNSUPPORTED, "%lld spins x %d replicas exceed 4 GiB of int8 spins",
                         (long long)P.N, R);
-        ds.Rp = round_up(R, kEaRPad);
+        // cube paths: PBIT_EA_STREAM=1 takes the stencil; PBIT_EA_MFMA=1 the matrix cores
+        // wherever built; by default cubes that fit LDS stay there, and for larger ones
+        // the stencil and the matrix cores (where built) are timed against each other
+        // (PBIT_EA_MFMA=0: the stencil)
+        const bool cube = P.kind == PBIT_EA3D, tiles = cube && P.ea.mfma_tiles;
+        bool tune = false;
+        if (cube && !ctx->ea_stream_forced) {
+            ds.mfma = tiles && ctx->ea_mfma == 1;
+            ds.slab = !ds.mfma && P.ea.slab_sites;
+            tune = !ds.mfma && !ds.slab && tiles && ctx->ea_mfma != 0 && d->n_sweeps > 0;
+        }
+        // the tuner times both layouts in one buffer: spins for replicas padded to 128
+        ds.Rp = round_up(R, ds.mfma || tune ? kEaMfmaRPad : kEaRPad);
         rc = take(ctx, ds, Slot::Spins, (size_t)P.N * ds.Rp, &v);
         if (rc) return rc;
         ds.spins = (int8_t *)v;
+        if (tune) {
+            if (ds.arena)
+                ds.mfma = R <= 1024;  // no timing without allocation: the measured default, not cached
+            else if ((rc = tune_cube(ctx, P, R, ds.spins, st, &ds.mfma)))
+                return rc;
+            ds.Rp = round_up(R, ds.mfma ? kEaMfmaRPad : kEaRPad);
+        }
     } else {
         // int8 spins, plus a bit copy where the sides are padded to 128 and the replicas to 256
         // (the tuner then times the bit kernel, whose tiles hold 256 replicas: a forced bit
@@ -767,8 +850,7 @@ static int prepare(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, h
         if (rc) return rc;
     }
     ds.bits = P.kind == PBIT_BICLIQUE && ds.variant == BqVariant::Bits;
-    ds.slab = P.kind == PBIT_EA3D && P.ea.slab_sites && !ctx->ea_stream_forced;
-    if (P.kind == PBIT_EA3D && d->n_sweeps > 0) ctx->ea_last_path = ds.slab ? 2 : 1;
+    if (P.kind == PBIT_EA3D && d->n_sweeps > 0) ctx->ea_last_path = ds.slab ? 2 : (ds.mfma ? 3 : 1);
     if (P.kind == PBIT_BICLIQUE && d->n_sweeps > 0) ctx->bq_last_variant = (int)ds.variant;
 
     const Key key{(uint32_t)d->seed, (uint32_t)(d->seed >> 32)};
@@ -783,7 +865,10 @@ static int prepare(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, h
         init_rows = ds.stage;
     }
     const bool rowlayout = P.kind != PBIT_BICLIQUE;  // cube and graph share the [N][Rp] layout
-    if (rowlayout)
+    if (ds.mfma)
+        e = init_rows ? eam_from_rows(P.ea, init_rows, R, (uint8_t *)ds.spins, ds.Rp, st)
+                      : eam_init(P.ea, (uint8_t *)ds.spins, ds.Rp, rq0, key, st);
+    else if (rowlayout)
         e = init_rows ? ea_from_rows(P.ea, init_rows, R, ds.spins, ds.Rp, st)
                       : ea_init(P.ea, ds.spins, ds.Rp, rq0, key, st);
     else
@@ -806,7 +891,9 @@ static hipError_t sweep(pbit_ctx *ctx, const Problem &P, DevState &ds, int s, ui
             e = prof_begin(ctx, P.kind, st);
             if (e != hipSuccess) return e;
         }
-        if (P.kind == PBIT_EA3D)
+        if (ds.mfma)
+            e = eam_halfsweep(P.ea, (uint8_t *)ds.spins, ds.Rp, c, earow, t, rq0, key, st);
+        else if (P.kind == PBIT_EA3D)
             e = ea_halfsweep(P.ea, ds.spins, ds.Rp, c, earow, t, rq0, key, st, ctx->ea_rows);
         else if (P.kind == PBIT_GRAPH)
             e = graph_halfsweep(P.graph, c, ds.spins, ds.Rp, row, ds.width, t, rq0, key, st);
@@ -845,6 +932,7 @@ static hipError_t sweeps(pbit_ctx *ctx, const Problem &P, DevState &ds, int s0, 
 static hipError_t energies(const Problem &P, DevState &ds, hipStream_t st)
 {
     if (P.kind == PBIT_GRAPH) return graph_energy(P.graph, ds.spins, ds.Rp, ds.R, ds.E32, st);
+    if (ds.mfma) return eam_energy(P.ea, (const uint8_t *)ds.spins, ds.Rp, ds.R, ds.E32, st);
     if (P.kind == PBIT_EA3D) return ea_energy(P.ea, ds.spins, ds.Rp, ds.R, ds.E32, st);
     if (ds.bits) {
         hipError_t e = bqb_unpack(P.bq, ds.MAb, ds.MBb, ds.MA, ds.MB, ds.Rp, st);
@@ -855,6 +943,7 @@ static hipError_t energies(const Problem &P, DevState &ds, hipStream_t st)
 
 static hipError_t to_rows(const Problem &P, DevState &ds, int8_t *dst, hipStream_t st)
 {
+    if (ds.mfma) return eam_to_rows(P.ea, (const uint8_t *)ds.spins, ds.Rp, dst, ds.R, st);
     if (P.kind != PBIT_BICLIQUE) return ea_to_rows(P.ea, ds.spins, ds.Rp, dst, ds.R, st);
     if (ds.bits) {
         hipError_t e = bqb_unpack(P.bq, ds.MAb, ds.MBb, ds.MA, ds.MB, ds.Rp, st);
@@ -1027,7 +1116,7 @@ static uint64_t launch_key(const Problem &P, const pbit_anneal_desc *d, const De
     mix(ptrs, sizeof ptrs);
     mix(d->beta, sizeof(double) * (size_t)d->n_sweeps);
     const int64_t f[] = {d->n_sweeps, d->sweep_offset, d->n_replicas, d->replica_offset, (int64_t)d->seed,
-                         ds.Rp, ds.width, (int64_t)ds.variant, ds.slab, ds.bits};
+                         ds.Rp, ds.width, (int64_t)ds.variant, ds.slab, ds.bits, ds.mfma};
     mix(f, sizeof f);
     return h;
 }
@@ -1111,7 +1200,7 @@ size_t anneal_dev_bytes(const pbit_ctx *ctx, const Problem &P, const pbit_anneal
         const size_t ab = Rp * (size_t)(P.bq.na_p + P.bq.nb_p);
         spins = ab + (bqb_supported(P.bq, (int)Rp) ? ab / 8 + 256 : 0);
     } else {
-        Rp = (R + kEaRPad - 1) / kEaRPad * kEaRPad;
+        Rp = (R + kEaMfmaRPad - 1) / kEaMfmaRPad * kEaMfmaRPad;  // the larger of the cube paths' paddings
         spins = (size_t)P.N * Rp;
     }
     const int width = d->n_sweeps > 0 ? table_width(d->beta, d->n_sweeps, P.amax) : 1;

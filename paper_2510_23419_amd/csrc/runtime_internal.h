@@ -75,6 +75,8 @@ struct pbit_ctx {
     int bq_last_variant = 0;  // biclique half-sweep variant of the latest biclique anneal (0: none yet)
     bool ea_stream_forced = false;  // cubes always take the streaming stencil (PBIT_EA_STREAM=1)
     int ea_rows = 0;                // lattice rows per workgroup of the streaming stencil (PBIT_EA_ROWS; 0 = default)
+    int ea_mfma = -1;  // matrix-core cube half-sweep: -1 timed against the stencil, 1 every cube, 0 none (PBIT_EA_MFMA)
+    std::map<std::array<int, 4>, bool> ea_tuned;  // (Lx, Ly, Lz, replicas padded to 128) -> matrix cores faster
     // pbit_anneal_dev's sweep launches as one HIP graph (PBIT_GRAPH=1), kept for replay
     bool use_graph = false;
     bool tile_tune = true;  // batched tile sizes timed per shape (PBIT_TILE_TUNE=0: the fixed rule)

@@ -32,20 +32,22 @@ def _context(**env):
                 os.environ[k] = v
 
 
-@pytest.mark.parametrize("name,make,R,S,stream", [
-    ("cube in LDS", lambda: synth.ea_instance(8, seed=3), 64, 40, "0"),
-    ("streaming cube", lambda: synth.ea_instance(8, seed=3, field="uniform3"), 48, 25, "1"),
-    ("biclique bits", lambda: synth.biclique_instance(512, seed=5), 256, 12, "0"),
-    ("small biclique", lambda: synth.biclique_instance(40, seed=5, nb=70), 33, 30, "0"),
-    ("graph", lambda: synth.dimerized_cube(4, seed=2), 40, 20, "0")])
-def test_graph_replays_equal_the_eager_run(name, make, R, S, stream):
+@pytest.mark.parametrize("name,make,R,S,env", [
+    ("cube in LDS", lambda: synth.ea_instance(8, seed=3), 64, 40, {}),
+    ("streaming cube", lambda: synth.ea_instance(8, seed=3, field="uniform3"), 48, 25, {"PBIT_EA_STREAM": "1"}),
+    ("matrix-core cube", lambda: synth.ea_instance(8, seed=3, field="uniform3"), 130, 25, {"PBIT_EA_MFMA": "1"}),
+    ("biclique bits", lambda: synth.biclique_instance(512, seed=5), 256, 12, {}),
+    ("small biclique", lambda: synth.biclique_instance(40, seed=5, nb=70), 33, 30, {}),
+    ("graph", lambda: synth.dimerized_cube(4, seed=2), 40, 20, {})])
+def test_graph_replays_equal_the_eager_run(name, make, R, S, env):
     import torch
 
     inst = make()
     beta = synth.beta_linear(0.1, 3.0, S)
     beta2 = synth.beta_geometric(0.2, 2.5, S)
-    eager = _context(PBIT_EA_STREAM=stream, PBIT_GRAPH="0")
-    graph = _context(PBIT_EA_STREAM=stream, PBIT_GRAPH="1")
+    env = {"PBIT_EA_STREAM": "0", "PBIT_EA_MFMA": "-1", **env}
+    eager = _context(PBIT_GRAPH="0", **env)
+    graph = _context(PBIT_GRAPH="1", **env)
     try:
         pe, pg = pbit.load_instance(eager.ctx, inst), pbit.load_instance(graph.ctx, inst)
         N = pbit.pbit_problem_spins(eager.ctx, pe)

@@ -32,28 +32,44 @@ def ctx():
     c.close()
 
 
-@pytest.fixture(scope="module", params=["lds", "stream"])
+@pytest.fixture(scope="module", params=["lds", "stream", "mfma"])
 def ectx(request):
-    """A context per cube path: small cubes held in LDS for runs of sweeps (the
-    default), or every cube on the streaming stencil (PBIT_EA_STREAM=1)."""
-    old = os.environ.get("PBIT_EA_STREAM")
-    os.environ["PBIT_EA_STREAM"] = "1" if request.param == "stream" else "0"
+    """A context per cube path: the default (small cubes held in LDS for runs of
+    sweeps, larger ones on the matrix cores where their tiles are built), every
+    cube on the streaming stencil (PBIT_EA_STREAM=1), or every cube on the
+    matrix cores where its tiles are built (PBIT_EA_MFMA=1)."""
+    env = {"lds": {"PBIT_EA_STREAM": "0"}, "stream": {"PBIT_EA_STREAM": "1"},
+           "mfma": {"PBIT_EA_STREAM": "0", "PBIT_EA_MFMA": "1"}}[request.param]
+    old = {k: os.environ.get(k) for k in ("PBIT_EA_STREAM", "PBIT_EA_MFMA")}
+    os.environ.update(env)
     try:
         c = pbit.Context(0)
     finally:
-        if old is None:
-            del os.environ["PBIT_EA_STREAM"]
-        else:
-            os.environ["PBIT_EA_STREAM"] = old
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
     c.mode = request.param
     yield c
     c.close()
 
 
+def _mfma_tiles(dims):
+    """The matrix-core path's tiles are built when a colour class splits into tiles of
+    32 sites (every shape tested here then needs at most 8 neighbour blocks per tile)."""
+    return (int(np.prod(dims)) // 2) % 32 == 0
+
+
 def _check_path(c, inst):
     """The cube path the latest anneal took is the one the context asks for."""
     small = int(np.prod(inst["dims"])) <= 8192
-    assert pbit.pbit_profile_ea_path(c.ctx) == (2 if c.mode == "lds" and small else 1)
+    tiles = _mfma_tiles(inst["dims"])
+    # by default a large cube takes whichever of the stencil and the matrix cores ran
+    # faster when timed
+    want = {"lds": {2} if small else ({1, 3} if tiles else {1}), "stream": {1},
+            "mfma": {3} if tiles else ({2} if small else {1})}[c.mode]
+    assert pbit.pbit_profile_ea_path(c.ctx) in want
 
 
 def _ea_with_zeros(dims, seed):
@@ -116,7 +132,8 @@ def test_ea_L6_every_replica_every_sweep(ectx):
     _check_path(ectx, inst)
 
 
-@pytest.mark.parametrize("dims,R", [((2, 2, 2), 5), ((4, 6, 2), 33), ((10, 8, 6), 20)])
+@pytest.mark.parametrize("dims,R", [((2, 2, 2), 5), ((4, 6, 2), 33), ((10, 8, 6), 20), ((8, 8, 8), 130),
+                                    ((16, 4, 6), 33), ((12, 10, 8), 7), ((32, 2, 4), 129), ((24, 4, 2), 64)])
 def test_ea_ragged_with_fields_and_zero_couplings(ectx, dims, R):
     inst = _ea_with_zeros(dims, seed=3 * R)
     _say("ea ragged %s R=%d (%s)" % (dims, R, ectx.mode))
@@ -231,7 +248,7 @@ def test_target_stops_at_first_reaching_sweep(ectx):
     (lambda: synth.biclique_instance(512, seed=9), 256, 120, 70),        # bit tiles; hit inside a chunk
     (lambda: synth.biclique_instance(40, seed=9, nb=33), 12, 100, 31),   # 64 x 64 tiles; hit on a chunk edge
     (lambda: synth.dimerized_cube(4, seed=4), 16, 90, 40),               # general graph, greedy groups
-    (lambda: synth.ea_instance(24, seed=2), 8, 70, 65)])                 # streaming cube
+    (lambda: synth.ea_instance(24, seed=2), 8, 70, 65)])                 # matrix-core cube
 def test_target_checked_on_the_device(ctx, make, R, S, k):
     """With a target and no trace the library checks the target on the device
     after every sweep and reads the result once per chunk of sweeps: the run
@@ -359,12 +376,13 @@ def test_ea_L16_full_size_sampled(ectx):
     _check_path(ectx, inst)
 
 
-def test_ea_L32_full_size_sampled(ctx):
+def test_ea_L32_full_size_sampled(ectx):
     """L=32 cube, 4096 replicas, beta geometric 0.1 -> 5.0 over 10^4 sweeps."""
     inst = synth.ea_instance(32, seed=32)
     beta = synth.beta_geometric(0.1, 5.0, 10_000)
     rng = np.random.default_rng(32)
-    _check_sampled(ctx, inst, beta, 4096, 1, [1, 2, 10, 100], [], rng)
+    _check_sampled(ectx.ctx, inst, beta, 4096, 1, [1, 2, 10, 100], [], rng)
+    _check_path(ectx, inst)
 
 
 @pytest.mark.parametrize("n,prefixes", [(512, [1, 2, 10, 100, 2000]), (1024, [1, 2, 10, 100]),

@@ -28,7 +28,7 @@ def _graph_of(inst):
     return oracle.biclique_graph(*inst["dims"], inst["J"], inst["h"])
 
 
-def _pair(ctx, inst, beta, R, seed):
+def _pair(ctx, inst, beta, R, seed, path=None):
     """The same anneal through both entry points; returns the no-alloc result
     after checking it against the allocating one.  The no-alloc call comes first
     and must not change the context's device memory."""
@@ -42,6 +42,8 @@ def _pair(ctx, inst, beta, R, seed):
     _say("noalloc %s dims=%s R=%d S=%d" % (inst["kind"], inst.get("dims", inst.get("n")), R, len(beta)))
     pbit.pbit_anneal_dev(ctx, prob, beta, R, seed, a_s, d_energies=a_e, noalloc=True)
     assert pbit.pbit_bytes_in_use(ctx) == held  # nothing allocated by the call
+    if path is not None:
+        assert pbit.pbit_profile_ea_path(ctx) == path
     b_s = torch.zeros((R, N), dtype=torch.int8, device="cuda:0")
     b_e = torch.zeros((R,), dtype=torch.int64, device="cuda:0")
     pbit.pbit_anneal_dev(ctx, prob, beta, R, seed, b_s, d_energies=b_e)
@@ -67,9 +69,14 @@ def test_cube_lds_resident_then_smaller(ctx):
     _pair(ctx, synth.ea_instance((8, 6, 4), seed=5, field="uniform3"), synth.beta_linear(0.1, 3.0, 40), 37, 3)
 
 
-def test_cube_streaming_then_smaller(ctx):
-    _pair(ctx, synth.ea_instance(24, seed=24), synth.beta_geometric(0.1, 5.0, 20), 1024, 2)
-    _pair(ctx, synth.ea_instance(22, seed=22, field="uniform3"), synth.beta_geometric(0.1, 5.0, 15), 100, 4)
+def test_cube_matrix_cores_then_smaller(ctx):
+    # without allocation (no timing), 24^3 and 32 x 16 x 20 at up to 1024 replicas take
+    # the matrix-core half-sweep; 22^3 (5324 sites per colour, not a multiple of 32)
+    # the streaming one
+    _pair(ctx, synth.ea_instance(24, seed=24), synth.beta_geometric(0.1, 5.0, 20), 1024, 2, path=3)
+    _pair(ctx, synth.ea_instance((32, 16, 20), seed=3, field="uniform3"), synth.beta_linear(0.1, 3.0, 12), 100, 3,
+          path=3)
+    _pair(ctx, synth.ea_instance(22, seed=22, field="uniform3"), synth.beta_geometric(0.1, 5.0, 15), 100, 4, path=1)
 
 
 def test_biclique_kernels_then_smaller(ctx):
