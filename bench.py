@@ -170,16 +170,19 @@ def profile_record(workload, kernel=None):
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
-    rec = json.load(open(path)).get(workload)
-    if not rec or (kernel and kernel not in rec["kernel"]):
-        return None
-    h = hashlib.sha256()
-    for src in rec["sources"]:
-        with open(os.path.join(ROOT, src), "rb") as f:
-            h.update(f.read())
-    if h.hexdigest() != rec["sha256"]:
-        return None
-    return rec
+    recs = json.load(open(path))
+    # a workload's records: one per kernel that runs it (the cube's matrix-core
+    # half-sweep under "<workload>_mfma")
+    for rec in (recs.get(workload), recs.get(workload + "_mfma")):
+        if not rec or (kernel and kernel not in rec["kernel"]):
+            continue
+        h = hashlib.sha256()
+        for src in rec["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+        if h.hexdigest() == rec["sha256"]:
+            return rec
+    return None
 
 
 def measured_traffic(workload, kernel=None):
