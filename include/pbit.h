@@ -195,7 +195,9 @@ int pbit_anneal_dev(pbit_ctx *ctx, uint64_t problem, const pbit_anneal_desc *des
  * device array of PBIT_NOALLOC_SCRATCH_BYTES instead of the context's
  * allocations.  The call itself allocates nothing on the device and creates no
  * events; the biclique kernel is the one already timed for the shape on this
- * context, else the bit or DMA tile without timing.  Requests whose buffers
+ * context, else the bit or DMA tile without timing, and a cube that both
+ * one-launch-per-half-sweep kernels can take runs the matrix-core half-sweep for
+ * at most 1024 replicas, else the streaming stencil.  Requests whose buffers
  * exceed the array return E_UNSUPPORTED before any work is enqueued (the bytes
  * needed are about N x R for the cube and graphs, (na + nb) x R x 9/8 for the
  * biclique, plus 4 S x (max |I| + 1) for the table).  The array lives on every
