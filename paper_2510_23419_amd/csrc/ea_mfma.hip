@@ -25,8 +25,10 @@
 // (replicas) x 32 bytes (positions), [2][Rp / 32][N / 64][32][32]; Rp a multiple
 // of 128.  An MFMA operand is then one contiguous 1 KiB read, and the results of a
 // tile fill one 1 KiB block.  The couplings are prepared once per problem: for
-// every colour and tile of 32 out-positions, the list of K blocks and the MFMA B
-// fragments (64 lanes x 16 bytes each).
+// every colour and tile of 32 out-positions the list of K blocks, and for every
+// position its (block, K index, -16 J) entries, at most six; each wave writes its
+// tile's MFMA B fragments (64 lanes x 16 bytes per block, mostly zeros) from these
+// entries into LDS and reads them back once.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -145,7 +147,7 @@ __global__ __launch_bounds__(kThreads) void k_eam_energy(const uint8_t *__restri
 
 // One half-sweep.  A wave (a unit of work) takes one tile of 32 out-positions of
 // colour c and RTW tiles of 32 replicas: its coupling fragments (one per K block)
-// are loaded once, then for every replica tile the spin fragments of the K blocks,
+// are built once, then for every replica tile the spin fragments of the K blocks,
 // NB MFMAs, and the decisions.  Lane l holds out-position l % 32; accumulator
 // element 4 q + i of lane l is replica 8 q + 4 (l / 32) + i of the tile, so a lane's
 // elements 4q .. 4q + 3 are the four replicas of one Philox block.
@@ -158,11 +160,12 @@ __global__ __launch_bounds__(kThreads) void k_eam_energy(const uint8_t *__restri
 template <int NB, int RTW>
 __global__ __launch_bounds__(kThreads) void k_eam_halfsweep(uint8_t *__restrict__ S, const int32_t *__restrict__ tiles,
                                                             const int2 *__restrict__ pos,
-                                                            const v4i *__restrict__ frags, EaRow row, int T, int RT,
+                                                            const v4i *__restrict__ bonds, EaRow row, int T, int RT,
                                                             int colour, int gx, uint32_t sweep, uint32_t rq0, uint32_t k0, uint32_t k1,
                                                             uint32_t one)
 {
     __shared__ uint64_t tab[kFieldSlots];
+    __shared__ v4i fragbuf[kThreads / 64][NB][64];  // each wave's B fragments
     const int tid = threadIdx.x;
     if (tid < kFieldSlots) {
         uint64_t v = row.s[0];
@@ -179,15 +182,36 @@ __global__ __launch_bounds__(kThreads) void k_eam_halfsweep(uint8_t *__restrict_
     const int t = t_lo + u % nt, rg = xr * gpx + u / nt;
     const int lane = tid & 63, n = lane & 31, g = lane >> 5;
     const int c = colour;
-    // tile record: first fragment, then the NB block starts (positions of colour 1 - c)
+    // tile record: the NB block starts (positions of colour 1 - c)
     const int32_t *tr = tiles + (size_t)(c * T + t) * 16;
-    const int frag0 = __builtin_amdgcn_readfirstlane(tr[0]);
     int blk[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) blk[b] = __builtin_amdgcn_readfirstlane(tr[1 + b]);
+    // B fragments: zero this wave's LDS copy, write the bonds of out-position n (lanes
+    // n and n + 32 take three entries each; entry: block, K index k, -16 J at lane
+    // n + 32 (k / 16), byte k % 16 of the block's fragment), read the fragments back
+    const int wv = tid >> 6;
+    const v4i ent = bonds[(size_t)c * (32 * T) + 32 * t + n];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) fragbuf[wv][b][lane] = v4i{0, 0, 0, 0};
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    char *fb = reinterpret_cast<char *>(&fragbuf[wv][0][0]);
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const int w16 = 3 * g + e;  // entry index 0..5
+        const uint32_t word = (uint32_t)ent[w16 >> 1] >> (16 * (w16 & 1));
+        const int b = (int)(word & 7u), k = (int)((word >> 3) & 31u);
+        const int8_t v = (int8_t)(word >> 8);
+        if (v != 0) fb[((b * 64) + n + 32 * (k >> 4)) * 16 + (k & 15)] = v;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     v4i B[NB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) B[b] = frags[(size_t)(frag0 + b) * 64 + lane];
+    for (int b = 0; b < NB; ++b) B[b] = fragbuf[wv][b][lane];
     const int2 pm = pos[(size_t)c * (32 * T) + 32 * t + n];  // site, 8 (h + sum J + 7)
     v16i cinit;
 #pragma unroll
@@ -291,10 +315,11 @@ bool ea_mfma_build(int Lx, int Ly, int Lz, const int8_t *J, const int8_t *h, EaM
             nb = std::max(nb, (int)bl.size());
         }
     if (nb > kEaMfmaMaxBlocks) return false;
+    nb = std::max(nb, 3);  // the kernel is instantiated for 3 to 8 blocks; extra blocks carry zero couplings
     out.nb = nb;
     out.n_tiles = n_tiles;
     out.tiles.assign((size_t)2 * n_tiles * 16, 0);
-    out.frags.assign((size_t)2 * n_tiles * nb * 64 * 16, 0);
+    out.bonds.assign((size_t)2 * N2 * 8, 0);
     out.pos.assign((size_t)2 * N2 * 2, 0);
     for (int c = 0; c < 2; ++c)
         for (int t = 0; t < n_tiles; ++t) {
@@ -302,7 +327,6 @@ bool ea_mfma_build(int Lx, int Ly, int Lz, const int8_t *J, const int8_t *h, EaM
             std::vector<int> bl = blocks[ti];
             while ((int)bl.size() < nb) bl.push_back(bl[0]);  // padding blocks carry zero couplings
             int32_t *rec = &out.tiles[ti * 16];
-            rec[0] = (int32_t)(ti * nb);
             for (int b = 0; b < nb; ++b) rec[1 + b] = bl[(size_t)b];
             for (int n = 0; n < 32; ++n) {
                 const int64_t j = 32 * (int64_t)t + n, rowi = j / hx, kx = j % hx;
@@ -317,17 +341,27 @@ bool ea_mfma_build(int Lx, int Ly, int Lz, const int8_t *J, const int8_t *h, EaM
                                        x + (int64_t)Lx * (y + (int64_t)Ly * zs[5])};
                 const int8_t Jd[6] = {J[i], J[im[0]], J[N + i], J[N + im[1]], J[2 * N + i], J[2 * N + im[2]]};
                 int base = h ? h[i] : 0;
+                // entries (block, K index, -16 J), bonds to the same neighbour merged (at most two
+                // bonds join a pair, when a side is 2: |value| <= 32)
+                int eb[6], ek[6], ev[6], ne = 0;
                 for (int d = 0; d < 6; ++d) {
                     base += Jd[d];
                     if (Jd[d] == 0) continue;
                     const int64_t jn = pos_of(xs[d], ys[d], zs[d]);
                     const int b = (int)(std::find(bl.begin(), bl.end(), (int)(32 * (jn / 32))) - bl.begin());
                     const int k = (int)(jn % 32);
-                    // B fragment of block b: lane n + 32 (k / 16) holds K bytes 16 (k / 16) .. + 15 of
-                    // column n, as -16 J (at most two bonds join a pair: |value| <= 32)
-                    int8_t &v = out.frags[(((size_t)ti * nb + b) * 64 + n + 32 * (k / 16)) * 16 + (k % 16)];
-                    v = (int8_t)(v - 16 * Jd[d]);
+                    int e = 0;
+                    while (e < ne && (eb[e] != b || ek[e] != k)) ++e;
+                    if (e == ne) {
+                        eb[ne] = b;
+                        ek[ne] = k;
+                        ev[ne++] = 0;
+                    }
+                    ev[e] -= 16 * Jd[d];
                 }
+                uint16_t *rec16 = &out.bonds[((size_t)c * N2 + j) * 8];
+                for (int e = 0; e < ne; ++e)
+                    rec16[e] = (uint16_t)(eb[e] | ek[e] << 3 | (uint32_t)(uint8_t)(int8_t)ev[e] << 8);
                 out.pos[((size_t)c * N2 + j) * 2] = (int32_t)i;
                 out.pos[((size_t)c * N2 + j) * 2 + 1] = 8 * (base + kFieldOff);
             }
@@ -396,7 +430,7 @@ hipError_t eam_halfsweep(const EaView &p, uint8_t *S, int Rp, int colour, const 
     const dim3 grid((unsigned)(kXcds * ((most + 3) / 4)));
 #define PBIT_EAM(NB, W)                                                                                          \
     hipLaunchKernelGGL((k_eam_halfsweep<NB, W>), grid, dim3(kThreads), 0, st, S, p.mfma_tiles, p.mfma_pos,        \
-                       reinterpret_cast<const v4i *>(p.mfma_frags), row, T, RT, colour, gx, sweep,                \
+                       reinterpret_cast<const v4i *>(p.mfma_bonds), row, T, RT, colour, gx, sweep,                \
                        rq0, key.k0, key.k1, 1u)
 #define PBIT_EAM_W(NB)              \
     if (rtw == 16) PBIT_EAM(NB, 16); \

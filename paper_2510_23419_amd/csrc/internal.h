@@ -35,7 +35,7 @@ struct EaView {
     // the B fragments (64 lanes x 16 bytes each); null where not built
     const int32_t *mfma_tiles;
     const int2 *mfma_pos;
-    const void *mfma_frags;
+    const void *mfma_bonds;
     int mfma_nb;       // K blocks per tile
     int mfma_n_tiles;  // tiles per colour
 };
@@ -45,7 +45,7 @@ struct EaMfmaHost {
     int nb = 0, n_tiles = 0;
     std::vector<int32_t> tiles;  // [2][n_tiles][16]
     std::vector<int32_t> pos;    // [2][N / 2][2]
-    std::vector<int8_t> frags;   // [2][n_tiles][nb][64][16]
+    std::vector<uint16_t> bonds; // [2][N / 2][8]: per position up to 6 (block, K index, -16 J) entries
 };
 // Builds the tiles of the matrix-core half-sweep; false where the shape does not allow it
 // (N / 2 not a multiple of 32, or a tile whose neighbours span more than kEaMfmaMaxBlocks blocks).

@@ -263,7 +263,7 @@ static int load_ea(pbit_ctx *ctx, const pbit_problem_desc *d, Problem &p)
         p.tile_sites = (const uint32_t *)ds;
         if (ea_slab_fits(v)) v.slab_sites = (const uint32_t *)ds;
     }
-    // the matrix-core half-sweep's tiles (about 160 bytes per site), where the shape
+    // the matrix-core half-sweep's tiles (about 24 bytes per site), where the shape
     // allows them and the path may run: every cube with PBIT_EA_MFMA=1; by default the
     // cubes too large for the LDS-resident path, up to 2^21 sites
     const bool mfma_wanted = !ctx->ea_stream_forced && (ctx->ea_mfma == 1 ||
@@ -274,10 +274,10 @@ static int load_ea(pbit_ctx *ctx, const pbit_problem_desc *d, Problem &p)
             void *dt = nullptr, *dp = nullptr, *df = nullptr;
             rc = upload(ctx, p, mh.tiles.data(), sizeof(int32_t) * mh.tiles.size(), &dt);
             if (rc == PBIT_OK) rc = upload(ctx, p, mh.pos.data(), sizeof(int32_t) * mh.pos.size(), &dp);
-            if (rc == PBIT_OK) rc = upload(ctx, p, mh.frags.data(), mh.frags.size(), &df);
+            if (rc == PBIT_OK) rc = upload(ctx, p, mh.bonds.data(), sizeof(uint16_t) * mh.bonds.size(), &df);
             v.mfma_tiles = (const int32_t *)dt;
             v.mfma_pos = (const int2 *)dp;
-            v.mfma_frags = df;
+            v.mfma_bonds = df;
             v.mfma_nb = mh.nb;
             v.mfma_n_tiles = mh.n_tiles;
         }

@@ -133,7 +133,8 @@ def test_ea_L6_every_replica_every_sweep(ectx):
 
 
 @pytest.mark.parametrize("dims,R", [((2, 2, 2), 5), ((4, 6, 2), 33), ((10, 8, 6), 20), ((8, 8, 8), 130),
-                                    ((16, 4, 6), 33), ((12, 10, 8), 7), ((32, 2, 4), 129), ((24, 4, 2), 64)])
+                                    ((16, 4, 6), 33), ((12, 10, 8), 7), ((32, 2, 4), 129), ((24, 4, 2), 64),
+                                    ((4, 4, 4), 20), ((32, 2, 2), 9)])
 def test_ea_ragged_with_fields_and_zero_couplings(ectx, dims, R):
     inst = _ea_with_zeros(dims, seed=3 * R)
     _say("ea ragged %s R=%d (%s)" % (dims, R, ectx.mode))
