@@ -63,6 +63,10 @@ struct WorkItem {
 };
 
 constexpr int kEaTileThreads = 512;
+// cube tiles with more than this many bytes of LDS rows run one workgroup per CU, as
+// kEaTileThreadsLarge threads (ea_tiles picks the form from the launch's LDS bytes)
+constexpr int kEaTileThreadsLarge = 1024;
+constexpr size_t kEaLargeTileLds = 80 * 1024;
 constexpr int kGraphTileThreads = 512;
 constexpr int kBqTileThreads = 512;
 

@@ -67,7 +67,7 @@ __device__ __forceinline__ uint32_t bit_mask(uint32_t c, int k) { return (uint32
 // I >= 0, 2^32 - Tm for I < 0) whose sum with the random word carries into bit 32
 // exactly when the new spin is -1.  `one` is 1 (passed in so that w * one + S is a
 // single v_mad_u64_u32).
-template <int W>
+template <int W, int TPB>
 __device__ __forceinline__ void ea_tile_item(const WorkItem &w, const EaJobDev &jb, uint4 *tile_rows,
                                              uint64_t *stab, int32_t *eacc, uint32_t one)
 {
@@ -85,7 +85,7 @@ __device__ __forceinline__ void ea_tile_item(const WorkItem &w, const EaJobDev &
     const int fix[6] = {-Lx, Lx, -plane, plane, -N, N};
 
     if (w.init) {
-        for (int i = tid; i < N; i += kEaTileThreads) {
+        for (int i = tid; i < N; i += TPB) {
             V d;
 #pragma unroll
             for (int k = 0; k < W; ++k) {
@@ -98,7 +98,7 @@ __device__ __forceinline__ void ea_tile_item(const WorkItem &w, const EaJobDev &
             rows[i] = d;
         }
     } else {
-        for (int i = tid; i < N; i += kEaTileThreads) rows[i] = load_global<V>(gst + i);
+        for (int i = tid; i < N; i += TPB) rows[i] = load_global<V>(gst + i);
     }
 
     for (int s = w.s_begin; s < w.s_end; ++s) {
@@ -113,7 +113,7 @@ __device__ __forceinline__ void ea_tile_item(const WorkItem &w, const EaJobDev &
         const uint32_t t = jb.sweep0 + (uint32_t)s;
         auto half_sweep = [&](int c, auto dense_tag) {
             constexpr bool DENSE = decltype(dense_tag)::value;
-            for (int j = tid; j < half; j += kEaTileThreads) {
+            for (int j = tid; j < half; j += TPB) {
                 const uint2 e = load_u2(jb.sites + (size_t)c * half + j);
                 const int i = (int)(e.x & 0xFFFFu);
                 const uint32_t wrap = e.x >> 16, code = e.y;
@@ -169,7 +169,7 @@ __device__ __forceinline__ void ea_tile_item(const WorkItem &w, const EaJobDev &
     int32_t er[RS];
 #pragma unroll
     for (int r = 0; r < RS; ++r) er[r] = 0;
-    for (int j = tid; j < N; j += kEaTileThreads) {
+    for (int j = tid; j < N; j += TPB) {
         const int c = j < half ? 0 : 1;
         const uint2 e = load_u2(jb.sites + j);  // colour 0 first, then colour 1
         const int i = (int)(e.x & 0xFFFFu);
@@ -207,14 +207,17 @@ __device__ __forceinline__ void ea_tile_item(const WorkItem &w, const EaJobDev &
     }
     __syncthreads();
     if (tid < RS) jb.energy[RS * w.tile + tid] = eacc[tid];
-    for (int i = tid; i < N; i += kEaTileThreads) gst[i] = rows[i];
+    for (int i = tid; i < N; i += TPB) gst[i] = rows[i];
 }
 
-// Persistent cube-tile kernel: items of any tile width share the launch.
-__global__ __launch_bounds__(kEaTileThreads) void k_ea_tiles(const EaJobDev *__restrict__ jobs,
-                                                             const WorkItem *__restrict__ items,
-                                                             const int32_t *__restrict__ n_items_p,
-                                                             int32_t *__restrict__ counter, uint32_t one)
+// Persistent cube-tile kernel: items of any tile width share the launch.  TPB is
+// 512, or 1024 for tiles whose LDS rows leave room for one workgroup per CU only
+// (four waves per SIMD instead of two).
+template <int TPB>
+__global__ __launch_bounds__(TPB) void k_ea_tiles(const EaJobDev *__restrict__ jobs,
+                                                  const WorkItem *__restrict__ items,
+                                                  const int32_t *__restrict__ n_items_p,
+                                                  int32_t *__restrict__ counter, uint32_t one)
 {
     extern __shared__ uint4 tile_rows[];
     __shared__ uint64_t stab[kFieldSlots];
@@ -227,11 +230,11 @@ __global__ __launch_bounds__(kEaTileThreads) void k_ea_tiles(const EaJobDev *__r
         const WorkItem w = items[it];
         const EaJobDev jb = jobs[w.job];
         if (jb.rs == 16)
-            ea_tile_item<4>(w, jb, tile_rows, stab, eacc, one);
+            ea_tile_item<4, TPB>(w, jb, tile_rows, stab, eacc, one);
         else if (jb.rs == 8)
-            ea_tile_item<2>(w, jb, tile_rows, stab, eacc, one);
+            ea_tile_item<2, TPB>(w, jb, tile_rows, stab, eacc, one);
         else
-            ea_tile_item<1>(w, jb, tile_rows, stab, eacc, one);
+            ea_tile_item<1, TPB>(w, jb, tile_rows, stab, eacc, one);
         __syncthreads();  // the next item's first LDS writes wait for this item's last reads
     }
 }
@@ -846,8 +849,11 @@ size_t bq_tile_lds(int rs, int na_p, int nb_p, int width, int mode)
 hipError_t tiles_set_lds_limit()
 {
     const int max_lds = 160 * 1024 - 4096;  // leave room for the static shared variables
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ea_tiles),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ea_tiles<kEaTileThreads>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ea_tiles<kEaTileThreadsLarge>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
     if (e == hipSuccess)
         e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_graph_tiles),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
@@ -865,8 +871,12 @@ hipError_t tiles_set_lds_limit()
 hipError_t ea_tiles(const EaJobDev *jobs, const WorkItem *items, const int32_t *n_items, int32_t *counter, int grid,
                     size_t lds_bytes, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_ea_tiles, dim3((unsigned)grid), dim3(kEaTileThreads), lds_bytes, st, jobs, items, n_items,
-                       counter, 1u);
+    if (lds_bytes > kEaLargeTileLds)
+        hipLaunchKernelGGL((k_ea_tiles<kEaTileThreadsLarge>), dim3((unsigned)grid), dim3(kEaTileThreadsLarge),
+                           lds_bytes, st, jobs, items, n_items, counter, 1u);
+    else
+        hipLaunchKernelGGL((k_ea_tiles<kEaTileThreads>), dim3((unsigned)grid), dim3(kEaTileThreads), lds_bytes, st,
+                           jobs, items, n_items, counter, 1u);
     return hipGetLastError();
 }
 

@@ -37,9 +37,12 @@ namespace {
 constexpr int kMaxLdsTile = 160 * 1024 - 4096;
 // tile kinds, one persistent launch and one stream each: cube tiles (4, 8 or 16
 // replicas, one launch); 128-, 64- and 32-replica biclique tiles; general-graph
-// tiles (4, 8 or 16 replicas, one launch)
-constexpr int kKinds = 5;
+// tiles (4, 8 or 16 replicas, one launch); cube tiles whose rows need more than
+// kEaLargeTileLds of LDS (one workgroup per CU, launched with more threads; apart
+// from the small ones, whose launch then keeps several workgroups per CU)
+constexpr int kKinds = 6;
 constexpr int kGraphKind = 4;
+constexpr int kCubeLargeKind = 5;
 inline int kind_of_rs(int rs) { return rs == 128 ? 1 : (rs == 64 ? 2 : 3); }
 constexpr double kItemOps = 1.5e11;  // multiply-adds of one biclique tile over its anneal
 inline int rs_of_kind(int k) { return k == 1 ? 128 : (k == 2 ? 64 : 32); }
@@ -432,7 +435,7 @@ static int launch_round(pbit_ctx *ctx, ServeState &s, const std::vector<BJob *> 
                         (uint32_t)j->d.sweep_offset, (uint32_t)j->d.replica_offset >> 2, key.k0, key.k1};
             const int idx = (int)ea.size();
             ea.push_back(jd);
-            const int k = 0;
+            const int k = ea_tile_lds(j->N, j->rs) > kEaLargeTileLds ? kCubeLargeKind : 0;
             for (int t = 0; t < j->tiles; ++t) {
                 items[k].push_back(WorkItem{idx, t, s0, s1, j->started ? 0 : 1, {0, 0, 0}});
                 cost[k].push_back((double)(s1 - s0) * j->N * j->rs);
@@ -514,9 +517,9 @@ static int launch_round(pbit_ctx *ctx, ServeState &s, const std::vector<BJob *> 
         const size_t per_cu_lds = std::max<size_t>(lds[k] + 2048, 1);
         const int per_cu = std::max(1, std::min(4, (int)((160 * 1024) / per_cu_lds)));
         const int grid = std::max(1, std::min((int)items[k].size(), cus * per_cu));
-        if (k == 0)
-            e = ea_tiles((const EaJobDev *)s.d_ea_jobs, (const WorkItem *)s.d_items[0], s.d_meta + kKinds,
-                         s.d_meta + 0, grid, lds[0], s.st[0]);
+        if (k == 0 || k == kCubeLargeKind)
+            e = ea_tiles((const EaJobDev *)s.d_ea_jobs, (const WorkItem *)s.d_items[k], s.d_meta + kKinds + k,
+                         s.d_meta + k, grid, lds[k], s.st[k]);
         else if (k == kGraphKind)
             e = graph_tiles((const GraphJobDev *)s.d_graph_jobs, (const WorkItem *)s.d_items[k], s.d_meta + kKinds + k,
                             s.d_meta + k, grid, lds[k], s.st[k]);

@@ -97,13 +97,15 @@ def test_batch_cube_tile_widths(ctx):
     """Cube jobs of every tile width: 16-replica tiles (lattices up to 8192 sites
     with at least 16 replicas), 8-replica tiles (where 16 do not fit the LDS or the
     job has 8..15 replicas) and 4-replica tiles, each with a ragged last tile, dense
-    and diluted couplings, with and without fields, and non-cubic sides: batched
-    results equal the per-instance path, and the first replica group and the
-    ragged last one equal the oracle."""
+    and diluted couplings, with and without fields, and non-cubic sides; tiles of more
+    and of less than 80 KiB of LDS rows (two cube launches of a round, 1024 and 512
+    threads per workgroup) in one call: batched results equal the per-instance path,
+    and the first replica group and the ragged last one equal the oracle."""
     rng = np.random.default_rng(7)
     cases = [((20, 20, 20), 20, "zero", 1.0), ((22, 22, 22), 12, "uniform3", 0.9), ((24, 24, 24), 8, "zero", 1.0),
              ((20, 22, 16), 17, "uniform3", 1.0), ((6, 6, 6), 16, "zero", 0.8), ((20, 20, 20), 5, "uniform3", 0.9),
-             ((2, 2, 2), 33, "uniform3", 1.0), ((26, 26, 26), 9, "zero", 1.0), ((28, 28, 28), 16, "zero", 1.0)]
+             ((2, 2, 2), 33, "uniform3", 1.0), ((26, 26, 26), 9, "zero", 1.0), ((28, 28, 28), 16, "zero", 1.0),
+             ((32, 32, 32), 6, "uniform3", 0.9)]
     jobs = []
     for k, (dims, R, field, keep) in enumerate(cases):
         inst = synth.ea_instance(dims, seed=40 + k, field=field)
