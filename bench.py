@@ -30,7 +30,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 INT8_MFMA_PEAK_TOPS = 5000.0   # MI355X dense int8 MFMA, published (TOP/s)
 # biclique half-sweep kernels by variant number (pbit_profile_variant)
-BQ_KERNELS = {1: "k_bq_halfsweep", 2: "k_bq_halfsweep_dma", 3: "k_bq_halfsweep_bits"}
+BQ_KERNELS = {1: "k_bq_halfsweep", 2: "k_bq_halfsweep_dma", 3: "k_bq_halfsweep_bits", 4: "k_bq_slab"}
 VALU_PEAK_TLANEOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 32-bit vector lane-ops/s: CUs x SIMDs x lanes x clock
 
 WORKLOADS = {

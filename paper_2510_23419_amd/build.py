@@ -19,7 +19,7 @@ ROOT = PKG.parent
 BUILD = ROOT / "_build" / "pbit"
 LIB = PKG / "libpbit.so"
 
-SOURCES = ["host.cpp", "runtime.cpp", "serve.cpp", "ea_kernels.hip", "ea_mfma.hip", "bq_kernels.hip", "batch_kernels.hip", "graph_kernels.hip", "misc_kernels.hip", "noalloc.cpp", "probe_kernels.hip"]
+SOURCES = ["host.cpp", "runtime.cpp", "serve.cpp", "ea_kernels.hip", "ea_mfma.hip", "bq_kernels.hip", "bq_slab.hip", "batch_kernels.hip", "graph_kernels.hip", "misc_kernels.hip", "noalloc.cpp", "probe_kernels.hip"]
 
 ARCH = "gfx950"
 FLAGS = [

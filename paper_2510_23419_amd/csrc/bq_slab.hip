@@ -1,0 +1,261 @@
+// bq_slab.hip — the biclique sweep of a small instance with everything in LDS, for
+// runs of sweeps in one launch.
+//
+// A half-sweep of a biclique updates one side from the other (Sec. 3; update
+// groups, Sec. 1.2.2): F = J m_other, I = F + h, heat-bath decision.  For sides of
+// at most 512 sites the couplings fit in LDS as two-bit codes of J + 1 in both
+// orientations (J for side A's fields, J^T for side B's: 64 KiB each at 512 x 512),
+// next to the int8 spin rows of 16 replicas.  Replica slices never interact, so a
+// workgroup holds one slice and runs a whole chunk of sweeps with workgroup
+// barriers only: no launch per half-sweep and no coupling traffic after the
+// first load.  Each half-sweep is a v_mfma_i32_16x16x64_i8 product of the spin rows
+// (16 replicas x K sites of the other side) with the widened codes (K x 16 sites),
+// int32 sums; with codes J + 1 the product exceeds the field by the replica's spin
+// sum over the other side, which is subtracted.  The decision is the carry of the
+// Philox word plus the 64-bit word S(I) (Tm(|I|) for I >= 0, 2^32 - Tm for I < 0),
+// as in the other kernels, with the same counters, so results do not depend on
+// the kernel.
+//
+// Spins stay in the library's int8 biclique layout in global memory (MA [Rp][na_p],
+// MB [Rp][nb_p], padding sites zero); the kernel loads a slice at its start and
+// stores it at its end.
+#include <hip/hip_runtime.h>
+
+#include "bq.h"
+#include "device.h"
+#include "internal.h"
+
+namespace pbit {
+
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+constexpr int kThreads = 1024;  // 16 waves: four per SIMD
+constexpr int kWaves = kThreads / 64;
+constexpr int kBlkPerWave = 2;  // 16-site blocks per wave and half-sweep: 32 blocks at 512 sites
+constexpr int kRS = 16;        // replicas per workgroup (the MFMA's 16 rows)
+constexpr int kMaxLds = 160 * 1024 - 4096;
+
+// 4 x 4 byte transpose across a quad of lanes: lane u holds bytes M[u][0..3] and
+// receives M[0..3][u] (two DPP quad permutations and two byte permutes).
+__device__ __forceinline__ uint32_t quad_transpose4(uint32_t d, int u)
+{
+    const uint32_t t = (uint32_t)__builtin_amdgcn_mov_dpp((int)d, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+    const uint32_t d1 = __builtin_amdgcn_perm(t, d, (u & 1) ? 0x03070105u : 0x06020400u);
+    const uint32_t t2 = (uint32_t)__builtin_amdgcn_mov_dpp((int)d1, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+    return __builtin_amdgcn_perm(t2, d1, (u & 2) ? 0x03020706u : 0x05040100u);
+}
+
+// 16 int8 K values from one word of two-bit codes: byte i of dword j is the code at
+// bits 8 i + 2 j (K index 4 j + i of the 16).
+__device__ __forceinline__ v4i widen16(uint32_t x)
+{
+    return v4i{(int)(x & 0x03030303u), (int)((x >> 2) & 0x03030303u), (int)((x >> 4) & 0x03030303u),
+               (int)((x >> 6) & 0x03030303u)};
+}
+
+// Codes of one orientation into LDS: word (kb, s, g) holds J[s][64 kb + 16 g + k] + 1
+// for k = 0..15 (k = 4 j + i at bits 8 i + 2 j), words ordered [kb][s][g] so that the
+// 64 lanes of an MFMA read 64 consecutive words.  Jrow is [ns_p][ko] int8 (padding 0).
+__device__ void stage_codes(const int8_t *__restrict__ Jrow, int ns_p, int ko, uint32_t *codes)
+{
+    const int nw = (ko / 16) * ns_p;  // words: (ko / 64) K steps x ns_p sites x 4 groups
+    for (int wi = threadIdx.x; wi < nw; wi += kThreads) {
+        const int g = wi & 3, s = (wi >> 2) % ns_p, kb = (wi >> 2) / ns_p;
+        const uint4 v = *reinterpret_cast<const uint4 *>(Jrow + (size_t)s * ko + 64 * kb + 16 * g);
+        const uint32_t dw[4] = {v.x, v.y, v.z, v.w};
+        uint32_t w = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t c = (uint32_t)((int)(int8_t)(dw[j] >> (8 * i)) + 1);  // K index 4 j + i
+                // K index k = 4 j' + i' goes to bits 8 i' + 2 j'
+                const int k = 4 * j + i;
+                w |= c << (8 * (k & 3) + 2 * (k >> 2));
+            }
+        codes[wi] = w;
+    }
+}
+
+// Sweeps [s_begin, s_end) of replicas [16 blockIdx.x, + 16) of a small biclique.
+__global__ __launch_bounds__(kThreads) void k_bq_slab(BqView p, int8_t *__restrict__ MA, int8_t *__restrict__ MB,
+                                                      int Rp, const uint32_t *__restrict__ table, int width,
+                                                      int s_begin, int s_end, uint32_t sweep0, uint32_t rq0,
+                                                      uint32_t k0, uint32_t k1, uint32_t one)
+{
+    extern __shared__ uint4 dyn[];
+    __shared__ int32_t mag[kRS];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int na = p.na, nb = p.nb, na_p = p.na_p, nb_p = p.nb_p;
+    const int pitch = na_p + nb_p + 16;
+    // LDS: codes of J (side A's fields, K over side B), codes of J^T, spin rows, decision words
+    uint32_t *codesA = reinterpret_cast<uint32_t *>(dyn);
+    uint32_t *codesB = codesA + (size_t)na_p * nb_p / 16;
+    uint8_t *sp = reinterpret_cast<uint8_t *>(codesB + (size_t)nb_p * na_p / 16);
+    uint64_t *Sw = reinterpret_cast<uint64_t *>(sp + (size_t)kRS * pitch);
+    const char *Sb = reinterpret_cast<const char *>(Sw);
+    const int r0 = kRS * blockIdx.x;  // first replica of the slice (local to this call)
+
+    stage_codes(p.J, na_p, nb_p, codesA);
+    stage_codes(p.JT, nb_p, na_p, codesB);
+    for (int k = tid; k < kRS * (pitch / 16); k += kThreads) {
+        const int r = k / (pitch / 16), c16 = k % (pitch / 16), c = 16 * c16;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (c < na_p)
+            v = *reinterpret_cast<const uint4 *>(MA + (size_t)(r0 + r) * na_p + c);
+        else if (c < na_p + nb_p)
+            v = *reinterpret_cast<const uint4 *>(MB + (size_t)(r0 + r) * nb_p + (c - na_p));
+        *reinterpret_cast<uint4 *>(sp + r * pitch + c) = v;
+    }
+
+    const int top = width - 1;
+    const int col = lane & 15, grp = lane >> 4;  // MFMA: row / column lane%16, K group and C rows lane/16
+    for (int s = s_begin; s < s_end; ++s) {
+        __syncthreads();
+        const uint32_t *trow = table + (size_t)s * width;
+        for (int e = tid; e <= 2 * top; e += kThreads) {
+            const int I = e - top;
+            const uint32_t Tm = trow[I >= 0 ? I : -I];
+            Sw[e] = I >= 0 ? (uint64_t)Tm : ((uint64_t)1 << 32) - Tm;
+        }
+        const uint32_t t = sweep0 + (uint32_t)s;
+#pragma unroll 1
+        for (int side = 0; side < 2; ++side) {
+            const int ns = side == 0 ? na : nb, ns_p = side == 0 ? na_p : nb_p;
+            const int ko = side == 0 ? nb_p : na_p;        // K: sites of the other side
+            const int in_col = side == 0 ? na_p : 0;       // the other side's columns
+            const int out_col = side == 0 ? 0 : na_p;      // this side's columns
+            const uint32_t *codes = side == 0 ? codesA : codesB;
+            const int8_t *hs = side == 0 ? p.hA : p.hB;
+            const uint32_t site_base = side == 0 ? 0u : (uint32_t)na;
+            const int nblk = ns_p / 16;
+            // the random words and fields of this wave's sites first: they do not depend on
+            // the spins, so they are drawn while the LDS reads below are in flight
+            Block4 w[kBlkPerWave];
+            int hv[kBlkPerWave];
+#pragma unroll
+            for (int q = 0; q < kBlkPerWave; ++q) {
+                const int site = (wave + kWaves * q) * 16 + col;
+                hv[q] = site < ns_p ? (int)hs[site] : 0;
+                w[q] = philox(site_base + (uint32_t)site, t, rq0 + (uint32_t)(blockIdx.x * (kRS / 4) + grp),
+                              kDomainSweep, k0, k1);
+            }
+            // the other side's spin sum per replica (padding sites are zero): one wave per row
+            if (wave < kRS) {
+                const uint32_t *row = reinterpret_cast<const uint32_t *>(sp + wave * pitch + in_col);
+                int v = 0;
+                for (int d = lane; d < ko / 4; d += 64) {
+                    const uint32_t x = row[d];
+                    v += (int)(int8_t)x + (int)(int8_t)(x >> 8) + (int)(int8_t)(x >> 16) + (int)(int8_t)(x >> 24);
+                }
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+                if (lane == 0) mag[wave] = v;
+            }
+            __syncthreads();
+            // fields of up to kBlkPerWave 16-site blocks per wave (blocks wave, wave + kWaves,
+            // ...), the operands of K step kb + 1 read from LDS before the MFMAs of step kb
+            v4i acc[kBlkPerWave];
+#pragma unroll
+            for (int q = 0; q < kBlkPerWave; ++q) acc[q] = v4i{0, 0, 0, 0};
+            const uint8_t *arow = sp + col * pitch + in_col + 16 * grp;
+            const int nkb = ko / 64;
+            auto codes_of = [&](int kb, uint32_t(&c)[kBlkPerWave]) {
+                const uint32_t *ck = codes + (size_t)kb * ns_p * 4;
+#pragma unroll
+                for (int q = 0; q < kBlkPerWave; ++q) {
+                    const int blk = wave + kWaves * q;
+                    c[q] = blk < nblk ? ck[(blk * 16 + col) * 4 + grp] : 0u;
+                }
+            };
+            v4i a = *reinterpret_cast<const v4i *>(arow);
+            uint32_t c[kBlkPerWave];
+            codes_of(0, c);
+            for (int kb = 0; kb < nkb; ++kb) {
+                v4i an = a;
+                uint32_t cn[kBlkPerWave];
+#pragma unroll
+                for (int q = 0; q < kBlkPerWave; ++q) cn[q] = c[q];
+                if (kb + 1 < nkb) {
+                    an = *reinterpret_cast<const v4i *>(arow + 64 * (kb + 1));
+                    codes_of(kb + 1, cn);
+                }
+#pragma unroll
+                for (int q = 0; q < kBlkPerWave; ++q)
+                    if (wave + kWaves * q < nblk)
+                        acc[q] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, widen16(c[q]), acc[q], 0, 0, 0);
+                a = an;
+#pragma unroll
+                for (int q = 0; q < kBlkPerWave; ++q) c[q] = cn[q];
+            }
+            // decisions: lane holds site blk * 16 + col for replicas 4 grp .. 4 grp + 3,
+            // one Philox block; the four bytes are transposed across the lane quad so that
+            // each lane writes four consecutive sites of one replica row
+            const int u4 = lane & 3;
+#pragma unroll
+            for (int q = 0; q < kBlkPerWave; ++q) {
+                const int blk = wave + kWaves * q;
+                if (blk >= nblk) continue;
+                const int site = blk * 16 + col;
+                const int hval = hv[q];
+                const int flo = -top - hval, fhi = top - hval;
+                const int base8 = 8 * (hval + top);
+                uint32_t sgn[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int F = acc[q][j] - mag[4 * grp + j];
+                    const int Fc = min(max(F, flo), fhi);
+                    const uint64_t S =
+                        *static_cast<const uint64_t *>(__builtin_assume_aligned(Sb + 8 * Fc + base8, 8));
+                    sgn[j] = (uint32_t)(((uint64_t)w[q].w[j] * one + S) >> 32);
+                }
+                const uint32_t lo = __builtin_amdgcn_perm(sgn[1], sgn[0], 0x0C0C0400u);
+                const uint32_t hi = __builtin_amdgcn_perm(sgn[3], sgn[2], 0x0C0C0400u);
+                uint32_t packed = __builtin_amdgcn_perm(0u, 0xFF01u, __builtin_amdgcn_perm(hi, lo, 0x05040100u));
+                if (site >= ns) packed = 0u;  // padding sites stay zero
+                const uint32_t x = quad_transpose4(packed, u4);
+                *reinterpret_cast<uint32_t *>(sp + (4 * grp + u4) * pitch + out_col + blk * 16 + (col & ~3)) = x;
+            }
+            __syncthreads();
+        }
+    }
+
+    for (int k = tid; k < kRS * ((na_p + nb_p) / 16); k += kThreads) {
+        const int r = k / ((na_p + nb_p) / 16), c = 16 * (k % ((na_p + nb_p) / 16));
+        const uint4 v = *reinterpret_cast<const uint4 *>(sp + r * pitch + c);
+        if (c < na_p)
+            *reinterpret_cast<uint4 *>(MA + (size_t)(r0 + r) * na_p + c) = v;
+        else
+            *reinterpret_cast<uint4 *>(MB + (size_t)(r0 + r) * nb_p + (c - na_p)) = v;
+    }
+}
+
+size_t slab_lds(const BqView &p, int width)
+{
+    return (size_t)2 * p.na_p * p.nb_p / 4 + (size_t)kRS * (p.na_p + p.nb_p + 16) +
+           sizeof(uint64_t) * (size_t)(2 * width - 1);
+}
+
+}  // namespace
+
+bool bq_slab_supported(const BqView &p, int Rp, int width)
+{
+    return p.na_p <= 512 && p.nb_p <= 512 && p.na_p % 64 == 0 && p.nb_p % 64 == 0 && Rp % kRS == 0 &&
+           width >= 1 && slab_lds(p, width) <= (size_t)kMaxLds;
+}
+
+hipError_t bq_slab(const BqView &p, int8_t *MA, int8_t *MB, int Rp, const uint32_t *table, int width, int s_begin,
+                   int s_end, uint32_t sweep0, uint32_t rq0, Key key, hipStream_t st)
+{
+    if (!bq_slab_supported(p, Rp, width) || s_end < s_begin) return hipErrorInvalidValue;
+    static const hipError_t lds_attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bq_slab),
+                                                           hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    if (lds_attr != hipSuccess) return lds_attr;
+    hipLaunchKernelGGL(k_bq_slab, dim3((unsigned)(Rp / kRS)), dim3(kThreads), slab_lds(p, width), st, p, MA, MB, Rp,
+                       table, width, s_begin, s_end, sweep0, rq0, key.k0, key.k1, 1u);
+    return hipGetLastError();
+}
+
+}  // namespace pbit

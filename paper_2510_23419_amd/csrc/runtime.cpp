@@ -125,9 +125,9 @@ extern "C" int pbit_create(pbit_ctx **out, int device, uint64_t hbm_budget_bytes
     if (!ctx) return fail(PBIT_E_NOMEM, "pbit_create: host allocation failed");
     ctx->device = device;
     ctx->budget = hbm_budget_bytes;
-    if (const char *v = std::getenv("PBIT_BQ_VARIANT")) {  // tuning override: 1..3 (see BqVariant)
+    if (const char *v = std::getenv("PBIT_BQ_VARIANT")) {  // tuning override: 1..4 (see BqVariant)
         const int k = std::atoi(v);
-        if (k >= 1 && k <= 3) ctx->bq_forced = (BqVariant)k;
+        if (k >= 1 && k <= 4) ctx->bq_forced = (BqVariant)k;
     }
     if (const char *v = std::getenv("PBIT_EA_STREAM")) ctx->ea_stream_forced = std::atoi(v) != 0;
     if (const char *v = std::getenv("PBIT_EA_ROWS")) ctx->ea_rows = std::max(0, std::atoi(v));  // tuning override
@@ -658,63 +658,93 @@ static int take(pbit_ctx *ctx, DevState &ds, Slot slot, size_t bytes, void **out
     return PBIT_OK;
 }
 
-constexpr int kSlabChunk = 1000;  // sweeps per launch of the LDS-resident cube kernel
+constexpr int kSlabChunk = 1000;  // sweeps per launch of the LDS-resident cube and biclique kernels
 
 // Pick the biclique kernel variant for this shape: the forced one, a cached
 // choice, or the fastest of the candidates timed here on the (not yet
 // initialised) spin buffers, whose contents do not affect the timing.
-static int tune_biclique(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStream_t st)
+static int tune_biclique(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStream_t st, int n_sweeps)
 {
     // the DMA and bit tiles need sides padded to 128 (and the bit tiles a bit copy of
-    // the spins, made where the replicas pad to 256)
+    // the spins, made where the replicas pad to 256); the LDS-resident form sides of
+    // at most 512 and its decision words in LDS
     const bool large = P.bq.na_p % 128 == 0 && P.bq.nb_p % 128 == 0;
+    const bool slab_ok = bq_slab_supported(P.bq, ds.Rp, ds.width);
     const BqVariant f = ctx->bq_forced;
-    if (f == BqVariant::Small || (f == BqVariant::Dma && large) || (f == BqVariant::Bits && ds.MAb)) {
+    if (f == BqVariant::Small || (f == BqVariant::Dma && large) || (f == BqVariant::Bits && ds.MAb) ||
+        (f == BqVariant::Slab && slab_ok)) {
         ds.variant = f;  // a forced kernel the shape cannot take falls back to the tuned choice
         return PBIT_OK;
     }
-    const std::array<int, 3> shape{P.bq.na_p, P.bq.nb_p, ds.Rp};
+    const std::array<int, 4> shape{P.bq.na_p, P.bq.nb_p, ds.Rp, slab_ok ? 1 : 0};
     auto it = ctx->bq_tuned.find(shape);
     if (it != ctx->bq_tuned.end()) {
         ds.variant = it->second;
         return PBIT_OK;
     }
-    if (!large) {
+    if (!large && !slab_ok) {
         ds.variant = BqVariant::Small;
         ctx->bq_tuned[shape] = ds.variant;
         return PBIT_OK;
     }
     if (ds.arena) {
         // no timing here (it would create events and wait for the stream): the kernel
-        // the tuner keeps at the benchmark's large sides, else the DMA tile; not cached
-        ds.variant = ds.MAb ? BqVariant::Bits : BqVariant::Dma;
+        // the tuner keeps at the benchmark's shapes (the LDS-resident form where it
+        // runs, else the bit tile), else the DMA or 64 x 64 tile; not cached
+        ds.variant = slab_ok ? BqVariant::Slab : ds.MAb ? BqVariant::Bits : large ? BqVariant::Dma : BqVariant::Small;
         return PBIT_OK;
     }
-    const BqVariant cand[] = {BqVariant::Dma, BqVariant::Small, BqVariant::Bits};
+    const BqVariant cand[] = {BqVariant::Small, BqVariant::Dma, BqVariant::Bits, BqVariant::Slab};
     hipEvent_t e0, e1;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     if (e != hipSuccess) return device_fail(ctx, e, "hipEventCreate (tuning)");
     const Key key{0u, 0u};
+    // the LDS-resident form loads its couplings once per launch of up to kSlabChunk sweeps:
+    // timed over 1 and 1 + m sweeps, and its cost for this call's sweeps set against the
+    // others' per half-sweep (table rows up to n_sweeps are read)
+    const int S = std::max(1, n_sweeps), m = std::min(8, S - 1);
     float best_ms = 0.f;
-    BqVariant best = BqVariant::Dma;
-    for (BqVariant v : cand) {
-        if (v == BqVariant::Bits && !ds.MAb) continue;  // no bit copy: the shape cannot take it
-        float ms = 0.f;
+    BqVariant best = BqVariant::Small;
+    bool have = false;
+    auto time_it = [&](BqVariant v, int slab_sweeps, float *ms) {
         for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // first pass warms up
             e = hipEventRecord(e0, st);
-            for (int k = 0; k < 4 && e == hipSuccess; ++k)
-                e = v == BqVariant::Bits
-                        ? bqb_halfsweep(P.bq, k & 1, ds.MAb, ds.MBb, ds.Rp, ds.table, ds.width, 0u, 0u, key, st)
-                        : bq_halfsweep(P.bq, k & 1, ds.MA, ds.MB, ds.R, ds.Rp, ds.table, ds.width, 0u, 0u, key, st, v);
+            if (v == BqVariant::Slab) {
+                if (e == hipSuccess)
+                    e = bq_slab(P.bq, ds.MA, ds.MB, ds.Rp, ds.table, ds.width, 0, slab_sweeps, 0u, 0u, key, st);
+            } else {
+                for (int k = 0; k < 4 && e == hipSuccess; ++k)
+                    e = v == BqVariant::Bits
+                            ? bqb_halfsweep(P.bq, k & 1, ds.MAb, ds.MBb, ds.Rp, ds.table, ds.width, 0u, 0u, key, st)
+                            : bq_halfsweep(P.bq, k & 1, ds.MA, ds.MB, ds.R, ds.Rp, ds.table, ds.width, 0u, 0u, key,
+                                           st, v);
+            }
             if (e == hipSuccess) e = hipEventRecord(e1, st);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+        }
+    };
+    for (BqVariant v : cand) {
+        if ((v == BqVariant::Dma && !large) || (v == BqVariant::Bits && !ds.MAb) || (v == BqVariant::Slab && !slab_ok))
+            continue;  // the shape cannot take it
+        float ms = 0.f;
+        if (v == BqVariant::Slab) {
+            float t1 = 0.f, t2 = 0.f;
+            time_it(v, 1, &t1);
+            if (m > 0) time_it(v, 1 + m, &t2);
+            const double per_sweep = m > 0 ? std::max(0.0, (double)(t2 - t1) / m) : t1;
+            const double load = m > 0 ? std::max(0.0, t1 - per_sweep) : 0.0;
+            const double total = (double)((S + kSlabChunk - 1) / kSlabChunk) * load + S * per_sweep;
+            ms = (float)(total * 2.0 / S);  // per four half-sweeps, as the others
+        } else {
+            time_it(v, 0, &ms);
         }
         if (e != hipSuccess) break;
-        if (v == cand[0] || ms < best_ms) {
+        if (!have || ms < best_ms) {
             best_ms = ms;
             best = v;
+            have = true;
         }
     }
     (void)hipEventDestroy(e0);
@@ -846,10 +876,11 @@ static int prepare(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, h
     if (e != hipSuccess) return device_fail(ctx, e, "hipMemcpyAsync (table)");
 
     if (P.kind == PBIT_BICLIQUE && d->n_sweeps > 0) {
-        rc = tune_biclique(ctx, P, ds, st);
+        rc = tune_biclique(ctx, P, ds, st, d->n_sweeps);
         if (rc) return rc;
     }
     ds.bits = P.kind == PBIT_BICLIQUE && ds.variant == BqVariant::Bits;
+    if (P.kind == PBIT_BICLIQUE && ds.variant == BqVariant::Slab) ds.slab = true;  // runs of sweeps per launch
     if (P.kind == PBIT_EA3D && d->n_sweeps > 0) ctx->ea_last_path = ds.slab ? 2 : (ds.mfma ? 3 : 1);
     if (P.kind == PBIT_BICLIQUE && d->n_sweeps > 0) ctx->bq_last_variant = (int)ds.variant;
 
@@ -921,7 +952,9 @@ static hipError_t sweeps(pbit_ctx *ctx, const Problem &P, DevState &ds, int s0, 
     hipError_t e = hipSuccess;
     const bool timed = ctx->prof_every > 0 && ctx->prof_open < 0;
     if (timed) e = prof_begin(ctx, P.kind, st);
-    if (e == hipSuccess) e = ea_slab(P.ea, ds.spins, ds.Rp, ds.table, ds.width, s0, s1, sweep0, rq0, key, st);
+    if (e == hipSuccess)
+        e = P.kind == PBIT_BICLIQUE ? bq_slab(P.bq, ds.MA, ds.MB, ds.Rp, ds.table, ds.width, s0, s1, sweep0, rq0, key, st)
+                                    : ea_slab(P.ea, ds.spins, ds.Rp, ds.table, ds.width, s0, s1, sweep0, rq0, key, st);
     if (e == hipSuccess && timed) {
         ctx->prof_launches.back() += 2 * (s1 - s0);
         e = prof_close(ctx, st);

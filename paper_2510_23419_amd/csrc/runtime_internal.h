@@ -84,7 +84,7 @@ struct pbit_ctx {
     uint64_t graph_key = 0;
     int64_t graph_captures = 0, graph_launches = 0;
     int ea_last_path = 0;           // cube path of the latest cube anneal: 1 stream, 2 LDS-resident (0: none)
-    std::map<std::array<int, 3>, pbit::BqVariant> bq_tuned;  // (na_p, nb_p, Rp) -> fastest
+    std::map<std::array<int, 4>, pbit::BqVariant> bq_tuned;  // (na_p, nb_p, Rp, LDS form possible) -> fastest
 };
 
 namespace pbit {

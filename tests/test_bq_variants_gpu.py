@@ -8,7 +8,10 @@ default is:
 * 3: spins held as bits, widened to bytes for the int8 MFMA; the field is the
   site's field plus its coupling sum minus twice the product (sides padded to
   128; a forced bit kernel pads the replicas to 256).  The batched engine's bit
-  tiles run under this variant too.
+  tiles run under this variant too;
+* 4: sides of at most 512 sites held in LDS with their couplings (two-bit codes of
+  J + 1 in both orientations) for runs of sweeps in one launch, 16 replicas per
+  workgroup, on the int8 MFMA 16 x 16 x 64.
 
 Each kernel is checked on every replica after every sweep on ragged sides, on
 sampled replicas at full size (n = 1024 and 4096, 1024 replicas), and at 128
@@ -150,3 +153,56 @@ def test_bit_tiles_and_default_tiles_agree(bits_ctx):
         assert np.array_equal(a.energies, b.energies)
     for p in probs:
         pbit.pbit_unload_problem(bits_ctx, p)
+
+
+@pytest.fixture(scope="module")
+def slab_ctx():
+    c = _forced_context("4")
+    yield c.ctx
+    c.close()
+
+
+@pytest.mark.parametrize("na,nb,R", [(40, 40, 70), (130, 70, 33), (512, 512, 130), (300, 500, 17), (64, 448, 5),
+                                     (7, 130, 129), (600, 40, 20)])
+def test_slab_every_replica_every_sweep(slab_ctx, na, nb, R):
+    """The LDS-resident form on ragged sides with fields, every replica after every
+    sweep (one launch per sweep here, as the trace asks for energies after each);
+    sides beyond 512 fall back to the tuned kernel."""
+    inst = synth.biclique_instance(na, seed=na + 5 * nb + R, nb=nb)
+    _say("slab biclique %dx%d R=%d every sweep" % (na, nb, R))
+    _every_sweep(slab_ctx, inst, synth.beta_linear(0.05, 2.0, 10), R, seed=17)
+    assert (pbit.pbit_profile_variant(slab_ctx) == 4) == (max(na, nb) <= 512)
+
+
+@pytest.mark.parametrize("n,R,prefixes", [(512, 1024, [1, 2, 10, 1500]), (256, 96, [3, 1200]), (448, 2000, [2, 40])])
+def test_slab_runs_of_sweeps_sampled(slab_ctx, n, R, prefixes):
+    """K_{n,n}, beta linear 0.05 -> 2.0 over 2000 sweeps: runs of up to 1000 sweeps per
+    launch (1500 and 1200 take two launches), sampled replica groups against the oracle."""
+    inst = synth.biclique_instance(n, seed=n + R)
+    beta = synth.beta_linear(0.05, 2.0, 2000)
+    _say("slab K_%d R=%d sampled" % (n, R))
+    _check_sampled(slab_ctx, inst, beta, R, 1, prefixes, [0, R // 4 - 1], np.random.default_rng(n))
+    assert pbit.pbit_profile_variant(slab_ctx) == 4
+
+
+def test_slab_offsets_resume_and_given_spins(slab_ctx):
+    """Replica slices, a split run resumed from its spins, and given initial spins on
+    the LDS-resident form equal the oracle."""
+    inst = synth.biclique_instance(200, seed=8, nb=136)
+    g = graph_of(inst)
+    beta = synth.beta_linear(0.1, 2.5, 60)
+    prob = pbit.load_instance(slab_ctx, inst)
+    full = pbit.pbit_anneal(slab_ctx, prob, beta, 40, seed=5)
+    assert pbit.pbit_profile_variant(slab_ctx) == 4
+    ref = oracle.anneal(g, beta, 40, seed=5)
+    assert np.array_equal(full.spins, ref.spins) and np.array_equal(full.energies, ref.energies)
+    a = pbit.pbit_anneal(slab_ctx, prob, beta[:23], 40, seed=5)
+    b = pbit.pbit_anneal(slab_ctx, prob, beta[23:], 40, seed=5, sweep_offset=23, init_spins=a.spins)
+    assert np.array_equal(b.spins, full.spins)
+    part = pbit.pbit_anneal(slab_ctx, prob, beta, 12, seed=5, replica_offset=16)
+    assert np.array_equal(part.spins, full.spins[16:28])
+    init = synth.random_spins(40, 336, seed=3)
+    got = pbit.pbit_anneal(slab_ctx, prob, beta, 40, seed=9, init_spins=init)
+    ref = oracle.anneal(g, beta, 40, seed=9, init_spins=init)
+    assert np.array_equal(got.spins, ref.spins)
+    pbit.pbit_unload_problem(slab_ctx, prob)
