@@ -86,16 +86,20 @@ __global__ __launch_bounds__(kThreads) void k_bq_slab(BqView p, int8_t *__restri
                                                       uint32_t k0, uint32_t k1, uint32_t one)
 {
     extern __shared__ uint4 dyn[];
-    __shared__ int32_t mag[kRS];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // spin sums per replica over side A and over side B, two of each by sweep parity: a
+    // half-sweep's decisions read the other side's sum while its epilogue adds up its own
+    // side's new spins for the next half-sweep
+    __shared__ int32_t magA[2][kRS], magB[2][kRS];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: block tests are scalar branches
     const int na = p.na, nb = p.nb, na_p = p.na_p, nb_p = p.nb_p;
     const int pitch = na_p + nb_p + 16;
     // LDS: codes of J (side A's fields, K over side B), codes of J^T, spin rows, decision words
     uint32_t *codesA = reinterpret_cast<uint32_t *>(dyn);
     uint32_t *codesB = codesA + (size_t)na_p * nb_p / 16;
     uint8_t *sp = reinterpret_cast<uint8_t *>(codesB + (size_t)nb_p * na_p / 16);
-    uint64_t *Sw = reinterpret_cast<uint64_t *>(sp + (size_t)kRS * pitch);
-    const char *Sb = reinterpret_cast<const char *>(Sw);
+    // decision words of two sweeps: those of sweep s + 1 are written during sweep s
+    uint64_t *Sw2 = reinterpret_cast<uint64_t *>(sp + (size_t)kRS * pitch);
     const int r0 = kRS * blockIdx.x;  // first replica of the slice (local to this call)
 
     stage_codes(p.J, na_p, nb_p, codesA);
@@ -112,15 +116,42 @@ __global__ __launch_bounds__(kThreads) void k_bq_slab(BqView p, int8_t *__restri
 
     const int top = width - 1;
     const int col = lane & 15, grp = lane >> 4;  // MFMA: row / column lane%16, K group and C rows lane/16
-    for (int s = s_begin; s < s_end; ++s) {
-        __syncthreads();
+    auto build_words = [&](int s) {
         const uint32_t *trow = table + (size_t)s * width;
+        uint64_t *Sw = Sw2 + (size_t)(s & 1) * (2 * top + 1);
         for (int e = tid; e <= 2 * top; e += kThreads) {
             const int I = e - top;
             const uint32_t Tm = trow[I >= 0 ? I : -I];
             Sw[e] = I >= 0 ? (uint64_t)Tm : ((uint64_t)1 << 32) - Tm;
         }
+    };
+    if (s_begin < s_end) build_words(s_begin);
+    __syncthreads();  // the spin rows are in LDS
+    // side B's spin sums for the first half-sweep, one wave per replica row; side A's sums
+    // start at zero
+    if (wave < kRS) {
+        const uint32_t *row = reinterpret_cast<const uint32_t *>(sp + wave * pitch + na_p);
+        int v = 0;
+        for (int d = lane; d < nb_p / 4; d += 64) v = __builtin_amdgcn_sdot4((int)row[d], 0x01010101, v, false);
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) {
+            magB[s_begin & 1][wave] = v;
+            magA[s_begin & 1][wave] = 0;
+        }
+    }
+    __syncthreads();  // codes, spins, the first decision words and sums are in LDS
+    // two barriers per sweep, one after each half-sweep (its spins, sums and, after side B,
+    // the next sweep's decision words are then complete)
+    for (int s = s_begin; s < s_end; ++s) {
+        const int par = s & 1;
         const uint32_t t = sweep0 + (uint32_t)s;
+        const char *Sb = reinterpret_cast<const char *>(Sw2 + (size_t)par * (2 * top + 1));
+        // the sums filled in the next two half-sweeps start at zero (last read a sweep ago)
+        if (tid < kRS) {
+            magB[par ^ 1][tid] = 0;
+            magA[par ^ 1][tid] = 0;
+        }
 #pragma unroll 1
         for (int side = 0; side < 2; ++side) {
             const int ns = side == 0 ? na : nb, ns_p = side == 0 ? na_p : nb_p;
@@ -142,19 +173,9 @@ __global__ __launch_bounds__(kThreads) void k_bq_slab(BqView p, int8_t *__restri
                 w[q] = philox(site_base + (uint32_t)site, t, rq0 + (uint32_t)(blockIdx.x * (kRS / 4) + grp),
                               kDomainSweep, k0, k1);
             }
-            // the other side's spin sum per replica (padding sites are zero): one wave per row
-            if (wave < kRS) {
-                const uint32_t *row = reinterpret_cast<const uint32_t *>(sp + wave * pitch + in_col);
-                int v = 0;
-                for (int d = lane; d < ko / 4; d += 64) {
-                    const uint32_t x = row[d];
-                    v += (int)(int8_t)x + (int)(int8_t)(x >> 8) + (int)(int8_t)(x >> 16) + (int)(int8_t)(x >> 24);
-                }
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-                if (lane == 0) mag[wave] = v;
-            }
-            __syncthreads();
+            // the other side's spin sums (side B's of this sweep's parity, side A's just filled)
+            const int32_t *mag = side == 0 ? magB[par] : magA[par];
+            int32_t *mag_out = side == 0 ? magA[par] : magB[par ^ 1];
             // fields of up to kBlkPerWave 16-site blocks per wave (blocks wave, wave + kWaves,
             // ...), the operands of K step kb + 1 read from LDS before the MFMAs of step kb
             v4i acc[kBlkPerWave];
@@ -170,25 +191,29 @@ __global__ __launch_bounds__(kThreads) void k_bq_slab(BqView p, int8_t *__restri
                     c[q] = blk < nblk ? ck[(blk * 16 + col) * 4 + grp] : 0u;
                 }
             };
-            v4i a = *reinterpret_cast<const v4i *>(arow);
-            uint32_t c[kBlkPerWave];
-            codes_of(0, c);
-            for (int kb = 0; kb < nkb; ++kb) {
-                v4i an = a;
-                uint32_t cn[kBlkPerWave];
-#pragma unroll
-                for (int q = 0; q < kBlkPerWave; ++q) cn[q] = c[q];
-                if (kb + 1 < nkb) {
-                    an = *reinterpret_cast<const v4i *>(arow + 64 * (kb + 1));
-                    codes_of(kb + 1, cn);
-                }
+            auto step = [&](const v4i &a, const uint32_t(&c)[kBlkPerWave]) {
 #pragma unroll
                 for (int q = 0; q < kBlkPerWave; ++q)
                     if (wave + kWaves * q < nblk)
                         acc[q] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, widen16(c[q]), acc[q], 0, 0, 0);
-                a = an;
-#pragma unroll
-                for (int q = 0; q < kBlkPerWave; ++q) c[q] = cn[q];
+            };
+            // two operand sets in turn (no register copies between the steps)
+            v4i a0 = *reinterpret_cast<const v4i *>(arow), a1 = a0;
+            uint32_t c0[kBlkPerWave], c1[kBlkPerWave];
+            codes_of(0, c0);
+            for (int kb = 0; kb < nkb; kb += 2) {
+                if (kb + 1 < nkb) {
+                    a1 = *reinterpret_cast<const v4i *>(arow + 64 * (kb + 1));
+                    codes_of(kb + 1, c1);
+                }
+                step(a0, c0);
+                if (kb + 1 < nkb) {
+                    if (kb + 2 < nkb) {
+                        a0 = *reinterpret_cast<const v4i *>(arow + 64 * (kb + 2));
+                        codes_of(kb + 2, c0);
+                    }
+                    step(a1, c1);
+                }
             }
             // decisions: lane holds site blk * 16 + col for replicas 4 grp .. 4 grp + 3,
             // one Philox block; the four bytes are transposed across the lane quad so that
@@ -217,7 +242,14 @@ __global__ __launch_bounds__(kThreads) void k_bq_slab(BqView p, int8_t *__restri
                 if (site >= ns) packed = 0u;  // padding sites stay zero
                 const uint32_t x = quad_transpose4(packed, u4);
                 *reinterpret_cast<uint32_t *>(sp + (4 * grp + u4) * pitch + out_col + blk * 16 + (col & ~3)) = x;
+                // replica 4 grp + u4's sum over these four sites, then over the block's four
+                // site quads (lanes 4 and 8 apart in the row of 16), added once per block
+                int ps = __builtin_amdgcn_sdot4((int)x, 0x01010101, 0, false);
+                ps += __builtin_amdgcn_update_dpp(0, ps, 0x124, 0xF, 0xF, false);  // row_ror:4
+                ps += __builtin_amdgcn_update_dpp(0, ps, 0x128, 0xF, 0xF, false);  // row_ror:8
+                if ((col & 12) == 0) atomicAdd(&mag_out[4 * grp + u4], ps);
             }
+            if (side == 1 && s + 1 < s_end) build_words(s + 1);  // published by the next barrier
             __syncthreads();
         }
     }
@@ -235,7 +267,7 @@ __global__ __launch_bounds__(kThreads) void k_bq_slab(BqView p, int8_t *__restri
 size_t slab_lds(const BqView &p, int width)
 {
     return (size_t)2 * p.na_p * p.nb_p / 4 + (size_t)kRS * (p.na_p + p.nb_p + 16) +
-           sizeof(uint64_t) * (size_t)(2 * width - 1);
+           2 * sizeof(uint64_t) * (size_t)(2 * width - 1);
 }
 
 }  // namespace
