@@ -71,7 +71,8 @@ def bits_ctx():
 @pytest.mark.parametrize("na,nb,R", [(600, 520, 200), (512, 1024, 130), (640, 512, 100), (520, 600, 3),
                                      (40, 40, 70)])
 def test_variant_every_replica_every_sweep(vctx, na, nb, R):
-    """Sides padded to 128 take the forced kernel; small sides keep the tuned one."""
+    """Sides padded to 128 take the forced kernel; small sides keep the tuned one (the
+    64 x 64 tile or the LDS-resident form)."""
     inst = synth.biclique_instance(na, seed=na + 3 * nb, nb=nb)
     _say("forced variant %d biclique %dx%d R=%d every sweep" % (_FORCED[vctx.value], na, nb, R))
     _every_sweep(vctx, inst, synth.beta_linear(0.05, 2.0, 8), R, seed=12)
@@ -79,7 +80,7 @@ def test_variant_every_replica_every_sweep(vctx, na, nb, R):
     if min(na, nb) >= 512:
         assert pbit.pbit_profile_variant(vctx) == _FORCED[vctx.value]
     else:
-        assert pbit.pbit_profile_variant(vctx) == 1
+        assert pbit.pbit_profile_variant(vctx) in (1, 4)
 
 
 @pytest.mark.parametrize("n,R,prefixes", [(1024, 1024, [1, 2, 10]), (4096, 1024, [1, 2]), (1024, 128, [1, 2, 10]),
@@ -95,13 +96,14 @@ def test_variant_full_size_sampled(vctx, n, R, prefixes):
 
 @pytest.mark.parametrize("na,nb,R", [(512, 512, 128), (640, 768, 100), (1024, 1024, 64)])
 def test_tuned_choice_without_the_bit_kernel(na, nb, R):
-    """At 128 replicas or fewer the tuner times the 64 x 64 and the DMA tiles
-    only; whichever it keeps is bit-exact every sweep."""
+    """At 128 replicas or fewer the tuner leaves the bit kernel out (and times the
+    LDS-resident form where the sides are at most 512); whichever it keeps is
+    bit-exact every sweep."""
     with pbit.Context(0) as c:
         inst = synth.biclique_instance(na, seed=na + nb + R, nb=nb)
         _say("tuned biclique %dx%d R=%d every sweep" % (na, nb, R))
         _every_sweep(c.ctx, inst, synth.beta_linear(0.05, 2.0, 6), R, seed=31)
-        assert pbit.pbit_profile_variant(c.ctx) in (1, 2)
+        assert pbit.pbit_profile_variant(c.ctx) in ((1, 2, 4) if max(na, nb) <= 512 else (1, 2))
 
 
 def test_bit_tiles_batched_match_oracle(bits_ctx):
