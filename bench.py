@@ -391,6 +391,10 @@ PROBES = {
     "philox": (1, 64, 50, "Philox4x32-10 words/s (the sweep's counter layout, no other work)", "words/s", None),
     "copy": (2, 1 << 30, 20, "device copy bandwidth (bytes read + written per second, 1 GiB each way)", "GB/s",
              HBM_PEAK_GBS),
+    # the spins of the EA L = 32, R = 4096 workload: 64 MiB per colour, each half-sweep reads
+    # one colour and writes the other (the pair fits the 256 MB last-level cache)
+    "copy64m": (2, 64 << 20, 50, "device copy bandwidth at the cube workload's size (64 MiB each way, "
+                "alternating direction)", "GB/s", HBM_PEAK_GBS),
     "mfma": (3, 64, 10, "int8 MFMA throughput (v_mfma_i32_32x32x32_i8 chains, operands in registers)", "TOP/s",
              INT8_MFMA_PEAK_TOPS),
 }
@@ -411,10 +415,10 @@ def probe_bench(args, pbit, name):
                  "valu_lane_ops_per_word_at_peak": VALU_PEAK_TLANEOPS * 1e12 / rate}
     res = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": reps, "warmup": 1,
            "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": {"philox": "u32", "copy": "u8", "mfma": "int8"}[name], "data": "synthetic",
+           "dtype": {"philox": "u32", "copy": "u8", "copy64m": "u8", "mfma": "int8"}[name], "data": "synthetic",
            "config": dict({"workload": "ceiling probe %s, size %d, %d launches" % (name, size, reps),
                            "work_per_launch": work}, **extra),
-           "roofline": {"bound": {"philox": "alu", "copy": "hbm", "mfma": "mfma"}[name], "achieved": value,
+           "roofline": {"bound": {"philox": "alu", "copy": "hbm", "copy64m": "hbm", "mfma": "mfma"}[name], "achieved": value,
                         "peak": peak if peak else VALU_PEAK_TLANEOPS * 1e12 / 10,
                         "unit": unit if peak else "words/s (10 lane-ops per word)",
                         "frac": value / peak if peak else rate / (VALU_PEAK_TLANEOPS * 1e12 / 10),

@@ -335,8 +335,9 @@ int pbit_profile_ea_path(pbit_ctx *ctx, int32_t *path);
  * the work one launch does:
  *   PBIT_PROBE_PHILOX  `size` Philox4x32-10 blocks per thread (the counter layout of
  *                      the sweep), 8 workgroups of 256 threads per CU; work = words drawn;
- *   PBIT_PROBE_COPY    a device copy of `size` bytes (16 bytes per thread and step);
- *                      work = bytes read plus bytes written;
+ *   PBIT_PROBE_COPY    a device copy of `size` bytes between two buffers, one 16-byte
+ *                      element per thread, each launch reading what the one before wrote;
+ *                      work = bytes read plus bytes written (at most 64 GiB);
  *   PBIT_PROBE_MFMA    `size` steps of four independent v_mfma_i32_32x32x32_i8 chains
  *                      per wave, operands in registers, 8 waves per CU; work = int8
  *                      operations (two per multiply-add).
