@@ -295,11 +295,14 @@ int pbit_profile_read(pbit_ctx *ctx, int32_t kind, double *total_ms, int64_t *la
 /* The biclique half-sweep kernel the latest biclique anneal on this context ran
  * (0 before any): 1 = 64 x 64 tiles from global memory (any side), 2 = 128 x 128
  * tiles staged in LDS by the global-to-LDS DMA (sides padded to 128), 3 = spins
- * held as bits, 64 x 256 tiles (sides padded to 128, replicas to 256).  The
- * library times the kernels the shape can take on the first anneal of a shape
- * and keeps the fastest, unless PBIT_BQ_VARIANT (1..3) names one when the context
- * is created; a named kernel the shape cannot take falls back to the timed
- * choice.  All give the same spins.  *variant is written on success only. */
+ * held as bits, tiles of 64 sites x 256, 128 or 64 replicas (sides padded to 128,
+ * replicas to 256), 4 = sides of at most 512 held in LDS with their couplings for
+ * runs of sweeps per launch.  The library times the kernels the shape can take
+ * (kernel 3 in each replica tile that divides the padded replica count) on the
+ * first anneal of a shape and keeps the fastest, unless PBIT_BQ_VARIANT (1..4)
+ * names a kernel, or PBIT_BQ_BITS_RT (64, 128, 256) a replica tile, when the
+ * context is created; a named kernel the shape cannot take falls back to the
+ * timed choice.  All give the same spins.  *variant is written on success only. */
 int pbit_profile_variant(pbit_ctx *ctx, int32_t *variant);
 
 /* Graph use of pbit_anneal_dev on this context.  With PBIT_GRAPH=1 set when the

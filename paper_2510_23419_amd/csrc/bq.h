@@ -37,8 +37,9 @@ constexpr int kMaxTableWidth = 4096;  // threshold-row entries a biclique kernel
 // Kernel variants of a biclique half-sweep.  Small: 64 x 64 tiles straight from
 // global memory (any padding); Dma: 128 x 128 tiles with K stages of 128 bytes
 // moved by the global-to-LDS DMA into a ring of 4 stages (sides padded to 128,
-// Rp a multiple of 128); Bits: 64 x 256 tiles on spins held as bits, widened for
-// the int8 MFMA (bqb_*; sides padded to 128, Rp a multiple of 256); Slab: sides of
+// Rp a multiple of 128); Bits: tiles of 64 sites x 256, 128 or 64 replicas on spins
+// held as bits, widened for the int8 MFMA (bqb_*; sides padded to 128, Rp a multiple
+// of 256); Slab: sides of
 // at most 512 sites, couplings and 16-replica slices held in LDS for runs of
 // sweeps in one launch (bq_slab).
 enum class BqVariant : int { Auto = 0, Small = 1, Dma = 2, Bits = 3, Slab = 4 };
@@ -61,7 +62,9 @@ hipError_t bqb_pack(const BqView &p, const int8_t *MA, const int8_t *MB, uint32_
                     hipStream_t st);
 hipError_t bqb_unpack(const BqView &p, const uint32_t *MAb, const uint32_t *MBb, int8_t *MA, int8_t *MB, int Rp,
                       hipStream_t st);
+// rt: replicas per tile, 64, 128 or 256; 0 (or a value that does not divide Rp): 256
+// where that gives at least 256 workgroups, else 128
 hipError_t bqb_halfsweep(const BqView &p, int side, uint32_t *MAb, uint32_t *MBb, int Rp, const uint32_t *trow,
-                         int width, uint32_t sweep, uint32_t rq0, Key key, hipStream_t st);
+                         int width, uint32_t sweep, uint32_t rq0, Key key, hipStream_t st, int rt = 0);
 
 }  // namespace pbit

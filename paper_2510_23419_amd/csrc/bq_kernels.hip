@@ -424,18 +424,23 @@ __global__ __launch_bounds__(kThreads) void k_bq_field_energy(const int8_t *__re
 // and a wave's 64 decisions form one ballot mask.
 
 constexpr int kBitsST = 64;     // sites per tile
-constexpr int kBitsRT = 256;    // replicas per tile
+constexpr int kBitsRT = 256;    // replicas per tile of the full-size form; Rp is a multiple of it
 constexpr int kBitsBlock = 128; // sites per block of the spin-word layout (four words)
-constexpr int kBitsWaves = 8;   // waves per workgroup: 4 (64 replicas each) or 8 (32 each, two per SIMD)
+constexpr int kBitsWaves = 8;   // waves per workgroup of the full-size form (32 replicas each, two per SIMD)
+constexpr int kBitsMinGroups = 256;  // workgroups (one per CU) below which the default tile shrinks
 
 // KT: K per stage, 128 (an 8-stage ring) or 256 (a 4-stage ring, half the
-// barriers per launch, for sides that are multiples of 256)
-template <int WAVES, int KT>
+// barriers per launch, for sides that are multiples of 256).  RT: replicas per
+// tile, 32 per wave; tiles of 128 and 64 replicas (four and two waves) give a
+// launch more workgroups where sides of 1024 or 2048 would fill only a quarter or
+// half of the CUs with 256.
+template <int WAVES, int KT, int RT>
 struct BitsGeom {
     static constexpr int threads = 64 * WAVES;
     static constexpr int NS = KT == 256 ? 4 : 8;          // stages in the ring
     static constexpr int jbytes = kBitsST * KT;            // coupling rows of one stage
-    static constexpr int bbytes = kBitsRT * KT / 8;        // spin words of one stage (KT / 128 blocks)
+    static constexpr int bbytes = RT * KT / 8;             // spin words of one stage (KT / 128 blocks)
+    static constexpr int bblock = 16 * RT;                 // bytes of one 128-site block of the stage's spin words
     static constexpr int stage = jbytes + bbytes;
     static constexpr int j_per_wave = jbytes / 1024 / WAVES;          // 16-byte-lane DMA instructions per wave
     static constexpr int bsz = (bbytes / WAVES) % 1024 == 0 ? 16 : 4; // bytes per lane of the spin-word DMA
@@ -443,20 +448,23 @@ struct BitsGeom {
     static constexpr int per_wave = j_per_wave + b_per_wave;
     static constexpr int ahead = per_wave * (NS - 2);
     static constexpr int ring = NS * stage;
-    static constexpr int bi = kBitsRT / WAVES / 32;  // 32-replica blocks per wave
+    static constexpr int bi = RT / WAVES / 32;  // 32-replica blocks per wave
+    static constexpr int waves_per_eu = WAVES >= 8 ? WAVES / 4 : 1;
+    static_assert(bi >= 1 && bi * WAVES * 32 == RT, "whole 32-replica blocks per wave");
     static_assert(ahead < 64, "vmcnt is a 6-bit field");
     static_assert(j_per_wave * WAVES * 1024 == jbytes && b_per_wave * WAVES * 64 * bsz == bbytes,
                   "whole DMA instructions");
 };
 
-template <int WAVES, int KT>
-__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(WAVES / 4, WAVES / 4))) void
+template <int WAVES, int KT, int RT>
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(BitsGeom<WAVES, KT, RT>::waves_per_eu,
+                                                                              BitsGeom<WAVES, KT, RT>::waves_per_eu))) void
 k_bq_halfsweep_bits(const uint32_t *__restrict__ Mob, const int8_t *__restrict__ Jb, const int32_t *__restrict__ hs2,
                     uint32_t *__restrict__ Msb, const uint32_t *__restrict__ trow, int width, int Ko, int Rp,
                     int tiles_s, int xcd_bands, uint32_t site_base, uint32_t sweep, uint32_t rq0, uint32_t k0,
                     uint32_t k1, uint32_t one)
 {
-    using G = BitsGeom<WAVES, KT>;
+    using G = BitsGeom<WAVES, KT, RT>;
     constexpr int NS = G::NS;
     constexpr int CH = KT / 16;       // 16-byte chunks per coupling row
     constexpr int kSubs = KT / 32;    // K steps per stage
@@ -489,7 +497,7 @@ k_bq_halfsweep_bits(const uint32_t *__restrict__ Mob, const int8_t *__restrict__
         ts = (int)blockIdx.x % tiles_s;
         tr = (int)blockIdx.x / tiles_s;
     }
-    const int r0 = tr * kBitsRT, s0 = ts * kBitsST;
+    const int r0 = tr * RT, s0 = ts * kBitsST;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: address math on the SALU
 
@@ -509,12 +517,12 @@ k_bq_halfsweep_bits(const uint32_t *__restrict__ Mob, const int8_t *__restrict__
         const int r = S / CH, c = (S % CH) ^ swzb(S / CH);
         offJl[j] = (uint32_t)(r * Ko + 16 * c);
     }
-    // spin words: byte o of a stage's spin area is byte o % 4096 of block o / 4096 of the
+    // spin words: byte o of a stage's spin area is byte o % bblock of block o / bblock of the
     // stage (its replicas' 16 bytes each, contiguous in the block layout)
 #pragma unroll
     for (int j = 0; j < G::b_per_wave; ++j) {
         const uint32_t o = (uint32_t)(G::bsz * (64 * (G::b_per_wave * wave + j) + lane));
-        offBl[j] = (o / 4096u) * 16u * (uint32_t)Rp + o % 4096u;
+        offBl[j] = (o / (uint32_t)G::bblock) * 16u * (uint32_t)Rp + o % (uint32_t)G::bblock;
     }
     const int8_t *Jt0 = Jb + (size_t)s0 * Ko;
     const char *Bt0 = reinterpret_cast<const char *>(Mob + (size_t)r0 * 4);
@@ -571,7 +579,7 @@ k_bq_halfsweep_bits(const uint32_t *__restrict__ Mob, const int8_t *__restrict__
         for (int bi = 0; bi < BI; ++bi)
 #pragma unroll
             for (int kb = 0; kb < KB; ++kb)
-                f.w[bi][kb] = *reinterpret_cast<const v4i *>(st + offB + 4096 * kb + 16 * 32 * bi);
+                f.w[bi][kb] = *reinterpret_cast<const v4i *>(st + offB + G::bblock * kb + 16 * 32 * bi);
 #pragma unroll
         for (int sub = 0; sub < kSubs; ++sub)
 #pragma unroll
@@ -836,23 +844,38 @@ bool bqb_supported(const BqView &p, int Rp)
            p.nb_p % kBitsBlock == 0 && Rp % kBitsRT == 0;
 }
 
-hipError_t bqb_halfsweep(const BqView &p, int side, uint32_t *MAb, uint32_t *MBb, int Rp, const uint32_t *trow,
-                         int width, uint32_t sweep, uint32_t rq0, Key key, hipStream_t st)
+// The replica tile of a launch: `rt` if it is 64, 128 or 256 and divides Rp, else 256
+// where that gives at least kBitsMinGroups workgroups and 128 elsewhere (measured at
+// R = 1024: 128 is fastest at n = 1024 and 2048, 256 at 4096; the tuner times all three)
+static int bits_rt(int tiles_s, int Rp, int rt)
 {
-    constexpr int WAVES = kBitsWaves;
-    using G1 = BitsGeom<WAVES, 128>;
-    using G2 = BitsGeom<WAVES, 256>;
-    if (!bqb_supported(p, Rp) || width < 1 || width > kMaxTableWidth) return hipErrorInvalidValue;
-    static const hipError_t lds_attr = [] {
-        const int tab = (int)sizeof(uint64_t) * (2 * kMaxTableWidth - 1);
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bq_halfsweep_bits<WAVES, 128>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, G1::ring + tab);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bq_halfsweep_bits<WAVES, 256>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, G2::ring + tab);
-        return e;
-    }();
+    if ((rt == 64 || rt == 128 || rt == 256) && Rp % rt == 0) return rt;
+    if (Rp % 256 == 0 && (int64_t)tiles_s * (Rp / 256) >= kBitsMinGroups) return 256;
+    return Rp % 128 == 0 ? 128 : 64;
+}
+
+template <int WAVES, int KT, int RT>
+static hipError_t bits_launch(const uint32_t *Mob, const int8_t *Jb, const int32_t *hs2, uint32_t *Msb,
+                              const uint32_t *trow, int width, int Ko, int Rp, int tiles_s, uint32_t site_base,
+                              uint32_t sweep, uint32_t rq0, Key key, hipStream_t st)
+{
+    using G = BitsGeom<WAVES, KT, RT>;
+    static const hipError_t lds_attr = hipFuncSetAttribute(
+        reinterpret_cast<const void *>(&k_bq_halfsweep_bits<WAVES, KT, RT>), hipFuncAttributeMaxDynamicSharedMemorySize,
+        G::ring + (int)sizeof(uint64_t) * (2 * kMaxTableWidth - 1));
     if (lds_attr != hipSuccess) return lds_attr;
+    const int bands = tiles_s % 8 == 0 ? 1 : 0;
+    const size_t tab = sizeof(uint64_t) * (size_t)(2 * width - 1);
+    const dim3 grid((unsigned)(tiles_s * (Rp / RT)));
+    hipLaunchKernelGGL((k_bq_halfsweep_bits<WAVES, KT, RT>), grid, dim3(G::threads), G::ring + tab, st, Mob, Jb, hs2,
+                       Msb, trow, width, Ko, Rp, tiles_s, bands, site_base, sweep, rq0, key.k0, key.k1, 1u);
+    return hipGetLastError();
+}
+
+hipError_t bqb_halfsweep(const BqView &p, int side, uint32_t *MAb, uint32_t *MBb, int Rp, const uint32_t *trow,
+                         int width, uint32_t sweep, uint32_t rq0, Key key, hipStream_t st, int rt)
+{
+    if (!bqb_supported(p, Rp) || width < 1 || width > kMaxTableWidth) return hipErrorInvalidValue;
     const bool A = side == 0;
     const int Ns_p = A ? p.na_p : p.nb_p, Ko = A ? p.nb_p : p.na_p;
     const uint32_t *Mob = A ? MBb : MAb;
@@ -860,17 +883,24 @@ hipError_t bqb_halfsweep(const BqView &p, int side, uint32_t *MAb, uint32_t *MBb
     const int32_t *hs2 = A ? p.hA2 : p.hB2;
     uint32_t *Msb = A ? MAb : MBb;
     const uint32_t site_base = A ? 0u : (uint32_t)p.na;
-    const int tiles_s = Ns_p / kBitsST, tiles_r = Rp / kBitsRT;
-    const int bands = tiles_s % 8 == 0 ? 1 : 0;
-    const size_t tab = sizeof(uint64_t) * (size_t)(2 * width - 1);
-    const dim3 grid((unsigned)(tiles_s * tiles_r));
-    if (Ko % 256 == 0)
-        hipLaunchKernelGGL((k_bq_halfsweep_bits<WAVES, 256>), grid, dim3(G2::threads), G2::ring + tab, st, Mob, Jb, hs2,
-                           Msb, trow, width, Ko, Rp, tiles_s, bands, site_base, sweep, rq0, key.k0, key.k1, 1u);
-    else
-        hipLaunchKernelGGL((k_bq_halfsweep_bits<WAVES, 128>), grid, dim3(G1::threads), G1::ring + tab, st, Mob, Jb, hs2,
-                           Msb, trow, width, Ko, Rp, tiles_s, bands, site_base, sweep, rq0, key.k0, key.k1, 1u);
-    return hipGetLastError();
+    const int tiles_s = Ns_p / kBitsST;
+    // two waves cannot take a 256-deep stage (its DMA needs more than four 16-byte
+    // loads per lane), so 64-replica tiles always stage 128
+    switch (bits_rt(tiles_s, Rp, rt)) {
+    case 256:
+        return Ko % 256 == 0 ? bits_launch<kBitsWaves, 256, 256>(Mob, Jb, hs2, Msb, trow, width, Ko, Rp, tiles_s,
+                                                                  site_base, sweep, rq0, key, st)
+                             : bits_launch<kBitsWaves, 128, 256>(Mob, Jb, hs2, Msb, trow, width, Ko, Rp, tiles_s,
+                                                                  site_base, sweep, rq0, key, st);
+    case 128:
+        return Ko % 256 == 0 ? bits_launch<4, 256, 128>(Mob, Jb, hs2, Msb, trow, width, Ko, Rp, tiles_s, site_base,
+                                                         sweep, rq0, key, st)
+                             : bits_launch<4, 128, 128>(Mob, Jb, hs2, Msb, trow, width, Ko, Rp, tiles_s, site_base,
+                                                         sweep, rq0, key, st);
+    default:
+        return bits_launch<2, 128, 64>(Mob, Jb, hs2, Msb, trow, width, Ko, Rp, tiles_s, site_base, sweep, rq0, key,
+                                       st);
+    }
 }
 
 hipError_t bq_energy(const BqView &p, const int8_t *MA, const int8_t *MB, int R, int Rp, int32_t *E, hipStream_t st)

@@ -129,6 +129,7 @@ extern "C" int pbit_create(pbit_ctx **out, int device, uint64_t hbm_budget_bytes
         const int k = std::atoi(v);
         if (k >= 1 && k <= 4) ctx->bq_forced = (BqVariant)k;
     }
+    if (const char *v = std::getenv("PBIT_BQ_BITS_RT")) ctx->bq_bits_rt = std::atoi(v);  // tuning override
     if (const char *v = std::getenv("PBIT_EA_STREAM")) ctx->ea_stream_forced = std::atoi(v) != 0;
     if (const char *v = std::getenv("PBIT_EA_ROWS")) ctx->ea_rows = std::max(0, std::atoi(v));  // tuning override
     if (const char *v = std::getenv("PBIT_GRAPH")) ctx->use_graph = std::atoi(v) != 0;
@@ -639,6 +640,7 @@ struct DevState {
     int32_t *E32 = nullptr;
     int8_t *stage = nullptr;  // [R][N] host-layout staging
     BqVariant variant = BqVariant::Auto;
+    int bits_rt = 0;  // replicas per tile of the bit kernel (0: its launcher's rule)
     bool slab = false;        // cube held in LDS for runs of sweeps (ea_slab)
     bool mfma = false;        // cube fields on the matrix cores (ea_mfma.hip), spins [2][Rp][N / 2]
     Arena *arena = nullptr;   // set: buffers are carved from it (no allocation, no kernel timing)
@@ -671,6 +673,7 @@ static int tune_biclique(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStrea
     const bool large = P.bq.na_p % 128 == 0 && P.bq.nb_p % 128 == 0;
     const bool slab_ok = bq_slab_supported(P.bq, ds.Rp, ds.width);
     const BqVariant f = ctx->bq_forced;
+    ds.bits_rt = ctx->bq_bits_rt;
     if (f == BqVariant::Small || (f == BqVariant::Dma && large) || (f == BqVariant::Bits && ds.MAb) ||
         (f == BqVariant::Slab && slab_ok)) {
         ds.variant = f;  // a forced kernel the shape cannot take falls back to the tuned choice
@@ -679,12 +682,13 @@ static int tune_biclique(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStrea
     const std::array<int, 4> shape{P.bq.na_p, P.bq.nb_p, ds.Rp, slab_ok ? 1 : 0};
     auto it = ctx->bq_tuned.find(shape);
     if (it != ctx->bq_tuned.end()) {
-        ds.variant = it->second;
+        ds.variant = it->second.first;
+        ds.bits_rt = it->second.second;
         return PBIT_OK;
     }
     if (!large && !slab_ok) {
         ds.variant = BqVariant::Small;
-        ctx->bq_tuned[shape] = ds.variant;
+        ctx->bq_tuned[shape] = {ds.variant, ds.bits_rt};
         return PBIT_OK;
     }
     if (ds.arena) {
@@ -706,9 +710,14 @@ static int tune_biclique(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStrea
     const int S = std::max(1, n_sweeps), m = std::min(8, S - 1);
     float best_ms = 0.f;
     BqVariant best = BqVariant::Small;
+    int best_rt = ds.bits_rt;
     bool have = false;
-    auto time_it = [&](BqVariant v, int slab_sweeps, float *ms) {
-        for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // first pass warms up
+    int rt = ds.bits_rt;  // the bit kernel's replica tile being timed
+    // one warm-up pass, then the best of three (a profiler's tracing stretches single launches)
+    auto time_it = [&](BqVariant v, int slab_sweeps, float *best_pass) {
+        *best_pass = 0.f;
+        for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
+            float one_pass = 0.f, *ms = &one_pass;
             e = hipEventRecord(e0, st);
             if (v == BqVariant::Slab) {
                 if (e == hipSuccess)
@@ -716,18 +725,33 @@ static int tune_biclique(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStrea
             } else {
                 for (int k = 0; k < 4 && e == hipSuccess; ++k)
                     e = v == BqVariant::Bits
-                            ? bqb_halfsweep(P.bq, k & 1, ds.MAb, ds.MBb, ds.Rp, ds.table, ds.width, 0u, 0u, key, st)
+                            ? bqb_halfsweep(P.bq, k & 1, ds.MAb, ds.MBb, ds.Rp, ds.table, ds.width, 0u, 0u, key, st,
+                                            rt)
                             : bq_halfsweep(P.bq, k & 1, ds.MA, ds.MB, ds.R, ds.Rp, ds.table, ds.width, 0u, 0u, key,
                                            st, v);
             }
             if (e == hipSuccess) e = hipEventRecord(e1, st);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+            if (rep == 1 || (rep > 1 && one_pass < *best_pass)) *best_pass = one_pass;
         }
     };
+    // the bit kernel in each replica tile that divides Rp (unless one is forced): more
+    // tiles fill more CUs, larger ones read the couplings fewer times
+    std::vector<std::pair<BqVariant, int>> runs;
     for (BqVariant v : cand) {
         if ((v == BqVariant::Dma && !large) || (v == BqVariant::Bits && !ds.MAb) || (v == BqVariant::Slab && !slab_ok))
             continue;  // the shape cannot take it
+        if (v == BqVariant::Bits && ds.bits_rt == 0) {
+            for (int w : {256, 128, 64})
+                if (ds.Rp % w == 0) runs.push_back({v, w});
+        } else {
+            runs.push_back({v, ds.bits_rt});
+        }
+    }
+    for (const auto &run : runs) {
+        const BqVariant v = run.first;
+        rt = run.second;
         float ms = 0.f;
         if (v == BqVariant::Slab) {
             float t1 = 0.f, t2 = 0.f;
@@ -744,6 +768,7 @@ static int tune_biclique(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStrea
         if (!have || ms < best_ms) {
             best_ms = ms;
             best = v;
+            best_rt = rt;
             have = true;
         }
     }
@@ -751,7 +776,8 @@ static int tune_biclique(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStrea
     (void)hipEventDestroy(e1);
     if (e != hipSuccess) return device_fail(ctx, e, "biclique kernel tuning");
     ds.variant = best;
-    ctx->bq_tuned[shape] = best;
+    if (best == BqVariant::Bits) ds.bits_rt = best_rt;
+    ctx->bq_tuned[shape] = {ds.variant, ds.bits_rt};
     return PBIT_OK;
 }
 
@@ -929,7 +955,7 @@ static hipError_t sweep(pbit_ctx *ctx, const Problem &P, DevState &ds, int s, ui
         else if (P.kind == PBIT_GRAPH)
             e = graph_halfsweep(P.graph, c, ds.spins, ds.Rp, row, ds.width, t, rq0, key, st);
         else if (ds.bits)
-            e = bqb_halfsweep(P.bq, c, ds.MAb, ds.MBb, ds.Rp, row, ds.width, t, rq0, key, st);
+            e = bqb_halfsweep(P.bq, c, ds.MAb, ds.MBb, ds.Rp, row, ds.width, t, rq0, key, st, ds.bits_rt);
         else
             e = bq_halfsweep(P.bq, c, ds.MA, ds.MB, ds.R, ds.Rp, row, ds.width, t, rq0, key, st, ds.variant);
         if (e == hipSuccess) e = prof_count_launch(ctx, st);

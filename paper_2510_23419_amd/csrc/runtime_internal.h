@@ -73,6 +73,7 @@ struct pbit_ctx {
     // biclique kernel variant: forced (PBIT_BQ_VARIANT) or autotuned per shape
     pbit::BqVariant bq_forced = pbit::BqVariant::Auto;
     int bq_last_variant = 0;  // biclique half-sweep variant of the latest biclique anneal (0: none yet)
+    int bq_bits_rt = 0;       // replicas per tile of the bit kernel (PBIT_BQ_BITS_RT: 64, 128, 256; 0 = by size)
     bool ea_stream_forced = false;  // cubes always take the streaming stencil (PBIT_EA_STREAM=1)
     int ea_rows = 0;                // lattice rows per workgroup of the streaming stencil (PBIT_EA_ROWS; 0 = default)
     int ea_mfma = -1;  // matrix-core cube half-sweep: -1 timed against the stencil, 1 every cube, 0 none (PBIT_EA_MFMA)
@@ -84,7 +85,8 @@ struct pbit_ctx {
     uint64_t graph_key = 0;
     int64_t graph_captures = 0, graph_launches = 0;
     int ea_last_path = 0;           // cube path of the latest cube anneal: 1 stream, 2 LDS-resident (0: none)
-    std::map<std::array<int, 4>, pbit::BqVariant> bq_tuned;  // (na_p, nb_p, Rp, LDS form possible) -> fastest
+    // (na_p, nb_p, Rp, LDS form possible) -> fastest kernel and, for the bit kernel, its replica tile
+    std::map<std::array<int, 4>, std::pair<pbit::BqVariant, int>> bq_tuned;
 };
 
 namespace pbit {

@@ -7,7 +7,8 @@ default is:
 * 2: 128 x 128 int8 tiles staged by the global-to-LDS DMA (sides padded to 128);
 * 3: spins held as bits, widened to bytes for the int8 MFMA; the field is the
   site's field plus its coupling sum minus twice the product (sides padded to
-  128; a forced bit kernel pads the replicas to 256).  The batched engine's bit
+  128; a forced bit kernel pads the replicas to 256), in tiles of 256, 128 or 64
+  replicas (each forced through PBIT_BQ_BITS_RT too).  The batched engine's bit
   tiles run under this variant too;
 * 4: sides of at most 512 sites held in LDS with their couplings (two-bit codes of
   J + 1 in both orientations) for runs of sweeps in one launch, 16 replicas per
@@ -84,7 +85,7 @@ def test_variant_every_replica_every_sweep(vctx, na, nb, R):
 
 
 @pytest.mark.parametrize("n,R,prefixes", [(1024, 1024, [1, 2, 10]), (4096, 1024, [1, 2]), (1024, 128, [1, 2, 10]),
-                                          (2048, 96, [1, 3])])
+                                          (2048, 96, [1, 3]), (2048, 1024, [1, 2])])
 def test_variant_full_size_sampled(vctx, n, R, prefixes):
     """K_{n,n}, beta linear 0.05 -> 2.0 over 2000 sweeps."""
     inst = synth.biclique_instance(n, seed=n)
@@ -92,6 +93,34 @@ def test_variant_full_size_sampled(vctx, n, R, prefixes):
     _say("forced variant %d K_%d R=%d sampled" % (_FORCED[vctx.value], n, R))
     _check_sampled(vctx, inst, beta, R, 1, prefixes, [0], np.random.default_rng(n + R))
     assert pbit.pbit_profile_variant(vctx) == _FORCED[vctx.value]
+
+
+@pytest.fixture(scope="module", params=["64", "128", "256"], ids=["rt64", "rt128", "rt256"])
+def rt_ctx(request):
+    """The bit kernel forced, with its replica tile forced too (PBIT_BQ_BITS_RT)."""
+    old = os.environ.get("PBIT_BQ_BITS_RT")
+    os.environ["PBIT_BQ_BITS_RT"] = request.param
+    try:
+        c = _forced_context("3")
+    finally:
+        if old is None:
+            del os.environ["PBIT_BQ_BITS_RT"]
+        else:
+            os.environ["PBIT_BQ_BITS_RT"] = old
+    yield c.ctx, int(request.param)
+    c.close()
+
+
+@pytest.mark.parametrize("na,nb,R", [(600, 520, 200), (512, 1024, 300), (640, 512, 70), (768, 896, 300)])
+def test_bit_tile_widths_every_replica_every_sweep(rt_ctx, na, nb, R):
+    """The bit kernel in each of its replica tiles (256 replicas on eight waves, 128 on
+    four, 64 on two), with stages of 256 K where a side is a multiple of 256 and 128
+    elsewhere, several replica tiles per launch: every replica after every sweep."""
+    ctx, rt = rt_ctx
+    inst = synth.biclique_instance(na, seed=na + 7 * nb + R, nb=nb)
+    _say("bit kernel, %d-replica tiles, biclique %dx%d R=%d every sweep" % (rt, na, nb, R))
+    _every_sweep(ctx, inst, synth.beta_linear(0.05, 2.0, 6), R, seed=23)
+    assert pbit.pbit_profile_variant(ctx) == 3
 
 
 @pytest.mark.parametrize("na,nb,R", [(512, 512, 128), (640, 768, 100), (1024, 1024, 64)])
