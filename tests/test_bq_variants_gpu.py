@@ -53,6 +53,17 @@ def _forced_context(variant):
     return c
 
 
+def _biclique_with_zeros(na, nb, seed):
+    """Couplings in {-1, 0, +1}, about a third of them zero (the diluted form the
+    problem statement allows), and fields in {-1, 0, +1}: the middle value of the
+    two-bit coupling codes occurs only here."""
+    inst = synth.biclique_instance(na, seed=seed, nb=nb)
+    rng = np.random.default_rng(seed + 1)
+    inst["J"] = (inst["J"] * (rng.random(inst["J"].shape) < 0.65)).astype(np.int8)
+    assert (inst["J"] == 0).any() and (inst["J"] == 1).any() and (inst["J"] == -1).any()
+    return inst
+
+
 @pytest.fixture(scope="module", params=["1", "2", "3"], ids=["small", "int8dma", "bits"])
 def vctx(request):
     """A context whose biclique kernels run the forced variant (read when the
@@ -82,6 +93,15 @@ def test_variant_every_replica_every_sweep(vctx, na, nb, R):
         assert pbit.pbit_profile_variant(vctx) == _FORCED[vctx.value]
     else:
         assert pbit.pbit_profile_variant(vctx) in (1, 4)
+
+
+@pytest.mark.parametrize("na,nb,R", [(600, 520, 70), (512, 640, 40)])
+def test_variant_zero_couplings_every_sweep(vctx, na, nb, R):
+    """Diluted couplings through the forced kernel: every replica after every sweep."""
+    inst = _biclique_with_zeros(na, nb, seed=na + 11 * nb + R)
+    _say("forced variant %d diluted biclique %dx%d R=%d every sweep" % (_FORCED[vctx.value], na, nb, R))
+    _every_sweep(vctx, inst, synth.beta_linear(0.05, 2.0, 8), R, seed=19)
+    assert pbit.pbit_profile_variant(vctx) == _FORCED[vctx.value]
 
 
 @pytest.mark.parametrize("n,R,prefixes", [(1024, 1024, [1, 2, 10]), (4096, 1024, [1, 2]), (1024, 128, [1, 2, 10]),
@@ -203,6 +223,38 @@ def test_slab_every_replica_every_sweep(slab_ctx, na, nb, R):
     _say("slab biclique %dx%d R=%d every sweep" % (na, nb, R))
     _every_sweep(slab_ctx, inst, synth.beta_linear(0.05, 2.0, 10), R, seed=17)
     assert (pbit.pbit_profile_variant(slab_ctx) == 4) == (max(na, nb) <= 512)
+
+
+@pytest.mark.parametrize("na,nb,R", [(300, 200, 40), (512, 512, 33), (70, 130, 17)])
+def test_slab_zero_couplings_every_sweep(slab_ctx, na, nb, R):
+    """Diluted couplings (code 1 of the two-bit codes) in the LDS-resident form."""
+    inst = _biclique_with_zeros(na, nb, seed=na + 13 * nb + R)
+    _say("slab diluted biclique %dx%d R=%d every sweep" % (na, nb, R))
+    _every_sweep(slab_ctx, inst, synth.beta_linear(0.05, 2.0, 10), R, seed=29)
+    assert pbit.pbit_profile_variant(slab_ctx) == 4
+
+
+@pytest.mark.parametrize("mode", ["3", None], ids=["bit_tiles", "int8_tiles"])
+def test_batched_tiles_zero_couplings(mode):
+    """Diluted bicliques through the batched tiles, with the spins as bits (forced) and
+    as int8 rows with two-bit coupling codes (default): every job equals the oracle."""
+    c = _forced_context(mode) if mode else pbit.Context(0)
+    try:
+        jobs = []
+        for k, (na, nb, R) in enumerate([(40, 40, 9), (130, 70, 33), (200, 260, 64), (520, 300, 40)]):
+            inst = _biclique_with_zeros(na, nb, seed=60 + k)
+            jobs.append(dict(inst=inst, beta=synth.beta_linear(0.05, 2.0, 12 + k), R=R, seed=500 + k))
+        probs = [pbit.load_instance(c.ctx, j["inst"]) for j in jobs]
+        _say("batched tiles (%s), %d diluted bicliques" % ("bits" if mode else "int8", len(jobs)))
+        outs = pbit.pbit_anneal_batch(c.ctx, [dict(problem=p, beta=j["beta"], n_replicas=j["R"], seed=j["seed"])
+                                              for p, j in zip(probs, jobs)])
+        for p, j, o in zip(probs, jobs, outs):
+            ref = oracle.anneal(graph_of(j["inst"]), j["beta"], j["R"], j["seed"])
+            assert np.array_equal(o.spins, ref.spins), j["inst"]["dims"]
+            assert np.array_equal(o.energies, ref.energies), j["inst"]["dims"]
+            pbit.pbit_unload_problem(c.ctx, p)
+    finally:
+        c.close()
 
 
 @pytest.mark.parametrize("n,R,prefixes", [(512, 1024, [1, 2, 10, 1500]), (256, 96, [3, 1200]), (448, 2000, [2, 40])])

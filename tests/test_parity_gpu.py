@@ -96,6 +96,9 @@ def test_ea_energy_matches_oracle(ctx, dims, R):
 @pytest.mark.parametrize("R", [1, 63, 65, 130])
 def test_biclique_energy_matches_oracle(ctx, na, nb, R):
     inst = synth.biclique_instance(na, seed=na * 7 + nb, nb=nb)
+    if R % 2:  # couplings in {-1, 0, +1} for the odd replica counts
+        keep = np.random.default_rng(na + nb).random(inst["J"].shape) < 0.65
+        inst["J"] = (inst["J"] * keep).astype(np.int8)
     prob = pbit.load_instance(ctx, inst)
     spins = synth.random_spins(R, na + nb, seed=R + na)
     _say("biclique energy %dx%d R=%d" % (na, nb, R))
