@@ -53,11 +53,11 @@ def _forced_context(variant):
     return c
 
 
-def _biclique_with_zeros(na, nb, seed):
+def _biclique_with_zeros(na, nb, seed, field="uniform3"):
     """Couplings in {-1, 0, +1}, about a third of them zero (the diluted form the
-    problem statement allows), and fields in {-1, 0, +1}: the middle value of the
-    two-bit coupling codes occurs only here."""
-    inst = synth.biclique_instance(na, seed=seed, nb=nb)
+    problem statement allows), and fields in {-1, 0, +1} or none: the middle value
+    of the two-bit coupling codes occurs only here."""
+    inst = synth.biclique_instance(na, seed=seed, nb=nb, field=field)
     rng = np.random.default_rng(seed + 1)
     inst["J"] = (inst["J"] * (rng.random(inst["J"].shape) < 0.65)).astype(np.int8)
     assert (inst["J"] == 0).any() and (inst["J"] == 1).any() and (inst["J"] == -1).any()
@@ -95,10 +95,11 @@ def test_variant_every_replica_every_sweep(vctx, na, nb, R):
         assert pbit.pbit_profile_variant(vctx) in (1, 4)
 
 
-@pytest.mark.parametrize("na,nb,R", [(600, 520, 70), (512, 640, 40)])
-def test_variant_zero_couplings_every_sweep(vctx, na, nb, R):
-    """Diluted couplings through the forced kernel: every replica after every sweep."""
-    inst = _biclique_with_zeros(na, nb, seed=na + 11 * nb + R)
+@pytest.mark.parametrize("na,nb,R,field", [(600, 520, 70, "uniform3"), (512, 640, 40, "zero")])
+def test_variant_zero_couplings_every_sweep(vctx, na, nb, R, field):
+    """Diluted couplings through the forced kernel, with fields and without (h = NULL):
+    every replica after every sweep."""
+    inst = _biclique_with_zeros(na, nb, seed=na + 11 * nb + R, field=field)
     _say("forced variant %d diluted biclique %dx%d R=%d every sweep" % (_FORCED[vctx.value], na, nb, R))
     _every_sweep(vctx, inst, synth.beta_linear(0.05, 2.0, 8), R, seed=19)
     assert pbit.pbit_profile_variant(vctx) == _FORCED[vctx.value]
@@ -225,10 +226,12 @@ def test_slab_every_replica_every_sweep(slab_ctx, na, nb, R):
     assert (pbit.pbit_profile_variant(slab_ctx) == 4) == (max(na, nb) <= 512)
 
 
-@pytest.mark.parametrize("na,nb,R", [(300, 200, 40), (512, 512, 33), (70, 130, 17)])
-def test_slab_zero_couplings_every_sweep(slab_ctx, na, nb, R):
-    """Diluted couplings (code 1 of the two-bit codes) in the LDS-resident form."""
-    inst = _biclique_with_zeros(na, nb, seed=na + 13 * nb + R)
+@pytest.mark.parametrize("na,nb,R,field", [(300, 200, 40, "uniform3"), (512, 512, 33, "uniform3"),
+                                           (70, 130, 17, "zero")])
+def test_slab_zero_couplings_every_sweep(slab_ctx, na, nb, R, field):
+    """Diluted couplings (code 1 of the two-bit codes) in the LDS-resident form, with
+    fields and without."""
+    inst = _biclique_with_zeros(na, nb, seed=na + 13 * nb + R, field=field)
     _say("slab diluted biclique %dx%d R=%d every sweep" % (na, nb, R))
     _every_sweep(slab_ctx, inst, synth.beta_linear(0.05, 2.0, 10), R, seed=29)
     assert pbit.pbit_profile_variant(slab_ctx) == 4
@@ -242,7 +245,7 @@ def test_batched_tiles_zero_couplings(mode):
     try:
         jobs = []
         for k, (na, nb, R) in enumerate([(40, 40, 9), (130, 70, 33), (200, 260, 64), (520, 300, 40)]):
-            inst = _biclique_with_zeros(na, nb, seed=60 + k)
+            inst = _biclique_with_zeros(na, nb, seed=60 + k, field="zero" if k == 1 else "uniform3")
             jobs.append(dict(inst=inst, beta=synth.beta_linear(0.05, 2.0, 12 + k), R=R, seed=500 + k))
         probs = [pbit.load_instance(c.ctx, j["inst"]) for j in jobs]
         _say("batched tiles (%s), %d diluted bicliques" % ("bits" if mode else "int8", len(jobs)))
