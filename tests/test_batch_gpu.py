@@ -62,6 +62,25 @@ def test_batch_matches_oracle(ctx):
         pbit.pbit_unload_problem(ctx, p)
 
 
+@pytest.mark.parametrize("sched", ["zero", "cold", "mixed"])
+def test_batch_extreme_betas(ctx, sched):
+    """The small mix at the ends of the schedule range (beta = 0 only, large beta only,
+    both interleaved): each tile kind builds its decision words from rows of every
+    width."""
+    from tests.test_parity_gpu import EXTREME_BETAS
+    beta = np.array(EXTREME_BETAS[sched])
+    jobs = _small_mix(seed=3)
+    probs = [pbit.load_instance(ctx, j["inst"]) for j in jobs]
+    _say("batch of %d small jobs, beta %s" % (len(jobs), sched))
+    outs = pbit.pbit_anneal_batch(ctx, [dict(problem=p, beta=beta, n_replicas=j["R"], seed=j["seed"])
+                                        for p, j in zip(probs, jobs)])
+    for p, j, o in zip(probs, jobs, outs):
+        ref = oracle.anneal(graph_of(j["inst"]), beta, j["R"], j["seed"])
+        assert np.array_equal(o.spins, ref.spins), j["inst"]["dims"]
+        assert np.array_equal(o.energies, ref.energies), j["inst"]["dims"]
+        pbit.pbit_unload_problem(ctx, p)
+
+
 def _oracle_groups(inst, beta, R, seed, got, groups):
     """Replica groups of a result against the oracle run on those replicas alone
     (replica_offset): the counters use the global replica index, so a slice of

@@ -27,7 +27,7 @@ import pytest
 import synth
 from oracle import oracle
 from paper_2510_23419_amd import pbit
-from tests.test_parity_gpu import _check_sampled, _every_sweep, graph_of
+from tests.test_parity_gpu import EXTREME_BETAS, _check_sampled, _every_sweep, graph_of
 
 pytestmark = pytest.mark.gpu
 
@@ -102,6 +102,16 @@ def test_variant_zero_couplings_every_sweep(vctx, na, nb, R, field):
     inst = _biclique_with_zeros(na, nb, seed=na + 11 * nb + R, field=field)
     _say("forced variant %d diluted biclique %dx%d R=%d every sweep" % (_FORCED[vctx.value], na, nb, R))
     _every_sweep(vctx, inst, synth.beta_linear(0.05, 2.0, 8), R, seed=19)
+    assert pbit.pbit_profile_variant(vctx) == _FORCED[vctx.value]
+
+
+@pytest.mark.parametrize("sched", sorted(EXTREME_BETAS))
+def test_variant_extreme_betas(vctx, sched):
+    """beta = 0 only (threshold rows as wide as the largest field), large beta only
+    (rows of two entries) and both interleaved, through the forced kernel."""
+    inst = _biclique_with_zeros(520, 600, seed=77)
+    _say("forced variant %d biclique 520x600 beta %s" % (_FORCED[vctx.value], sched))
+    _every_sweep(vctx, inst, np.array(EXTREME_BETAS[sched]), 40, seed=43)
     assert pbit.pbit_profile_variant(vctx) == _FORCED[vctx.value]
 
 
@@ -234,6 +244,16 @@ def test_slab_zero_couplings_every_sweep(slab_ctx, na, nb, R, field):
     inst = _biclique_with_zeros(na, nb, seed=na + 13 * nb + R, field=field)
     _say("slab diluted biclique %dx%d R=%d every sweep" % (na, nb, R))
     _every_sweep(slab_ctx, inst, synth.beta_linear(0.05, 2.0, 10), R, seed=29)
+    assert pbit.pbit_profile_variant(slab_ctx) == 4
+
+
+@pytest.mark.parametrize("sched", sorted(EXTREME_BETAS))
+def test_slab_extreme_betas(slab_ctx, sched):
+    """The LDS-resident form at the ends of the schedule range (its decision words are
+    built from each sweep's threshold row in LDS)."""
+    inst = _biclique_with_zeros(130, 70, seed=78)
+    _say("slab biclique 130x70 beta %s" % sched)
+    _every_sweep(slab_ctx, inst, np.array(EXTREME_BETAS[sched]), 21, seed=47)
     assert pbit.pbit_profile_variant(slab_ctx) == 4
 
 

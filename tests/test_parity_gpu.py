@@ -126,6 +126,24 @@ def _every_sweep(ctx, inst, beta, R, seed, init=None):
     return got
 
 
+# schedules at the ends of the threshold table: beta = 0 (every update a fair coin, rows
+# as wide as the largest field), large beta only (rows of two entries: every |I| >= 1
+# clamps to the last, zero, threshold) and the two interleaved
+EXTREME_BETAS = {"zero": [0.0, 0.0, 0.0], "cold": [25.0, 30.0, 40.0, 25.0],
+                 "mixed": [0.0, 30.0, 0.4, 0.0, 50.0]}
+
+
+@pytest.mark.parametrize("sched", sorted(EXTREME_BETAS))
+@pytest.mark.parametrize("dims,R", [((8, 8, 8), 37), ((6, 4, 2), 5)])
+def test_ea_extreme_betas(ectx, sched, dims, R):
+    """Every replica after every sweep at the ends of the schedule range, on each cube
+    path, with fields and zero couplings."""
+    inst = _ea_with_zeros(dims, seed=5 * R + sum(dims))
+    _say("ea %s R=%d beta %s (%s)" % (dims, R, sched, ectx.mode))
+    _every_sweep(ectx.ctx, inst, np.array(EXTREME_BETAS[sched]), R, seed=41)
+    _check_path(ectx, inst)
+
+
 def test_ea_L6_every_replica_every_sweep(ectx):
     """EA L=6 (216 spins), +-1 couplings, h = 0, 64 replicas from random starts,
     beta linear 0.1 -> 3.0 over 1000 sweeps, seed 1."""
