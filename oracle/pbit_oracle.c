@@ -188,7 +188,7 @@ int oracle_anneal(int32_t n, int32_t n_bonds, const int32_t *bi, const int32_t *
     int rc = ORACLE_OK;
     int32_t n_snap = trace_every > 0 ? n_sweeps / trace_every : 0;
     for (int32_t r = 0; r < R && rc == ORACLE_OK; ++r) {
-        uint32_t rg = (uint32_t)(replica_offset + r);
+        uint32_t rg = (uint32_t)replica_offset + (uint32_t)r;  /* global replica index, 32 bits */
         if (init_spins) {
             memcpy(m, init_spins + (size_t)r * n, (size_t)n);
         } else {
@@ -197,7 +197,7 @@ int oracle_anneal(int32_t n, int32_t n_bonds, const int32_t *bi, const int32_t *
         }
         int64_t e = energy_one(n, n_bonds, bi, bj, bJ, h, m);
         for (int32_t s = 0; s < n_sweeps; ++s) {
-            uint32_t t = (uint32_t)(sweep_offset + s);
+            uint32_t t = (uint32_t)sweep_offset + (uint32_t)s;  /* absolute sweep, 32 bits */
             const uint32_t *row = table + (size_t)s * width;
             for (int32_t c = 0; c < n_colours; ++c) {
                 for (int32_t k = 0; k < n; ++k) {

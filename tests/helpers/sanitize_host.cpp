@@ -121,6 +121,12 @@ int main()
         CHECK(oracle_anneal(n, (int32_t)bi.size(), bi.data(), bj.data(), bJ.data(), h.data(), colour.data(), 3,
                             beta.data(), S, 4, R, 8, rng(), nullptr, nullptr, spins.data(), en.data(), every,
                             etrace.data(), strace.data()) == 0);
+        // counters past 31 bits: absolute sweeps from 2^31 - 3, replicas from 2^31 - 64
+        std::vector<int8_t> spins_hi((size_t)R * n);
+        std::vector<int64_t> en_hi((size_t)R);
+        CHECK(oracle_anneal(n, (int32_t)bi.size(), bi.data(), bj.data(), bJ.data(), h.data(), colour.data(), 3,
+                            beta.data(), S, 2147483645, R, 2147483584, rng(), nullptr, nullptr, spins_hi.data(),
+                            en_hi.data(), 0, nullptr, nullptr) == 0);
         std::vector<int64_t> en2((size_t)R);
         CHECK(oracle_energy(n, (int32_t)bi.size(), bi.data(), bj.data(), bJ.data(), h.data(), spins.data(), R,
                             en2.data()) == 0);
