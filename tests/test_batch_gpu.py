@@ -81,6 +81,24 @@ def test_batch_extreme_betas(ctx, sched):
         pbit.pbit_unload_problem(ctx, p)
 
 
+def test_batch_counters_past_31_bits(ctx):
+    """The small mix with sweep and replica counters near the top of their 32-bit range
+    (the absolute sweep index crosses 2^31 during the run)."""
+    from tests.test_parity_gpu import HIGH_REPLICA, HIGH_SWEEP
+    jobs = _small_mix(seed=4)
+    probs = [pbit.load_instance(ctx, j["inst"]) for j in jobs]
+    _say("batch of %d small jobs, counters past 31 bits" % len(jobs))
+    outs = pbit.pbit_anneal_batch(ctx, [dict(problem=p, beta=j["beta"], n_replicas=j["R"], seed=j["seed"],
+                                             sweep_offset=HIGH_SWEEP - 2, replica_offset=HIGH_REPLICA)
+                                        for p, j in zip(probs, jobs)])
+    for p, j, o in zip(probs, jobs, outs):
+        ref = oracle.anneal(graph_of(j["inst"]), j["beta"], j["R"], j["seed"], sweep_offset=HIGH_SWEEP - 2,
+                            replica_offset=HIGH_REPLICA)
+        assert np.array_equal(o.spins, ref.spins), j["inst"]["dims"]
+        assert np.array_equal(o.energies, ref.energies), j["inst"]["dims"]
+        pbit.pbit_unload_problem(ctx, p)
+
+
 def _oracle_groups(inst, beta, R, seed, got, groups):
     """Replica groups of a result against the oracle run on those replicas alone
     (replica_offset): the counters use the global replica index, so a slice of

@@ -27,7 +27,7 @@ import pytest
 import synth
 from oracle import oracle
 from paper_2510_23419_amd import pbit
-from tests.test_parity_gpu import EXTREME_BETAS, _check_sampled, _every_sweep, graph_of
+from tests.test_parity_gpu import EXTREME_BETAS, HIGH_REPLICA, HIGH_SWEEP, _check_sampled, _every_sweep, graph_of
 
 pytestmark = pytest.mark.gpu
 
@@ -112,6 +112,16 @@ def test_variant_extreme_betas(vctx, sched):
     inst = _biclique_with_zeros(520, 600, seed=77)
     _say("forced variant %d biclique 520x600 beta %s" % (_FORCED[vctx.value], sched))
     _every_sweep(vctx, inst, np.array(EXTREME_BETAS[sched]), 40, seed=43)
+    assert pbit.pbit_profile_variant(vctx) == _FORCED[vctx.value]
+
+
+def test_variant_counters_past_31_bits(vctx):
+    """Sweep and replica counters near the top of their 32-bit range through the forced
+    kernel."""
+    inst = _biclique_with_zeros(520, 600, seed=79)
+    _say("forced variant %d biclique 520x600 counters past 31 bits" % _FORCED[vctx.value])
+    _every_sweep(vctx, inst, synth.beta_linear(0.05, 2.0, 6), 40, seed=59, sweep_offset=HIGH_SWEEP,
+                 replica_offset=HIGH_REPLICA)
     assert pbit.pbit_profile_variant(vctx) == _FORCED[vctx.value]
 
 
@@ -254,6 +264,15 @@ def test_slab_extreme_betas(slab_ctx, sched):
     inst = _biclique_with_zeros(130, 70, seed=78)
     _say("slab biclique 130x70 beta %s" % sched)
     _every_sweep(slab_ctx, inst, np.array(EXTREME_BETAS[sched]), 21, seed=47)
+    assert pbit.pbit_profile_variant(slab_ctx) == 4
+
+
+def test_slab_counters_past_31_bits(slab_ctx):
+    """The LDS-resident form (runs of sweeps in one launch) with its counters past 31 bits."""
+    inst = _biclique_with_zeros(130, 70, seed=80)
+    _say("slab biclique 130x70 counters past 31 bits")
+    _every_sweep(slab_ctx, inst, synth.beta_linear(0.05, 2.0, 6), 21, seed=61, sweep_offset=HIGH_SWEEP,
+                 replica_offset=HIGH_REPLICA)
     assert pbit.pbit_profile_variant(slab_ctx) == 4
 
 

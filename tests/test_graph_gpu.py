@@ -36,11 +36,12 @@ def _with_zeros(g, frac, seed):
     return g
 
 
-def _every_sweep(ctx, g, beta, R, seed, colour=None, n_colours=None):
+def _every_sweep(ctx, g, beta, R, seed, colour=None, n_colours=None, sweep_offset=0, replica_offset=0):
     prob = pbit.pbit_load_graph(ctx, g["n"], g["bond_i"], g["bond_j"], g["bond_J"], g.get("h"), colour,
                                 n_colours or 0)
-    got = pbit.pbit_anneal(ctx, prob, beta, R, seed, trace_every=1, trace_spins=True)
-    ref = oracle.anneal(_oracle_graph(g, colour, n_colours), beta, R, seed, trace_every=1, trace_spins=True)
+    off = dict(sweep_offset=sweep_offset, replica_offset=replica_offset)
+    got = pbit.pbit_anneal(ctx, prob, beta, R, seed, trace_every=1, trace_spins=True, **off)
+    ref = oracle.anneal(_oracle_graph(g, colour, n_colours), beta, R, seed, trace_every=1, trace_spins=True, **off)
     pbit.pbit_unload_problem(ctx, prob)
     for s in range(len(beta)):
         if not np.array_equal(got.spin_trace[s], ref.spin_trace[s]):
@@ -64,6 +65,27 @@ def test_random_sparse_graph_every_sweep(ctx, n, deg, R):
     g = _with_zeros(synth.random_sparse_graph(n, deg, seed=n + deg), 0.1, seed=n)
     _say("random graph n=%d deg=%d R=%d every sweep" % (n, deg, R))
     _every_sweep(ctx, g, synth.beta_linear(0.05, 3.0, 30), R, seed=7)
+
+
+@pytest.mark.parametrize("sched", ["zero", "cold", "mixed"])
+def test_graph_extreme_betas(ctx, sched):
+    """The group sweep at the ends of the schedule range (beta = 0 only, large beta
+    only, both interleaved)."""
+    from tests.test_parity_gpu import EXTREME_BETAS
+    g = _with_zeros(synth.random_sparse_graph(300, 8, seed=31), 0.1, seed=3)
+    _say("random graph n=300 beta %s every sweep" % sched)
+    _every_sweep(ctx, g, np.array(EXTREME_BETAS[sched]), 21, seed=53)
+
+
+def test_graph_counters_past_31_bits(ctx):
+    """The group sweep with its sweep and replica counters near the top of their
+    32-bit range."""
+    from tests.test_parity_gpu import HIGH_REPLICA, HIGH_SWEEP
+    inst = synth.ea_instance((5, 5, 5), seed=8, field="uniform3")
+    g = _with_zeros(synth.ea_bond_list(inst), 0.15, seed=8)
+    _say("odd cube 5^3 counters past 31 bits")
+    _every_sweep(ctx, g, synth.beta_linear(0.1, 3.0, 6), 19, seed=67, sweep_offset=HIGH_SWEEP,
+                 replica_offset=HIGH_REPLICA)
 
 
 @pytest.mark.parametrize("L,R,field", [(3, 5, "uniform3"), (7, 50, "zero"), (7, 33, "uniform3")])

@@ -108,10 +108,11 @@ def test_biclique_energy_matches_oracle(ctx, na, nb, R):
 
 # ---------------------------------------------------------------- every sweep
 
-def _every_sweep(ctx, inst, beta, R, seed, init=None):
+def _every_sweep(ctx, inst, beta, R, seed, init=None, sweep_offset=0, replica_offset=0):
     prob = pbit.load_instance(ctx, inst)
-    got = pbit.pbit_anneal(ctx, prob, beta, R, seed, init_spins=init, trace_every=1, trace_spins=True)
-    ref = oracle.anneal(graph_of(inst), beta, R, seed, init_spins=init, trace_every=1, trace_spins=True)
+    off = dict(sweep_offset=sweep_offset, replica_offset=replica_offset)
+    got = pbit.pbit_anneal(ctx, prob, beta, R, seed, init_spins=init, trace_every=1, trace_spins=True, **off)
+    ref = oracle.anneal(graph_of(inst), beta, R, seed, init_spins=init, trace_every=1, trace_spins=True, **off)
     pbit.pbit_unload_problem(ctx, prob)
     assert got.spin_trace.shape == ref.spin_trace.shape
     for s in range(len(beta)):
@@ -141,6 +142,22 @@ def test_ea_extreme_betas(ectx, sched, dims, R):
     inst = _ea_with_zeros(dims, seed=5 * R + sum(dims))
     _say("ea %s R=%d beta %s (%s)" % (dims, R, sched, ectx.mode))
     _every_sweep(ectx.ctx, inst, np.array(EXTREME_BETAS[sched]), R, seed=41)
+    _check_path(ectx, inst)
+
+
+# Philox counter words past 31 bits: absolute sweeps from 2^31 - 3 (the index crosses 2^31
+# during a run) and global replicas from 2^31 - 64
+HIGH_SWEEP, HIGH_REPLICA = 2**31 - 3, 2**31 - 64
+
+
+@pytest.mark.parametrize("dims,R", [((8, 8, 8), 37), ((6, 4, 2), 5)])
+def test_ea_counters_past_31_bits(ectx, dims, R):
+    """Every replica after every sweep with the sweep and replica counters near the top
+    of their 32-bit range, on each cube path."""
+    inst = _ea_with_zeros(dims, seed=97 + R)
+    _say("ea %s R=%d counters past 31 bits (%s)" % (dims, R, ectx.mode))
+    _every_sweep(ectx.ctx, inst, synth.beta_linear(0.1, 3.0, 6), R, seed=11, sweep_offset=HIGH_SWEEP,
+                 replica_offset=HIGH_REPLICA)
     _check_path(ectx, inst)
 
 
