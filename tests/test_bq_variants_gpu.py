@@ -115,6 +115,23 @@ def test_variant_extreme_betas(vctx, sched):
     assert pbit.pbit_profile_variant(vctx) == _FORCED[vctx.value]
 
 
+def test_variant_given_spins_and_resume(vctx):
+    """Given initial spins, and a run split in two (resumed from the first half's spins
+    at its sweep offset), through the forced kernel."""
+    inst = _biclique_with_zeros(520, 600, seed=81)
+    R = 40
+    beta = synth.beta_linear(0.05, 2.0, 8)
+    _say("forced variant %d biclique 520x600 given spins and resume" % _FORCED[vctx.value])
+    _every_sweep(vctx, inst, beta, R, seed=71, init=synth.random_spins(R, 1120, seed=6))
+    prob = pbit.load_instance(vctx, inst)
+    first = pbit.pbit_anneal(vctx, prob, beta[:3], R, seed=71)
+    second = pbit.pbit_anneal(vctx, prob, beta[3:], R, seed=71, sweep_offset=3, init_spins=first.spins)
+    assert pbit.pbit_profile_variant(vctx) == _FORCED[vctx.value]
+    pbit.pbit_unload_problem(vctx, prob)
+    whole = oracle.anneal(graph_of(inst), beta, R, seed=71)
+    assert np.array_equal(second.spins, whole.spins) and np.array_equal(second.energies, whole.energies)
+
+
 def test_variant_counters_past_31_bits(vctx):
     """Sweep and replica counters near the top of their 32-bit range through the forced
     kernel."""

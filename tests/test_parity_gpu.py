@@ -224,6 +224,24 @@ def test_given_initial_spins(ctx):
     _every_sweep(ctx, binst, synth.beta_linear(0.5, 1.0, 10), 9, seed=2, init=synth.random_spins(9, 40, seed=1))
 
 
+def test_given_spins_and_resume_each_cube_path(ectx):
+    """Given initial spins, and a run split in two (the second half resumed from the first
+    half's spins at its sweep offset), on each cube path: every sweep equals the oracle."""
+    inst = _ea_with_zeros((8, 8, 8), seed=101)
+    N, R = 512, 37
+    beta = synth.beta_linear(0.2, 2.0, 12)
+    init = synth.random_spins(R, N, seed=5)
+    _say("ea 8^3 given spins and resume (%s)" % ectx.mode)
+    _every_sweep(ectx.ctx, inst, beta, R, seed=17, init=init)
+    _check_path(ectx, inst)
+    prob = pbit.load_instance(ectx.ctx, inst)
+    first = pbit.pbit_anneal(ectx.ctx, prob, beta[:5], R, seed=17)
+    second = pbit.pbit_anneal(ectx.ctx, prob, beta[5:], R, seed=17, sweep_offset=5, init_spins=first.spins)
+    whole = oracle.anneal(graph_of(inst), beta, R, seed=17)
+    pbit.pbit_unload_problem(ectx.ctx, prob)
+    assert np.array_equal(second.spins, whole.spins) and np.array_equal(second.energies, whole.energies)
+
+
 def test_zero_sweeps_returns_the_random_start(ctx):
     for inst in (synth.ea_instance(4, seed=5), synth.biclique_instance(33, seed=5)):
         prob = pbit.load_instance(ctx, inst)
