@@ -403,19 +403,20 @@ __global__ __launch_bounds__(kThreads) void k_bq_field_energy(const int8_t *__re
 // 2^(3 - j) (Jb, JTb, values in [-8, 8]), so every product is 8 J b and the
 // accumulator holds 8 sum_k J_sk b_k exactly.
 //
-// Tile: 64 sites x 256 replicas per workgroup.  The bytes that reach a CU per
-// multiply-add, 1 / 256 for the couplings plus 1 / 512 for the spin bits, bound
-// these tiles on large bicliques (the L2-to-CU rate of one CU is about 20 bytes
-// per clock).  Eight waves, two per SIMD so that one wave's waits are covered by
-// the other's MFMAs, each own RW = 32 replicas and all 64 sites (1 x 2 MFMA
-// blocks); with kBitsWaves = 4 the template builds the four-wave form (64
-// replicas, 2 x 2 blocks), about 5 % slower.  Either way the vector work stays
-// near 2.5 instructions per MFMA (an
-// MFMA holds the wave's VALU issue for about half of its 32 cycles) and the LDS
-// fragment reads under the matrix-core time of a stage.
-// Stages of 128 K move by the global-to-LDS DMA into a ring: 64 coupling rows
-// of 128 bytes (chunk c of row r at position c ^ swzb(r)), then the 256
-// replicas' 16 bytes (four spin words) of the K block.
+// Tile: 64 sites x RT replicas per workgroup, RT = 256 on large bicliques.  The
+// bytes that reach a CU per multiply-add, 1 / RT for the couplings plus 1 / 512
+// for the spin bits, bound these tiles there (the L2-to-CU rate of one CU is
+// about 20 bytes per clock).  Waves of 32 replicas and all 64 sites (1 x 2 MFMA
+// blocks): eight at RT = 256, two per SIMD so that one wave's waits are covered
+// by the other's MFMAs (a four-wave form of 64 replicas per wave, 2 x 2 blocks,
+// measured about 5 % slower); four at RT = 128 and two at RT = 64, which give
+// sides of 1024 and 2048 more workgroups than CUs would get at 256.  The vector
+// work stays near 2.5 instructions per MFMA (an MFMA holds the wave's VALU issue
+// for about half of its 32 cycles) and the LDS fragment reads under the
+// matrix-core time of a stage.
+// Stages of KT = 128 or 256 K move by the global-to-LDS DMA into a ring: 64
+// coupling rows of KT bytes (chunk c of row r at position c ^ swzb(r)), then the
+// RT replicas' 16 bytes (four spin words) per 128-site block of the stage.
 //
 // Decisions through 64-bit words in LDS, one per clamped field value:
 // S(I) = Tm(|I|) for I >= 0, 2^32 - Tm(|I|) for I < 0; the new spin is -1
