@@ -183,36 +183,25 @@ __global__ __launch_bounds__(kThreads) void k_bq_slab(BqView p, int8_t *__restri
             for (int q = 0; q < kBlkPerWave; ++q) acc[q] = v4i{0, 0, 0, 0};
             const uint8_t *arow = sp + col * pitch + in_col + 16 * grp;
             const int nkb = ko / 64;
-            auto codes_of = [&](int kb, uint32_t(&c)[kBlkPerWave]) {
-                const uint32_t *ck = codes + (size_t)kb * ns_p * 4;
+            // the K loop unrolled to its largest trip count (ko <= 512: 8 steps) under
+            // wave-uniform guards: the spin rows then sit at fixed offsets from one
+            // address, the code words of step kb at kb * 4 ns_p words from a pointer that
+            // advances once per step, and block q's at a fixed offset from block 0's
+            const bool one = wave < nblk, two = wave + kWaves < nblk;  // this wave's blocks
+            const uint32_t *ck = codes + (wave * 16 + col) * 4 + grp;
+            constexpr int kMaxKb = 512 / 64;
+            static_assert(kBlkPerWave == 2, "two blocks per wave below");
 #pragma unroll
-                for (int q = 0; q < kBlkPerWave; ++q) {
-                    const int blk = wave + kWaves * q;
-                    c[q] = blk < nblk ? ck[(blk * 16 + col) * 4 + grp] : 0u;
-                }
-            };
-            auto step = [&](const v4i &a, const uint32_t(&c)[kBlkPerWave]) {
-#pragma unroll
-                for (int q = 0; q < kBlkPerWave; ++q)
-                    if (wave + kWaves * q < nblk)
-                        acc[q] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, widen16(c[q]), acc[q], 0, 0, 0);
-            };
-            // two operand sets in turn (no register copies between the steps)
-            v4i a0 = *reinterpret_cast<const v4i *>(arow), a1 = a0;
-            uint32_t c0[kBlkPerWave], c1[kBlkPerWave];
-            codes_of(0, c0);
-            for (int kb = 0; kb < nkb; kb += 2) {
-                if (kb + 1 < nkb) {
-                    a1 = *reinterpret_cast<const v4i *>(arow + 64 * (kb + 1));
-                    codes_of(kb + 1, c1);
-                }
-                step(a0, c0);
-                if (kb + 1 < nkb) {
-                    if (kb + 2 < nkb) {
-                        a0 = *reinterpret_cast<const v4i *>(arow + 64 * (kb + 2));
-                        codes_of(kb + 2, c0);
+            for (int kb = 0; kb < kMaxKb; ++kb) {
+                if (one && kb < nkb) {
+                    const v4i a = *reinterpret_cast<const v4i *>(arow + 64 * kb);
+                    const uint32_t c0 = ck[0];
+                    acc[0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, widen16(c0), acc[0], 0, 0, 0);
+                    if (two) {
+                        const uint32_t c1 = ck[64 * kWaves];
+                        acc[1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, widen16(c1), acc[1], 0, 0, 0);
                     }
-                    step(a1, c1);
+                    ck += (size_t)ns_p * 4;
                 }
             }
             // decisions: lane holds site blk * 16 + col for replicas 4 grp .. 4 grp + 3,
