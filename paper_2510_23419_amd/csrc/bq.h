@@ -40,14 +40,17 @@ constexpr int kMaxTableWidth = 4096;  // threshold-row entries a biclique kernel
 // Rp a multiple of 128); Bits: tiles of 64 sites x 256, 128 or 64 replicas on spins
 // held as bits, widened for the int8 MFMA (bqb_*; sides padded to 128, Rp a multiple
 // of 256); Slab: sides of
-// at most 512 sites, couplings and 16-replica slices held in LDS for runs of
+// at most 512 sites, couplings and 16- or 8-replica slices held in LDS for runs of
 // sweeps in one launch (bq_slab).
 enum class BqVariant : int { Auto = 0, Small = 1, Dma = 2, Bits = 3, Slab = 4 };
 // The LDS-resident form for small sides: sweeps [s_begin, s_end) (table rows), absolute
-// index sweep0 + s, of all Rp replicas (Rp / 16 workgroups) on MA / MB in place.
-bool bq_slab_supported(const BqView &p, int Rp, int width);
+// index sweep0 + s, of all Rp replicas (Rp / rs workgroups of rs-replica slices) on MA / MB
+// in place.  rs is 16 or 8; 0 picks 16 when that gives a workgroup to every compute unit,
+// else 8.  bq_slab_rs returns the slice that a launch with rs uses (0: none fits Rp).
+int bq_slab_rs(int Rp, int rs);
+bool bq_slab_supported(const BqView &p, int Rp, int width, int rs = 0);
 hipError_t bq_slab(const BqView &p, int8_t *MA, int8_t *MB, int Rp, const uint32_t *table, int width, int s_begin,
-                   int s_end, uint32_t sweep0, uint32_t rq0, Key key, hipStream_t st);
+                   int s_end, uint32_t sweep0, uint32_t rq0, Key key, hipStream_t st, int rs = 0);
 hipError_t bq_init(const BqView &p, int8_t *MA, int8_t *MB, int R, uint32_t rq0, Key key, hipStream_t st);
 hipError_t bq_from_rows(const BqView &p, const int8_t *src_rn, int R, int8_t *MA, int8_t *MB, hipStream_t st);
 hipError_t bq_to_rows(const BqView &p, const int8_t *MA, const int8_t *MB, int8_t *dst_rn, int R, hipStream_t st);

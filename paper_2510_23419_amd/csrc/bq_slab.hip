@@ -34,7 +34,6 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 constexpr int kThreads = 1024;  // 16 waves: four per SIMD
 constexpr int kWaves = kThreads / 64;
 constexpr int kBlkPerWave = 2;  // 16-site blocks per wave and half-sweep: 32 blocks at 512 sites
-constexpr int kRS = 16;        // replicas per workgroup (the MFMA's 16 rows)
 constexpr int kMaxLds = 160 * 1024 - 4096;
 
 // 4 x 4 byte transpose across a quad of lanes: lane u holds bytes M[u][0..3] and
@@ -79,17 +78,27 @@ __device__ void stage_codes(const int8_t *__restrict__ Jrow, int ns_p, int ko, u
     }
 }
 
-// Sweeps [s_begin, s_end) of replicas [16 blockIdx.x, + 16) of a small biclique.
+// Sweeps [s_begin, s_end) of replicas [RS blockIdx.x, + RS) of a small biclique.
+//
+// RS = 16 fills the MFMA's 16 rows.  RS = 8 gives twice the workgroups for the same
+// replicas (a launch of 1024 replicas then uses 128 CUs instead of 64): the rows 8 .. 15
+// read a zero row, and the two site blocks of a wave, whose valid rows sit in lanes
+// 0 .. 31 of their accumulators, are packed into one register (lanes 32 .. 63 from the
+// second block: v_permlane32_swap), so the decision epilogue runs once per wave for
+// both blocks instead of twice on half-empty lanes.
+template <int RS>
 __global__ __launch_bounds__(kThreads) void k_bq_slab(BqView p, int8_t *__restrict__ MA, int8_t *__restrict__ MB,
                                                       int Rp, const uint32_t *__restrict__ table, int width,
                                                       int s_begin, int s_end, uint32_t sweep0, uint32_t rq0,
                                                       uint32_t k0, uint32_t k1, uint32_t one)
 {
+    static_assert(RS == 16 || RS == 8, "slices of 16 or 8 replicas");
+    constexpr int kRows = RS == 16 ? 16 : RS + 1;  // spin rows, plus a zero row for the unused MFMA rows
     extern __shared__ uint4 dyn[];
     // spin sums per replica over side A and over side B, two of each by sweep parity: a
     // half-sweep's decisions read the other side's sum while its epilogue adds up its own
     // side's new spins for the next half-sweep
-    __shared__ int32_t magA[2][kRS], magB[2][kRS];
+    __shared__ int32_t magA[2][RS], magB[2][RS];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: block tests are scalar branches
     const int na = p.na, nb = p.nb, na_p = p.na_p, nb_p = p.nb_p;
@@ -99,18 +108,20 @@ __global__ __launch_bounds__(kThreads) void k_bq_slab(BqView p, int8_t *__restri
     uint32_t *codesB = codesA + (size_t)na_p * nb_p / 16;
     uint8_t *sp = reinterpret_cast<uint8_t *>(codesB + (size_t)nb_p * na_p / 16);
     // decision words of two sweeps: those of sweep s + 1 are written during sweep s
-    uint64_t *Sw2 = reinterpret_cast<uint64_t *>(sp + (size_t)kRS * pitch);
-    const int r0 = kRS * blockIdx.x;  // first replica of the slice (local to this call)
+    uint64_t *Sw2 = reinterpret_cast<uint64_t *>(sp + (size_t)kRows * pitch);
+    const int r0 = RS * blockIdx.x;  // first replica of the slice (local to this call)
 
     stage_codes(p.J, na_p, nb_p, codesA);
     stage_codes(p.JT, nb_p, na_p, codesB);
-    for (int k = tid; k < kRS * (pitch / 16); k += kThreads) {
+    for (int k = tid; k < kRows * (pitch / 16); k += kThreads) {
         const int r = k / (pitch / 16), c16 = k % (pitch / 16), c = 16 * c16;
         uint4 v = make_uint4(0, 0, 0, 0);
-        if (c < na_p)
-            v = *reinterpret_cast<const uint4 *>(MA + (size_t)(r0 + r) * na_p + c);
-        else if (c < na_p + nb_p)
-            v = *reinterpret_cast<const uint4 *>(MB + (size_t)(r0 + r) * nb_p + (c - na_p));
+        if (r < RS) {
+            if (c < na_p)
+                v = *reinterpret_cast<const uint4 *>(MA + (size_t)(r0 + r) * na_p + c);
+            else if (c < na_p + nb_p)
+                v = *reinterpret_cast<const uint4 *>(MB + (size_t)(r0 + r) * nb_p + (c - na_p));
+        }
         *reinterpret_cast<uint4 *>(sp + r * pitch + c) = v;
     }
 
@@ -129,7 +140,7 @@ __global__ __launch_bounds__(kThreads) void k_bq_slab(BqView p, int8_t *__restri
     __syncthreads();  // the spin rows are in LDS
     // side B's spin sums for the first half-sweep, one wave per replica row; side A's sums
     // start at zero
-    if (wave < kRS) {
+    if (wave < RS) {
         const uint32_t *row = reinterpret_cast<const uint32_t *>(sp + wave * pitch + na_p);
         int v = 0;
         for (int d = lane; d < nb_p / 4; d += 64) v = __builtin_amdgcn_sdot4((int)row[d], 0x01010101, v, false);
@@ -141,6 +152,12 @@ __global__ __launch_bounds__(kThreads) void k_bq_slab(BqView p, int8_t *__restri
         }
     }
     __syncthreads();  // codes, spins, the first decision words and sums are in LDS
+    // A rows: replica row col, or (RS = 8, col >= 8) the zero row
+    const int arow_r = col < RS ? col : RS;
+    // the replica rows of a lane's accumulator elements: 4 gr + j (RS = 8: the merged
+    // register holds rows 0 .. 7 of block wave in lanes 0 .. 31 and of block wave + kWaves
+    // in lanes 32 .. 63)
+    const int gr = RS == 16 ? grp : (grp & 1);
     // two barriers per sweep, one after each half-sweep (its spins, sums and, after side B,
     // the next sweep's decision words are then complete)
     for (int s = s_begin; s < s_end; ++s) {
@@ -148,7 +165,7 @@ __global__ __launch_bounds__(kThreads) void k_bq_slab(BqView p, int8_t *__restri
         const uint32_t t = sweep0 + (uint32_t)s;
         const char *Sb = reinterpret_cast<const char *>(Sw2 + (size_t)par * (2 * top + 1));
         // the sums filled in the next two half-sweeps start at zero (last read a sweep ago)
-        if (tid < kRS) {
+        if (tid < RS) {
             magB[par ^ 1][tid] = 0;
             magA[par ^ 1][tid] = 0;
         }
@@ -162,38 +179,41 @@ __global__ __launch_bounds__(kThreads) void k_bq_slab(BqView p, int8_t *__restri
             const int8_t *hs = side == 0 ? p.hA : p.hB;
             const uint32_t site_base = side == 0 ? 0u : (uint32_t)na;
             const int nblk = ns_p / 16;
-            // the random words and fields of this wave's sites first: they do not depend on
-            // the spins, so they are drawn while the LDS reads below are in flight
-            Block4 w[kBlkPerWave];
-            int hv[kBlkPerWave];
+            // the random words and fields of this lane's sites first: they do not depend on
+            // the spins, so they are drawn while the LDS reads below are in flight (RS = 16:
+            // one block of four replicas for each of the wave's two site blocks; RS = 8: one
+            // for the lane's site in the merged register)
+            constexpr int kDraws = RS == 16 ? kBlkPerWave : 1;
+            Block4 w[kDraws];
+            int hv[kDraws];
 #pragma unroll
-            for (int q = 0; q < kBlkPerWave; ++q) {
-                const int site = (wave + kWaves * q) * 16 + col;
+            for (int q = 0; q < kDraws; ++q) {
+                const int blk = wave + kWaves * (RS == 16 ? q : (lane >> 5));
+                const int site = blk * 16 + col;
                 hv[q] = site < ns_p ? (int)hs[site] : 0;
-                w[q] = philox(site_base + (uint32_t)site, t, rq0 + (uint32_t)(blockIdx.x * (kRS / 4) + grp),
+                w[q] = philox(site_base + (uint32_t)site, t, rq0 + (uint32_t)(blockIdx.x * (RS / 4) + gr),
                               kDomainSweep, k0, k1);
             }
             // the other side's spin sums (side B's of this sweep's parity, side A's just filled)
             const int32_t *mag = side == 0 ? magB[par] : magA[par];
             int32_t *mag_out = side == 0 ? magA[par] : magB[par ^ 1];
-            // fields of up to kBlkPerWave 16-site blocks per wave (blocks wave, wave + kWaves,
-            // ...), the operands of K step kb + 1 read from LDS before the MFMAs of step kb
+            // fields of up to kBlkPerWave 16-site blocks per wave (blocks wave, wave + kWaves)
             v4i acc[kBlkPerWave];
 #pragma unroll
             for (int q = 0; q < kBlkPerWave; ++q) acc[q] = v4i{0, 0, 0, 0};
-            const uint8_t *arow = sp + col * pitch + in_col + 16 * grp;
+            const uint8_t *arow = sp + arow_r * pitch + in_col + 16 * grp;
             const int nkb = ko / 64;
             // the K loop unrolled to its largest trip count (ko <= 512: 8 steps) under
             // wave-uniform guards: the spin rows then sit at fixed offsets from one
             // address, the code words of step kb at kb * 4 ns_p words from a pointer that
             // advances once per step, and block q's at a fixed offset from block 0's
-            const bool one = wave < nblk, two = wave + kWaves < nblk;  // this wave's blocks
+            const bool one_blk = wave < nblk, two = wave + kWaves < nblk;  // this wave's blocks
             const uint32_t *ck = codes + (wave * 16 + col) * 4 + grp;
             constexpr int kMaxKb = 512 / 64;
             static_assert(kBlkPerWave == 2, "two blocks per wave below");
 #pragma unroll
             for (int kb = 0; kb < kMaxKb; ++kb) {
-                if (one && kb < nkb) {
+                if (one_blk && kb < nkb) {
                     const v4i a = *reinterpret_cast<const v4i *>(arow + 64 * kb);
                     const uint32_t c0 = ck[0];
                     acc[0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, widen16(c0), acc[0], 0, 0, 0);
@@ -204,46 +224,57 @@ __global__ __launch_bounds__(kThreads) void k_bq_slab(BqView p, int8_t *__restri
                     ck += (size_t)ns_p * 4;
                 }
             }
-            // decisions: lane holds site blk * 16 + col for replicas 4 grp .. 4 grp + 3,
-            // one Philox block; the four bytes are transposed across the lane quad so that
-            // each lane writes four consecutive sites of one replica row
+            // decisions of one site block in a lane: site blk * 16 + col, replicas 4 gr .. 4 gr
+            // + 3 (one Philox block); the four bytes are transposed across the lane quad so
+            // that each lane writes four consecutive sites of one replica row
             const int u4 = lane & 3;
-#pragma unroll
-            for (int q = 0; q < kBlkPerWave; ++q) {
-                const int blk = wave + kWaves * q;
-                if (blk >= nblk) continue;
+            auto decide = [&](const v4i &f, int blk, int hval, const Block4 &wq) {
                 const int site = blk * 16 + col;
-                const int hval = hv[q];
                 const int flo = -top - hval, fhi = top - hval;
                 const int base8 = 8 * (hval + top);
                 uint32_t sgn[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const int F = acc[q][j] - mag[4 * grp + j];
+                    const int F = f[j] - mag[4 * gr + j];
                     const int Fc = min(max(F, flo), fhi);
                     const uint64_t S =
                         *static_cast<const uint64_t *>(__builtin_assume_aligned(Sb + 8 * Fc + base8, 8));
-                    sgn[j] = (uint32_t)(((uint64_t)w[q].w[j] * one + S) >> 32);
+                    sgn[j] = (uint32_t)(((uint64_t)wq.w[j] * one + S) >> 32);
                 }
                 const uint32_t lo = __builtin_amdgcn_perm(sgn[1], sgn[0], 0x0C0C0400u);
                 const uint32_t hi = __builtin_amdgcn_perm(sgn[3], sgn[2], 0x0C0C0400u);
                 uint32_t packed = __builtin_amdgcn_perm(0u, 0xFF01u, __builtin_amdgcn_perm(hi, lo, 0x05040100u));
                 if (site >= ns) packed = 0u;  // padding sites stay zero
                 const uint32_t x = quad_transpose4(packed, u4);
-                *reinterpret_cast<uint32_t *>(sp + (4 * grp + u4) * pitch + out_col + blk * 16 + (col & ~3)) = x;
-                // replica 4 grp + u4's sum over these four sites, then over the block's four
+                *reinterpret_cast<uint32_t *>(sp + (4 * gr + u4) * pitch + out_col + blk * 16 + (col & ~3)) = x;
+                // replica 4 gr + u4's sum over these four sites, then over the block's four
                 // site quads (lanes 4 and 8 apart in the row of 16), added once per block
                 int ps = __builtin_amdgcn_sdot4((int)x, 0x01010101, 0, false);
                 ps += __builtin_amdgcn_update_dpp(0, ps, 0x124, 0xF, 0xF, false);  // row_ror:4
                 ps += __builtin_amdgcn_update_dpp(0, ps, 0x128, 0xF, 0xF, false);  // row_ror:8
-                if ((col & 12) == 0) atomicAdd(&mag_out[4 * grp + u4], ps);
+                if ((col & 12) == 0) atomicAdd(&mag_out[4 * gr + u4], ps);
+            };
+            if constexpr (RS == 16) {
+#pragma unroll
+                for (int q = 0; q < kBlkPerWave; ++q)
+                    if (wave + kWaves * q < nblk) decide(acc[q], wave + kWaves * q, hv[q], w[q]);
+            } else {
+                // rows 0 .. 7 of both blocks in one register: lanes 32 .. 63 take lanes 0 .. 31
+                // of the second block's accumulator
+                v4i m;
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    m[j] = (int)__builtin_amdgcn_permlane32_swap((unsigned)acc[0][j], (unsigned)acc[1][j], false,
+                                                                 false)[0];
+                const int blk = wave + kWaves * (lane >> 5);
+                if (blk < nblk) decide(m, blk, hv[0], w[0]);  // the same on all 16 lanes of a DPP row
             }
             if (side == 1 && s + 1 < s_end) build_words(s + 1);  // published by the next barrier
             __syncthreads();
         }
     }
 
-    for (int k = tid; k < kRS * ((na_p + nb_p) / 16); k += kThreads) {
+    for (int k = tid; k < RS * ((na_p + nb_p) / 16); k += kThreads) {
         const int r = k / ((na_p + nb_p) / 16), c = 16 * (k % ((na_p + nb_p) / 16));
         const uint4 v = *reinterpret_cast<const uint4 *>(sp + r * pitch + c);
         if (c < na_p)
@@ -253,30 +284,55 @@ __global__ __launch_bounds__(kThreads) void k_bq_slab(BqView p, int8_t *__restri
     }
 }
 
-size_t slab_lds(const BqView &p, int width)
+// LDS of a launch: the two code orientations, the spin rows (RS = 8: plus the zero row)
+// and the decision words of two sweeps
+size_t slab_lds(const BqView &p, int width, int rs)
 {
-    return (size_t)2 * p.na_p * p.nb_p / 4 + (size_t)kRS * (p.na_p + p.nb_p + 16) +
+    const int rows = rs == 16 ? 16 : rs + 1;
+    return (size_t)2 * p.na_p * p.nb_p / 4 + (size_t)rows * (p.na_p + p.nb_p + 16) +
            2 * sizeof(uint64_t) * (size_t)(2 * width - 1);
+}
+
+template <int RS>
+hipError_t slab_launch(const BqView &p, int8_t *MA, int8_t *MB, int Rp, const uint32_t *table, int width,
+                       int s_begin, int s_end, uint32_t sweep0, uint32_t rq0, Key key, hipStream_t st)
+{
+    static const hipError_t lds_attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bq_slab<RS>),
+                                                           hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    if (lds_attr != hipSuccess) return lds_attr;
+    hipLaunchKernelGGL(k_bq_slab<RS>, dim3((unsigned)(Rp / RS)), dim3(kThreads), slab_lds(p, width, RS), st, p, MA,
+                       MB, Rp, table, width, s_begin, s_end, sweep0, rq0, key.k0, key.k1, 1u);
+    return hipGetLastError();
 }
 
 }  // namespace
 
-bool bq_slab_supported(const BqView &p, int Rp, int width)
+int bq_slab_rs(int Rp, int rs)
 {
-    return p.na_p <= 512 && p.nb_p <= 512 && p.na_p % 64 == 0 && p.nb_p % 64 == 0 && Rp % kRS == 0 &&
-           width >= 1 && slab_lds(p, width) <= (size_t)kMaxLds;
+    if (rs == 16 || rs == 8) return Rp % rs == 0 ? rs : 0;
+    if (rs != 0) return 0;
+    // slices of 16 unless they leave most compute units idle
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 256;
+    return Rp % 16 == 0 && Rp / 16 >= cus ? 16 : 8;
+}
+
+bool bq_slab_supported(const BqView &p, int Rp, int width, int rs)
+{
+    rs = bq_slab_rs(Rp, rs);
+    return rs != 0 && p.na_p <= 512 && p.nb_p <= 512 && p.na_p % 64 == 0 && p.nb_p % 64 == 0 && width >= 1 &&
+           slab_lds(p, width, rs) <= (size_t)kMaxLds;
 }
 
 hipError_t bq_slab(const BqView &p, int8_t *MA, int8_t *MB, int Rp, const uint32_t *table, int width, int s_begin,
-                   int s_end, uint32_t sweep0, uint32_t rq0, Key key, hipStream_t st)
+                   int s_end, uint32_t sweep0, uint32_t rq0, Key key, hipStream_t st, int rs)
 {
-    if (!bq_slab_supported(p, Rp, width) || s_end < s_begin) return hipErrorInvalidValue;
-    static const hipError_t lds_attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bq_slab),
-                                                           hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
-    if (lds_attr != hipSuccess) return lds_attr;
-    hipLaunchKernelGGL(k_bq_slab, dim3((unsigned)(Rp / kRS)), dim3(kThreads), slab_lds(p, width), st, p, MA, MB, Rp,
-                       table, width, s_begin, s_end, sweep0, rq0, key.k0, key.k1, 1u);
-    return hipGetLastError();
+    if (!bq_slab_supported(p, Rp, width, rs) || s_end < s_begin) return hipErrorInvalidValue;
+    if (bq_slab_rs(Rp, rs) == 16)
+        return slab_launch<16>(p, MA, MB, Rp, table, width, s_begin, s_end, sweep0, rq0, key, st);
+    return slab_launch<8>(p, MA, MB, Rp, table, width, s_begin, s_end, sweep0, rq0, key, st);
 }
 
 }  // namespace pbit

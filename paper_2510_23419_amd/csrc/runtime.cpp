@@ -130,6 +130,10 @@ extern "C" int pbit_create(pbit_ctx **out, int device, uint64_t hbm_budget_bytes
         if (k >= 1 && k <= 4) ctx->bq_forced = (BqVariant)k;
     }
     if (const char *v = std::getenv("PBIT_BQ_BITS_RT")) ctx->bq_bits_rt = std::atoi(v);  // tuning override
+    if (const char *v = std::getenv("PBIT_BQ_SLAB_RS")) {  // tuning override: 16 or 8
+        const int k = std::atoi(v);
+        ctx->bq_slab_rs = k == 16 || k == 8 ? k : 0;
+    }
     if (const char *v = std::getenv("PBIT_EA_STREAM")) ctx->ea_stream_forced = std::atoi(v) != 0;
     if (const char *v = std::getenv("PBIT_EA_ROWS")) ctx->ea_rows = std::max(0, std::atoi(v));  // tuning override
     if (const char *v = std::getenv("PBIT_GRAPH")) ctx->use_graph = std::atoi(v) != 0;
@@ -641,6 +645,7 @@ struct DevState {
     int8_t *stage = nullptr;  // [R][N] host-layout staging
     BqVariant variant = BqVariant::Auto;
     int bits_rt = 0;  // replicas per tile of the bit kernel (0: its launcher's rule)
+    int slab_rs = 0;  // replicas per slice of the LDS-resident biclique kernel (0: its launcher's rule)
     bool slab = false;        // cube held in LDS for runs of sweeps (ea_slab)
     bool mfma = false;        // cube fields on the matrix cores (ea_mfma.hip), spins [2][Rp][N / 2]
     Arena *arena = nullptr;   // set: buffers are carved from it (no allocation, no kernel timing)
@@ -671,9 +676,10 @@ static int tune_biclique(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStrea
     // the spins, made where the replicas pad to 256); the LDS-resident form sides of
     // at most 512 and its decision words in LDS
     const bool large = P.bq.na_p % 128 == 0 && P.bq.nb_p % 128 == 0;
-    const bool slab_ok = bq_slab_supported(P.bq, ds.Rp, ds.width);
+    const bool slab_ok = bq_slab_supported(P.bq, ds.Rp, ds.width, ctx->bq_slab_rs);
     const BqVariant f = ctx->bq_forced;
     ds.bits_rt = ctx->bq_bits_rt;
+    ds.slab_rs = ctx->bq_slab_rs;
     if (f == BqVariant::Small || (f == BqVariant::Dma && large) || (f == BqVariant::Bits && ds.MAb) ||
         (f == BqVariant::Slab && slab_ok)) {
         ds.variant = f;  // a forced kernel the shape cannot take falls back to the tuned choice
@@ -683,12 +689,12 @@ static int tune_biclique(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStrea
     auto it = ctx->bq_tuned.find(shape);
     if (it != ctx->bq_tuned.end()) {
         ds.variant = it->second.first;
-        ds.bits_rt = it->second.second;
+        (ds.variant == BqVariant::Slab ? ds.slab_rs : ds.bits_rt) = it->second.second;
         return PBIT_OK;
     }
     if (!large && !slab_ok) {
         ds.variant = BqVariant::Small;
-        ctx->bq_tuned[shape] = {ds.variant, ds.bits_rt};
+        ctx->bq_tuned[shape] = {ds.variant, 0};
         return PBIT_OK;
     }
     if (ds.arena) {
@@ -710,9 +716,9 @@ static int tune_biclique(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStrea
     const int S = std::max(1, n_sweeps), m = std::min(8, S - 1);
     float best_ms = 0.f;
     BqVariant best = BqVariant::Small;
-    int best_rt = ds.bits_rt;
+    int best_rt = 0;
     bool have = false;
-    int rt = ds.bits_rt;  // the bit kernel's replica tile being timed
+    int rt = 0;  // the bit kernel's replica tile or the LDS-resident kernel's slice being timed
     // one warm-up pass, then the best of three (a profiler's tracing stretches single launches)
     auto time_it = [&](BqVariant v, int slab_sweeps, float *best_pass) {
         *best_pass = 0.f;
@@ -721,7 +727,8 @@ static int tune_biclique(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStrea
             e = hipEventRecord(e0, st);
             if (v == BqVariant::Slab) {
                 if (e == hipSuccess)
-                    e = bq_slab(P.bq, ds.MA, ds.MB, ds.Rp, ds.table, ds.width, 0, slab_sweeps, 0u, 0u, key, st);
+                    e = bq_slab(P.bq, ds.MA, ds.MB, ds.Rp, ds.table, ds.width, 0, slab_sweeps, 0u, 0u, key, st,
+                                rt);
             } else {
                 for (int k = 0; k < 4 && e == hipSuccess; ++k)
                     e = v == BqVariant::Bits
@@ -736,8 +743,9 @@ static int tune_biclique(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStrea
             if (rep == 1 || (rep > 1 && one_pass < *best_pass)) *best_pass = one_pass;
         }
     };
-    // the bit kernel in each replica tile that divides Rp (unless one is forced): more
-    // tiles fill more CUs, larger ones read the couplings fewer times
+    // the bit kernel in each replica tile that divides Rp, and the LDS-resident kernel in
+    // slices of 16 and 8 replicas (unless forced): more tiles or slices fill more CUs,
+    // larger ones read the couplings fewer times or use more of the MFMA's rows
     std::vector<std::pair<BqVariant, int>> runs;
     for (BqVariant v : cand) {
         if ((v == BqVariant::Dma && !large) || (v == BqVariant::Bits && !ds.MAb) || (v == BqVariant::Slab && !slab_ok))
@@ -745,8 +753,11 @@ static int tune_biclique(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStrea
         if (v == BqVariant::Bits && ds.bits_rt == 0) {
             for (int w : {256, 128, 64})
                 if (ds.Rp % w == 0) runs.push_back({v, w});
+        } else if (v == BqVariant::Slab && ds.slab_rs == 0) {
+            for (int w : {16, 8})
+                if (bq_slab_supported(P.bq, ds.Rp, ds.width, w)) runs.push_back({v, w});
         } else {
-            runs.push_back({v, ds.bits_rt});
+            runs.push_back({v, v == BqVariant::Slab ? ds.slab_rs : ds.bits_rt});
         }
     }
     for (const auto &run : runs) {
@@ -777,7 +788,8 @@ static int tune_biclique(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStrea
     if (e != hipSuccess) return device_fail(ctx, e, "biclique kernel tuning");
     ds.variant = best;
     if (best == BqVariant::Bits) ds.bits_rt = best_rt;
-    ctx->bq_tuned[shape] = {ds.variant, ds.bits_rt};
+    if (best == BqVariant::Slab) ds.slab_rs = best_rt;
+    ctx->bq_tuned[shape] = {ds.variant, best == BqVariant::Slab ? ds.slab_rs : ds.bits_rt};
     return PBIT_OK;
 }
 
@@ -979,7 +991,8 @@ static hipError_t sweeps(pbit_ctx *ctx, const Problem &P, DevState &ds, int s0, 
     const bool timed = ctx->prof_every > 0 && ctx->prof_open < 0;
     if (timed) e = prof_begin(ctx, P.kind, st);
     if (e == hipSuccess)
-        e = P.kind == PBIT_BICLIQUE ? bq_slab(P.bq, ds.MA, ds.MB, ds.Rp, ds.table, ds.width, s0, s1, sweep0, rq0, key, st)
+        e = P.kind == PBIT_BICLIQUE ? bq_slab(P.bq, ds.MA, ds.MB, ds.Rp, ds.table, ds.width, s0, s1, sweep0, rq0, key, st,
+                                              ds.slab_rs)
                                     : ea_slab(P.ea, ds.spins, ds.Rp, ds.table, ds.width, s0, s1, sweep0, rq0, key, st);
     if (e == hipSuccess && timed) {
         ctx->prof_launches.back() += 2 * (s1 - s0);

@@ -74,6 +74,7 @@ struct pbit_ctx {
     pbit::BqVariant bq_forced = pbit::BqVariant::Auto;
     int bq_last_variant = 0;  // biclique half-sweep variant of the latest biclique anneal (0: none yet)
     int bq_bits_rt = 0;       // replicas per tile of the bit kernel (PBIT_BQ_BITS_RT: 64, 128, 256; 0 = by size)
+    int bq_slab_rs = 0;       // replicas per slice of the LDS-resident kernel (PBIT_BQ_SLAB_RS: 16, 8; 0 = timed)
     bool ea_stream_forced = false;  // cubes always take the streaming stencil (PBIT_EA_STREAM=1)
     int ea_rows = 0;                // lattice rows per workgroup of the streaming stencil (PBIT_EA_ROWS; 0 = default)
     int ea_mfma = -1;  // matrix-core cube half-sweep: -1 timed against the stencil, 1 every cube, 0 none (PBIT_EA_MFMA)
@@ -85,7 +86,8 @@ struct pbit_ctx {
     uint64_t graph_key = 0;
     int64_t graph_captures = 0, graph_launches = 0;
     int ea_last_path = 0;           // cube path of the latest cube anneal: 1 stream, 2 LDS-resident (0: none)
-    // (na_p, nb_p, Rp, LDS form possible) -> fastest kernel and, for the bit kernel, its replica tile
+    // (na_p, nb_p, Rp, LDS form possible) -> fastest kernel and its replica tile (bit kernel) or
+    // slice (LDS-resident kernel)
     std::map<std::array<int, 4>, std::pair<pbit::BqVariant, int>> bq_tuned;
 };
 

@@ -11,8 +11,8 @@ default is:
   replicas (each forced through PBIT_BQ_BITS_RT too).  The batched engine's bit
   tiles run under this variant too;
 * 4: sides of at most 512 sites held in LDS with their couplings (two-bit codes of
-  J + 1 in both orientations) for runs of sweeps in one launch, 16 replicas per
-  workgroup, on the int8 MFMA 16 x 16 x 64.
+  J + 1 in both orientations) for runs of sweeps in one launch, 16 or 8 replicas
+  per workgroup (each forced through PBIT_BQ_SLAB_RS), on the int8 MFMA 16 x 16 x 64.
 
 Each kernel is checked on every replica after every sweep on ragged sides, on
 sampled replicas at full size (n = 1024 and 4096, 1024 replicas), and at 128
@@ -244,9 +244,19 @@ def test_bit_tiles_and_default_tiles_agree(bits_ctx):
         pbit.pbit_unload_problem(bits_ctx, p)
 
 
-@pytest.fixture(scope="module")
-def slab_ctx():
-    c = _forced_context("4")
+@pytest.fixture(scope="module", params=["16", "8"], ids=["rs16", "rs8"])
+def slab_ctx(request):
+    """The LDS-resident kernel forced, in slices of 16 replicas (the MFMA's 16 rows) or
+    of 8 (two site blocks' rows merged in one epilogue), forced through PBIT_BQ_SLAB_RS."""
+    old = os.environ.get("PBIT_BQ_SLAB_RS")
+    os.environ["PBIT_BQ_SLAB_RS"] = request.param
+    try:
+        c = _forced_context("4")
+    finally:
+        if old is None:
+            del os.environ["PBIT_BQ_SLAB_RS"]
+        else:
+            os.environ["PBIT_BQ_SLAB_RS"] = old
     yield c.ctx
     c.close()
 
