@@ -297,10 +297,11 @@ int pbit_profile_read(pbit_ctx *ctx, int32_t kind, double *total_ms, int64_t *la
  * tiles staged in LDS by the global-to-LDS DMA (sides padded to 128), 3 = spins
  * held as bits, tiles of 64 sites x 256, 128 or 64 replicas (sides padded to 128,
  * replicas to 256), 4 = sides of at most 512 held in LDS with their couplings for
- * runs of sweeps per launch.  The library times the kernels the shape can take
- * (kernel 3 in each replica tile that divides the padded replica count) on the
- * first anneal of a shape and keeps the fastest, unless PBIT_BQ_VARIANT (1..4)
- * names a kernel, or PBIT_BQ_BITS_RT (64, 128, 256) a replica tile, when the
+ * runs of sweeps per launch, in slices of 16 or 8 replicas.  The library times the
+ * kernels the shape can take (kernel 3 in each replica tile that divides the padded
+ * replica count, kernel 4 in both slice widths) on the first anneal of a shape and
+ * keeps the fastest, unless PBIT_BQ_VARIANT (1..4) names a kernel, PBIT_BQ_BITS_RT
+ * (64, 128, 256) a replica tile or PBIT_BQ_SLAB_RS (16, 8) a slice width, when the
  * context is created; a named kernel the shape cannot take falls back to the
  * timed choice.  All give the same spins.  *variant is written on success only. */
 int pbit_profile_variant(pbit_ctx *ctx, int32_t *variant);

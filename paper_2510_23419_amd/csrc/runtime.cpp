@@ -713,7 +713,8 @@ static int tune_biclique(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStrea
     // the LDS-resident form loads its couplings once per launch of up to kSlabChunk sweeps:
     // timed over 1 and 1 + m sweeps, and its cost for this call's sweeps set against the
     // others' per half-sweep (table rows up to n_sweeps are read)
-    const int S = std::max(1, n_sweeps), m = std::min(8, S - 1);
+    // (32 more sweeps: enough that a traced run's longer launches do not flip its slice choice)
+    const int S = std::max(1, n_sweeps), m = std::min(32, S - 1);
     float best_ms = 0.f;
     BqVariant best = BqVariant::Small;
     int best_rt = 0;

@@ -10,9 +10,10 @@ default is:
   128; a forced bit kernel pads the replicas to 256), in tiles of 256, 128 or 64
   replicas (each forced through PBIT_BQ_BITS_RT too).  The batched engine's bit
   tiles run under this variant too;
-* 4: sides of at most 512 sites held in LDS with their couplings (two-bit codes of
-  J + 1 in both orientations) for runs of sweeps in one launch, 16 or 8 replicas
-  per workgroup (each forced through PBIT_BQ_SLAB_RS), on the int8 MFMA 16 x 16 x 64.
+* 4: sides of at most 512 sites held in LDS with their couplings (two-bit codes in
+  both orientations, widened to fp4) for runs of sweeps in one launch, 16 or 8
+  replicas per workgroup (each forced through PBIT_BQ_SLAB_RS), on the fp8 x fp4
+  MFMA 16 x 16 x 128 with fp32 sums.
 
 Each kernel is checked on every replica after every sweep on ragged sides, on
 sampled replicas at full size (n = 1024 and 4096, 1024 replicas), and at 128
@@ -55,8 +56,8 @@ def _forced_context(variant):
 
 def _biclique_with_zeros(na, nb, seed, field="uniform3"):
     """Couplings in {-1, 0, +1}, about a third of them zero (the diluted form the
-    problem statement allows), and fields in {-1, 0, +1} or none: the middle value
-    of the two-bit coupling codes occurs only here."""
+    problem statement allows), and fields in {-1, 0, +1} or none: the zero
+    coupling, a code of its own in the two-bit forms, occurs only here."""
     inst = synth.biclique_instance(na, seed=seed, nb=nb, field=field)
     rng = np.random.default_rng(seed + 1)
     inst["J"] = (inst["J"] * (rng.random(inst["J"].shape) < 0.65)).astype(np.int8)
@@ -276,8 +277,8 @@ def test_slab_every_replica_every_sweep(slab_ctx, na, nb, R):
 @pytest.mark.parametrize("na,nb,R,field", [(300, 200, 40, "uniform3"), (512, 512, 33, "uniform3"),
                                            (70, 130, 17, "zero")])
 def test_slab_zero_couplings_every_sweep(slab_ctx, na, nb, R, field):
-    """Diluted couplings (code 1 of the two-bit codes) in the LDS-resident form, with
-    fields and without."""
+    """Diluted couplings (the zero code, an fp4 zero on the matrix cores) in the
+    LDS-resident form, with fields and without."""
     inst = _biclique_with_zeros(na, nb, seed=na + 13 * nb + R, field=field)
     _say("slab diluted biclique %dx%d R=%d every sweep" % (na, nb, R))
     _every_sweep(slab_ctx, inst, synth.beta_linear(0.05, 2.0, 10), R, seed=29)
