@@ -194,9 +194,9 @@ def measured_traffic(workload, kernel=None):
 
 
 def _bag_dtype():
-    """Arithmetic of the batched tiles: int8 spins and couplings, biclique fields as
-    int8 MFMA products with int32 sums."""
-    return "int8"
+    """Arithmetic of the batched tiles: int8 cube spins and couplings; biclique fields
+    as fp8 spin x fp4 coupling MFMA products with fp32 sums (exact integers)."""
+    return "int8,fp8xfp4"
 
 
 def mixed_bag_bench(args, pbit, torch):

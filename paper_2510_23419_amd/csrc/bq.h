@@ -21,8 +21,9 @@ struct BqView {
     const int8_t *JTb;
     const int32_t *hA2;  // [na_p]
     const int32_t *hB2;  // [nb_p]
-    // for the batched int8 tiles: J + 1 (padding included) as two-bit codes, 16 per word,
-    // in MFMA fragment order (see load_biclique), [na_p * nb_p / 16] and [nb_p * na_p / 16]
+    // for the batched int8-row tiles: (sign, nonzero) two-bit codes, 16 per word, placed
+    // for fp4 operands, in MFMA fragment order (see load_biclique), [na_p * nb_p / 16] and
+    // [nb_p * na_p / 16]
     const uint32_t *J2;
     const uint32_t *JT2;
 };

@@ -367,19 +367,23 @@ static int load_biclique(pbit_ctx *ctx, const pbit_problem_desc *d, Problem &p)
     }
     void *dJ2 = nullptr, *dJT2 = nullptr;
     if (rc == PBIT_OK) {
-        // two-bit couplings for the batched int8 tiles: J + 1 in {0, 1, 2}, padding included
-        // (J = 0 there, so the code is 1: the tiles subtract every spin of the other side,
-        // and padding spins take arbitrary values after the first update), 16 per word in
-        // fragment order: word ((blk nku + u) 2 + g) 32 + l holds row 32 blk + l, columns
-        // 32 u + 16 g + 4 j + i, as bits 2 j (low) and 2 j + 1 (high) of byte i
+        // two-bit couplings for the batched int8-row tiles (fp4 operands on the fp8 x fp4
+        // MFMA): per coupling a sign bit and a nonzero bit (padding 0), 16 per word in
+        // fragment order: the pair of words (((blk nku + u) 2 + g) 32 + l) holds row
+        // 32 blk + l, columns 64 u + 32 g + 16 h + k (word h of the pair); for k < 8 the
+        // nonzero bit of column k sits at bit 4 k + 1 and the sign at 4 k + 3, for k >= 8 at
+        // 4 (k - 8) and 4 (k - 8) + 2, so that a mask, or a shift and a mask, gives fp4 e2m1
         auto pack2 = [](const std::vector<int8_t> &M, int rows, int cols, std::vector<uint32_t> &out) {
-            const int nku = cols / 32;
+            const int nku = cols / 64;
             out.assign((size_t)rows * cols / 16, 0u);
             for (int r = 0; r < rows; ++r)
                 for (int c = 0; c < cols; ++c) {
-                    const uint32_t v = (uint32_t)(M[(size_t)r * cols + c] + 1);
-                    const int blk = r / 32, l = r % 32, u = c / 32, g = (c / 16) % 2, j = (c / 4) % 4, i = c % 4;
-                    out[(((size_t)blk * nku + u) * 2 + g) * 32 + l] |= v << (8 * i + 2 * j);
+                    const int v = M[(size_t)r * cols + c];
+                    if (v == 0) continue;
+                    const int blk = r / 32, l = r % 32, u = c / 64, g = (c / 32) % 2, h = (c / 16) % 2, k = c % 16;
+                    const int at = k < 8 ? 4 * k + 1 : 4 * (k - 8);
+                    const size_t word = ((((size_t)blk * nku + u) * 2 + g) * 32 + l) * 2 + h;
+                    out[word] |= (1u << at) | ((v < 0 ? 1u : 0u) << (at + 2));
                 }
         };
         std::vector<uint32_t> J2, JT2;
