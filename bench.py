@@ -560,14 +560,15 @@ def main():
         alg_ops = 2 * n * n * R  # one side's fields: n x n couplings times n x R spins
         # the kernel the library ran (autotuned unless PBIT_BQ_VARIANT forces one)
         variant = pbit.pbit_profile_variant(ctx.ctx)
-        # the LDS-resident kernel multiplies fp8 spins by fp4 couplings (fp32 sums), the
-        # others int8 by int8 (int32 sums); every product and sum is an exact integer
-        slab = variant == 4
+        # the kernels multiply fp8 spins by fp4 couplings (fp32 sums) or int8 by int8
+        # (int32 sums), as the library reports; every product and sum is an exact integer
+        operands = {1: "int8", 2: "fp8xfp4", 3: "int8,fp8xfp4"}.get(pbit.pbit_profile_operands(ctx.ctx), "int8")
+        fp = operands == "fp8xfp4"
         roof = {"bound": "mfma", "achieved": alg_ops / (avg_ms * 1e-3) / 1e12,
-                "peak": FP8_MFMA_PEAK_TFLOPS if slab else INT8_MFMA_PEAK_TOPS,
-                "unit": "TFLOP/s" if slab else "TOP/s", "traffic": None,
+                "peak": FP8_MFMA_PEAK_TFLOPS if fp else INT8_MFMA_PEAK_TOPS,
+                "unit": "TFLOP/s" if fp else "TOP/s", "traffic": None,
                 "kernel": BQ_KERNELS.get(variant, "k_bq_halfsweep"), "variant": variant,
-                "operands": "fp8xfp4" if slab else "int8",
+                "operands": operands,
                 "alg_ops_per_launch": alg_ops, "avg_launch_us": avg_ms * 1e3, "launches_timed": launches}
     if launches == 0:  # launch timing switched off (--profile-every 0)
         roof["achieved"] = None

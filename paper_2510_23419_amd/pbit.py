@@ -40,7 +40,8 @@ EXPORTS = ("pbit_create", "pbit_destroy", "pbit_last_error", "pbit_bytes_in_use"
            "pbit_submit", "pbit_poll", "pbit_progress", "pbit_threshold_table", "pbit_version",
            "pbit_profile_enable", "pbit_profile_read", "pbit_anneal_batch", "pbit_serve_config",
            "pbit_load_graph", "pbit_problem_colouring", "pbit_greedy_colouring", "pbit_profile_variant",
-           "pbit_profile_ea_path", "pbit_anneal_dev_noalloc", "pbit_probe", "pbit_profile_graph", "pbit_profile_tiles")
+           "pbit_profile_ea_path", "pbit_anneal_dev_noalloc", "pbit_probe", "pbit_profile_graph", "pbit_profile_tiles",
+           "pbit_profile_operands")
 
 
 class PbitError(RuntimeError):
@@ -116,6 +117,7 @@ def lib() -> ctypes.CDLL:
             "pbit_profile_enable": ([P, i32], ctypes.c_int),
             "pbit_profile_read": ([P, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), i32], ctypes.c_int),
             "pbit_profile_variant": ([P, ctypes.POINTER(i32)], ctypes.c_int),
+            "pbit_profile_operands": ([P, ctypes.POINTER(i32)], ctypes.c_int),
             "pbit_profile_ea_path": ([P, ctypes.POINTER(i32)], ctypes.c_int),
             "pbit_profile_graph": ([P, ctypes.POINTER(i64), ctypes.POINTER(i64)], ctypes.c_int),
             "pbit_profile_tiles": ([P, ctypes.POINTER(i64), ctypes.POINTER(i32)], ctypes.c_int),
@@ -347,6 +349,14 @@ def pbit_profile_variant(ctx) -> int:
     """Biclique half-sweep kernel variant of the latest biclique anneal (0: none yet)."""
     v = ctypes.c_int32(0)
     _check(lib().pbit_profile_variant(ctx, ctypes.byref(v)))
+    return int(v.value)
+
+
+def pbit_profile_operands(ctx) -> int:
+    """MFMA operands of the latest biclique anneal: 1 int8 x int8, 2 fp8 x fp4, 3 one
+    side each (0: none yet)."""
+    v = ctypes.c_int32(0)
+    _check(lib().pbit_profile_operands(ctx, ctypes.byref(v)))
     return int(v.value)
 
 def pbit_probe(ctx, probe: int, size: int, reps: int = 20):
