@@ -173,8 +173,9 @@ def profile_record(workload, kernel=None):
         return None
     recs = json.load(open(path))
     # a workload's records: one per kernel that runs it (the cube's matrix-core
-    # half-sweep under "<workload>_mfma")
-    for rec in (recs.get(workload), recs.get(workload + "_mfma")):
+    # half-sweep under "<workload>_mfma", the graph's launch per colour class under
+    # "<workload>_class")
+    for rec in (recs.get(workload), recs.get(workload + "_mfma"), recs.get(workload + "_class")):
         if not rec or (kernel and kernel not in rec["kernel"]):
             continue
         h = hashlib.sha256()
@@ -534,7 +535,9 @@ def main():
         rec = profile_record(args.workload, "k_ea_slab")
         lops = None
         if rec and rec.get("valu_insts_per_dispatch"):
-            lops = float(rec["valu_insts_per_dispatch"]) * 64 / (N * R * rec["sweeps_per_dispatch"])
+            # the counter run's one launch holds all of its sweeps
+            sweeps = rec.get("sweeps_per_dispatch") or rec["pmc_sweeps"]
+            lops = float(rec["valu_insts_per_dispatch"]) * 64 / (N * R * sweeps)
         upd_per_s = (N * R / 2) / (avg_ms * 1e-3)  # updates per second inside the kernel
         roof = {"bound": "alu", "achieved": None if lops is None else upd_per_s * lops / 1e12,
                 "peak": VALU_PEAK_TLANEOPS, "unit": "Tlane-op/s", "traffic": None, "kernel": "k_ea_slab",
@@ -550,6 +553,21 @@ def main():
                 "unit": "GB/s", "traffic": None, "kernel": "k_eam_halfsweep" if ea_path == 3 else "k_ea_halfsweep",
                 "ea_path": ea_path,
                 "alg_bytes_per_launch": alg_bytes, "avg_launch_us": avg_ms * 1e3, "launches_timed": launches}
+    elif w["kind"] == "graph" and pbit.pbit_profile_graph_path(ctx.ctx) == 2:
+        # the graph held in LDS for runs of sweeps (a tile of replicas per workgroup): the
+        # vector ALU is the roof, as for the cube in LDS; the window counts one launch per
+        # colour class and sweep, so a "launch" is one class update on average
+        groups = pbit.pbit_problem_colouring(ctx.ctx, prob)[1]
+        rec = profile_record(args.workload, "k_graph_slab")
+        lops = None
+        if rec and rec.get("valu_insts_per_dispatch"):
+            sweeps = rec.get("sweeps_per_dispatch") or rec["pmc_sweeps"]
+            lops = float(rec["valu_insts_per_dispatch"]) * 64 / (N * R * sweeps)
+        upd_per_s = (N * R / groups) / (avg_ms * 1e-3)  # updates per second inside the kernel
+        roof = {"bound": "alu", "achieved": None if lops is None else upd_per_s * lops / 1e12,
+                "peak": VALU_PEAK_TLANEOPS, "unit": "Tlane-op/s", "traffic": None, "kernel": "k_graph_slab",
+                "groups": groups, "lane_ops_per_update": lops, "updates_per_s_in_kernel": upd_per_s,
+                "avg_class_update_us": avg_ms * 1e3, "class_updates_timed": launches}
     elif w["kind"] == "graph":
         alg_bytes, groups = graph_launch_bytes(ctx.ctx, prob, inst, R)
         roof = {"bound": "hbm", "achieved": alg_bytes / (avg_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
@@ -573,10 +591,11 @@ def main():
     if launches == 0:  # launch timing switched off (--profile-every 0)
         roof["achieved"] = None
     roof["frac"] = None if roof["achieved"] is None else roof["achieved"] / roof["peak"]
-    if ea_path != 2:
+    lds_resident = roof["bound"] == "alu"  # a cube or graph held in LDS: no per-launch HBM traffic
+    if not lds_resident:
         roof["traffic"] = measured_traffic(args.workload, roof["kernel"])
     rec = profile_record(args.workload, roof["kernel"])
-    if ea_path != 2 and rec and rec.get("valu_insts_per_dispatch") and launches:
+    if not lds_resident and rec and rec.get("valu_insts_per_dispatch") and launches:
         # vector ALU issue: wave instructions x 64 lanes per launch over the measured
         # launch time, against 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
         lane_ops = float(rec["valu_insts_per_dispatch"]) * 64

@@ -342,6 +342,17 @@ int pbit_profile_graph(pbit_ctx *ctx, int64_t *captures, int64_t *launches);
  * *path is written on success only. */
 int pbit_profile_ea_path(pbit_ctx *ctx, int32_t *path);
 
+/* The general-graph path of the latest graph anneal on this context (0 before
+ * any): 1 = one launch per colour class (every site of the class, 16 replicas per
+ * thread); 2 = the whole graph for a tile of 16, 8 or 4 replicas held in one
+ * workgroup's LDS for runs of up to 1000 sweeps per launch, taken when the graph's
+ * spins for 4 replicas fit (at most 39 936 spins), with the narrowest tile that
+ * fits and leaves at most two workgroups per compute unit (else the widest that
+ * fits).  When the context is created, PBIT_GRAPH_SLAB=0 keeps path 1 and
+ * PBIT_GRAPH_SLAB=4, 8 or 16 forces that tile width where it fits.  Both paths give
+ * the same spins.  *path is written on success only. */
+int pbit_profile_graph_path(pbit_ctx *ctx, int32_t *path);
+
 /* The ceilings the sweep kernels are measured against, each timed as a kernel of
  * its own over `reps` launches (after one warm-up launch) on the context's
  * stream.  *ms_per_launch receives the mean launch time and *work_per_launch

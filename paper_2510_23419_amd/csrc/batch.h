@@ -51,6 +51,9 @@ struct GraphJobDev {
     int32_t *energy;           // [tiles * rs]
     int n, n_bonds, n_colours, width, rs;
     uint32_t sweep0, rq0, k0, k1;
+    // 0: the layout above; else the bytes from one site's row to the next in a [n][row_stride]
+    // matrix whose columns [rs t, + rs) are tile t (the per-instance spins, row_stride = Rp)
+    int row_stride = 0;
 };
 
 struct WorkItem {
@@ -81,6 +84,10 @@ hipError_t bq_tiles(const BqJobDev *jobs, const WorkItem *items, const int32_t *
 
 hipError_t graph_tiles(const GraphJobDev *jobs, const WorkItem *items, const int32_t *n_items, int32_t *counter,
                        int grid, size_t lds_bytes, hipStream_t st);
+// The per-instance graph sweep held in LDS: sweeps [s_begin, s_end) of tiles [0, tiles) of
+// job `jb` (row_stride set: the spins stay in the per-instance [n][Rp] layout), one
+// workgroup per tile, no work queue.  jb.energy receives each replica's energy.
+hipError_t graph_slab(const GraphJobDev &jb, int tiles, int s_begin, int s_end, hipStream_t st);
 
 // LDS a tile kernel needs for the given job shape.
 size_t ea_tile_lds(int64_t N, int rs);  // rs = 4, 8 or 16 replicas

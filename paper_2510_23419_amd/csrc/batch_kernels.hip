@@ -265,7 +265,9 @@ __device__ __forceinline__ void graph_tile_item(const WorkItem &w, const GraphJo
     const int tid = threadIdx.x;
     const int n = jb.n;
     const uint32_t rgw = jb.rq0 + (uint32_t)W * (uint32_t)w.tile;  // Philox counter word 2 of the tile's first group
-    V *gst = reinterpret_cast<V *>(jb.state) + (size_t)w.tile * n;
+    // the tile's rows: contiguous (batch state) or strided columns of the per-instance spins
+    const size_t rstride = jb.row_stride ? (size_t)jb.row_stride : (size_t)RS;
+    int8_t *gst = jb.state + (size_t)w.tile * (jb.row_stride ? (size_t)RS : (size_t)n * RS);
 
     if (w.init) {
         for (int i = tid; i < n; i += kGraphTileThreads) {
@@ -281,7 +283,7 @@ __device__ __forceinline__ void graph_tile_item(const WorkItem &w, const GraphJo
             rows[i] = d;
         }
     } else {
-        for (int i = tid; i < n; i += kGraphTileThreads) rows[i] = load_global<V>(gst + i);
+        for (int i = tid; i < n; i += kGraphTileThreads) rows[i] = load_global<V>(gst + rstride * i);
     }
 
     for (int s = w.s_begin; s < w.s_end; ++s) {
@@ -372,7 +374,7 @@ __device__ __forceinline__ void graph_tile_item(const WorkItem &w, const GraphJo
     }
     __syncthreads();
     if (tid < RS) jb.energy[RS * w.tile + tid] = eacc[tid];
-    for (int i = tid; i < n; i += kGraphTileThreads) gst[i] = rows[i];
+    for (int i = tid; i < n; i += kGraphTileThreads) *reinterpret_cast<V *>(gst + rstride * i) = rows[i];
 }
 
 // Persistent graph-tile kernel: items of any tile width share the launch.
@@ -399,6 +401,20 @@ __global__ __launch_bounds__(kGraphTileThreads) void k_graph_tiles(const GraphJo
             graph_tile_item<1>(w, jb, tile_rows, gtab, eacc, one);
         __syncthreads();  // the next item's first LDS writes wait for this item's last reads
     }
+}
+
+// The per-instance graph sweep held in LDS: workgroup t runs tile t (replicas
+// [4 W t, + 4 W)) of the job for sweeps [s_begin, s_end), reading and writing its
+// columns of the per-instance spins.
+template <int W>
+__global__ __launch_bounds__(kGraphTileThreads) void k_graph_slab(GraphJobDev jb, int s_begin, int s_end,
+                                                                  uint32_t one)
+{
+    extern __shared__ uint4 tile_rows[];
+    __shared__ uint64_t gtab[kGraphSlots];
+    __shared__ int32_t eacc[16];
+    const WorkItem w{0, (int)blockIdx.x, s_begin, s_end, 0, {0, 0, 0}};
+    graph_tile_item<W>(w, jb, tile_rows, gtab, eacc, one);
 }
 
 // ---------------------------------------------------------------- biclique tiles
@@ -836,6 +852,29 @@ size_t bq_tile_lds(int rs, int na_p, int nb_p, int width, int mode)
     else
         rows = (size_t)rs * ((size_t)(na_p + nb_p) + 16);
     return rows + sizeof(uint64_t) * (size_t)(2 * width - 1);
+}
+
+template <int W>
+static hipError_t graph_slab_launch(const GraphJobDev &jb, int tiles, int s_begin, int s_end, hipStream_t st)
+{
+    static const hipError_t lds_attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_graph_slab<W>),
+                                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                           160 * 1024 - 4096);
+    if (lds_attr != hipSuccess) return lds_attr;
+    hipLaunchKernelGGL(k_graph_slab<W>, dim3((unsigned)tiles), dim3(kGraphTileThreads), graph_tile_lds(jb.n, 4 * W),
+                       st, jb, s_begin, s_end, 1u);
+    return hipGetLastError();
+}
+
+hipError_t graph_slab(const GraphJobDev &jb, int tiles, int s_begin, int s_end, hipStream_t st)
+{
+    if (tiles < 1 || jb.row_stride % 16 != 0 || jb.row_stride < tiles * jb.rs || s_end < s_begin ||
+        graph_tile_lds(jb.n, jb.rs) > (size_t)(160 * 1024 - 4096))
+        return hipErrorInvalidValue;
+    if (jb.rs == 16) return graph_slab_launch<4>(jb, tiles, s_begin, s_end, st);
+    if (jb.rs == 8) return graph_slab_launch<2>(jb, tiles, s_begin, s_end, st);
+    if (jb.rs == 4) return graph_slab_launch<1>(jb, tiles, s_begin, s_end, st);
+    return hipErrorInvalidValue;
 }
 
 hipError_t tiles_set_lds_limit()

@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "../../include/pbit.h"
+#include "batch.h"
 #include "internal.h"
 #include "runtime_internal.h"
 
@@ -131,6 +132,11 @@ extern "C" int pbit_create(pbit_ctx **out, int device, uint64_t hbm_budget_bytes
     }
     if (const char *v = std::getenv("PBIT_BQ_BITS_RT")) ctx->bq_bits_rt = std::atoi(v);  // tuning override
     if (const char *v = std::getenv("PBIT_BQ_BITS_F4")) ctx->bq_bits_f4 = std::atoi(v) != 0;  // tuning override
+    if (const char *v = std::getenv("PBIT_GRAPH_SLAB")) {  // tuning override: 0 off, 4 / 8 / 16 a tile width
+        const int k = std::atoi(v);
+        ctx->graph_slab = k != 0;
+        ctx->graph_slab_rs = k == 4 || k == 8 || k == 16 ? k : 0;
+    }
     if (const char *v = std::getenv("PBIT_BQ_SLAB_RS")) {  // tuning override: 16 or 8
         const int k = std::atoi(v);
         ctx->bq_slab_rs = k == 16 || k == 8 ? k : 0;
@@ -678,7 +684,9 @@ struct DevState {
     int bits_rt = 0;  // replicas per tile of the bit kernel (0: its launcher's rule)
     bool bits_f4 = true;  // the bit kernel's fp4 couplings where the other side is a multiple of 256
     int slab_rs = 0;  // replicas per slice of the LDS-resident biclique kernel (0: its launcher's rule)
-    bool slab = false;        // cube held in LDS for runs of sweeps (ea_slab)
+    bool slab = false;        // cube, graph or small biclique held in LDS for runs of sweeps
+    int graph_rs = 0;         // replicas per workgroup of the LDS-resident graph sweep (graph_slab)
+    int32_t *graph_energy = nullptr;  // its per-replica energies (not used by the runtime)
     bool mfma = false;        // cube fields on the matrix cores (ea_mfma.hip), spins [2][Rp][N / 2]
     Arena *arena = nullptr;   // set: buffers are carved from it (no allocation, no kernel timing)
 };
@@ -697,7 +705,8 @@ static int take(pbit_ctx *ctx, DevState &ds, Slot slot, size_t bytes, void **out
     return PBIT_OK;
 }
 
-constexpr int kSlabChunk = 1000;  // sweeps per launch of the LDS-resident cube and biclique kernels
+constexpr int kSlabChunk = 1000;  // sweeps per launch of the LDS-resident cube, graph and biclique kernels
+constexpr size_t kGraphSlabLds = 160 * 1024 - 4096;  // spin rows of a graph tile in LDS (beside its decision words)
 
 // Pick the biclique kernel variant for this shape: the forced one, a cached
 // choice, or the fastest of the candidates timed here on the (not yet
@@ -941,6 +950,28 @@ static int prepare(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, h
             if (e != hipSuccess) return device_fail(ctx, e, "spin bit buffer clear");
         }
     }
+    if (P.kind == PBIT_GRAPH && ctx->graph_slab) {
+        // the whole graph for a tile of replicas in LDS, runs of sweeps per launch: the
+        // narrowest tile (4, 8 or 16 replicas) that fits and leaves at most two workgroups
+        // per compute unit, else the widest that fits.  Measured on the L = 14 dimerized
+        // cube: a workgroup's sweep costs about the same at any tile width up to two per
+        // CU, so narrow tiles spread small replica counts over more CUs, and past two per
+        // CU the wider tile wins.
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess) cus = 256;
+        for (int rs : {4, 8, 16}) {
+            if (ds.Rp % rs != 0 || graph_tile_lds(P.N, rs) > kGraphSlabLds) continue;
+            if (ctx->graph_slab_rs && rs != ctx->graph_slab_rs) continue;
+            ds.graph_rs = rs;
+            if (ds.Rp / rs <= 2 * cus) break;
+        }
+        if (ds.graph_rs) {
+            rc = take(ctx, ds, Slot::Aux, sizeof(int32_t) * (size_t)ds.Rp, &v);
+            if (rc) return rc;
+            ds.graph_energy = (int32_t *)v;
+            ds.slab = true;
+        }
+    }
     rc = take(ctx, ds, Slot::E32, sizeof(int32_t) * (size_t)ds.Rp, &v);
     if (rc) return rc;
     ds.E32 = (int32_t *)v;
@@ -967,6 +998,7 @@ static int prepare(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, h
     ds.bits = P.kind == PBIT_BICLIQUE && ds.variant == BqVariant::Bits;
     if (P.kind == PBIT_BICLIQUE && ds.variant == BqVariant::Slab) ds.slab = true;  // runs of sweeps per launch
     if (P.kind == PBIT_EA3D && d->n_sweeps > 0) ctx->ea_last_path = ds.slab ? 2 : (ds.mfma ? 3 : 1);
+    if (P.kind == PBIT_GRAPH && d->n_sweeps > 0) ctx->graph_last_path = ds.slab ? 2 : 1;
     if (P.kind == PBIT_BICLIQUE && d->n_sweeps > 0) {
         ctx->bq_last_variant = (int)ds.variant;
         // operands: the LDS-resident kernel always multiplies fp8 by fp4; the bit kernel
@@ -1046,12 +1078,23 @@ static hipError_t sweeps(pbit_ctx *ctx, const Problem &P, DevState &ds, int s0, 
     hipError_t e = hipSuccess;
     const bool timed = ctx->prof_every > 0 && ctx->prof_open < 0;
     if (timed) e = prof_begin(ctx, P.kind, st);
-    if (e == hipSuccess)
-        e = P.kind == PBIT_BICLIQUE ? bq_slab(P.bq, ds.MA, ds.MB, ds.Rp, ds.table, ds.width, s0, s1, sweep0, rq0, key, st,
-                                              ds.slab_rs)
-                                    : ea_slab(P.ea, ds.spins, ds.Rp, ds.table, ds.width, s0, s1, sweep0, rq0, key, st);
+    if (e == hipSuccess) {
+        if (P.kind == PBIT_BICLIQUE) {
+            e = bq_slab(P.bq, ds.MA, ds.MB, ds.Rp, ds.table, ds.width, s0, s1, sweep0, rq0, key, st, ds.slab_rs);
+        } else if (P.kind == PBIT_GRAPH) {
+            const GraphView &g = P.graph;
+            GraphJobDev jb{reinterpret_cast<const int4 *>(g.site_meta), g.adj, g.class_start_dev, g.bi, g.bj, g.bJ,
+                           g.h, ds.table, ds.spins, ds.graph_energy, g.n, g.n_bonds, g.n_colours, ds.width,
+                           ds.graph_rs, sweep0, rq0, key.k0, key.k1};
+            jb.row_stride = ds.Rp;
+            e = graph_slab(jb, ds.Rp / ds.graph_rs, s0, s1, st);
+        } else {
+            e = ea_slab(P.ea, ds.spins, ds.Rp, ds.table, ds.width, s0, s1, sweep0, rq0, key, st);
+        }
+    }
     if (e == hipSuccess && timed) {
-        ctx->prof_launches.back() += 2 * (s1 - s0);
+        // counted as its class updates: two per sweep for a cube or biclique, one per colour class
+        ctx->prof_launches.back() += (P.kind == PBIT_GRAPH ? P.graph.n_colours : 2) * (s1 - s0);
         e = prof_close(ctx, st);
     }
     return e;
@@ -1514,6 +1557,14 @@ extern "C" int pbit_profile_ea_path(pbit_ctx *ctx, int32_t *path)
     PBIT_ENTER(ctx);
     if (!path) return fail(PBIT_E_ARG, "pbit_profile_ea_path: path is NULL");
     *path = ctx->ea_last_path;
+    return PBIT_OK;
+}
+
+extern "C" int pbit_profile_graph_path(pbit_ctx *ctx, int32_t *path)
+{
+    PBIT_ENTER(ctx);
+    if (!path) return fail(PBIT_E_ARG, "pbit_profile_graph_path: path is NULL");
+    *path = ctx->graph_last_path;
     return PBIT_OK;
 }
 

@@ -88,6 +88,9 @@ struct pbit_ctx {
     uint64_t graph_key = 0;
     int64_t graph_captures = 0, graph_launches = 0;
     int ea_last_path = 0;           // cube path of the latest cube anneal: 1 stream, 2 LDS-resident (0: none)
+    int graph_last_path = 0;        // graph path of the latest graph anneal: 1 per class, 2 LDS-resident (0: none)
+    bool graph_slab = true;         // graphs that fit LDS run there (PBIT_GRAPH_SLAB=0: one launch per class)
+    int graph_slab_rs = 0;          // its tile width when forced (PBIT_GRAPH_SLAB=4, 8 or 16; 0: by the rule)
     // (na_p, nb_p, Rp, LDS form possible) -> fastest kernel and its replica tile (bit kernel) or
     // slice (LDS-resident kernel)
     std::map<std::array<int, 4>, std::pair<pbit::BqVariant, int>> bq_tuned;

@@ -1,7 +1,11 @@
 """General sparse graphs with k update groups (paper Sec. 1.2.2): the HIP
 path through the C ABI against the oracle, bit-exact, on odd cubes (which a
 checkerboard cannot colour), random sparse graphs with fields and zero
-couplings, caller-given colourings, and the degree limits."""
+couplings, caller-given colourings, and the degree limits.  Every test runs on
+both per-instance paths: graphs that fit LDS held there for runs of sweeps (the
+default tile width, and tiles of 16 and 8 replicas forced through
+PBIT_GRAPH_SLAB) and one launch per colour class (PBIT_GRAPH_SLAB=0)."""
+import os
 import sys
 
 import numpy as np
@@ -19,9 +23,21 @@ def _say(msg):
     sys.stdout.flush()
 
 
-@pytest.fixture(scope="module")
-def ctx():
-    c = pbit.Context(0)
+SLAB = {}  # context -> graphs that fit LDS run there
+
+
+@pytest.fixture(scope="module", params=["1", "16", "8", "0"], ids=["slab", "slab_rs16", "slab_rs8", "per_class"])
+def ctx(request):
+    old = os.environ.get("PBIT_GRAPH_SLAB")
+    os.environ["PBIT_GRAPH_SLAB"] = request.param
+    try:
+        c = pbit.Context(0)
+    finally:
+        if old is None:
+            del os.environ["PBIT_GRAPH_SLAB"]
+        else:
+            os.environ["PBIT_GRAPH_SLAB"] = old
+    SLAB[c.ctx.value] = request.param != "0"
     yield c.ctx
     c.close()
 
@@ -106,6 +122,7 @@ def test_dimerized_cube_benchmark_size_sampled(ctx):
     beta = synth.beta_geometric(0.1, 5.0, 2000)[:12]
     _say("dimerized cube L=14 R=4096 S=12")
     got = pbit.pbit_anneal(ctx, prob, beta, 4096, seed=1)
+    assert pbit.pbit_profile_graph_path(ctx) == (2 if SLAB[ctx.value] else 1)
     og = _oracle_graph(g)
     for off in (0, 1360, 4092):
         ref = oracle.anneal(og, beta, 4, seed=1, replica_offset=off)
@@ -204,6 +221,7 @@ def test_large_graph_sampled_replicas(ctx):
     beta = synth.beta_linear(0.1, 2.0, 20)
     _say("graph n=100000 R=512 S=20")
     got = pbit.pbit_anneal(ctx, prob, beta, 512, seed=21)
+    assert pbit.pbit_profile_graph_path(ctx) == 1  # 100k spins do not fit LDS
     og = _oracle_graph(g)
     for off in (0, 252, 508):
         ref = oracle.anneal(og, beta, 4, seed=21, replica_offset=off)
