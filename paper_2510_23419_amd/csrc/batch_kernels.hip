@@ -306,14 +306,23 @@ __device__ __forceinline__ void graph_tile_item(const WorkItem &w, const GraphJo
                 uint32_t cnt[W];
 #pragma unroll
                 for (int k = 0; k < W; ++k) cnt[k] = 0u;
-                for (int e = m.y; e < m.z; ++e) {
-                    const uint32_t a = load_global<uint32_t>(jb.adj + e);
-                    const V v = rows[a >> 2];
-                    // 0x02 in every byte where J != 0 (keep) and where J = -1 (flip)
-                    const uint32_t keep = (uint32_t)((int32_t)(a << 31) >> 31) & 0x02020202u;
-                    const uint32_t flip = (uint32_t)((int32_t)(a << 30) >> 31) & 0x02020202u;
+                // four adjacency entries, then their four rows, in flight together; an entry
+                // past the end reads as 0 (row 0, no coupling), so it adds nothing
+                for (int e = m.y; e < m.z; e += 4) {
+                    uint32_t a[4];
 #pragma unroll
-                    for (int k = 0; k < W; ++k) cnt[k] += neg2(v[k], keep, flip);
+                    for (int u = 0; u < 4; ++u) a[u] = e + u < m.z ? load_global<uint32_t>(jb.adj + e + u) : 0u;
+                    V v[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) v[u] = rows[a[u] >> 2];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        // 0x02 in every byte where J != 0 (keep) and where J = -1 (flip)
+                        const uint32_t keep = (uint32_t)((int32_t)(a[u] << 31) >> 31) & 0x02020202u;
+                        const uint32_t flip = (uint32_t)((int32_t)(a[u] << 30) >> 31) & 0x02020202u;
+#pragma unroll
+                        for (int k = 0; k < W; ++k) cnt[k] += neg2(v[u][k], keep, flip);
+                    }
                 }
                 // a byte c of cnt (two per negative product) gives I = base - c: entry kGraphOff - base + c
                 const char *tb = reinterpret_cast<const char *>(gtab) + 8 * (kGraphOff - m.w);
