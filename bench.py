@@ -12,7 +12,7 @@ sizes, printed in the same format.
 
 Prints one JSON line with the throughput in p-bit updates per second (one
 update = one spin of one replica in one sweep), the roofline of the dominant
-kernel (its algorithmic bytes or matrix-core ops per launch over its mean launch time,
+kernel (its algorithmic bytes or int8 ops per launch over its mean launch time,
 measured with HIP events on the stream the kernels run on), and the CPU
 oracle timed on a bounded sample of the same workload.
 """
@@ -29,7 +29,6 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 INT8_MFMA_PEAK_TOPS = 5000.0   # MI355X dense int8 MFMA, published (TOP/s)
-FP8_MFMA_PEAK_TFLOPS = 5000.0  # MI355X dense fp8 MFMA, published (TFLOP/s); fp8 x fp4 issues at the fp8 rate
 # biclique half-sweep kernels by variant number (pbit_profile_variant)
 BQ_KERNELS = {1: "k_bq_halfsweep", 2: "k_bq_halfsweep_dma", 3: "k_bq_halfsweep_bits", 4: "k_bq_slab"}
 VALU_PEAK_TLANEOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 32-bit vector lane-ops/s: CUs x SIMDs x lanes x clock
@@ -195,9 +194,9 @@ def measured_traffic(workload, kernel=None):
 
 
 def _bag_dtype():
-    """Arithmetic of the batched tiles: int8 cube spins and couplings; biclique fields
-    as fp8 spin x fp4 coupling MFMA products with fp32 sums (exact integers)."""
-    return "int8,fp8xfp4"
+    """Arithmetic of the batched tiles: int8 spins and couplings, biclique fields as
+    int8 MFMA products with int32 sums."""
+    return "int8"
 
 
 def mixed_bag_bench(args, pbit, torch):
@@ -578,15 +577,9 @@ def main():
         alg_ops = 2 * n * n * R  # one side's fields: n x n couplings times n x R spins
         # the kernel the library ran (autotuned unless PBIT_BQ_VARIANT forces one)
         variant = pbit.pbit_profile_variant(ctx.ctx)
-        # the kernels multiply fp8 spins by fp4 couplings (fp32 sums) or int8 by int8
-        # (int32 sums), as the library reports; every product and sum is an exact integer
-        operands = {1: "int8", 2: "fp8xfp4", 3: "int8,fp8xfp4"}.get(pbit.pbit_profile_operands(ctx.ctx), "int8")
-        fp = operands == "fp8xfp4"
         roof = {"bound": "mfma", "achieved": alg_ops / (avg_ms * 1e-3) / 1e12,
-                "peak": FP8_MFMA_PEAK_TFLOPS if fp else INT8_MFMA_PEAK_TOPS,
-                "unit": "TFLOP/s" if fp else "TOP/s", "traffic": None,
-                "kernel": BQ_KERNELS.get(variant, "k_bq_halfsweep"), "variant": variant,
-                "operands": operands,
+                "peak": INT8_MFMA_PEAK_TOPS, "unit": "TOP/s", "traffic": None,
+                "kernel": BQ_KERNELS.get(variant, "k_bq_halfsweep"), "variant": variant, "operands": "int8",
                 "alg_ops_per_launch": alg_ops, "avg_launch_us": avg_ms * 1e3, "launches_timed": launches}
     if launches == 0:  # launch timing switched off (--profile-every 0)
         roof["achieved"] = None

@@ -306,15 +306,6 @@ int pbit_profile_read(pbit_ctx *ctx, int32_t kind, double *total_ms, int64_t *la
  * timed choice.  All give the same spins.  *variant is written on success only. */
 int pbit_profile_variant(pbit_ctx *ctx, int32_t *variant);
 
-/* The matrix-core operands of the latest biclique anneal's half-sweeps on this
- * context (0 before any): 1 = int8 spins x int8 couplings with int32 sums; 2 = fp8
- * e4m3 spin bytes x fp4 e2m1 couplings with fp32 sums (the LDS-resident kernel, and
- * the bit kernel where both sides are multiples of 256 and its fp4 form was timed
- * faster or forced); 3 = the bit kernel with fp4 couplings for one side only.  Every
- * product and sum is a small integer in all of them, so results are the same.
- * *operands is written on success only. */
-int pbit_profile_operands(pbit_ctx *ctx, int32_t *operands);
-
 /* Graph use of pbit_anneal_dev on this context.  With PBIT_GRAPH=1 set when the
  * context is created, the sweep launches of pbit_anneal_dev are captured into
  * one HIP graph, instantiated and launched; the executable graph is kept and

@@ -29,7 +29,7 @@ struct BqJobDev {
     const int8_t *J, *JT;     // int8 couplings [na_p][nb_p], [nb_p][na_p]
     const int8_t *Jb, *JTb;   // couplings in the widened-bit column order, scaled (bit tiles)
     const int32_t *hA2, *hB2; // field plus coupling sum per site (bit tiles)
-    const uint32_t *J2, *JT2; // two-bit (sign, nonzero) codes in fragment order (int8-row tiles)
+    const uint32_t *J2, *JT2; // J + 1 as two-bit codes in fragment order (int8 tiles)
     const int8_t *hA, *hB;    // [na_p], [nb_p]
     const uint32_t *table;    // [S][width]
     uint8_t *state;           // [tiles][RS][row]: row r = side A then side B, as int8 (na_p + nb_p

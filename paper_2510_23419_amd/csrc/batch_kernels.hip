@@ -20,8 +20,6 @@ namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
-typedef int v8i __attribute__((ext_vector_type(8)));
-typedef float v16f __attribute__((ext_vector_type(16)));
 
 typedef unsigned v2u __attribute__((ext_vector_type(2)));
 typedef unsigned v4u __attribute__((ext_vector_type(4)));
@@ -450,22 +448,18 @@ __device__ __forceinline__ uint32_t quad_transpose(uint32_t d, int u)
     return __builtin_amdgcn_perm(t2, d1, (u & 2) ? 0x03020706u : 0x05040100u);
 }
 
-// The fp4 e2m1 B operand of one K unit (32 couplings of a site) from a pair of two-bit
-// code words: a word holds 16 couplings as (sign, nonzero) bits, the first eight at
-// nibble bits 3 and 1, the last eight at bits 2 and 0, so that a mask, or a shift and
-// a mask, leaves eight e2m1 values (+1 0x2, -1 0xA, 0).
-constexpr uint32_t kFp4Mask = 0xAAAAAAAAu;
-__device__ __forceinline__ v8i fp4_operand(v2u c)
+// Four dwords of int8 K bytes from one word of two-bit codes: byte i of dword j is
+// the code at bits 2 j, 2 j + 1 of byte i (the value J + 1 in {0, 1, 2}).
+__device__ __forceinline__ v4i widen_codes(uint32_t x)
 {
-    return v8i{(int)(c.x & kFp4Mask), (int)((c.x << 1) & kFp4Mask), (int)(c.y & kFp4Mask),
-               (int)((c.y << 1) & kFp4Mask), 0, 0, 0, 0};
+    return v4i{(int)(x & 0x03030303u), (int)((x >> 2) & 0x03030303u), (int)((x >> 4) & 0x03030303u),
+               (int)((x >> 6) & 0x03030303u)};
 }
 
-// fp8 e4m3 bytes (+1 0x38, -1 0xB8, 0) of four int8 spins (+1, -1, 0), and back
-__device__ __forceinline__ uint32_t int8_to_fp8(uint32_t x) { return (x & 0x01010101u) * 0x38u | (x & 0x80808080u); }
-__device__ __forceinline__ uint32_t fp8_to_int8(uint32_t y)
+// Sum of the four bytes of x.
+__device__ __forceinline__ int byte_sum(uint32_t x)
 {
-    return ((y >> 3) & 0x01010101u) | ((y >> 7) & 0x01010101u) * 0xFEu;
+    return (int)((x & 0xFFu) + ((x >> 8) & 0xFFu) + ((x >> 16) & 0xFFu) + (x >> 24));
 }
 
 // Biclique tiles with the spins held as bits in LDS: row r holds one bit per site (set = -1), 32 sites per word, side A
@@ -639,16 +633,15 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles_bits(const BqJobDev
 }
 
 // A tile holds RB x 32 replicas of both sides in LDS, one row per replica:
-// side A first, then side B, zero padding.  A row holds one fp8 e4m3 byte per
-// site (+1, -1), and the half-sweep is the fp8 x fp4 MFMA
-// (v_mfma_scale_f32_32x32x64_f8f6f4, unit scales) with fp32 sums, exact for
-// these small integers; the couplings stream as two-bit codes (a quarter of
-// int8 bytes: these tiles are bound by how fast a CU pulls couplings from L2),
-// turned into fp4 operands by masks in registers.  Each half-sweep multiplies the
-// LDS rows by the couplings streamed from global memory (L2-resident, shared by
-// all tiles of the job); each coupling fragment feeds RB MFMAs, so larger tiles
-// stream fewer bytes per replica.  The decision epilogue writes the new side into
-// LDS.  The tile's state in global memory is int8, converted on load and store.
+// side A first, then side B, zero padding.  With int8 operands a row holds one
+// byte per site and the half-sweep is the int8 MFMA with int32
+// accumulation; the couplings stream as two-bit codes of J + 1 (a quarter of
+// the int8 bytes: these tiles are bound by how fast a CU pulls couplings from
+// L2), widened to bytes in registers, and the field is the product minus the
+// replica's sum over the other side's spins.  Each half-sweep multiplies the LDS rows by the
+// couplings streamed from global memory (L2-resident, shared by all tiles of
+// the job); each coupling fragment feeds RB MFMAs, so larger tiles stream
+// fewer bytes per replica.  The decision epilogue writes the new side into LDS.
 template <int RB>
 __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__restrict__ jobs,
                                                              const WorkItem *__restrict__ items,
@@ -658,6 +651,7 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
     constexpr int RS = 32 * RB;
     extern __shared__ uint4 dyn[];
     __shared__ int32_t eacc[RS];
+    __shared__ int32_t mag[RS];  // sum of the other side's spins per replica
     __shared__ int slot;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6, ln = lane & 31, kg = lane >> 5;
@@ -691,14 +685,13 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
                 const uint32_t i0 = (uint32_t)(A ? s0 : na + s0);
                 const Block4 b0 = philox(i0, 0u, rg0 + (uint32_t)g, kDomainInit, jb.k0, jb.k1);
 #pragma unroll
-                for (int p = 0; p < 4; ++p) sp[(4 * g + p) * pitch + pi] = init_spin(b0.w[p]) < 0 ? 0xB8 : 0x38;
+                for (int p = 0; p < 4; ++p) sp[(4 * g + p) * pitch + pi] = (uint8_t)init_spin(b0.w[p]);
             }
         } else {
             for (int k = tid; k < RS * (PR / 16); k += kBqTileThreads) {
                 const int r = k / (PR / 16), c16 = k % (PR / 16);
-                const uint4 v = *reinterpret_cast<const uint4 *>(gst + (size_t)r * PR + 16 * c16);
                 *reinterpret_cast<uint4 *>(sp + r * pitch + 16 * c16) =
-                    make_uint4(int8_to_fp8(v.x), int8_to_fp8(v.y), int8_to_fp8(v.z), int8_to_fp8(v.w));
+                    *reinterpret_cast<const uint4 *>(gst + (size_t)r * PR + 16 * c16);
             }
         }
         if (tid < RS) eacc[tid] = 0;
@@ -726,19 +719,41 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
                 const int8_t *hs = side == 0 ? jb.hA : jb.hB;
                 const uint32_t site_base = side == 0 ? 0u : (uint32_t)na;
                 // one 32-site block per wave at a time; its coupling fragments stream
-                // from global memory through a ring kRing K-units (64 couplings) ahead.
+                // from global memory through a ring kRing K-units (32 bytes) ahead.
                 // Past the end of a block the ring fills with the first units of the
                 // wave's next block, so that they arrive during this block's epilogue.
-                const int nku = ko / 64;
+                const int nku = ko / 32;
                 constexpr int kStep = kBqTileThreads / 64;
                 const int nblk = ns_p / 32;
-                // coupling fragments: [K unit][site block] of a pair of code words per lane,
-                // 64 pairs per K unit and block
-                using Frag = v2u;
+                {
+                    // the other side's spin sum per replica, padding sites included (their
+                    // codes are 1): T threads per row, bytewise
+                    // counts of nonzero and of -1 spins (at most 72 per byte for the
+                    // row lengths that fit LDS), then a sum over the T lanes
+                    constexpr int T = kBqTileThreads / RS;
+                    const int r = tid / T, part = tid % T;
+                    const uint4 *row = reinterpret_cast<const uint4 *>(sp + r * pitch + in_col);
+                    uint32_t nz = 0u, neg = 0u;
+#pragma unroll 4
+                    for (int d = part; d < ko / 16; d += T) {
+                        const uint4 x = row[d];
+                        nz += (x.x & 0x01010101u) + (x.y & 0x01010101u) + (x.z & 0x01010101u) + (x.w & 0x01010101u);
+                        neg += ((x.x >> 7) & 0x01010101u) + ((x.y >> 7) & 0x01010101u) + ((x.z >> 7) & 0x01010101u) +
+                               ((x.w >> 7) & 0x01010101u);
+                    }
+                    int v = byte_sum(nz) - 2 * byte_sum(neg);
+#pragma unroll
+                    for (int off = T / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+                    if (part == 0) mag[r] = v;
+                    __syncthreads();
+                }
+                // coupling fragments: [K step][site block] of one word of codes per lane,
+                // 64 words per K step and block
+                using Frag = uint32_t;
                 auto frag_ptr = [&](int blk) -> const uint8_t * {
-                    return Jx + 8 * (((size_t)blk * nku * 2 + kg) * 32 + ln);
+                    return Jx + 4 * (((size_t)blk * nku * 2 + kg) * 32 + ln);
                 };
-                constexpr int kUnit = 512;  // bytes from one K unit of a fragment to the next
+                constexpr int kUnit = 256;  // bytes from one K step of a fragment to the next
                 Frag ring[kRing];
                 if (wave < nblk) {
                     const uint8_t *br0 = frag_ptr(wave);
@@ -751,19 +766,16 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
                     const uint8_t *br = frag_ptr(blk);
                     // the next block of this wave, or this one again when there is none
                     const uint8_t *bn = blk + kStep < nblk ? frag_ptr(blk + kStep) : br;
-                    v16f acc[RB];
+                    v16i acc[RB];
 #pragma unroll
-                    for (int rb = 0; rb < RB; ++rb) acc[rb] = v16f{0.f};
-                    // A operand of K unit ku: bytes 0 .. 15 are the row's K 16 kg .. + 15 of
-                    // the unit's 64, bytes 16 .. 31 its K 32 + 16 kg .. + 15; B operand:
-                    // nibble j of the four words is K 32 kg + j
+                    for (int rb = 0; rb < RB; ++rb) acc[rb] = v16i{0};
                     const uint8_t *abase = sp + ln * pitch + in_col + 16 * kg;
                     for (int kb = 0; kb < nku; kb += kRing) {
 #pragma unroll
                         for (int u = 0; u < kRing; ++u) {
                             const int ku = kb + u;
                             if (ku < nku) {
-                                const v8i b = fp4_operand(ring[u]);
+                                const v4i b = widen_codes(ring[u]);
                                 // slot u takes unit ku + kRing of this block, or, after this
                                 // block's last unit of its residue class, unit u of the next block
                                 const int kn = ku + kRing;
@@ -771,13 +783,8 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
                                                                      : bn + (size_t)kUnit * min(u, nku - 1));
 #pragma unroll
                                 for (int rb = 0; rb < RB; ++rb) {
-                                    const uint8_t *ar = abase + rb * 32 * pitch + 64 * ku;
-                                    const uint4 lo = *reinterpret_cast<const uint4 *>(ar);
-                                    const uint4 hi = *reinterpret_cast<const uint4 *>(ar + 32);
-                                    const v8i a = v8i{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w,
-                                                      (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
-                                    acc[rb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, acc[rb], 0, 4, 0,
-                                                                                              127, 0, 127);
+                                    const v4i a = *reinterpret_cast<const v4i *>(abase + rb * 32 * pitch + 32 * ku);
+                                    acc[rb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, acc[rb], 0, 0, 0);
                                 }
                             }
                         }
@@ -805,7 +812,9 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
                             uint32_t sgn[4];  // 1: the replica's new spin is -1
 #pragma unroll
                             for (int p = 0; p < 4; ++p) {
-                                const int F = (int)acc[rb][4 * q + p];  // an exact integer
+                                // an exact integer; with codes of J + 1 the product exceeds the
+                                // field by the replica's spin sum over the other side
+                                const int F = (int)acc[rb][4 * q + p] - mag[r4 + p];
                                 const int Fc = min(max(F, flo), fhi);
                                 const uint64_t S = *static_cast<const uint64_t *>(
                                     __builtin_assume_aligned(Sb + 8 * Fc + base8, 8));
@@ -816,8 +825,8 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
                             }
                             const uint32_t lo = __builtin_amdgcn_perm(sgn[1], sgn[0], 0x0C0C0400u);
                             const uint32_t hi = __builtin_amdgcn_perm(sgn[3], sgn[2], 0x0C0C0400u);
-                            // sign bit 0 -> +1, 1 -> -1: e4m3 0x38 / 0xB8 bytes
-                            const uint32_t packed = __builtin_amdgcn_perm(0u, 0xB838u,
+                            // sign bit 0 -> +1, 1 -> -1: 0x01 / 0xFF bytes
+                            const uint32_t packed = __builtin_amdgcn_perm(0u, 0xFF01u,
                                                                           __builtin_amdgcn_perm(hi, lo, 0x05040100u));
                             const uint32_t x = quad_transpose(packed, u4);  // four sites, one byte each
                             *reinterpret_cast<uint32_t *>(sp + (r4 + u4) * pitch + quad_col) = x;
@@ -831,7 +840,7 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
         // field part of side A, then the energies and the spins go back to global memory
         for (int k = tid; k < RS * na; k += kBqTileThreads) {
             const int r = k / na, a = k % na;
-            const int m = (int)(int8_t)fp8_to_int8(sp[r * pitch + a]);
+            const int m = (int)(int8_t)sp[r * pitch + a];
             const int v = (int)jb.hA[a] * m;
             if (v != 0) atomicAdd(&eacc[r], -v);
         }
@@ -839,9 +848,8 @@ __global__ __launch_bounds__(kBqTileThreads) void k_bq_tiles(const BqJobDev *__r
         if (tid < RS) jb.energy[w.tile * RS + tid] = eacc[tid];
         for (int k = tid; k < RS * (PR / 16); k += kBqTileThreads) {
             const int r = k / (PR / 16), c16 = k % (PR / 16);
-            const uint4 v = *reinterpret_cast<const uint4 *>(sp + r * pitch + 16 * c16);
             *reinterpret_cast<uint4 *>(gst + (size_t)r * PR + 16 * c16) =
-                make_uint4(fp8_to_int8(v.x), fp8_to_int8(v.y), fp8_to_int8(v.z), fp8_to_int8(v.w));
+                *reinterpret_cast<const uint4 *>(sp + r * pitch + 16 * c16);
         }
     }
 }

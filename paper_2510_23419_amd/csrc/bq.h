@@ -21,16 +21,10 @@ struct BqView {
     const int8_t *JTb;
     const int32_t *hA2;  // [na_p]
     const int32_t *hB2;  // [nb_p]
-    // for the batched int8-row tiles: (sign, nonzero) two-bit codes, 16 per word, placed
-    // for fp4 operands, in MFMA fragment order (see load_biclique), [na_p * nb_p / 16] and
-    // [nb_p * na_p / 16]
+    // for the batched int8 tiles: J + 1 (padding included) as two-bit codes, 16 per word,
+    // in MFMA fragment order (see load_biclique), [na_p * nb_p / 16] and [nb_p * na_p / 16]
     const uint32_t *J2;
     const uint32_t *JT2;
-    // for the per-instance bit kernel's fp4 form (sides padded to 128): the couplings in
-    // every group of 64 columns reordered to the two spin words' widened bits and
-    // scaled by 2^(2 - j), as e2m1 nibbles, [na_p][nb_p / 2] and [nb_p][na_p / 2] bytes
-    const uint8_t *Jb4;
-    const uint8_t *JTb4;
 };
 
 constexpr int kBqPad = 64;       // site padding of small biclique sides (MFMA K and N tiles)
@@ -72,10 +66,8 @@ hipError_t bqb_pack(const BqView &p, const int8_t *MA, const int8_t *MB, uint32_
 hipError_t bqb_unpack(const BqView &p, const uint32_t *MAb, const uint32_t *MBb, int8_t *MA, int8_t *MB, int Rp,
                       hipStream_t st);
 // rt: replicas per tile, 64, 128 or 256; 0 (or a value that does not divide Rp): 256
-// where that gives at least 256 workgroups, else 128.  f4: the fp4 couplings on the
-// fp8 x fp4 MFMA where the other side is a multiple of 256, else the int8 ones
+// where that gives at least 256 workgroups, else 128
 hipError_t bqb_halfsweep(const BqView &p, int side, uint32_t *MAb, uint32_t *MBb, int Rp, const uint32_t *trow,
-                         int width, uint32_t sweep, uint32_t rq0, Key key, hipStream_t st, int rt = 0,
-                         bool f4 = true);
+                         int width, uint32_t sweep, uint32_t rq0, Key key, hipStream_t st, int rt = 0);
 
 }  // namespace pbit

@@ -424,32 +424,6 @@ __global__ __launch_bounds__(kThreads) void k_bq_field_energy(const int8_t *__re
 // uniform word w), so a lane's decision is one multiply-add and one compare,
 // and a wave's 64 decisions form one ballot mask.
 
-typedef int v8i __attribute__((ext_vector_type(8)));
-typedef float v16f __attribute__((ext_vector_type(16)));
-
-// The accumulator of the bit kernel: int32 (8 sum J b, int8 couplings scaled by
-// 2^(3 - j)) or fp32 (2^-7 sum J b, fp4 couplings scaled by 2^(2 - j) against fp8
-// spin bytes 2^j 2^-9), and 2 sum J b from one element of it.
-template <bool F4> struct BitsAcc {
-    typedef v16i type;
-    static __device__ __forceinline__ int twice_sum(int c) { return c >> 2; }
-};
-template <> struct BitsAcc<true> {
-    typedef v16f type;
-    static __device__ __forceinline__ int twice_sum(float c) { return (int)(c * 256.f); }
-};
-
-// Spin bits widened for the fp8 x fp4 MFMA (32 x 32 x 64): lane half g holds 32 K
-// bytes, byte 4 j + i at K position 16 g + 4 j + i and byte 16 + 4 j + i at 32 + 16 g
-// + 4 j + i, from bit 8 i + 4 g + j of the group's first and second spin word, as the
-// value 0 or 2^j; read as e4m3 these bytes are 0 or 2^(j - 9), the same ratios.
-__device__ __forceinline__ v8i widen_bits8(uint32_t w0, uint32_t w1, int g)
-{
-    const uint32_t x = w0 >> (4 * g), y = w1 >> (4 * g);
-    return v8i{(int)(x & 0x01010101u), (int)(x & 0x02020202u), (int)(x & 0x04040404u), (int)(x & 0x08080808u),
-               (int)(y & 0x01010101u), (int)(y & 0x02020202u), (int)(y & 0x04040404u), (int)(y & 0x08080808u)};
-}
-
 constexpr int kBitsST = 64;     // sites per tile
 constexpr int kBitsRT = 256;    // replicas per tile of the full-size form; Rp is a multiple of it
 constexpr int kBitsBlock = 128; // sites per block of the spin-word layout (four words)
@@ -460,14 +434,12 @@ constexpr int kBitsMinGroups = 256;  // workgroups (one per CU) below which the 
 // barriers per launch, for sides that are multiples of 256).  RT: replicas per
 // tile, 32 per wave; tiles of 128 and 64 replicas (four and two waves) give a
 // launch more workgroups where sides of 1024 or 2048 would fill only a quarter or
-// half of the CUs with 256.  F4: couplings as fp4 (half a byte each, Jb4 / JTb4) on
-// the fp8 x fp4 MFMA, stages of KT = 256 in a 6-stage ring.
-template <int WAVES, int KT, int RT, bool F4 = false>
+// half of the CUs with 256.
+template <int WAVES, int KT, int RT>
 struct BitsGeom {
     static constexpr int threads = 64 * WAVES;
-    static constexpr int NS = F4 ? 6 : KT == 256 ? 4 : 8;  // stages in the ring
-    static constexpr int rowb = F4 ? KT / 2 : KT;          // bytes of one coupling row in a stage
-    static constexpr int jbytes = kBitsST * rowb;          // coupling rows of one stage
+    static constexpr int NS = KT == 256 ? 4 : 8;          // stages in the ring
+    static constexpr int jbytes = kBitsST * KT;            // coupling rows of one stage
     static constexpr int bbytes = RT * KT / 8;             // spin words of one stage (KT / 128 blocks)
     static constexpr int bblock = 16 * RT;                 // bytes of one 128-site block of the stage's spin words
     static constexpr int stage = jbytes + bbytes;
@@ -480,25 +452,23 @@ struct BitsGeom {
     static constexpr int bi = RT / WAVES / 32;  // 32-replica blocks per wave
     static constexpr int waves_per_eu = WAVES >= 8 ? WAVES / 4 : 1;
     static_assert(bi >= 1 && bi * WAVES * 32 == RT, "whole 32-replica blocks per wave");
-    static_assert(!F4 || KT == 256, "fp4 couplings stage 256 K (rows of 128 bytes)");
     static_assert(ahead < 64, "vmcnt is a 6-bit field");
     static_assert(j_per_wave * WAVES * 1024 == jbytes && b_per_wave * WAVES * 64 * bsz == bbytes,
                   "whole DMA instructions");
 };
 
-template <int WAVES, int KT, int RT, bool F4>
-__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(BitsGeom<WAVES, KT, RT, F4>::waves_per_eu,
-                                                                              BitsGeom<WAVES, KT, RT, F4>::waves_per_eu))) void
+template <int WAVES, int KT, int RT>
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(BitsGeom<WAVES, KT, RT>::waves_per_eu,
+                                                                              BitsGeom<WAVES, KT, RT>::waves_per_eu))) void
 k_bq_halfsweep_bits(const uint32_t *__restrict__ Mob, const int8_t *__restrict__ Jb, const int32_t *__restrict__ hs2,
                     uint32_t *__restrict__ Msb, const uint32_t *__restrict__ trow, int width, int Ko, int Rp,
                     int tiles_s, int xcd_bands, uint32_t site_base, uint32_t sweep, uint32_t rq0, uint32_t k0,
                     uint32_t k1, uint32_t one)
 {
-    using G = BitsGeom<WAVES, KT, RT, F4>;
+    using G = BitsGeom<WAVES, KT, RT>;
     constexpr int NS = G::NS;
-    constexpr int CH = G::rowb / 16;           // 16-byte chunks per coupling row
-    constexpr int kSubs = KT / (F4 ? 64 : 32);  // MFMA K steps per stage
-    const int row_stride = F4 ? Ko / 2 : Ko;    // bytes of a whole coupling row
+    constexpr int CH = KT / 16;       // 16-byte chunks per coupling row
+    constexpr int kSubs = KT / 32;    // K steps per stage
     constexpr int KB = KT / kBitsBlock;  // spin-word blocks per stage
     constexpr int BI = G::bi;         // replica blocks of 32 per wave
     constexpr int RW = 32 * BI;       // replicas per wave
@@ -546,7 +516,7 @@ k_bq_halfsweep_bits(const uint32_t *__restrict__ Mob, const int8_t *__restrict__
     for (int j = 0; j < G::j_per_wave; ++j) {
         const int S = 64 * (G::j_per_wave * wave + j) + lane;
         const int r = S / CH, c = (S % CH) ^ swzb(S / CH);
-        offJl[j] = (uint32_t)(r * row_stride + 16 * c);
+        offJl[j] = (uint32_t)(r * Ko + 16 * c);
     }
     // spin words: byte o of a stage's spin area is byte o % bblock of block o / bblock of the
     // stage (its replicas' 16 bytes each, contiguous in the block layout)
@@ -555,7 +525,7 @@ k_bq_halfsweep_bits(const uint32_t *__restrict__ Mob, const int8_t *__restrict__
         const uint32_t o = (uint32_t)(G::bsz * (64 * (G::b_per_wave * wave + j) + lane));
         offBl[j] = (o / (uint32_t)G::bblock) * 16u * (uint32_t)Rp + o % (uint32_t)G::bblock;
     }
-    const int8_t *Jt0 = Jb + (size_t)s0 * row_stride;
+    const int8_t *Jt0 = Jb + (size_t)s0 * Ko;
     const char *Bt0 = reinterpret_cast<const char *>(Mob + (size_t)r0 * 4);
     const int nk = Ko / KT;
     const int ln = lane & 31, kg = lane >> 5;
@@ -565,7 +535,7 @@ k_bq_halfsweep_bits(const uint32_t *__restrict__ Mob, const int8_t *__restrict__
     auto issue = [&](int t) {
         int8_t *dJ = ring + (t % NS) * G::stage + 1024 * G::j_per_wave * wave;
         int8_t *dB = ring + (t % NS) * G::stage + G::jbytes + 64 * G::bsz * G::b_per_wave * wave;
-        const int8_t *Jt = Jt0 + (size_t)t * G::rowb;
+        const int8_t *Jt = Jt0 + (size_t)t * KT;
         const char *Bt = Bt0 + (size_t)t * KB * 16 * Rp;
 #pragma unroll
         for (int j = 0; j < G::j_per_wave; ++j) __builtin_amdgcn_global_load_lds(Jt + offJl[j], dJ + 1024 * j, 16, 0, 0);
@@ -587,13 +557,11 @@ k_bq_halfsweep_bits(const uint32_t *__restrict__ Mob, const int8_t *__restrict__
     // r mod 32 = ln only, so site block bj = 1 sits 32 rows further
     int offJ[8];
 #pragma unroll
-    for (int sub = 0; sub < kSubs; ++sub) offJ[sub] = G::rowb * ln + 16 * ((2 * sub + kg) ^ swzb(ln));
+    for (int sub = 0; sub < kSubs; ++sub) offJ[sub] = KT * ln + 16 * ((2 * sub + kg) ^ swzb(ln));
     const int offB = G::jbytes + 16 * (RW * wave + ln);  // spin words of replica rows RW wave + 32 bi + ln
-    // int8: 8 sum J b exactly; fp4: 2^-7 sum J b exactly (fp32)
-    using Acc = typename BitsAcc<F4>::type;
-    Acc acc[BI][2];  // [replica block][site block]
+    v16i acc[BI][2];  // [replica block][site block]
 #pragma unroll
-    for (int bi = 0; bi < BI; ++bi) acc[bi][0] = acc[bi][1] = Acc{0};
+    for (int bi = 0; bi < BI; ++bi) acc[bi][0] = acc[bi][1] = v16i{0};
     uint32_t words[8 * BI][4];
 
     // the fragments of one stage in registers: the next stage's are read from LDS
@@ -617,30 +585,17 @@ k_bq_halfsweep_bits(const uint32_t *__restrict__ Mob, const int8_t *__restrict__
         for (int sub = 0; sub < kSubs; ++sub)
 #pragma unroll
             for (int bj = 0; bj < 2; ++bj)
-                f.b[sub][bj] = *reinterpret_cast<const v4i *>(st + offJ[sub] + 32 * G::rowb * bj);
+                f.b[sub][bj] = *reinterpret_cast<const v4i *>(st + offJ[sub] + 32 * KT * bj);
     };
     auto mfmas = [&](const Frag &f) {
 #pragma unroll
         for (int sub = 0; sub < kSubs; ++sub)
 #pragma unroll
             for (int bi = 0; bi < BI; ++bi) {
-                if constexpr (F4) {
-                    // 64 sites: words 2 (sub % 2) and + 1 of block sub / 2
-                    const v8i a = widen_bits8((uint32_t)f.w[bi][sub / 2][2 * (sub % 2)],
-                                              (uint32_t)f.w[bi][sub / 2][2 * (sub % 2) + 1], kg);
+                const v4i a = widen_bits((uint32_t)f.w[bi][sub / 4][sub % 4], kg);
 #pragma unroll
-                    for (int bj = 0; bj < 2; ++bj) {
-                        const v4i b4 = f.b[sub][bj];
-                        const v8i b = v8i{b4[0], b4[1], b4[2], b4[3], 0, 0, 0, 0};
-                        acc[bi][bj] =
-                            __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, acc[bi][bj], 0, 4, 0, 127, 0, 127);
-                    }
-                } else {
-                    const v4i a = widen_bits((uint32_t)f.w[bi][sub / 4][sub % 4], kg);
-#pragma unroll
-                    for (int bj = 0; bj < 2; ++bj)
-                        acc[bi][bj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, f.b[sub][bj], acc[bi][bj], 0, 0, 0);
-                }
+                for (int bj = 0; bj < 2; ++bj)
+                    acc[bi][bj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, f.b[sub][bj], acc[bi][bj], 0, 0, 0);
             }
     };
     // an empty statement that takes the fragments as its outputs: called where they are
@@ -740,8 +695,7 @@ k_bq_halfsweep_bits(const uint32_t *__restrict__ Mob, const int8_t *__restrict__
                 const int blk = (bj * BI + bi) * 4 + q;
 #pragma unroll
                 for (int p = 0; p < 4; ++p) {
-                    // I = (h + sum J) - 2 sum J b
-                    const int I = h2 - BitsAcc<F4>::twice_sum(acc[bi][bj][4 * q + p]);
+                    const int I = h2 - (acc[bi][bj][4 * q + p] >> 2);  // the accumulator holds 8 sum J b
                     const int Ic = min(max(I, -top), top);
                     const uint64_t S =
                         *static_cast<const uint64_t *>(__builtin_assume_aligned(Sb + 8 * (Ic + top), 8));
@@ -901,26 +855,26 @@ static int bits_rt(int tiles_s, int Rp, int rt)
     return Rp % 128 == 0 ? 128 : 64;
 }
 
-template <int WAVES, int KT, int RT, bool F4 = false>
+template <int WAVES, int KT, int RT>
 static hipError_t bits_launch(const uint32_t *Mob, const int8_t *Jb, const int32_t *hs2, uint32_t *Msb,
                               const uint32_t *trow, int width, int Ko, int Rp, int tiles_s, uint32_t site_base,
                               uint32_t sweep, uint32_t rq0, Key key, hipStream_t st)
 {
-    using G = BitsGeom<WAVES, KT, RT, F4>;
+    using G = BitsGeom<WAVES, KT, RT>;
     static const hipError_t lds_attr = hipFuncSetAttribute(
-        reinterpret_cast<const void *>(&k_bq_halfsweep_bits<WAVES, KT, RT, F4>),
-        hipFuncAttributeMaxDynamicSharedMemorySize, G::ring + (int)sizeof(uint64_t) * (2 * kMaxTableWidth - 1));
+        reinterpret_cast<const void *>(&k_bq_halfsweep_bits<WAVES, KT, RT>), hipFuncAttributeMaxDynamicSharedMemorySize,
+        G::ring + (int)sizeof(uint64_t) * (2 * kMaxTableWidth - 1));
     if (lds_attr != hipSuccess) return lds_attr;
     const int bands = tiles_s % 8 == 0 ? 1 : 0;
     const size_t tab = sizeof(uint64_t) * (size_t)(2 * width - 1);
     const dim3 grid((unsigned)(tiles_s * (Rp / RT)));
-    hipLaunchKernelGGL((k_bq_halfsweep_bits<WAVES, KT, RT, F4>), grid, dim3(G::threads), G::ring + tab, st, Mob, Jb,
-                       hs2, Msb, trow, width, Ko, Rp, tiles_s, bands, site_base, sweep, rq0, key.k0, key.k1, 1u);
+    hipLaunchKernelGGL((k_bq_halfsweep_bits<WAVES, KT, RT>), grid, dim3(G::threads), G::ring + tab, st, Mob, Jb, hs2,
+                       Msb, trow, width, Ko, Rp, tiles_s, bands, site_base, sweep, rq0, key.k0, key.k1, 1u);
     return hipGetLastError();
 }
 
 hipError_t bqb_halfsweep(const BqView &p, int side, uint32_t *MAb, uint32_t *MBb, int Rp, const uint32_t *trow,
-                         int width, uint32_t sweep, uint32_t rq0, Key key, hipStream_t st, int rt, bool f4)
+                         int width, uint32_t sweep, uint32_t rq0, Key key, hipStream_t st, int rt)
 {
     if (!bqb_supported(p, Rp) || width < 1 || width > kMaxTableWidth) return hipErrorInvalidValue;
     const bool A = side == 0;
@@ -931,21 +885,6 @@ hipError_t bqb_halfsweep(const BqView &p, int side, uint32_t *MAb, uint32_t *MBb
     uint32_t *Msb = A ? MAb : MBb;
     const uint32_t site_base = A ? 0u : (uint32_t)p.na;
     const int tiles_s = Ns_p / kBitsST;
-    if (f4 && Ko % 256 == 0 && p.Jb4 && p.JTb4) {
-        // fp4 couplings: stages of 256 K for every tile
-        const int8_t *Jb4 = reinterpret_cast<const int8_t *>(A ? p.Jb4 : p.JTb4);
-        switch (bits_rt(tiles_s, Rp, rt)) {
-        case 256:
-            return bits_launch<kBitsWaves, 256, 256, true>(Mob, Jb4, hs2, Msb, trow, width, Ko, Rp, tiles_s,
-                                                           site_base, sweep, rq0, key, st);
-        case 128:
-            return bits_launch<4, 256, 128, true>(Mob, Jb4, hs2, Msb, trow, width, Ko, Rp, tiles_s, site_base, sweep,
-                                                  rq0, key, st);
-        default:
-            return bits_launch<2, 256, 64, true>(Mob, Jb4, hs2, Msb, trow, width, Ko, Rp, tiles_s, site_base, sweep,
-                                                 rq0, key, st);
-        }
-    }
     // two waves cannot take a 256-deep stage (its DMA needs more than four 16-byte
     // loads per lane), so 64-replica tiles always stage 128
     switch (bits_rt(tiles_s, Rp, rt)) {

@@ -131,7 +131,6 @@ extern "C" int pbit_create(pbit_ctx **out, int device, uint64_t hbm_budget_bytes
         if (k >= 1 && k <= 4) ctx->bq_forced = (BqVariant)k;
     }
     if (const char *v = std::getenv("PBIT_BQ_BITS_RT")) ctx->bq_bits_rt = std::atoi(v);  // tuning override
-    if (const char *v = std::getenv("PBIT_BQ_BITS_F4")) ctx->bq_bits_f4 = std::atoi(v) != 0;  // tuning override
     if (const char *v = std::getenv("PBIT_GRAPH_SLAB")) {  // tuning override: 0 off, 4 / 8 / 16 a tile width
         const int k = std::atoi(v);
         ctx->graph_slab = k != 0;
@@ -372,51 +371,21 @@ static int load_biclique(pbit_ctx *ctx, const pbit_problem_desc *d, Problem &p)
         if (rc == PBIT_OK) rc = upload(ctx, p, hA2.data(), sizeof(int32_t) * hA2.size(), &dhA2);
         if (rc == PBIT_OK) rc = upload(ctx, p, hB2.data(), sizeof(int32_t) * hB2.size(), &dhB2);
     }
-    void *dJb4 = nullptr, *dJTb4 = nullptr;
-    if (rc == PBIT_OK) {
-        // the per-instance bit kernel's fp4 form: in every group of 64 columns, K position
-        // k = 32 h + 16 g + 4 j + i holds column 32 h + 8 i + 4 g + j of the group (the
-        // spin byte it meets holds that site's bit times 2^j, an e4m3 2^(j - 9)) times
-        // 2^(2 - j), as an e2m1 nibble (0.5, 1, 2, 4: 0x1, 0x2, 0x4, 0x6; sign 0x8), the
-        // low nibble of byte k / 2 for even k
-        auto pack4 = [](const std::vector<int8_t> &M, int rows, int cols, std::vector<uint8_t> &out) {
-            static const uint8_t kMag[4] = {0x6, 0x4, 0x2, 0x1};  // 2^(2 - j)
-            out.assign((size_t)rows * cols / 2, 0);
-            for (int r = 0; r < rows; ++r)
-                for (int c0 = 0; c0 < cols; c0 += 64)
-                    for (int k = 0; k < 64; ++k) {
-                        const int h = k >> 5, g = (k >> 4) & 1, j = (k >> 2) & 3, i = k & 3;
-                        const int v = M[(size_t)r * cols + c0 + 32 * h + 8 * i + 4 * g + j];
-                        if (v == 0) continue;
-                        const uint8_t nib = (uint8_t)(kMag[j] | (v < 0 ? 0x8 : 0x0));
-                        out[((size_t)r * cols + c0 + k) / 2] |= (uint8_t)(nib << (4 * (k & 1)));
-                    }
-        };
-        std::vector<uint8_t> Jb4, JTb4;
-        pack4(J, na_p, nb_p, Jb4);
-        pack4(JT, nb_p, na_p, JTb4);
-        rc = upload(ctx, p, Jb4.data(), Jb4.size(), &dJb4);
-        if (rc == PBIT_OK) rc = upload(ctx, p, JTb4.data(), JTb4.size(), &dJTb4);
-    }
     void *dJ2 = nullptr, *dJT2 = nullptr;
     if (rc == PBIT_OK) {
-        // two-bit couplings for the batched int8-row tiles (fp4 operands on the fp8 x fp4
-        // MFMA): per coupling a sign bit and a nonzero bit (padding 0), 16 per word in
-        // fragment order: the pair of words (((blk nku + u) 2 + g) 32 + l) holds row
-        // 32 blk + l, columns 64 u + 32 g + 16 h + k (word h of the pair); for k < 8 the
-        // nonzero bit of column k sits at bit 4 k + 1 and the sign at 4 k + 3, for k >= 8 at
-        // 4 (k - 8) and 4 (k - 8) + 2, so that a mask, or a shift and a mask, gives fp4 e2m1
+        // two-bit couplings for the batched int8 tiles: J + 1 in {0, 1, 2}, padding included
+        // (J = 0 there, so the code is 1: the tiles subtract every spin of the other side,
+        // and padding spins take arbitrary values after the first update), 16 per word in
+        // fragment order: word ((blk nku + u) 2 + g) 32 + l holds row 32 blk + l, columns
+        // 32 u + 16 g + 4 j + i, as bits 2 j (low) and 2 j + 1 (high) of byte i
         auto pack2 = [](const std::vector<int8_t> &M, int rows, int cols, std::vector<uint32_t> &out) {
-            const int nku = cols / 64;
+            const int nku = cols / 32;
             out.assign((size_t)rows * cols / 16, 0u);
             for (int r = 0; r < rows; ++r)
                 for (int c = 0; c < cols; ++c) {
-                    const int v = M[(size_t)r * cols + c];
-                    if (v == 0) continue;
-                    const int blk = r / 32, l = r % 32, u = c / 64, g = (c / 32) % 2, h = (c / 16) % 2, k = c % 16;
-                    const int at = k < 8 ? 4 * k + 1 : 4 * (k - 8);
-                    const size_t word = ((((size_t)blk * nku + u) * 2 + g) * 32 + l) * 2 + h;
-                    out[word] |= (1u << at) | ((v < 0 ? 1u : 0u) << (at + 2));
+                    const uint32_t v = (uint32_t)(M[(size_t)r * cols + c] + 1);
+                    const int blk = r / 32, l = r % 32, u = c / 32, g = (c / 16) % 2, j = (c / 4) % 4, i = c % 4;
+                    out[(((size_t)blk * nku + u) * 2 + g) * 32 + l] |= v << (8 * i + 2 * j);
                 }
         };
         std::vector<uint32_t> J2, JT2;
@@ -431,7 +400,7 @@ static int load_biclique(pbit_ctx *ctx, const pbit_problem_desc *d, Problem &p)
     p.amax = amax;
     p.bq = BqView{na, nb, na_p, nb_p, (const int8_t *)dJ, (const int8_t *)dJT, (const int8_t *)dhA,
                   (const int8_t *)dhB, (const int8_t *)dJb, (const int8_t *)dJTb, (const int32_t *)dhA2, (const int32_t *)dhB2,
-                  (const uint32_t *)dJ2, (const uint32_t *)dJT2, (const uint8_t *)dJb4, (const uint8_t *)dJTb4};
+                  (const uint32_t *)dJ2, (const uint32_t *)dJT2};
     return PBIT_OK;
 }
 
@@ -682,7 +651,6 @@ struct DevState {
     int8_t *stage = nullptr;  // [R][N] host-layout staging
     BqVariant variant = BqVariant::Auto;
     int bits_rt = 0;  // replicas per tile of the bit kernel (0: its launcher's rule)
-    bool bits_f4 = true;  // the bit kernel's fp4 couplings where the other side is a multiple of 256
     int slab_rs = 0;  // replicas per slice of the LDS-resident biclique kernel (0: its launcher's rule)
     bool slab = false;        // cube, graph or small biclique held in LDS for runs of sweeps
     int graph_rs = 0;         // replicas per workgroup of the LDS-resident graph sweep (graph_slab)
@@ -720,10 +688,7 @@ static int tune_biclique(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStrea
     const bool slab_ok = bq_slab_supported(P.bq, ds.Rp, ds.width, ctx->bq_slab_rs);
     const BqVariant f = ctx->bq_forced;
     ds.bits_rt = ctx->bq_bits_rt;
-    ds.bits_f4 = ctx->bq_bits_f4;
     ds.slab_rs = ctx->bq_slab_rs;
-    // a tuned bit-kernel choice: its replica tile, and kBitsF4 where it takes the fp4 couplings
-    constexpr int kBitsF4 = 1 << 16;
     if (f == BqVariant::Small || (f == BqVariant::Dma && large) || (f == BqVariant::Bits && ds.MAb) ||
         (f == BqVariant::Slab && slab_ok)) {
         ds.variant = f;  // a forced kernel the shape cannot take falls back to the tuned choice
@@ -733,11 +698,7 @@ static int tune_biclique(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStrea
     auto it = ctx->bq_tuned.find(shape);
     if (it != ctx->bq_tuned.end()) {
         ds.variant = it->second.first;
-        if (ds.variant == BqVariant::Slab) ds.slab_rs = it->second.second;
-        if (ds.variant == BqVariant::Bits) {
-            ds.bits_rt = it->second.second & (kBitsF4 - 1);
-            ds.bits_f4 = (it->second.second & kBitsF4) != 0;
-        }
+        (ds.variant == BqVariant::Slab ? ds.slab_rs : ds.bits_rt) = it->second.second;
         return PBIT_OK;
     }
     if (!large && !slab_ok) {
@@ -782,7 +743,7 @@ static int tune_biclique(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStrea
                 for (int k = 0; k < 4 && e == hipSuccess; ++k)
                     e = v == BqVariant::Bits
                             ? bqb_halfsweep(P.bq, k & 1, ds.MAb, ds.MBb, ds.Rp, ds.table, ds.width, 0u, 0u, key, st,
-                                            rt & (kBitsF4 - 1), (rt & kBitsF4) != 0)
+                                            rt)
                             : bq_halfsweep(P.bq, k & 1, ds.MA, ds.MB, ds.R, ds.Rp, ds.table, ds.width, 0u, 0u, key,
                                            st, v);
             }
@@ -799,13 +760,9 @@ static int tune_biclique(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStrea
     for (BqVariant v : cand) {
         if ((v == BqVariant::Dma && !large) || (v == BqVariant::Bits && !ds.MAb) || (v == BqVariant::Slab && !slab_ok))
             continue;  // the shape cannot take it
-        if (v == BqVariant::Bits) {
-            // each replica tile (or the forced one), with the fp4 couplings (unless switched
-            // off) and with the int8 ones
+        if (v == BqVariant::Bits && ds.bits_rt == 0) {
             for (int w : {256, 128, 64})
-                if ((ds.bits_rt == 0 || w == ds.bits_rt) && ds.Rp % w == 0)
-                    for (bool f4 : {true, false})
-                        if (!f4 || ds.bits_f4) runs.push_back({v, w | (f4 ? kBitsF4 : 0)});
+                if (ds.Rp % w == 0) runs.push_back({v, w});
         } else if (v == BqVariant::Slab && ds.slab_rs == 0) {
             for (int w : {16, 8})
                 if (bq_slab_supported(P.bq, ds.Rp, ds.width, w)) runs.push_back({v, w});
@@ -840,12 +797,9 @@ static int tune_biclique(pbit_ctx *ctx, const Problem &P, DevState &ds, hipStrea
     (void)hipEventDestroy(e1);
     if (e != hipSuccess) return device_fail(ctx, e, "biclique kernel tuning");
     ds.variant = best;
-    if (best == BqVariant::Bits) {
-        ds.bits_rt = best_rt & (kBitsF4 - 1);
-        ds.bits_f4 = (best_rt & kBitsF4) != 0;
-    }
+    if (best == BqVariant::Bits) ds.bits_rt = best_rt;
     if (best == BqVariant::Slab) ds.slab_rs = best_rt;
-    ctx->bq_tuned[shape] = {ds.variant, best == BqVariant::Slab ? ds.slab_rs : best == BqVariant::Bits ? best_rt : 0};
+    ctx->bq_tuned[shape] = {ds.variant, best == BqVariant::Slab ? ds.slab_rs : ds.bits_rt};
     return PBIT_OK;
 }
 
@@ -999,15 +953,7 @@ static int prepare(pbit_ctx *ctx, const Problem &P, const pbit_anneal_desc *d, h
     if (P.kind == PBIT_BICLIQUE && ds.variant == BqVariant::Slab) ds.slab = true;  // runs of sweeps per launch
     if (P.kind == PBIT_EA3D && d->n_sweeps > 0) ctx->ea_last_path = ds.slab ? 2 : (ds.mfma ? 3 : 1);
     if (P.kind == PBIT_GRAPH && d->n_sweeps > 0) ctx->graph_last_path = ds.slab ? 2 : 1;
-    if (P.kind == PBIT_BICLIQUE && d->n_sweeps > 0) {
-        ctx->bq_last_variant = (int)ds.variant;
-        // operands: the LDS-resident kernel always multiplies fp8 by fp4; the bit kernel
-        // does for the sides whose other side is a multiple of 256 when it takes fp4
-        const bool fa = ds.bits_f4 && P.bq.nb_p % 256 == 0, fb = ds.bits_f4 && P.bq.na_p % 256 == 0;
-        ctx->bq_last_operands = ds.variant == BqVariant::Slab ? 2
-                                : ds.variant != BqVariant::Bits ? 1
-                                : fa && fb ? 2 : fa || fb ? 3 : 1;
-    }
+    if (P.kind == PBIT_BICLIQUE && d->n_sweeps > 0) ctx->bq_last_variant = (int)ds.variant;
 
     const Key key{(uint32_t)d->seed, (uint32_t)(d->seed >> 32)};
     const uint32_t rq0 = (uint32_t)d->replica_offset >> 2;
@@ -1054,8 +1000,7 @@ static hipError_t sweep(pbit_ctx *ctx, const Problem &P, DevState &ds, int s, ui
         else if (P.kind == PBIT_GRAPH)
             e = graph_halfsweep(P.graph, c, ds.spins, ds.Rp, row, ds.width, t, rq0, key, st);
         else if (ds.bits)
-            e = bqb_halfsweep(P.bq, c, ds.MAb, ds.MBb, ds.Rp, row, ds.width, t, rq0, key, st, ds.bits_rt,
-                              ds.bits_f4);
+            e = bqb_halfsweep(P.bq, c, ds.MAb, ds.MBb, ds.Rp, row, ds.width, t, rq0, key, st, ds.bits_rt);
         else
             e = bq_halfsweep(P.bq, c, ds.MA, ds.MB, ds.R, ds.Rp, row, ds.width, t, rq0, key, st, ds.variant);
         if (e == hipSuccess) e = prof_count_launch(ctx, st);
@@ -1533,14 +1478,6 @@ extern "C" int pbit_profile_variant(pbit_ctx *ctx, int32_t *variant)
     PBIT_ENTER(ctx);
     if (!variant) return fail(PBIT_E_ARG, "pbit_profile_variant: variant is NULL");
     *variant = ctx->bq_last_variant;
-    return PBIT_OK;
-}
-
-extern "C" int pbit_profile_operands(pbit_ctx *ctx, int32_t *operands)
-{
-    PBIT_ENTER(ctx);
-    if (!operands) return fail(PBIT_E_ARG, "pbit_profile_operands: operands is NULL");
-    *operands = ctx->bq_last_operands;
     return PBIT_OK;
 }
 

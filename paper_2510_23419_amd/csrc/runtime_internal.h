@@ -73,10 +73,8 @@ struct pbit_ctx {
     // biclique kernel variant: forced (PBIT_BQ_VARIANT) or autotuned per shape
     pbit::BqVariant bq_forced = pbit::BqVariant::Auto;
     int bq_last_variant = 0;  // biclique half-sweep variant of the latest biclique anneal (0: none yet)
-    int bq_last_operands = 0; // its MFMA operands: 1 int8 x int8, 2 fp8 x fp4, 3 one side each (0: none yet)
     int bq_bits_rt = 0;       // replicas per tile of the bit kernel (PBIT_BQ_BITS_RT: 64, 128, 256; 0 = by size)
     int bq_slab_rs = 0;       // replicas per slice of the LDS-resident kernel (PBIT_BQ_SLAB_RS: 16, 8; 0 = timed)
-    bool bq_bits_f4 = true;   // the bit kernel's fp4 couplings where they fit (PBIT_BQ_BITS_F4=0: int8 only)
     bool ea_stream_forced = false;  // cubes always take the streaming stencil (PBIT_EA_STREAM=1)
     int ea_rows = 0;                // lattice rows per workgroup of the streaming stencil (PBIT_EA_ROWS; 0 = default)
     int ea_mfma = -1;  // matrix-core cube half-sweep: -1 timed against the stencil, 1 every cube, 0 none (PBIT_EA_MFMA)

@@ -41,7 +41,7 @@ EXPORTS = ("pbit_create", "pbit_destroy", "pbit_last_error", "pbit_bytes_in_use"
            "pbit_profile_enable", "pbit_profile_read", "pbit_anneal_batch", "pbit_serve_config",
            "pbit_load_graph", "pbit_problem_colouring", "pbit_greedy_colouring", "pbit_profile_variant",
            "pbit_profile_ea_path", "pbit_anneal_dev_noalloc", "pbit_probe", "pbit_profile_graph", "pbit_profile_tiles",
-           "pbit_profile_operands", "pbit_profile_graph_path")
+           "pbit_profile_graph_path")
 
 
 class PbitError(RuntimeError):
@@ -117,7 +117,6 @@ def lib() -> ctypes.CDLL:
             "pbit_profile_enable": ([P, i32], ctypes.c_int),
             "pbit_profile_read": ([P, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), i32], ctypes.c_int),
             "pbit_profile_variant": ([P, ctypes.POINTER(i32)], ctypes.c_int),
-            "pbit_profile_operands": ([P, ctypes.POINTER(i32)], ctypes.c_int),
             "pbit_profile_graph_path": ([P, ctypes.POINTER(i32)], ctypes.c_int),
             "pbit_profile_ea_path": ([P, ctypes.POINTER(i32)], ctypes.c_int),
             "pbit_profile_graph": ([P, ctypes.POINTER(i64), ctypes.POINTER(i64)], ctypes.c_int),
@@ -360,13 +359,6 @@ def pbit_profile_graph_path(ctx) -> int:
     _check(lib().pbit_profile_graph_path(ctx, ctypes.byref(v)))
     return int(v.value)
 
-
-def pbit_profile_operands(ctx) -> int:
-    """MFMA operands of the latest biclique anneal: 1 int8 x int8, 2 fp8 x fp4, 3 one
-    side each (0: none yet)."""
-    v = ctypes.c_int32(0)
-    _check(lib().pbit_profile_operands(ctx, ctypes.byref(v)))
-    return int(v.value)
 
 def pbit_probe(ctx, probe: int, size: int, reps: int = 20):
     """Mean launch time (ms) and work per launch of a ceiling kernel (PBIT_PROBE_*)."""

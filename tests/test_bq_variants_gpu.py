@@ -5,17 +5,14 @@ default is:
 * 1: 64 x 64 tiles straight from global memory (any padding; the choice for
   sides below 512, forced here on large sides too);
 * 2: 128 x 128 int8 tiles staged by the global-to-LDS DMA (sides padded to 128);
-* 3: spins held as bits, widened to bytes for the MFMA; the field is the
+* 3: spins held as bits, widened to bytes for the int8 MFMA; the field is the
   site's field plus its coupling sum minus twice the product (sides padded to
   128; a forced bit kernel pads the replicas to 256), in tiles of 256, 128 or 64
-  replicas (each forced through PBIT_BQ_BITS_RT too), with the couplings as fp4
-  against fp8 bytes where the other side is a multiple of 256 and as int8
-  elsewhere (and everywhere with PBIT_BQ_BITS_F4=0).  The batched engine's bit
+  replicas (each forced through PBIT_BQ_BITS_RT too).  The batched engine's bit
   tiles run under this variant too;
-* 4: sides of at most 512 sites held in LDS with their couplings (two-bit codes in
-  both orientations, widened to fp4) for runs of sweeps in one launch, 16 or 8
-  replicas per workgroup (each forced through PBIT_BQ_SLAB_RS), on the fp8 x fp4
-  MFMA 16 x 16 x 128 with fp32 sums.
+* 4: sides of at most 512 sites held in LDS with their couplings (two-bit codes of
+  J + 1 in both orientations) for runs of sweeps in one launch, 16 or 8 replicas
+  per workgroup (each forced through PBIT_BQ_SLAB_RS), on the int8 MFMA 16 x 16 x 64.
 
 Each kernel is checked on every replica after every sweep on ragged sides, on
 sampled replicas at full size (n = 1024 and 4096, 1024 replicas), and at 128
@@ -94,11 +91,8 @@ def test_variant_every_replica_every_sweep(vctx, na, nb, R):
     # the library reports the kernel that ran on large sides: the forced one
     if min(na, nb) >= 512:
         assert pbit.pbit_profile_variant(vctx) == _FORCED[vctx.value]
-        if _FORCED[vctx.value] in (1, 2):  # the int8 tiles
-            assert pbit.pbit_profile_operands(vctx) == 1
     else:
         assert pbit.pbit_profile_variant(vctx) in (1, 4)
-        assert pbit.pbit_profile_operands(vctx) == (2 if pbit.pbit_profile_variant(vctx) == 4 else 1)
 
 
 @pytest.mark.parametrize("na,nb,R,field", [(600, 520, 70, "uniform3"), (512, 640, 40, "zero")])
@@ -159,25 +153,19 @@ def test_variant_full_size_sampled(vctx, n, R, prefixes):
     assert pbit.pbit_profile_variant(vctx) == _FORCED[vctx.value]
 
 
-@pytest.fixture(scope="module", params=[(rt, f4) for f4 in ("1", "0") for rt in ("64", "128", "256")],
-                ids=lambda p: "rt%s-%s" % (p[0], "fp4" if p[1] == "1" else "int8"))
+@pytest.fixture(scope="module", params=["64", "128", "256"], ids=["rt64", "rt128", "rt256"])
 def rt_ctx(request):
-    """The bit kernel forced, with its replica tile forced too (PBIT_BQ_BITS_RT), and its
-    couplings as fp4 on the fp8 x fp4 MFMA where the other side is a multiple of 256
-    (the default) or always as int8 (PBIT_BQ_BITS_F4=0)."""
-    rt, f4 = request.param
-    old = {k: os.environ.get(k) for k in ("PBIT_BQ_BITS_RT", "PBIT_BQ_BITS_F4")}
-    os.environ["PBIT_BQ_BITS_RT"] = rt
-    os.environ["PBIT_BQ_BITS_F4"] = f4
+    """The bit kernel forced, with its replica tile forced too (PBIT_BQ_BITS_RT)."""
+    old = os.environ.get("PBIT_BQ_BITS_RT")
+    os.environ["PBIT_BQ_BITS_RT"] = request.param
     try:
         c = _forced_context("3")
     finally:
-        for k, v in old.items():
-            if v is None:
-                del os.environ[k]
-            else:
-                os.environ[k] = v
-    yield c.ctx, int(rt), f4 == "1"
+        if old is None:
+            del os.environ["PBIT_BQ_BITS_RT"]
+        else:
+            os.environ["PBIT_BQ_BITS_RT"] = old
+    yield c.ctx, int(request.param)
     c.close()
 
 
@@ -185,20 +173,12 @@ def rt_ctx(request):
 def test_bit_tile_widths_every_replica_every_sweep(rt_ctx, na, nb, R):
     """The bit kernel in each of its replica tiles (256 replicas on eight waves, 128 on
     four, 64 on two), with stages of 256 K where a side is a multiple of 256 and 128
-    elsewhere, several replica tiles per launch, with fp4 and with int8 couplings (the
-    fp4 form takes the sides whose other side is a multiple of 256: both at 512 x 1024,
-    one at 768 x 896, none at 600 x 520): every replica after every sweep."""
-    ctx, rt, f4 = rt_ctx
+    elsewhere, several replica tiles per launch: every replica after every sweep."""
+    ctx, rt = rt_ctx
     inst = synth.biclique_instance(na, seed=na + 7 * nb + R, nb=nb)
-    _say("bit kernel, %d-replica tiles, %s couplings, biclique %dx%d R=%d every sweep"
-         % (rt, "fp4" if f4 else "int8", na, nb, R))
+    _say("bit kernel, %d-replica tiles, biclique %dx%d R=%d every sweep" % (rt, na, nb, R))
     _every_sweep(ctx, inst, synth.beta_linear(0.05, 2.0, 6), R, seed=23)
     assert pbit.pbit_profile_variant(ctx) == 3
-    # the operands it reports: fp4 for a side whose other side (padded to 128 here) is a
-    # multiple of 256
-    pad = lambda n: -(-n // 128) * 128
-    fa, fb = f4 and pad(nb) % 256 == 0, f4 and pad(na) % 256 == 0
-    assert pbit.pbit_profile_operands(ctx) == (2 if fa and fb else 3 if fa or fb else 1)
 
 
 @pytest.mark.parametrize("na,nb,R", [(512, 512, 128), (640, 768, 100), (1024, 1024, 64)])
@@ -296,8 +276,8 @@ def test_slab_every_replica_every_sweep(slab_ctx, na, nb, R):
 @pytest.mark.parametrize("na,nb,R,field", [(300, 200, 40, "uniform3"), (512, 512, 33, "uniform3"),
                                            (70, 130, 17, "zero")])
 def test_slab_zero_couplings_every_sweep(slab_ctx, na, nb, R, field):
-    """Diluted couplings (the zero code, an fp4 zero on the matrix cores) in the
-    LDS-resident form, with fields and without."""
+    """Diluted couplings (code 1 of the two-bit codes) in the LDS-resident form, with
+    fields and without."""
     inst = _biclique_with_zeros(na, nb, seed=na + 13 * nb + R, field=field)
     _say("slab diluted biclique %dx%d R=%d every sweep" % (na, nb, R))
     _every_sweep(slab_ctx, inst, synth.beta_linear(0.05, 2.0, 10), R, seed=29)
@@ -365,7 +345,7 @@ def test_slab_offsets_resume_and_given_spins(slab_ctx):
     beta = synth.beta_linear(0.1, 2.5, 60)
     prob = pbit.load_instance(slab_ctx, inst)
     full = pbit.pbit_anneal(slab_ctx, prob, beta, 40, seed=5)
-    assert pbit.pbit_profile_variant(slab_ctx) == 4 and pbit.pbit_profile_operands(slab_ctx) == 2
+    assert pbit.pbit_profile_variant(slab_ctx) == 4
     ref = oracle.anneal(g, beta, 40, seed=5)
     assert np.array_equal(full.spins, ref.spins) and np.array_equal(full.energies, ref.energies)
     a = pbit.pbit_anneal(slab_ctx, prob, beta[:23], 40, seed=5)
